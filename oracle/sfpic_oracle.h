@@ -1,0 +1,124 @@
+/*
+ * sfpic_oracle.h -- plain FP64 CPU oracle of the scattered-field PIC step.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only tests/, the package smoke check and the
+ * benchmark's CPU-baseline leg may load this code.  It shares no source,
+ * header, table or helper with the HIP library under paper_2310_11393_amd/.
+ *
+ * Method (Lytova et al., "Scattered field formalism in the particle-in-cell
+ * method ...", arXiv 2310.11393):
+ *   - Sec. 2: total field F = F_inc + F_scatt; only F_scatt lives on the Yee
+ *     grid and obeys Maxwell's equations with the plasma current as source
+ *     (Ampere dE/dt = curl B - J, Faraday dB/dt = -curl E); particles feel
+ *     F_inc + F_scatt at their position.
+ *   - Table 1: normalized plasma units (c = eps0 = 1, lengths 1/k, time 1/omega,
+ *     fields m_e c omega / e, density n_c, current e n_c c).
+ *   - Sec. 3.1: exact 1D plane-wave pulse used as incident field.
+ *   - Sec. 4.1: April's isodiffracting pulsed beam (phasor Psi, Poisson
+ *     spectrum f, derivatives g^(n)); LP from the field-component combination of
+ *     Psi; RP (TM01) from the electric Hertz vector z*Psi (cited, not printed).
+ *
+ * Grid (build axes: propagation +x, polarization y, ignorable z): dims 1 or 2,
+ * nx (x ny) physical cells plus ORC_GUARD guard cells on every side.  Array
+ * index I holds primal node x = (I - G) dx or dual node x = (I - G + 1/2) dx.
+ * Staggering: Ex(I+1/2,J) Ey(I,J+1/2) Ez(I,J) Bx(I,J+1/2) By(I+1/2,J)
+ * Bz(I+1/2,J+1/2); Jx, Jy, Jz co-located with Ex, Ey, Ez.  Arrays are row-major
+ * [J][I] with I fastest; 1D uses NY = 1 (Ey, Ez, Bx primal; Ex, By, Bz dual).
+ */
+#ifndef SFPIC_ORACLE_H
+#define SFPIC_ORACLE_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ORC_GUARD 3
+
+enum {
+  ORC_EX = 0, ORC_EY, ORC_EZ, ORC_BX, ORC_BY, ORC_BZ, ORC_JX, ORC_JY, ORC_JZ,
+  ORC_NCOMP
+};
+
+enum {
+  ORC_INC_NONE = 0,
+  ORC_INC_PLANE_PULSE_1D = 1, /* Sec. 3.1 exact pulse, along +x, E_y = B_z */
+  ORC_INC_APRIL_LP = 2,       /* Sec. 4.1, linear polarization            */
+  ORC_INC_APRIL_RP = 3        /* radial polarization (TM01), Hertz z*Psi  */
+};
+
+typedef struct {
+  int kind;
+  double a0;      /* peak amplitude (E in m_e c omega / e)                     */
+  double fwhm_t;  /* plane pulse: FWHM of the field envelope                  */
+  double t0;      /* plane pulse: envelope centre at x = 0                    */
+  double ka;      /* April: complex-source parameter a (k = 1 units)          */
+  double s;       /* April: Poisson-spectrum parameter                        */
+  double phi0;    /* April: constant phase                                    */
+  double x_focus, y_focus, t_focus; /* April: focus (build axes), focal time */
+  double norm;    /* April: field scale, set by orc_incident_setup            */
+} orc_incident;
+
+typedef struct {
+  int dims;
+  long nx, ny;
+  double dx, dy, dt;
+} orc_grid;
+
+typedef struct orc_sim orc_sim;
+
+/* ---- incident fields (Sec. 3.1, Sec. 4.1) ---- */
+double orc_april_ka_from_w0(double w0);
+int orc_incident_setup(orc_incident *inc);
+void orc_incident_eval(const orc_incident *inc, int dims, double x, double y,
+                       double t, double E[3], double B[3]);
+/* Complex April field in the paper's own axes and dimensionless variables
+ * X = x/a, Y = y/a, Z = z/a, T = c t / a (relative to focus and focal time),
+ * unnormalized (the Psi0/a^3 factor omitted).  out = {Ex,Ey,Ez,cBx,cBy,cBz} as
+ * (re, im) pairs.  use_series: -1 automatic, 0 closed form, 1 ring series. */
+void orc_april_complex(int kind, double X, double Y, double Z, double T,
+                       double ka, double s, double phi0, int use_series,
+                       double out[12]);
+
+/* ---- building blocks, exposed for pinning ---- */
+double orc_shape2(double d);
+void orc_boris(double qm, double dt, double u[3], const double E[3],
+               const double B[3]);
+
+/* ---- simulation ---- */
+orc_sim *orc_create(const orc_grid *g, const orc_incident *inc);
+void orc_destroy(orc_sim *S);
+int orc_add_species(orc_sim *S, double q, double m, double w, long n,
+                    const double *x, const double *y, const double *ux,
+                    const double *uy, const double *uz);
+void orc_step(orc_sim *S, long nsteps);
+long orc_nx_alloc(const orc_sim *S);
+long orc_ny_alloc(const orc_sim *S);
+long orc_step_index(const orc_sim *S);
+void orc_set_step_index(orc_sim *S, long n);
+double *orc_field(orc_sim *S, int comp);
+long orc_count(const orc_sim *S, int sp);
+long orc_alive(const orc_sim *S, int sp);
+void orc_get_particles(const orc_sim *S, int sp, double *x, double *y,
+                       double *ux, double *uy, double *uz, int *alive);
+void orc_set_particles(orc_sim *S, int sp, const double *x, const double *y,
+                       const double *ux, const double *uy, const double *uz,
+                       const int *alive);
+/* Gather E and B from the current E and B arrays at position (x, y). */
+void orc_gather_arrays(const orc_sim *S, double x, double y, double E[3],
+                       double B[3]);
+/* Charge density of the live particles of all species, order-2 shapes,
+ * on primal nodes (NX x NY). */
+void orc_deposit_rho(const orc_sim *S, double *rho);
+/* out: {W_kin, W_em(E^n, B^{n-1/2}), charge, n_alive} */
+void orc_diagnostics(const orc_sim *S, double out[4]);
+/* Energy-angle histogram (weights) over species sp: energy bins [0, emax)
+ * linear, angle from +x in [0, 180] degrees.  mom: {sum w, <Ek>, <Ek^2>,
+ * <theta>, <theta^2>} over particles with Ek > ek_min (theta in degrees). */
+void orc_energy_angle(const orc_sim *S, int sp, int n_e, double emax,
+                      int n_theta, double ek_min, double *hist,
+                      double mom[5]);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
