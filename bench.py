@@ -1,0 +1,174 @@
+#!/usr/bin/env python3
+"""Throughput of the scattered-field PIC step on one MI355X.
+
+A step is one pass of the whole hot path over the full particle set: Yee
+update of the scattered field, order-2 gather, closed-form incident field at
+every particle, Boris push, Esirkepov deposition, Ampere update with Mur
+edges.  The default workload is the 2D3V FP64 case: 2048 x 1024 cells at
+lambda/32, 16.8M electrons (16 per cell, 1 eV) in the central 1024 x 1024
+cells at 0.05 n_c, a tightly focused linearly polarized April beam (w0 =
+lambda, s = 20, a0 = 10) focused at the box centre, 1500 steps.
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("particle-pushes/sec (push+deposit+field) FP32 vs FP64 at stated "
+          "error; sweep p50/p99")
+
+# Algorithmic work of the push kernel per particle (2D3V, FP64, LP April
+# field, closed-form branch); the derivation is listed in the design doc.
+PUSH_BYTES_PARTICLE = 2 * 5 * 8     # read + write x, y, ux, uy, uz (double)
+PUSH_BYTES_CELL = (6 + 3) * 8        # gather 6 field planes, deposit 3 planes
+PUSH_FLOPS = 1050                    # gather 164, incident 314, Boris+advance
+                                     # 68, deposit 491, rounded
+PEAK_FP64_TFLOPS = 78.6
+PEAK_HBM_GBPS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def cpu_baseline(work, sample_rows=128, steps=3):
+    """The FP64 oracle (single thread) on a bounded sample of the same
+    workload: the full field grid with the particles of a band of
+    `sample_rows` plasma rows centred on the beam axis, `steps` steps."""
+    import numpy as np
+    import oracle
+    from paper_2310_11393_amd import workloads as wl
+    sp = work.species[0]
+    x0, x1, y0, y1 = sp.region
+    mid = (y0 + y1) // 2
+    r0 = mid - sample_rows // 2
+    ncx = x1 - x0
+    first = (r0 - y0) * ncx * sp.ppc
+    count = sample_rows * ncx * sp.ppc
+    x, y, ux, uy, uz = wl.generate_particles(sp, work.grid, first, count)
+    sim = oracle.OracleSim(work.grid, work.incident)
+    sim.add_species(sp.q, sp.m, sp.weight, x, y, ux, uy, uz)
+    t0 = time.perf_counter()
+    sim.step(steps)
+    dt = time.perf_counter() - t0
+    return {"value": count * steps / dt, "unit": "particle-pushes/s",
+            "cores": 1, "kind": "oracle",
+            "sample": (f"full {work.grid.nx}x{work.grid.ny} grid, "
+                       f"{count} particles (plasma rows {r0}-"
+                       f"{r0 + sample_rows - 1}), {steps} steps from t=0, "
+                       f"{dt:.1f} s")}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1500)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-rows", type=int, default=128)
+    ap.add_argument("--cpu-steps", type=int, default=3)
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(the domain decomposition is described in DESIGN.md); "
+              "run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2310_11393_amd import workloads as wl
+    from paper_2310_11393_amd.binding import Simulation
+
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    work = wl.lp_2048x1024()
+    log(f"workload {work.name}: creating {work.species[0].count()} particles")
+    sim = Simulation.from_workload(work)
+    sim.step(args.warmup)
+    sim.sync()
+    log(f"warmup {args.warmup} steps done")
+    n0 = sim.particle_count()
+    stream = torch.cuda.current_stream()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    sim.profile(True)
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter()
+    ev0.record(stream)
+    done = 0
+    chunk = max(1, args.steps // 10)
+    while done < args.steps:
+        k = min(chunk, args.steps - done)
+        sim.step(k)
+        done += k
+        if done < args.steps:
+            sim.sync()
+            log(f"{done}/{args.steps} steps")
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter() - t_wall
+    ms = ev0.elapsed_time(ev1)
+    stats = sim.profile_read()
+    sim.profile(False)
+    n1 = sim.particle_count()
+    diag = sim.diagnostics()
+    pushes = args.steps * 0.5 * (n0 + n1)
+    value = pushes / (ms * 1e-3)
+    log(f"{args.steps} steps in {ms:.1f} ms (wall {t_wall:.2f} s): "
+        f"{value / 1e9:.2f} G pushes/s; kernels {stats}")
+
+    # dominant kernel: the particle push
+    launches, push_ms = stats["push"]
+    avg_s = push_ms / launches * 1e-3
+    n_avg = 0.5 * (n0 + n1)
+    plasma_cells = n_avg / work.species[0].ppc
+    flops = n_avg * PUSH_FLOPS
+    bytes_ = n_avg * PUSH_BYTES_PARTICLE + plasma_cells * PUSH_BYTES_CELL
+    achieved = flops / avg_s / 1e12
+    roofline = {"bound": "alu", "achieved": round(achieved, 3),
+                "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / PEAK_FP64_TFLOPS, 4),
+                "traffic": None,
+                "kernel": "push_kernel_f64<2>",
+                "avg_launch_ms": round(avg_s * 1e3, 4),
+                "hbm_achieved_GBps": round(bytes_ / avg_s / 1e9, 1),
+                "hbm_frac": round(bytes_ / avg_s / 1e9 / PEAK_HBM_GBPS, 4)}
+    out = {
+        "metric": METRIC, "value": value, "unit": "particle-pushes/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": ("2D3V FP64 scattered-field PIC, 2048x1024 "
+                                "cells (lambda/32), 16.8M electrons 16 ppc "
+                                "1 eV at 0.05 n_c, April LP beam w0=lambda "
+                                "s=20 a0=10, 1500-step run"),
+                   "grid": [work.grid.nx, work.grid.ny],
+                   "particles": work.species[0].count(),
+                   "precision": "fp64", "parallelism": "single GPU"},
+        "roofline": roofline,
+        "checks": {"gauss_residual_rel": diag["gauss_residual"] /
+                   max(diag["rho_max"], 1e-300),
+                   "nonfinite": diag["nonfinite"], "n_alive": diag["n_alive"]},
+    }
+    sim.close()
+    if not args.no_cpu_baseline:
+        log("timing the oracle on a bounded sample (CPU)")
+        out["cpu_baseline"] = cpu_baseline(work, args.cpu_rows,
+                                           args.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

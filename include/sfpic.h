@@ -1,0 +1,260 @@
+/*
+ * sfpic.h -- C ABI of the scattered-field particle-in-cell library for AMD
+ * MI355X (gfx950).
+ *
+ * The method (Lytova et al., arXiv 2310.11393, Sec. 2): the total field is
+ * split as F = F_inc + F_scatt.  F_inc is a known vacuum solution evaluated in
+ * closed form wherever it is needed; only F_scatt lives on a staggered Yee grid
+ * and is advanced by Maxwell's equations with the plasma current as its only
+ * source.  Macro-particles are pushed in F_inc + F_scatt taken at their own
+ * position and time, and their charge-conserving current feeds F_scatt.
+ *
+ * One step n -> n+1 (state E^n, B^{n-1/2}, x^n, u^{n-1/2}; t^n = n dt):
+ *   Faraday B^{n+1/2} = B^{n-1/2} - dt curl E^n; Bbar^n = (B^{n-1/2} +
+ *   B^{n+1/2})/2; order-2 gather of E^n, Bbar^n at x^n; add F_inc(x^n, t^n);
+ *   Boris push; x^{n+1} = x^n + dt u^{n+1/2}/gamma; Esirkepov current
+ *   J^{n+1/2}; particles leaving the physical box are removed after they
+ *   deposit; Ampere E^{n+1} = E^n + dt (curl B^{n+1/2} - J^{n+1/2}) with a
+ *   first-order Mur absorbing condition on tangential E at the outer faces.
+ *
+ * Units (Table 1 of the paper): c = eps0 = 1; lengths in lambda/(2 pi), time
+ * in 1/omega, E in m_e c omega / e, B in m_e omega / e, density in n_c,
+ * current in e n_c c, charge in e, mass in m_e.  Momenta are u = gamma v.
+ *
+ * Axes: propagation +x, linear polarization along y, z ignorable.  The
+ * paper's (x, y, z) map to (y, z, x) here (a cyclic permutation).
+ *
+ * Grid layout: dims = 1 or 2, nx (x ny) physical cells of size dx (x dy) and
+ * SFPIC_GUARD guard cells on every side.  Array index I of a field holds the
+ * primal node x = (I - GUARD) dx or the dual node x = (I - GUARD + 1/2) dx;
+ * staggering Ex(I+1/2,J) Ey(I,J+1/2) Ez(I,J) Bx(I,J+1/2) By(I+1/2,J)
+ * Bz(I+1/2,J+1/2), J co-located with E.  Host-side field arrays are row-major
+ * [J][I] with I fastest, NX = nx + 2 GUARD, NY = ny + 2 GUARD (1 in 1D).
+ * Physical particle box: [0, nx dx) x [0, ny dy).
+ *
+ * Conventions shared by every call:
+ *   - Every call returns SFPIC_OK (0) or a negative status; no C++ exception
+ *     crosses the ABI.  sfpic_last_error() describes the last failure of the
+ *     calling thread.
+ *   - Host buffers belong to the caller; inputs are read only during the call
+ *     and outputs are written into caller-sized buffers (SFPIC_E_SIZE when
+ *     the size does not match).
+ *   - Device memory and handles belong to the library; *_destroy releases
+ *     them.  A handle is used by one host thread at a time.
+ *   - Work is enqueued on the runtime's HIP stream; sfpic_sync waits for it.
+ *     Read calls synchronize the stream themselves.
+ *   - Precision is fixed at create: SFPIC_FP64 stores everything in double;
+ *     SFPIC_FP32 stores fields and momenta in float and positions as an
+ *     integer cell plus a float offset, keeping double for the incident-field
+ *     phase and for all diagnostics.
+ */
+#ifndef SFPIC_H
+#define SFPIC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SFPIC_OK 0
+#define SFPIC_E_INVAL (-1)   /* invalid argument                          */
+#define SFPIC_E_SIZE (-2)    /* caller buffer size mismatch               */
+#define SFPIC_E_NOMEM (-3)   /* device or host allocation failed          */
+#define SFPIC_E_DEVICE (-4)  /* HIP runtime error                         */
+#define SFPIC_E_NUMERIC (-5) /* non-finite values found                   */
+#define SFPIC_E_BUSY (-6)    /* resource limit reached (try again later)  */
+#define SFPIC_E_STATE (-7)   /* call not valid in the current state       */
+
+#define SFPIC_GUARD 3
+
+enum {
+  SFPIC_EX = 0, SFPIC_EY, SFPIC_EZ, SFPIC_BX, SFPIC_BY, SFPIC_BZ,
+  SFPIC_JX, SFPIC_JY, SFPIC_JZ, SFPIC_NCOMP
+};
+
+typedef enum { SFPIC_FP64 = 0, SFPIC_FP32 = 1 } sfpic_precision;
+
+/* Incident-field models (the paper's closed forms). */
+enum {
+  SFPIC_INC_NONE = 0,
+  /* Sec. 3.1 exact plane-wave pulse along +x: E_y = B_z =
+   * a0 sin(t - t0 - x) 2^{-4 (t - t0 - x)^2 / fwhm_t^2}. */
+  SFPIC_INC_PLANE_PULSE_1D = 1,
+  /* Sec. 4.1 April isodiffracting pulse, linear polarization (along y). */
+  SFPIC_INC_APRIL_LP = 2,
+  /* April pulse, radial polarization (TM01, electric Hertz vector along the
+   * propagation axis; cited in Sec. 4, derived here from the same phasor). */
+  SFPIC_INC_APRIL_RP = 3
+};
+
+typedef struct {
+  int32_t dims;      /* 1 or 2                                            */
+  int64_t nx, ny;    /* physical cells (ny ignored in 1D)                 */
+  double dx, dy;     /* cell sizes                                        */
+  double dt;         /* time step; must satisfy the Yee CFL limit         */
+} sfpic_grid;
+
+/* One mobile particle species.  Either generated on the device (n_explicit
+ * == 0: exactly ppc particles per cell of region, uniform in the cell,
+ * Philox4x32-10 keyed by (seed, species_index), counter = particle id;
+ * Maxwellian momenta of temperature_ev or cold) or given explicitly
+ * (n_explicit > 0: arrays of length n_explicit in physical units, each
+ * particle carrying density `weight`).  An immobile neutralizing background
+ * equal to minus the initial charge density is implied. */
+typedef struct {
+  double q, m;              /* charge (e), mass (m_e)                      */
+  double density;           /* generated: n_c units, weight = density/ppc */
+  int64_t region[4];        /* generated: cells [x0,x1) x [y0,y1)         */
+  int32_t ppc;              /* generated: particles per cell              */
+  double temperature_ev;    /* generated: 0 = cold                        */
+  uint64_t seed;            /* generated: Philox key word 0               */
+  int32_t species_index;    /* generated: Philox key word 1               */
+  int64_t n_explicit;       /* > 0: explicit arrays below                 */
+  double weight;            /* explicit: density per macro-particle      */
+  const double *x, *y, *ux, *uy, *uz; /* explicit (y ignored in 1D)      */
+} sfpic_species;
+
+/* Incident field parameters.  April models: w0 is the waist (the complex
+ * source parameter a follows from k^2 w0^2 = 2 (sqrt(1 + (ka)^2) - 1),
+ * Sec. 4.1), s the Poisson-spectrum parameter (a positive integer here),
+ * phi0 the constant phase, (x_focus, y_focus) the focus in the plane,
+ * t_focus the focal time.  a0 is the modulus of the complex on-axis field
+ * component at the focus at the focal time (E along y for LP, E along x for
+ * RP).  Plane pulse: a0, fwhm_t (FWHM of the field envelope) and t0. */
+typedef struct {
+  int32_t kind;
+  double a0;
+  double fwhm_t, t0;
+  double w0, s, phi0;
+  double x_focus, y_focus, t_focus;
+} sfpic_incident;
+
+/* Device allocator callback (e.g. a framework's caching allocator).  Must
+ * return device memory of at least `bytes`, aligned to 256 bytes, or NULL. */
+typedef void *(*sfpic_alloc_fn)(size_t bytes, void *ctx);
+typedef void (*sfpic_free_fn)(void *ptr, size_t bytes, void *ctx);
+
+typedef struct {
+  void *stream;          /* hipStream_t; NULL = the null stream            */
+  sfpic_alloc_fn alloc;  /* NULL = hipMalloc                               */
+  sfpic_free_fn free;    /* NULL = hipFree                                 */
+  void *alloc_ctx;
+  int32_t tile_x, tile_y; /* particle tile in cells; 0 = library default   */
+  int32_t sort_every;     /* steps between tile sorts; 0 = default         */
+  int32_t device;         /* HIP device ordinal                            */
+} sfpic_runtime;
+
+typedef struct {
+  int64_t step;          /* steps taken                                    */
+  double time;           /* step * dt                                      */
+  int64_t n_alive;       /* live macro-particles, all species              */
+  double w_kin;          /* sum w m (gamma - 1) dV                         */
+  double w_em;           /* 1/2 sum (E^n . E^n + B^{n-1/2} . B^{n-1/2}) dV,
+                            scattered field only                           */
+  double charge;         /* sum q w dV of live particles                   */
+  double gauss_residual; /* max |div_h E - (rho - rho_0)| over nodes at
+                            least 4 cells inside the physical box          */
+  double rho_max;        /* max |rho - rho_0| over the same nodes          */
+  int32_t nonfinite;     /* 1 if a non-finite field or momentum was seen   */
+} sfpic_diag;
+
+typedef struct {
+  int32_t species;
+  int32_t n_energy;  /* linear kinetic-energy bins over [0, e_max) (m_e c^2) */
+  double e_max;
+  int32_t n_theta;   /* angle from +x, bins over [0, 180] degrees          */
+  double ek_min;     /* moments use particles with E_k > ek_min            */
+} sfpic_hist_spec;
+
+typedef struct sfpic_sim sfpic_sim;
+
+/* Create a simulation: allocate and zero the scattered field (Sec. 2: the
+ * fields of the unperturbed plasma are zero at the initial time), place the
+ * particles, set u^{-1/2} = u^0.  nspecies in [1, 8] (0 allowed: vacuum).
+ * Returns SFPIC_E_INVAL for bad sizes or parameters, SFPIC_E_NOMEM when
+ * device memory is short, SFPIC_E_DEVICE on HIP errors. */
+int sfpic_create(const sfpic_grid *grid, const sfpic_species *species,
+                 int nspecies, const sfpic_incident *incident,
+                 sfpic_precision precision, const sfpic_runtime *runtime,
+                 sfpic_sim **out);
+
+/* Enqueue nsteps >= 0 steps on the runtime stream (asynchronous). */
+int sfpic_step(sfpic_sim *sim, int64_t nsteps);
+
+/* Wait for all work queued on the sim's stream. */
+int sfpic_sync(sfpic_sim *sim);
+
+/* Copy one scattered-field component (SFPIC_EX .. SFPIC_JZ) to out, as
+ * double, row-major [NY][NX] including guards; n must be NX * NY.  J holds
+ * J^{n-1/2}, the current deposited by the last step. */
+int sfpic_read_field(sfpic_sim *sim, int comp, double *out, size_t n);
+
+/* Overwrite one field component from a host array laid out as for
+ * sfpic_read_field (for example to seed a run from an external state). */
+int sfpic_write_field(sfpic_sim *sim, int comp, const double *in, size_t n);
+
+/* Set the step counter n (the next step starts at t^n = n dt). */
+int sfpic_set_step_index(sfpic_sim *sim, int64_t step);
+
+/* Number of live particles of a species. */
+int sfpic_particle_count(sfpic_sim *sim, int species, int64_t *n);
+
+/* Copy the live particles of a species (device order) as double, physical
+ * units; id (nullable) receives each particle's creation index.  capacity
+ * is the length of the caller's arrays; *n_out receives the count written
+ * (SFPIC_E_SIZE if capacity is too small).  y may be NULL in 1D. */
+int sfpic_read_particles(sfpic_sim *sim, int species, double *x, double *y,
+                         double *ux, double *uy, double *uz, uint32_t *id,
+                         size_t capacity, size_t *n_out);
+
+/* FP64 global diagnostics (energies, charge, Gauss-law residual). */
+int sfpic_diagnostics(sfpic_sim *sim, sfpic_diag *out);
+
+/* Energy-angle histogram of a species (weights w dV), out has
+ * n_energy * n_theta doubles [energy][theta]; moments (nullable) receives
+ * {sum of weights, <E_k>, <E_k^2>, <theta>, <theta^2>} (theta in degrees)
+ * over particles with E_k > ek_min. */
+int sfpic_histogram(sfpic_sim *sim, const sfpic_hist_spec *spec,
+                    double *out, size_t n, double *moments);
+
+/* Checkpoint: serialize the full state (fields, particles, step) into buf.
+ * With buf == NULL, *n receives the size needed.  Otherwise *n is the
+ * buffer size on input and the size written on output. */
+int sfpic_get_state(sfpic_sim *sim, void *buf, size_t *n);
+
+/* Restore a state produced by sfpic_get_state of a sim with the same grid,
+ * precision and species count. */
+int sfpic_set_state(sfpic_sim *sim, const void *buf, size_t n);
+
+/* Per-kernel timing.  While profiling is on, every kernel launch of the
+ * sim's steps is bracketed by HIP events on the sim's stream.  Kernel
+ * classes: 0 Faraday (+ centred B, J clear), 1 particle push (gather,
+ * incident field, Boris, deposit), 2 Ampere + Mur, 3 tile sort. */
+#define SFPIC_KCLASSES 4
+typedef struct {
+  int64_t launches[SFPIC_KCLASSES];
+  double total_ms[SFPIC_KCLASSES];
+} sfpic_kernel_stats;
+
+/* Start (enable != 0) or stop profiling; starting clears the counters. */
+int sfpic_profile(sfpic_sim *sim, int enable);
+
+/* Wait for the stream and return the accumulated per-class launch counts
+ * and summed kernel durations since profiling was last started. */
+int sfpic_profile_read(sfpic_sim *sim, sfpic_kernel_stats *out);
+
+/* Release the sim and its device memory (waits for queued work). */
+void sfpic_destroy(sfpic_sim *sim);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char *sfpic_last_error(void);
+
+/* Library version string. */
+const char *sfpic_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SFPIC_H */

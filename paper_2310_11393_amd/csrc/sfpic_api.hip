@@ -1,0 +1,716 @@
+// Host runtime behind the C ABI of include/sfpic.h: validation, device memory,
+// particle placement, step scheduling on the caller's HIP stream, reads,
+// diagnostics and checkpoints.
+#include "../../include/sfpic.h"
+#include "sfpic_common.h"
+
+#include <math.h>
+#include <string.h>
+
+#include <new>
+#include <string>
+#include <vector>
+
+using namespace sfpic;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string &msg) {
+  g_last_error = msg;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                   \
+  do {                                                                  \
+    hipError_t e_ = (expr);                                             \
+    if (e_ != hipSuccess)                                               \
+      return fail(SFPIC_E_DEVICE, std::string(#expr) + ": " +           \
+                                      hipGetErrorString(e_));           \
+  } while (0)
+
+struct SpeciesState {
+  double q = -1.0, m = 1.0, weight = 0.0;
+  int64_t n = 0;  // slots (live + removed)
+  Particles<double> p64{};
+  Particles<float> p32{};
+};
+
+constexpr uint64_t kStateMagic = 0x53465049435354ull;  // "SFPICST"
+
+}  // namespace
+
+struct sfpic_sim {
+  sfpic_grid grid{};
+  int precision = SFPIC_FP64;
+  sfpic_runtime rt{};
+  hipStream_t stream = nullptr;
+  int NX = 0, NY = 0, pitch = 0;
+  int64_t step = 0;
+  IncParams inc{};
+  Fields<double> f64{};
+  Fields<float> f32{};
+  void *planes[12] = {};
+  std::vector<SpeciesState> sp;
+  double *rho0 = nullptr, *rho = nullptr, *acc = nullptr;
+  std::vector<std::pair<void *, size_t>> allocs;
+  // profiling: event pairs per kernel class, recorded in launch order
+  bool profiling = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_used[SFPIC_KCLASSES];
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_free;
+
+  std::pair<hipEvent_t, hipEvent_t> take_events() {
+    if (!ev_free.empty()) {
+      auto e = ev_free.back();
+      ev_free.pop_back();
+      return e;
+    }
+    std::pair<hipEvent_t, hipEvent_t> e{nullptr, nullptr};
+    (void)hipEventCreate(&e.first);
+    (void)hipEventCreate(&e.second);
+    return e;
+  }
+  void recycle_events() {
+    for (auto &v : ev_used) {
+      for (auto &e : v) ev_free.push_back(e);
+      v.clear();
+    }
+  }
+  void destroy_events() {
+    recycle_events();
+    for (auto &e : ev_free) {
+      (void)hipEventDestroy(e.first);
+      (void)hipEventDestroy(e.second);
+    }
+    ev_free.clear();
+  }
+
+  void *dalloc(size_t bytes) {
+    bytes = (bytes + 255) & ~(size_t)255;
+    void *p = nullptr;
+    if (rt.alloc) {
+      p = rt.alloc(bytes, rt.alloc_ctx);
+    } else if (hipMalloc(&p, bytes) != hipSuccess) {
+      p = nullptr;
+    }
+    if (p) allocs.emplace_back(p, bytes);
+    return p;
+  }
+  void release() {
+    for (auto &a : allocs) {
+      if (rt.free)
+        rt.free(a.first, a.second, rt.alloc_ctx);
+      else
+        (void)hipFree(a.first);
+    }
+    allocs.clear();
+  }
+  size_t esize() const { return precision == SFPIC_FP64 ? 8 : 4; }
+  double cell_volume() const {
+    return grid.dims == 2 ? grid.dx * grid.dy : grid.dx;
+  }
+};
+
+namespace {
+
+// Incident-field preparation: waist relation and amplitude normalization
+// (a0 = modulus of the complex on-axis component at the focus and focal time).
+int prepare_incident(const sfpic_incident *in, IncParams &P) {
+  memset(&P, 0, sizeof(P));
+  P.kind = in ? in->kind : SFPIC_INC_NONE;
+  if (P.kind == SFPIC_INC_NONE) return SFPIC_OK;
+  if (P.kind == SFPIC_INC_PLANE_PULSE_1D) {
+    if (!(in->fwhm_t > 0.0) || !isfinite(in->a0) || !isfinite(in->t0))
+      return fail(SFPIC_E_INVAL, "plane pulse needs fwhm_t > 0, finite a0/t0");
+    P.a0 = in->a0;
+    P.t0 = in->t0;
+    P.env_k = -4.0 / (in->fwhm_t * in->fwhm_t);
+    return SFPIC_OK;
+  }
+  if (P.kind != SFPIC_INC_APRIL_LP && P.kind != SFPIC_INC_APRIL_RP)
+    return fail(SFPIC_E_INVAL, "unknown incident kind");
+  const double s = in->s;
+  if (!(in->w0 > 0.0) || !(s >= 1.0) || s > 1000.0 || s != floor(s))
+    return fail(SFPIC_E_INVAL, "April beam needs w0 > 0 and integer s >= 1");
+  // k^2 w0^2 = 2 (sqrt(1 + (ka)^2) - 1)  =>  ka = sqrt((1 + w0^2/2)^2 - 1)
+  const double h = 1.0 + 0.5 * in->w0 * in->w0;
+  P.a = sqrt(h * h - 1.0);
+  P.inv_a = 1.0 / P.a;
+  P.s_int = (int)s;
+  P.inv_s = 1.0 / s;
+  P.a_over_s = P.a / s;
+  P.x_focus = in->x_focus;
+  P.y_focus = in->y_focus;
+  P.t_focus = in->t_focus;
+  auto set_coeffs = [&](double norm) {
+    const double pr = norm * cos(in->phi0), pi = norm * sin(in->phi0);
+    P.e_phase_r = pr;
+    P.e_phase_i = pi;
+    cx<double> c = mk(pr, pi);
+    cx<double> ias = mk(0.0, P.a_over_s);
+    for (int n = 0; n < 3; ++n) {
+      P.cr[n] = c.r;
+      P.ci[n] = c.i;
+      c = (s + n + 1.0) * (c * ias);
+    }
+  };
+  set_coeffs(1.0);
+  cx<double> e[3], b[3];
+  april_complex_fields(P, 0.0, 0.0, 0.0, 0.0, e, b);
+  const cx<double> d = (P.kind == SFPIC_INC_APRIL_LP) ? e[0] : e[2];
+  const double m = sqrt(d.r * d.r + d.i * d.i);
+  if (!(m > 0.0) || !isfinite(m))
+    return fail(SFPIC_E_INVAL, "April beam normalization failed");
+  set_coeffs(in->a0 / m);
+  return SFPIC_OK;
+}
+
+int check_grid(const sfpic_grid *g) {
+  if (!g) return fail(SFPIC_E_INVAL, "grid is NULL");
+  if (g->dims != 1 && g->dims != 2) return fail(SFPIC_E_INVAL, "dims must be 1 or 2");
+  const int64_t lim = 65535 - 2 * kGuard;
+  if (g->nx < 8 || g->nx > lim) return fail(SFPIC_E_INVAL, "nx out of range [8, 65529]");
+  if (g->dims == 2 && (g->ny < 8 || g->ny > lim))
+    return fail(SFPIC_E_INVAL, "ny out of range [8, 65529]");
+  if (!(g->dx > 0.0) || (g->dims == 2 && !(g->dy > 0.0)) || !(g->dt > 0.0))
+    return fail(SFPIC_E_INVAL, "dx, dy, dt must be positive");
+  const double lim_dt = (g->dims == 2)
+                            ? 1.0 / sqrt(1.0 / (g->dx * g->dx) + 1.0 / (g->dy * g->dy))
+                            : g->dx;
+  if (!(g->dt < lim_dt)) return fail(SFPIC_E_INVAL, "dt violates the CFL limit");
+  return SFPIC_OK;
+}
+
+template <typename R>
+void set_field_ptrs(Fields<R> &f, void *const planes[12], int NX, int NY,
+                    int pitch) {
+  R **dst[12] = {&f.ex, &f.ey, &f.ez, &f.bx, &f.by, &f.bz,
+                 &f.jx, &f.jy, &f.jz, &f.mx, &f.my, &f.mz};
+  for (int c = 0; c < 12; ++c) *dst[c] = (R *)planes[c];
+  f.nx_alloc = NX;
+  f.ny_alloc = NY;
+  f.pitch = pitch;
+}
+
+int alloc_species(sfpic_sim *s, SpeciesState &st, int64_t n) {
+  st.n = n;
+  const size_t cnt = (size_t)(n > 0 ? n : 1);
+  if (s->precision == SFPIC_FP64) {
+    double **arr[5] = {&st.p64.px, &st.p64.py, &st.p64.ux, &st.p64.uy, &st.p64.uz};
+    for (auto a : arr) {
+      *a = (double *)s->dalloc(cnt * 8);
+      if (!*a) return fail(SFPIC_E_NOMEM, "particle allocation failed");
+    }
+    st.p64.id = (uint32_t *)s->dalloc(cnt * 4);
+    if (!st.p64.id) return fail(SFPIC_E_NOMEM, "particle allocation failed");
+  } else {
+    return fail(SFPIC_E_INVAL, "FP32 precision is not available in this build");
+  }
+  return SFPIC_OK;
+}
+
+int place_species(sfpic_sim *s, SpeciesState &st, const sfpic_species &in,
+                  int index) {
+  const sfpic_grid &g = s->grid;
+  if (!(in.m > 0.0) || !isfinite(in.q)) return fail(SFPIC_E_INVAL, "species needs m > 0");
+  st.q = in.q;
+  st.m = in.m;
+  if (in.n_explicit > 0) {
+    const int64_t n = in.n_explicit;
+    if (n > 0xFFFFFFFFll) return fail(SFPIC_E_INVAL, "too many particles");
+    if (!in.x || !in.ux || !in.uy || !in.uz || (g.dims == 2 && !in.y))
+      return fail(SFPIC_E_INVAL, "explicit particle arrays are NULL");
+    if (!isfinite(in.weight)) return fail(SFPIC_E_NUMERIC, "weight not finite");
+    const double X = g.nx * g.dx, Y = g.ny * g.dy;
+    for (int64_t i = 0; i < n; ++i) {
+      if (!isfinite(in.ux[i]) || !isfinite(in.uy[i]) || !isfinite(in.uz[i]))
+        return fail(SFPIC_E_NUMERIC, "non-finite particle momentum");
+      if (!(in.x[i] >= 0.0 && in.x[i] < X) ||
+          (g.dims == 2 && !(in.y[i] >= 0.0 && in.y[i] < Y)))
+        return fail(SFPIC_E_INVAL, "particle outside the physical box");
+    }
+    st.weight = in.weight;
+    int r = alloc_species(s, st, n);
+    if (r) return r;
+    // stage the host arrays through one device buffer
+    double *tmp = (double *)s->dalloc((size_t)n * 5 * 8);
+    if (!tmp) return fail(SFPIC_E_NOMEM, "staging allocation failed");
+    const double *src[5] = {in.x, g.dims == 2 ? in.y : in.x, in.ux, in.uy, in.uz};
+    for (int k = 0; k < 5; ++k)
+      HIP_TRY(hipMemcpyAsync(tmp + (size_t)k * n, src[k], (size_t)n * 8,
+                             hipMemcpyHostToDevice, s->stream));
+    HIP_TRY(launch_load_particles<double>(st.p64, n, g.dims, tmp, tmp + n,
+                                          tmp + 2 * n, tmp + 3 * n, tmp + 4 * n,
+                                          1.0 / g.dx, 1.0 / g.dy, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    // release the staging buffer now
+    for (size_t k = 0; k < s->allocs.size(); ++k)
+      if (s->allocs[k].first == tmp) {
+        if (s->rt.free)
+          s->rt.free(tmp, s->allocs[k].second, s->rt.alloc_ctx);
+        else
+          (void)hipFree(tmp);
+        s->allocs.erase(s->allocs.begin() + k);
+        break;
+      }
+    return SFPIC_OK;
+  }
+  // generated placement
+  const int64_t x0 = in.region[0], x1 = in.region[1];
+  int64_t y0 = in.region[2], y1 = in.region[3];
+  if (g.dims == 1) {
+    y0 = 0;
+    y1 = 1;
+  }
+  if (in.ppc < 0 || x0 < 0 || x1 > g.nx || x0 > x1 || y0 < 0 ||
+      (g.dims == 2 && y1 > g.ny) || y0 > y1)
+    return fail(SFPIC_E_INVAL, "species region outside the grid");
+  if (in.ppc > 0 && !(in.density >= 0.0)) return fail(SFPIC_E_INVAL, "density < 0");
+  if (!(in.temperature_ev >= 0.0)) return fail(SFPIC_E_INVAL, "temperature < 0");
+  const int64_t n = (x1 - x0) * (y1 - y0) * (int64_t)in.ppc;
+  if (n > 0xFFFFFFFFll) return fail(SFPIC_E_INVAL, "too many particles");
+  st.weight = in.ppc > 0 ? in.density / in.ppc : 0.0;
+  int r = alloc_species(s, st, n);
+  if (r) return r;
+  const double sigma = sqrt(in.temperature_ev / (510998.95 * in.m));
+  HIP_TRY(launch_init_particles<double>(st.p64, n, g.dims, x0, x1 - x0, y0,
+                                        in.ppc > 0 ? in.ppc : 1, sigma,
+                                        in.seed, (uint32_t)in.species_index,
+                                        g.dx, g.dy, s->stream));
+  (void)index;
+  return SFPIC_OK;
+}
+
+int deposit_rho(sfpic_sim *s, double *rho) {
+  const size_t bytes = (size_t)s->NY * s->pitch * 8;
+  HIP_TRY(hipMemsetAsync(rho, 0, bytes, s->stream));
+  for (auto &st : s->sp)
+    HIP_TRY(launch_deposit_rho<double>(st.p64, st.n, s->grid.dims,
+                                       st.q * st.weight, rho, s->pitch,
+                                       s->stream));
+  return SFPIC_OK;
+}
+
+int guarded(sfpic_sim *s) {
+  if (!s) return fail(SFPIC_E_INVAL, "sim is NULL");
+  HIP_TRY(hipSetDevice(s->rt.device));
+  return SFPIC_OK;
+}
+
+}  // namespace
+
+// Launch helper: bracket a kernel launch with events when profiling.
+template <typename F>
+static hipError_t timed(sfpic_sim *s, int cls, F &&launch) {
+  if (!s->profiling) return launch();
+  auto e = s->take_events();
+  hipError_t r = hipEventRecord(e.first, s->stream);
+  if (r == hipSuccess) r = launch();
+  if (r == hipSuccess) r = hipEventRecord(e.second, s->stream);
+  s->ev_used[cls].push_back(e);
+  return r;
+}
+
+extern "C" {
+
+const char *sfpic_last_error(void) { return g_last_error.c_str(); }
+
+const char *sfpic_version(void) { return "sfpic 0.1 (gfx950)"; }
+
+int sfpic_create(const sfpic_grid *grid, const sfpic_species *species,
+                 int nspecies, const sfpic_incident *incident,
+                 sfpic_precision precision, const sfpic_runtime *runtime,
+                 sfpic_sim **out) {
+  try {
+    if (!out) return fail(SFPIC_E_INVAL, "out is NULL");
+    *out = nullptr;
+    int r = check_grid(grid);
+    if (r) return r;
+    if (nspecies < 0 || nspecies > 8 || (nspecies > 0 && !species))
+      return fail(SFPIC_E_INVAL, "nspecies must be in [0, 8]");
+    if (precision != SFPIC_FP64 && precision != SFPIC_FP32)
+      return fail(SFPIC_E_INVAL, "unknown precision");
+    IncParams inc;
+    r = prepare_incident(incident, inc);
+    if (r) return r;
+    sfpic_sim *s = new (std::nothrow) sfpic_sim();
+    if (!s) return fail(SFPIC_E_NOMEM, "host allocation failed");
+    s->grid = *grid;
+    if (grid->dims == 1) {
+      s->grid.ny = 1;
+      s->grid.dy = grid->dx;
+    }
+    s->precision = precision;
+    if (runtime) s->rt = *runtime;
+    s->stream = (hipStream_t)s->rt.stream;
+    s->inc = inc;
+    auto bail = [&](int code) {
+      s->release();
+      delete s;
+      return code;
+    };
+    if (hipSetDevice(s->rt.device) != hipSuccess)
+      return bail(fail(SFPIC_E_DEVICE, "hipSetDevice failed"));
+    if (precision == SFPIC_FP32)
+      return bail(fail(SFPIC_E_INVAL, "FP32 precision is not available in this build"));
+    s->NX = (int)(s->grid.nx + 2 * kGuard);
+    s->NY = (grid->dims == 2) ? (int)(s->grid.ny + 2 * kGuard) : 1;
+    s->pitch = (s->NX + 63) & ~63;
+    const size_t plane = (size_t)s->NY * s->pitch * s->esize();
+    for (int c = 0; c < 12; ++c) {
+      s->planes[c] = s->dalloc(plane);
+      if (!s->planes[c]) return bail(fail(SFPIC_E_NOMEM, "field allocation failed"));
+      if (hipMemsetAsync(s->planes[c], 0, plane, s->stream) != hipSuccess)
+        return bail(fail(SFPIC_E_DEVICE, "hipMemsetAsync failed"));
+    }
+    set_field_ptrs(s->f64, s->planes, s->NX, s->NY, s->pitch);
+    set_field_ptrs(s->f32, s->planes, s->NX, s->NY, s->pitch);
+    s->sp.resize(nspecies);
+    for (int k = 0; k < nspecies; ++k) {
+      r = place_species(s, s->sp[k], species[k], k);
+      if (r) return bail(r);
+    }
+    const size_t rbytes = (size_t)s->NY * s->pitch * 8;
+    s->rho0 = (double *)s->dalloc(rbytes);
+    s->rho = (double *)s->dalloc(rbytes);
+    s->acc = (double *)s->dalloc(64 * 8);
+    if (!s->rho0 || !s->rho || !s->acc)
+      return bail(fail(SFPIC_E_NOMEM, "diagnostic allocation failed"));
+    r = deposit_rho(s, s->rho0);
+    if (r) return bail(r);
+    if (hipStreamSynchronize(s->stream) != hipSuccess)
+      return bail(fail(SFPIC_E_DEVICE, "initialization failed"));
+    *out = s;
+    return SFPIC_OK;
+  } catch (...) {
+    return fail(SFPIC_E_NOMEM, "exception during create");
+  }
+}
+
+int sfpic_step(sfpic_sim *s, int64_t nsteps) {
+  int r = guarded(s);
+  if (r) return r;
+  if (nsteps < 0) return fail(SFPIC_E_INVAL, "nsteps < 0");
+  const sfpic_grid &g = s->grid;
+  for (int64_t k = 0; k < nsteps; ++k) {
+    HIP_TRY(timed(s, 0, [&] {
+      return launch_faraday<double>(s->f64, g.dims, g.dt, g.dx, g.dy, s->stream);
+    }));
+    for (auto &st : s->sp) {
+      PushParams pp;
+      pp.dt = g.dt;
+      pp.dx = g.dx;
+      pp.dy = g.dy;
+      pp.inv_dx = 1.0 / g.dx;
+      pp.inv_dy = 1.0 / g.dy;
+      pp.qm = st.q / st.m;
+      pp.qw = st.q * st.weight;
+      pp.time = (double)s->step * g.dt;
+      pp.nx = (int)g.nx;
+      pp.ny = (int)g.ny;
+      HIP_TRY(timed(s, 1, [&] {
+        return launch_push<double>(s->f64, st.p64, st.n, g.dims, pp, s->inc,
+                                   s->stream);
+      }));
+    }
+    HIP_TRY(timed(s, 2, [&] {
+      return launch_ampere<double>(s->f64, g.dims, g.dt, g.dx, g.dy, s->stream);
+    }));
+    s->step++;
+  }
+  return SFPIC_OK;
+}
+
+int sfpic_sync(sfpic_sim *s) {
+  int r = guarded(s);
+  if (r) return r;
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  return SFPIC_OK;
+}
+
+int sfpic_read_field(sfpic_sim *s, int comp, double *out, size_t n) {
+  int r = guarded(s);
+  if (r) return r;
+  if (comp < 0 || comp >= SFPIC_NCOMP || !out)
+    return fail(SFPIC_E_INVAL, "bad component or NULL output");
+  if (n != (size_t)s->NX * s->NY) return fail(SFPIC_E_SIZE, "n must be NX*NY");
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  HIP_TRY(hipMemcpy2D(out, (size_t)s->NX * 8, s->planes[comp],
+                      (size_t)s->pitch * 8, (size_t)s->NX * 8, s->NY,
+                      hipMemcpyDeviceToHost));
+  return SFPIC_OK;
+}
+
+int sfpic_write_field(sfpic_sim *s, int comp, const double *in, size_t n) {
+  int r = guarded(s);
+  if (r) return r;
+  if (comp < 0 || comp >= SFPIC_NCOMP || !in)
+    return fail(SFPIC_E_INVAL, "bad component or NULL input");
+  if (n != (size_t)s->NX * s->NY) return fail(SFPIC_E_SIZE, "n must be NX*NY");
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  HIP_TRY(hipMemcpy2D(s->planes[comp], (size_t)s->pitch * 8, in,
+                      (size_t)s->NX * 8, (size_t)s->NX * 8, s->NY,
+                      hipMemcpyHostToDevice));
+  return SFPIC_OK;
+}
+
+int sfpic_set_step_index(sfpic_sim *s, int64_t step) {
+  int r = guarded(s);
+  if (r) return r;
+  if (step < 0) return fail(SFPIC_E_INVAL, "step < 0");
+  s->step = step;
+  return SFPIC_OK;
+}
+
+int sfpic_particle_count(sfpic_sim *s, int species, int64_t *n) {
+  int r = guarded(s);
+  if (r) return r;
+  if (species < 0 || species >= (int)s->sp.size() || !n)
+    return fail(SFPIC_E_INVAL, "bad species");
+  SpeciesState &st = s->sp[species];
+  HIP_TRY(hipMemsetAsync(s->acc, 0, 8 * 8, s->stream));
+  HIP_TRY(launch_particle_sums<double>(st.p64, st.n, st.m, st.q, 0.0, s->acc,
+                                       s->stream));
+  double h[8];
+  HIP_TRY(hipMemcpyAsync(h, s->acc, 8 * 8, hipMemcpyDeviceToHost, s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  *n = (int64_t)llround(h[2]);
+  return SFPIC_OK;
+}
+
+int sfpic_read_particles(sfpic_sim *s, int species, double *x, double *y,
+                         double *ux, double *uy, double *uz, uint32_t *id,
+                         size_t capacity, size_t *n_out) {
+  int r = guarded(s);
+  if (r) return r;
+  if (species < 0 || species >= (int)s->sp.size())
+    return fail(SFPIC_E_INVAL, "bad species");
+  if (!x || !ux || !uy || !uz || (s->grid.dims == 2 && !y))
+    return fail(SFPIC_E_INVAL, "NULL output array");
+  try {
+    SpeciesState &st = s->sp[species];
+    const size_t n = (size_t)st.n;
+    std::vector<double> hx(n), hy(n), hux(n), huy(n), huz(n);
+    std::vector<uint32_t> hid(n);
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    if (n) {
+      HIP_TRY(hipMemcpy(hx.data(), st.p64.px, n * 8, hipMemcpyDeviceToHost));
+      if (s->grid.dims == 2)
+        HIP_TRY(hipMemcpy(hy.data(), st.p64.py, n * 8, hipMemcpyDeviceToHost));
+      HIP_TRY(hipMemcpy(hux.data(), st.p64.ux, n * 8, hipMemcpyDeviceToHost));
+      HIP_TRY(hipMemcpy(huy.data(), st.p64.uy, n * 8, hipMemcpyDeviceToHost));
+      HIP_TRY(hipMemcpy(huz.data(), st.p64.uz, n * 8, hipMemcpyDeviceToHost));
+      HIP_TRY(hipMemcpy(hid.data(), st.p64.id, n * 4, hipMemcpyDeviceToHost));
+    }
+    size_t live = 0;
+    for (size_t i = 0; i < n; ++i) live += hx[i] >= -1.0;
+    if (n_out) *n_out = live;
+    if (live > capacity) return fail(SFPIC_E_SIZE, "capacity too small");
+    size_t o = 0;
+    for (size_t i = 0; i < n; ++i) {
+      if (hx[i] < -1.0) continue;
+      x[o] = hx[i] * s->grid.dx;
+      if (y) y[o] = s->grid.dims == 2 ? hy[i] * s->grid.dy : 0.0;
+      ux[o] = hux[i];
+      uy[o] = huy[i];
+      uz[o] = huz[i];
+      if (id) id[o] = hid[i];
+      ++o;
+    }
+    return SFPIC_OK;
+  } catch (...) {
+    return fail(SFPIC_E_NOMEM, "host allocation failed");
+  }
+}
+
+int sfpic_diagnostics(sfpic_sim *s, sfpic_diag *out) {
+  int r = guarded(s);
+  if (r) return r;
+  if (!out) return fail(SFPIC_E_INVAL, "out is NULL");
+  const double dv = s->cell_volume();
+  HIP_TRY(hipMemsetAsync(s->acc, 0, 8 * 8, s->stream));
+  for (auto &st : s->sp)
+    HIP_TRY(launch_particle_sums<double>(st.p64, st.n, st.m, st.q,
+                                         st.weight * dv, s->acc, s->stream));
+  HIP_TRY(launch_field_sums<double>(s->f64, s->acc, s->stream));
+  r = deposit_rho(s, s->rho);
+  if (r) return r;
+  HIP_TRY(launch_gauss<double>(s->f64, s->grid.dims, (int)s->grid.nx,
+                               (int)s->grid.ny, s->grid.dx, s->grid.dy, s->rho,
+                               s->rho0, s->pitch, s->acc, s->stream));
+  double h[8];
+  HIP_TRY(hipMemcpyAsync(h, s->acc, 8 * 8, hipMemcpyDeviceToHost, s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  out->step = s->step;
+  out->time = (double)s->step * s->grid.dt;
+  out->w_kin = h[0];
+  out->charge = h[1];
+  out->n_alive = (int64_t)llround(h[2]);
+  out->nonfinite = h[3] > 0.0 ? 1 : 0;
+  out->w_em = h[4] * dv;
+  out->gauss_residual = h[5];
+  out->rho_max = h[6];
+  return SFPIC_OK;
+}
+
+int sfpic_histogram(sfpic_sim *s, const sfpic_hist_spec *spec, double *out,
+                    size_t n, double *moments) {
+  int r = guarded(s);
+  if (r) return r;
+  if (!spec || !out) return fail(SFPIC_E_INVAL, "NULL argument");
+  if (spec->species < 0 || spec->species >= (int)s->sp.size() ||
+      spec->n_energy <= 0 || spec->n_theta <= 0 || !(spec->e_max > 0.0))
+    return fail(SFPIC_E_INVAL, "bad histogram spec");
+  const size_t nb = (size_t)spec->n_energy * spec->n_theta;
+  if (n != nb) return fail(SFPIC_E_SIZE, "n must be n_energy * n_theta");
+  double *d = (double *)s->dalloc((nb + 8) * 8);
+  if (!d) return fail(SFPIC_E_NOMEM, "histogram allocation failed");
+  SpeciesState &st = s->sp[spec->species];
+  int rc = SFPIC_OK;
+  double mom[8] = {0};
+  if (hipMemsetAsync(d, 0, (nb + 8) * 8, s->stream) != hipSuccess ||
+      launch_histogram<double>(st.p64, st.n, st.m, st.weight * s->cell_volume(),
+                               spec->n_energy, spec->e_max, spec->n_theta,
+                               spec->ek_min, d + 8, d, s->stream) != hipSuccess ||
+      hipMemcpyAsync(out, d + 8, nb * 8, hipMemcpyDeviceToHost, s->stream) != hipSuccess ||
+      hipMemcpyAsync(mom, d, 8 * 8, hipMemcpyDeviceToHost, s->stream) != hipSuccess ||
+      hipStreamSynchronize(s->stream) != hipSuccess)
+    rc = fail(SFPIC_E_DEVICE, "histogram failed");
+  for (size_t k = 0; k < s->allocs.size(); ++k)
+    if (s->allocs[k].first == d) {
+      if (s->rt.free)
+        s->rt.free(d, s->allocs[k].second, s->rt.alloc_ctx);
+      else
+        (void)hipFree(d);
+      s->allocs.erase(s->allocs.begin() + k);
+      break;
+    }
+  if (rc) return rc;
+  if (moments) {
+    moments[0] = mom[0];
+    for (int k = 1; k < 5; ++k) moments[k] = mom[0] > 0.0 ? mom[k] / mom[0] : 0.0;
+  }
+  return SFPIC_OK;
+}
+
+// State layout: header (magic, dims, nx, ny, precision, nspecies, step,
+// element size), 9 field planes [NY][NX], then per species: slot count and
+// the raw particle arrays.
+int sfpic_get_state(sfpic_sim *s, void *buf, size_t *n) {
+  int r = guarded(s);
+  if (r) return r;
+  if (!n) return fail(SFPIC_E_INVAL, "n is NULL");
+  const size_t es = s->esize();
+  size_t need = 8 * 8 + 9 * (size_t)s->NX * s->NY * es;
+  for (auto &st : s->sp) need += 8 + (size_t)st.n * (5 * es + 4);
+  if (!buf) {
+    *n = need;
+    return SFPIC_OK;
+  }
+  if (*n < need) return fail(SFPIC_E_SIZE, "state buffer too small");
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  uint8_t *p = (uint8_t *)buf;
+  int64_t hdr[8] = {(int64_t)kStateMagic, s->grid.dims, s->grid.nx, s->grid.ny,
+                    s->precision, (int64_t)s->sp.size(), s->step, (int64_t)es};
+  memcpy(p, hdr, sizeof(hdr));
+  p += sizeof(hdr);
+  for (int c = 0; c < 9; ++c) {
+    HIP_TRY(hipMemcpy2D(p, (size_t)s->NX * es, s->planes[c], (size_t)s->pitch * es,
+                        (size_t)s->NX * es, s->NY, hipMemcpyDeviceToHost));
+    p += (size_t)s->NX * s->NY * es;
+  }
+  for (auto &st : s->sp) {
+    memcpy(p, &st.n, 8);
+    p += 8;
+    const size_t bytes = (size_t)st.n * es;
+    void *arrs[5] = {st.p64.px, st.p64.py, st.p64.ux, st.p64.uy, st.p64.uz};
+    for (auto a : arrs) {
+      if (bytes) HIP_TRY(hipMemcpy(p, a, bytes, hipMemcpyDeviceToHost));
+      p += bytes;
+    }
+    if (st.n) HIP_TRY(hipMemcpy(p, st.p64.id, (size_t)st.n * 4, hipMemcpyDeviceToHost));
+    p += (size_t)st.n * 4;
+  }
+  *n = need;
+  return SFPIC_OK;
+}
+
+int sfpic_set_state(sfpic_sim *s, const void *buf, size_t n) {
+  int r = guarded(s);
+  if (r) return r;
+  if (!buf) return fail(SFPIC_E_INVAL, "buf is NULL");
+  const size_t es = s->esize();
+  if (n < 64) return fail(SFPIC_E_SIZE, "state too short");
+  const uint8_t *p = (const uint8_t *)buf;
+  int64_t hdr[8];
+  memcpy(hdr, p, sizeof(hdr));
+  if (hdr[0] != (int64_t)kStateMagic || hdr[1] != s->grid.dims ||
+      hdr[2] != s->grid.nx || hdr[3] != s->grid.ny || hdr[4] != s->precision ||
+      hdr[5] != (int64_t)s->sp.size() || hdr[7] != (int64_t)es)
+    return fail(SFPIC_E_INVAL, "state does not match this sim");
+  size_t need = 64 + 9 * (size_t)s->NX * s->NY * es;
+  for (auto &st : s->sp) need += 8 + (size_t)st.n * (5 * es + 4);
+  if (n != need) return fail(SFPIC_E_SIZE, "state size does not match this sim");
+  p += 64;
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  for (int c = 0; c < 9; ++c) {
+    HIP_TRY(hipMemcpy2D(s->planes[c], (size_t)s->pitch * es, p, (size_t)s->NX * es,
+                        (size_t)s->NX * es, s->NY, hipMemcpyHostToDevice));
+    p += (size_t)s->NX * s->NY * es;
+  }
+  for (auto &st : s->sp) {
+    int64_t cnt;
+    memcpy(&cnt, p, 8);
+    if (cnt != st.n) return fail(SFPIC_E_INVAL, "particle slot count mismatch");
+    p += 8;
+    const size_t bytes = (size_t)st.n * es;
+    void *arrs[5] = {st.p64.px, st.p64.py, st.p64.ux, st.p64.uy, st.p64.uz};
+    for (auto a : arrs) {
+      if (bytes) HIP_TRY(hipMemcpy(a, p, bytes, hipMemcpyHostToDevice));
+      p += bytes;
+    }
+    if (st.n) HIP_TRY(hipMemcpy(st.p64.id, p, (size_t)st.n * 4, hipMemcpyHostToDevice));
+    p += (size_t)st.n * 4;
+  }
+  s->step = hdr[6];
+  return SFPIC_OK;
+}
+
+int sfpic_profile(sfpic_sim *s, int enable) {
+  int r = guarded(s);
+  if (r) return r;
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  if (enable) s->recycle_events();
+  s->profiling = enable != 0;
+  return SFPIC_OK;
+}
+
+int sfpic_profile_read(sfpic_sim *s, sfpic_kernel_stats *out) {
+  int r = guarded(s);
+  if (r) return r;
+  if (!out) return fail(SFPIC_E_INVAL, "out is NULL");
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  for (int c = 0; c < SFPIC_KCLASSES; ++c) {
+    out->launches[c] = (int64_t)s->ev_used[c].size();
+    double tot = 0.0;
+    for (auto &e : s->ev_used[c]) {
+      float ms = 0.0f;
+      HIP_TRY(hipEventElapsedTime(&ms, e.first, e.second));
+      tot += ms;
+    }
+    out->total_ms[c] = tot;
+  }
+  return SFPIC_OK;
+}
+
+void sfpic_destroy(sfpic_sim *s) {
+  if (!s) return;
+  (void)hipSetDevice(s->rt.device);
+  (void)hipStreamSynchronize(s->stream);
+  s->destroy_events();
+  s->release();
+  delete s;
+}
+
+}  // extern "C"

@@ -1,0 +1,338 @@
+// Internal structures shared by the host runtime and the gfx950 kernels of the
+// scattered-field PIC library.  Not part of the public ABI (include/sfpic.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sfpic {
+
+constexpr int kGuard = 3;
+constexpr double kDeadPos = -1.0e30;     // FP64 position of a removed particle
+constexpr uint32_t kDeadCell = 0xFFFFFFFFu;  // FP32 cell of a removed particle
+
+// ---------------------------------------------------------------------------
+// Incident-field parameters (prepared on the host, read by every particle).
+// ---------------------------------------------------------------------------
+struct IncParams {
+  int kind;        // SFPIC_INC_*
+  int s_int;       // April: integer Poisson-spectrum parameter s
+  double a0;       // plane pulse amplitude
+  double t0;       // plane pulse centre
+  double env_k;    // plane pulse: -4 / fwhm^2 (exponent base 2)
+  double a;        // April: complex-source parameter (k = 1 units)
+  double inv_a;
+  double inv_s;
+  double a_over_s;
+  double x_focus, y_focus, t_focus;
+  // N e^{i phi0} Gamma(s+n+1)/Gamma(s+1) (i a / s)^n for n = 0, 1, 2, with N
+  // the amplitude normalization (real, imaginary pairs).
+  double cr[3], ci[3];
+  double e_phase_r, e_phase_i;  // N e^{i phi0}
+};
+
+// ---------------------------------------------------------------------------
+// Field planes of one simulation (device pointers, row pitch in elements).
+// ---------------------------------------------------------------------------
+template <typename R>
+struct Fields {
+  R *ex, *ey, *ez, *bx, *by, *bz;  // scattered E^n, B^{n-1/2}
+  R *jx, *jy, *jz;                 // current J^{n+1/2}
+  R *mx, *my, *mz;                 // centred Bbar^n
+  int nx_alloc, ny_alloc;          // NX, NY including guards
+  int pitch;                       // row pitch (elements)
+};
+
+// Particle storage of one species: structure of arrays.
+//  FP64: positions as doubles in cell units (xi = x / dx).
+//  FP32: packed cell (ix | iy << 16) plus float in-cell offsets in [0, 1).
+template <typename R>
+struct Particles;
+
+template <>
+struct Particles<double> {
+  double *px, *py, *ux, *uy, *uz;
+  uint32_t *id;
+};
+
+template <>
+struct Particles<float> {
+  uint32_t *cell;
+  float *ox, *oy, *ux, *uy, *uz;
+  uint32_t *id;
+};
+
+// Per-step scalars of one species push.
+struct PushParams {
+  double dt, dx, dy;
+  double inv_dx, inv_dy;
+  double qm;       // q / m
+  double qw;       // q * weight
+  double time;     // t^n
+  int nx, ny;      // physical cells
+};
+
+// ---------------------------------------------------------------------------
+// Minimal complex arithmetic for device code.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct cx {
+  T r, i;
+};
+
+template <typename T>
+__host__ __device__ __forceinline__ cx<T> mk(T r, T i) {
+  return cx<T>{r, i};
+}
+template <typename T>
+__host__ __device__ __forceinline__ cx<T> operator+(cx<T> a, cx<T> b) {
+  return cx<T>{a.r + b.r, a.i + b.i};
+}
+template <typename T>
+__host__ __device__ __forceinline__ cx<T> operator-(cx<T> a, cx<T> b) {
+  return cx<T>{a.r - b.r, a.i - b.i};
+}
+template <typename T>
+__host__ __device__ __forceinline__ cx<T> operator*(cx<T> a, cx<T> b) {
+  return cx<T>{a.r * b.r - a.i * b.i, a.r * b.i + a.i * b.r};
+}
+template <typename T>
+__host__ __device__ __forceinline__ cx<T> operator*(T s, cx<T> a) {
+  return cx<T>{s * a.r, s * a.i};
+}
+template <typename T>
+__host__ __device__ __forceinline__ cx<T> cinv(cx<T> a) {
+  T d = T(1) / (a.r * a.r + a.i * a.i);
+  return cx<T>{a.r * d, -a.i * d};
+}
+
+// Integer power by binary exponentiation (n >= 1).
+template <typename T>
+__host__ __device__ __forceinline__ cx<T> cpowi(cx<T> b, int n) {
+  cx<T> r = b;
+  n -= 1;
+  cx<T> p = b;
+  while (n > 0) {
+    if (n & 1) r = r * p;
+    n >>= 1;
+    if (n) p = p * p;
+  }
+  return r;
+}
+
+// Square root with a branch that is continuous away from the negative real
+// axis; the April fields are even in this root, so any branch is valid.
+template <typename T>
+__host__ __device__ __forceinline__ cx<T> csqrt_any(cx<T> z) {
+  T m = sqrt(z.r * z.r + z.i * z.i);
+  if (z.r >= T(0)) {
+    T re = sqrt(T(0.5) * (m + z.r));
+    return cx<T>{re, re > T(0) ? z.i / (T(2) * re) : T(0)};
+  }
+  T im = sqrt(T(0.5) * (m - z.r));
+  im = (z.i < T(0)) ? -im : im;
+  return cx<T>{z.i / (T(2) * im), im};
+}
+
+// ---------------------------------------------------------------------------
+// April isodiffracting pulse (Sec. 4.1).  All lengths are scaled by a:
+// X = x/a etc.; u^2 = X^2 + Y^2 + (Z + i)^2.  The phasor Psi = [f(t+) -
+// f(t-)]/Rtilde has field components that are second derivatives of Psi; with
+// d/dX = (X/u) d/du they reduce to four blocks of u and T:
+//   Phi_TT = G-2/u,
+//   D1     = G+1/u^2 - G-0/u^3,
+//   D1_T   = G+2/u^2 - G-1/u^3,
+//   D2     = (3 G-0/u^3 - 3 G+1/u^2 + G-2/u) / u^2,
+// where G+-n = g^(n)(tau+) +- g^(n)(tau-), tau+- = tau + a(+-u + i) and
+// g^(n)(tau) = C_n (1 - i tau/s)^{-(s+n+1)}.
+// On the ring u -> 0 (r = a in the focal plane) the blocks are 0/0 but
+// analytic in u^2; there a Taylor series in u^2 about u = 0 is used with
+// coefficients c_m = g^(m)(tau + i a).
+// ---------------------------------------------------------------------------
+constexpr double kRingU2 = 0.0625;  // series when |u^2| < 0.25^2
+constexpr int kRingTerms = 16;
+
+struct AprilBlocks {
+  cx<double> phitt, d1, d1t, d2;
+};
+
+__host__ __device__ inline AprilBlocks april_blocks_closed(const IncParams &P,
+                                                            cx<double> u2,
+                                                            double tau) {
+  cx<double> u = csqrt_any(u2);
+  // 1 - i tau+-/s = (1 + a/s +- a u_i/s) - i (tau +- a u_r)/s
+  const double as = P.a_over_s;
+  cx<double> wp = mk(1.0 + as + as * u.i, -(tau + P.a * u.r) * P.inv_s);
+  cx<double> wm = mk(1.0 + as - as * u.i, -(tau - P.a * u.r) * P.inv_s);
+  cx<double> rp = cinv(wp), rm = cinv(wm);
+  cx<double> pp0 = cpowi(rp, P.s_int + 1), pm0 = cpowi(rm, P.s_int + 1);
+  cx<double> pp1 = pp0 * rp, pm1 = pm0 * rm;
+  cx<double> pp2 = pp1 * rp, pm2 = pm1 * rm;
+  cx<double> c0 = mk(P.cr[0], P.ci[0]), c1 = mk(P.cr[1], P.ci[1]),
+             c2 = mk(P.cr[2], P.ci[2]);
+  cx<double> gp0 = c0 * pp0, gm0 = c0 * pm0;
+  cx<double> gp1 = c1 * pp1, gm1 = c1 * pm1;
+  cx<double> gp2 = c2 * pp2, gm2 = c2 * pm2;
+  cx<double> Gm0 = gp0 - gm0, Gp1 = gp1 + gm1, Gm1 = gp1 - gm1;
+  cx<double> Gp2 = gp2 + gm2, Gm2 = gp2 - gm2;
+  cx<double> iu = cinv(u);
+  cx<double> iu2 = iu * iu, iu3 = iu2 * iu;
+  AprilBlocks b;
+  b.phitt = Gm2 * iu;
+  b.d1 = Gp1 * iu2 - Gm0 * iu3;
+  b.d1t = Gp2 * iu2 - Gm1 * iu3;
+  b.d2 = (3.0 * (Gm0 * iu3) - 3.0 * (Gp1 * iu2) + Gm2 * iu) * iu2;
+  return b;
+}
+
+__host__ __device__ inline AprilBlocks april_blocks_series(const IncParams &P,
+                                                            cx<double> u2,
+                                                            double tau) {
+  // c_m = N e^{i phi0} [prod_{k<=m} (s+k)] (i a/s)^m (1 + a/s - i tau/s)^{-(s+m+1)}
+  cx<double> base = cinv(mk(1.0 + P.a_over_s, -tau * P.inv_s));
+  cx<double> c = mk(P.e_phase_r, P.e_phase_i) * cpowi(base, P.s_int + 1);
+  const double s = (double)P.s_int;
+  cx<double> step_b = mk(0.0, P.a_over_s) * base;  // (i a/s) * base
+  cx<double> phitt = mk(0.0, 0.0), d1 = phitt, d1t = phitt, d2 = phitt;
+  cx<double> cm[2 * kRingTerms + 4];
+  cm[0] = c;
+  for (int m = 1; m < 2 * kRingTerms + 4; ++m) {
+    c = (s + m) * (c * step_b);
+    cm[m] = c;
+  }
+  cx<double> pw = mk(1.0, 0.0), pw1 = mk(0.0, 0.0), pw2 = mk(0.0, 0.0);
+  double inv_fact = 1.0;  // 1/(2j+1)!
+  for (int j = 0; j < kRingTerms; ++j) {
+    if (j > 0) inv_fact /= (2.0 * j) * (2.0 * j + 1.0);
+    // pw = u^{2j}, pw1 = u^{2j-2}, pw2 = u^{2j-4}
+    phitt = phitt + (2.0 * inv_fact) * (pw * cm[2 * j + 3]);
+    if (j >= 1) {
+      d1 = d1 + (4.0 * j * inv_fact) * (pw1 * cm[2 * j + 1]);
+      d1t = d1t + (4.0 * j * inv_fact) * (pw1 * cm[2 * j + 2]);
+    }
+    if (j >= 2)
+      d2 = d2 + (4.0 * j * (2.0 * j - 2.0) * inv_fact) * (pw2 * cm[2 * j + 1]);
+    pw2 = pw1;
+    pw1 = pw;
+    pw = pw * u2;
+  }
+  AprilBlocks b;
+  b.phitt = phitt;
+  b.d1 = d1;
+  b.d1t = d1t;
+  b.d2 = d2;
+  return b;
+}
+
+// Complex fields in the paper's axes at dimensionless (X, Y, Z) and tau, with
+// the normalization N folded in.  e[0..2] = E_x, E_y, E_z; b[0..2] = cB.
+__host__ __device__ inline void april_complex_fields(const IncParams &P,
+                                                     double X, double Y,
+                                                     double Z, double tau,
+                                                     cx<double> e[3],
+                                                     cx<double> b[3]) {
+  cx<double> u2 = mk(X * X + Y * Y + Z * Z - 1.0, 2.0 * Z);
+  double m2 = u2.r * u2.r + u2.i * u2.i;
+  AprilBlocks k = (m2 < kRingU2 * kRingU2) ? april_blocks_series(P, u2, tau)
+                                           : april_blocks_closed(P, u2, tau);
+  cx<double> zp = mk(Z, 1.0);
+  if (P.kind == 2) {  // LP
+    cx<double> common = k.d1 - k.phitt + zp * k.d1t;
+    e[0] = (X * X) * k.d2 + common;
+    e[1] = (X * Y) * k.d2;
+    e[2] = X * (zp * k.d2) - X * k.d1t;
+    b[0] = e[1];
+    b[1] = (Y * Y) * k.d2 + common;
+    b[2] = Y * (zp * k.d2) - Y * k.d1t;
+  } else {  // RP: Hertz vector along the propagation axis
+    cx<double> zd2 = zp * k.d2;
+    e[0] = X * zd2;
+    e[1] = Y * zd2;
+    e[2] = k.d1 + zp * zd2 - k.phitt;
+    b[0] = Y * k.d1t;
+    b[1] = -X * k.d1t;
+    b[2] = mk(0.0, 0.0);
+  }
+}
+
+// Real incident field in build axes (propagation +x, LP polarization y) at
+// (x, y, z = 0) and time t.
+__host__ __device__ inline void incident_field(const IncParams &P, int dims,
+                                               double x, double y, double t,
+                                               double E[3], double B[3]) {
+  E[0] = E[1] = E[2] = 0.0;
+  B[0] = B[1] = B[2] = 0.0;
+  if (P.kind == 1) {
+    double ph = t - P.t0 - x;
+    double v = P.a0 * sin(ph) * exp2(P.env_k * ph * ph);
+    E[1] = v;
+    B[2] = v;
+  } else if (P.kind == 2 || P.kind == 3) {
+    double X = (dims == 2 ? (y - P.y_focus) : 0.0) * P.inv_a;  // paper x
+    double Z = (x - P.x_focus) * P.inv_a;                       // paper z
+    cx<double> e[3], b[3];
+    april_complex_fields(P, X, 0.0, Z, t - P.t_focus, e, b);
+    E[0] = e[2].r;  // build x = paper z
+    E[1] = e[0].r;  // build y = paper x
+    E[2] = e[1].r;  // build z = paper y
+    B[0] = b[2].r;
+    B[1] = b[0].r;
+    B[2] = b[1].r;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Kernel launchers (sfpic_kernels.hip)
+// ---------------------------------------------------------------------------
+template <typename R>
+hipError_t launch_faraday(const Fields<R> &f, int dims, double dt, double dx,
+                          double dy, hipStream_t st);
+template <typename R>
+hipError_t launch_ampere(const Fields<R> &f, int dims, double dt, double dx,
+                         double dy, hipStream_t st);
+template <typename R>
+hipError_t launch_push(const Fields<R> &f, const Particles<R> &p, int64_t n,
+                       int dims, const PushParams &pp, const IncParams &inc,
+                       hipStream_t st);
+template <typename R>
+hipError_t launch_init_particles(const Particles<R> &p, int64_t n, int dims,
+                                 int64_t x0, int64_t ncx, int64_t y0,
+                                 int ppc, double sigma, uint64_t seed,
+                                 uint32_t key1, double dx, double dy,
+                                 hipStream_t st);
+template <typename R>
+hipError_t launch_load_particles(const Particles<R> &p, int64_t n, int dims,
+                                 const double *x, const double *y,
+                                 const double *ux, const double *uy,
+                                 const double *uz, double inv_dx,
+                                 double inv_dy, hipStream_t st);
+template <typename R>
+hipError_t launch_export_particles(const Particles<R> &p, int64_t n, int dims,
+                                   double *x, double *y, double *ux,
+                                   double *uy, double *uz, uint32_t *id,
+                                   unsigned long long *count, double dx,
+                                   double dy, hipStream_t st);
+
+// FP64 diagnostics: particle sums {w_kin, charge, n_alive, nonfinite}.
+template <typename R>
+hipError_t launch_particle_sums(const Particles<R> &p, int64_t n, double m,
+                                double q, double wdv, double *acc,
+                                hipStream_t st);
+template <typename R>
+hipError_t launch_field_sums(const Fields<R> &f, double *acc, hipStream_t st);
+template <typename R>
+hipError_t launch_deposit_rho(const Particles<R> &p, int64_t n, int dims,
+                              double qw, double *rho, int pitch,
+                              hipStream_t st);
+template <typename R>
+hipError_t launch_gauss(const Fields<R> &f, int dims, int nx, int ny,
+                        double dx, double dy, const double *rho,
+                        const double *rho0, int rpitch, double *acc,
+                        hipStream_t st);
+template <typename R>
+hipError_t launch_histogram(const Particles<R> &p, int64_t n, double m,
+                            double wdv, int n_e, double emax, int n_t,
+                            double ek_min, double *hist, double *mom,
+                            hipStream_t st);
+
+}  // namespace sfpic
