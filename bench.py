@@ -140,7 +140,7 @@ def main():
                 "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / PEAK_FP64_TFLOPS, 4),
                 "traffic": None,
-                "kernel": "push_kernel_f64<2>",
+                "kernel": "push_tiled_f64<2>",
                 "avg_launch_ms": round(avg_s * 1e3, 4),
                 "hbm_achieved_GBps": round(bytes_ / avg_s / 1e9, 1),
                 "hbm_frac": round(bytes_ / avg_s / 1e9 / PEAK_HBM_GBPS, 4)}
@@ -158,6 +158,8 @@ def main():
                    "particles": work.species[0].count(),
                    "precision": "fp64", "parallelism": "single GPU"},
         "roofline": roofline,
+        "kernel_ms_per_step": {k: round(v[1] / max(v[0], 1), 4) * (
+            v[0] / args.steps) for k, v in stats.items()},
         "checks": {"gauss_residual_rel": diag["gauss_residual"] /
                    max(diag["rho_max"], 1e-300),
                    "nonfinite": diag["nonfinite"], "n_alive": diag["n_alive"]},

@@ -230,9 +230,10 @@ int sfpic_set_state(sfpic_sim *sim, const void *buf, size_t n);
 
 /* Per-kernel timing.  While profiling is on, every kernel launch of the
  * sim's steps is bracketed by HIP events on the sim's stream.  Kernel
- * classes: 0 Faraday (+ centred B, J clear), 1 particle push (gather,
- * incident field, Boris, deposit), 2 Ampere + Mur, 3 tile sort. */
-#define SFPIC_KCLASSES 4
+ * classes: 0 Faraday (+ centred B, J clear), 1 tiled particle push (gather,
+ * incident field, Boris, deposit), 2 Ampere + Mur, 3 cell sort, 4 push of
+ * the particles that left their tile window since the last sort. */
+#define SFPIC_KCLASSES 5
 typedef struct {
   int64_t launches[SFPIC_KCLASSES];
   double total_ms[SFPIC_KCLASSES];

@@ -92,11 +92,11 @@ EXPORTS = ["sfpic_create", "sfpic_step", "sfpic_sync", "sfpic_read_field",
            "sfpic_set_state", "sfpic_profile", "sfpic_profile_read",
            "sfpic_destroy", "sfpic_last_error", "sfpic_version"]
 
-KCLASSES = ("faraday", "push", "ampere", "sort")
+KCLASSES = ("faraday", "push", "ampere", "sort", "stragglers")
 
 
 class sfpic_kernel_stats(C.Structure):
-    _fields_ = [("launches", C.c_int64 * 4), ("total_ms", C.c_double * 4)]
+    _fields_ = [("launches", C.c_int64 * 5), ("total_ms", C.c_double * 5)]
 
 
 def lib():

@@ -9,6 +9,7 @@
 
 #include <new>
 #include <string>
+#include <utility>
 #include <vector>
 
 using namespace sfpic;
@@ -32,9 +33,11 @@ int fail(int code, const std::string &msg) {
 
 struct SpeciesState {
   double q = -1.0, m = 1.0, weight = 0.0;
-  int64_t n = 0;  // slots (live + removed)
-  Particles<double> p64{};
-  Particles<float> p32{};
+  int64_t n = 0;               // slots (capacity)
+  uint32_t *n_valid = nullptr; // device: slots in use (live or removed)
+  uint32_t *start = nullptr;   // device: cell start offsets (nkeys + 1)
+  Particles<double> p64{}, p64_alt{};
+  Particles<float> p32{}, p32_alt{};
 };
 
 constexpr uint64_t kStateMagic = 0x53465049435354ull;  // "SFPICST"
@@ -53,6 +56,11 @@ struct sfpic_sim {
   Fields<float> f32{};
   void *planes[12] = {};
   std::vector<SpeciesState> sp;
+  TileGeom tg{};
+  SortScratch ss{};
+  int sort_every = 4;
+  int64_t since_sort = 0;
+  uint32_t *strag = nullptr, *n_strag = nullptr;  // straggler list
   double *rho0 = nullptr, *rho = nullptr, *acc = nullptr;
   std::vector<std::pair<void *, size_t>> allocs;
   // profiling: event pairs per kernel class, recorded in launch order
@@ -196,14 +204,21 @@ void set_field_ptrs(Fields<R> &f, void *const planes[12], int NX, int NY,
 int alloc_species(sfpic_sim *s, SpeciesState &st, int64_t n) {
   st.n = n;
   const size_t cnt = (size_t)(n > 0 ? n : 1);
+  st.n_valid = (uint32_t *)s->dalloc(4);
+  if (!st.n_valid) return fail(SFPIC_E_NOMEM, "particle allocation failed");
   if (s->precision == SFPIC_FP64) {
-    double **arr[5] = {&st.p64.px, &st.p64.py, &st.p64.ux, &st.p64.uy, &st.p64.uz};
-    for (auto a : arr) {
-      *a = (double *)s->dalloc(cnt * 8);
-      if (!*a) return fail(SFPIC_E_NOMEM, "particle allocation failed");
+    for (Particles<double> *q : {&st.p64, &st.p64_alt}) {
+      double **arr[5] = {&q->px, &q->py, &q->ux, &q->uy, &q->uz};
+      for (auto a : arr) {
+        *a = (double *)s->dalloc(cnt * 8);
+        if (!*a) return fail(SFPIC_E_NOMEM, "particle allocation failed");
+      }
+      q->id = (uint32_t *)s->dalloc(cnt * 4);
+      if (!q->id) return fail(SFPIC_E_NOMEM, "particle allocation failed");
     }
-    st.p64.id = (uint32_t *)s->dalloc(cnt * 4);
-    if (!st.p64.id) return fail(SFPIC_E_NOMEM, "particle allocation failed");
+    const uint32_t nv = (uint32_t)n;
+    if (hipMemcpy(st.n_valid, &nv, 4, hipMemcpyHostToDevice) != hipSuccess)
+      return fail(SFPIC_E_DEVICE, "hipMemcpy failed");
   } else {
     return fail(SFPIC_E_INVAL, "FP32 precision is not available in this build");
   }
@@ -286,9 +301,73 @@ int deposit_rho(sfpic_sim *s, double *rho) {
   const size_t bytes = (size_t)s->NY * s->pitch * 8;
   HIP_TRY(hipMemsetAsync(rho, 0, bytes, s->stream));
   for (auto &st : s->sp)
-    HIP_TRY(launch_deposit_rho<double>(st.p64, st.n, s->grid.dims,
+    HIP_TRY(launch_deposit_rho<double>(st.p64, st.n, st.n_valid, s->grid.dims,
                                        st.q * st.weight, rho, s->pitch,
                                        s->stream));
+  return SFPIC_OK;
+}
+
+int setup_tiles(sfpic_sim *s) {
+  const sfpic_grid &g = s->grid;
+  TileGeom &t = s->tg;
+  int max_lds = 64 * 1024;
+  (void)hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock,
+                              s->rt.device);
+  if (g.dims == 1) {
+    t.tx = s->rt.tile_x > 0 ? s->rt.tile_x : 256;
+    t.ty = 1;
+  } else {
+    t.tx = s->rt.tile_x > 0 ? s->rt.tile_x : 16;
+    t.ty = s->rt.tile_y > 0 ? s->rt.tile_y : 8;
+    if (s->rt.tile_x <= 0 && s->rt.tile_y <= 0 && s->precision == SFPIC_FP64 &&
+        push_lds_bytes<double>(t, 2) > (size_t)max_lds)
+      t.tx = 8;  // 8 x 8 tiles fit a 64 KB workgroup limit
+  }
+  if (t.tx < 1 || t.ty < 1 || t.tx > 1024 || t.ty > 256)
+    return fail(SFPIC_E_INVAL, "tile size out of range");
+  t.ntx = (int)((g.nx + t.tx - 1) / t.tx);
+  t.nty = (g.dims == 2) ? (int)((g.ny + t.ty - 1) / t.ty) : 1;
+  t.ntiles = t.ntx * t.nty;
+  t.cells_per_tile = (uint32_t)(t.tx * t.ty);
+  const uint64_t nk = (uint64_t)t.ntiles * t.cells_per_tile;
+  if (nk >= 0xFFFFFFF0ull) return fail(SFPIC_E_INVAL, "too many cells");
+  t.nkeys = (uint32_t)nk;
+  const size_t lds = s->precision == SFPIC_FP64
+                         ? push_lds_bytes<double>(t, g.dims)
+                         : (size_t)0;
+  if (lds > (size_t)max_lds) return fail(SFPIC_E_INVAL, "tile too large for LDS");
+  if (s->rt.sort_every > 0) s->sort_every = s->rt.sort_every;
+  const size_t nk1 = (size_t)t.nkeys + 1;
+  s->ss.counts = (uint32_t *)s->dalloc(nk1 * 4);
+  for (auto &st : s->sp) {
+    st.start = (uint32_t *)s->dalloc(nk1 * 4);
+    if (!st.start) return fail(SFPIC_E_NOMEM, "sort allocation failed");
+  }
+  s->ss.block_sums = (uint32_t *)s->dalloc(((nk1 + 1023) / 1024 + 1) * 4);
+  int64_t nmax = 1;
+  for (auto &st : s->sp) nmax = st.n > nmax ? st.n : nmax;
+  s->ss.key = (uint32_t *)s->dalloc((size_t)nmax * 4);
+  s->ss.rank = (uint32_t *)s->dalloc((size_t)nmax * 4);
+  s->strag = (uint32_t *)s->dalloc((size_t)nmax * 4);
+  s->n_strag = (uint32_t *)s->dalloc(4);
+  if (!s->strag || !s->n_strag)
+    return fail(SFPIC_E_NOMEM, "straggler list allocation failed");
+  if (!s->ss.counts || !s->ss.block_sums || !s->ss.key ||
+      !s->ss.rank)
+    return fail(SFPIC_E_NOMEM, "sort scratch allocation failed");
+  return SFPIC_OK;
+}
+
+// Counting sort of every species by cell (compacts removed particles).
+int sort_all(sfpic_sim *s) {
+  for (auto &st : s->sp) {
+    HIP_TRY(launch_sort<double>(st.p64, st.p64_alt, (uint32_t)st.n, st.n_valid,
+                                st.start, s->tg, (int)s->grid.nx,
+                                (int)s->grid.ny, s->grid.dims, s->ss,
+                                s->stream));
+    std::swap(st.p64, st.p64_alt);
+  }
+  s->since_sort = 0;
   return SFPIC_OK;
 }
 
@@ -371,6 +450,8 @@ int sfpic_create(const sfpic_grid *grid, const sfpic_species *species,
       r = place_species(s, s->sp[k], species[k], k);
       if (r) return bail(r);
     }
+    r = setup_tiles(s);
+    if (r) return bail(r);
     const size_t rbytes = (size_t)s->NY * s->pitch * 8;
     s->rho0 = (double *)s->dalloc(rbytes);
     s->rho = (double *)s->dalloc(rbytes);
@@ -378,6 +459,8 @@ int sfpic_create(const sfpic_grid *grid, const sfpic_species *species,
     if (!s->rho0 || !s->rho || !s->acc)
       return bail(fail(SFPIC_E_NOMEM, "diagnostic allocation failed"));
     r = deposit_rho(s, s->rho0);
+    if (r) return bail(r);
+    r = sort_all(s);
     if (r) return bail(r);
     if (hipStreamSynchronize(s->stream) != hipSuccess)
       return bail(fail(SFPIC_E_DEVICE, "initialization failed"));
@@ -394,6 +477,11 @@ int sfpic_step(sfpic_sim *s, int64_t nsteps) {
   if (nsteps < 0) return fail(SFPIC_E_INVAL, "nsteps < 0");
   const sfpic_grid &g = s->grid;
   for (int64_t k = 0; k < nsteps; ++k) {
+    if (s->since_sort >= s->sort_every) {
+      HIP_TRY(timed(s, 3, [&] {
+        return sort_all(s) == SFPIC_OK ? hipSuccess : hipErrorUnknown;
+      }));
+    }
     HIP_TRY(timed(s, 0, [&] {
       return launch_faraday<double>(s->f64, g.dims, g.dt, g.dx, g.dy, s->stream);
     }));
@@ -410,14 +498,21 @@ int sfpic_step(sfpic_sim *s, int64_t nsteps) {
       pp.nx = (int)g.nx;
       pp.ny = (int)g.ny;
       HIP_TRY(timed(s, 1, [&] {
-        return launch_push<double>(s->f64, st.p64, st.n, g.dims, pp, s->inc,
-                                   s->stream);
+        return launch_push_tiled<double>(s->f64, st.p64, st.start, s->tg,
+                                         g.dims, pp, s->inc, s->strag,
+                                         s->n_strag, s->stream);
+      }));
+      HIP_TRY(timed(s, 4, [&] {
+        return launch_push_stragglers<double>(s->f64, st.p64, g.dims, pp,
+                                              s->inc, s->strag, s->n_strag,
+                                              s->stream);
       }));
     }
     HIP_TRY(timed(s, 2, [&] {
       return launch_ampere<double>(s->f64, g.dims, g.dt, g.dx, g.dy, s->stream);
     }));
     s->step++;
+    s->since_sort++;
   }
   return SFPIC_OK;
 }
@@ -470,8 +565,8 @@ int sfpic_particle_count(sfpic_sim *s, int species, int64_t *n) {
     return fail(SFPIC_E_INVAL, "bad species");
   SpeciesState &st = s->sp[species];
   HIP_TRY(hipMemsetAsync(s->acc, 0, 8 * 8, s->stream));
-  HIP_TRY(launch_particle_sums<double>(st.p64, st.n, st.m, st.q, 0.0, s->acc,
-                                       s->stream));
+  HIP_TRY(launch_particle_sums<double>(st.p64, st.n, st.n_valid, st.m, st.q,
+                                       0.0, s->acc, s->stream));
   double h[8];
   HIP_TRY(hipMemcpyAsync(h, s->acc, 8 * 8, hipMemcpyDeviceToHost, s->stream));
   HIP_TRY(hipStreamSynchronize(s->stream));
@@ -490,10 +585,12 @@ int sfpic_read_particles(sfpic_sim *s, int species, double *x, double *y,
     return fail(SFPIC_E_INVAL, "NULL output array");
   try {
     SpeciesState &st = s->sp[species];
-    const size_t n = (size_t)st.n;
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    uint32_t nv = 0;
+    HIP_TRY(hipMemcpy(&nv, st.n_valid, 4, hipMemcpyDeviceToHost));
+    const size_t n = nv;
     std::vector<double> hx(n), hy(n), hux(n), huy(n), huz(n);
     std::vector<uint32_t> hid(n);
-    HIP_TRY(hipStreamSynchronize(s->stream));
     if (n) {
       HIP_TRY(hipMemcpy(hx.data(), st.p64.px, n * 8, hipMemcpyDeviceToHost));
       if (s->grid.dims == 2)
@@ -531,7 +628,7 @@ int sfpic_diagnostics(sfpic_sim *s, sfpic_diag *out) {
   const double dv = s->cell_volume();
   HIP_TRY(hipMemsetAsync(s->acc, 0, 8 * 8, s->stream));
   for (auto &st : s->sp)
-    HIP_TRY(launch_particle_sums<double>(st.p64, st.n, st.m, st.q,
+    HIP_TRY(launch_particle_sums<double>(st.p64, st.n, st.n_valid, st.m, st.q,
                                          st.weight * dv, s->acc, s->stream));
   HIP_TRY(launch_field_sums<double>(s->f64, s->acc, s->stream));
   r = deposit_rho(s, s->rho);
@@ -570,7 +667,8 @@ int sfpic_histogram(sfpic_sim *s, const sfpic_hist_spec *spec, double *out,
   int rc = SFPIC_OK;
   double mom[8] = {0};
   if (hipMemsetAsync(d, 0, (nb + 8) * 8, s->stream) != hipSuccess ||
-      launch_histogram<double>(st.p64, st.n, st.m, st.weight * s->cell_volume(),
+      launch_histogram<double>(st.p64, st.n, st.n_valid, st.m,
+                               st.weight * s->cell_volume(),
                                spec->n_energy, spec->e_max, spec->n_theta,
                                spec->ek_min, d + 8, d, s->stream) != hipSuccess ||
       hipMemcpyAsync(out, d + 8, nb * 8, hipMemcpyDeviceToHost, s->stream) != hipSuccess ||
@@ -602,14 +700,17 @@ int sfpic_get_state(sfpic_sim *s, void *buf, size_t *n) {
   if (r) return r;
   if (!n) return fail(SFPIC_E_INVAL, "n is NULL");
   const size_t es = s->esize();
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  std::vector<uint32_t> nv(s->sp.size());
+  for (size_t k = 0; k < s->sp.size(); ++k)
+    HIP_TRY(hipMemcpy(&nv[k], s->sp[k].n_valid, 4, hipMemcpyDeviceToHost));
   size_t need = 8 * 8 + 9 * (size_t)s->NX * s->NY * es;
-  for (auto &st : s->sp) need += 8 + (size_t)st.n * (5 * es + 4);
+  for (size_t k = 0; k < s->sp.size(); ++k) need += 8 + (size_t)nv[k] * (5 * es + 4);
   if (!buf) {
     *n = need;
     return SFPIC_OK;
   }
   if (*n < need) return fail(SFPIC_E_SIZE, "state buffer too small");
-  HIP_TRY(hipStreamSynchronize(s->stream));
   uint8_t *p = (uint8_t *)buf;
   int64_t hdr[8] = {(int64_t)kStateMagic, s->grid.dims, s->grid.nx, s->grid.ny,
                     s->precision, (int64_t)s->sp.size(), s->step, (int64_t)es};
@@ -620,17 +721,19 @@ int sfpic_get_state(sfpic_sim *s, void *buf, size_t *n) {
                         (size_t)s->NX * es, s->NY, hipMemcpyDeviceToHost));
     p += (size_t)s->NX * s->NY * es;
   }
-  for (auto &st : s->sp) {
-    memcpy(p, &st.n, 8);
+  for (size_t k = 0; k < s->sp.size(); ++k) {
+    SpeciesState &st = s->sp[k];
+    const int64_t cnt = nv[k];
+    memcpy(p, &cnt, 8);
     p += 8;
-    const size_t bytes = (size_t)st.n * es;
+    const size_t bytes = (size_t)cnt * es;
     void *arrs[5] = {st.p64.px, st.p64.py, st.p64.ux, st.p64.uy, st.p64.uz};
     for (auto a : arrs) {
       if (bytes) HIP_TRY(hipMemcpy(p, a, bytes, hipMemcpyDeviceToHost));
       p += bytes;
     }
-    if (st.n) HIP_TRY(hipMemcpy(p, st.p64.id, (size_t)st.n * 4, hipMemcpyDeviceToHost));
-    p += (size_t)st.n * 4;
+    if (cnt) HIP_TRY(hipMemcpy(p, st.p64.id, (size_t)cnt * 4, hipMemcpyDeviceToHost));
+    p += (size_t)cnt * 4;
   }
   *n = need;
   return SFPIC_OK;
@@ -643,37 +746,53 @@ int sfpic_set_state(sfpic_sim *s, const void *buf, size_t n) {
   const size_t es = s->esize();
   if (n < 64) return fail(SFPIC_E_SIZE, "state too short");
   const uint8_t *p = (const uint8_t *)buf;
+  const uint8_t *end = p + n;
   int64_t hdr[8];
   memcpy(hdr, p, sizeof(hdr));
   if (hdr[0] != (int64_t)kStateMagic || hdr[1] != s->grid.dims ||
       hdr[2] != s->grid.nx || hdr[3] != s->grid.ny || hdr[4] != s->precision ||
       hdr[5] != (int64_t)s->sp.size() || hdr[7] != (int64_t)es)
     return fail(SFPIC_E_INVAL, "state does not match this sim");
-  size_t need = 64 + 9 * (size_t)s->NX * s->NY * es;
-  for (auto &st : s->sp) need += 8 + (size_t)st.n * (5 * es + 4);
-  if (n != need) return fail(SFPIC_E_SIZE, "state size does not match this sim");
   p += 64;
+  const size_t plane = (size_t)s->NX * s->NY * es;
+  if ((size_t)(end - p) < 9 * plane) return fail(SFPIC_E_SIZE, "state truncated");
+  // validate the particle blocks before touching device state
+  const uint8_t *q = p + 9 * plane;
+  for (auto &st : s->sp) {
+    if (end - q < 8) return fail(SFPIC_E_SIZE, "state truncated");
+    int64_t cnt;
+    memcpy(&cnt, q, 8);
+    if (cnt < 0 || cnt > st.n)
+      return fail(SFPIC_E_INVAL, "particle count exceeds this sim's capacity");
+    q += 8 + (size_t)cnt * (5 * es + 4);
+    if (q > end) return fail(SFPIC_E_SIZE, "state truncated");
+  }
+  if (q != end) return fail(SFPIC_E_SIZE, "state size does not match this sim");
   HIP_TRY(hipStreamSynchronize(s->stream));
   for (int c = 0; c < 9; ++c) {
     HIP_TRY(hipMemcpy2D(s->planes[c], (size_t)s->pitch * es, p, (size_t)s->NX * es,
                         (size_t)s->NX * es, s->NY, hipMemcpyHostToDevice));
-    p += (size_t)s->NX * s->NY * es;
+    p += plane;
   }
   for (auto &st : s->sp) {
     int64_t cnt;
     memcpy(&cnt, p, 8);
-    if (cnt != st.n) return fail(SFPIC_E_INVAL, "particle slot count mismatch");
     p += 8;
-    const size_t bytes = (size_t)st.n * es;
+    const size_t bytes = (size_t)cnt * es;
     void *arrs[5] = {st.p64.px, st.p64.py, st.p64.ux, st.p64.uy, st.p64.uz};
     for (auto a : arrs) {
       if (bytes) HIP_TRY(hipMemcpy(a, p, bytes, hipMemcpyHostToDevice));
       p += bytes;
     }
-    if (st.n) HIP_TRY(hipMemcpy(st.p64.id, p, (size_t)st.n * 4, hipMemcpyHostToDevice));
-    p += (size_t)st.n * 4;
+    if (cnt) HIP_TRY(hipMemcpy(st.p64.id, p, (size_t)cnt * 4, hipMemcpyHostToDevice));
+    p += (size_t)cnt * 4;
+    const uint32_t nv = (uint32_t)cnt;
+    HIP_TRY(hipMemcpy(st.n_valid, &nv, 4, hipMemcpyHostToDevice));
   }
   s->step = hdr[6];
+  r = sort_all(s);
+  if (r) return r;
+  HIP_TRY(hipStreamSynchronize(s->stream));
   return SFPIC_OK;
 }
 

@@ -62,6 +62,24 @@ struct Particles<float> {
   uint32_t *id;
 };
 
+// Particle tiles: tx x ty cells (ty = 1 in 1D).  Cells are keyed tile-major:
+// key = tile * cells_per_tile + (iy mod ty) * tx + (ix mod tx).
+struct TileGeom {
+  int tx, ty;
+  int ntx, nty, ntiles;
+  uint32_t cells_per_tile;
+  uint32_t nkeys;  // ntiles * cells_per_tile
+};
+
+// Scratch of the counting sort (shared by the species of one sim; each
+// species keeps its own `start` array, the exclusive scan of the counts,
+// which also gives its tile ranges until the next sort).
+struct SortScratch {
+  uint32_t *counts;      // nkeys + 1
+  uint32_t *block_sums;  // ceil((nkeys + 1) / 1024)
+  uint32_t *key, *rank;  // per particle slot
+};
+
 // Per-step scalars of one species push.
 struct PushParams {
   double dt, dx, dy;
@@ -185,36 +203,39 @@ __host__ __device__ inline AprilBlocks april_blocks_closed(const IncParams &P,
   return b;
 }
 
-__host__ __device__ inline AprilBlocks april_blocks_series(const IncParams &P,
+// Rare branch (particles near the ring): kept out of line so its registers do
+// not add to those of the common closed-form path.
+static __host__ __device__ __attribute__((noinline)) AprilBlocks
+april_blocks_series(const IncParams &P,
                                                             cx<double> u2,
                                                             double tau) {
   // c_m = N e^{i phi0} [prod_{k<=m} (s+k)] (i a/s)^m (1 + a/s - i tau/s)^{-(s+m+1)}
+  // generated in order: c_{m} = (s + m) (i a/s) base c_{m-1}.
   cx<double> base = cinv(mk(1.0 + P.a_over_s, -tau * P.inv_s));
-  cx<double> c = mk(P.e_phase_r, P.e_phase_i) * cpowi(base, P.s_int + 1);
   const double s = (double)P.s_int;
-  cx<double> step_b = mk(0.0, P.a_over_s) * base;  // (i a/s) * base
+  const cx<double> step_b = mk(0.0, P.a_over_s) * base;
+  cx<double> c = mk(P.e_phase_r, P.e_phase_i) * cpowi(base, P.s_int + 1);
+  c = (s + 1.0) * (c * step_b);  // c_1
   cx<double> phitt = mk(0.0, 0.0), d1 = phitt, d1t = phitt, d2 = phitt;
-  cx<double> cm[2 * kRingTerms + 4];
-  cm[0] = c;
-  for (int m = 1; m < 2 * kRingTerms + 4; ++m) {
-    c = (s + m) * (c * step_b);
-    cm[m] = c;
-  }
   cx<double> pw = mk(1.0, 0.0), pw1 = mk(0.0, 0.0), pw2 = mk(0.0, 0.0);
   double inv_fact = 1.0;  // 1/(2j+1)!
+#pragma unroll 1
   for (int j = 0; j < kRingTerms; ++j) {
     if (j > 0) inv_fact /= (2.0 * j) * (2.0 * j + 1.0);
+    const cx<double> c1 = c;                                      // c_{2j+1}
+    const cx<double> c2 = (s + 2.0 * j + 2.0) * (c1 * step_b);    // c_{2j+2}
+    const cx<double> c3 = (s + 2.0 * j + 3.0) * (c2 * step_b);    // c_{2j+3}
     // pw = u^{2j}, pw1 = u^{2j-2}, pw2 = u^{2j-4}
-    phitt = phitt + (2.0 * inv_fact) * (pw * cm[2 * j + 3]);
+    phitt = phitt + (2.0 * inv_fact) * (pw * c3);
     if (j >= 1) {
-      d1 = d1 + (4.0 * j * inv_fact) * (pw1 * cm[2 * j + 1]);
-      d1t = d1t + (4.0 * j * inv_fact) * (pw1 * cm[2 * j + 2]);
+      d1 = d1 + (4.0 * j * inv_fact) * (pw1 * c1);
+      d1t = d1t + (4.0 * j * inv_fact) * (pw1 * c2);
     }
-    if (j >= 2)
-      d2 = d2 + (4.0 * j * (2.0 * j - 2.0) * inv_fact) * (pw2 * cm[2 * j + 1]);
+    if (j >= 2) d2 = d2 + (4.0 * j * (2.0 * j - 2.0) * inv_fact) * (pw2 * c1);
     pw2 = pw1;
     pw1 = pw;
     pw = pw * u2;
+    c = c3;
   }
   AprilBlocks b;
   b.phitt = phitt;
@@ -291,9 +312,27 @@ template <typename R>
 hipError_t launch_ampere(const Fields<R> &f, int dims, double dt, double dx,
                          double dy, hipStream_t st);
 template <typename R>
-hipError_t launch_push(const Fields<R> &f, const Particles<R> &p, int64_t n,
-                       int dims, const PushParams &pp, const IncParams &inc,
-                       hipStream_t st);
+size_t push_lds_bytes(const TileGeom &tg, int dims);
+// Tiled push; particles that drifted out of their tile window are appended
+// to strag (count in *n_strag, reset by the launcher) for the straggler push.
+template <typename R>
+hipError_t launch_push_tiled(const Fields<R> &f, const Particles<R> &p,
+                             const uint32_t *start, const TileGeom &tg,
+                             int dims, const PushParams &pp,
+                             const IncParams &inc, uint32_t *strag,
+                             uint32_t *n_strag, hipStream_t st);
+template <typename R>
+hipError_t launch_push_stragglers(const Fields<R> &f, const Particles<R> &p,
+                                  int dims, const PushParams &pp,
+                                  const IncParams &inc, const uint32_t *strag,
+                                  const uint32_t *n_strag, hipStream_t st);
+// Sort src into dst by cell key; n_valid (device) holds the number of used
+// slots of src on entry and of dst on exit.
+template <typename R>
+hipError_t launch_sort(const Particles<R> &src, const Particles<R> &dst,
+                       uint32_t n_slots, uint32_t *n_valid, uint32_t *start,
+                       const TileGeom &tg, int nx, int ny, int dims,
+                       const SortScratch &s, hipStream_t st);
 template <typename R>
 hipError_t launch_init_particles(const Particles<R> &p, int64_t n, int dims,
                                  int64_t x0, int64_t ncx, int64_t y0,
@@ -306,33 +345,26 @@ hipError_t launch_load_particles(const Particles<R> &p, int64_t n, int dims,
                                  const double *ux, const double *uy,
                                  const double *uz, double inv_dx,
                                  double inv_dy, hipStream_t st);
-template <typename R>
-hipError_t launch_export_particles(const Particles<R> &p, int64_t n, int dims,
-                                   double *x, double *y, double *ux,
-                                   double *uy, double *uz, uint32_t *id,
-                                   unsigned long long *count, double dx,
-                                   double dy, hipStream_t st);
-
 // FP64 diagnostics: particle sums {w_kin, charge, n_alive, nonfinite}.
 template <typename R>
-hipError_t launch_particle_sums(const Particles<R> &p, int64_t n, double m,
-                                double q, double wdv, double *acc,
-                                hipStream_t st);
+hipError_t launch_particle_sums(const Particles<R> &p, int64_t n,
+                                const uint32_t *n_valid, double m, double q,
+                                double wdv, double *acc, hipStream_t st);
 template <typename R>
 hipError_t launch_field_sums(const Fields<R> &f, double *acc, hipStream_t st);
 template <typename R>
-hipError_t launch_deposit_rho(const Particles<R> &p, int64_t n, int dims,
-                              double qw, double *rho, int pitch,
-                              hipStream_t st);
+hipError_t launch_deposit_rho(const Particles<R> &p, int64_t n,
+                              const uint32_t *n_valid, int dims, double qw,
+                              double *rho, int pitch, hipStream_t st);
 template <typename R>
 hipError_t launch_gauss(const Fields<R> &f, int dims, int nx, int ny,
                         double dx, double dy, const double *rho,
                         const double *rho0, int rpitch, double *acc,
                         hipStream_t st);
 template <typename R>
-hipError_t launch_histogram(const Particles<R> &p, int64_t n, double m,
-                            double wdv, int n_e, double emax, int n_t,
-                            double ek_min, double *hist, double *mom,
-                            hipStream_t st);
+hipError_t launch_histogram(const Particles<R> &p, int64_t n,
+                            const uint32_t *n_valid, double m, double wdv,
+                            int n_e, double emax, int n_t, double ek_min,
+                            double *hist, double *mom, hipStream_t st);
 
 }  // namespace sfpic

@@ -3,6 +3,7 @@
 // field at the particle, Boris push, Esirkepov deposition; plus particle
 // placement and FP64 diagnostics.
 #include "sfpic_common.h"
+#include "sfpic_device.h"
 
 #include <math.h>
 
@@ -167,264 +168,8 @@ hipError_t launch_ampere(const Fields<R> &f, int dims, double dt, double dx,
 
 
 // ---------------------------------------------------------------------------
-// Particles: order-2 shapes
+// Particle placement (Philox4x32-10 counter-based draws, see sfpic_device.h)
 // ---------------------------------------------------------------------------
-
-// Three quadratic B-spline weights for offset d in [-1/2, 1/2] from the
-// nearest node (nodes -1, 0, +1).
-template <typename R>
-__device__ __forceinline__ void weights3(R d, R w[3]) {
-  const R a = R(0.5) - d, b = R(0.5) + d;
-  w[0] = R(0.5) * a * a;
-  w[1] = R(0.75) - d * d;
-  w[2] = R(0.5) * b * b;
-}
-
-// Quadratic B-spline at distance d (cell units).
-template <typename R>
-__device__ __forceinline__ R spline2(R d) {
-  const R a = fabs(d);
-  const R b = R(1.5) - a;
-  return a <= R(0.5) ? R(0.75) - a * a : (a <= R(1.5) ? R(0.5) * b * b : R(0));
-}
-
-// Weighted 3-tap (1D) or 3x3-tap (2D) gather from one field plane; (bx, by)
-// is the array index of the first tap.
-template <typename R, int DIMS>
-__device__ __forceinline__ R gather_plane(const R *__restrict__ a, int P,
-                                          int bx, int by, const R wx[3],
-                                          const R wy[3]) {
-  if (DIMS == 1) return wx[0] * a[bx] + wx[1] * a[bx + 1] + wx[2] * a[bx + 2];
-  R v = R(0);
-#pragma unroll
-  for (int b = 0; b < 3; ++b) {
-    const R *row = a + (size_t)(by + b) * P + bx;
-    v += wy[b] * (wx[0] * row[0] + wx[1] * row[1] + wx[2] * row[2]);
-  }
-  return v;
-}
-
-// Boris rotation (Boris 1970) of u = gamma v for charge-to-mass ratio qm.
-template <typename R>
-__device__ __forceinline__ void boris(R qm, R dt, R u[3], const R E[3],
-                                      const R B[3]) {
-  const R h = R(0.5) * qm * dt;
-  const R um0 = u[0] + h * E[0], um1 = u[1] + h * E[1], um2 = u[2] + h * E[2];
-  const R gi = R(1) / sqrt(R(1) + um0 * um0 + um1 * um1 + um2 * um2);
-  const R t0 = h * B[0] * gi, t1 = h * B[1] * gi, t2 = h * B[2] * gi;
-  const R f = R(2) / (R(1) + t0 * t0 + t1 * t1 + t2 * t2);
-  const R s0 = f * t0, s1 = f * t1, s2 = f * t2;
-  const R up0 = um0 + (um1 * t2 - um2 * t1);
-  const R up1 = um1 + (um2 * t0 - um0 * t2);
-  const R up2 = um2 + (um0 * t1 - um1 * t0);
-  u[0] = um0 + (up1 * s2 - up2 * s1) + h * E[0];
-  u[1] = um1 + (up2 * s0 - up0 * s2) + h * E[1];
-  u[2] = um2 + (up0 * s1 - up1 * s0) + h * E[2];
-}
-
-// ---------------------------------------------------------------------------
-// Push: gather + incident field + Boris + advance + Esirkepov deposit.
-// One thread per particle; the current goes to the grid by global atomics.
-// ---------------------------------------------------------------------------
-template <int DIMS>
-__global__ void __launch_bounds__(256)
-push_kernel_f64(Fields<double> f, Particles<double> p, int64_t n,
-                PushParams pp, IncParams inc) {
-  const int64_t ip = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (ip >= n) return;
-  const double xi = p.px[ip];
-  if (xi < -1.0) return;  // removed
-  const double yi = (DIMS == 2) ? p.py[ip] : 0.0;
-  const int P = f.pitch;
-
-  // nearest primal / dual nodes and offsets
-  const int ix = (int)floor(xi);
-  const double fx = xi - ix;
-  const int hx = fx >= 0.5;
-  const int ipx = ix + hx;
-  const double dpx = fx - hx;
-  double wxp[3], wxd[3], wyp[3] = {1, 0, 0}, wyd[3] = {1, 0, 0};
-  weights3(dpx, wxp);
-  weights3(fx - 0.5, wxd);
-  int iy = 0, ipy = 0;
-  double dpy = 0.0;
-  if (DIMS == 2) {
-    iy = (int)floor(yi);
-    const double fy = yi - iy;
-    const int hy = fy >= 0.5;
-    ipy = iy + hy;
-    dpy = fy - hy;
-    weights3(dpy, wyp);
-    weights3(fy - 0.5, wyd);
-  }
-  const int bxp = ipx - 1 + kGuard, bxd = ix - 1 + kGuard;
-  const int byp = (DIMS == 2) ? ipy - 1 + kGuard : 0;
-  const int byd = (DIMS == 2) ? iy - 1 + kGuard : 0;
-
-  double E[3], B[3];
-  E[0] = gather_plane<double, DIMS>(f.ex, P, bxd, byp, wxd, wyp);
-  E[1] = gather_plane<double, DIMS>(f.ey, P, bxp, byd, wxp, wyd);
-  E[2] = gather_plane<double, DIMS>(f.ez, P, bxp, byp, wxp, wyp);
-  B[0] = (DIMS == 2) ? gather_plane<double, DIMS>(f.mx, P, bxp, byd, wxp, wyd)
-                     : 0.0;
-  B[1] = gather_plane<double, DIMS>(f.my, P, bxd, byp, wxd, wyp);
-  B[2] = gather_plane<double, DIMS>(f.mz, P, bxd, byd, wxd, wyd);
-
-  // incident field at (x^n, t^n), superposed on the scattered field
-  double Ei[3], Bi[3];
-  incident_field(inc, DIMS, xi * pp.dx, yi * pp.dy, pp.time, Ei, Bi);
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    E[c] += Ei[c];
-    B[c] += Bi[c];
-  }
-
-  double u[3] = {p.ux[ip], p.uy[ip], p.uz[ip]};
-  boris(pp.qm, pp.dt, u, E, B);
-  const double gi = 1.0 / sqrt(1.0 + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
-  const double xi1 = xi + pp.dt * pp.inv_dx * (u[0] * gi);
-  const double yi1 = (DIMS == 2) ? yi + pp.dt * pp.inv_dy * (u[1] * gi) : 0.0;
-
-  // Esirkepov: shapes at x^n and x^{n+1} on the 5 nodes around ipx
-  double S0x[5], S1x[5];
-  S0x[0] = 0.0;
-  S0x[1] = wxp[0];
-  S0x[2] = wxp[1];
-  S0x[3] = wxp[2];
-  S0x[4] = 0.0;
-  const double d1x = xi1 - ipx;
-#pragma unroll
-  for (int k = 0; k < 5; ++k) S1x[k] = spline2(d1x - (k - 2));
-  double* jx = f.jx;
-  double* jy = f.jy;
-  double* jz = f.jz;
-  if (DIMS == 1) {
-    const double cxq = -pp.qw * pp.dx / pp.dt;
-    double acc = 0.0;
-    const int b0 = ipx - 2 + kGuard;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      acc += cxq * (S1x[k] - S0x[k]);
-      if (acc != 0.0) unsafeAtomicAdd(&jx[b0 + k], acc);
-    }
-    const double qvy = pp.qw * u[1] * gi, qvz = pp.qw * u[2] * gi;
-#pragma unroll
-    for (int k = 0; k < 5; ++k) {
-      const double wv = 0.5 * (S0x[k] + S1x[k]);
-      if (wv != 0.0) {
-        unsafeAtomicAdd(&jy[b0 + k], qvy * wv);
-        unsafeAtomicAdd(&jz[b0 + k], qvz * wv);
-      }
-    }
-  } else {
-    double S0y[5], S1y[5];
-    S0y[0] = 0.0;
-    S0y[1] = wyp[0];
-    S0y[2] = wyp[1];
-    S0y[3] = wyp[2];
-    S0y[4] = 0.0;
-    const double d1y = yi1 - ipy;
-#pragma unroll
-    for (int k = 0; k < 5; ++k) S1y[k] = spline2(d1y - (k - 2));
-    double DSx[5], DSy[5];
-#pragma unroll
-    for (int k = 0; k < 5; ++k) {
-      DSx[k] = S1x[k] - S0x[k];
-      DSy[k] = S1y[k] - S0y[k];
-    }
-    const double cxq = -pp.qw * pp.dx / pp.dt;
-    const double cyq = -pp.qw * pp.dy / pp.dt;
-    const double qvz = pp.qw * u[2] * gi;
-    const int bx0 = ipx - 2 + kGuard, by0 = ipy - 2 + kGuard;
-#pragma unroll
-    for (int b = 0; b < 5; ++b) {
-      const double wyb = S0y[b] + 0.5 * DSy[b];
-      double acc = 0.0;
-      double *row = jx + (size_t)(by0 + b) * P + bx0;
-#pragma unroll
-      for (int a = 0; a < 4; ++a) {
-        acc += cxq * (DSx[a] * wyb);
-        if (acc != 0.0) unsafeAtomicAdd(&row[a], acc);
-      }
-    }
-#pragma unroll
-    for (int a = 0; a < 5; ++a) {
-      const double wxa = S0x[a] + 0.5 * DSx[a];
-      double acc = 0.0;
-#pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        acc += cyq * (DSy[b] * wxa);
-        if (acc != 0.0)
-          unsafeAtomicAdd(&jy[(size_t)(by0 + b) * P + bx0 + a], acc);
-      }
-    }
-#pragma unroll
-    for (int b = 0; b < 5; ++b) {
-      double *row = jz + (size_t)(by0 + b) * P + bx0;
-#pragma unroll
-      for (int a = 0; a < 5; ++a) {
-        const double wz = S0x[a] * S0y[b] + 0.5 * DSx[a] * S0y[b] +
-                          0.5 * S0x[a] * DSy[b] +
-                          DSx[a] * DSy[b] * (1.0 / 3.0);
-        if (wz != 0.0) unsafeAtomicAdd(&row[a], qvz * wz);
-      }
-    }
-  }
-
-  p.ux[ip] = u[0];
-  p.uy[ip] = u[1];
-  p.uz[ip] = u[2];
-  const bool inside = (xi1 >= 0.0 && xi1 < (double)pp.nx) &&
-                      (DIMS == 1 || (yi1 >= 0.0 && yi1 < (double)pp.ny));
-  p.px[ip] = inside ? xi1 : kDeadPos;
-  if (DIMS == 2) p.py[ip] = yi1;
-}
-
-template <>
-hipError_t launch_push<double>(const Fields<double> &f,
-                               const Particles<double> &p, int64_t n,
-                               int dims, const PushParams &pp,
-                               const IncParams &inc, hipStream_t st) {
-  if (n <= 0) return hipSuccess;
-  const int bs = 256;
-  const unsigned g = (unsigned)((n + bs - 1) / bs);
-  if (dims == 1)
-    push_kernel_f64<1><<<g, bs, 0, st>>>(f, p, n, pp, inc);
-  else
-    push_kernel_f64<2><<<g, bs, 0, st>>>(f, p, n, pp, inc);
-  return hipGetLastError();
-}
-
-// ---------------------------------------------------------------------------
-// Particle placement: Philox4x32-10 (Salmon et al., SC'11) keyed by
-// (seed, species index), counter (id low, id high, stream, 0).
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0,
-                                              uint32_t k1) {
-  for (int r = 0; r < 10; ++r) {
-    if (r > 0) {
-      k0 += 0x9E3779B9u;
-      k1 += 0xBB67AE85u;
-    }
-    const uint64_t p0 = (uint64_t)0xD2511F53u * c[0];
-    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c[2];
-    const uint32_t h0 = (uint32_t)(p0 >> 32), l0 = (uint32_t)p0;
-    const uint32_t h1 = (uint32_t)(p1 >> 32), l1 = (uint32_t)p1;
-    const uint32_t n0 = h1 ^ c[1] ^ k0, n2 = h0 ^ c[3] ^ k1;
-    c[0] = n0;
-    c[1] = l1;
-    c[2] = n2;
-    c[3] = l0;
-  }
-}
-
-__device__ __forceinline__ void u01_pair(const uint32_t r[4], double &a,
-                                         double &b) {
-  const double sc = 1.0 / 9007199254740992.0;
-  a = ((double)(r[0] >> 5) * 67108864.0 + (double)(r[1] >> 6)) * sc;
-  b = ((double)(r[2] >> 5) * 67108864.0 + (double)(r[3] >> 6)) * sc;
-}
-
 __global__ void init_particles_f64(Particles<double> p, int64_t n, int dims,
                                    int64_t x0, int64_t ncx, int64_t y0,
                                    int ppc, double sigma, uint32_t k0,
@@ -521,12 +266,13 @@ __device__ __forceinline__ void atomic_max_pos(double *addr, double v) {
   atomicMax((unsigned long long *)addr, (unsigned long long)__double_as_longlong(v));
 }
 
-__global__ void particle_sums_f64(Particles<double> p, int64_t n, double m,
-                                  double q, double wdv, double *acc) {
+__global__ void particle_sums_f64(Particles<double> p, int64_t n,
+                                  const uint32_t *n_valid, double m, double q,
+                                  double wdv, double *acc) {
   __shared__ double sh[4][8];
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   double wk = 0.0, ch = 0.0, na = 0.0, bad = 0.0;
-  if (i < n && p.px[i] >= -1.0) {
+  if (i < n && i < (int64_t)*n_valid && p.px[i] >= -1.0) {
     const double ux = p.ux[i], uy = p.uy[i], uz = p.uz[i];
     const double g = sqrt(1.0 + ux * ux + uy * uy + uz * uz);
     if (!isfinite(g)) bad = 1.0;
@@ -548,11 +294,12 @@ __global__ void particle_sums_f64(Particles<double> p, int64_t n, double m,
 
 template <>
 hipError_t launch_particle_sums<double>(const Particles<double> &p, int64_t n,
-                                        double m, double q, double wdv,
-                                        double *acc, hipStream_t st) {
+                                        const uint32_t *n_valid, double m,
+                                        double q, double wdv, double *acc,
+                                        hipStream_t st) {
   if (n <= 0) return hipSuccess;
-  particle_sums_f64<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(p, n, m, q,
-                                                                 wdv, acc);
+  particle_sums_f64<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(
+      p, n, n_valid, m, q, wdv, acc);
   return hipGetLastError();
 }
 
@@ -586,10 +333,11 @@ hipError_t launch_field_sums(const Fields<R> &f, double *acc, hipStream_t st) {
   return hipGetLastError();
 }
 
-__global__ void deposit_rho_f64(Particles<double> p, int64_t n, int dims,
-                                double qw, double *rho, int pitch) {
+__global__ void deposit_rho_f64(Particles<double> p, int64_t n,
+                                const uint32_t *n_valid, int dims, double qw,
+                                double *rho, int pitch) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+  if (i >= n || i >= (int64_t)*n_valid) return;
   const double xi = p.px[i];
   if (xi < -1.0) return;
   const int ix = (int)floor(xi);
@@ -614,11 +362,12 @@ __global__ void deposit_rho_f64(Particles<double> p, int64_t n, int dims,
 
 template <>
 hipError_t launch_deposit_rho<double>(const Particles<double> &p, int64_t n,
-                                      int dims, double qw, double *rho,
-                                      int pitch, hipStream_t st) {
+                                      const uint32_t *n_valid, int dims,
+                                      double qw, double *rho, int pitch,
+                                      hipStream_t st) {
   if (n <= 0) return hipSuccess;
-  deposit_rho_f64<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(p, n, dims, qw,
-                                                               rho, pitch);
+  deposit_rho_f64<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(
+      p, n, n_valid, dims, qw, rho, pitch);
   return hipGetLastError();
 }
 
@@ -654,11 +403,12 @@ hipError_t launch_gauss(const Fields<R> &f, int dims, int nx, int ny,
   return hipGetLastError();
 }
 
-__global__ void histogram_f64(Particles<double> p, int64_t n, double m,
-                              double wdv, int n_e, double emax, int n_t,
-                              double ek_min, double *hist, double *mom) {
+__global__ void histogram_f64(Particles<double> p, int64_t n,
+                              const uint32_t *n_valid, double m, double wdv,
+                              int n_e, double emax, int n_t, double ek_min,
+                              double *hist, double *mom) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n || p.px[i] < -1.0) return;
+  if (i >= n || i >= (int64_t)*n_valid || p.px[i] < -1.0) return;
   const double ux = p.ux[i], uy = p.uy[i], uz = p.uz[i];
   const double ek = m * (sqrt(1.0 + ux * ux + uy * uy + uz * uz) - 1.0);
   const double th = atan2(sqrt(uy * uy + uz * uz), ux) * (180.0 / 3.14159265358979323846);
@@ -678,13 +428,13 @@ __global__ void histogram_f64(Particles<double> p, int64_t n, double m,
 
 template <>
 hipError_t launch_histogram<double>(const Particles<double> &p, int64_t n,
-                                    double m, double wdv, int n_e,
-                                    double emax, int n_t, double ek_min,
-                                    double *hist, double *mom,
+                                    const uint32_t *n_valid, double m,
+                                    double wdv, int n_e, double emax, int n_t,
+                                    double ek_min, double *hist, double *mom,
                                     hipStream_t st) {
   if (n <= 0) return hipSuccess;
   histogram_f64<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(
-      p, n, m, wdv, n_e, emax, n_t, ek_min, hist, mom);
+      p, n, n_valid, m, wdv, n_e, emax, n_t, ek_min, hist, mom);
   return hipGetLastError();
 }
 

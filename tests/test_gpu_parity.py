@@ -74,6 +74,23 @@ def test_fp64_parity_50_steps(case):
     assert gd["nonfinite"] == 0
 
 
+@pytest.mark.parametrize("tile,sort_every", [((4, 4), 7), ((32, 4), 1),
+                                              ((16, 8), 25)])
+def test_fp64_parity_tiling(tile, sort_every):
+    """Tile shape and sort cadence change only the summation order: tiny
+    tiles sorted rarely push most particles through the straggler path."""
+    work = _small_lp(a0=30.0, s=10.0)
+    sp = explicit_species(work)
+    g = make_gpu(work, sp, tile=tile, sort_every=sort_every)
+    o = make_oracle(work, sp)
+    g.step(work.steps)
+    o.step(work.steps)
+    rel, den = field_rel_l2(g, o)
+    assert den > 0 and rel <= FP64_FIELD_TOL, rel
+    dpos, du, umax = particle_errors(g, o)
+    assert dpos <= 1e-12 and du <= 1e-12 * max(1.0, umax), (dpos, du)
+
+
 def test_fp64_two_species_parity():
     work = _small_lp(nx=80, ny=48, plasma=(20, 60, 4, 44), ppc=3)
     e = explicit_species(work)[0]
