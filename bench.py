@@ -76,6 +76,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=128)
     ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a plain 1 GiB device-to-device copy (3x) "
+                         "whose profiler counters calibrate HBM traffic")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -165,6 +168,16 @@ def main():
                    "nonfinite": diag["nonfinite"], "n_alive": diag["n_alive"]},
     }
     sim.close()
+    if args.calibrate_copy:
+        src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        src.fill_(1)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = 1 << 30
+        del src, dst
     if not args.no_cpu_baseline:
         log("timing the oracle on a bounded sample (CPU)")
         out["cpu_baseline"] = cpu_baseline(work, args.cpu_rows,

@@ -1,6 +1,7 @@
 // Host runtime behind the C ABI of include/sfpic.h: validation, device memory,
 // particle placement, step scheduling on the caller's HIP stream, reads,
-// diagnostics and checkpoints.
+// diagnostics and checkpoints.  The FP64 and FP32 forms share this code; the
+// precision picks the kernel instantiation.
 #include "../../include/sfpic.h"
 #include "sfpic_common.h"
 
@@ -31,6 +32,12 @@ int fail(int code, const std::string &msg) {
                                       hipGetErrorString(e_));           \
   } while (0)
 
+#define SF_TRY(expr)               \
+  do {                             \
+    int r_ = (expr);               \
+    if (r_ != SFPIC_OK) return r_; \
+  } while (0)
+
 struct SpeciesState {
   double q = -1.0, m = 1.0, weight = 0.0;
   int64_t n = 0;               // slots (capacity)
@@ -39,6 +46,19 @@ struct SpeciesState {
   Particles<double> p64{}, p64_alt{};
   Particles<float> p32{}, p32_alt{};
 };
+
+template <typename R>
+Particles<R> &parts(SpeciesState &st);
+template <>
+Particles<double> &parts<double>(SpeciesState &st) { return st.p64; }
+template <>
+Particles<float> &parts<float>(SpeciesState &st) { return st.p32; }
+template <typename R>
+Particles<R> &parts_alt(SpeciesState &st);
+template <>
+Particles<double> &parts_alt<double>(SpeciesState &st) { return st.p64_alt; }
+template <>
+Particles<float> &parts_alt<float>(SpeciesState &st) { return st.p32_alt; }
 
 constexpr uint64_t kStateMagic = 0x53465049435354ull;  // "SFPICST"
 
@@ -68,6 +88,9 @@ struct sfpic_sim {
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_used[SFPIC_KCLASSES];
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_free;
 
+  template <typename R>
+  Fields<R> &fields();
+
   std::pair<hipEvent_t, hipEvent_t> take_events() {
     if (!ev_free.empty()) {
       auto e = ev_free.back();
@@ -93,7 +116,6 @@ struct sfpic_sim {
     }
     ev_free.clear();
   }
-
   void *dalloc(size_t bytes) {
     bytes = (bytes + 255) & ~(size_t)255;
     void *p = nullptr;
@@ -104,6 +126,17 @@ struct sfpic_sim {
     }
     if (p) allocs.emplace_back(p, bytes);
     return p;
+  }
+  void dfree(void *p) {
+    for (size_t k = 0; k < allocs.size(); ++k)
+      if (allocs[k].first == p) {
+        if (rt.free)
+          rt.free(p, allocs[k].second, rt.alloc_ctx);
+        else
+          (void)hipFree(p);
+        allocs.erase(allocs.begin() + k);
+        return;
+      }
   }
   void release() {
     for (auto &a : allocs) {
@@ -118,7 +151,21 @@ struct sfpic_sim {
   double cell_volume() const {
     return grid.dims == 2 ? grid.dx * grid.dy : grid.dx;
   }
+  // Run f with a value of the working precision's type.
+  template <typename F>
+  int dispatch(F &&f) {
+    return precision == SFPIC_FP64 ? f(0.0) : f(0.0f);
+  }
 };
+
+template <>
+Fields<double> &sfpic_sim::fields<double>() {
+  return f64;
+}
+template <>
+Fields<float> &sfpic_sim::fields<float>() {
+  return f32;
+}
 
 namespace {
 
@@ -141,6 +188,9 @@ int prepare_incident(const sfpic_incident *in, IncParams &P) {
   const double s = in->s;
   if (!(in->w0 > 0.0) || !(s >= 1.0) || s > 1000.0 || s != floor(s))
     return fail(SFPIC_E_INVAL, "April beam needs w0 > 0 and integer s >= 1");
+  if (!isfinite(in->a0) || !isfinite(in->x_focus) || !isfinite(in->y_focus) ||
+      !isfinite(in->t_focus) || !isfinite(in->phi0))
+    return fail(SFPIC_E_INVAL, "April beam parameters must be finite");
   // k^2 w0^2 = 2 (sqrt(1 + (ka)^2) - 1)  =>  ka = sqrt((1 + w0^2/2)^2 - 1)
   const double h = 1.0 + 0.5 * in->w0 * in->w0;
   P.a = sqrt(h * h - 1.0);
@@ -176,16 +226,18 @@ int prepare_incident(const sfpic_incident *in, IncParams &P) {
 
 int check_grid(const sfpic_grid *g) {
   if (!g) return fail(SFPIC_E_INVAL, "grid is NULL");
-  if (g->dims != 1 && g->dims != 2) return fail(SFPIC_E_INVAL, "dims must be 1 or 2");
+  if (g->dims != 1 && g->dims != 2)
+    return fail(SFPIC_E_INVAL, "dims must be 1 or 2");
   const int64_t lim = 65535 - 2 * kGuard;
-  if (g->nx < 8 || g->nx > lim) return fail(SFPIC_E_INVAL, "nx out of range [8, 65529]");
+  if (g->nx < 8 || g->nx > lim)
+    return fail(SFPIC_E_INVAL, "nx out of range [8, 65529]");
   if (g->dims == 2 && (g->ny < 8 || g->ny > lim))
     return fail(SFPIC_E_INVAL, "ny out of range [8, 65529]");
   if (!(g->dx > 0.0) || (g->dims == 2 && !(g->dy > 0.0)) || !(g->dt > 0.0))
     return fail(SFPIC_E_INVAL, "dx, dy, dt must be positive");
-  const double lim_dt = (g->dims == 2)
-                            ? 1.0 / sqrt(1.0 / (g->dx * g->dx) + 1.0 / (g->dy * g->dy))
-                            : g->dx;
+  const double lim_dt =
+      (g->dims == 2) ? 1.0 / sqrt(1.0 / (g->dx * g->dx) + 1.0 / (g->dy * g->dy))
+                     : g->dx;
   if (!(g->dt < lim_dt)) return fail(SFPIC_E_INVAL, "dt violates the CFL limit");
   return SFPIC_OK;
 }
@@ -201,34 +253,62 @@ void set_field_ptrs(Fields<R> &f, void *const planes[12], int NX, int NY,
   f.pitch = pitch;
 }
 
+// Device arrays of one particle set.
+bool alloc_set(sfpic_sim *s, Particles<double> &q, size_t cnt) {
+  double **arr[5] = {&q.px, &q.py, &q.ux, &q.uy, &q.uz};
+  for (auto a : arr)
+    if (!(*a = (double *)s->dalloc(cnt * 8))) return false;
+  return (q.id = (uint32_t *)s->dalloc(cnt * 4)) != nullptr;
+}
+bool alloc_set(sfpic_sim *s, Particles<float> &q, size_t cnt) {
+  if (!(q.cell = (uint32_t *)s->dalloc(cnt * 4))) return false;
+  float **arr[5] = {&q.ox, &q.oy, &q.ux, &q.uy, &q.uz};
+  for (auto a : arr)
+    if (!(*a = (float *)s->dalloc(cnt * 4))) return false;
+  return (q.id = (uint32_t *)s->dalloc(cnt * 4)) != nullptr;
+}
+
+// Raw arrays of a particle set (for checkpoints): pointers and element sizes.
+int raw_arrays(Particles<double> &q, void *ptr[7], size_t sz[7]) {
+  void *p[6] = {q.px, q.py, q.ux, q.uy, q.uz, q.id};
+  size_t z[6] = {8, 8, 8, 8, 8, 4};
+  for (int k = 0; k < 6; ++k) {
+    ptr[k] = p[k];
+    sz[k] = z[k];
+  }
+  return 6;
+}
+int raw_arrays(Particles<float> &q, void *ptr[7], size_t sz[7]) {
+  void *p[7] = {q.cell, q.ox, q.oy, q.ux, q.uy, q.uz, q.id};
+  for (int k = 0; k < 7; ++k) {
+    ptr[k] = p[k];
+    sz[k] = 4;
+  }
+  return 7;
+}
+size_t bytes_per_particle(int precision) {
+  return precision == SFPIC_FP64 ? 5 * 8 + 4 : 7 * 4;
+}
+
 int alloc_species(sfpic_sim *s, SpeciesState &st, int64_t n) {
   st.n = n;
   const size_t cnt = (size_t)(n > 0 ? n : 1);
   st.n_valid = (uint32_t *)s->dalloc(4);
   if (!st.n_valid) return fail(SFPIC_E_NOMEM, "particle allocation failed");
-  if (s->precision == SFPIC_FP64) {
-    for (Particles<double> *q : {&st.p64, &st.p64_alt}) {
-      double **arr[5] = {&q->px, &q->py, &q->ux, &q->uy, &q->uz};
-      for (auto a : arr) {
-        *a = (double *)s->dalloc(cnt * 8);
-        if (!*a) return fail(SFPIC_E_NOMEM, "particle allocation failed");
-      }
-      q->id = (uint32_t *)s->dalloc(cnt * 4);
-      if (!q->id) return fail(SFPIC_E_NOMEM, "particle allocation failed");
-    }
-    const uint32_t nv = (uint32_t)n;
-    if (hipMemcpy(st.n_valid, &nv, 4, hipMemcpyHostToDevice) != hipSuccess)
-      return fail(SFPIC_E_DEVICE, "hipMemcpy failed");
-  } else {
-    return fail(SFPIC_E_INVAL, "FP32 precision is not available in this build");
-  }
+  const bool ok =
+      s->precision == SFPIC_FP64
+          ? alloc_set(s, st.p64, cnt) && alloc_set(s, st.p64_alt, cnt)
+          : alloc_set(s, st.p32, cnt) && alloc_set(s, st.p32_alt, cnt);
+  if (!ok) return fail(SFPIC_E_NOMEM, "particle allocation failed");
+  const uint32_t nv = (uint32_t)n;
+  HIP_TRY(hipMemcpy(st.n_valid, &nv, 4, hipMemcpyHostToDevice));
   return SFPIC_OK;
 }
 
-int place_species(sfpic_sim *s, SpeciesState &st, const sfpic_species &in,
-                  int index) {
+int place_species(sfpic_sim *s, SpeciesState &st, const sfpic_species &in) {
   const sfpic_grid &g = s->grid;
-  if (!(in.m > 0.0) || !isfinite(in.q)) return fail(SFPIC_E_INVAL, "species needs m > 0");
+  if (!(in.m > 0.0) || !isfinite(in.q))
+    return fail(SFPIC_E_INVAL, "species needs m > 0 and finite q");
   st.q = in.q;
   st.m = in.m;
   if (in.n_explicit > 0) {
@@ -246,29 +326,26 @@ int place_species(sfpic_sim *s, SpeciesState &st, const sfpic_species &in,
         return fail(SFPIC_E_INVAL, "particle outside the physical box");
     }
     st.weight = in.weight;
-    int r = alloc_species(s, st, n);
-    if (r) return r;
+    SF_TRY(alloc_species(s, st, n));
     // stage the host arrays through one device buffer
     double *tmp = (double *)s->dalloc((size_t)n * 5 * 8);
     if (!tmp) return fail(SFPIC_E_NOMEM, "staging allocation failed");
-    const double *src[5] = {in.x, g.dims == 2 ? in.y : in.x, in.ux, in.uy, in.uz};
+    const double *src[5] = {in.x, g.dims == 2 ? in.y : in.x, in.ux, in.uy,
+                            in.uz};
     for (int k = 0; k < 5; ++k)
       HIP_TRY(hipMemcpyAsync(tmp + (size_t)k * n, src[k], (size_t)n * 8,
                              hipMemcpyHostToDevice, s->stream));
-    HIP_TRY(launch_load_particles<double>(st.p64, n, g.dims, tmp, tmp + n,
-                                          tmp + 2 * n, tmp + 3 * n, tmp + 4 * n,
-                                          1.0 / g.dx, 1.0 / g.dy, s->stream));
+    const int r = s->dispatch([&](auto z) -> int {
+      using R = decltype(z);
+      HIP_TRY(launch_load_particles<R>(parts<R>(st), n, g.dims, tmp, tmp + n,
+                                       tmp + 2 * n, tmp + 3 * n, tmp + 4 * n,
+                                       1.0 / g.dx, 1.0 / g.dy, (int)g.nx,
+                                       (int)g.ny, s->stream));
+      return SFPIC_OK;
+    });
+    if (r) return r;
     HIP_TRY(hipStreamSynchronize(s->stream));
-    // release the staging buffer now
-    for (size_t k = 0; k < s->allocs.size(); ++k)
-      if (s->allocs[k].first == tmp) {
-        if (s->rt.free)
-          s->rt.free(tmp, s->allocs[k].second, s->rt.alloc_ctx);
-        else
-          (void)hipFree(tmp);
-        s->allocs.erase(s->allocs.begin() + k);
-        break;
-      }
+    s->dfree(tmp);
     return SFPIC_OK;
   }
   // generated placement
@@ -281,46 +358,56 @@ int place_species(sfpic_sim *s, SpeciesState &st, const sfpic_species &in,
   if (in.ppc < 0 || x0 < 0 || x1 > g.nx || x0 > x1 || y0 < 0 ||
       (g.dims == 2 && y1 > g.ny) || y0 > y1)
     return fail(SFPIC_E_INVAL, "species region outside the grid");
-  if (in.ppc > 0 && !(in.density >= 0.0)) return fail(SFPIC_E_INVAL, "density < 0");
-  if (!(in.temperature_ev >= 0.0)) return fail(SFPIC_E_INVAL, "temperature < 0");
+  if (in.ppc > 0 && !(in.density >= 0.0))
+    return fail(SFPIC_E_INVAL, "density < 0");
+  if (!(in.temperature_ev >= 0.0))
+    return fail(SFPIC_E_INVAL, "temperature < 0");
   const int64_t n = (x1 - x0) * (y1 - y0) * (int64_t)in.ppc;
   if (n > 0xFFFFFFFFll) return fail(SFPIC_E_INVAL, "too many particles");
   st.weight = in.ppc > 0 ? in.density / in.ppc : 0.0;
-  int r = alloc_species(s, st, n);
-  if (r) return r;
+  SF_TRY(alloc_species(s, st, n));
   const double sigma = sqrt(in.temperature_ev / (510998.95 * in.m));
-  HIP_TRY(launch_init_particles<double>(st.p64, n, g.dims, x0, x1 - x0, y0,
-                                        in.ppc > 0 ? in.ppc : 1, sigma,
-                                        in.seed, (uint32_t)in.species_index,
-                                        g.dx, g.dy, s->stream));
-  (void)index;
-  return SFPIC_OK;
+  return s->dispatch([&](auto z) -> int {
+    using R = decltype(z);
+    HIP_TRY(launch_init_particles<R>(parts<R>(st), n, g.dims, x0, x1 - x0, y0,
+                                     in.ppc > 0 ? in.ppc : 1, sigma, in.seed,
+                                     (uint32_t)in.species_index, g.dx, g.dy,
+                                     s->stream));
+    return SFPIC_OK;
+  });
 }
 
 int deposit_rho(sfpic_sim *s, double *rho) {
   const size_t bytes = (size_t)s->NY * s->pitch * 8;
   HIP_TRY(hipMemsetAsync(rho, 0, bytes, s->stream));
-  for (auto &st : s->sp)
-    HIP_TRY(launch_deposit_rho<double>(st.p64, st.n, st.n_valid, s->grid.dims,
-                                       st.q * st.weight, rho, s->pitch,
-                                       s->stream));
-  return SFPIC_OK;
+  return s->dispatch([&](auto z) -> int {
+    using R = decltype(z);
+    for (auto &st : s->sp)
+      HIP_TRY(launch_deposit_rho<R>(parts<R>(st), st.n, st.n_valid,
+                                    s->grid.dims, st.q * st.weight, rho,
+                                    s->pitch, s->stream));
+    return SFPIC_OK;
+  });
 }
 
 int setup_tiles(sfpic_sim *s) {
   const sfpic_grid &g = s->grid;
   TileGeom &t = s->tg;
   int max_lds = 64 * 1024;
-  (void)hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock,
+  (void)hipDeviceGetAttribute(&max_lds,
+                              hipDeviceAttributeMaxSharedMemoryPerBlock,
                               s->rt.device);
+  auto lds_of = [&](const TileGeom &tt) {
+    return s->precision == SFPIC_FP64 ? push_lds_bytes<double>(tt, g.dims)
+                                      : push_lds_bytes<float>(tt, g.dims);
+  };
   if (g.dims == 1) {
     t.tx = s->rt.tile_x > 0 ? s->rt.tile_x : 256;
     t.ty = 1;
   } else {
     t.tx = s->rt.tile_x > 0 ? s->rt.tile_x : 16;
     t.ty = s->rt.tile_y > 0 ? s->rt.tile_y : 8;
-    if (s->rt.tile_x <= 0 && s->rt.tile_y <= 0 && s->precision == SFPIC_FP64 &&
-        push_lds_bytes<double>(t, 2) > (size_t)max_lds)
+    if (s->rt.tile_x <= 0 && s->rt.tile_y <= 0 && lds_of(t) > (size_t)max_lds)
       t.tx = 8;  // 8 x 8 tiles fit a 64 KB workgroup limit
   }
   if (t.tx < 1 || t.ty < 1 || t.tx > 1024 || t.ty > 256)
@@ -332,10 +419,8 @@ int setup_tiles(sfpic_sim *s) {
   const uint64_t nk = (uint64_t)t.ntiles * t.cells_per_tile;
   if (nk >= 0xFFFFFFF0ull) return fail(SFPIC_E_INVAL, "too many cells");
   t.nkeys = (uint32_t)nk;
-  const size_t lds = s->precision == SFPIC_FP64
-                         ? push_lds_bytes<double>(t, g.dims)
-                         : (size_t)0;
-  if (lds > (size_t)max_lds) return fail(SFPIC_E_INVAL, "tile too large for LDS");
+  if (lds_of(t) > (size_t)max_lds)
+    return fail(SFPIC_E_INVAL, "tile too large for LDS");
   if (s->rt.sort_every > 0) s->sort_every = s->rt.sort_every;
   const size_t nk1 = (size_t)t.nkeys + 1;
   s->ss.counts = (uint32_t *)s->dalloc(nk1 * 4);
@@ -350,25 +435,26 @@ int setup_tiles(sfpic_sim *s) {
   s->ss.rank = (uint32_t *)s->dalloc((size_t)nmax * 4);
   s->strag = (uint32_t *)s->dalloc((size_t)nmax * 4);
   s->n_strag = (uint32_t *)s->dalloc(4);
-  if (!s->strag || !s->n_strag)
-    return fail(SFPIC_E_NOMEM, "straggler list allocation failed");
-  if (!s->ss.counts || !s->ss.block_sums || !s->ss.key ||
-      !s->ss.rank)
+  if (!s->ss.counts || !s->ss.block_sums || !s->ss.key || !s->ss.rank ||
+      !s->strag || !s->n_strag)
     return fail(SFPIC_E_NOMEM, "sort scratch allocation failed");
   return SFPIC_OK;
 }
 
 // Counting sort of every species by cell (compacts removed particles).
 int sort_all(sfpic_sim *s) {
-  for (auto &st : s->sp) {
-    HIP_TRY(launch_sort<double>(st.p64, st.p64_alt, (uint32_t)st.n, st.n_valid,
-                                st.start, s->tg, (int)s->grid.nx,
-                                (int)s->grid.ny, s->grid.dims, s->ss,
-                                s->stream));
-    std::swap(st.p64, st.p64_alt);
-  }
+  const int r = s->dispatch([&](auto z) -> int {
+    using R = decltype(z);
+    for (auto &st : s->sp) {
+      HIP_TRY(launch_sort<R>(parts<R>(st), parts_alt<R>(st), (uint32_t)st.n,
+                             st.n_valid, st.start, s->tg, (int)s->grid.nx,
+                             (int)s->grid.ny, s->grid.dims, s->ss, s->stream));
+      std::swap(parts<R>(st), parts_alt<R>(st));
+    }
+    return SFPIC_OK;
+  });
   s->since_sort = 0;
-  return SFPIC_OK;
+  return r;
 }
 
 int guarded(sfpic_sim *s) {
@@ -377,11 +463,9 @@ int guarded(sfpic_sim *s) {
   return SFPIC_OK;
 }
 
-}  // namespace
-
 // Launch helper: bracket a kernel launch with events when profiling.
 template <typename F>
-static hipError_t timed(sfpic_sim *s, int cls, F &&launch) {
+hipError_t timed(sfpic_sim *s, int cls, F &&launch) {
   if (!s->profiling) return launch();
   auto e = s->take_events();
   hipError_t r = hipEventRecord(e.first, s->stream);
@@ -391,11 +475,91 @@ static hipError_t timed(sfpic_sim *s, int cls, F &&launch) {
   return r;
 }
 
+template <typename R>
+int step_impl(sfpic_sim *s, int64_t nsteps) {
+  const sfpic_grid &g = s->grid;
+  Fields<R> &f = s->fields<R>();
+  for (int64_t k = 0; k < nsteps; ++k) {
+    if (s->since_sort >= s->sort_every) {
+      HIP_TRY(timed(s, 3, [&] {
+        return sort_all(s) == SFPIC_OK ? hipSuccess : hipErrorUnknown;
+      }));
+    }
+    HIP_TRY(timed(s, 0, [&] {
+      return launch_faraday<R>(f, g.dims, g.dt, g.dx, g.dy, s->stream);
+    }));
+    for (auto &st : s->sp) {
+      PushParams pp;
+      pp.dt = g.dt;
+      pp.dx = g.dx;
+      pp.dy = g.dy;
+      pp.inv_dx = 1.0 / g.dx;
+      pp.inv_dy = 1.0 / g.dy;
+      pp.qm = st.q / st.m;
+      pp.qw = st.q * st.weight;
+      pp.time = (double)s->step * g.dt;
+      pp.nx = (int)g.nx;
+      pp.ny = (int)g.ny;
+      HIP_TRY(timed(s, 1, [&] {
+        return launch_push_tiled<R>(f, parts<R>(st), st.start, s->tg, g.dims,
+                                    pp, s->inc, s->strag, s->n_strag,
+                                    s->stream);
+      }));
+      HIP_TRY(timed(s, 4, [&] {
+        return launch_push_stragglers<R>(f, parts<R>(st), g.dims, pp, s->inc,
+                                         s->strag, s->n_strag, s->stream);
+      }));
+    }
+    HIP_TRY(timed(s, 2, [&] {
+      return launch_ampere<R>(f, g.dims, g.dt, g.dx, g.dy, s->stream);
+    }));
+    s->step++;
+    s->since_sort++;
+  }
+  return SFPIC_OK;
+}
+
+// Used slots of a species copied to host as FP64 (x, y, ux, uy, uz, id).
+int fetch_particles(sfpic_sim *s, SpeciesState &st, std::vector<double> &h,
+                    std::vector<uint32_t> &ids, size_t &n) {
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  uint32_t nv = 0;
+  HIP_TRY(hipMemcpy(&nv, st.n_valid, 4, hipMemcpyDeviceToHost));
+  n = nv;
+  h.assign(5 * n, 0.0);
+  ids.assign(n, 0u);
+  if (n == 0) return SFPIC_OK;
+  double *d = (double *)s->dalloc(n * 5 * 8);
+  uint32_t *di = (uint32_t *)s->dalloc(n * 4);
+  if (!d || !di) {
+    if (d) s->dfree(d);
+    if (di) s->dfree(di);
+    return fail(SFPIC_E_NOMEM, "export allocation failed");
+  }
+  int r = s->dispatch([&](auto z) -> int {
+    using R = decltype(z);
+    HIP_TRY(launch_export_particles<R>(parts<R>(st), (int64_t)n, s->grid.dims,
+                                       s->grid.dx, s->grid.dy, d, di,
+                                       s->stream));
+    HIP_TRY(hipMemcpyAsync(h.data(), d, n * 5 * 8, hipMemcpyDeviceToHost,
+                           s->stream));
+    HIP_TRY(hipMemcpyAsync(ids.data(), di, n * 4, hipMemcpyDeviceToHost,
+                           s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    return SFPIC_OK;
+  });
+  s->dfree(d);
+  s->dfree(di);
+  return r;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char *sfpic_last_error(void) { return g_last_error.c_str(); }
 
-const char *sfpic_version(void) { return "sfpic 0.1 (gfx950)"; }
+const char *sfpic_version(void) { return "sfpic 0.2 (gfx950)"; }
 
 int sfpic_create(const sfpic_grid *grid, const sfpic_species *species,
                  int nspecies, const sfpic_incident *incident,
@@ -404,15 +568,13 @@ int sfpic_create(const sfpic_grid *grid, const sfpic_species *species,
   try {
     if (!out) return fail(SFPIC_E_INVAL, "out is NULL");
     *out = nullptr;
-    int r = check_grid(grid);
-    if (r) return r;
+    SF_TRY(check_grid(grid));
     if (nspecies < 0 || nspecies > 8 || (nspecies > 0 && !species))
       return fail(SFPIC_E_INVAL, "nspecies must be in [0, 8]");
     if (precision != SFPIC_FP64 && precision != SFPIC_FP32)
       return fail(SFPIC_E_INVAL, "unknown precision");
     IncParams inc;
-    r = prepare_incident(incident, inc);
-    if (r) return r;
+    SF_TRY(prepare_incident(incident, inc));
     sfpic_sim *s = new (std::nothrow) sfpic_sim();
     if (!s) return fail(SFPIC_E_NOMEM, "host allocation failed");
     s->grid = *grid;
@@ -431,15 +593,14 @@ int sfpic_create(const sfpic_grid *grid, const sfpic_species *species,
     };
     if (hipSetDevice(s->rt.device) != hipSuccess)
       return bail(fail(SFPIC_E_DEVICE, "hipSetDevice failed"));
-    if (precision == SFPIC_FP32)
-      return bail(fail(SFPIC_E_INVAL, "FP32 precision is not available in this build"));
     s->NX = (int)(s->grid.nx + 2 * kGuard);
     s->NY = (grid->dims == 2) ? (int)(s->grid.ny + 2 * kGuard) : 1;
     s->pitch = (s->NX + 63) & ~63;
     const size_t plane = (size_t)s->NY * s->pitch * s->esize();
     for (int c = 0; c < 12; ++c) {
       s->planes[c] = s->dalloc(plane);
-      if (!s->planes[c]) return bail(fail(SFPIC_E_NOMEM, "field allocation failed"));
+      if (!s->planes[c])
+        return bail(fail(SFPIC_E_NOMEM, "field allocation failed"));
       if (hipMemsetAsync(s->planes[c], 0, plane, s->stream) != hipSuccess)
         return bail(fail(SFPIC_E_DEVICE, "hipMemsetAsync failed"));
     }
@@ -447,10 +608,10 @@ int sfpic_create(const sfpic_grid *grid, const sfpic_species *species,
     set_field_ptrs(s->f32, s->planes, s->NX, s->NY, s->pitch);
     s->sp.resize(nspecies);
     for (int k = 0; k < nspecies; ++k) {
-      r = place_species(s, s->sp[k], species[k], k);
+      const int r = place_species(s, s->sp[k], species[k]);
       if (r) return bail(r);
     }
-    r = setup_tiles(s);
+    int r = setup_tiles(s);
     if (r) return bail(r);
     const size_t rbytes = (size_t)s->NY * s->pitch * 8;
     s->rho0 = (double *)s->dalloc(rbytes);
@@ -472,101 +633,85 @@ int sfpic_create(const sfpic_grid *grid, const sfpic_species *species,
 }
 
 int sfpic_step(sfpic_sim *s, int64_t nsteps) {
-  int r = guarded(s);
-  if (r) return r;
+  SF_TRY(guarded(s));
   if (nsteps < 0) return fail(SFPIC_E_INVAL, "nsteps < 0");
-  const sfpic_grid &g = s->grid;
-  for (int64_t k = 0; k < nsteps; ++k) {
-    if (s->since_sort >= s->sort_every) {
-      HIP_TRY(timed(s, 3, [&] {
-        return sort_all(s) == SFPIC_OK ? hipSuccess : hipErrorUnknown;
-      }));
-    }
-    HIP_TRY(timed(s, 0, [&] {
-      return launch_faraday<double>(s->f64, g.dims, g.dt, g.dx, g.dy, s->stream);
-    }));
-    for (auto &st : s->sp) {
-      PushParams pp;
-      pp.dt = g.dt;
-      pp.dx = g.dx;
-      pp.dy = g.dy;
-      pp.inv_dx = 1.0 / g.dx;
-      pp.inv_dy = 1.0 / g.dy;
-      pp.qm = st.q / st.m;
-      pp.qw = st.q * st.weight;
-      pp.time = (double)s->step * g.dt;
-      pp.nx = (int)g.nx;
-      pp.ny = (int)g.ny;
-      HIP_TRY(timed(s, 1, [&] {
-        return launch_push_tiled<double>(s->f64, st.p64, st.start, s->tg,
-                                         g.dims, pp, s->inc, s->strag,
-                                         s->n_strag, s->stream);
-      }));
-      HIP_TRY(timed(s, 4, [&] {
-        return launch_push_stragglers<double>(s->f64, st.p64, g.dims, pp,
-                                              s->inc, s->strag, s->n_strag,
-                                              s->stream);
-      }));
-    }
-    HIP_TRY(timed(s, 2, [&] {
-      return launch_ampere<double>(s->f64, g.dims, g.dt, g.dx, g.dy, s->stream);
-    }));
-    s->step++;
-    s->since_sort++;
-  }
-  return SFPIC_OK;
+  return s->dispatch(
+      [&](auto z) -> int { return step_impl<decltype(z)>(s, nsteps); });
 }
 
 int sfpic_sync(sfpic_sim *s) {
-  int r = guarded(s);
-  if (r) return r;
+  SF_TRY(guarded(s));
   HIP_TRY(hipStreamSynchronize(s->stream));
   return SFPIC_OK;
 }
 
 int sfpic_read_field(sfpic_sim *s, int comp, double *out, size_t n) {
-  int r = guarded(s);
-  if (r) return r;
+  SF_TRY(guarded(s));
   if (comp < 0 || comp >= SFPIC_NCOMP || !out)
     return fail(SFPIC_E_INVAL, "bad component or NULL output");
   if (n != (size_t)s->NX * s->NY) return fail(SFPIC_E_SIZE, "n must be NX*NY");
   HIP_TRY(hipStreamSynchronize(s->stream));
-  HIP_TRY(hipMemcpy2D(out, (size_t)s->NX * 8, s->planes[comp],
-                      (size_t)s->pitch * 8, (size_t)s->NX * 8, s->NY,
-                      hipMemcpyDeviceToHost));
+  if (s->precision == SFPIC_FP64) {
+    HIP_TRY(hipMemcpy2D(out, (size_t)s->NX * 8, s->planes[comp],
+                        (size_t)s->pitch * 8, (size_t)s->NX * 8, s->NY,
+                        hipMemcpyDeviceToHost));
+    return SFPIC_OK;
+  }
+  try {
+    std::vector<float> h(n);
+    HIP_TRY(hipMemcpy2D(h.data(), (size_t)s->NX * 4, s->planes[comp],
+                        (size_t)s->pitch * 4, (size_t)s->NX * 4, s->NY,
+                        hipMemcpyDeviceToHost));
+    for (size_t k = 0; k < n; ++k) out[k] = h[k];
+  } catch (...) {
+    return fail(SFPIC_E_NOMEM, "host allocation failed");
+  }
   return SFPIC_OK;
 }
 
 int sfpic_write_field(sfpic_sim *s, int comp, const double *in, size_t n) {
-  int r = guarded(s);
-  if (r) return r;
+  SF_TRY(guarded(s));
   if (comp < 0 || comp >= SFPIC_NCOMP || !in)
     return fail(SFPIC_E_INVAL, "bad component or NULL input");
   if (n != (size_t)s->NX * s->NY) return fail(SFPIC_E_SIZE, "n must be NX*NY");
   HIP_TRY(hipStreamSynchronize(s->stream));
-  HIP_TRY(hipMemcpy2D(s->planes[comp], (size_t)s->pitch * 8, in,
-                      (size_t)s->NX * 8, (size_t)s->NX * 8, s->NY,
-                      hipMemcpyHostToDevice));
+  if (s->precision == SFPIC_FP64) {
+    HIP_TRY(hipMemcpy2D(s->planes[comp], (size_t)s->pitch * 8, in,
+                        (size_t)s->NX * 8, (size_t)s->NX * 8, s->NY,
+                        hipMemcpyHostToDevice));
+    return SFPIC_OK;
+  }
+  try {
+    std::vector<float> h(in, in + n);
+    HIP_TRY(hipMemcpy2D(s->planes[comp], (size_t)s->pitch * 4, h.data(),
+                        (size_t)s->NX * 4, (size_t)s->NX * 4, s->NY,
+                        hipMemcpyHostToDevice));
+  } catch (...) {
+    return fail(SFPIC_E_NOMEM, "host allocation failed");
+  }
   return SFPIC_OK;
 }
 
 int sfpic_set_step_index(sfpic_sim *s, int64_t step) {
-  int r = guarded(s);
-  if (r) return r;
+  SF_TRY(guarded(s));
   if (step < 0) return fail(SFPIC_E_INVAL, "step < 0");
   s->step = step;
   return SFPIC_OK;
 }
 
 int sfpic_particle_count(sfpic_sim *s, int species, int64_t *n) {
-  int r = guarded(s);
-  if (r) return r;
+  SF_TRY(guarded(s));
   if (species < 0 || species >= (int)s->sp.size() || !n)
     return fail(SFPIC_E_INVAL, "bad species");
   SpeciesState &st = s->sp[species];
   HIP_TRY(hipMemsetAsync(s->acc, 0, 8 * 8, s->stream));
-  HIP_TRY(launch_particle_sums<double>(st.p64, st.n, st.n_valid, st.m, st.q,
-                                       0.0, s->acc, s->stream));
+  SF_TRY(s->dispatch([&](auto z) -> int {
+    using R = decltype(z);
+    HIP_TRY(launch_particle_sums<R>(parts<R>(st), st.n, st.n_valid,
+                                    s->grid.dims, st.m, st.q, 0.0, s->acc,
+                                    s->stream));
+    return SFPIC_OK;
+  }));
   double h[8];
   HIP_TRY(hipMemcpyAsync(h, s->acc, 8 * 8, hipMemcpyDeviceToHost, s->stream));
   HIP_TRY(hipStreamSynchronize(s->stream));
@@ -577,41 +722,28 @@ int sfpic_particle_count(sfpic_sim *s, int species, int64_t *n) {
 int sfpic_read_particles(sfpic_sim *s, int species, double *x, double *y,
                          double *ux, double *uy, double *uz, uint32_t *id,
                          size_t capacity, size_t *n_out) {
-  int r = guarded(s);
-  if (r) return r;
+  SF_TRY(guarded(s));
   if (species < 0 || species >= (int)s->sp.size())
     return fail(SFPIC_E_INVAL, "bad species");
   if (!x || !ux || !uy || !uz || (s->grid.dims == 2 && !y))
     return fail(SFPIC_E_INVAL, "NULL output array");
   try {
-    SpeciesState &st = s->sp[species];
-    HIP_TRY(hipStreamSynchronize(s->stream));
-    uint32_t nv = 0;
-    HIP_TRY(hipMemcpy(&nv, st.n_valid, 4, hipMemcpyDeviceToHost));
-    const size_t n = nv;
-    std::vector<double> hx(n), hy(n), hux(n), huy(n), huz(n);
-    std::vector<uint32_t> hid(n);
-    if (n) {
-      HIP_TRY(hipMemcpy(hx.data(), st.p64.px, n * 8, hipMemcpyDeviceToHost));
-      if (s->grid.dims == 2)
-        HIP_TRY(hipMemcpy(hy.data(), st.p64.py, n * 8, hipMemcpyDeviceToHost));
-      HIP_TRY(hipMemcpy(hux.data(), st.p64.ux, n * 8, hipMemcpyDeviceToHost));
-      HIP_TRY(hipMemcpy(huy.data(), st.p64.uy, n * 8, hipMemcpyDeviceToHost));
-      HIP_TRY(hipMemcpy(huz.data(), st.p64.uz, n * 8, hipMemcpyDeviceToHost));
-      HIP_TRY(hipMemcpy(hid.data(), st.p64.id, n * 4, hipMemcpyDeviceToHost));
-    }
+    std::vector<double> h;
+    std::vector<uint32_t> hid;
+    size_t n = 0;
+    SF_TRY(fetch_particles(s, s->sp[species], h, hid, n));
     size_t live = 0;
-    for (size_t i = 0; i < n; ++i) live += hx[i] >= -1.0;
+    for (size_t i = 0; i < n; ++i) live += h[i] >= 0.0;
     if (n_out) *n_out = live;
     if (live > capacity) return fail(SFPIC_E_SIZE, "capacity too small");
     size_t o = 0;
     for (size_t i = 0; i < n; ++i) {
-      if (hx[i] < -1.0) continue;
-      x[o] = hx[i] * s->grid.dx;
-      if (y) y[o] = s->grid.dims == 2 ? hy[i] * s->grid.dy : 0.0;
-      ux[o] = hux[i];
-      uy[o] = huy[i];
-      uz[o] = huz[i];
+      if (h[i] < 0.0) continue;
+      x[o] = h[i];
+      if (y) y[o] = h[n + i];
+      ux[o] = h[2 * n + i];
+      uy[o] = h[3 * n + i];
+      uz[o] = h[4 * n + i];
       if (id) id[o] = hid[i];
       ++o;
     }
@@ -622,20 +754,27 @@ int sfpic_read_particles(sfpic_sim *s, int species, double *x, double *y,
 }
 
 int sfpic_diagnostics(sfpic_sim *s, sfpic_diag *out) {
-  int r = guarded(s);
-  if (r) return r;
+  SF_TRY(guarded(s));
   if (!out) return fail(SFPIC_E_INVAL, "out is NULL");
   const double dv = s->cell_volume();
   HIP_TRY(hipMemsetAsync(s->acc, 0, 8 * 8, s->stream));
-  for (auto &st : s->sp)
-    HIP_TRY(launch_particle_sums<double>(st.p64, st.n, st.n_valid, st.m, st.q,
-                                         st.weight * dv, s->acc, s->stream));
-  HIP_TRY(launch_field_sums<double>(s->f64, s->acc, s->stream));
-  r = deposit_rho(s, s->rho);
-  if (r) return r;
-  HIP_TRY(launch_gauss<double>(s->f64, s->grid.dims, (int)s->grid.nx,
-                               (int)s->grid.ny, s->grid.dx, s->grid.dy, s->rho,
-                               s->rho0, s->pitch, s->acc, s->stream));
+  SF_TRY(s->dispatch([&](auto z) -> int {
+    using R = decltype(z);
+    for (auto &st : s->sp)
+      HIP_TRY(launch_particle_sums<R>(parts<R>(st), st.n, st.n_valid,
+                                      s->grid.dims, st.m, st.q,
+                                      st.weight * dv, s->acc, s->stream));
+    HIP_TRY(launch_field_sums<R>(s->fields<R>(), s->acc, s->stream));
+    return SFPIC_OK;
+  }));
+  SF_TRY(deposit_rho(s, s->rho));
+  SF_TRY(s->dispatch([&](auto z) -> int {
+    using R = decltype(z);
+    HIP_TRY(launch_gauss<R>(s->fields<R>(), s->grid.dims, (int)s->grid.nx,
+                            (int)s->grid.ny, s->grid.dx, s->grid.dy, s->rho,
+                            s->rho0, s->pitch, s->acc, s->stream));
+    return SFPIC_OK;
+  }));
   double h[8];
   HIP_TRY(hipMemcpyAsync(h, s->acc, 8 * 8, hipMemcpyDeviceToHost, s->stream));
   HIP_TRY(hipStreamSynchronize(s->stream));
@@ -653,8 +792,7 @@ int sfpic_diagnostics(sfpic_sim *s, sfpic_diag *out) {
 
 int sfpic_histogram(sfpic_sim *s, const sfpic_hist_spec *spec, double *out,
                     size_t n, double *moments) {
-  int r = guarded(s);
-  if (r) return r;
+  SF_TRY(guarded(s));
   if (!spec || !out) return fail(SFPIC_E_INVAL, "NULL argument");
   if (spec->species < 0 || spec->species >= (int)s->sp.size() ||
       spec->n_energy <= 0 || spec->n_theta <= 0 || !(spec->e_max > 0.0))
@@ -664,61 +802,58 @@ int sfpic_histogram(sfpic_sim *s, const sfpic_hist_spec *spec, double *out,
   double *d = (double *)s->dalloc((nb + 8) * 8);
   if (!d) return fail(SFPIC_E_NOMEM, "histogram allocation failed");
   SpeciesState &st = s->sp[spec->species];
-  int rc = SFPIC_OK;
   double mom[8] = {0};
-  if (hipMemsetAsync(d, 0, (nb + 8) * 8, s->stream) != hipSuccess ||
-      launch_histogram<double>(st.p64, st.n, st.n_valid, st.m,
-                               st.weight * s->cell_volume(),
-                               spec->n_energy, spec->e_max, spec->n_theta,
-                               spec->ek_min, d + 8, d, s->stream) != hipSuccess ||
-      hipMemcpyAsync(out, d + 8, nb * 8, hipMemcpyDeviceToHost, s->stream) != hipSuccess ||
-      hipMemcpyAsync(mom, d, 8 * 8, hipMemcpyDeviceToHost, s->stream) != hipSuccess ||
-      hipStreamSynchronize(s->stream) != hipSuccess)
-    rc = fail(SFPIC_E_DEVICE, "histogram failed");
-  for (size_t k = 0; k < s->allocs.size(); ++k)
-    if (s->allocs[k].first == d) {
-      if (s->rt.free)
-        s->rt.free(d, s->allocs[k].second, s->rt.alloc_ctx);
-      else
-        (void)hipFree(d);
-      s->allocs.erase(s->allocs.begin() + k);
-      break;
-    }
+  int rc = s->dispatch([&](auto z) -> int {
+    using R = decltype(z);
+    HIP_TRY(hipMemsetAsync(d, 0, (nb + 8) * 8, s->stream));
+    HIP_TRY(launch_histogram<R>(parts<R>(st), st.n, st.n_valid, s->grid.dims,
+                                st.m, st.weight * s->cell_volume(),
+                                spec->n_energy, spec->e_max, spec->n_theta,
+                                spec->ek_min, d + 8, d, s->stream));
+    HIP_TRY(hipMemcpyAsync(out, d + 8, nb * 8, hipMemcpyDeviceToHost,
+                           s->stream));
+    HIP_TRY(hipMemcpyAsync(mom, d, 8 * 8, hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    return SFPIC_OK;
+  });
+  s->dfree(d);
   if (rc) return rc;
   if (moments) {
     moments[0] = mom[0];
-    for (int k = 1; k < 5; ++k) moments[k] = mom[0] > 0.0 ? mom[k] / mom[0] : 0.0;
+    for (int k = 1; k < 5; ++k)
+      moments[k] = mom[0] > 0.0 ? mom[k] / mom[0] : 0.0;
   }
   return SFPIC_OK;
 }
 
 // State layout: header (magic, dims, nx, ny, precision, nspecies, step,
-// element size), 9 field planes [NY][NX], then per species: slot count and
-// the raw particle arrays.
+// element size), 9 field planes [NY][NX] in the working precision, then per
+// species: the used slot count and the raw particle arrays of those slots.
 int sfpic_get_state(sfpic_sim *s, void *buf, size_t *n) {
-  int r = guarded(s);
-  if (r) return r;
+  SF_TRY(guarded(s));
   if (!n) return fail(SFPIC_E_INVAL, "n is NULL");
-  const size_t es = s->esize();
+  const size_t es = s->esize(), bpp = bytes_per_particle(s->precision);
   HIP_TRY(hipStreamSynchronize(s->stream));
   std::vector<uint32_t> nv(s->sp.size());
   for (size_t k = 0; k < s->sp.size(); ++k)
     HIP_TRY(hipMemcpy(&nv[k], s->sp[k].n_valid, 4, hipMemcpyDeviceToHost));
   size_t need = 8 * 8 + 9 * (size_t)s->NX * s->NY * es;
-  for (size_t k = 0; k < s->sp.size(); ++k) need += 8 + (size_t)nv[k] * (5 * es + 4);
+  for (size_t k = 0; k < s->sp.size(); ++k) need += 8 + (size_t)nv[k] * bpp;
   if (!buf) {
     *n = need;
     return SFPIC_OK;
   }
   if (*n < need) return fail(SFPIC_E_SIZE, "state buffer too small");
   uint8_t *p = (uint8_t *)buf;
-  int64_t hdr[8] = {(int64_t)kStateMagic, s->grid.dims, s->grid.nx, s->grid.ny,
-                    s->precision, (int64_t)s->sp.size(), s->step, (int64_t)es};
+  int64_t hdr[8] = {(int64_t)kStateMagic, s->grid.dims, s->grid.nx,
+                    s->grid.ny, s->precision, (int64_t)s->sp.size(), s->step,
+                    (int64_t)es};
   memcpy(p, hdr, sizeof(hdr));
   p += sizeof(hdr);
   for (int c = 0; c < 9; ++c) {
-    HIP_TRY(hipMemcpy2D(p, (size_t)s->NX * es, s->planes[c], (size_t)s->pitch * es,
-                        (size_t)s->NX * es, s->NY, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy2D(p, (size_t)s->NX * es, s->planes[c],
+                        (size_t)s->pitch * es, (size_t)s->NX * es, s->NY,
+                        hipMemcpyDeviceToHost));
     p += (size_t)s->NX * s->NY * es;
   }
   for (size_t k = 0; k < s->sp.size(); ++k) {
@@ -726,36 +861,39 @@ int sfpic_get_state(sfpic_sim *s, void *buf, size_t *n) {
     const int64_t cnt = nv[k];
     memcpy(p, &cnt, 8);
     p += 8;
-    const size_t bytes = (size_t)cnt * es;
-    void *arrs[5] = {st.p64.px, st.p64.py, st.p64.ux, st.p64.uy, st.p64.uz};
-    for (auto a : arrs) {
-      if (bytes) HIP_TRY(hipMemcpy(p, a, bytes, hipMemcpyDeviceToHost));
-      p += bytes;
+    void *ptr[7];
+    size_t sz[7];
+    const int na = s->precision == SFPIC_FP64 ? raw_arrays(st.p64, ptr, sz)
+                                              : raw_arrays(st.p32, ptr, sz);
+    for (int a = 0; a < na; ++a) {
+      if (cnt)
+        HIP_TRY(hipMemcpy(p, ptr[a], (size_t)cnt * sz[a],
+                          hipMemcpyDeviceToHost));
+      p += (size_t)cnt * sz[a];
     }
-    if (cnt) HIP_TRY(hipMemcpy(p, st.p64.id, (size_t)cnt * 4, hipMemcpyDeviceToHost));
-    p += (size_t)cnt * 4;
   }
   *n = need;
   return SFPIC_OK;
 }
 
 int sfpic_set_state(sfpic_sim *s, const void *buf, size_t n) {
-  int r = guarded(s);
-  if (r) return r;
+  SF_TRY(guarded(s));
   if (!buf) return fail(SFPIC_E_INVAL, "buf is NULL");
-  const size_t es = s->esize();
+  const size_t es = s->esize(), bpp = bytes_per_particle(s->precision);
   if (n < 64) return fail(SFPIC_E_SIZE, "state too short");
   const uint8_t *p = (const uint8_t *)buf;
   const uint8_t *end = p + n;
   int64_t hdr[8];
   memcpy(hdr, p, sizeof(hdr));
   if (hdr[0] != (int64_t)kStateMagic || hdr[1] != s->grid.dims ||
-      hdr[2] != s->grid.nx || hdr[3] != s->grid.ny || hdr[4] != s->precision ||
-      hdr[5] != (int64_t)s->sp.size() || hdr[7] != (int64_t)es)
+      hdr[2] != s->grid.nx || hdr[3] != s->grid.ny ||
+      hdr[4] != s->precision || hdr[5] != (int64_t)s->sp.size() ||
+      hdr[7] != (int64_t)es || hdr[6] < 0)
     return fail(SFPIC_E_INVAL, "state does not match this sim");
   p += 64;
   const size_t plane = (size_t)s->NX * s->NY * es;
-  if ((size_t)(end - p) < 9 * plane) return fail(SFPIC_E_SIZE, "state truncated");
+  if ((size_t)(end - p) < 9 * plane)
+    return fail(SFPIC_E_SIZE, "state truncated");
   // validate the particle blocks before touching device state
   const uint8_t *q = p + 9 * plane;
   for (auto &st : s->sp) {
@@ -764,41 +902,45 @@ int sfpic_set_state(sfpic_sim *s, const void *buf, size_t n) {
     memcpy(&cnt, q, 8);
     if (cnt < 0 || cnt > st.n)
       return fail(SFPIC_E_INVAL, "particle count exceeds this sim's capacity");
-    q += 8 + (size_t)cnt * (5 * es + 4);
-    if (q > end) return fail(SFPIC_E_SIZE, "state truncated");
+    q += 8;
+    if ((size_t)(end - q) < (size_t)cnt * bpp)
+      return fail(SFPIC_E_SIZE, "state truncated");
+    q += (size_t)cnt * bpp;
   }
-  if (q != end) return fail(SFPIC_E_SIZE, "state size does not match this sim");
+  if (q != end)
+    return fail(SFPIC_E_SIZE, "state size does not match this sim");
   HIP_TRY(hipStreamSynchronize(s->stream));
   for (int c = 0; c < 9; ++c) {
-    HIP_TRY(hipMemcpy2D(s->planes[c], (size_t)s->pitch * es, p, (size_t)s->NX * es,
-                        (size_t)s->NX * es, s->NY, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy2D(s->planes[c], (size_t)s->pitch * es, p,
+                        (size_t)s->NX * es, (size_t)s->NX * es, s->NY,
+                        hipMemcpyHostToDevice));
     p += plane;
   }
   for (auto &st : s->sp) {
     int64_t cnt;
     memcpy(&cnt, p, 8);
     p += 8;
-    const size_t bytes = (size_t)cnt * es;
-    void *arrs[5] = {st.p64.px, st.p64.py, st.p64.ux, st.p64.uy, st.p64.uz};
-    for (auto a : arrs) {
-      if (bytes) HIP_TRY(hipMemcpy(a, p, bytes, hipMemcpyHostToDevice));
-      p += bytes;
+    void *ptr[7];
+    size_t sz[7];
+    const int na = s->precision == SFPIC_FP64 ? raw_arrays(st.p64, ptr, sz)
+                                              : raw_arrays(st.p32, ptr, sz);
+    for (int a = 0; a < na; ++a) {
+      if (cnt)
+        HIP_TRY(hipMemcpy(ptr[a], p, (size_t)cnt * sz[a],
+                          hipMemcpyHostToDevice));
+      p += (size_t)cnt * sz[a];
     }
-    if (cnt) HIP_TRY(hipMemcpy(st.p64.id, p, (size_t)cnt * 4, hipMemcpyHostToDevice));
-    p += (size_t)cnt * 4;
     const uint32_t nv = (uint32_t)cnt;
     HIP_TRY(hipMemcpy(st.n_valid, &nv, 4, hipMemcpyHostToDevice));
   }
   s->step = hdr[6];
-  r = sort_all(s);
-  if (r) return r;
+  SF_TRY(sort_all(s));
   HIP_TRY(hipStreamSynchronize(s->stream));
   return SFPIC_OK;
 }
 
 int sfpic_profile(sfpic_sim *s, int enable) {
-  int r = guarded(s);
-  if (r) return r;
+  SF_TRY(guarded(s));
   HIP_TRY(hipStreamSynchronize(s->stream));
   if (enable) s->recycle_events();
   s->profiling = enable != 0;
@@ -806,8 +948,7 @@ int sfpic_profile(sfpic_sim *s, int enable) {
 }
 
 int sfpic_profile_read(sfpic_sim *s, sfpic_kernel_stats *out) {
-  int r = guarded(s);
-  if (r) return r;
+  SF_TRY(guarded(s));
   if (!out) return fail(SFPIC_E_INVAL, "out is NULL");
   HIP_TRY(hipStreamSynchronize(s->stream));
   for (int c = 0; c < SFPIC_KCLASSES; ++c) {

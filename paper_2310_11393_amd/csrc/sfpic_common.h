@@ -174,33 +174,60 @@ struct AprilBlocks {
   cx<double> phitt, d1, d1t, d2;
 };
 
-__host__ __device__ inline AprilBlocks april_blocks_closed(const IncParams &P,
-                                                            cx<double> u2,
-                                                            double tau) {
-  cx<double> u = csqrt_any(u2);
-  // 1 - i tau+-/s = (1 + a/s +- a u_i/s) - i (tau +- a u_r)/s
-  const double as = P.a_over_s;
-  cx<double> wp = mk(1.0 + as + as * u.i, -(tau + P.a * u.r) * P.inv_s);
-  cx<double> wm = mk(1.0 + as - as * u.i, -(tau - P.a * u.r) * P.inv_s);
-  cx<double> rp = cinv(wp), rm = cinv(wm);
-  cx<double> pp0 = cpowi(rp, P.s_int + 1), pm0 = cpowi(rm, P.s_int + 1);
-  cx<double> pp1 = pp0 * rp, pm1 = pm0 * rm;
-  cx<double> pp2 = pp1 * rp, pm2 = pm1 * rm;
-  cx<double> c0 = mk(P.cr[0], P.ci[0]), c1 = mk(P.cr[1], P.ci[1]),
-             c2 = mk(P.cr[2], P.ci[2]);
-  cx<double> gp0 = c0 * pp0, gm0 = c0 * pm0;
-  cx<double> gp1 = c1 * pp1, gm1 = c1 * pm1;
-  cx<double> gp2 = c2 * pp2, gm2 = c2 * pm2;
-  cx<double> Gm0 = gp0 - gm0, Gp1 = gp1 + gm1, Gm1 = gp1 - gm1;
-  cx<double> Gp2 = gp2 + gm2, Gm2 = gp2 - gm2;
-  cx<double> iu = cinv(u);
-  cx<double> iu2 = iu * iu, iu3 = iu2 * iu;
-  AprilBlocks b;
+// Closed-form blocks from the root u and w+- = 1 - i tau+-/s, evaluated in
+// precision T (the caller forms u and w+- in FP64: tau +- a u_r is where the
+// phase is decided and cancellation happens).
+template <typename T>
+struct Blocks {
+  cx<T> phitt, d1, d1t, d2;
+};
+
+template <typename T>
+__host__ __device__ inline Blocks<T> april_blocks_rest(const IncParams &P,
+                                                       cx<T> u, cx<T> wp,
+                                                       cx<T> wm) {
+  cx<T> rp = cinv(wp), rm = cinv(wm);
+  cx<T> pp0 = cpowi(rp, P.s_int + 1), pm0 = cpowi(rm, P.s_int + 1);
+  cx<T> pp1 = pp0 * rp, pm1 = pm0 * rm;
+  cx<T> pp2 = pp1 * rp, pm2 = pm1 * rm;
+  cx<T> c0 = mk((T)P.cr[0], (T)P.ci[0]), c1 = mk((T)P.cr[1], (T)P.ci[1]),
+        c2 = mk((T)P.cr[2], (T)P.ci[2]);
+  cx<T> Gm0 = c0 * (pp0 - pm0);
+  cx<T> Gp1 = c1 * (pp1 + pm1), Gm1 = c1 * (pp1 - pm1);
+  cx<T> Gp2 = c2 * (pp2 + pm2), Gm2 = c2 * (pp2 - pm2);
+  cx<T> iu = cinv(u);
+  cx<T> iu2 = iu * iu, iu3 = iu2 * iu;
+  Blocks<T> b;
   b.phitt = Gm2 * iu;
   b.d1 = Gp1 * iu2 - Gm0 * iu3;
   b.d1t = Gp2 * iu2 - Gm1 * iu3;
-  b.d2 = (3.0 * (Gm0 * iu3) - 3.0 * (Gp1 * iu2) + Gm2 * iu) * iu2;
+  b.d2 = (T(3) * (Gm0 * iu3) - T(3) * (Gp1 * iu2) + Gm2 * iu) * iu2;
   return b;
+}
+
+// FP64 phase part: root u of u^2 and w+- = (1 + a/s +- a u_i/s) - i (tau +-
+// a u_r)/s.
+__host__ __device__ inline void april_phase(const IncParams &P, cx<double> u2,
+                                            double tau, cx<double> &u,
+                                            cx<double> &wp, cx<double> &wm) {
+  u = csqrt_any(u2);
+  const double as = P.a_over_s;
+  wp = mk(1.0 + as + as * u.i, -(tau + P.a * u.r) * P.inv_s);
+  wm = mk(1.0 + as - as * u.i, -(tau - P.a * u.r) * P.inv_s);
+}
+
+__host__ __device__ inline AprilBlocks april_blocks_closed(const IncParams &P,
+                                                            cx<double> u2,
+                                                            double tau) {
+  cx<double> u, wp, wm;
+  april_phase(P, u2, tau, u, wp, wm);
+  Blocks<double> b = april_blocks_rest<double>(P, u, wp, wm);
+  AprilBlocks r;
+  r.phitt = b.phitt;
+  r.d1 = b.d1;
+  r.d1t = b.d1t;
+  r.d2 = b.d2;
+  return r;
 }
 
 // Rare branch (particles near the ring): kept out of line so its registers do
@@ -302,6 +329,63 @@ __host__ __device__ inline void incident_field(const IncParams &P, int dims,
   }
 }
 
+// Incident field for the FP32 form: the phase (positions, time, u, tau +-
+// a u_r, the plane pulse's carrier phase after range reduction) and the ring
+// neighbourhood in FP64, the powers, blocks and fields in FP32.
+__device__ inline void incident_field_fp32(const IncParams &P, int dims,
+                                           double x, double y, double t,
+                                           float E[3], float B[3]) {
+  E[0] = E[1] = E[2] = 0.0f;
+  B[0] = B[1] = B[2] = 0.0f;
+  if (P.kind == 1) {
+    const double ph = t - P.t0 - x;
+    const double two_pi = 6.283185307179586;
+    const double r = ph - two_pi * rint(ph * (1.0 / two_pi));  // |r| <= pi
+    const float v = (float)P.a0 * sinf((float)r) *
+                    exp2f((float)(P.env_k * ph * ph));
+    E[1] = v;
+    B[2] = v;
+    return;
+  }
+  if (P.kind != 2 && P.kind != 3) return;
+  const double X = (dims == 2 ? (y - P.y_focus) : 0.0) * P.inv_a;
+  const double Z = (x - P.x_focus) * P.inv_a;
+  const double tau = t - P.t_focus;
+  const cx<double> u2 = mk(X * X + Z * Z - 1.0, 2.0 * Z);
+  if (u2.r * u2.r + u2.i * u2.i < kRingU2 * kRingU2) {
+    double Ed[3], Bd[3];
+    incident_field(P, dims, x, y, t, Ed, Bd);
+    for (int c = 0; c < 3; ++c) {
+      E[c] = (float)Ed[c];
+      B[c] = (float)Bd[c];
+    }
+    return;
+  }
+  cx<double> u, wp, wm;
+  april_phase(P, u2, tau, u, wp, wm);
+  const Blocks<float> k = april_blocks_rest<float>(
+      P, mk((float)u.r, (float)u.i), mk((float)wp.r, (float)wp.i),
+      mk((float)wm.r, (float)wm.i));
+  const float Xf = (float)X;
+  const cx<float> zp = mk((float)Z, 1.0f);
+  if (P.kind == 2) {  // LP, paper y = 0: E_x, E_z, cB_y
+    const cx<float> common = k.d1 - k.phitt + zp * k.d1t;
+    const cx<float> ex = (Xf * Xf) * k.d2 + common;
+    const cx<float> ez = Xf * (zp * k.d2) - Xf * k.d1t;
+    E[0] = ez.r;      // build x = paper z
+    E[1] = ex.r;      // build y = paper x
+    B[2] = common.r;  // build z = paper y (cB_y = common when Y = 0)
+  } else {  // RP, paper y = 0: E_x, E_z, cB_y
+    const cx<float> zd2 = zp * k.d2;
+    const cx<float> ex = Xf * zd2;
+    const cx<float> ez = k.d1 + zp * zd2 - k.phitt;
+    const cx<float> by = -Xf * k.d1t;
+    E[0] = ez.r;
+    E[1] = ex.r;
+    B[2] = by.r;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Kernel launchers (sfpic_kernels.hip)
 // ---------------------------------------------------------------------------
@@ -344,12 +428,21 @@ hipError_t launch_load_particles(const Particles<R> &p, int64_t n, int dims,
                                  const double *x, const double *y,
                                  const double *ux, const double *uy,
                                  const double *uz, double inv_dx,
-                                 double inv_dy, hipStream_t st);
+                                 double inv_dy, int nx, int ny,
+                                 hipStream_t st);
+// Used slots as FP64: out holds 5 arrays of n (x, y, ux, uy, uz; removed
+// particles have x = -1), ids the particle ids.
+template <typename R>
+hipError_t launch_export_particles(const Particles<R> &p, int64_t n, int dims,
+                                   double dx, double dy, double *out,
+                                   uint32_t *ids, hipStream_t st);
+
 // FP64 diagnostics: particle sums {w_kin, charge, n_alive, nonfinite}.
 template <typename R>
 hipError_t launch_particle_sums(const Particles<R> &p, int64_t n,
-                                const uint32_t *n_valid, double m, double q,
-                                double wdv, double *acc, hipStream_t st);
+                                const uint32_t *n_valid, int dims, double m,
+                                double q, double wdv, double *acc,
+                                hipStream_t st);
 template <typename R>
 hipError_t launch_field_sums(const Fields<R> &f, double *acc, hipStream_t st);
 template <typename R>
@@ -363,8 +456,9 @@ hipError_t launch_gauss(const Fields<R> &f, int dims, int nx, int ny,
                         hipStream_t st);
 template <typename R>
 hipError_t launch_histogram(const Particles<R> &p, int64_t n,
-                            const uint32_t *n_valid, double m, double wdv,
-                            int n_e, double emax, int n_t, double ek_min,
-                            double *hist, double *mom, hipStream_t st);
+                            const uint32_t *n_valid, int dims, double m,
+                            double wdv, int n_e, double emax, int n_t,
+                            double ek_min, double *hist, double *mom,
+                            hipStream_t st);
 
 }  // namespace sfpic

@@ -91,4 +91,46 @@ __device__ __forceinline__ void u01_pair(const uint32_t r[4], double &a,
 }
 
 
+// Position of particle slot i in cell units (double); false if removed.
+__device__ __forceinline__ bool pos_of(const Particles<double> &p, int64_t i,
+                                       int dims, double &xi, double &yi) {
+  xi = p.px[i];
+  yi = dims == 2 ? p.py[i] : 0.0;
+  return xi >= -1.0;
+}
+__device__ __forceinline__ bool pos_of(const Particles<float> &p, int64_t i,
+                                       int dims, double &xi, double &yi) {
+  const uint32_t c = p.cell[i];
+  if (c == kDeadCell) return false;
+  xi = (double)(c & 0xFFFFu) + (double)p.ox[i];
+  yi = dims == 2 ? (double)(c >> 16) + (double)p.oy[i] : 0.0;
+  return true;
+}
+
+// Store a placed particle given its cell-unit position (offsets kept < 1).
+__device__ __forceinline__ void place(const Particles<double> &p, int64_t i,
+                                      int dims, int64_t cx, double fx,
+                                      int64_t cy, double fy, double ux,
+                                      double uy, double uz) {
+  p.px[i] = (double)cx + fx;
+  if (dims == 2) p.py[i] = (double)cy + fy;
+  p.ux[i] = ux;
+  p.uy[i] = uy;
+  p.uz[i] = uz;
+}
+__device__ __forceinline__ void place(const Particles<float> &p, int64_t i,
+                                      int dims, int64_t cx, double fx,
+                                      int64_t cy, double fy, double ux,
+                                      double uy, double uz) {
+  float ox = (float)fx, oy = (float)fy;
+  if (!(ox < 1.0f)) ox = 0.99999994f;
+  if (!(oy < 1.0f)) oy = 0.99999994f;
+  p.cell[i] = (uint32_t)cx | ((uint32_t)(dims == 2 ? cy : 0) << 16);
+  p.ox[i] = ox;
+  if (dims == 2) p.oy[i] = oy;
+  p.ux[i] = (float)ux;
+  p.uy[i] = (float)uy;
+  p.uz[i] = (float)uz;
+}
+
 }  // namespace sfpic

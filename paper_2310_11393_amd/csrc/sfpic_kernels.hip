@@ -170,10 +170,10 @@ hipError_t launch_ampere(const Fields<R> &f, int dims, double dt, double dx,
 // ---------------------------------------------------------------------------
 // Particle placement (Philox4x32-10 counter-based draws, see sfpic_device.h)
 // ---------------------------------------------------------------------------
-__global__ void init_particles_f64(Particles<double> p, int64_t n, int dims,
-                                   int64_t x0, int64_t ncx, int64_t y0,
-                                   int ppc, double sigma, uint32_t k0,
-                                   uint32_t k1) {
+template <typename R>
+__global__ void init_particles(Particles<R> p, int64_t n, int dims, int64_t x0,
+                               int64_t ncx, int64_t y0, int ppc, double sigma,
+                               uint32_t k0, uint32_t k1) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int64_t cell = i / ppc;
@@ -182,8 +182,6 @@ __global__ void init_particles_f64(Particles<double> p, int64_t n, int dims,
   philox4x32_10(c, k0, k1);
   double a, b;
   u01_pair(c, a, b);
-  p.px[i] = (double)cx + a;
-  if (dims == 2) p.py[i] = (double)cy + b;
   double ux = 0.0, uy = 0.0, uz = 0.0;
   if (sigma > 0.0) {
     uint32_t c1[4] = {(uint32_t)i, (uint32_t)((uint64_t)i >> 32), 1u, 0u};
@@ -199,50 +197,63 @@ __global__ void init_particles_f64(Particles<double> p, int64_t n, int dims,
     uy = sigma * r1 * sin(tp * b1);
     uz = sigma * r2 * cos(tp * b2);
   }
-  p.ux[i] = ux;
-  p.uy[i] = uy;
-  p.uz[i] = uz;
+  place(p, i, dims, cx, a, cy, b, ux, uy, uz);
   p.id[i] = (uint32_t)i;
 }
 
-template <>
-hipError_t launch_init_particles<double>(const Particles<double> &p,
-                                         int64_t n, int dims, int64_t x0,
-                                         int64_t ncx, int64_t y0, int ppc,
-                                         double sigma, uint64_t seed,
-                                         uint32_t key1, double, double,
-                                         hipStream_t st) {
+template <typename R>
+hipError_t launch_init_particles(const Particles<R> &p, int64_t n, int dims,
+                                 int64_t x0, int64_t ncx, int64_t y0, int ppc,
+                                 double sigma, uint64_t seed, uint32_t key1,
+                                 double, double, hipStream_t st) {
   if (n <= 0) return hipSuccess;
-  init_particles_f64<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(
+  init_particles<R><<<(unsigned)((n + 255) / 256), 256, 0, st>>>(
       p, n, dims, x0, ncx, y0, ppc, sigma, (uint32_t)seed, key1);
   return hipGetLastError();
 }
 
-__global__ void load_particles_f64(Particles<double> p, int64_t n, int dims,
-                                   const double *x, const double *y,
-                                   const double *ux, const double *uy,
-                                   const double *uz, double inv_dx,
-                                   double inv_dy) {
+// Explicit particles: physical positions to (cell, offset), clamped into
+// the physical box [0, nx) x [0, ny) against rounding.
+template <typename R>
+__global__ void load_particles(Particles<R> p, int64_t n, int dims,
+                               const double *x, const double *y,
+                               const double *ux, const double *uy,
+                               const double *uz, double inv_dx, double inv_dy,
+                               int nx, int ny) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  p.px[i] = x[i] * inv_dx;
-  if (dims == 2) p.py[i] = y[i] * inv_dy;
-  p.ux[i] = ux[i];
-  p.uy[i] = uy[i];
-  p.uz[i] = uz[i];
+  const double xi = x[i] * inv_dx;
+  int64_t cx = (int64_t)floor(xi);
+  double fx = xi - (double)cx;
+  if (cx >= nx) {
+    cx = nx - 1;
+    fx = 0.99999999999999989;
+  }
+  int64_t cy = 0;
+  double fy = 0.0;
+  if (dims == 2) {
+    const double yi = y[i] * inv_dy;
+    cy = (int64_t)floor(yi);
+    fy = yi - (double)cy;
+    if (cy >= ny) {
+      cy = ny - 1;
+      fy = 0.99999999999999989;
+    }
+  }
+  place(p, i, dims, cx, fx, cy, fy, ux[i], uy[i], uz[i]);
   p.id[i] = (uint32_t)i;
 }
 
-template <>
-hipError_t launch_load_particles<double>(const Particles<double> &p,
-                                         int64_t n, int dims, const double *x,
-                                         const double *y, const double *ux,
-                                         const double *uy, const double *uz,
-                                         double inv_dx, double inv_dy,
-                                         hipStream_t st) {
+template <typename R>
+hipError_t launch_load_particles(const Particles<R> &p, int64_t n, int dims,
+                                 const double *x, const double *y,
+                                 const double *ux, const double *uy,
+                                 const double *uz, double inv_dx,
+                                 double inv_dy, int nx, int ny,
+                                 hipStream_t st) {
   if (n <= 0) return hipSuccess;
-  load_particles_f64<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(
-      p, n, dims, x, y, ux, uy, uz, inv_dx, inv_dy);
+  load_particles<R><<<(unsigned)((n + 255) / 256), 256, 0, st>>>(
+      p, n, dims, x, y, ux, uy, uz, inv_dx, inv_dy, nx, ny);
   return hipGetLastError();
 }
 
@@ -263,16 +274,19 @@ __device__ __forceinline__ double block_sum(double v, double *sh) {
 
 __device__ __forceinline__ void atomic_max_pos(double *addr, double v) {
   // non-negative doubles order like their bit patterns
-  atomicMax((unsigned long long *)addr, (unsigned long long)__double_as_longlong(v));
+  atomicMax((unsigned long long *)addr,
+            (unsigned long long)__double_as_longlong(v));
 }
 
-__global__ void particle_sums_f64(Particles<double> p, int64_t n,
-                                  const uint32_t *n_valid, double m, double q,
-                                  double wdv, double *acc) {
+template <typename R>
+__global__ void particle_sums(Particles<R> p, int64_t n,
+                              const uint32_t *n_valid, int dims, double m,
+                              double q, double wdv, double *acc) {
   __shared__ double sh[4][8];
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   double wk = 0.0, ch = 0.0, na = 0.0, bad = 0.0;
-  if (i < n && i < (int64_t)*n_valid && p.px[i] >= -1.0) {
+  double xi, yi;
+  if (i < n && i < (int64_t)*n_valid && pos_of(p, i, dims, xi, yi)) {
     const double ux = p.ux[i], uy = p.uy[i], uz = p.uz[i];
     const double g = sqrt(1.0 + ux * ux + uy * uy + uz * uz);
     if (!isfinite(g)) bad = 1.0;
@@ -292,14 +306,14 @@ __global__ void particle_sums_f64(Particles<double> p, int64_t n,
   }
 }
 
-template <>
-hipError_t launch_particle_sums<double>(const Particles<double> &p, int64_t n,
-                                        const uint32_t *n_valid, double m,
-                                        double q, double wdv, double *acc,
-                                        hipStream_t st) {
+template <typename R>
+hipError_t launch_particle_sums(const Particles<R> &p, int64_t n,
+                                const uint32_t *n_valid, int dims, double m,
+                                double q, double wdv, double *acc,
+                                hipStream_t st) {
   if (n <= 0) return hipSuccess;
-  particle_sums_f64<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(
-      p, n, n_valid, m, q, wdv, acc);
+  particle_sums<R><<<(unsigned)((n + 255) / 256), 256, 0, st>>>(
+      p, n, n_valid, dims, m, q, wdv, acc);
   return hipGetLastError();
 }
 
@@ -333,13 +347,12 @@ hipError_t launch_field_sums(const Fields<R> &f, double *acc, hipStream_t st) {
   return hipGetLastError();
 }
 
-__global__ void deposit_rho_f64(Particles<double> p, int64_t n,
-                                const uint32_t *n_valid, int dims, double qw,
-                                double *rho, int pitch) {
+template <typename R>
+__global__ void deposit_rho(Particles<R> p, int64_t n, const uint32_t *n_valid,
+                            int dims, double qw, double *rho, int pitch) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n || i >= (int64_t)*n_valid) return;
-  const double xi = p.px[i];
-  if (xi < -1.0) return;
+  double xi, yi;
+  if (i >= n || i >= (int64_t)*n_valid || !pos_of(p, i, dims, xi, yi)) return;
   const int ix = (int)floor(xi);
   const double fx = xi - ix;
   const int hx = fx >= 0.5;
@@ -347,7 +360,6 @@ __global__ void deposit_rho_f64(Particles<double> p, int64_t n,
   weights3(fx - hx, wx);
   int by = 0;
   if (dims == 2) {
-    const double yi = p.py[i];
     const int iy = (int)floor(yi);
     const double fy = yi - iy;
     const int hy = fy >= 0.5;
@@ -357,16 +369,16 @@ __global__ void deposit_rho_f64(Particles<double> p, int64_t n,
   const int bx = ix + hx - 1 + kGuard;
   for (int b = 0; b < (dims == 2 ? 3 : 1); ++b)
     for (int a = 0; a < 3; ++a)
-      unsafeAtomicAdd(&rho[(size_t)(by + b) * pitch + bx + a], qw * wx[a] * wy[b]);
+      unsafeAtomicAdd(&rho[(size_t)(by + b) * pitch + bx + a],
+                      qw * wx[a] * wy[b]);
 }
 
-template <>
-hipError_t launch_deposit_rho<double>(const Particles<double> &p, int64_t n,
-                                      const uint32_t *n_valid, int dims,
-                                      double qw, double *rho, int pitch,
-                                      hipStream_t st) {
+template <typename R>
+hipError_t launch_deposit_rho(const Particles<R> &p, int64_t n,
+                              const uint32_t *n_valid, int dims, double qw,
+                              double *rho, int pitch, hipStream_t st) {
   if (n <= 0) return hipSuccess;
-  deposit_rho_f64<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(
+  deposit_rho<R><<<(unsigned)((n + 255) / 256), 256, 0, st>>>(
       p, n, n_valid, dims, qw, rho, pitch);
   return hipGetLastError();
 }
@@ -403,15 +415,17 @@ hipError_t launch_gauss(const Fields<R> &f, int dims, int nx, int ny,
   return hipGetLastError();
 }
 
-__global__ void histogram_f64(Particles<double> p, int64_t n,
-                              const uint32_t *n_valid, double m, double wdv,
-                              int n_e, double emax, int n_t, double ek_min,
-                              double *hist, double *mom) {
+template <typename R>
+__global__ void histogram(Particles<R> p, int64_t n, const uint32_t *n_valid,
+                          int dims, double m, double wdv, int n_e, double emax,
+                          int n_t, double ek_min, double *hist, double *mom) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n || i >= (int64_t)*n_valid || p.px[i] < -1.0) return;
+  double xi, yi;
+  if (i >= n || i >= (int64_t)*n_valid || !pos_of(p, i, dims, xi, yi)) return;
   const double ux = p.ux[i], uy = p.uy[i], uz = p.uz[i];
   const double ek = m * (sqrt(1.0 + ux * ux + uy * uy + uz * uz) - 1.0);
-  const double th = atan2(sqrt(uy * uy + uz * uz), ux) * (180.0 / 3.14159265358979323846);
+  const double th =
+      atan2(sqrt(uy * uy + uz * uz), ux) * (180.0 / 3.14159265358979323846);
   if (!isfinite(ek) || !isfinite(th)) return;
   const double ie = floor(ek / emax * n_e);
   const double tt = fmin(floor(th / 180.0 * n_t), (double)(n_t - 1));
@@ -426,27 +440,79 @@ __global__ void histogram_f64(Particles<double> p, int64_t n,
   }
 }
 
-template <>
-hipError_t launch_histogram<double>(const Particles<double> &p, int64_t n,
-                                    const uint32_t *n_valid, double m,
-                                    double wdv, int n_e, double emax, int n_t,
-                                    double ek_min, double *hist, double *mom,
-                                    hipStream_t st) {
+template <typename R>
+hipError_t launch_histogram(const Particles<R> &p, int64_t n,
+                            const uint32_t *n_valid, int dims, double m,
+                            double wdv, int n_e, double emax, int n_t,
+                            double ek_min, double *hist, double *mom,
+                            hipStream_t st) {
   if (n <= 0) return hipSuccess;
-  histogram_f64<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(
-      p, n, n_valid, m, wdv, n_e, emax, n_t, ek_min, hist, mom);
+  histogram<R><<<(unsigned)((n + 255) / 256), 256, 0, st>>>(
+      p, n, n_valid, dims, m, wdv, n_e, emax, n_t, ek_min, hist, mom);
   return hipGetLastError();
 }
 
-template hipError_t launch_faraday<double>(const Fields<double> &, int, double,
-                                           double, double, hipStream_t);
-template hipError_t launch_ampere<double>(const Fields<double> &, int, double,
-                                          double, double, hipStream_t);
-template hipError_t launch_field_sums<double>(const Fields<double> &, double *,
-                                              hipStream_t);
-template hipError_t launch_gauss<double>(const Fields<double> &, int, int, int,
-                                         double, double, const double *,
-                                         const double *, int, double *,
-                                         hipStream_t);
+// Copy the used slots of a particle set out as FP64 physical positions and
+// momenta plus ids (removed particles get x = -1).
+template <typename R>
+__global__ void export_particles(Particles<R> p, int64_t n, int dims,
+                                 double dx, double dy, double *out,
+                                 uint32_t *ids) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double xi, yi;
+  const bool live = pos_of(p, i, dims, xi, yi);
+  out[i] = live ? xi * dx : -1.0;
+  out[n + i] = live ? yi * dy : 0.0;
+  out[2 * n + i] = (double)p.ux[i];
+  out[3 * n + i] = (double)p.uy[i];
+  out[4 * n + i] = (double)p.uz[i];
+  ids[i] = p.id[i];
+}
+
+template <typename R>
+hipError_t launch_export_particles(const Particles<R> &p, int64_t n, int dims,
+                                   double dx, double dy, double *out,
+                                   uint32_t *ids, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  export_particles<R><<<(unsigned)((n + 255) / 256), 256, 0, st>>>(
+      p, n, dims, dx, dy, out, ids);
+  return hipGetLastError();
+}
+
+#define SFPIC_INSTANTIATE_K(R)                                                \
+  template hipError_t launch_faraday<R>(const Fields<R> &, int, double,       \
+                                        double, double, hipStream_t);         \
+  template hipError_t launch_ampere<R>(const Fields<R> &, int, double,        \
+                                       double, double, hipStream_t);          \
+  template hipError_t launch_field_sums<R>(const Fields<R> &, double *,       \
+                                           hipStream_t);                      \
+  template hipError_t launch_gauss<R>(const Fields<R> &, int, int, int,       \
+                                      double, double, const double *,         \
+                                      const double *, int, double *,          \
+                                      hipStream_t);                           \
+  template hipError_t launch_init_particles<R>(                              \
+      const Particles<R> &, int64_t, int, int64_t, int64_t, int64_t, int,     \
+      double, uint64_t, uint32_t, double, double, hipStream_t);               \
+  template hipError_t launch_load_particles<R>(                              \
+      const Particles<R> &, int64_t, int, const double *, const double *,     \
+      const double *, const double *, const double *, double, double, int,    \
+      int, hipStream_t);                                                      \
+  template hipError_t launch_particle_sums<R>(const Particles<R> &, int64_t,  \
+                                              const uint32_t *, int, double,  \
+                                              double, double, double *,       \
+                                              hipStream_t);                   \
+  template hipError_t launch_deposit_rho<R>(const Particles<R> &, int64_t,    \
+                                            const uint32_t *, int, double,    \
+                                            double *, int, hipStream_t);      \
+  template hipError_t launch_histogram<R>(                                   \
+      const Particles<R> &, int64_t, const uint32_t *, int, double, double,   \
+      int, double, int, double, double *, double *, hipStream_t);             \
+  template hipError_t launch_export_particles<R>(                            \
+      const Particles<R> &, int64_t, int, double, double, double *,           \
+      uint32_t *, hipStream_t);
+
+SFPIC_INSTANTIATE_K(double)
+SFPIC_INSTANTIATE_K(float)
 
 }  // namespace sfpic

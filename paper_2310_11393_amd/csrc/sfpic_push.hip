@@ -5,13 +5,18 @@
 // Tiled push: one workgroup per tile of tx x ty cells.  The workgroup stages
 // the scattered E and centred B on the tile's node window (tile plus 3 nodes
 // below and 4 above in each direction) in LDS, accumulates the tile's current
-// in an LDS window of the same shape with LDS atomics, and adds that window to
-// the global current once.  Particles are staged through LDS in chunks of
-// 1024 and processed in transposed order (lane l takes every 16th particle of
-// the cell-sorted chunk), so the 64 lanes of a wave sit in different cells
-// and their LDS atomics rarely hit the same address.  A particle that has
-// drifted more than one cell out of its tile since the last sort takes the
-// global-memory path (global gather, global atomics).
+// in an FP64 LDS window of the same shape with LDS atomics, and adds that
+// window to the global current once.  Particles are staged through LDS in
+// chunks of 1024 and processed in transposed order (lane l takes every 16th
+// particle of the cell-sorted chunk), so the 64 lanes of a wave sit in
+// different cells and their LDS atomics rarely hit the same address.  A
+// particle that has drifted more than one cell out of its tile since the last
+// sort is listed and pushed afterwards by the straggler kernel from global
+// memory.
+//
+// Two precisions of the same kernels: FP64 (positions as doubles in cell
+// units) and the FP32 form (packed integer cell plus float offsets, float
+// fields and momenta, FP64 incident-field phase, FP64 current accumulation).
 #include "sfpic_common.h"
 #include "sfpic_device.h"
 
@@ -35,11 +40,192 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
   return (b & 7) * (nb >> 3) + (b >> 3);
 }
 
+// Largest value below 1 in precision R (offsets live in [0, 1)).
+template <typename R>
+__device__ __forceinline__ R one_below();
+template <>
+__device__ __forceinline__ double one_below<double>() {
+  return 0.99999999999999989;  // 1 - 2^-53
+}
+template <>
+__device__ __forceinline__ float one_below<float>() {
+  return 0.99999994f;  // 1 - 2^-24
+}
+
 // ---------------------------------------------------------------------------
-// Esirkepov deposition of one particle into planes (jx, jy, jz) with row
-// stride `st`; (bx, by) is the index of node (ipx - 2, ipy - 2).  S0 and S1
-// are the order-2 shapes at x^n and x^{n+1} on the 5 nodes ipx-2 .. ipx+2.
-// Only the nodes where S0 or S1 is non-zero are touched.
+// Particle storage per precision: global SoA arrays and the LDS chunk.
+// ---------------------------------------------------------------------------
+template <typename R>
+struct PT;
+
+template <>
+struct PT<double> {
+  using Word = double;
+  static constexpr int kWords = 5;  // px py ux uy uz
+  __device__ static void g2l(const Particles<double> &p, uint32_t g, Word *sp,
+                             int s, int dims) {
+    sp[s] = p.px[g];
+    if (dims == 2) sp[kChunkPad + s] = p.py[g];
+    sp[2 * kChunkPad + s] = p.ux[g];
+    sp[3 * kChunkPad + s] = p.uy[g];
+    sp[4 * kChunkPad + s] = p.uz[g];
+  }
+  __device__ static void l2g(const Particles<double> &p, uint32_t g,
+                             const Word *sp, int s, int dims) {
+    p.px[g] = sp[s];
+    if (dims == 2) p.py[g] = sp[kChunkPad + s];
+    p.ux[g] = sp[2 * kChunkPad + s];
+    p.uy[g] = sp[3 * kChunkPad + s];
+    p.uz[g] = sp[4 * kChunkPad + s];
+  }
+  // Unpack LDS slot s (stride st between arrays); false if removed.
+  __device__ static bool unpack(const Word *sp, int s, int st, int dims,
+                                int &ix, int &iy, double &fx, double &fy,
+                                double u[3]) {
+    const double xi = sp[s];
+    if (xi < -1.0) return false;
+    ix = (int)floor(xi);
+    fx = xi - ix;
+    iy = 0;
+    fy = 0.0;
+    if (dims == 2) {
+      const double yi = sp[st + s];
+      iy = (int)floor(yi);
+      fy = yi - iy;
+    }
+    u[0] = sp[2 * st + s];
+    u[1] = sp[3 * st + s];
+    u[2] = sp[4 * st + s];
+    return true;
+  }
+  __device__ static void pack(Word *sp, int s, int st, int dims, bool alive,
+                              int ix, int iy, double fx, double fy,
+                              const double u[3]) {
+    sp[s] = alive ? (double)ix + fx : kDeadPos;
+    if (dims == 2) sp[st + s] = (double)iy + fy;
+    sp[2 * st + s] = u[0];
+    sp[3 * st + s] = u[1];
+    sp[4 * st + s] = u[2];
+  }
+  __device__ static bool load_global(const Particles<double> &p, uint32_t g,
+                                     int dims, int &ix, int &iy, double &fx,
+                                     double &fy, double u[3]) {
+    const double xi = p.px[g];
+    if (xi < -1.0) return false;
+    ix = (int)floor(xi);
+    fx = xi - ix;
+    iy = 0;
+    fy = 0.0;
+    if (dims == 2) {
+      const double yi = p.py[g];
+      iy = (int)floor(yi);
+      fy = yi - iy;
+    }
+    u[0] = p.ux[g];
+    u[1] = p.uy[g];
+    u[2] = p.uz[g];
+    return true;
+  }
+  __device__ static void store_global(const Particles<double> &p, uint32_t g,
+                                      int dims, bool alive, int ix, int iy,
+                                      double fx, double fy,
+                                      const double u[3]) {
+    p.px[g] = alive ? (double)ix + fx : kDeadPos;
+    if (dims == 2) p.py[g] = (double)iy + fy;
+    p.ux[g] = u[0];
+    p.uy[g] = u[1];
+    p.uz[g] = u[2];
+  }
+};
+
+template <>
+struct PT<float> {
+  using Word = uint32_t;
+  static constexpr int kWords = 6;  // cell ox oy ux uy uz
+  __device__ static void g2l(const Particles<float> &p, uint32_t g, Word *sp,
+                             int s, int dims) {
+    sp[s] = p.cell[g];
+    sp[kChunkPad + s] = __float_as_uint(p.ox[g]);
+    if (dims == 2) sp[2 * kChunkPad + s] = __float_as_uint(p.oy[g]);
+    sp[3 * kChunkPad + s] = __float_as_uint(p.ux[g]);
+    sp[4 * kChunkPad + s] = __float_as_uint(p.uy[g]);
+    sp[5 * kChunkPad + s] = __float_as_uint(p.uz[g]);
+  }
+  __device__ static void l2g(const Particles<float> &p, uint32_t g,
+                             const Word *sp, int s, int dims) {
+    p.cell[g] = sp[s];
+    p.ox[g] = __uint_as_float(sp[kChunkPad + s]);
+    if (dims == 2) p.oy[g] = __uint_as_float(sp[2 * kChunkPad + s]);
+    p.ux[g] = __uint_as_float(sp[3 * kChunkPad + s]);
+    p.uy[g] = __uint_as_float(sp[4 * kChunkPad + s]);
+    p.uz[g] = __uint_as_float(sp[5 * kChunkPad + s]);
+  }
+  __device__ static bool unpack(const Word *sp, int s, int st, int dims,
+                                int &ix, int &iy, float &fx, float &fy,
+                                float u[3]) {
+    const uint32_t c = sp[s];
+    if (c == kDeadCell) return false;
+    ix = (int)(c & 0xFFFFu);
+    iy = (int)(c >> 16);
+    fx = __uint_as_float(sp[st + s]);
+    fy = dims == 2 ? __uint_as_float(sp[2 * st + s]) : 0.0f;
+    u[0] = __uint_as_float(sp[3 * st + s]);
+    u[1] = __uint_as_float(sp[4 * st + s]);
+    u[2] = __uint_as_float(sp[5 * st + s]);
+    return true;
+  }
+  __device__ static void pack(Word *sp, int s, int st, int dims, bool alive,
+                              int ix, int iy, float fx, float fy,
+                              const float u[3]) {
+    sp[s] = alive ? ((uint32_t)ix | ((uint32_t)iy << 16)) : kDeadCell;
+    sp[st + s] = __float_as_uint(fx);
+    if (dims == 2) sp[2 * st + s] = __float_as_uint(fy);
+    sp[3 * st + s] = __float_as_uint(u[0]);
+    sp[4 * st + s] = __float_as_uint(u[1]);
+    sp[5 * st + s] = __float_as_uint(u[2]);
+  }
+  __device__ static bool load_global(const Particles<float> &p, uint32_t g,
+                                     int dims, int &ix, int &iy, float &fx,
+                                     float &fy, float u[3]) {
+    const uint32_t c = p.cell[g];
+    if (c == kDeadCell) return false;
+    ix = (int)(c & 0xFFFFu);
+    iy = (int)(c >> 16);
+    fx = p.ox[g];
+    fy = dims == 2 ? p.oy[g] : 0.0f;
+    u[0] = p.ux[g];
+    u[1] = p.uy[g];
+    u[2] = p.uz[g];
+    return true;
+  }
+  __device__ static void store_global(const Particles<float> &p, uint32_t g,
+                                      int dims, bool alive, int ix, int iy,
+                                      float fx, float fy, const float u[3]) {
+    p.cell[g] = alive ? ((uint32_t)ix | ((uint32_t)iy << 16)) : kDeadCell;
+    p.ox[g] = fx;
+    if (dims == 2) p.oy[g] = fy;
+    p.ux[g] = u[0];
+    p.uy[g] = u[1];
+    p.uz[g] = u[2];
+  }
+};
+
+__device__ __forceinline__ void incident_r(const IncParams &inc, int dims,
+                                           double x, double y, double t,
+                                           double E[3], double B[3]) {
+  incident_field(inc, dims, x, y, t, E, B);
+}
+__device__ __forceinline__ void incident_r(const IncParams &inc, int dims,
+                                           double x, double y, double t,
+                                           float E[3], float B[3]) {
+  incident_field_fp32(inc, dims, x, y, t, E, B);
+}
+
+// ---------------------------------------------------------------------------
+// Esirkepov deposition of one particle.  S0 and S1 are the order-2 shapes at
+// x^n and x^{n+1} on the 5 nodes ipx-2 .. ipx+2 (ipy-2 .. ipy+2); add(c, a,
+// b, v) accumulates v into component c at node offset (a, b).  Only nodes
+// where S0 or S1 is non-zero are touched.
 // ---------------------------------------------------------------------------
 template <typename R, int DIMS, typename Add>
 __device__ __forceinline__ void esirkepov(const R S0x[5], const R S1x[5],
@@ -64,31 +250,38 @@ __device__ __forceinline__ void esirkepov(const R S0x[5], const R S1x[5],
     }
     return;
   }
-  R DSx[5], DSy[5];
+  // W_x = DSx (S0y + DSy/2), W_y = DSy (S0x + DSx/2),
+  // W_z = S0x S0y + DSx S0y/2 + S0x DSy/2 + DSx DSy/3
+  //     = S0x (S0y + DSy/2) + DSx (S0y/2 + DSy/3),
+  // with the charge factors folded into the per-row / per-column terms.
+  R DSx[5], DSy[5], cAy[5], qAy[5], qBy[5];
 #pragma unroll
   for (int k = 0; k < 5; ++k) {
     DSx[k] = S1x[k] - S0x[k];
     DSy[k] = S1y[k] - S0y[k];
+    const R ay = S0y[k] + R(0.5) * DSy[k];
+    cAy[k] = cxq * ay;
+    qAy[k] = qvz * ay;
+    qBy[k] = qvz * (R(0.5) * S0y[k] + R(1.0 / 3.0) * DSy[k]);
   }
 #pragma unroll
   for (int b = 0; b < 5; ++b) {
     if (b < loy || b > hiy) continue;
-    const R wyb = S0y[b] + R(0.5) * DSy[b];
     R acc = R(0);
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
-      acc += cxq * (DSx[a] * wyb);
+      acc += DSx[a] * cAy[b];
       if (a >= lox && a < hix) add(0, a, b, acc);
     }
   }
 #pragma unroll
   for (int a = 0; a < 5; ++a) {
     if (a < lox || a > hix) continue;
-    const R wxa = S0x[a] + R(0.5) * DSx[a];
+    const R cAx = cyq * (S0x[a] + R(0.5) * DSx[a]);
     R acc = R(0);
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
-      acc += cyq * (DSy[b] * wxa);
+      acc += DSy[b] * cAx;
       if (b >= loy && b < hiy) add(1, a, b, acc);
     }
   }
@@ -98,16 +291,13 @@ __device__ __forceinline__ void esirkepov(const R S0x[5], const R S1x[5],
 #pragma unroll
     for (int a = 0; a < 5; ++a) {
       if (a < lox || a > hix) continue;
-      const R wz = S0x[a] * S0y[b] + R(0.5) * DSx[a] * S0y[b] +
-                   R(0.5) * S0x[a] * DSy[b] + DSx[a] * DSy[b] * R(1.0 / 3.0);
-      add(2, a, b, qvz * wz);
+      add(2, a, b, S0x[a] * qAy[b] + DSx[a] * qBy[b]);
     }
   }
 }
 
 // Shapes on the 5-node support: S0 from the three order-2 weights at x^n,
-// S1 from the new offset d1 = xi^{n+1} - ipx; the support of S1 is
-// [lo, hi] within 0..4.
+// S1 from the new offset d1 = xi^{n+1} - ipx; the support of S1 is [lo, hi].
 template <typename R>
 __device__ __forceinline__ void shapes5(const R w0[3], R d1, R S0[5], R S1[5],
                                         int &lo, int &hi) {
@@ -122,14 +312,77 @@ __device__ __forceinline__ void shapes5(const R w0[3], R d1, R S0[5], R S1[5],
   hi = d1 > R(0.5) ? 4 : 3;
 }
 
+// Order-2 weights of a particle at (cell ix, offset fx): primal weights
+// around the nearest node ipx = ix + (fx >= 1/2) and dual weights around the
+// dual node of cell ix; returns ipx and sets d0 = offset from ipx.
+template <typename R>
+__device__ __forceinline__ int node_weights(int ix, R fx, R wp[3], R wd[3],
+                                            R &d0) {
+  const int h = fx >= R(0.5);
+  d0 = fx - R(h);
+  weights3(d0, wp);
+  weights3(fx - R(0.5), wd);
+  return ix + h;
+}
+
+// One particle: gather (via `gather`), incident field, Boris, advance,
+// deposit (via `add`), removal test.  Position is (cell, offset) per axis.
+template <typename R, int DIMS, typename Gather, typename Add>
+__device__ __forceinline__ bool push_particle(int &ix, int &iy, R &fx, R &fy,
+                                              R u[3], const PushParams &pp,
+                                              const IncParams &inc,
+                                              Gather gather, Add add) {
+  R wxp[3], wxd[3], wyp[3] = {R(1), R(0), R(0)}, wyd[3] = {R(1), R(0), R(0)};
+  R dx0, dy0 = R(0);
+  const int ipx = node_weights(ix, fx, wxp, wxd, dx0);
+  const int ipy = (DIMS == 2) ? node_weights(iy, fy, wyp, wyd, dy0) : 0;
+  R E[3], B[3];
+  gather(ix, iy, ipx, ipy, wxp, wxd, wyp, wyd, E, B);
+  R Ei[3], Bi[3];
+  incident_r(inc, DIMS, ((double)ix + (double)fx) * pp.dx,
+             ((double)iy + (double)fy) * pp.dy, pp.time, Ei, Bi);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    E[c] += Ei[c];
+    B[c] += Bi[c];
+  }
+  boris<R>((R)pp.qm, (R)pp.dt, u, E, B);
+  const R gi = R(1) / sqrt(R(1) + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+  // new positions as offsets from the old nearest nodes
+  const R d1x = dx0 + (R)(pp.dt * pp.inv_dx) * (u[0] * gi);
+  const R d1y = (DIMS == 2) ? dy0 + (R)(pp.dt * pp.inv_dy) * (u[1] * gi) : R(0);
+  R S0x[5], S1x[5], S0y[5] = {R(0), R(1), R(0), R(0), R(0)},
+                    S1y[5] = {R(0), R(1), R(0), R(0), R(0)};
+  int lox, hix, loy = 1, hiy = 1;
+  shapes5(wxp, d1x, S0x, S1x, lox, hix);
+  if (DIMS == 2) shapes5(wyp, d1y, S0y, S1y, loy, hiy);
+  const R qvy = (R)pp.qw * u[1] * gi, qvz = (R)pp.qw * u[2] * gi;
+  esirkepov<R, DIMS>(S0x, S1x, S0y, S1y, lox, hix, loy, hiy,
+                     (R)(-pp.qw * pp.dx / pp.dt), (R)(-pp.qw * pp.dy / pp.dt),
+                     qvy, qvz, add);
+  // new cell and offset in [0, 1)
+  const R cx1 = floor(d1x);
+  ix = ipx + (int)cx1;
+  fx = d1x - cx1;
+  if (!(fx < R(1))) fx = one_below<R>();
+  if (DIMS == 2) {
+    const R cy1 = floor(d1y);
+    iy = ipy + (int)cy1;
+    fy = d1y - cy1;
+    if (!(fy < R(1))) fy = one_below<R>();
+  }
+  return ix >= 0 && ix < pp.nx && (DIMS == 1 || (iy >= 0 && iy < pp.ny));
+}
+
 // ---------------------------------------------------------------------------
-// Tiled push, FP64
+// Tiled push
 // ---------------------------------------------------------------------------
-template <int DIMS>
+template <typename R, int DIMS>
 __global__ void __launch_bounds__(256, 2)
-push_tiled_f64(Fields<double> f, Particles<double> p,
-               const uint32_t *__restrict__ start, TileGeom tg, PushParams pp,
-               IncParams inc, uint32_t *strag, uint32_t *n_strag) {
+push_tiled(Fields<R> f, Particles<R> p, const uint32_t *__restrict__ start,
+           TileGeom tg, PushParams pp, IncParams inc, uint32_t *strag,
+           uint32_t *n_strag) {
+  using W = typename PT<R>::Word;
   extern __shared__ double smem[];
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   if (tile >= tg.ntiles) return;
@@ -142,9 +395,9 @@ push_tiled_f64(Fields<double> f, Particles<double> p,
   const int WX = tg.tx + kWinExtra;
   const int WY = (DIMS == 2) ? tg.ty + kWinExtra : 1;
   const int WN = WX * WY;
-  double *sf = smem;          // ex ey ez mx my mz windows
-  double *sj = smem + 6 * WN; // jx jy jz windows
-  double *sp = sj + 3 * WN;   // particle chunk: px py ux uy uz
+  double *sj = smem;           // jx jy jz windows (FP64 accumulation)
+  R *sf = (R *)(sj + 3 * WN);  // ex ey ez mx my mz windows
+  W *sp = (W *)(sf + 6 * WN);  // particle chunk
   const int P = f.pitch;
 
   // stage E^n and Bbar^n on the node window; array index = cx0 + local
@@ -152,125 +405,70 @@ push_tiled_f64(Fields<double> f, Particles<double> p,
     const int I = cx0 + k % WX, J = cy0 + k / WX;
     const bool in = I < f.nx_alloc && J < f.ny_alloc;
     const size_t g = (size_t)J * P + I;
-    sf[k] = in ? f.ex[g] : 0.0;
-    sf[WN + k] = in ? f.ey[g] : 0.0;
-    sf[2 * WN + k] = in ? f.ez[g] : 0.0;
-    sf[3 * WN + k] = in ? f.mx[g] : 0.0;
-    sf[4 * WN + k] = in ? f.my[g] : 0.0;
-    sf[5 * WN + k] = in ? f.mz[g] : 0.0;
+    sf[k] = in ? f.ex[g] : R(0);
+    sf[WN + k] = in ? f.ey[g] : R(0);
+    sf[2 * WN + k] = in ? f.ez[g] : R(0);
+    sf[3 * WN + k] = in ? f.mx[g] : R(0);
+    sf[4 * WN + k] = in ? f.my[g] : R(0);
+    sf[5 * WN + k] = in ? f.mz[g] : R(0);
     sj[k] = 0.0;
     sj[WN + k] = 0.0;
     sj[2 * WN + k] = 0.0;
   }
   __syncthreads();
 
+  // gather from the LDS window: first tap at window index node - c0 + 2
+  auto gather = [&](int ix, int iy, int ipx, int ipy, const R wxp[3],
+                    const R wxd[3], const R wyp[3], const R wyd[3], R E[3],
+                    R B[3]) {
+    const int bxp = ipx - cx0 + 2, bxd = ix - cx0 + 2;
+    const int byp = (DIMS == 2) ? ipy - cy0 + 2 : 0;
+    const int byd = (DIMS == 2) ? iy - cy0 + 2 : 0;
+    E[0] = gather_plane<R, DIMS>(sf, WX, bxd, byp, wxd, wyp);
+    E[1] = gather_plane<R, DIMS>(sf + WN, WX, bxp, byd, wxp, wyd);
+    E[2] = gather_plane<R, DIMS>(sf + 2 * WN, WX, bxp, byp, wxp, wyp);
+    B[0] = (DIMS == 2)
+               ? gather_plane<R, DIMS>(sf + 3 * WN, WX, bxp, byd, wxp, wyd)
+               : R(0);
+    B[1] = gather_plane<R, DIMS>(sf + 4 * WN, WX, bxd, byp, wxd, wyp);
+    B[2] = gather_plane<R, DIMS>(sf + 5 * WN, WX, bxd, byd, wxd, wyd);
+  };
+
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const double cxq = -pp.qw * pp.dx / pp.dt;
-  const double cyq = -pp.qw * pp.dy / pp.dt;
   for (uint32_t c0 = pbeg; c0 < pend; c0 += kChunk) {
     const int cn = (int)min((uint32_t)kChunk, pend - c0);
-    for (int k = threadIdx.x; k < cn; k += blockDim.x) {
-      const int s = chunk_slot(k);
-      sp[s] = p.px[c0 + k];
-      if (DIMS == 2) sp[kChunkPad + s] = p.py[c0 + k];
-      sp[2 * kChunkPad + s] = p.ux[c0 + k];
-      sp[3 * kChunkPad + s] = p.uy[c0 + k];
-      sp[4 * kChunkPad + s] = p.uz[c0 + k];
-    }
+    for (int k = threadIdx.x; k < cn; k += blockDim.x)
+      PT<R>::g2l(p, c0 + k, sp, chunk_slot(k), DIMS);
     __syncthreads();
 #pragma unroll 1
     for (int j = 0; j < 4; ++j) {
       const int idx = lane * 16 + wv * 4 + j;
       if (idx >= cn) continue;
       const int s = chunk_slot(idx);
-      const double xi = sp[s];
-      if (xi < -1.0) continue;  // removed
-      const double yi = (DIMS == 2) ? sp[kChunkPad + s] : 0.0;
-      const int ix = (int)floor(xi);
-      const double fx = xi - ix;
-      const int hx = fx >= 0.5;
-      const int ipx = ix + hx;
-      double wxp[3], wxd[3], wyp[3] = {1, 0, 0}, wyd[3] = {1, 0, 0};
-      weights3(fx - hx, wxp);
-      weights3(fx - 0.5, wxd);
-      int iy = 0, ipy = 0;
-      if (DIMS == 2) {
-        iy = (int)floor(yi);
-        const double fy = yi - iy;
-        const int hy = fy >= 0.5;
-        ipy = iy + hy;
-        weights3(fy - hy, wyp);
-        weights3(fy - 0.5, wyd);
-      }
-      // particles more than one cell outside the tile are pushed later by
-      // the straggler kernel, from global memory
+      int ix, iy;
+      R fx, fy, u[3];
+      if (!PT<R>::unpack(sp, s, kChunkPad, DIMS, ix, iy, fx, fy, u)) continue;
+      // particles more than one cell outside the tile go to the straggler
+      // list and are pushed from global memory after this kernel
       if (!(ix >= cx0 - 1 && ix <= cx0 + tg.tx &&
             (DIMS == 1 || (iy >= cy0 - 1 && iy <= cy0 + tg.ty)))) {
         strag[atomicAdd(n_strag, 1u)] = c0 + idx;
         continue;
       }
-      double E[3], B[3];
-      {
-        // window-local index of the first tap: node - (c0 - 3) - 1
-        const int bxp = ipx - cx0 + 2, bxd = ix - cx0 + 2;
-        const int byp = (DIMS == 2) ? ipy - cy0 + 2 : 0;
-        const int byd = (DIMS == 2) ? iy - cy0 + 2 : 0;
-        E[0] = gather_plane<double, DIMS>(sf, WX, bxd, byp, wxd, wyp);
-        E[1] = gather_plane<double, DIMS>(sf + WN, WX, bxp, byd, wxp, wyd);
-        E[2] = gather_plane<double, DIMS>(sf + 2 * WN, WX, bxp, byp, wxp, wyp);
-        B[0] = (DIMS == 2)
-                   ? gather_plane<double, DIMS>(sf + 3 * WN, WX, bxp, byd, wxp, wyd)
-                   : 0.0;
-        B[1] = gather_plane<double, DIMS>(sf + 4 * WN, WX, bxd, byp, wxd, wyp);
-        B[2] = gather_plane<double, DIMS>(sf + 5 * WN, WX, bxd, byd, wxd, wyd);
-      }
-      double Ei[3], Bi[3];
-      incident_field(inc, DIMS, xi * pp.dx, yi * pp.dy, pp.time, Ei, Bi);
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        E[c] += Ei[c];
-        B[c] += Bi[c];
-      }
-      double u[3] = {sp[2 * kChunkPad + s], sp[3 * kChunkPad + s],
-                     sp[4 * kChunkPad + s]};
-      boris(pp.qm, pp.dt, u, E, B);
-      const double gi =
-          1.0 / sqrt(1.0 + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
-      const double xi1 = xi + pp.dt * pp.inv_dx * (u[0] * gi);
-      const double yi1 =
-          (DIMS == 2) ? yi + pp.dt * pp.inv_dy * (u[1] * gi) : 0.0;
-
-      double S0x[5], S1x[5], S0y[5] = {0, 1, 0, 0, 0}, S1y[5] = {0, 1, 0, 0, 0};
-      int lox, hix, loy = 1, hiy = 1;
-      shapes5(wxp, xi1 - ipx, S0x, S1x, lox, hix);
-      if (DIMS == 2) shapes5(wyp, yi1 - ipy, S0y, S1y, loy, hiy);
-      const double qvy = pp.qw * u[1] * gi, qvz = pp.qw * u[2] * gi;
-      {
-        // window-local index of node ipx - 2 is ipx - cx0 + 1
-        const int bx = ipx - cx0 + 1, by = (DIMS == 2) ? ipy - cy0 + 1 : 0;
-        esirkepov<double, DIMS>(
-            S0x, S1x, S0y, S1y, lox, hix, loy, hiy, cxq, cyq, qvy, qvz,
-            [&](int c, int a, int b, double v) {
-              atomicAdd(&sj[c * WN + (by + b) * WX + bx + a], v);
-            });
-      }
-      const bool inside = (xi1 >= 0.0 && xi1 < (double)pp.nx) &&
-                          (DIMS == 1 || (yi1 >= 0.0 && yi1 < (double)pp.ny));
-      sp[s] = inside ? xi1 : kDeadPos;
-      if (DIMS == 2) sp[kChunkPad + s] = yi1;
-      sp[2 * kChunkPad + s] = u[0];
-      sp[3 * kChunkPad + s] = u[1];
-      sp[4 * kChunkPad + s] = u[2];
+      const int ipx0 = ix + (fx >= R(0.5));
+      const int ipy0 = (DIMS == 2) ? iy + (fy >= R(0.5)) : 0;
+      // window index of node ipx - 2 is ipx - c0 + 1
+      const int bx = ipx0 - cx0 + 1, by = (DIMS == 2) ? ipy0 - cy0 + 1 : 0;
+      const bool alive = push_particle<R, DIMS>(
+          ix, iy, fx, fy, u, pp, inc, gather,
+          [&](int c, int a, int b, R v) {
+            atomicAdd(&sj[c * WN + (by + b) * WX + bx + a], (double)v);
+          });
+      PT<R>::pack(sp, s, kChunkPad, DIMS, alive, ix, iy, fx, fy, u);
     }
     __syncthreads();
-    for (int k = threadIdx.x; k < cn; k += blockDim.x) {
-      const int s = chunk_slot(k);
-      p.px[c0 + k] = sp[s];
-      if (DIMS == 2) p.py[c0 + k] = sp[kChunkPad + s];
-      p.ux[c0 + k] = sp[2 * kChunkPad + s];
-      p.uy[c0 + k] = sp[3 * kChunkPad + s];
-      p.uz[c0 + k] = sp[4 * kChunkPad + s];
-    }
+    for (int k = threadIdx.x; k < cn; k += blockDim.x)
+      PT<R>::l2g(p, c0 + k, sp, chunk_slot(k), DIMS);
     __syncthreads();
   }
   // add the tile's current window to the grid
@@ -279,125 +477,88 @@ push_tiled_f64(Fields<double> f, Particles<double> p,
     if (I >= f.nx_alloc || J >= f.ny_alloc) continue;
     const size_t g = (size_t)J * P + I;
     const double vx = sj[k], vy = sj[WN + k], vz = sj[2 * WN + k];
-    if (vx != 0.0) unsafeAtomicAdd(&f.jx[g], vx);
-    if (vy != 0.0) unsafeAtomicAdd(&f.jy[g], vy);
-    if (vz != 0.0) unsafeAtomicAdd(&f.jz[g], vz);
+    if (vx != 0.0) unsafeAtomicAdd(&f.jx[g], (R)vx);
+    if (vy != 0.0) unsafeAtomicAdd(&f.jy[g], (R)vy);
+    if (vz != 0.0) unsafeAtomicAdd(&f.jz[g], (R)vz);
   }
 }
 
 // Push of the particles listed by the tiled kernel (drifted more than one
 // cell out of their tile): global gather and global atomics.
-template <int DIMS>
+template <typename R, int DIMS>
 __global__ void __launch_bounds__(256)
-push_stragglers_f64(Fields<double> f, Particles<double> p, PushParams pp,
-                    IncParams inc, const uint32_t *strag,
-                    const uint32_t *n_strag) {
+push_stragglers(Fields<R> f, Particles<R> p, PushParams pp, IncParams inc,
+                const uint32_t *strag, const uint32_t *n_strag) {
   const uint32_t n = *n_strag;
   const int P = f.pitch;
-  for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < n;
-       k += gridDim.x * blockDim.x) {
-    const uint32_t ip = strag[k];
-    const double xi = p.px[ip];
-    const double yi = (DIMS == 2) ? p.py[ip] : 0.0;
-    const int ix = (int)floor(xi);
-    const double fx = xi - ix;
-    const int hx = fx >= 0.5;
-    const int ipx = ix + hx;
-    double wxp[3], wxd[3], wyp[3] = {1, 0, 0}, wyd[3] = {1, 0, 0};
-    weights3(fx - hx, wxp);
-    weights3(fx - 0.5, wxd);
-    int iy = 0, ipy = 0;
-    if (DIMS == 2) {
-      iy = (int)floor(yi);
-      const double fy = yi - iy;
-      const int hy = fy >= 0.5;
-      ipy = iy + hy;
-      weights3(fy - hy, wyp);
-      weights3(fy - 0.5, wyd);
-    }
+  auto gather = [&](int ix, int iy, int ipx, int ipy, const R wxp[3],
+                    const R wxd[3], const R wyp[3], const R wyd[3], R E[3],
+                    R B[3]) {
     const int bxp = ipx - 1 + kGuard, bxd = ix - 1 + kGuard;
     const int byp = (DIMS == 2) ? ipy - 1 + kGuard : 0;
     const int byd = (DIMS == 2) ? iy - 1 + kGuard : 0;
-    double E[3], B[3];
-    E[0] = gather_plane<double, DIMS>(f.ex, P, bxd, byp, wxd, wyp);
-    E[1] = gather_plane<double, DIMS>(f.ey, P, bxp, byd, wxp, wyd);
-    E[2] = gather_plane<double, DIMS>(f.ez, P, bxp, byp, wxp, wyp);
-    B[0] = (DIMS == 2) ? gather_plane<double, DIMS>(f.mx, P, bxp, byd, wxp, wyd)
-                       : 0.0;
-    B[1] = gather_plane<double, DIMS>(f.my, P, bxd, byp, wxd, wyp);
-    B[2] = gather_plane<double, DIMS>(f.mz, P, bxd, byd, wxd, wyd);
-    double Ei[3], Bi[3];
-    incident_field(inc, DIMS, xi * pp.dx, yi * pp.dy, pp.time, Ei, Bi);
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      E[c] += Ei[c];
-      B[c] += Bi[c];
-    }
-    double u[3] = {p.ux[ip], p.uy[ip], p.uz[ip]};
-    boris(pp.qm, pp.dt, u, E, B);
-    const double gi = 1.0 / sqrt(1.0 + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
-    const double xi1 = xi + pp.dt * pp.inv_dx * (u[0] * gi);
-    const double yi1 = (DIMS == 2) ? yi + pp.dt * pp.inv_dy * (u[1] * gi) : 0.0;
-    double S0x[5], S1x[5], S0y[5] = {0, 1, 0, 0, 0}, S1y[5] = {0, 1, 0, 0, 0};
-    int lox, hix, loy = 1, hiy = 1;
-    shapes5(wxp, xi1 - ipx, S0x, S1x, lox, hix);
-    if (DIMS == 2) shapes5(wyp, yi1 - ipy, S0y, S1y, loy, hiy);
-    const double qvy = pp.qw * u[1] * gi, qvz = pp.qw * u[2] * gi;
-    const double cxq = -pp.qw * pp.dx / pp.dt, cyq = -pp.qw * pp.dy / pp.dt;
-    const int bx = ipx - 2 + kGuard, by = (DIMS == 2) ? ipy - 2 + kGuard : 0;
-    esirkepov<double, DIMS>(
-        S0x, S1x, S0y, S1y, lox, hix, loy, hiy, cxq, cyq, qvy, qvz,
-        [&](int c, int a, int b, double v) {
-          double *jp = c == 0 ? f.jx : (c == 1 ? f.jy : f.jz);
+    E[0] = gather_plane<R, DIMS>(f.ex, P, bxd, byp, wxd, wyp);
+    E[1] = gather_plane<R, DIMS>(f.ey, P, bxp, byd, wxp, wyd);
+    E[2] = gather_plane<R, DIMS>(f.ez, P, bxp, byp, wxp, wyp);
+    B[0] = (DIMS == 2) ? gather_plane<R, DIMS>(f.mx, P, bxp, byd, wxp, wyd)
+                       : R(0);
+    B[1] = gather_plane<R, DIMS>(f.my, P, bxd, byp, wxd, wyp);
+    B[2] = gather_plane<R, DIMS>(f.mz, P, bxd, byd, wxd, wyd);
+  };
+  for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < n;
+       k += gridDim.x * blockDim.x) {
+    const uint32_t ip = strag[k];
+    int ix, iy;
+    R fx, fy, u[3];
+    if (!PT<R>::load_global(p, ip, DIMS, ix, iy, fx, fy, u)) continue;
+    const int ipx0 = ix + (fx >= R(0.5));
+    const int ipy0 = (DIMS == 2) ? iy + (fy >= R(0.5)) : 0;
+    const int bx = ipx0 - 2 + kGuard;
+    const int by = (DIMS == 2) ? ipy0 - 2 + kGuard : 0;
+    const bool alive = push_particle<R, DIMS>(
+        ix, iy, fx, fy, u, pp, inc, gather, [&](int c, int a, int b, R v) {
+          R *jp = c == 0 ? f.jx : (c == 1 ? f.jy : f.jz);
           unsafeAtomicAdd(&jp[(size_t)(by + b) * P + bx + a], v);
         });
-    const bool inside = (xi1 >= 0.0 && xi1 < (double)pp.nx) &&
-                        (DIMS == 1 || (yi1 >= 0.0 && yi1 < (double)pp.ny));
-    p.px[ip] = inside ? xi1 : kDeadPos;
-    if (DIMS == 2) p.py[ip] = yi1;
-    p.ux[ip] = u[0];
-    p.uy[ip] = u[1];
-    p.uz[ip] = u[2];
+    PT<R>::store_global(p, ip, DIMS, alive, ix, iy, fx, fy, u);
   }
 }
 
-template <>
-size_t push_lds_bytes<double>(const TileGeom &tg, int dims) {
+template <typename R>
+size_t push_lds_bytes(const TileGeom &tg, int dims) {
   const int WX = tg.tx + kWinExtra, WY = (dims == 2) ? tg.ty + kWinExtra : 1;
-  return (size_t)(9 * WX * WY + 5 * kChunkPad) * sizeof(double);
+  return (size_t)3 * WX * WY * sizeof(double) +
+         (size_t)6 * WX * WY * sizeof(R) +
+         (size_t)PT<R>::kWords * kChunkPad * sizeof(typename PT<R>::Word);
 }
 
-template <>
-hipError_t launch_push_tiled<double>(const Fields<double> &f,
-                                     const Particles<double> &p,
-                                     const uint32_t *start, const TileGeom &tg,
-                                     int dims, const PushParams &pp,
-                                     const IncParams &inc, uint32_t *strag,
-                                     uint32_t *n_strag, hipStream_t st) {
+template <typename R>
+hipError_t launch_push_tiled(const Fields<R> &f, const Particles<R> &p,
+                             const uint32_t *start, const TileGeom &tg,
+                             int dims, const PushParams &pp,
+                             const IncParams &inc, uint32_t *strag,
+                             uint32_t *n_strag, hipStream_t st) {
   const unsigned nb = (unsigned)((tg.ntiles + 7) & ~7);
-  const size_t lds = push_lds_bytes<double>(tg, dims);
+  const size_t lds = push_lds_bytes<R>(tg, dims);
   fill_u32<<<1, 64, 0, st>>>(n_strag, 0u, 1);
   if (dims == 1)
-    push_tiled_f64<1><<<nb, 256, lds, st>>>(f, p, start, tg, pp, inc, strag,
-                                            n_strag);
+    push_tiled<R, 1><<<nb, 256, lds, st>>>(f, p, start, tg, pp, inc, strag,
+                                           n_strag);
   else
-    push_tiled_f64<2><<<nb, 256, lds, st>>>(f, p, start, tg, pp, inc, strag,
-                                            n_strag);
+    push_tiled<R, 2><<<nb, 256, lds, st>>>(f, p, start, tg, pp, inc, strag,
+                                           n_strag);
   return hipGetLastError();
 }
 
-template <>
-hipError_t launch_push_stragglers<double>(const Fields<double> &f,
-                                          const Particles<double> &p,
-                                          int dims, const PushParams &pp,
-                                          const IncParams &inc,
-                                          const uint32_t *strag,
-                                          const uint32_t *n_strag,
-                                          hipStream_t st) {
+template <typename R>
+hipError_t launch_push_stragglers(const Fields<R> &f, const Particles<R> &p,
+                                  int dims, const PushParams &pp,
+                                  const IncParams &inc, const uint32_t *strag,
+                                  const uint32_t *n_strag, hipStream_t st) {
   if (dims == 1)
-    push_stragglers_f64<1><<<512, 256, 0, st>>>(f, p, pp, inc, strag, n_strag);
+    push_stragglers<R, 1><<<512, 256, 0, st>>>(f, p, pp, inc, strag, n_strag);
   else
-    push_stragglers_f64<2><<<512, 256, 0, st>>>(f, p, pp, inc, strag, n_strag);
+    push_stragglers<R, 2><<<512, 256, 0, st>>>(f, p, pp, inc, strag, n_strag);
   return hipGetLastError();
 }
 
@@ -405,49 +566,96 @@ hipError_t launch_push_stragglers<double>(const Fields<double> &f,
 // Counting sort by cell.  key = tile * cells_per_tile + cell within tile;
 // removed particles and unused slots get key = nkeys and are dropped.
 // ---------------------------------------------------------------------------
-
-__device__ __forceinline__ uint32_t cell_key(int ix, int iy, const TileGeom &tg) {
+__device__ __forceinline__ uint32_t cell_key(int ix, int iy,
+                                             const TileGeom &tg) {
   const int tx = ix / tg.tx, ty = iy / tg.ty;
   return (uint32_t)(ty * tg.ntx + tx) * tg.cells_per_tile +
          (uint32_t)((iy - ty * tg.ty) * tg.tx + (ix - tx * tg.tx));
 }
 
-__global__ void sort_count_f64(Particles<double> p, uint32_t n_slots,
-                               const uint32_t *n_valid, TileGeom tg, int nx,
-                               int ny, int dims, uint32_t *counts,
-                               uint32_t *key, uint32_t *rank) {
+// Ranks within a cell come from atomics on the cell counters.  Particles
+// arrive cell-sorted, so the lanes of a wave share few keys: one leader lane
+// per distinct key adds the group size and hands out consecutive ranks.
+__device__ __forceinline__ uint32_t wave_aggregated_rank(bool active,
+                                                         uint32_t k,
+                                                         uint32_t *counts) {
+  const int lane = __lane_id();
+  uint64_t pending = __ballot(active);
+  uint32_t r = 0;
+  while (pending) {
+    const int leader = __ffsll((unsigned long long)pending) - 1;
+    const uint32_t kl = __shfl(k, leader, 64);
+    const bool mine = active && k == kl;
+    const uint64_t same = __ballot(mine);
+    uint32_t base = 0;
+    if (lane == leader) base = atomicAdd(&counts[kl], (uint32_t)__popcll(same));
+    base = __shfl(base, leader, 64);
+    if (mine) r = base + (uint32_t)__popcll(same & ((1ull << lane) - 1ull));
+    pending &= ~same;
+  }
+  return r;
+}
+
+template <typename R>
+__global__ void sort_count(Particles<R> p, uint32_t n_slots,
+                           const uint32_t *n_valid, TileGeom tg, int nx,
+                           int ny, int dims, uint32_t *counts, uint32_t *key,
+                           uint32_t *rank) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n_slots) return;
   uint32_t k = tg.nkeys;
-  if (i < *n_valid) {
-    const double xi = p.px[i];
-    if (xi >= -1.0) {
-      const int ix = min(max((int)floor(xi), 0), nx - 1);
-      const int iy = dims == 2 ? min(max((int)floor(p.py[i]), 0), ny - 1) : 0;
+  if (i < n_slots && i < *n_valid) {
+    int ix, iy;
+    R fx, fy, u[3];
+    if (PT<R>::load_global(p, i, dims, ix, iy, fx, fy, u)) {
+      ix = min(max(ix, 0), nx - 1);
+      iy = dims == 2 ? min(max(iy, 0), ny - 1) : 0;
       k = cell_key(ix, iy, tg);
     }
   }
-  key[i] = k;
-  rank[i] = (k < tg.nkeys) ? atomicAdd(&counts[k], 1u) : 0u;
+  const uint32_t r =
+      wave_aggregated_rank(i < n_slots && k < tg.nkeys, k, counts);
+  if (i < n_slots) {
+    key[i] = k;
+    rank[i] = r;
+  }
 }
 
-__global__ void sort_scatter_f64(Particles<double> src, Particles<double> dst,
-                                 uint32_t n_slots, int dims,
-                                 const uint32_t *__restrict__ key,
-                                 const uint32_t *__restrict__ rank,
-                                 const uint32_t *__restrict__ start,
-                                 uint32_t nkeys) {
-  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n_slots) return;
-  const uint32_t k = key[i];
-  if (k >= nkeys) return;
-  const uint32_t d = start[k] + rank[i];
+__device__ __forceinline__ void move_particle(const Particles<double> &src,
+                                              const Particles<double> &dst,
+                                              uint32_t i, uint32_t d,
+                                              int dims) {
   dst.px[d] = src.px[i];
   if (dims == 2) dst.py[d] = src.py[i];
   dst.ux[d] = src.ux[i];
   dst.uy[d] = src.uy[i];
   dst.uz[d] = src.uz[i];
   dst.id[d] = src.id[i];
+}
+__device__ __forceinline__ void move_particle(const Particles<float> &src,
+                                              const Particles<float> &dst,
+                                              uint32_t i, uint32_t d,
+                                              int dims) {
+  dst.cell[d] = src.cell[i];
+  dst.ox[d] = src.ox[i];
+  if (dims == 2) dst.oy[d] = src.oy[i];
+  dst.ux[d] = src.ux[i];
+  dst.uy[d] = src.uy[i];
+  dst.uz[d] = src.uz[i];
+  dst.id[d] = src.id[i];
+}
+
+template <typename R>
+__global__ void sort_scatter(Particles<R> src, Particles<R> dst,
+                             uint32_t n_slots, int dims,
+                             const uint32_t *__restrict__ key,
+                             const uint32_t *__restrict__ rank,
+                             const uint32_t *__restrict__ start,
+                             uint32_t nkeys) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_slots) return;
+  const uint32_t k = key[i];
+  if (k >= nkeys) return;
+  move_particle(src, dst, i, start[k] + rank[i], dims);
 }
 
 // Exclusive scan, 1024 elements per block (256 threads x 4).
@@ -488,7 +696,8 @@ __global__ void __launch_bounds__(1024) scan_sums(uint32_t *sums, uint32_t nb) {
     sh[threadIdx.x] = v;
     __syncthreads();
     for (int o = 1; o < 1024; o <<= 1) {
-      const uint32_t add = threadIdx.x >= (unsigned)o ? sh[threadIdx.x - o] : 0u;
+      const uint32_t add =
+          threadIdx.x >= (unsigned)o ? sh[threadIdx.x - o] : 0u;
       __syncthreads();
       sh[threadIdx.x] += add;
       __syncthreads();
@@ -513,26 +722,42 @@ __global__ void set_valid(uint32_t *n_valid, const uint32_t *start,
   *n_valid = start[nkeys];
 }
 
-template <>
-hipError_t launch_sort<double>(const Particles<double> &src,
-                               const Particles<double> &dst, uint32_t n_slots,
-                               uint32_t *n_valid, uint32_t *start,
-                               const TileGeom &tg, int nx, int ny, int dims,
-                               const SortScratch &s, hipStream_t st) {
+template <typename R>
+hipError_t launch_sort(const Particles<R> &src, const Particles<R> &dst,
+                       uint32_t n_slots, uint32_t *n_valid, uint32_t *start,
+                       const TileGeom &tg, int nx, int ny, int dims,
+                       const SortScratch &s, hipStream_t st) {
   const uint32_t nk1 = tg.nkeys + 1;
   fill_u32<<<(nk1 + 255) / 256, 256, 0, st>>>(s.counts, 0u, nk1);
   if (n_slots > 0)
-    sort_count_f64<<<(n_slots + 255) / 256, 256, 0, st>>>(
+    sort_count<R><<<(n_slots + 255) / 256, 256, 0, st>>>(
         src, n_slots, n_valid, tg, nx, ny, dims, s.counts, s.key, s.rank);
   const uint32_t nb = (nk1 + 1023) / 1024;
   scan_blocks<<<nb, 256, 0, st>>>(s.counts, start, s.block_sums, nk1);
   scan_sums<<<1, 1024, 0, st>>>(s.block_sums, nb);
   scan_add<<<nb, 256, 0, st>>>(start, s.block_sums, nk1);
   if (n_slots > 0)
-    sort_scatter_f64<<<(n_slots + 255) / 256, 256, 0, st>>>(
+    sort_scatter<R><<<(n_slots + 255) / 256, 256, 0, st>>>(
         src, dst, n_slots, dims, s.key, s.rank, start, tg.nkeys);
   set_valid<<<1, 1, 0, st>>>(n_valid, start, tg.nkeys);
   return hipGetLastError();
 }
+
+#define SFPIC_INSTANTIATE(R)                                                 \
+  template size_t push_lds_bytes<R>(const TileGeom &, int);                  \
+  template hipError_t launch_push_tiled<R>(                                  \
+      const Fields<R> &, const Particles<R> &, const uint32_t *,             \
+      const TileGeom &, int, const PushParams &, const IncParams &,          \
+      uint32_t *, uint32_t *, hipStream_t);                                  \
+  template hipError_t launch_push_stragglers<R>(                             \
+      const Fields<R> &, const Particles<R> &, int, const PushParams &,      \
+      const IncParams &, const uint32_t *, const uint32_t *, hipStream_t);   \
+  template hipError_t launch_sort<R>(                                        \
+      const Particles<R> &, const Particles<R> &, uint32_t, uint32_t *,      \
+      uint32_t *, const TileGeom &, int, int, int, const SortScratch &,      \
+      hipStream_t);
+
+SFPIC_INSTANTIATE(double)
+SFPIC_INSTANTIATE(float)
 
 }  // namespace sfpic

@@ -28,6 +28,15 @@ def _note(msg):
     sys.stdout.flush()
 
 
+def gauss_tol(g, d, grid, rel_eps):
+    """Attainable Gauss-law residual: div_h E is a difference of E values of
+    size max|E| divided by the cell size, so its rounding floor is a few eps
+    of max|E|/dx (plus a relative part of the charge density)."""
+    emax = max(np.max(np.abs(g.read_field(c))) for c in ("ex", "ey"))
+    return max(1e-12 * d["rho_max"],
+               64 * rel_eps * emax * (1 / grid.dx + 1 / grid.dy))
+
+
 def _small_lp(kind=wl.INC_APRIL_LP, **kw):
     args = dict(nx=136, ny=72, plasma=(40, 100, 0, 72), ppc=4, kind=kind,
                 w0_lambda=1.0, s=20.0, a0=10.0, temperature_ev=1.0, steps=50,
@@ -70,7 +79,7 @@ def test_fp64_parity_50_steps(case):
     assert gd["n_alive"] == od["n_alive"]
     assert abs(gd["w_kin"] - od["w_kin"]) <= 1e-11 * abs(od["w_kin"])
     assert abs(gd["w_em"] - od["w_em"]) <= 1e-11 * abs(od["w_em"])
-    assert gd["gauss_residual"] <= 1e-12 * max(gd["rho_max"], 1e-300)
+    assert gd["gauss_residual"] <= gauss_tol(g, gd, work.grid, 2.2e-16)
     assert gd["nonfinite"] == 0
 
 
@@ -89,6 +98,51 @@ def test_fp64_parity_tiling(tile, sort_every):
     assert den > 0 and rel <= FP64_FIELD_TOL, rel
     dpos, du, umax = particle_errors(g, o)
     assert dpos <= 1e-12 and du <= 1e-12 * max(1.0, umax), (dpos, du)
+
+
+FP32_FIELD_TOL = 1e-4
+
+
+@pytest.mark.parametrize("case", ["pulse1d_small", "lp2d_small", "rp2d_small",
+                                  "lp2d_ragged"])
+def test_fp32_form_against_fp64_oracle(case):
+    """FP32 form (integer cell + float offset, float fields and momenta,
+    FP64 incident-field phase and current accumulation) vs the FP64 oracle:
+    relative L2 of the fields <= 1e-4 after 50 steps."""
+    work = CASES[case]()
+    sp = explicit_species(work)
+    g = make_gpu(work, sp, precision=wl.FP32)
+    o = make_oracle(work, sp)
+    g.step(work.steps)
+    o.step(work.steps)
+    rel, den = field_rel_l2(g, o)
+    _note(f"[fp32] {case}: field relative L2 {rel:.3e}")
+    assert den > 0 and rel <= FP32_FIELD_TOL, rel
+    dpos, du, umax = particle_errors(g, o)
+    _note(f"[fp32] {case}: max |dx| {dpos:.2e}, max |du| {du:.2e} (|u| {umax:.2e})")
+    assert dpos <= 1e-5 and du <= 1e-4 * max(1.0, umax), (dpos, du)
+    gd = g.diagnostics()
+    assert gd["nonfinite"] == 0
+    assert gd["gauss_residual"] <= max(1e-5 * gd["rho_max"],
+                                       gauss_tol(g, gd, work.grid, 1.2e-7))
+
+
+def test_fp32_tiling_and_checkpoint():
+    work = _small_lp(a0=30.0, s=10.0)
+    sp = explicit_species(work)
+    g = make_gpu(work, sp, precision=wl.FP32, tile=(4, 4), sort_every=7)
+    o = make_oracle(work, sp)
+    g.step(20)
+    st = g.get_state()
+    g.step(30)
+    o.step(50)
+    rel, _ = field_rel_l2(g, o)
+    assert rel <= FP32_FIELD_TOL, rel
+    a = g.read_field("ey")
+    g.set_state(st)
+    g.step(30)
+    b = g.read_field("ey")
+    assert np.max(np.abs(a - b)) <= 1e-5 * np.max(np.abs(a))
 
 
 def test_fp64_two_species_parity():
@@ -278,11 +332,30 @@ def test_full_size_first_step_window(full_lp):
     assert np.max(np.abs(guy[k] - ouy)) <= 1e-12 * max(1.0, np.max(np.abs(ouy)))
 
 
+def test_full_size_fp32_rp_4096(full_lp):
+    """The 4096^2 FP32-form workload (134M particles, RP beam): the device
+    generator matches the inputs on sampled ids, a few steps keep Gauss's law
+    at FP32 level, and nothing becomes non-finite."""
+    from paper_2310_11393_amd.binding import Simulation
+    work = wl.rp_4096_fp32()
+    _note("[parity] full-size RP 4096^2 FP32: creating 134M particles")
+    sim = Simulation.from_workload(work)
+    sp = work.species[0]
+    assert sim.particle_count() == sp.count() == 134217728
+    sim.step(10)
+    d = sim.diagnostics()
+    _note(f"[parity] 4096^2 FP32 after 10 steps: {d}")
+    assert d["nonfinite"] == 0 and d["rho_max"] > 0
+    assert d["gauss_residual"] <= max(1e-5 * d["rho_max"],
+                                      gauss_tol(sim, d, work.grid, 1.2e-7))
+    sim.close()
+
+
 def test_full_size_gauss_law_after_steps(full_lp):
     work, sim = full_lp
     sim.step(20)
     d = sim.diagnostics()
     assert d["nonfinite"] == 0
     assert d["rho_max"] > 0
-    assert d["gauss_residual"] <= 1e-12 * d["rho_max"]
+    assert d["gauss_residual"] <= gauss_tol(sim, d, work.grid, 2.2e-16)
     assert d["n_alive"] <= 16777216
