@@ -30,8 +30,9 @@ METRIC = ("particle-pushes/sec (push+deposit+field) FP32 vs FP64 at stated "
 # field, closed-form branch); the derivation is listed in the design doc.
 PUSH_BYTES_PARTICLE = 2 * 5 * 8     # read + write x, y, ux, uy, uz (double)
 PUSH_BYTES_CELL = (6 + 3) * 8        # gather 6 field planes, deposit 3 planes
-PUSH_FLOPS = 1050                    # gather 164, incident 314, Boris+advance
-                                     # 68, deposit 491, rounded
+PUSH_FLOPS = 790                     # weights 36, gather 126, incident 317,
+                                     # Boris 62, advance 16, shapes 60,
+                                     # deposit 165, misc 8 (common path)
 PEAK_FP64_TFLOPS = 78.6
 PEAK_HBM_GBPS = 8000.0
 
@@ -68,6 +69,55 @@ def cpu_baseline(work, sample_rows=128, steps=3):
                        f"{dt:.1f} s")}
 
 
+def fp32_vs_fp64(steps=200, err_steps=50):
+    """The 4096^2 RP workload (134M particles) in the FP32 form and in plain
+    FP64, from the same seeded particles: throughput of each and the relative
+    L2 difference of the scattered fields after `err_steps` steps."""
+    import numpy as np
+    import torch
+    from paper_2310_11393_amd import workloads as wl
+    from paper_2310_11393_amd.binding import Simulation
+    work = wl.rp_4096_fp32()
+    res = {"workload": ("2D3V 4096x4096 cells (lambda/48), 134M cold "
+                        "electrons 32 ppc at 0.02 n_c, April RP beam "
+                        "w0=0.8 lambda s=10 a0=30"),
+           "steps": steps}
+    fields = {}
+    for prec, tag in ((wl.FP32, "fp32"), (wl.FP64, "fp64")):
+        log(f"4096^2 RP {tag}: creating {work.species[0].count()} particles")
+        sim = Simulation(work.grid, work.incident, species=work.species,
+                         precision=prec)
+        n0 = sim.particle_count()
+        stream = torch.cuda.current_stream()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e2 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        sim.step(err_steps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        fields[tag] = [sim.read_field(c) for c in
+                       ("ex", "ey", "ez", "bx", "by", "bz")]
+        sim.step(steps - err_steps)
+        e2.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) + e1.elapsed_time(e2)
+        n1 = sim.particle_count()
+        res[tag + "_pushes_per_s"] = steps * 0.5 * (n0 + n1) / (ms * 1e-3)
+        res[tag + "_ms_per_step"] = ms / steps
+        log(f"4096^2 RP {tag}: {res[tag + '_pushes_per_s'] / 1e9:.2f} G "
+            f"pushes/s")
+        sim.close()
+    num = sum(float(np.sum((a - b) ** 2)) for a, b in
+              zip(fields["fp32"], fields["fp64"]))
+    den = sum(float(np.sum(b ** 2)) for b in fields["fp64"])
+    res["fp32_vs_fp64_field_rel_l2"] = (num / den) ** 0.5
+    res["error_after_steps"] = err_steps
+    res["fp32_over_fp64"] = res["fp32_pushes_per_s"] / res["fp64_pushes_per_s"]
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -76,6 +126,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=128)
     ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--no-fp32-compare", action="store_true",
+                    help="skip the 4096^2 FP32-form vs FP64 comparison")
+    ap.add_argument("--compare-steps", type=int, default=200)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device-to-device copy (3x) "
                          "whose profiler counters calibrate HBM traffic")
@@ -168,6 +221,8 @@ def main():
                    "nonfinite": diag["nonfinite"], "n_alive": diag["n_alive"]},
     }
     sim.close()
+    if not args.no_fp32_compare:
+        out["fp32_vs_fp64"] = fp32_vs_fp64(args.compare_steps)
     if args.calibrate_copy:
         src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
         dst = torch.empty_like(src)
