@@ -144,7 +144,15 @@ typedef struct {
   int32_t tile_x, tile_y; /* particle tile in cells; 0 = library default   */
   int32_t sort_every;     /* steps between tile sorts; 0 = default         */
   int32_t device;         /* HIP device ordinal                            */
+  int32_t flags;          /* SFPIC_RT_* (batches and servers)              */
 } sfpic_runtime;
+
+/* runtime.flags: launch a batch's steps one by one instead of replaying a
+ * captured HIP graph of sort_every steps. */
+#define SFPIC_RT_NO_GRAPH 1
+/* runtime.flags: never run the batch autotuner (tile and sort cadence then
+ * come from tile_x, tile_y, sort_every or the library defaults). */
+#define SFPIC_RT_NO_AUTOTUNE 2
 
 typedef struct {
   int64_t step;          /* steps taken                                    */
@@ -248,6 +256,153 @@ int sfpic_profile_read(sfpic_sim *sim, sfpic_kernel_stats *out);
 
 /* Release the sim and its device memory (waits for queued work). */
 void sfpic_destroy(sfpic_sim *sim);
+
+/* Device memory held by the sim, in bytes. */
+int sfpic_device_bytes(sfpic_sim *sim, size_t *bytes);
+
+/* ---------------------------------------------------------------------------
+ * Sweeps.  The paper studies the same set-up over ranges of beam and plasma
+ * parameters (focusing, polarization, density: Secs. 3 and 4); a sweep runs
+ * many independent simulations of uneven size on one GPU.  Members of one
+ * precision and dimensionality advance together: each phase of a step is a
+ * single launch over all of them (the particle push is a persistent kernel
+ * that takes tiles of every member from one queue), and sort_every steps
+ * plus the tile sort are captured once as a HIP graph and replayed.
+ * ------------------------------------------------------------------------- */
+
+/* One sweep member: the arguments of sfpic_create, the number of steps to
+ * run and the energy-angle histogram reported with its result
+ * (hist.n_energy == 0: none). */
+typedef struct {
+  sfpic_grid grid;
+  const sfpic_species *species;
+  int32_t nspecies;
+  sfpic_incident incident;
+  sfpic_precision precision;
+  int64_t nsteps;
+  sfpic_hist_spec hist;
+} sfpic_sim_desc;
+
+typedef struct {
+  int32_t status;      /* SFPIC_OK, or the error that ended the member      */
+  char error[128];     /* message when status != SFPIC_OK                   */
+  sfpic_diag diag;     /* FP64 diagnostics at the end of the run            */
+  double moments[5];   /* of hist, as sfpic_histogram; zeros if none        */
+  int64_t steps;       /* steps run                                         */
+  double pushes;       /* particle pushes (live particles x steps, approx.) */
+  double t_submit;     /* seconds on the owner's clock: batch run start or  */
+  double t_start;      /*   server creation; submit, admission and result   */
+  double t_done;       /*   times                                           */
+  size_t device_bytes; /* device memory the member held                     */
+} sfpic_result;
+
+/* Device bytes a simulation created from desc with runtime rt would hold. */
+int sfpic_desc_footprint(const sfpic_sim_desc *desc, const sfpic_runtime *rt,
+                         size_t *bytes);
+
+typedef struct sfpic_batch sfpic_batch;
+
+/* Create the n members (placing their particles).  rt->stream NULL: the
+ * batch creates its own stream.  Tile size and sort cadence: rt->tile_x,
+ * tile_y, sort_every if given, otherwise chosen by the autotuner during the
+ * first steps of sfpic_batch_run (unless SFPIC_RT_NO_AUTOTUNE). */
+int sfpic_batch_create(int n, const sfpic_sim_desc *descs,
+                       const sfpic_runtime *rt, sfpic_batch **out);
+
+/* Run every member to its nsteps and compute the results (blocking). */
+int sfpic_batch_run(sfpic_batch *batch);
+
+/* Result of member i after sfpic_batch_run. */
+int sfpic_batch_result(sfpic_batch *batch, int i, sfpic_result *out);
+
+/* Borrowed handle of member i (fields, particles, histograms through the
+ * single-simulation calls; not to be stepped or destroyed by the caller). */
+int sfpic_batch_member(sfpic_batch *batch, int i, sfpic_sim **sim);
+
+#define SFPIC_MAX_GROUPS 4
+#define SFPIC_MAX_CANDIDATES 16
+typedef struct {
+  int32_t ngroups;     /* (precision, dims) classes                         */
+  int32_t precision[SFPIC_MAX_GROUPS], dims[SFPIC_MAX_GROUPS];
+  int32_t members[SFPIC_MAX_GROUPS];
+  int32_t tile_x[SFPIC_MAX_GROUPS], tile_y[SFPIC_MAX_GROUPS];
+  int32_t sort_every[SFPIC_MAX_GROUPS];
+  int32_t tuned[SFPIC_MAX_GROUPS];  /* 1: chosen by the autotuner            */
+  int32_t push_workgroups[SFPIC_MAX_GROUPS];  /* persistent push grid       */
+  /* autotuner trials of each group: tile, cadence, ns per particle push    */
+  int32_t n_candidates[SFPIC_MAX_GROUPS];
+  int32_t cand_tile_x[SFPIC_MAX_GROUPS][SFPIC_MAX_CANDIDATES];
+  int32_t cand_tile_y[SFPIC_MAX_GROUPS][SFPIC_MAX_CANDIDATES];
+  int32_t cand_sort_every[SFPIC_MAX_GROUPS][SFPIC_MAX_CANDIDATES];
+  double cand_ns_per_push[SFPIC_MAX_GROUPS][SFPIC_MAX_CANDIDATES];
+  double run_ms;       /* sfpic_batch_run, first launch to last result      */
+  double step_ms;      /* of which stepping (stream time)                   */
+  double pushes;       /* particle pushes of all members                    */
+  int64_t graph_launches;
+} sfpic_batch_info;
+
+int sfpic_batch_stats(sfpic_batch *batch, sfpic_batch_info *out);
+void sfpic_batch_destroy(sfpic_batch *batch);
+
+/* ---------------------------------------------------------------------------
+ * Serving: a request loop on a library thread.  Submitted members wait in a
+ * FIFO queue and are admitted when a slot is free and their device
+ * footprint fits the HBM budget; admitted members stay resident and advance
+ * together, sort_every steps per tick, with members admitted later joining
+ * at the next tick (continuous batching).  A finished member's result is
+ * kept on the host and its device memory released.
+ * ------------------------------------------------------------------------- */
+typedef struct sfpic_server sfpic_server;
+
+enum {
+  SFPIC_REQ_QUEUED = 1,
+  SFPIC_REQ_RUNNING = 2,
+  SFPIC_REQ_DONE = 3,
+  SFPIC_REQ_FAILED = 4
+};
+
+typedef struct {
+  int64_t submitted, admitted, completed, failed, queued, running;
+  double p50_s, p99_s, mean_s, max_s; /* submit-to-result of completed ones */
+  double pushes;         /* particle pushes done (all requests)             */
+  double busy_s;         /* wall time with at least one request running     */
+  double pushes_per_s;   /* pushes / busy_s                                 */
+  size_t bytes_in_use, bytes_peak, budget;
+  int64_t ticks;
+  int32_t max_running;   /* most requests resident at once                  */
+} sfpic_server_info;
+
+/* hbm_budget: device bytes the resident members may hold (0: 90% of the
+ * free device memory at create); max_slots: most members resident at once.
+ * The server allocates with hipMalloc on its own stream (rt->alloc and
+ * rt->stream are not used); tile and cadence come from rt or the defaults. */
+int sfpic_server_create(size_t hbm_budget, int max_slots,
+                        const sfpic_runtime *rt, sfpic_server **out);
+
+/* Queue a request (desc and its arrays are copied).  SFPIC_E_INVAL if it is
+ * invalid or could never fit the budget. */
+int sfpic_server_submit(sfpic_server *srv, const sfpic_sim_desc *desc,
+                        uint64_t *ticket);
+
+/* State of a request (SFPIC_REQ_*). */
+int sfpic_server_poll(sfpic_server *srv, uint64_t ticket, int *state);
+
+/* Block until the request is done or failed, or timeout_s passes
+ * (SFPIC_E_BUSY). */
+int sfpic_server_wait(sfpic_server *srv, uint64_t ticket, double timeout_s);
+
+/* Result of a finished request (SFPIC_E_STATE while it is not finished). */
+int sfpic_server_result(sfpic_server *srv, uint64_t ticket,
+                        sfpic_result *out);
+
+/* The request's histogram (n = hist.n_energy * hist.n_theta). */
+int sfpic_server_histogram(sfpic_server *srv, uint64_t ticket, double *out,
+                           size_t n);
+
+int sfpic_server_stats(sfpic_server *srv, sfpic_server_info *out);
+
+/* Stop the loop (running requests are abandoned) and release everything. */
+void sfpic_server_destroy(sfpic_server *srv);
 
 /* Message of the last failing call on this thread ("" if none). */
 const char *sfpic_last_error(void);

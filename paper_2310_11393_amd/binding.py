@@ -65,7 +65,11 @@ class sfpic_runtime(C.Structure):
     _fields_ = [("stream", C.c_void_p), ("alloc", ALLOC_FN),
                 ("free", FREE_FN), ("alloc_ctx", C.c_void_p),
                 ("tile_x", C.c_int32), ("tile_y", C.c_int32),
-                ("sort_every", C.c_int32), ("device", C.c_int32)]
+                ("sort_every", C.c_int32), ("device", C.c_int32),
+                ("flags", C.c_int32)]
+
+
+RT_NO_GRAPH, RT_NO_AUTOTUNE = 1, 2
 
 
 class sfpic_diag(C.Structure):
@@ -82,6 +86,53 @@ class sfpic_hist_spec(C.Structure):
                 ("ek_min", C.c_double)]
 
 
+class sfpic_sim_desc(C.Structure):
+    _fields_ = [("grid", sfpic_grid), ("species", C.POINTER(sfpic_species)),
+                ("nspecies", C.c_int32), ("incident", sfpic_incident),
+                ("precision", C.c_int), ("nsteps", C.c_int64),
+                ("hist", sfpic_hist_spec)]
+
+
+class sfpic_result(C.Structure):
+    _fields_ = [("status", C.c_int32), ("error", C.c_char * 128),
+                ("diag", sfpic_diag), ("moments", C.c_double * 5),
+                ("steps", C.c_int64), ("pushes", C.c_double),
+                ("t_submit", C.c_double), ("t_start", C.c_double),
+                ("t_done", C.c_double), ("device_bytes", C.c_size_t)]
+
+
+MAX_GROUPS, MAX_CANDIDATES = 4, 16
+_GI = C.c_int32 * MAX_GROUPS
+_GC = (C.c_int32 * MAX_CANDIDATES) * MAX_GROUPS
+
+
+class sfpic_batch_info(C.Structure):
+    _fields_ = [("ngroups", C.c_int32), ("precision", _GI), ("dims", _GI),
+                ("members", _GI), ("tile_x", _GI), ("tile_y", _GI),
+                ("sort_every", _GI), ("tuned", _GI),
+                ("push_workgroups", _GI), ("n_candidates", _GI),
+                ("cand_tile_x", _GC), ("cand_tile_y", _GC),
+                ("cand_sort_every", _GC),
+                ("cand_ns_per_push", (C.c_double * MAX_CANDIDATES)
+                 * MAX_GROUPS),
+                ("run_ms", C.c_double), ("step_ms", C.c_double),
+                ("pushes", C.c_double), ("graph_launches", C.c_int64)]
+
+
+class sfpic_server_info(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("admitted", C.c_int64),
+                ("completed", C.c_int64), ("failed", C.c_int64),
+                ("queued", C.c_int64), ("running", C.c_int64),
+                ("p50_s", C.c_double), ("p99_s", C.c_double),
+                ("mean_s", C.c_double), ("max_s", C.c_double),
+                ("pushes", C.c_double), ("busy_s", C.c_double),
+                ("pushes_per_s", C.c_double), ("bytes_in_use", C.c_size_t),
+                ("bytes_peak", C.c_size_t), ("budget", C.c_size_t),
+                ("ticks", C.c_int64), ("max_running", C.c_int32)]
+
+
+REQ_QUEUED, REQ_RUNNING, REQ_DONE, REQ_FAILED = 1, 2, 3, 4
+
 _lib = None
 
 # every symbol declared in include/sfpic.h
@@ -90,7 +141,13 @@ EXPORTS = ["sfpic_create", "sfpic_step", "sfpic_sync", "sfpic_read_field",
            "sfpic_particle_count", "sfpic_read_particles",
            "sfpic_diagnostics", "sfpic_histogram", "sfpic_get_state",
            "sfpic_set_state", "sfpic_profile", "sfpic_profile_read",
-           "sfpic_destroy", "sfpic_last_error", "sfpic_version"]
+           "sfpic_destroy", "sfpic_device_bytes", "sfpic_last_error",
+           "sfpic_version", "sfpic_desc_footprint", "sfpic_batch_create",
+           "sfpic_batch_run", "sfpic_batch_result", "sfpic_batch_member",
+           "sfpic_batch_stats", "sfpic_batch_destroy", "sfpic_server_create",
+           "sfpic_server_submit", "sfpic_server_poll", "sfpic_server_wait",
+           "sfpic_server_result", "sfpic_server_histogram",
+           "sfpic_server_stats", "sfpic_server_destroy"]
 
 KCLASSES = ("faraday", "push", "ampere", "sort", "stragglers")
 
@@ -137,8 +194,29 @@ def lib():
     L.sfpic_profile_read.argtypes = [vp, C.POINTER(sfpic_kernel_stats)]
     L.sfpic_destroy.argtypes = [vp]
     L.sfpic_destroy.restype = None
+    L.sfpic_device_bytes.argtypes = [vp, C.POINTER(sz)]
     L.sfpic_last_error.restype = C.c_char_p
     L.sfpic_version.restype = C.c_char_p
+    D = C.POINTER(sfpic_sim_desc)
+    RT = C.POINTER(sfpic_runtime)
+    L.sfpic_desc_footprint.argtypes = [D, RT, C.POINTER(sz)]
+    L.sfpic_batch_create.argtypes = [C.c_int, D, RT, C.POINTER(vp)]
+    L.sfpic_batch_run.argtypes = [vp]
+    L.sfpic_batch_result.argtypes = [vp, C.c_int, C.POINTER(sfpic_result)]
+    L.sfpic_batch_member.argtypes = [vp, C.c_int, C.POINTER(vp)]
+    L.sfpic_batch_stats.argtypes = [vp, C.POINTER(sfpic_batch_info)]
+    L.sfpic_batch_destroy.argtypes = [vp]
+    L.sfpic_batch_destroy.restype = None
+    L.sfpic_server_create.argtypes = [sz, C.c_int, RT, C.POINTER(vp)]
+    L.sfpic_server_submit.argtypes = [vp, D, C.POINTER(C.c_uint64)]
+    L.sfpic_server_poll.argtypes = [vp, C.c_uint64, C.POINTER(C.c_int)]
+    L.sfpic_server_wait.argtypes = [vp, C.c_uint64, C.c_double]
+    L.sfpic_server_result.argtypes = [vp, C.c_uint64,
+                                      C.POINTER(sfpic_result)]
+    L.sfpic_server_histogram.argtypes = [vp, C.c_uint64, _DP, sz]
+    L.sfpic_server_stats.argtypes = [vp, C.POINTER(sfpic_server_info)]
+    L.sfpic_server_destroy.argtypes = [vp]
+    L.sfpic_server_destroy.restype = None
     _lib = L
     return L
 
@@ -181,11 +259,12 @@ class _TorchMemory:
 
 
 def make_runtime(use_torch: bool = True, device: int = 0, tile=(0, 0),
-                 sort_every: int = 0):
+                 sort_every: int = 0, flags: int = 0):
     rt = sfpic_runtime()
     rt.device = device
     rt.tile_x, rt.tile_y = tile
     rt.sort_every = sort_every
+    rt.flags = flags
     keep = None
     if use_torch:
         try:
@@ -216,6 +295,81 @@ def _incident_struct(inc) -> sfpic_incident:
     return s
 
 
+def _species_structs(species=(), explicit=None):
+    """sfpic_species array from workloads.Species (generated on the device)
+    or explicit dicts {q, m, weight, x, y, ux, uy, uz}; returns the array,
+    its length and the numpy columns it points into (keep them alive)."""
+    keep = []
+    arr = []
+    if explicit is not None:
+        for e in explicit:
+            sp = sfpic_species()
+            sp.q, sp.m = e["q"], e["m"]
+            sp.weight = e["weight"]
+            cols = [np.ascontiguousarray(e[k], dtype=np.float64)
+                    for k in ("x", "y", "ux", "uy", "uz")]
+            keep += cols
+            sp.n_explicit = len(cols[0])
+            sp.x, sp.y, sp.ux, sp.uy, sp.uz = [_dp(c) for c in cols]
+            arr.append(sp)
+    else:
+        for spec in species:
+            sp = sfpic_species()
+            sp.q, sp.m, sp.density = spec.q, spec.m, spec.density
+            for i in range(4):
+                sp.region[i] = int(spec.region[i])
+            sp.ppc = spec.ppc
+            sp.temperature_ev = spec.temperature_ev
+            sp.seed = spec.seed
+            sp.species_index = spec.species_index
+            arr.append(sp)
+    return (sfpic_species * max(1, len(arr)))(*arr), len(arr), keep
+
+
+def hist_spec(sp=0, n_e=256, emax=1.0, n_theta=180,
+              ek_min=1.0e3 / 510998.95) -> sfpic_hist_spec:
+    """Energy-angle histogram: n_e energy bins over [0, emax) m_e c^2,
+    n_theta one-degree bins, moments over E_k > ek_min (default 1 keV)."""
+    return sfpic_hist_spec(sp, n_e, emax, n_theta, ek_min)
+
+
+class SimDesc:
+    """sfpic_sim_desc of a workload (keeps the arrays it points into)."""
+
+    def __init__(self, wl, nsteps=None, hist=None, explicit=None,
+                 precision=None):
+        arr, n, keep = _species_structs(wl.species if explicit is None
+                                        else (), explicit)
+        self._keep = (arr, keep)
+        d = sfpic_sim_desc()
+        d.grid = _grid_struct(wl.grid)
+        d.species = C.cast(arr, C.POINTER(sfpic_species))
+        d.nspecies = n
+        d.incident = _incident_struct(wl.incident)
+        d.precision = wl.precision if precision is None else precision
+        d.nsteps = wl.steps if nsteps is None else int(nsteps)
+        if hist is not None:
+            d.hist = hist
+        self.desc = d
+        self.workload = wl
+
+    def footprint(self, tile=(0, 0)) -> int:
+        rt = make_runtime(False, 0, tile)[0]
+        n = C.c_size_t()
+        _check(lib().sfpic_desc_footprint(C.byref(self.desc), C.byref(rt),
+                                          C.byref(n)))
+        return n.value
+
+
+def _result_dict(r: sfpic_result) -> dict:
+    return {"status": r.status, "error": r.error.decode(errors="replace"),
+            "diag": {f: getattr(r.diag, f) for f, _ in sfpic_diag._fields_},
+            "moments": list(r.moments), "steps": r.steps,
+            "pushes": r.pushes, "t_submit": r.t_submit,
+            "t_start": r.t_start, "t_done": r.t_done,
+            "device_bytes": r.device_bytes}
+
+
 class Simulation:
     """One simulation held by the library (owns the sfpic_sim handle)."""
 
@@ -228,42 +382,33 @@ class Simulation:
         L = lib()
         self.grid = grid
         self.precision = precision
+        self._borrowed = False
         self._rt, self._mem = make_runtime(use_torch, device, tile, sort_every)
-        self._keep = []
-        arr = []
-        if explicit is not None:
-            for e in explicit:
-                sp = sfpic_species()
-                sp.q, sp.m = e["q"], e["m"]
-                sp.weight = e["weight"]
-                cols = [np.ascontiguousarray(e[k], dtype=np.float64)
-                        for k in ("x", "y", "ux", "uy", "uz")]
-                self._keep += cols
-                sp.n_explicit = len(cols[0])
-                sp.x, sp.y, sp.ux, sp.uy, sp.uz = [_dp(c) for c in cols]
-                arr.append(sp)
-        else:
-            for k, spec in enumerate(species):
-                sp = sfpic_species()
-                sp.q, sp.m, sp.density = spec.q, spec.m, spec.density
-                for i in range(4):
-                    sp.region[i] = int(spec.region[i])
-                sp.ppc = spec.ppc
-                sp.temperature_ev = spec.temperature_ev
-                sp.seed = spec.seed
-                sp.species_index = spec.species_index
-                arr.append(sp)
-        self.nspecies = len(arr)
-        sp_arr = (sfpic_species * max(1, len(arr)))(*arr)
+        sp_arr, n, keep = _species_structs(species, explicit)
+        self.nspecies = n
         g = _grid_struct(grid)
         inc = _incident_struct(incident)
         h = C.c_void_p()
-        _check(L.sfpic_create(C.byref(g), sp_arr, len(arr), C.byref(inc),
+        _check(L.sfpic_create(C.byref(g), sp_arr, n, C.byref(inc),
                               precision, C.byref(self._rt), C.byref(h)))
-        self._keep = []
+        del keep
         self.h = h
         self.NX = int(grid.nx) + 2 * GUARD
         self.NY = int(grid.ny) + 2 * GUARD if grid.dims == 2 else 1
+
+    @classmethod
+    def _borrow(cls, handle, grid, precision, nspecies, owner):
+        """View of a sim owned by a batch (never destroyed from here)."""
+        self = object.__new__(cls)
+        self.grid = grid
+        self.precision = precision
+        self.nspecies = nspecies
+        self._borrowed = True
+        self._owner = owner
+        self.h = handle
+        self.NX = int(grid.nx) + 2 * GUARD
+        self.NY = int(grid.ny) + 2 * GUARD if grid.dims == 2 else 1
+        return self
 
     @classmethod
     def from_workload(cls, wl, **kw):
@@ -271,9 +416,14 @@ class Simulation:
                    precision=wl.precision, **kw)
 
     def close(self):
-        if getattr(self, "h", None):
+        if getattr(self, "h", None) and not getattr(self, "_borrowed", False):
             lib().sfpic_destroy(self.h)
-            self.h = None
+        self.h = None
+
+    def device_bytes(self) -> int:
+        n = C.c_size_t()
+        _check(lib().sfpic_device_bytes(self.h, C.byref(n)))
+        return n.value
 
     def __del__(self):
         try:
@@ -351,3 +501,131 @@ class Simulation:
     def set_state(self, state: bytes):
         buf = C.create_string_buffer(state, len(state))
         _check(lib().sfpic_set_state(self.h, buf, len(state)))
+
+
+class Batch:
+    """Many simulations advanced together (sfpic_batch_*).  members: list of
+    workloads.Workload; nsteps (default each workload's steps) may be one
+    number or a list.  Memory comes from hipMalloc, work runs on the batch's
+    own stream."""
+
+    def __init__(self, members, nsteps=None, hist=None, device=0,
+                 tile=(0, 0), sort_every=0, graph=True, autotune=True):
+        L = lib()
+        if not isinstance(nsteps, (list, tuple)):
+            nsteps = [nsteps] * len(members)
+        self.descs = [SimDesc(wl, n, hist) for wl, n in zip(members, nsteps)]
+        arr = (sfpic_sim_desc * len(self.descs))(
+            *[d.desc for d in self.descs])
+        flags = (0 if graph else RT_NO_GRAPH) | (0 if autotune
+                                                 else RT_NO_AUTOTUNE)
+        self._rt, _ = make_runtime(False, device, tile, sort_every, flags)
+        h = C.c_void_p()
+        _check(L.sfpic_batch_create(len(self.descs), arr, C.byref(self._rt),
+                                    C.byref(h)))
+        self.h = h
+        self.n = len(self.descs)
+
+    def run(self):
+        _check(lib().sfpic_batch_run(self.h))
+
+    def result(self, i) -> dict:
+        r = sfpic_result()
+        _check(lib().sfpic_batch_result(self.h, i, C.byref(r)))
+        return _result_dict(r)
+
+    def member(self, i) -> Simulation:
+        h = C.c_void_p()
+        _check(lib().sfpic_batch_member(self.h, i, C.byref(h)))
+        wl = self.descs[i].workload
+        return Simulation._borrow(h, wl.grid, self.descs[i].desc.precision,
+                                  self.descs[i].desc.nspecies, self)
+
+    def stats(self) -> dict:
+        st = sfpic_batch_info()
+        _check(lib().sfpic_batch_stats(self.h, C.byref(st)))
+        groups = []
+        for g in range(st.ngroups):
+            nc = st.n_candidates[g]
+            groups.append({
+                "precision": st.precision[g], "dims": st.dims[g],
+                "members": st.members[g],
+                "tile": (st.tile_x[g], st.tile_y[g]),
+                "sort_every": st.sort_every[g], "tuned": bool(st.tuned[g]),
+                "push_workgroups": st.push_workgroups[g],
+                "trials": [((st.cand_tile_x[g][k], st.cand_tile_y[g][k]),
+                            st.cand_sort_every[g][k],
+                            st.cand_ns_per_push[g][k]) for k in range(nc)]})
+        return {"groups": groups, "run_ms": st.run_ms,
+                "step_ms": st.step_ms, "pushes": st.pushes,
+                "graph_launches": st.graph_launches}
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().sfpic_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Request loop on a library thread (sfpic_server_*)."""
+
+    def __init__(self, budget_bytes=0, max_slots=64, device=0, tile=(0, 0),
+                 sort_every=0, graph=True):
+        L = lib()
+        flags = 0 if graph else RT_NO_GRAPH
+        self._rt, _ = make_runtime(False, device, tile, sort_every, flags)
+        h = C.c_void_p()
+        _check(L.sfpic_server_create(int(budget_bytes), int(max_slots),
+                                     C.byref(self._rt), C.byref(h)))
+        self.h = h
+        self._descs = {}
+
+    def submit(self, wl, nsteps=None, hist=None, explicit=None) -> int:
+        d = SimDesc(wl, nsteps, hist, explicit)
+        t = C.c_uint64()
+        _check(lib().sfpic_server_submit(self.h, C.byref(d.desc),
+                                         C.byref(t)))
+        self._descs[t.value] = d.desc.hist
+        return t.value
+
+    def poll(self, ticket) -> int:
+        s = C.c_int()
+        _check(lib().sfpic_server_poll(self.h, ticket, C.byref(s)))
+        return s.value
+
+    def wait(self, ticket, timeout_s=600.0):
+        _check(lib().sfpic_server_wait(self.h, ticket, float(timeout_s)))
+
+    def result(self, ticket) -> dict:
+        r = sfpic_result()
+        _check(lib().sfpic_server_result(self.h, ticket, C.byref(r)))
+        return _result_dict(r)
+
+    def histogram(self, ticket) -> np.ndarray:
+        h = self._descs[ticket]
+        out = np.empty((h.n_energy, h.n_theta))
+        _check(lib().sfpic_server_histogram(self.h, ticket, _dp(out),
+                                            out.size))
+        return out
+
+    def stats(self) -> dict:
+        st = sfpic_server_info()
+        _check(lib().sfpic_server_stats(self.h, C.byref(st)))
+        return {f: getattr(st, f) for f, _ in sfpic_server_info._fields_}
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().sfpic_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

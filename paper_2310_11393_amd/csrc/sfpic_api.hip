@@ -2,8 +2,7 @@
 // particle placement, step scheduling on the caller's HIP stream, reads,
 // diagnostics and checkpoints.  The FP64 and FP32 forms share this code; the
 // precision picks the kernel instantiation.
-#include "../../include/sfpic.h"
-#include "sfpic_common.h"
+#include "sfpic_sim.h"
 
 #include <math.h>
 #include <string.h>
@@ -15,7 +14,7 @@
 
 using namespace sfpic;
 
-namespace {
+namespace sfpic {
 
 thread_local std::string g_last_error;
 
@@ -24,148 +23,13 @@ int fail(int code, const std::string &msg) {
   return code;
 }
 
-#define HIP_TRY(expr)                                                   \
-  do {                                                                  \
-    hipError_t e_ = (expr);                                             \
-    if (e_ != hipSuccess)                                               \
-      return fail(SFPIC_E_DEVICE, std::string(#expr) + ": " +           \
-                                      hipGetErrorString(e_));           \
-  } while (0)
+}  // namespace sfpic
 
-#define SF_TRY(expr)               \
-  do {                             \
-    int r_ = (expr);               \
-    if (r_ != SFPIC_OK) return r_; \
-  } while (0)
-
-struct SpeciesState {
-  double q = -1.0, m = 1.0, weight = 0.0;
-  int64_t n = 0;               // slots (capacity)
-  uint32_t *n_valid = nullptr; // device: slots in use (live or removed)
-  uint32_t *start = nullptr;   // device: cell start offsets (nkeys + 1)
-  Particles<double> p64{}, p64_alt{};
-  Particles<float> p32{}, p32_alt{};
-};
-
-template <typename R>
-Particles<R> &parts(SpeciesState &st);
-template <>
-Particles<double> &parts<double>(SpeciesState &st) { return st.p64; }
-template <>
-Particles<float> &parts<float>(SpeciesState &st) { return st.p32; }
-template <typename R>
-Particles<R> &parts_alt(SpeciesState &st);
-template <>
-Particles<double> &parts_alt<double>(SpeciesState &st) { return st.p64_alt; }
-template <>
-Particles<float> &parts_alt<float>(SpeciesState &st) { return st.p32_alt; }
+namespace {
 
 constexpr uint64_t kStateMagic = 0x53465049435354ull;  // "SFPICST"
 
 }  // namespace
-
-struct sfpic_sim {
-  sfpic_grid grid{};
-  int precision = SFPIC_FP64;
-  sfpic_runtime rt{};
-  hipStream_t stream = nullptr;
-  int NX = 0, NY = 0, pitch = 0;
-  int64_t step = 0;
-  IncParams inc{};
-  Fields<double> f64{};
-  Fields<float> f32{};
-  void *planes[12] = {};
-  std::vector<SpeciesState> sp;
-  TileGeom tg{};
-  SortScratch ss{};
-  int sort_every = 4;
-  int64_t since_sort = 0;
-  uint32_t *strag = nullptr, *n_strag = nullptr;  // straggler list
-  double *rho0 = nullptr, *rho = nullptr, *acc = nullptr;
-  std::vector<std::pair<void *, size_t>> allocs;
-  // profiling: event pairs per kernel class, recorded in launch order
-  bool profiling = false;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_used[SFPIC_KCLASSES];
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_free;
-
-  template <typename R>
-  Fields<R> &fields();
-
-  std::pair<hipEvent_t, hipEvent_t> take_events() {
-    if (!ev_free.empty()) {
-      auto e = ev_free.back();
-      ev_free.pop_back();
-      return e;
-    }
-    std::pair<hipEvent_t, hipEvent_t> e{nullptr, nullptr};
-    (void)hipEventCreate(&e.first);
-    (void)hipEventCreate(&e.second);
-    return e;
-  }
-  void recycle_events() {
-    for (auto &v : ev_used) {
-      for (auto &e : v) ev_free.push_back(e);
-      v.clear();
-    }
-  }
-  void destroy_events() {
-    recycle_events();
-    for (auto &e : ev_free) {
-      (void)hipEventDestroy(e.first);
-      (void)hipEventDestroy(e.second);
-    }
-    ev_free.clear();
-  }
-  void *dalloc(size_t bytes) {
-    bytes = (bytes + 255) & ~(size_t)255;
-    void *p = nullptr;
-    if (rt.alloc) {
-      p = rt.alloc(bytes, rt.alloc_ctx);
-    } else if (hipMalloc(&p, bytes) != hipSuccess) {
-      p = nullptr;
-    }
-    if (p) allocs.emplace_back(p, bytes);
-    return p;
-  }
-  void dfree(void *p) {
-    for (size_t k = 0; k < allocs.size(); ++k)
-      if (allocs[k].first == p) {
-        if (rt.free)
-          rt.free(p, allocs[k].second, rt.alloc_ctx);
-        else
-          (void)hipFree(p);
-        allocs.erase(allocs.begin() + k);
-        return;
-      }
-  }
-  void release() {
-    for (auto &a : allocs) {
-      if (rt.free)
-        rt.free(a.first, a.second, rt.alloc_ctx);
-      else
-        (void)hipFree(a.first);
-    }
-    allocs.clear();
-  }
-  size_t esize() const { return precision == SFPIC_FP64 ? 8 : 4; }
-  double cell_volume() const {
-    return grid.dims == 2 ? grid.dx * grid.dy : grid.dx;
-  }
-  // Run f with a value of the working precision's type.
-  template <typename F>
-  int dispatch(F &&f) {
-    return precision == SFPIC_FP64 ? f(0.0) : f(0.0f);
-  }
-};
-
-template <>
-Fields<double> &sfpic_sim::fields<double>() {
-  return f64;
-}
-template <>
-Fields<float> &sfpic_sim::fields<float>() {
-  return f32;
-}
 
 namespace {
 
@@ -441,6 +305,10 @@ int setup_tiles(sfpic_sim *s) {
   return SFPIC_OK;
 }
 
+}  // namespace
+
+namespace sfpic {
+
 // Counting sort of every species by cell (compacts removed particles).
 int sort_all(sfpic_sim *s) {
   const int r = s->dispatch([&](auto z) -> int {
@@ -456,6 +324,108 @@ int sort_all(sfpic_sim *s) {
   s->since_sort = 0;
   return r;
 }
+
+int sim_retile(sfpic_sim *s, int tx, int ty) {
+  if (!s) return fail(SFPIC_E_INVAL, "sim is NULL");
+  const sfpic_grid &g = s->grid;
+  TileGeom t{};
+  t.tx = tx;
+  t.ty = g.dims == 2 ? ty : 1;
+  if (t.tx < 1 || t.ty < 1 || t.tx > 1024 || t.ty > 256)
+    return fail(SFPIC_E_INVAL, "tile size out of range");
+  t.ntx = (int)((g.nx + t.tx - 1) / t.tx);
+  t.nty = (g.dims == 2) ? (int)((g.ny + t.ty - 1) / t.ty) : 1;
+  t.ntiles = t.ntx * t.nty;
+  t.cells_per_tile = (uint32_t)(t.tx * t.ty);
+  const uint64_t nk = (uint64_t)t.ntiles * t.cells_per_tile;
+  if (nk >= 0xFFFFFFF0ull) return fail(SFPIC_E_INVAL, "too many cells");
+  t.nkeys = (uint32_t)nk;
+  int max_lds = 64 * 1024;
+  (void)hipDeviceGetAttribute(&max_lds,
+                              hipDeviceAttributeMaxSharedMemoryPerBlock,
+                              s->rt.device);
+  const size_t lds = s->precision == SFPIC_FP64
+                         ? push_lds_bytes<double>(t, g.dims)
+                         : push_lds_bytes<float>(t, g.dims);
+  if (lds > (size_t)max_lds) return fail(SFPIC_E_INVAL, "tile too large for LDS");
+  if (t.nkeys > s->tg.nkeys) {
+    // the old arrays may still be in use by queued work
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    const size_t nk1 = (size_t)t.nkeys + 1;
+    uint32_t *counts = (uint32_t *)s->dalloc(nk1 * 4);
+    uint32_t *sums = (uint32_t *)s->dalloc(((nk1 + 1023) / 1024 + 1) * 4);
+    if (!counts || !sums) return fail(SFPIC_E_NOMEM, "sort allocation failed");
+    std::vector<uint32_t *> starts;
+    for (size_t k = 0; k < s->sp.size(); ++k) {
+      uint32_t *st = (uint32_t *)s->dalloc(nk1 * 4);
+      if (!st) return fail(SFPIC_E_NOMEM, "sort allocation failed");
+      starts.push_back(st);
+    }
+    s->dfree(s->ss.counts);
+    s->dfree(s->ss.block_sums);
+    s->ss.counts = counts;
+    s->ss.block_sums = sums;
+    for (size_t k = 0; k < s->sp.size(); ++k) {
+      s->dfree(s->sp[k].start);
+      s->sp[k].start = starts[k];
+    }
+  }
+  s->tg = t;
+  return sort_all(s);
+}
+
+size_t sim_device_bytes(const sfpic_sim *s) {
+  size_t b = 0;
+  for (auto &a : s->allocs) b += a.second;
+  return b;
+}
+
+int sim_footprint(const sfpic_grid *grid, const sfpic_species *species,
+                  int nspecies, sfpic_precision precision,
+                  const sfpic_runtime *rt, size_t *bytes) {
+  SF_TRY(check_grid(grid));
+  if (!bytes) return fail(SFPIC_E_INVAL, "bytes is NULL");
+  if (nspecies < 0 || nspecies > 8 || (nspecies > 0 && !species))
+    return fail(SFPIC_E_INVAL, "nspecies must be in [0, 8]");
+  auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  const int dims = grid->dims;
+  const size_t es = precision == SFPIC_FP64 ? 8 : 4;
+  const size_t NX = (size_t)grid->nx + 2 * kGuard;
+  const size_t NY = dims == 2 ? (size_t)grid->ny + 2 * kGuard : 1;
+  const size_t pitch = (NX + 63) & ~(size_t)63;
+  size_t b = 12 * al(NY * pitch * es) + 2 * al(NY * pitch * 8) + al(64 * 8);
+  int tx = rt && rt->tile_x > 0 ? rt->tile_x : (dims == 2 ? 16 : 256);
+  int ty = dims == 2 ? (rt && rt->tile_y > 0 ? rt->tile_y : 8) : 1;
+  const size_t ntx = ((size_t)grid->nx + tx - 1) / tx;
+  const size_t nty = dims == 2 ? ((size_t)grid->ny + ty - 1) / ty : 1;
+  const size_t nk1 = ntx * nty * (size_t)tx * ty + 1;
+  b += al(nk1 * 4) + al(((nk1 + 1023) / 1024 + 1) * 4) + al(4);
+  size_t nmax = 1, staging = 0;
+  for (int k = 0; k < nspecies; ++k) {
+    const sfpic_species &in = species[k];
+    int64_t n = in.n_explicit;
+    if (n <= 0) {
+      const int64_t y0 = dims == 2 ? in.region[2] : 0;
+      const int64_t y1 = dims == 2 ? in.region[3] : 1;
+      n = (in.region[1] - in.region[0]) * (y1 - y0) * (int64_t)in.ppc;
+      if (n < 0) return fail(SFPIC_E_INVAL, "species region is empty");
+    } else if ((size_t)n * 40 > staging) {
+      staging = (size_t)n * 40;
+    }
+    const size_t cnt = n > 0 ? (size_t)n : 1;
+    nmax = cnt > nmax ? cnt : nmax;
+    const size_t set = precision == SFPIC_FP64 ? 5 * al(cnt * 8) + al(cnt * 4)
+                                               : 7 * al(cnt * 4);
+    b += al(4) + 2 * set + al(nk1 * 4);
+  }
+  b += 3 * al(nmax * 4) + al(staging);
+  *bytes = b;
+  return SFPIC_OK;
+}
+
+}  // namespace sfpic
+
+namespace {
 
 int guarded(sfpic_sim *s) {
   if (!s) return fail(SFPIC_E_INVAL, "sim is NULL");
@@ -961,6 +931,13 @@ int sfpic_profile_read(sfpic_sim *s, sfpic_kernel_stats *out) {
     }
     out->total_ms[c] = tot;
   }
+  return SFPIC_OK;
+}
+
+int sfpic_device_bytes(sfpic_sim *s, size_t *bytes) {
+  SF_TRY(guarded(s));
+  if (!bytes) return fail(SFPIC_E_INVAL, "bytes is NULL");
+  *bytes = sim_device_bytes(s);
   return SFPIC_OK;
 }
 

@@ -91,6 +91,56 @@ struct PushParams {
 };
 
 // ---------------------------------------------------------------------------
+// Batched execution: many independent simulations of one precision and
+// dimensionality advanced by the same launches.  Every launch reads a table
+// of per-member descriptors; a workgroup finds its member from a prefix table
+// of block (or tile) offsets.  The step counter, the steps still to run and
+// the current particle buffer live on the device, so a captured graph of a
+// few steps can be replayed without host updates.
+// ---------------------------------------------------------------------------
+struct MemberState {
+  int64_t step;        // n of the next step (t^n = n dt)
+  int64_t steps_left;  // 0: finished; every kernel skips the member
+};
+
+template <typename R>
+struct FieldJob {
+  Fields<R> f;
+  R dt, cx, cy, kx, ky;  // dt, dt/dx, dt/dy, Mur coefficients
+  int member;
+};
+
+template <typename R>
+struct PushJob {
+  Fields<R> f;
+  Particles<R> pa[2];  // pa[cur] is the current set, the other the sort target
+  uint32_t *start, *n_valid, *strag;
+  SortScratch ss;
+  TileGeom tg;
+  PushParams pp;       // pp.time is formed on the device from the step
+  IncParams inc;
+  uint32_t n_slots;
+  int member;
+  int cur;             // flipped on the device by every sort
+};
+
+// Device view of one batch group.  Offset tables have n + 1 entries.
+template <typename R>
+struct BatchView {
+  const FieldJob<R> *fjobs;
+  PushJob<R> *pjobs;
+  MemberState *ms;
+  int nmembers, nf, np;
+  const uint32_t *far_off, *amp_off;  // field jobs: Faraday / Ampere blocks
+  const uint32_t *tile_off;           // push jobs: tiles
+  const uint32_t *slot_off;           // push jobs: blocks of 256 slots
+  const uint32_t *key_off;            // push jobs: blocks of 256 keys
+  const uint32_t *scan_off;           // push jobs: blocks of 1024 keys
+  uint32_t *counters;                 // [0] tile queue, [1 + j] stragglers
+  uint32_t n_far, n_amp, n_tiles, n_slot_blocks, n_key_blocks, n_scan_blocks;
+};
+
+// ---------------------------------------------------------------------------
 // Minimal complex arithmetic for device code.
 // ---------------------------------------------------------------------------
 template <typename T>
@@ -460,5 +510,26 @@ hipError_t launch_histogram(const Particles<R> &p, int64_t n,
                             double wdv, int n_e, double emax, int n_t,
                             double ek_min, double *hist, double *mom,
                             hipStream_t st);
+
+// Batched launches (one per phase for the whole group).  `grid` of the push
+// is the number of persistent workgroups pulling tiles from the queue.
+template <typename R>
+hipError_t launch_batch_faraday(const BatchView<R> &v, int dims,
+                                hipStream_t st);
+template <typename R>
+hipError_t launch_batch_ampere(const BatchView<R> &v, int dims,
+                               hipStream_t st);
+template <typename R>
+hipError_t launch_batch_push(const BatchView<R> &v, int dims, size_t lds,
+                             int grid, hipStream_t st);
+template <typename R>
+hipError_t launch_batch_stragglers(const BatchView<R> &v, int dims,
+                                   hipStream_t st);
+template <typename R>
+hipError_t launch_batch_sort(const BatchView<R> &v, int dims, hipStream_t st);
+hipError_t launch_batch_advance(MemberState *ms, int n, hipStream_t st);
+// Resident workgroups of the batched push per CU (0 on error).
+int batch_push_blocks_per_cu(bool fp64, int dims, size_t lds);
+hipError_t launch_fill_u32(uint32_t *a, uint32_t v, size_t n, hipStream_t st);
 
 }  // namespace sfpic

@@ -6,6 +6,22 @@
 
 namespace sfpic {
 
+// Segment of a prefix table: the largest j in [0, n) with off[j] <= x, for
+// 0 <= x < off[n].  Empty segments (off[j] == off[j + 1]) are never returned.
+// Called with wave-uniform arguments, so the loads are scalar.
+__device__ __forceinline__ int find_segment(const uint32_t *off, int n,
+                                            uint32_t x) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (off[mid] <= x)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
 // ---------------------------------------------------------------------------
 // Particles: order-2 shapes
 // ---------------------------------------------------------------------------

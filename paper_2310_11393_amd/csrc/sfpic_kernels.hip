@@ -16,10 +16,8 @@ namespace sfpic {
 
 // Faraday: B^{n+1/2} = B^{n-1/2} - dt curl E^n, Bbar^n = average, J = 0.
 template <typename R, int DIMS>
-__global__ void __launch_bounds__(256)
-faraday_kernel(Fields<R> f, R cx_, R cy_) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int j = blockIdx.y * blockDim.y + threadIdx.y;
+__device__ __forceinline__ void faraday_at(const Fields<R> &f, int i, int j,
+                                           R cx_, R cy_) {
   const int NX = f.nx_alloc, NY = f.ny_alloc, P = f.pitch;
   if (i >= NX || j >= NY) return;
   const size_t k = (size_t)j * P + i;
@@ -48,6 +46,13 @@ faraday_kernel(Fields<R> f, R cx_, R cy_) {
   f.jz[k] = R(0);
 }
 
+template <typename R, int DIMS>
+__global__ void __launch_bounds__(256)
+faraday_kernel(Fields<R> f, R cx_, R cy_) {
+  faraday_at<R, DIMS>(f, blockIdx.x * blockDim.x + threadIdx.x,
+                      blockIdx.y * blockDim.y + threadIdx.y, cx_, cy_);
+}
+
 // First-order Mur: face node b, inward neighbour n.
 template <typename R>
 __device__ __forceinline__ R mur(R n_old, R n_new, R b_old, R k) {
@@ -58,10 +63,8 @@ __device__ __forceinline__ R mur(R n_old, R n_new, R b_old, R k) {
 // j in [1, NY-2], and also the outer-ring nodes next to it, so the Mur update
 // of a face node reads old and new values of its neighbour without a race.
 template <typename R, int DIMS>
-__global__ void __launch_bounds__(256)
-ampere_kernel(Fields<R> f, R dt, R cx_, R cy_, R kx, R ky) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x + 1;
-  const int j = blockIdx.y * blockDim.y + threadIdx.y + (DIMS == 2 ? 1 : 0);
+__device__ __forceinline__ void ampere_at(const Fields<R> &f, int i, int j,
+                                          R dt, R cx_, R cy_, R kx, R ky) {
   const int NX = f.nx_alloc, NY = f.ny_alloc, P = f.pitch;
   if (i > NX - 2) return;
   if (DIMS == 2 && j > NY - 2) return;
@@ -138,6 +141,14 @@ ampere_kernel(Fields<R> f, R dt, R cx_, R cy_, R kx, R ky) {
   }
 }
 
+template <typename R, int DIMS>
+__global__ void __launch_bounds__(256)
+ampere_kernel(Fields<R> f, R dt, R cx_, R cy_, R kx, R ky) {
+  ampere_at<R, DIMS>(f, blockIdx.x * blockDim.x + threadIdx.x + 1,
+                     blockIdx.y * blockDim.y + threadIdx.y + (DIMS == 2 ? 1 : 0),
+                     dt, cx_, cy_, kx, ky);
+}
+
 template <typename R>
 hipError_t launch_faraday(const Fields<R> &f, int dims, double dt, double dx,
                           double dy, hipStream_t st) {
@@ -166,6 +177,77 @@ hipError_t launch_ampere(const Fields<R> &f, int dims, double dt, double dx,
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Batched Yee sweeps: one launch for all members of a group.  Workgroups of
+// 256 threads cover 64 x 4 nodes (2D) or 256 nodes (1D); block b belongs to
+// the member whose segment of the block-offset table holds b.
+// ---------------------------------------------------------------------------
+template <typename R, int DIMS, bool FARADAY>
+__global__ void __launch_bounds__(256)
+batch_yee_kernel(BatchView<R> v) {
+  const uint32_t *off = FARADAY ? v.far_off : v.amp_off;
+  const uint32_t b = blockIdx.x;
+  const int jb = find_segment(off, v.nf, b);
+  const FieldJob<R> &J = v.fjobs[jb];
+  if (v.ms[J.member].steps_left <= 0) return;
+  const uint32_t lb = b - off[jb];
+  const int t = threadIdx.x;
+  // interior sweep of Ampere starts at node 1 in each direction
+  const int o = FARADAY ? 0 : 1;
+  int i, j;
+  if (DIMS == 2) {
+    const int nbx = (J.f.nx_alloc - 2 * o + 63) / 64;
+    i = (int)(lb % nbx) * 64 + (t & 63) + o;
+    j = (int)(lb / nbx) * 4 + (t >> 6) + o;
+  } else {
+    i = (int)lb * 256 + t + o;
+    j = 0;
+  }
+  if (FARADAY) {
+    faraday_at<R, DIMS>(J.f, i, j, J.cx, J.cy);
+  } else {
+    if (i > J.f.nx_alloc - 2 || (DIMS == 2 && j > J.f.ny_alloc - 2)) return;
+    ampere_at<R, DIMS>(J.f, i, j, J.dt, J.cx, J.cy, J.kx, J.ky);
+  }
+}
+
+template <typename R>
+hipError_t launch_batch_faraday(const BatchView<R> &v, int dims,
+                                hipStream_t st) {
+  if (v.n_far == 0) return hipSuccess;
+  if (dims == 1)
+    batch_yee_kernel<R, 1, true><<<v.n_far, 256, 0, st>>>(v);
+  else
+    batch_yee_kernel<R, 2, true><<<v.n_far, 256, 0, st>>>(v);
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_batch_ampere(const BatchView<R> &v, int dims,
+                               hipStream_t st) {
+  if (v.n_amp == 0) return hipSuccess;
+  if (dims == 1)
+    batch_yee_kernel<R, 1, false><<<v.n_amp, 256, 0, st>>>(v);
+  else
+    batch_yee_kernel<R, 2, false><<<v.n_amp, 256, 0, st>>>(v);
+  return hipGetLastError();
+}
+
+// End of a batched step: advance the step counter of every running member.
+__global__ void batch_advance_kernel(MemberState *ms, int n) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= n) return;
+  if (ms[m].steps_left > 0) {
+    ms[m].steps_left -= 1;
+    ms[m].step += 1;
+  }
+}
+
+hipError_t launch_batch_advance(MemberState *ms, int n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  batch_advance_kernel<<<(n + 255) / 256, 256, 0, st>>>(ms, n);
+  return hipGetLastError();
+}
 
 // ---------------------------------------------------------------------------
 // Particle placement (Philox4x32-10 counter-based draws, see sfpic_device.h)
@@ -510,7 +592,11 @@ hipError_t launch_export_particles(const Particles<R> &p, int64_t n, int dims,
       int, double, int, double, double *, double *, hipStream_t);             \
   template hipError_t launch_export_particles<R>(                            \
       const Particles<R> &, int64_t, int, double, double, double *,           \
-      uint32_t *, hipStream_t);
+      uint32_t *, hipStream_t);                                               \
+  template hipError_t launch_batch_faraday<R>(const BatchView<R> &, int,      \
+                                              hipStream_t);                   \
+  template hipError_t launch_batch_ampere<R>(const BatchView<R> &, int,       \
+                                             hipStream_t);
 
 SFPIC_INSTANTIATE_K(double)
 SFPIC_INSTANTIATE_K(float)

@@ -377,15 +377,18 @@ __device__ __forceinline__ bool push_particle(int &ix, int &iy, R &fx, R &fy,
 // ---------------------------------------------------------------------------
 // Tiled push
 // ---------------------------------------------------------------------------
+// One workgroup pushes every particle of one tile; smem holds the windows
+// and the particle chunk (push_lds_bytes).
 template <typename R, int DIMS>
-__global__ void __launch_bounds__(256, 2)
-push_tiled(Fields<R> f, Particles<R> p, const uint32_t *__restrict__ start,
-           TileGeom tg, PushParams pp, IncParams inc, uint32_t *strag,
-           uint32_t *n_strag) {
+__device__ __forceinline__ void push_tile(const Fields<R> &f,
+                                          const Particles<R> &p,
+                                          const uint32_t *__restrict__ start,
+                                          const TileGeom &tg,
+                                          const PushParams &pp,
+                                          const IncParams &inc,
+                                          uint32_t *strag, uint32_t *n_strag,
+                                          int tile, double *smem) {
   using W = typename PT<R>::Word;
-  extern __shared__ double smem[];
-  const int tile = xcd_tile(blockIdx.x, gridDim.x);
-  if (tile >= tg.ntiles) return;
   const uint32_t cpt = tg.cells_per_tile;
   const uint32_t pbeg = start[(size_t)tile * cpt];
   const uint32_t pend = start[(size_t)(tile + 1) * cpt];
@@ -483,13 +486,25 @@ push_tiled(Fields<R> f, Particles<R> p, const uint32_t *__restrict__ start,
   }
 }
 
-// Push of the particles listed by the tiled kernel (drifted more than one
-// cell out of their tile): global gather and global atomics.
 template <typename R, int DIMS>
-__global__ void __launch_bounds__(256)
-push_stragglers(Fields<R> f, Particles<R> p, PushParams pp, IncParams inc,
-                const uint32_t *strag, const uint32_t *n_strag) {
-  const uint32_t n = *n_strag;
+__global__ void __launch_bounds__(256, 2)
+push_tiled(Fields<R> f, Particles<R> p, const uint32_t *__restrict__ start,
+           TileGeom tg, PushParams pp, IncParams inc, uint32_t *strag,
+           uint32_t *n_strag) {
+  extern __shared__ double smem[];
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  if (tile >= tg.ntiles) return;
+  push_tile<R, DIMS>(f, p, start, tg, pp, inc, strag, n_strag, tile, smem);
+}
+
+// Push of one particle listed by the tiled kernel (drifted more than one
+// cell out of its tile): global gather and global atomics.
+template <typename R, int DIMS>
+__device__ __forceinline__ void push_straggler(const Fields<R> &f,
+                                               const Particles<R> &p,
+                                               const PushParams &pp,
+                                               const IncParams &inc,
+                                               uint32_t ip) {
   const int P = f.pitch;
   auto gather = [&](int ix, int iy, int ipx, int ipy, const R wxp[3],
                     const R wxd[3], const R wyp[3], const R wyd[3], R E[3],
@@ -505,23 +520,29 @@ push_stragglers(Fields<R> f, Particles<R> p, PushParams pp, IncParams inc,
     B[1] = gather_plane<R, DIMS>(f.my, P, bxd, byp, wxd, wyp);
     B[2] = gather_plane<R, DIMS>(f.mz, P, bxd, byd, wxd, wyd);
   };
+  int ix, iy;
+  R fx, fy, u[3];
+  if (!PT<R>::load_global(p, ip, DIMS, ix, iy, fx, fy, u)) return;
+  const int ipx0 = ix + (fx >= R(0.5));
+  const int ipy0 = (DIMS == 2) ? iy + (fy >= R(0.5)) : 0;
+  const int bx = ipx0 - 2 + kGuard;
+  const int by = (DIMS == 2) ? ipy0 - 2 + kGuard : 0;
+  const bool alive = push_particle<R, DIMS>(
+      ix, iy, fx, fy, u, pp, inc, gather, [&](int c, int a, int b, R v) {
+        R *jp = c == 0 ? f.jx : (c == 1 ? f.jy : f.jz);
+        unsafeAtomicAdd(&jp[(size_t)(by + b) * P + bx + a], v);
+      });
+  PT<R>::store_global(p, ip, DIMS, alive, ix, iy, fx, fy, u);
+}
+
+template <typename R, int DIMS>
+__global__ void __launch_bounds__(256)
+push_stragglers(Fields<R> f, Particles<R> p, PushParams pp, IncParams inc,
+                const uint32_t *strag, const uint32_t *n_strag) {
+  const uint32_t n = *n_strag;
   for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < n;
-       k += gridDim.x * blockDim.x) {
-    const uint32_t ip = strag[k];
-    int ix, iy;
-    R fx, fy, u[3];
-    if (!PT<R>::load_global(p, ip, DIMS, ix, iy, fx, fy, u)) continue;
-    const int ipx0 = ix + (fx >= R(0.5));
-    const int ipy0 = (DIMS == 2) ? iy + (fy >= R(0.5)) : 0;
-    const int bx = ipx0 - 2 + kGuard;
-    const int by = (DIMS == 2) ? ipy0 - 2 + kGuard : 0;
-    const bool alive = push_particle<R, DIMS>(
-        ix, iy, fx, fy, u, pp, inc, gather, [&](int c, int a, int b, R v) {
-          R *jp = c == 0 ? f.jx : (c == 1 ? f.jy : f.jz);
-          unsafeAtomicAdd(&jp[(size_t)(by + b) * P + bx + a], v);
-        });
-    PT<R>::store_global(p, ip, DIMS, alive, ix, iy, fx, fy, u);
-  }
+       k += gridDim.x * blockDim.x)
+    push_straggler<R, DIMS>(f, p, pp, inc, strag[k]);
 }
 
 template <typename R>
@@ -597,13 +618,15 @@ __device__ __forceinline__ uint32_t wave_aggregated_rank(bool active,
 }
 
 template <typename R>
-__global__ void sort_count(Particles<R> p, uint32_t n_slots,
-                           const uint32_t *n_valid, TileGeom tg, int nx,
-                           int ny, int dims, uint32_t *counts, uint32_t *key,
-                           uint32_t *rank) {
-  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void sort_count_at(const Particles<R> &p,
+                                              uint32_t i, uint32_t n_slots,
+                                              uint32_t n_valid,
+                                              const TileGeom &tg, int nx,
+                                              int ny, int dims,
+                                              uint32_t *counts, uint32_t *key,
+                                              uint32_t *rank) {
   uint32_t k = tg.nkeys;
-  if (i < n_slots && i < *n_valid) {
+  if (i < n_slots && i < n_valid) {
     int ix, iy;
     R fx, fy, u[3];
     if (PT<R>::load_global(p, i, dims, ix, iy, fx, fy, u)) {
@@ -618,6 +641,15 @@ __global__ void sort_count(Particles<R> p, uint32_t n_slots,
     key[i] = k;
     rank[i] = r;
   }
+}
+
+template <typename R>
+__global__ void sort_count(Particles<R> p, uint32_t n_slots,
+                           const uint32_t *n_valid, TileGeom tg, int nx,
+                           int ny, int dims, uint32_t *counts, uint32_t *key,
+                           uint32_t *rank) {
+  sort_count_at<R>(p, blockIdx.x * blockDim.x + threadIdx.x, n_slots,
+                   *n_valid, tg, nx, ny, dims, counts, key, rank);
 }
 
 __device__ __forceinline__ void move_particle(const Particles<double> &src,
@@ -645,24 +677,38 @@ __device__ __forceinline__ void move_particle(const Particles<float> &src,
 }
 
 template <typename R>
-__global__ void sort_scatter(Particles<R> src, Particles<R> dst,
-                             uint32_t n_slots, int dims,
-                             const uint32_t *__restrict__ key,
-                             const uint32_t *__restrict__ rank,
-                             const uint32_t *__restrict__ start,
-                             uint32_t nkeys) {
-  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void scatter_at(const Particles<R> &src,
+                                           const Particles<R> &dst,
+                                           uint32_t i, uint32_t n_slots,
+                                           int dims,
+                                           const uint32_t *__restrict__ key,
+                                           const uint32_t *__restrict__ rank,
+                                           const uint32_t *__restrict__ start,
+                                           uint32_t nkeys) {
   if (i >= n_slots) return;
   const uint32_t k = key[i];
   if (k >= nkeys) return;
   move_particle(src, dst, i, start[k] + rank[i], dims);
 }
 
-// Exclusive scan, 1024 elements per block (256 threads x 4).
-__global__ void __launch_bounds__(256)
-scan_blocks(const uint32_t *in, uint32_t *out, uint32_t *sums, uint32_t n) {
-  __shared__ uint32_t sh[256];
-  const uint32_t base = blockIdx.x * 1024 + threadIdx.x * 4;
+template <typename R>
+__global__ void sort_scatter(Particles<R> src, Particles<R> dst,
+                             uint32_t n_slots, int dims,
+                             const uint32_t *__restrict__ key,
+                             const uint32_t *__restrict__ rank,
+                             const uint32_t *__restrict__ start,
+                             uint32_t nkeys) {
+  scatter_at<R>(src, dst, blockIdx.x * blockDim.x + threadIdx.x, n_slots,
+                dims, key, rank, start, nkeys);
+}
+
+// Exclusive scan of block lb of a 1024-element segment (256 threads x 4);
+// sh is a 256-word LDS array.
+__device__ __forceinline__ void scan_block_at(const uint32_t *in,
+                                              uint32_t *out, uint32_t *sums,
+                                              uint32_t n, uint32_t lb,
+                                              uint32_t *sh) {
+  const uint32_t base = lb * 1024 + threadIdx.x * 4;
   uint32_t v[4], tot = 0;
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
@@ -683,12 +729,19 @@ scan_blocks(const uint32_t *in, uint32_t *out, uint32_t *sums, uint32_t n) {
     if (base + k < n) out[base + k] = run;
     run += v[k];
   }
-  if (threadIdx.x == 255) sums[blockIdx.x] = sh[255];
+  if (threadIdx.x == 255) sums[lb] = sh[255];
 }
 
-// In-place exclusive scan of the block sums by one workgroup.
-__global__ void __launch_bounds__(1024) scan_sums(uint32_t *sums, uint32_t nb) {
-  __shared__ uint32_t sh[1024];
+__global__ void __launch_bounds__(256)
+scan_blocks(const uint32_t *in, uint32_t *out, uint32_t *sums, uint32_t n) {
+  __shared__ uint32_t sh[256];
+  scan_block_at(in, out, sums, n, blockIdx.x, sh);
+}
+
+// In-place exclusive scan of nb block sums by one workgroup of 1024 threads;
+// sh is a 1024-word LDS array.
+__device__ __forceinline__ void scan_sums_at(uint32_t *sums, uint32_t nb,
+                                             uint32_t *sh) {
   uint32_t carry = 0;
   for (uint32_t b0 = 0; b0 < nb; b0 += 1024) {
     const uint32_t i = b0 + threadIdx.x;
@@ -709,12 +762,23 @@ __global__ void __launch_bounds__(1024) scan_sums(uint32_t *sums, uint32_t nb) {
   }
 }
 
-__global__ void scan_add(uint32_t *out, const uint32_t *sums, uint32_t n) {
-  const uint32_t i = blockIdx.x * 1024 + threadIdx.x;
-  const uint32_t add = sums[blockIdx.x];
+__global__ void __launch_bounds__(1024) scan_sums(uint32_t *sums, uint32_t nb) {
+  __shared__ uint32_t sh[1024];
+  scan_sums_at(sums, nb, sh);
+}
+
+__device__ __forceinline__ void scan_add_at(uint32_t *out,
+                                            const uint32_t *sums, uint32_t n,
+                                            uint32_t lb) {
+  const uint32_t i = lb * 1024 + threadIdx.x;
+  const uint32_t add = sums[lb];
 #pragma unroll
   for (int k = 0; k < 4; ++k)
     if (i + 256 * k < n) out[i + 256 * k] += add;
+}
+
+__global__ void scan_add(uint32_t *out, const uint32_t *sums, uint32_t n) {
+  scan_add_at(out, sums, n, blockIdx.x);
 }
 
 __global__ void set_valid(uint32_t *n_valid, const uint32_t *start,
@@ -743,6 +807,198 @@ hipError_t launch_sort(const Particles<R> &src, const Particles<R> &dst,
   return hipGetLastError();
 }
 
+hipError_t launch_fill_u32(uint32_t *a, uint32_t v, size_t n, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  fill_u32<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(a, v, n);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Batched particle phases.  The push is persistent: `grid` workgroups take
+// tiles of all members from one atomic queue (counters[0], cleared by the
+// first launch of the step) until the queue is exhausted, so large and small
+// members share the chip without a tail per member.  A member whose
+// steps_left is 0 is skipped by every phase.
+// ---------------------------------------------------------------------------
+template <typename R>
+__device__ __forceinline__ PushParams member_params(const BatchView<R> &v,
+                                                    const PushJob<R> &J) {
+  PushParams pp = J.pp;
+  pp.time = (double)v.ms[J.member].step * pp.dt;
+  return pp;
+}
+
+template <typename R, int DIMS>
+__global__ void __launch_bounds__(256, 2) batch_push_kernel(BatchView<R> v) {
+  extern __shared__ double smem[];
+  __shared__ uint32_t s_item;
+  for (;;) {
+    if (threadIdx.x == 0) s_item = atomicAdd(&v.counters[0], 1u);
+    __syncthreads();
+    const uint32_t item = __builtin_amdgcn_readfirstlane(s_item);
+    __syncthreads();  // s_item is rewritten only after every thread read it
+    if (item >= v.n_tiles) break;
+    const int jb = find_segment(v.tile_off, v.np, item);
+    const PushJob<R> &J = v.pjobs[jb];
+    if (v.ms[J.member].steps_left <= 0) continue;
+    const PushParams pp = member_params(v, J);
+    push_tile<R, DIMS>(J.f, J.pa[J.cur], J.start, J.tg, pp, J.inc, J.strag,
+                       &v.counters[1 + jb], (int)(item - v.tile_off[jb]),
+                       smem);
+  }
+}
+
+// Stragglers: blockIdx.y is the push job, blockIdx.x strides its list.
+template <typename R, int DIMS>
+__global__ void __launch_bounds__(256) batch_stragglers_kernel(BatchView<R> v) {
+  const int jb = blockIdx.y;
+  const PushJob<R> &J = v.pjobs[jb];
+  if (v.ms[J.member].steps_left <= 0) return;
+  const uint32_t n = v.counters[1 + jb];
+  if (n == 0) return;
+  const PushParams pp = member_params(v, J);
+  const Particles<R> p = J.pa[J.cur];
+  for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < n;
+       k += gridDim.x * blockDim.x)
+    push_straggler<R, DIMS>(J.f, p, pp, J.inc, J.strag[k]);
+}
+
+template <typename R>
+hipError_t launch_batch_push(const BatchView<R> &v, int dims, size_t lds,
+                             int grid, hipStream_t st) {
+  if (v.np == 0) return hipSuccess;
+  if (dims == 1)
+    batch_push_kernel<R, 1><<<grid, 256, lds, st>>>(v);
+  else
+    batch_push_kernel<R, 2><<<grid, 256, lds, st>>>(v);
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_batch_stragglers(const BatchView<R> &v, int dims,
+                                   hipStream_t st) {
+  if (v.np == 0) return hipSuccess;
+  const dim3 g(16, (unsigned)v.np);
+  if (dims == 1)
+    batch_stragglers_kernel<R, 1><<<g, 256, 0, st>>>(v);
+  else
+    batch_stragglers_kernel<R, 2><<<g, 256, 0, st>>>(v);
+  return hipGetLastError();
+}
+
+int batch_push_blocks_per_cu(bool fp64, int dims, size_t lds) {
+  int nb = 0;
+  hipError_t e;
+  if (fp64)
+    e = dims == 1 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                        &nb, batch_push_kernel<double, 1>, 256, lds)
+                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                        &nb, batch_push_kernel<double, 2>, 256, lds);
+  else
+    e = dims == 1 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                        &nb, batch_push_kernel<float, 1>, 256, lds)
+                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                        &nb, batch_push_kernel<float, 2>, 256, lds);
+  return e == hipSuccess ? nb : 0;
+}
+
+// Batched counting sort: the same five passes as launch_sort, each one
+// launch over all push jobs of the group.
+template <typename R>
+__device__ __forceinline__ const PushJob<R> *sort_job(const BatchView<R> &v,
+                                                      const uint32_t *off,
+                                                      uint32_t &lb) {
+  const uint32_t b = blockIdx.x;
+  const int jb = find_segment(off, v.np, b);
+  const PushJob<R> *J = &v.pjobs[jb];
+  if (v.ms[J->member].steps_left <= 0) return nullptr;
+  lb = b - off[jb];
+  return J;
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256) batch_sort_clear(BatchView<R> v) {
+  uint32_t lb;
+  const PushJob<R> *J = sort_job(v, v.key_off, lb);
+  if (!J) return;
+  const uint32_t i = lb * 256 + threadIdx.x;
+  if (i <= J->tg.nkeys) J->ss.counts[i] = 0u;
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256) batch_sort_count(BatchView<R> v,
+                                                        int dims) {
+  uint32_t lb;
+  const PushJob<R> *J = sort_job(v, v.slot_off, lb);
+  if (!J) return;
+  sort_count_at<R>(J->pa[J->cur], lb * 256 + threadIdx.x, J->n_slots,
+                   *J->n_valid, J->tg, J->pp.nx, J->pp.ny, dims, J->ss.counts,
+                   J->ss.key, J->ss.rank);
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256) batch_scan_blocks(BatchView<R> v) {
+  __shared__ uint32_t sh[256];
+  uint32_t lb;
+  const PushJob<R> *J = sort_job(v, v.scan_off, lb);
+  if (!J) return;
+  scan_block_at(J->ss.counts, J->start, J->ss.block_sums, J->tg.nkeys + 1, lb,
+                sh);
+}
+
+template <typename R>
+__global__ void __launch_bounds__(1024) batch_scan_sums(BatchView<R> v) {
+  __shared__ uint32_t sh[1024];
+  const PushJob<R> &J = v.pjobs[blockIdx.x];
+  if (v.ms[J.member].steps_left <= 0) return;
+  scan_sums_at(J.ss.block_sums, (J.tg.nkeys + 1 + 1023) / 1024, sh);
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256) batch_scan_add(BatchView<R> v) {
+  uint32_t lb;
+  const PushJob<R> *J = sort_job(v, v.scan_off, lb);
+  if (!J) return;
+  scan_add_at(J->start, J->ss.block_sums, J->tg.nkeys + 1, lb);
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256) batch_sort_scatter(BatchView<R> v,
+                                                          int dims) {
+  uint32_t lb;
+  const PushJob<R> *J = sort_job(v, v.slot_off, lb);
+  if (!J) return;
+  scatter_at<R>(J->pa[J->cur], J->pa[J->cur ^ 1], lb * 256 + threadIdx.x,
+                J->n_slots, dims, J->ss.key, J->ss.rank, J->start,
+                J->tg.nkeys);
+}
+
+// Slots in use after the sort, and the sorted set becomes current.
+template <typename R>
+__global__ void batch_sort_finish(BatchView<R> v) {
+  const int jb = blockIdx.x * blockDim.x + threadIdx.x;
+  if (jb >= v.np) return;
+  PushJob<R> &J = v.pjobs[jb];
+  if (v.ms[J.member].steps_left <= 0) return;
+  *J.n_valid = J.start[J.tg.nkeys];
+  J.cur ^= 1;
+}
+
+template <typename R>
+hipError_t launch_batch_sort(const BatchView<R> &v, int dims, hipStream_t st) {
+  if (v.np == 0) return hipSuccess;
+  if (v.n_key_blocks) batch_sort_clear<R><<<v.n_key_blocks, 256, 0, st>>>(v);
+  if (v.n_slot_blocks)
+    batch_sort_count<R><<<v.n_slot_blocks, 256, 0, st>>>(v, dims);
+  if (v.n_scan_blocks) batch_scan_blocks<R><<<v.n_scan_blocks, 256, 0, st>>>(v);
+  batch_scan_sums<R><<<v.np, 1024, 0, st>>>(v);
+  if (v.n_scan_blocks) batch_scan_add<R><<<v.n_scan_blocks, 256, 0, st>>>(v);
+  if (v.n_slot_blocks)
+    batch_sort_scatter<R><<<v.n_slot_blocks, 256, 0, st>>>(v, dims);
+  batch_sort_finish<R><<<(v.np + 255) / 256, 256, 0, st>>>(v);
+  return hipGetLastError();
+}
+
 #define SFPIC_INSTANTIATE(R)                                                 \
   template size_t push_lds_bytes<R>(const TileGeom &, int);                  \
   template hipError_t launch_push_tiled<R>(                                  \
@@ -755,7 +1011,13 @@ hipError_t launch_sort(const Particles<R> &src, const Particles<R> &dst,
   template hipError_t launch_sort<R>(                                        \
       const Particles<R> &, const Particles<R> &, uint32_t, uint32_t *,      \
       uint32_t *, const TileGeom &, int, int, int, const SortScratch &,      \
-      hipStream_t);
+      hipStream_t);                                                          \
+  template hipError_t launch_batch_push<R>(const BatchView<R> &, int, size_t,\
+                                           int, hipStream_t);                \
+  template hipError_t launch_batch_stragglers<R>(const BatchView<R> &, int,  \
+                                                 hipStream_t);               \
+  template hipError_t launch_batch_sort<R>(const BatchView<R> &, int,        \
+                                           hipStream_t);
 
 SFPIC_INSTANTIATE(double)
 SFPIC_INSTANTIATE(float)

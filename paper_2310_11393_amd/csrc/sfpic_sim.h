@@ -1,0 +1,189 @@
+// Host-side state of one simulation, shared by the single-simulation calls
+// and the batch / server runtime.  Internal: not part of the public ABI.
+#pragma once
+
+#include "../../include/sfpic.h"
+#include "sfpic_common.h"
+
+#include <string>
+#include <utility>
+#include <vector>
+
+namespace sfpic {
+
+// Record msg as the calling thread's last error and return code.
+int fail(int code, const std::string &msg);
+
+#define HIP_TRY(expr)                                                   \
+  do {                                                                  \
+    hipError_t e_ = (expr);                                             \
+    if (e_ != hipSuccess)                                               \
+      return ::sfpic::fail(SFPIC_E_DEVICE, std::string(#expr) + ": " +  \
+                                               hipGetErrorString(e_));  \
+  } while (0)
+
+#define SF_TRY(expr)               \
+  do {                             \
+    int r_ = (expr);               \
+    if (r_ != SFPIC_OK) return r_; \
+  } while (0)
+
+struct SpeciesState {
+  double q = -1.0, m = 1.0, weight = 0.0;
+  int64_t n = 0;               // slots (capacity)
+  uint32_t *n_valid = nullptr; // device: slots in use (live or removed)
+  uint32_t *start = nullptr;   // device: cell start offsets (nkeys + 1)
+  Particles<double> p64{}, p64_alt{};
+  Particles<float> p32{}, p32_alt{};
+  // Sort scratch and straggler list of a species other than the first when
+  // its sim is advanced in a batch (all species of a member are pushed and
+  // sorted by the same launches there); bss_nk1 is the key capacity.
+  SortScratch bss{};
+  uint32_t *bstrag = nullptr;
+  size_t bss_nk1 = 0;
+};
+
+template <typename R>
+Particles<R> &parts(SpeciesState &st);
+template <>
+inline Particles<double> &parts<double>(SpeciesState &st) { return st.p64; }
+template <>
+inline Particles<float> &parts<float>(SpeciesState &st) { return st.p32; }
+template <typename R>
+Particles<R> &parts_alt(SpeciesState &st);
+template <>
+inline Particles<double> &parts_alt<double>(SpeciesState &st) {
+  return st.p64_alt;
+}
+template <>
+inline Particles<float> &parts_alt<float>(SpeciesState &st) {
+  return st.p32_alt;
+}
+
+}  // namespace sfpic
+
+struct sfpic_sim {
+  using SpeciesState = sfpic::SpeciesState;
+  using IncParams = sfpic::IncParams;
+  using TileGeom = sfpic::TileGeom;
+  using SortScratch = sfpic::SortScratch;
+  template <typename R>
+  using Fields = sfpic::Fields<R>;
+  sfpic_grid grid{};
+  int precision = SFPIC_FP64;
+  sfpic_runtime rt{};
+  hipStream_t stream = nullptr;
+  int NX = 0, NY = 0, pitch = 0;
+  int64_t step = 0;
+  IncParams inc{};
+  Fields<double> f64{};
+  Fields<float> f32{};
+  void *planes[12] = {};
+  std::vector<SpeciesState> sp;
+  TileGeom tg{};
+  SortScratch ss{};
+  int sort_every = 4;
+  int64_t since_sort = 0;
+  uint32_t *strag = nullptr, *n_strag = nullptr;  // straggler list
+  double *rho0 = nullptr, *rho = nullptr, *acc = nullptr;
+  std::vector<std::pair<void *, size_t>> allocs;
+  // profiling: event pairs per kernel class, recorded in launch order
+  bool profiling = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_used[SFPIC_KCLASSES];
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_free;
+
+  template <typename R>
+  Fields<R> &fields();
+
+  std::pair<hipEvent_t, hipEvent_t> take_events() {
+    if (!ev_free.empty()) {
+      auto e = ev_free.back();
+      ev_free.pop_back();
+      return e;
+    }
+    std::pair<hipEvent_t, hipEvent_t> e{nullptr, nullptr};
+    (void)hipEventCreate(&e.first);
+    (void)hipEventCreate(&e.second);
+    return e;
+  }
+  void recycle_events() {
+    for (auto &v : ev_used) {
+      for (auto &e : v) ev_free.push_back(e);
+      v.clear();
+    }
+  }
+  void destroy_events() {
+    recycle_events();
+    for (auto &e : ev_free) {
+      (void)hipEventDestroy(e.first);
+      (void)hipEventDestroy(e.second);
+    }
+    ev_free.clear();
+  }
+  void *dalloc(size_t bytes) {
+    bytes = (bytes + 255) & ~(size_t)255;
+    void *p = nullptr;
+    if (rt.alloc) {
+      p = rt.alloc(bytes, rt.alloc_ctx);
+    } else if (hipMalloc(&p, bytes) != hipSuccess) {
+      p = nullptr;
+    }
+    if (p) allocs.emplace_back(p, bytes);
+    return p;
+  }
+  void dfree(void *p) {
+    for (size_t k = 0; k < allocs.size(); ++k)
+      if (allocs[k].first == p) {
+        if (rt.free)
+          rt.free(p, allocs[k].second, rt.alloc_ctx);
+        else
+          (void)hipFree(p);
+        allocs.erase(allocs.begin() + k);
+        return;
+      }
+  }
+  void release() {
+    for (auto &a : allocs) {
+      if (rt.free)
+        rt.free(a.first, a.second, rt.alloc_ctx);
+      else
+        (void)hipFree(a.first);
+    }
+    allocs.clear();
+  }
+  size_t esize() const { return precision == SFPIC_FP64 ? 8 : 4; }
+  double cell_volume() const {
+    return grid.dims == 2 ? grid.dx * grid.dy : grid.dx;
+  }
+  // Run f with a value of the working precision's type.
+  template <typename F>
+  int dispatch(F &&f) {
+    return precision == SFPIC_FP64 ? f(0.0) : f(0.0f);
+  }
+};
+
+template <>
+inline sfpic::Fields<double> &sfpic_sim::fields<double>() {
+  return f64;
+}
+template <>
+inline sfpic::Fields<float> &sfpic_sim::fields<float>() {
+  return f32;
+}
+
+namespace sfpic {
+
+// Internal operations used by the batch and server runtime.
+int sort_all(sfpic_sim *s);
+// Set the particle tile to tx x ty cells (reallocating the sort arrays when
+// the key count grows) and re-sort every species.
+int sim_retile(sfpic_sim *s, int tx, int ty);
+// Device bytes held by the sim.
+size_t sim_device_bytes(const sfpic_sim *s);
+// Device bytes a sim created from these arguments would hold (without
+// creating it), with the runtime's tile.
+int sim_footprint(const sfpic_grid *grid, const sfpic_species *species,
+                  int nspecies, sfpic_precision precision,
+                  const sfpic_runtime *rt, size_t *bytes);
+
+}  // namespace sfpic

@@ -52,3 +52,69 @@ def test_null_handles_rejected(L):
     assert L.sfpic_step(None, 1) == -1
     assert L.sfpic_sync(None) == -1
     L.sfpic_destroy(None)  # no-op
+
+
+STRUCTS = ["sfpic_grid", "sfpic_species", "sfpic_incident", "sfpic_runtime",
+           "sfpic_diag", "sfpic_hist_spec", "sfpic_kernel_stats",
+           "sfpic_sim_desc", "sfpic_result", "sfpic_batch_info",
+           "sfpic_server_info"]
+
+
+def test_ctypes_layouts_match_the_header(tmp_path):
+    """Size and every field offset of the binding's ctypes structures equal
+    what a C compiler makes of include/sfpic.h."""
+    import subprocess
+    from paper_2310_11393_amd import binding as b
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "sfpic.h"',
+             'int main(void) {']
+    for name in STRUCTS:
+        cls = getattr(b, name)
+        lines.append(f'printf("{name} %zu\\n", sizeof({name}));')
+        for f, _ in cls._fields_:
+            lines.append(f'printf("{name}.{f} %zu\\n", offsetof({name}, {f}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"),
+                    str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True,
+                         text=True).stdout.split("\n")
+    got = dict(l.split() for l in out if l.strip())
+    for name in STRUCTS:
+        cls = getattr(b, name)
+        assert int(got[name]) == C.sizeof(cls), name
+        for f, _ in cls._fields_:
+            assert int(got[f"{name}.{f}"]) == getattr(cls, f).offset, (name, f)
+
+
+def test_footprint_is_computed_on_the_host(L):
+    """sfpic_desc_footprint needs no GPU; it grows with the particle count
+    by the bytes of two particle sets plus the sort and straggler arrays."""
+    from paper_2310_11393_amd import binding as b
+    from paper_2310_11393_amd import workloads as wl
+    w = wl.sweep_member(3)
+    d1 = b.SimDesc(w).footprint()
+    w.species[0].ppc *= 2
+    d2 = b.SimDesc(w).footprint()
+    n = w.species[0].count() // 2
+    per = 2 * 7 * 4 + 3 * 4  # FP32: two sets of 7 words, key/rank/straggler
+    assert abs((d2 - d1) - n * per) <= 64 * 256
+    assert d1 > 12 * (w.grid.nx + 6) * (w.grid.ny + 6) * 4
+
+
+def test_batch_and_server_reject_bad_arguments(L):
+    from paper_2310_11393_amd import binding as b
+    from paper_2310_11393_amd import workloads as wl
+    h = C.c_void_p()
+    assert L.sfpic_batch_create(0, None, None, C.byref(h)) == -1
+    d = b.SimDesc(wl.sweep_member(0), nsteps=-1)
+    assert L.sfpic_batch_create(1, C.byref(d.desc), None, C.byref(h)) == -1
+    assert b"nsteps" in L.sfpic_last_error()
+    d = b.SimDesc(wl.sweep_member(0), hist=b.hist_spec(sp=3))
+    assert L.sfpic_batch_create(1, C.byref(d.desc), None, C.byref(h)) == -1
+    assert L.sfpic_server_create(0, 0, None, C.byref(h)) == -1
+    assert L.sfpic_batch_run(None) == -1
+    assert L.sfpic_server_submit(None, None, None) == -1
+    L.sfpic_batch_destroy(None)
+    L.sfpic_server_destroy(None)

@@ -1,0 +1,213 @@
+"""Sweeps on the GPU: batches and the request server (needs an MI355X).
+
+Members of a batch are advanced by the batched launches (one launch per
+phase for all members, persistent push over a shared tile queue, graph
+replay of sort_every steps).  Each member must still equal its own oracle run
+(FP64: relative L2 of the fields <= 1e-12 after its steps) and its own run
+alone (FP32 form: <= 1e-4), whatever the other members, the tile chosen by
+the autotuner, the cadence or the step count (not a multiple of the cadence).
+"""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+from paper_2310_11393_amd import workloads as wl
+from paper_2310_11393_amd.binding import (REQ_DONE, Batch, Server, SimDesc,
+                                          hist_spec)
+
+from parity_util import (explicit_species, field_rel_l2, make_gpu,
+                         make_oracle, particle_errors)
+
+pytestmark = pytest.mark.gpu
+
+FP64_FIELD_TOL = 1e-12
+FP32_FIELD_TOL = 1e-4
+
+
+def _note(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _lp(**kw):
+    args = dict(nx=136, ny=72, plasma=(40, 100, 0, 72), ppc=4,
+                kind=wl.INC_APRIL_LP, w0_lambda=1.0, s=20.0, a0=10.0,
+                temperature_ev=1.0, steps=50, seed=11)
+    args.update(kw)
+    return wl.april_2d(**args)
+
+
+def _members(precision):
+    """Uneven members: LP / RP, different grids, densities, a ragged grid
+    and a 1D member (its own group)."""
+    ms = [_lp(precision=precision),
+          _lp(kind=wl.INC_APRIL_RP, w0_lambda=0.8, s=10.0, a0=30.0,
+              temperature_ev=0.0, nx=96, ny=96, plasma=(30, 70, 20, 80),
+              ppc=3, n=0.02, seed=12, precision=precision),
+          _lp(nx=101, ny=77, plasma=(30, 81, 3, 70), ppc=3, s=10.0, seed=13,
+              precision=precision),
+          wl.plane_pulse_1d(nx=300, slab=(100, 230), ppc=16, a0=3.0,
+                            steps=50)]
+    ms[3].precision = precision
+    return ms
+
+
+STEPS = [50, 37, 44, 41]  # not all multiples of any cadence
+
+
+@pytest.mark.parametrize("mode", ["autotune", "fixed_eager"])
+def test_fp64_batch_members_match_oracle(mode):
+    members = _members(wl.FP64)
+    kw = {} if mode == "autotune" else dict(tile=(8, 4), sort_every=3,
+                                            graph=False, autotune=False)
+    _note(f"[batch] fp64 {mode}: {len(members)} members")
+    b = Batch(members, nsteps=STEPS, **kw)
+    b.run()
+    st = b.stats()
+    _note(f"[batch] groups {[(g['dims'], g['tile'], g['sort_every']) for g in st['groups']]}")
+    assert len(st["groups"]) == 2
+    if mode == "autotune":
+        assert all(g["tuned"] for g in st["groups"])
+        assert st["graph_launches"] > 0
+    for i, (work, n) in enumerate(zip(members, STEPS)):
+        sp = explicit_species(work)
+        o = make_oracle(work, sp)
+        o.step(n)
+        g = b.member(i)
+        rel, den = field_rel_l2(g, o)
+        assert den > 0 and rel <= FP64_FIELD_TOL, (i, rel)
+        jrel, _ = field_rel_l2(g, o, comps=("jx", "jy", "jz"))
+        assert jrel <= FP64_FIELD_TOL, (i, jrel)
+        dpos, du, umax = particle_errors(g, o)
+        assert dpos <= 1e-12 and du <= 1e-12 * max(1.0, umax), (i, dpos, du)
+        r = b.result(i)
+        od = o.diagnostics()
+        assert r["status"] == 0 and r["steps"] == n
+        assert r["diag"]["step"] == n
+        assert r["diag"]["n_alive"] == od["n_alive"]
+        assert abs(r["diag"]["w_kin"] - od["w_kin"]) <= 1e-11 * abs(od["w_kin"])
+        assert abs(r["diag"]["w_em"] - od["w_em"]) <= 1e-11 * abs(od["w_em"])
+        # the member can be stepped on as an ordinary simulation afterwards
+    b.close()
+
+
+def test_fp32_batch_member_equals_its_run_alone():
+    """Each FP32 member in the mix vs the same member run alone, and both vs
+    the FP64 oracle."""
+    members = _members(wl.FP32)
+    b = Batch(members, nsteps=STEPS, hist=hist_spec(n_e=64, emax=0.05,
+                                                    n_theta=36, ek_min=0.0))
+    b.run()
+    for i, (work, n) in enumerate(zip(members, STEPS)):
+        alone = make_gpu(work, explicit_species(work), precision=wl.FP32)
+        alone.step(n)
+        g = b.member(i)
+        num = den = 0.0
+        for c in ("ex", "ey", "ez", "bx", "by", "bz"):
+            a, m = alone.read_field(c), g.read_field(c)
+            num += float(np.sum((a - m) ** 2))
+            den += float(np.sum(a ** 2))
+        rel = (num / den) ** 0.5
+        _note(f"[batch] fp32 member {i}: mix vs alone {rel:.2e}")
+        assert den > 0 and rel <= FP32_FIELD_TOL, (i, rel)
+        o = make_oracle(work, explicit_species(work))
+        o.step(n)
+        orel, _ = field_rel_l2(g, o)
+        assert orel <= FP32_FIELD_TOL, (i, orel)
+        r = b.result(i)
+        ad = alone.diagnostics()
+        assert r["diag"]["n_alive"] == ad["n_alive"]
+        assert abs(r["diag"]["w_kin"] - ad["w_kin"]) <= 1e-4 * ad["w_kin"]
+        if work.grid.dims == 2:
+            _, mom = alone.histogram(0, 64, 0.05, 36, 0.0)
+            assert abs(r["moments"][0] - mom[0]) <= 1e-6 * mom[0]
+            for k in range(1, 5):
+                assert abs(r["moments"][k] - mom[k]) <= 1e-3 * abs(mom[k])
+        alone.close()
+    b.close()
+
+
+def test_batch_graph_replays_equal_eager_launches():
+    """Graph replays (with the eager sorts and reads between them) give the
+    results of eager launches, member by member, to the FP64 tolerance."""
+    members = _members(wl.FP64)[:3]
+    steps = [29, 17, 23]
+    ga = Batch(members, nsteps=steps, tile=(16, 8), sort_every=4, graph=True)
+    ea = Batch(members, nsteps=steps, tile=(16, 8), sort_every=4, graph=False)
+    ga.run()
+    ea.run()
+    assert ga.stats()["graph_launches"] >= 8
+    assert ea.stats()["graph_launches"] == 0
+    for i in range(len(members)):
+        a, e = ga.member(i), ea.member(i)
+        num = den = 0.0
+        for c in ("ex", "ey", "ez", "bx", "by", "bz", "jx", "jy", "jz"):
+            x, y = a.read_field(c), e.read_field(c)
+            num += float(np.sum((x - y) ** 2))
+            den += float(np.sum(y ** 2))
+        assert den > 0 and (num / den) ** 0.5 <= FP64_FIELD_TOL, i
+    ga.close()
+    ea.close()
+
+
+def test_server_results_equal_runs_alone():
+    """Requests submitted while others run join at the next tick; each
+    result equals the same simulation run alone (FP64 to 1e-11 on the
+    energies, FP32 to 1e-4)."""
+    srv = Server(max_slots=8)
+    hs = hist_spec(n_e=64, emax=0.05, n_theta=36, ek_min=0.0)
+    reqs = []
+    works = _members(wl.FP64)[:3] + _members(wl.FP32)[:3]
+    steps = [40, 23, 31, 40, 23, 31]
+    # two at once, then the rest while those run
+    for k, (w, n) in enumerate(zip(works, steps)):
+        reqs.append((srv.submit(w, nsteps=n, hist=hs), w, n))
+        if k == 1:
+            time.sleep(0.2)
+    for t, w, n in reqs:
+        srv.wait(t, 300.0)
+        assert srv.poll(t) == REQ_DONE
+    st = srv.stats()
+    _note(f"[server] {st}")
+    assert st["completed"] == len(reqs) and st["failed"] == 0
+    assert st["p99_s"] >= st["p50_s"] > 0.0
+    for t, w, n in reqs:
+        r = srv.result(t)
+        assert r["status"] == 0 and r["steps"] == n
+        alone = make_gpu(w, explicit_species(w))
+        alone.step(n)
+        ad = alone.diagnostics()
+        tol = 1e-11 if w.precision == wl.FP64 else 1e-4
+        assert r["diag"]["n_alive"] == ad["n_alive"]
+        for key in ("w_kin", "w_em"):
+            assert abs(r["diag"][key] - ad[key]) <= tol * abs(ad[key]), key
+        if w.grid.dims == 2:
+            h, mom = alone.histogram(0, 64, 0.05, 36, 0.0)
+            hs_ = srv.histogram(t)
+            assert np.abs(hs_ - h).sum() <= 10 * tol * max(h.sum(), 1e-300)
+        alone.close()
+    srv.close()
+
+
+def test_server_admits_by_device_footprint():
+    """With a budget for two members, at most two are resident; the rest wait
+    in FIFO order and all finish."""
+    works = [_lp(precision=wl.FP32, seed=20 + k) for k in range(5)]
+    fp = SimDesc(works[0]).footprint()
+    srv = Server(budget_bytes=int(2.5 * fp), max_slots=16)
+    tickets = [srv.submit(w, nsteps=12) for w in works]
+    for t in tickets:
+        srv.wait(t, 300.0)
+    st = srv.stats()
+    assert st["completed"] == 5
+    assert st["max_running"] <= 2
+    assert st["bytes_peak"] <= st["budget"]
+    rs = [srv.result(t) for t in tickets]
+    # FIFO: admission order follows submission order
+    starts = [r["t_start"] for r in rs]
+    assert starts == sorted(starts)
+    for r in rs:
+        assert r["device_bytes"] <= fp
+    srv.close()
