@@ -96,6 +96,9 @@ struct Group {
   hipGraphExec_t exec = nullptr;
   bool stale = true;  // tables (and graph) must be rebuilt before launching
   bool ran = false;   // work was launched since the host view was refreshed
+  // members in the order of the device tables (as of the last build);
+  // members added since are not on the device yet
+  std::vector<Member *> built;
 };
 
 // Shared engine of batches and servers: one device, one stream.
@@ -319,6 +322,7 @@ struct Engine {
     g.off_ms = o_ms;
     g.off_pj = o_pj;
     g.np = np;
+    g.built = g.members;
     g.lds = lds;
     const int per_cu =
         batch_push_blocks_per_cu(g.precision == SFPIC_FP64, g.dims, lds);
@@ -334,6 +338,7 @@ struct Engine {
   int build(Group &g) {
     SF_TRY(pull(g));
     if (g.members.empty()) {
+      g.built.clear();
       g.stale = false;
       return SFPIC_OK;
     }
@@ -396,13 +401,13 @@ struct Engine {
   // (waits for the stream).  The device tables stay valid.
   int counts(Group &g) {
     HIP_TRY(hipStreamSynchronize(stream));
-    const int nm = (int)g.members.size();
+    const int nm = (int)g.built.size();
     if (!g.ran || nm == 0) return SFPIC_OK;
     std::vector<MemberState> ms(nm);
     HIP_TRY(hipMemcpy(ms.data(), (uint8_t *)g.dbuf + g.off_ms,
                       nm * sizeof(MemberState), hipMemcpyDeviceToHost));
     for (int mi = 0; mi < nm; ++mi) {
-      Member *m = g.members[mi];
+      Member *m = g.built[mi];
       m->sim->step = ms[mi].step;
       m->done = m->nsteps - ms[mi].steps_left;
     }
@@ -420,7 +425,7 @@ struct Engine {
     HIP_TRY(hipMemcpy(pj.data(), (uint8_t *)g.dbuf + g.off_pj,
                       g.np * sizeof(PushJob<R>), hipMemcpyDeviceToHost));
     int j = 0;
-    for (Member *m : g.members) {
+    for (Member *m : g.built) {
       sfpic_sim *s = m->sim;
       s->since_sort = s->sort_every;
       for (size_t k = 0; k < s->sp.size(); ++k, ++j)
@@ -432,7 +437,7 @@ struct Engine {
   }
 
   int pull(Group &g) {
-    if (!g.ran || g.members.empty()) {
+    if (!g.ran || g.built.empty()) {
       g.ran = false;
       return SFPIC_OK;
     }
@@ -457,7 +462,8 @@ struct Engine {
   // candidate timed on real super-steps of the run, two rounds in opposite
   // orders so that the slow drift of the particle distribution during the
   // run does not favour one candidate.
-  int tune(Group &g) {
+  // rounds: 1 or 2 passes over the candidates (about 30 steps each).
+  int tune(Group &g, int rounds) {
     std::vector<std::pair<int, int>> tiles;
     if (g.dims == 2)
       tiles = {{16, 8}, {16, 16}, {32, 8}, {8, 8}};
@@ -507,7 +513,7 @@ struct Engine {
       const size_t n = tl.size() * cs.size();
       std::vector<double> sum(n, 0.0);
       std::vector<int> cnt(n, 0);
-      for (int round = 0; round < 2; ++round)
+      for (int round = 0; round < rounds; ++round)
         for (size_t q = 0; q < n; ++q) {
           const size_t k = round == 0 ? q : n - 1 - q;
           double ns = 0.0;
@@ -614,7 +620,12 @@ int batch_run_impl(sfpic_batch *b) {
     if (g.members.empty()) continue;
     g.tx = g.members[0]->sim->tg.tx;
     g.ty = g.members[0]->sim->tg.ty;
-    if (autotune) SF_TRY(eng.tune(g));
+    // the trials are real steps of the run; keep them to a quarter of it
+    int64_t longest = 0;
+    for (Member *m : g.members)
+      longest = std::max<int64_t>(longest, m->nsteps - m->done);
+    const int rounds = longest >= 240 ? 2 : (longest >= 120 ? 1 : 0);
+    if (autotune && rounds > 0) SF_TRY(eng.tune(g, rounds));
     for (;;) {
       SF_TRY(eng.pull(g));
       bool any = false;
