@@ -118,6 +118,100 @@ def fp32_vs_fp64(steps=200, err_steps=50):
     return res
 
 
+def batched_sweep(members=256, steps=200):
+    """The laser-focus / density sweep as one batch: `members` FP32 2D3V
+    simulations (grid side 256..1024, 8..32 ppc, LP / RP, density and beam
+    drawn per member), `steps` steps each, tile and sort cadence from the
+    autotuner."""
+    from paper_2310_11393_amd import workloads as wl
+    from paper_2310_11393_amd.binding import Batch
+    ms = [wl.sweep_member(i) for i in range(members)]
+    npart = sum(w.species[0].count() for w in ms)
+    log(f"batched sweep: {members} members, {npart / 1e6:.1f}M particles, "
+        f"{steps} steps each")
+    t0 = time.perf_counter()
+    b = Batch(ms, nsteps=steps)
+    t_create = time.perf_counter() - t0
+    b.run()
+    st = b.stats()
+    b.close()
+    g = st["groups"][0]
+    rate = st["pushes"] / (st["step_ms"] * 1e-3)
+    log(f"batched sweep: {rate / 1e9:.2f} G pushes/s, tile {g['tile']}, "
+        f"cadence {g['sort_every']}")
+    return {"workload": (f"{members} FP32 2D3V sweep members (side 256-1024 "
+                         f"cells at lambda/32, 8-32 ppc, n 0.001-0.1 n_c, "
+                         f"w0 0.6-2 lambda, a0 5-50, LP/RP), {steps} steps "
+                         f"each"),
+            "members": members, "particles": npart, "steps": steps,
+            "pushes_per_s": rate, "step_ms": st["step_ms"],
+            "run_ms": st["run_ms"], "create_s": t_create,
+            "tile": list(g["tile"]), "sort_every": g["sort_every"],
+            "tuned": g["tuned"], "push_workgroups": g["push_workgroups"],
+            "graph_launches": st["graph_launches"],
+            "tuner_trials": [[list(t[0]), t[1], round(t[2], 4)]
+                             for t in g["trials"]]}
+
+
+def served_sweep(rate=2.0, window=30.0, steps=800, slots=16):
+    """Poisson arrivals of sweep requests (10% at 2048^2 x 16 ppc) for
+    `window` seconds at `rate` per second, served with continuous batching;
+    all arrivals are served to completion (none dropped)."""
+    from paper_2310_11393_amd import workloads as wl
+    from paper_2310_11393_amd.binding import Server
+    arrivals = wl.served_sweep(rate=rate, window=window, steps=steps)
+    offered = sum(w.species[0].count() * w.steps for _, w in arrivals)
+    log(f"served sweep: {len(arrivals)} requests over {window:.0f} s "
+        f"(offered {offered / window / 1e9:.1f} G pushes/s), {slots} slots")
+    srv = Server(max_slots=slots)
+    t0 = time.perf_counter()
+    tickets = []
+    last = t0
+    for t_arr, w in arrivals:
+        delay = t0 + t_arr - time.perf_counter()
+        if delay > 0:
+            time.sleep(delay)
+        tickets.append(srv.submit(w))
+        if time.perf_counter() - last > 10.0:
+            last = time.perf_counter()
+            st = srv.stats()
+            log(f"served sweep: t={last - t0:.0f} s submitted "
+                f"{st['submitted']} done {st['completed']} running "
+                f"{st['running']} queued {st['queued']}")
+    queued_at_window_end = srv.stats()["queued"]
+    for k, tk in enumerate(tickets):
+        while True:
+            try:
+                srv.wait(tk, 10.0)
+                break
+            except Exception as e:  # still running: report progress
+                if getattr(e, "code", 0) != -6:
+                    raise
+                st = srv.stats()
+                log(f"served sweep: draining, done {st['completed']}/"
+                    f"{len(tickets)} running {st['running']} queued "
+                    f"{st['queued']}")
+    wall = time.perf_counter() - t0
+    st = srv.stats()
+    srv.close()
+    log(f"served sweep: p50 {st['p50_s']:.2f} s p99 {st['p99_s']:.2f} s, "
+        f"{st['pushes_per_s'] / 1e9:.2f} G pushes/s")
+    return {"workload": (f"Poisson arrivals {rate}/s for {window:.0f} s of "
+                         f"FP32 sweep requests ({steps} steps; 10% at "
+                         f"2048^2 x 16 ppc), {slots} resident slots"),
+            "requests": len(arrivals), "completed": st["completed"],
+            "failed": st["failed"],
+            "offered_pushes_per_s": offered / window,
+            "pushes_per_s": st["pushes_per_s"],
+            "pushes_per_s_wall": st["pushes"] / wall,
+            "p50_s": st["p50_s"], "p99_s": st["p99_s"],
+            "mean_s": st["mean_s"], "max_s": st["max_s"],
+            "queued_at_window_end": queued_at_window_end,
+            "stable": st["pushes_per_s"] > offered / window,
+            "max_resident": st["max_running"], "wall_s": wall,
+            "peak_device_bytes": st["bytes_peak"]}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -125,10 +219,20 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=128)
-    ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--cpu-steps", type=int, default=8)
     ap.add_argument("--no-fp32-compare", action="store_true",
                     help="skip the 4096^2 FP32-form vs FP64 comparison")
     ap.add_argument("--compare-steps", type=int, default=200)
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the batched sweep")
+    ap.add_argument("--batch-members", type=int, default=256)
+    ap.add_argument("--batch-steps", type=int, default=200)
+    ap.add_argument("--no-serve", action="store_true",
+                    help="skip the served sweep")
+    ap.add_argument("--serve-rate", type=float, default=2.0)
+    ap.add_argument("--serve-window", type=float, default=30.0)
+    ap.add_argument("--serve-steps", type=int, default=800)
+    ap.add_argument("--serve-slots", type=int, default=16)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device-to-device copy (3x) "
                          "whose profiler counters calibrate HBM traffic")
@@ -223,6 +327,13 @@ def main():
     sim.close()
     if not args.no_fp32_compare:
         out["fp32_vs_fp64"] = fp32_vs_fp64(args.compare_steps)
+    if not args.no_batch:
+        out["batched_sweep"] = batched_sweep(args.batch_members,
+                                             args.batch_steps)
+    if not args.no_serve:
+        out["served_sweep"] = served_sweep(args.serve_rate,
+                                           args.serve_window,
+                                           args.serve_steps, args.serve_slots)
     if args.calibrate_copy:
         src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
         dst = torch.empty_like(src)

@@ -247,3 +247,42 @@ def sweep_member(i: int, precision=FP32, steps=800) -> Workload:
                   precision=precision)
     wl.name = f"sweep_{i}_{wl.name}"
     return wl
+
+
+def big_sweep_member(i: int, precision=FP32, steps=800) -> Workload:
+    """A large request of the served sweep: 2048^2 cells, 16 ppc in the
+    central 1024^2 cells, beam and density drawn as for sweep_member."""
+    wl = sweep_member(i, precision, steps)
+    inc = wl.incident
+    sp = wl.species[0]
+    kind = inc.kind
+    w0_lambda = inc.w0 / TWO_PI
+    big = april_2d(nx=2048, ny=2048, plasma=(512, 1536, 512, 1536),
+                   n=sp.density, ppc=16, kind=kind, w0_lambda=w0_lambda,
+                   s=10.0, a0=inc.a0, temperature_ev=0.0, steps=steps,
+                   seed=(5 << 16) | i, precision=precision)
+    big.name = f"sweep_big_{i}_{big.name}"
+    return big
+
+
+def served_sweep(rate=20.0, window=60.0, seed=5, big_fraction=0.1,
+                 precision=FP32, steps=800):
+    """Poisson arrivals of sweep requests over `window` seconds: a list of
+    (arrival time in s, workload).  A fraction `big_fraction` are 2048^2
+    requests (big_sweep_member), the rest sweep_member draws."""
+    out = []
+    t = 0.0
+    i = 0
+    while True:
+        r = philox4x32_10(np.array([[i, 0, 0, 0]], dtype=np.uint32),
+                          (seed, 0xA221))
+        u_gap, u_big = u01_pair(r)
+        t += -math.log1p(-float(u_gap[0])) / rate
+        if t >= window:
+            break
+        if float(u_big[0]) < big_fraction:
+            out.append((t, big_sweep_member(i, precision, steps)))
+        else:
+            out.append((t, sweep_member(i, precision, steps)))
+        i += 1
+    return out

@@ -29,12 +29,17 @@ def _note(msg):
 
 
 def gauss_tol(g, d, grid, rel_eps):
-    """Attainable Gauss-law residual: div_h E is a difference of E values of
-    size max|E| divided by the cell size, so its rounding floor is a few eps
-    of max|E|/dx (plus a relative part of the charge density)."""
+    """Attainable Gauss-law residual.  In exact arithmetic the Esirkepov
+    current keeps div_h E - (rho - rho_0) at zero for ever; in floating
+    point every step adds the rounding of the Ampere update and of the
+    deposited current, a few units of rel_eps * max|E| per node, which the
+    discrete divergence divides by the cell size.  The bound therefore grows
+    linearly with the number of steps taken (plus a relative part of the
+    charge density)."""
     emax = max(np.max(np.abs(g.read_field(c))) for c in ("ex", "ey"))
+    steps = max(1, int(d["step"]))
     return max(1e-12 * d["rho_max"],
-               64 * rel_eps * emax * (1 / grid.dx + 1 / grid.dy))
+               8 * steps * rel_eps * emax * (1 / grid.dx + 1 / grid.dy))
 
 
 def _small_lp(kind=wl.INC_APRIL_LP, **kw):
