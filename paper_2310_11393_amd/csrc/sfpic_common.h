@@ -168,9 +168,49 @@ template <typename T>
 __host__ __device__ __forceinline__ cx<T> operator*(T s, cx<T> a) {
   return cx<T>{s * a.r, s * a.i};
 }
+// Reciprocal and reciprocal square root for the particle path.  On the
+// device: the hardware estimate (v_rcp / v_rsq) refined by Newton-Raphson
+// steps, y <- y + y (1 - a y) and y <- y + (y/2)(1 - a y^2), each of which
+// squares the relative error; two steps bring the FP64 estimate to within
+// about an ulp of the rounded result, far cheaper than the IEEE division
+// and square-root sequences.  FP32 uses the estimate alone (about 1 ulp).
+// The host (parameter preparation) divides.
+__host__ __device__ __forceinline__ double rcp(double a) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  double y = __builtin_amdgcn_rcp(a);
+  y = fma(y, fma(-a, y, 1.0), y);
+  return fma(y, fma(-a, y, 1.0), y);
+#else
+  return 1.0 / a;
+#endif
+}
+__host__ __device__ __forceinline__ float rcp(float a) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __builtin_amdgcn_rcpf(a);
+#else
+  return 1.0f / a;
+#endif
+}
+__host__ __device__ __forceinline__ double rsqrt(double a) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  double y = __builtin_amdgcn_rsq(a);
+  y = fma(0.5 * y, fma(-a * y, y, 1.0), y);
+  return fma(0.5 * y, fma(-a * y, y, 1.0), y);
+#else
+  return 1.0 / sqrt(a);
+#endif
+}
+__host__ __device__ __forceinline__ float rsqrt(float a) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __builtin_amdgcn_rsqf(a);
+#else
+  return 1.0f / sqrtf(a);
+#endif
+}
+
 template <typename T>
 __host__ __device__ __forceinline__ cx<T> cinv(cx<T> a) {
-  T d = T(1) / (a.r * a.r + a.i * a.i);
+  T d = rcp(a.r * a.r + a.i * a.i);
   return cx<T>{a.r * d, -a.i * d};
 }
 
@@ -190,16 +230,18 @@ __host__ __device__ __forceinline__ cx<T> cpowi(cx<T> b, int n) {
 
 // Square root with a branch that is continuous away from the negative real
 // axis; the April fields are even in this root, so any branch is valid.
+// With h = (|z| + |Re z|)/2 > 0 the root's larger part is sqrt(h) = h /
+// sqrt(h) and the other part Im z / (2 sqrt(h)); z = 0 is excluded by the
+// callers (the ring neighbourhood uses the series).
 template <typename T>
 __host__ __device__ __forceinline__ cx<T> csqrt_any(cx<T> z) {
-  T m = sqrt(z.r * z.r + z.i * z.i);
-  if (z.r >= T(0)) {
-    T re = sqrt(T(0.5) * (m + z.r));
-    return cx<T>{re, re > T(0) ? z.i / (T(2) * re) : T(0)};
-  }
-  T im = sqrt(T(0.5) * (m - z.r));
-  im = (z.i < T(0)) ? -im : im;
-  return cx<T>{z.i / (T(2) * im), im};
+  const T q = z.r * z.r + z.i * z.i;
+  const T m = q * rsqrt(q);
+  const T h = T(0.5) * (m + fabs(z.r));
+  const T g = rsqrt(h);
+  const T big = h * g, small = T(0.5) * z.i * g;
+  if (z.r >= T(0)) return cx<T>{big, small};
+  return cx<T>{(z.i < T(0)) ? -small : small, (z.i < T(0)) ? -big : big};
 }
 
 // ---------------------------------------------------------------------------

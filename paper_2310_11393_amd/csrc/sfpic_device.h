@@ -66,9 +66,9 @@ __device__ __forceinline__ void boris(R qm, R dt, R u[3], const R E[3],
                                       const R B[3]) {
   const R h = R(0.5) * qm * dt;
   const R um0 = u[0] + h * E[0], um1 = u[1] + h * E[1], um2 = u[2] + h * E[2];
-  const R gi = R(1) / sqrt(R(1) + um0 * um0 + um1 * um1 + um2 * um2);
+  const R gi = rsqrt(R(1) + um0 * um0 + um1 * um1 + um2 * um2);
   const R t0 = h * B[0] * gi, t1 = h * B[1] * gi, t2 = h * B[2] * gi;
-  const R f = R(2) / (R(1) + t0 * t0 + t1 * t1 + t2 * t2);
+  const R f = R(2) * rcp(R(1) + t0 * t0 + t1 * t1 + t2 * t2);
   const R s0 = f * t0, s1 = f * t1, s2 = f * t2;
   const R up0 = um0 + (um1 * t2 - um2 * t1);
   const R up1 = um1 + (um2 * t0 - um0 * t2);

@@ -347,7 +347,7 @@ __device__ __forceinline__ bool push_particle(int &ix, int &iy, R &fx, R &fy,
     B[c] += Bi[c];
   }
   boris<R>((R)pp.qm, (R)pp.dt, u, E, B);
-  const R gi = R(1) / sqrt(R(1) + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+  const R gi = rsqrt(R(1) + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
   // new positions as offsets from the old nearest nodes
   const R d1x = dx0 + (R)(pp.dt * pp.inv_dx) * (u[0] * gi);
   const R d1y = (DIMS == 2) ? dy0 + (R)(pp.dt * pp.inv_dy) * (u[1] * gi) : R(0);
