@@ -118,7 +118,7 @@ def fp32_vs_fp64(steps=200, err_steps=50):
     return res
 
 
-def batched_sweep(members=256, steps=200):
+def batched_sweep(members=256, steps=400):
     """The laser-focus / density sweep as one batch: `members` FP32 2D3V
     simulations (grid side 256..1024, 8..32 ppc, LP / RP, density and beam
     drawn per member), `steps` steps each, tile and sort cadence from the
@@ -226,7 +226,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batched sweep")
     ap.add_argument("--batch-members", type=int, default=256)
-    ap.add_argument("--batch-steps", type=int, default=200)
+    ap.add_argument("--batch-steps", type=int, default=400)
     ap.add_argument("--no-serve", action="store_true",
                     help="skip the served sweep")
     ap.add_argument("--serve-rate", type=float, default=2.0)

@@ -269,10 +269,14 @@ int setup_tiles(sfpic_sim *s) {
     t.tx = s->rt.tile_x > 0 ? s->rt.tile_x : 256;
     t.ty = 1;
   } else {
+    // 16 x 16 by default (measured fastest in both precisions on gfx950);
+    // smaller tiles where the workgroup LDS limit is lower
     t.tx = s->rt.tile_x > 0 ? s->rt.tile_x : 16;
-    t.ty = s->rt.tile_y > 0 ? s->rt.tile_y : 8;
+    t.ty = s->rt.tile_y > 0 ? s->rt.tile_y : 16;
     if (s->rt.tile_x <= 0 && s->rt.tile_y <= 0 && lds_of(t) > (size_t)max_lds)
-      t.tx = 8;  // 8 x 8 tiles fit a 64 KB workgroup limit
+      t.ty = 8;
+    if (s->rt.tile_x <= 0 && s->rt.tile_y <= 0 && lds_of(t) > (size_t)max_lds)
+      t.tx = 8;
   }
   if (t.tx < 1 || t.ty < 1 || t.tx > 1024 || t.ty > 256)
     return fail(SFPIC_E_INVAL, "tile size out of range");
@@ -395,7 +399,7 @@ int sim_footprint(const sfpic_grid *grid, const sfpic_species *species,
   const size_t pitch = (NX + 63) & ~(size_t)63;
   size_t b = 12 * al(NY * pitch * es) + 2 * al(NY * pitch * 8) + al(64 * 8);
   int tx = rt && rt->tile_x > 0 ? rt->tile_x : (dims == 2 ? 16 : 256);
-  int ty = dims == 2 ? (rt && rt->tile_y > 0 ? rt->tile_y : 8) : 1;
+  int ty = dims == 2 ? (rt && rt->tile_y > 0 ? rt->tile_y : 16) : 1;
   const size_t ntx = ((size_t)grid->nx + tx - 1) / tx;
   const size_t nty = dims == 2 ? ((size_t)grid->ny + ty - 1) / ty : 1;
   const size_t nk1 = ntx * nty * (size_t)tx * ty + 1;

@@ -157,7 +157,7 @@ struct Engine {
     Group &g = groups.back();
     g.precision = precision;
     g.dims = dims;
-    g.sort_every = rt.sort_every > 0 ? rt.sort_every : 4;
+    g.sort_every = rt.sort_every > 0 ? rt.sort_every : 8;
     return g;
   }
 
@@ -458,15 +458,15 @@ struct Engine {
     return p;
   }
 
-  // Autotuner: tile size first (cadence 4), then the sort cadence, each
+  // Autotuner: tile size first (cadence 8), then the sort cadence, each
   // candidate timed on real super-steps of the run, two rounds in opposite
   // orders so that the slow drift of the particle distribution during the
   // run does not favour one candidate.
-  // rounds: 1 or 2 passes over the candidates (about 30 steps each).
+  // rounds: 1 or 2 passes over the candidates (about 60 steps each).
   int tune(Group &g, int rounds) {
     std::vector<std::pair<int, int>> tiles;
     if (g.dims == 2)
-      tiles = {{16, 8}, {16, 16}, {32, 8}, {8, 8}};
+      tiles = {{16, 16}, {16, 8}, {32, 8}, {8, 8}};
     else
       tiles = {{256, 1}, {128, 1}, {512, 1}};
     std::vector<std::pair<int, int>> ok;
@@ -534,12 +534,12 @@ struct Engine {
       return SFPIC_OK;
     };
     int bt = 0, bc = 4;
-    int r = pick(ok, {4}, bt, bc);
+    int r = pick(ok, {8}, bt, bc);
     if (r == SFPIC_OK) {
       const std::pair<int, int> best_tile = ok[bt];
       int bt2 = 0;
       bc = 4;
-      r = pick({best_tile}, {2, 4, 8}, bt2, bc);
+      r = pick({best_tile}, {4, 8, 16}, bt2, bc);
       if (r == SFPIC_OK) {
         SF_TRY(pull(g));
         if (best_tile.first != g.tx || best_tile.second != g.ty) {
@@ -624,7 +624,7 @@ int batch_run_impl(sfpic_batch *b) {
     int64_t longest = 0;
     for (Member *m : g.members)
       longest = std::max<int64_t>(longest, m->nsteps - m->done);
-    const int rounds = longest >= 240 ? 2 : (longest >= 120 ? 1 : 0);
+    const int rounds = longest >= 480 ? 2 : (longest >= 240 ? 1 : 0);
     if (autotune && rounds > 0) SF_TRY(eng.tune(g, rounds));
     for (;;) {
       SF_TRY(eng.pull(g));

@@ -7,8 +7,8 @@
 // below and 4 above in each direction) in LDS, accumulates the tile's current
 // in an FP64 LDS window of the same shape with LDS atomics, and adds that
 // window to the global current once.  Particles are staged through LDS in
-// chunks of 1024 and processed in transposed order (lane l takes every 16th
-// particle of the cell-sorted chunk), so the 64 lanes of a wave sit in
+// chunks of 256 kPer and processed in transposed order (lane l takes every
+// (4 kPer)-th particle of the cell-sorted chunk), so the 64 lanes of a wave sit in
 // different cells and their LDS atomics rarely hit the same address.  A
 // particle that has drifted more than one cell out of its tile since the last
 // sort is listed and pushed afterwards by the straggler kernel from global
@@ -22,8 +22,21 @@
 
 namespace sfpic {
 
-constexpr int kChunk = 1024;
-constexpr int kChunkPad = kChunk + kChunk / 16;  // one pad word per 16
+// Particle chunk staged in LDS: kPer particles per thread.  In the
+// transposed order lane l of wave w takes chunk slots l*kStride + w*kPer + j,
+// and one pad word every kStride words spreads those lanes over the banks.
+#ifndef SFPIC_CHUNK_PER
+#define SFPIC_CHUNK_PER 4
+#endif
+// Minimum resident workgroups per CU requested from the compiler for the
+// push kernels (bounds their register use).
+#ifndef SFPIC_PUSH_MIN_BLOCKS
+#define SFPIC_PUSH_MIN_BLOCKS 2
+#endif
+constexpr int kPer = SFPIC_CHUNK_PER;
+constexpr int kChunk = 256 * kPer;
+constexpr int kStride = 4 * kPer;
+constexpr int kChunkPad = kChunk + kChunk / kStride;
 constexpr int kWinExtra = 7;  // window: nodes c0-3 .. c0+T+3
 
 __global__ void fill_u32(uint32_t *a, uint32_t v, size_t n) {
@@ -31,7 +44,7 @@ __global__ void fill_u32(uint32_t *a, uint32_t v, size_t n) {
   if (i < n) a[i] = v;
 }
 
-__device__ __forceinline__ int chunk_slot(int k) { return k + (k >> 4); }
+__device__ __forceinline__ int chunk_slot(int k) { return k + k / kStride; }
 
 // Workgroup -> tile: the hardware deals workgroups round-robin to the 8 XCDs;
 // giving each XCD a contiguous band of tiles keeps the halo rows that
@@ -398,7 +411,9 @@ __device__ __forceinline__ void push_tile(const Fields<R> &f,
   const int WX = tg.tx + kWinExtra;
   const int WY = (DIMS == 2) ? tg.ty + kWinExtra : 1;
   const int WN = WX * WY;
-  double *sj = smem;           // jx jy jz windows (FP64 accumulation)
+  // jx jy jz windows accumulate in FP64 in both precisions (on gfx950 an
+  // FP64 LDS atomic add is several times faster than an FP32 one)
+  double *sj = smem;
   R *sf = (R *)(sj + 3 * WN);  // ex ey ez mx my mz windows
   W *sp = (W *)(sf + 6 * WN);  // particle chunk
   const int P = f.pitch;
@@ -444,8 +459,8 @@ __device__ __forceinline__ void push_tile(const Fields<R> &f,
       PT<R>::g2l(p, c0 + k, sp, chunk_slot(k), DIMS);
     __syncthreads();
 #pragma unroll 1
-    for (int j = 0; j < 4; ++j) {
-      const int idx = lane * 16 + wv * 4 + j;
+    for (int j = 0; j < kPer; ++j) {
+      const int idx = lane * kStride + wv * kPer + j;
       if (idx >= cn) continue;
       const int s = chunk_slot(idx);
       int ix, iy;
@@ -487,7 +502,7 @@ __device__ __forceinline__ void push_tile(const Fields<R> &f,
 }
 
 template <typename R, int DIMS>
-__global__ void __launch_bounds__(256, 2)
+__global__ void __launch_bounds__(256, SFPIC_PUSH_MIN_BLOCKS)
 push_tiled(Fields<R> f, Particles<R> p, const uint32_t *__restrict__ start,
            TileGeom tg, PushParams pp, IncParams inc, uint32_t *strag,
            uint32_t *n_strag) {
@@ -829,7 +844,8 @@ __device__ __forceinline__ PushParams member_params(const BatchView<R> &v,
 }
 
 template <typename R, int DIMS>
-__global__ void __launch_bounds__(256, 2) batch_push_kernel(BatchView<R> v) {
+__global__ void __launch_bounds__(256, SFPIC_PUSH_MIN_BLOCKS)
+batch_push_kernel(BatchView<R> v) {
   extern __shared__ double smem[];
   __shared__ uint32_t s_item;
   for (;;) {

@@ -82,7 +82,7 @@ struct sfpic_sim {
   std::vector<SpeciesState> sp;
   TileGeom tg{};
   SortScratch ss{};
-  int sort_every = 4;
+  int sort_every = 8;
   int64_t since_sort = 0;
   uint32_t *strag = nullptr, *n_strag = nullptr;  // straggler list
   double *rho0 = nullptr, *rho = nullptr, *acc = nullptr;

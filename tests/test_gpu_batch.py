@@ -133,8 +133,9 @@ def test_fp32_batch_member_equals_its_run_alone():
 
 def test_autotuned_fp32_batch():
     """Runs long enough are tuned on their own first steps: every tile and
-    cadence candidate is timed twice on real steps, members are re-tiled in
-    between, and the result still equals each member's run alone."""
+    cadence candidate is timed on real steps (one pass for runs of 240 to
+    479 steps), members are re-tiled in between, and the result still
+    equals each member's run alone."""
     members = [_lp(precision=wl.FP32, seed=31),
                _lp(kind=wl.INC_APRIL_RP, w0_lambda=0.8, s=10.0, a0=30.0,
                    temperature_ev=0.0, nx=96, ny=96, plasma=(30, 70, 20, 80),
@@ -146,9 +147,9 @@ def test_autotuned_fp32_batch():
     g = st["groups"][0]
     _note(f"[batch] tuned: tile {g['tile']} cadence {g['sort_every']} "
           f"trials {g['trials']}")
-    assert g["tuned"] and len(g["trials"]) == 4 * 2 + 3 * 2
+    assert g["tuned"] and len(g["trials"]) == 4 + 3
     assert g["tile"] in [t[0] for t in g["trials"]]
-    assert g["sort_every"] in (2, 4, 8)
+    assert g["sort_every"] in (4, 8, 16)
     assert all(t[2] > 0 for t in g["trials"])
     for i, (work, n) in enumerate(zip(members, steps)):
         alone = make_gpu(work, explicit_species(work), precision=wl.FP32)
