@@ -142,16 +142,17 @@ typedef struct {
   sfpic_free_fn free;    /* NULL = hipFree                                 */
   void *alloc_ctx;
   int32_t tile_x, tile_y; /* particle tile in cells; 0 = library default   */
-  int32_t sort_every;     /* steps between tile sorts; 0 = default         */
+  int32_t sort_every;     /* steps between tile sorts; 0 = default (single
+                             sims 8, batches and servers 4)               */
   int32_t device;         /* HIP device ordinal                            */
   int32_t flags;          /* SFPIC_RT_* (batches and servers)              */
 } sfpic_runtime;
 
 /* runtime.flags: launch a batch's steps one by one instead of replaying a
- * captured HIP graph of sort_every steps. */
+ * captured HIP graph of 8 steps. */
 #define SFPIC_RT_NO_GRAPH 1
-/* runtime.flags: never run the batch autotuner (tile and sort cadence then
- * come from tile_x, tile_y, sort_every or the library defaults). */
+/* runtime.flags: never run the batch autotuner (the tile then comes from
+ * tile_x, tile_y or the library default). */
 #define SFPIC_RT_NO_AUTOTUNE 2
 
 typedef struct {
@@ -266,8 +267,10 @@ int sfpic_device_bytes(sfpic_sim *sim, size_t *bytes);
  * many independent simulations of uneven size on one GPU.  Members of one
  * precision and dimensionality advance together: each phase of a step is a
  * single launch over all of them (the particle push is a persistent kernel
- * that takes tiles of every member from one queue), and sort_every steps
- * plus the tile sort are captured once as a HIP graph and replayed.
+ * that takes tiles of every member from one queue), and 8 steps are
+ * captured once as a HIP graph and replayed.  After every step the tile
+ * sort runs for the members it is due for: every sort_every of a member's
+ * own steps (default 4).
  * ------------------------------------------------------------------------- */
 
 /* One sweep member: the arguments of sfpic_create, the number of steps to
@@ -303,9 +306,10 @@ int sfpic_desc_footprint(const sfpic_sim_desc *desc, const sfpic_runtime *rt,
 typedef struct sfpic_batch sfpic_batch;
 
 /* Create the n members (placing their particles).  rt->stream NULL: the
- * batch creates its own stream.  Tile size and sort cadence: rt->tile_x,
- * tile_y, sort_every if given, otherwise chosen by the autotuner during the
- * first steps of sfpic_batch_run (unless SFPIC_RT_NO_AUTOTUNE). */
+ * batch creates its own stream.  Tile: rt->tile_x, tile_y if given,
+ * otherwise chosen by the autotuner in the first steps of sfpic_batch_run
+ * (runs of 128 steps or more, unless SFPIC_RT_NO_AUTOTUNE).  Sort cadence:
+ * rt->sort_every if given, else 4. */
 int sfpic_batch_create(int n, const sfpic_sim_desc *descs,
                        const sfpic_runtime *rt, sfpic_batch **out);
 
@@ -327,7 +331,7 @@ typedef struct {
   int32_t members[SFPIC_MAX_GROUPS];
   int32_t tile_x[SFPIC_MAX_GROUPS], tile_y[SFPIC_MAX_GROUPS];
   int32_t sort_every[SFPIC_MAX_GROUPS];
-  int32_t tuned[SFPIC_MAX_GROUPS];  /* 1: chosen by the autotuner            */
+  int32_t tuned[SFPIC_MAX_GROUPS];  /* 1: tile chosen by the autotuner       */
   int32_t push_workgroups[SFPIC_MAX_GROUPS];  /* persistent push grid       */
   /* autotuner trials of each group: tile, cadence, ns per particle push    */
   int32_t n_candidates[SFPIC_MAX_GROUPS];
@@ -348,7 +352,7 @@ void sfpic_batch_destroy(sfpic_batch *batch);
  * Serving: a request loop on a library thread.  Submitted members wait in a
  * FIFO queue and are admitted when a slot is free and their device
  * footprint fits the HBM budget; admitted members stay resident and advance
- * together, sort_every steps per tick, with members admitted later joining
+ * together, 8 steps per tick, with members admitted later joining
  * at the next tick (continuous batching).  A finished member's result is
  * kept on the host and its device memory released.
  * ------------------------------------------------------------------------- */

@@ -265,6 +265,9 @@ int setup_tiles(sfpic_sim *s) {
     return s->precision == SFPIC_FP64 ? push_lds_bytes<double>(tt, g.dims)
                                       : push_lds_bytes<float>(tt, g.dims);
   };
+  // drift allowance of the tile window: 1 cell keeps two 16 x 16 FP64
+  // workgroups (81.6 KB each) and three FP32 ones per CU (160 KiB LDS)
+  t.slack = 1;
   if (g.dims == 1) {
     t.tx = s->rt.tile_x > 0 ? s->rt.tile_x : 256;
     t.ty = 1;
@@ -329,10 +332,13 @@ int sort_all(sfpic_sim *s) {
   return r;
 }
 
-int sim_retile(sfpic_sim *s, int tx, int ty) {
+int sim_retile(sfpic_sim *s, int tx, int ty, int slack) {
   if (!s) return fail(SFPIC_E_INVAL, "sim is NULL");
   const sfpic_grid &g = s->grid;
   TileGeom t{};
+  t.slack = slack > 0 ? slack : s->tg.slack;
+  if (t.slack < 1 || t.slack > 4)
+    return fail(SFPIC_E_INVAL, "tile slack out of range");
   t.tx = tx;
   t.ty = g.dims == 2 ? ty : 1;
   if (t.tx < 1 || t.ty < 1 || t.tx > 1024 || t.ty > 256)

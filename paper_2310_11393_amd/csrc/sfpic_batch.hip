@@ -2,8 +2,9 @@
 // (sfpic_server_*).  Both hold ordinary simulations (sfpic_sim) and advance
 // all members of one precision and dimensionality with the batched launches:
 // one launch per phase for the whole group, a persistent push kernel fed by
-// a tile queue, and a HIP graph of `sort_every` steps plus the tile sort that
-// is captured once per membership and replayed.
+// a tile queue, a tile sort after every step that sorts only the members
+// it is due for (each every sort_every of its own steps), and a HIP graph of a few steps that is captured once per
+// membership and replayed.
 #include "sfpic_sim.h"
 
 #include <math.h>
@@ -76,7 +77,11 @@ int check_desc(const sfpic_sim_desc *d) {
 struct Group {
   int precision = SFPIC_FP64, dims = 2;
   std::vector<Member *> members;
-  int tx = 0, ty = 0, sort_every = 4;
+  int tx = 0, ty = 0;
+  // sort cadence: measured on the laser-focus sweep, every 4 steps beats
+  // 8 once the beam has heated the plasma (most of a run)
+  SortRule rule{4};
+  int graph_steps = 8;  // steps per captured graph (a tick of the server)
   bool tuned = false;
   struct Trial {
     int tx, ty, c;
@@ -157,7 +162,7 @@ struct Engine {
     Group &g = groups.back();
     g.precision = precision;
     g.dims = dims;
-    g.sort_every = rt.sort_every > 0 ? rt.sort_every : 8;
+    if (rt.sort_every > 0) g.rule = SortRule{rt.sort_every};
     return g;
   }
 
@@ -206,15 +211,16 @@ struct Engine {
     off = al(off + (size_t)nm * sizeof(FieldJob<R>));
     const size_t o_pj = off;
     off = al(off + (size_t)np * sizeof(PushJob<R>));
-    size_t o_tab[6];
-    const size_t nent[6] = {(size_t)nm + 1, (size_t)nm + 1, (size_t)np + 1,
-                            (size_t)np + 1, (size_t)np + 1, (size_t)np + 1};
-    for (int t = 0; t < 6; ++t) {
+    size_t o_tab[3];
+    const size_t nent[3] = {(size_t)nm + 1, (size_t)nm + 1, (size_t)np + 1};
+    for (int t = 0; t < 3; ++t) {
       o_tab[t] = off;
       off = al(off + nent[t] * 4);
     }
     const size_t o_cnt = off;
-    off = al(off + (size_t)(1 + np) * 4);
+    off = al(off + (size_t)(2 + np) * 4);
+    const size_t o_due = off;
+    off = al(off + (size_t)(np > 0 ? np : 1) * 4);
     if (off > g.dbytes) {
       HIP_TRY(hipStreamSynchronize(stream));
       if (g.dbuf) (void)hipFree(g.dbuf);
@@ -229,9 +235,9 @@ struct Engine {
     MemberState *ms = (MemberState *)(h + o_ms);
     FieldJob<R> *fj = (FieldJob<R> *)(h + o_fj);
     PushJob<R> *pj = (PushJob<R> *)(h + o_pj);
-    uint32_t *tab[6];
-    for (int t = 0; t < 6; ++t) tab[t] = (uint32_t *)(h + o_tab[t]);
-    for (int t = 0; t < 6; ++t) tab[t][0] = 0;
+    uint32_t *tab[3];
+    for (int t = 0; t < 3; ++t) tab[t] = (uint32_t *)(h + o_tab[t]);
+    for (int t = 0; t < 3; ++t) tab[t][0] = 0;
     int j = 0;
     size_t lds = 0;
     for (int mi = 0; mi < nm; ++mi) {
@@ -240,6 +246,8 @@ struct Engine {
       const sfpic_grid &gr = s->grid;
       ms[mi].step = s->step;
       ms[mi].steps_left = m->nsteps - m->done;
+      ms[mi].since_sort = 0;
+      ms[mi].sort_due = 0;
       FieldJob<R> &F = fj[mi];
       F.f = s->fields<R>();
       F.dt = R(gr.dt);
@@ -248,6 +256,8 @@ struct Engine {
       F.kx = R((gr.dt - gr.dx) / (gr.dt + gr.dx));
       F.ky = R((gr.dt - gr.dy) / (gr.dt + gr.dy));
       F.member = mi;
+      F.job0 = j;
+      F.njobs = (int)s->sp.size();
       const uint32_t NX = (uint32_t)s->NX, NY = (uint32_t)s->NY;
       const uint32_t nfar = g.dims == 2 ? ((NX + 63) / 64) * ((NY + 3) / 4)
                                         : (NX + 255) / 256;
@@ -289,11 +299,7 @@ struct Engine {
         P.n_slots = (uint32_t)st.n;
         P.member = mi;
         P.cur = 0;
-        const uint64_t nk1 = (uint64_t)s->tg.nkeys + 1;
         tab[2][j + 1] = tab[2][j] + (uint32_t)s->tg.ntiles;
-        tab[3][j + 1] = tab[3][j] + (uint32_t)((st.n + 255) / 256);
-        tab[4][j + 1] = tab[4][j] + (uint32_t)((nk1 + 255) / 256);
-        tab[5][j + 1] = tab[5][j] + (uint32_t)((nk1 + 1023) / 1024);
       }
     }
     if (lds > max_lds) return fail(SFPIC_E_INVAL, "tile too large for LDS");
@@ -309,16 +315,11 @@ struct Engine {
     v.far_off = (const uint32_t *)(d + o_tab[0]);
     v.amp_off = (const uint32_t *)(d + o_tab[1]);
     v.tile_off = (const uint32_t *)(d + o_tab[2]);
-    v.slot_off = (const uint32_t *)(d + o_tab[3]);
-    v.key_off = (const uint32_t *)(d + o_tab[4]);
-    v.scan_off = (const uint32_t *)(d + o_tab[5]);
     v.counters = (uint32_t *)(d + o_cnt);
+    v.due = (uint32_t *)(d + o_due);
     v.n_far = tab[0][nm];
     v.n_amp = tab[1][nm];
     v.n_tiles = tab[2][np];
-    v.n_slot_blocks = tab[3][np];
-    v.n_key_blocks = tab[4][np];
-    v.n_scan_blocks = tab[5][np];
     g.off_ms = o_ms;
     g.off_pj = o_pj;
     g.np = np;
@@ -349,38 +350,38 @@ struct Engine {
   // One step of every running member of the group.
   template <typename R>
   int enqueue_step_t(Group &g, const BatchView<R> &v) {
-    HIP_TRY(launch_fill_u32(v.counters, 0u, (size_t)(1 + v.np), stream));
+    HIP_TRY(launch_fill_u32(v.counters, 0u, (size_t)(2 + v.np), stream));
     HIP_TRY(launch_batch_faraday<R>(v, g.dims, stream));
     HIP_TRY(launch_batch_push<R>(v, g.dims, g.lds, g.grid, stream));
     HIP_TRY(launch_batch_stragglers<R>(v, g.dims, stream));
     HIP_TRY(launch_batch_ampere<R>(v, g.dims, stream));
-    HIP_TRY(launch_batch_advance(v.ms, v.nmembers, stream));
+    HIP_TRY(launch_batch_advance<R>(v, g.rule, stream));
+    HIP_TRY(launch_batch_sort<R>(v, g.dims, stream));
     return SFPIC_OK;
   }
 
-  // `c` steps followed by the tile sort.
+  // `c` steps, each followed by the sort of the members it is due for.
   int enqueue_superstep(Group &g, int c) {
-    if (g.precision == SFPIC_FP64) {
-      for (int k = 0; k < c; ++k) SF_TRY(enqueue_step_t<double>(g, g.v64));
-      HIP_TRY(launch_batch_sort<double>(g.v64, g.dims, stream));
-    } else {
-      for (int k = 0; k < c; ++k) SF_TRY(enqueue_step_t<float>(g, g.v32));
-      HIP_TRY(launch_batch_sort<float>(g.v32, g.dims, stream));
+    for (int k = 0; k < c; ++k) {
+      if (g.precision == SFPIC_FP64)
+        SF_TRY(enqueue_step_t<double>(g, g.v64));
+      else
+        SF_TRY(enqueue_step_t<float>(g, g.v32));
     }
     return SFPIC_OK;
   }
 
-  // Launch one super-step of sort_every steps, replaying the captured graph
-  // unless graphs are off.
+  // Launch one super-step of graph_steps steps, replaying the captured
+  // graph unless graphs are off.
   int launch_superstep(Group &g) {
     if (g.stale) SF_TRY(build(g));
     if (g.members.empty()) return SFPIC_OK;
     g.ran = true;
-    if (rt.flags & SFPIC_RT_NO_GRAPH) return enqueue_superstep(g, g.sort_every);
+    if (rt.flags & SFPIC_RT_NO_GRAPH) return enqueue_superstep(g, g.graph_steps);
     if (!g.exec) {
       hipGraph_t graph = nullptr;
       HIP_TRY(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
-      const int r = enqueue_superstep(g, g.sort_every);
+      const int r = enqueue_superstep(g, g.graph_steps);
       const hipError_t e = hipStreamEndCapture(stream, &graph);
       if (r != SFPIC_OK) {
         if (graph) (void)hipGraphDestroy(graph);
@@ -452,17 +453,16 @@ struct Engine {
     double p = 0.0;
     for (const Member *m : g.members) {
       const int64_t left = m->nsteps - m->done;
-      const int64_t k = left < g.sort_every ? left : g.sort_every;
+      const int64_t k = left < g.graph_steps ? left : g.graph_steps;
       if (k > 0) p += m->n0 * (double)k;
     }
     return p;
   }
 
-  // Autotuner: tile size first (cadence 8), then the sort cadence, each
-  // candidate timed on real super-steps of the run, two rounds in opposite
-  // orders so that the slow drift of the particle distribution during the
-  // run does not favour one candidate.
-  // rounds: 1 or 2 passes over the candidates (about 60 steps each).
+  // Autotuner: the particle tile, each candidate timed on real super-steps
+  // of the run (graph_steps steps, the group's sort rule) in `rounds`
+  // passes of alternating order, so that the slow drift of the particle
+  // distribution during the run does not favour one candidate.
   int tune(Group &g, int rounds) {
     std::vector<std::pair<int, int>> tiles;
     if (g.dims == 2)
@@ -479,17 +479,18 @@ struct Engine {
                            : push_lds_bytes<float>(tt, g.dims);
       if (l <= max_lds) ok.push_back(t);
     }
+    if (ok.empty()) return SFPIC_OK;
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
-    auto trial = [&](int tx, int ty, int c, double &ns) -> int {
+    const int c = g.rule.c_max;
+    auto trial = [&](int tx, int ty, double &ns) -> int {
       SF_TRY(pull(g));
       if (tx != g.tx || ty != g.ty) {
-        for (Member *m : g.members) SF_TRY(sim_retile(m->sim, tx, ty));
+        for (Member *m : g.members) SF_TRY(sim_retile(m->sim, tx, ty, 0));
         g.tx = tx;
         g.ty = ty;
       }
-      g.sort_every = c;
       g.stale = true;
       SF_TRY(build(g));
       const double pushes = superstep_pushes(g);
@@ -499,7 +500,7 @@ struct Engine {
       }
       HIP_TRY(hipEventRecord(e0, stream));
       g.ran = true;
-      SF_TRY(enqueue_superstep(g, c));
+      SF_TRY(enqueue_superstep(g, g.graph_steps));
       HIP_TRY(hipEventRecord(e1, stream));
       HIP_TRY(hipEventSynchronize(e1));
       float ms = 0.0f;
@@ -508,50 +509,39 @@ struct Engine {
       g.trials.push_back({tx, ty, c, ns});
       return SFPIC_OK;
     };
-    auto pick = [&](const std::vector<std::pair<int, int>> &tl,
-                    const std::vector<int> &cs, int &bt, int &bc) -> int {
-      const size_t n = tl.size() * cs.size();
-      std::vector<double> sum(n, 0.0);
-      std::vector<int> cnt(n, 0);
-      for (int round = 0; round < rounds; ++round)
-        for (size_t q = 0; q < n; ++q) {
-          const size_t k = round == 0 ? q : n - 1 - q;
-          double ns = 0.0;
-          SF_TRY(trial(tl[k / cs.size()].first, tl[k / cs.size()].second,
-                       cs[k % cs.size()], ns));
-          if (ns > 0.0) {
-            sum[k] += ns;
-            cnt[k] += 1;
-          }
+    const size_t n = ok.size();
+    std::vector<double> sum(n, 0.0);
+    std::vector<int> cnt(n, 0);
+    int r = SFPIC_OK;
+    for (int round = 0; round < rounds && r == SFPIC_OK; ++round)
+      for (size_t q = 0; q < n && r == SFPIC_OK; ++q) {
+        const size_t k = round % 2 == 0 ? q : n - 1 - q;
+        double ns = 0.0;
+        r = trial(ok[k].first, ok[k].second, ns);
+        if (ns > 0.0) {
+          sum[k] += ns;
+          cnt[k] += 1;
         }
+      }
+    if (r == SFPIC_OK) {
+      size_t bt = 0;
       double best = 1e300;
       for (size_t k = 0; k < n; ++k)
         if (cnt[k] > 0 && sum[k] / cnt[k] < best) {
           best = sum[k] / cnt[k];
-          bt = (int)(k / cs.size());
-          bc = cs[k % cs.size()];
+          bt = k;
         }
-      return SFPIC_OK;
-    };
-    int bt = 0, bc = 4;
-    int r = pick(ok, {8}, bt, bc);
-    if (r == SFPIC_OK) {
-      const std::pair<int, int> best_tile = ok[bt];
-      int bt2 = 0;
-      bc = 4;
-      r = pick({best_tile}, {4, 8, 16}, bt2, bc);
-      if (r == SFPIC_OK) {
-        SF_TRY(pull(g));
-        if (best_tile.first != g.tx || best_tile.second != g.ty) {
-          for (Member *m : g.members)
-            SF_TRY(sim_retile(m->sim, best_tile.first, best_tile.second));
-          g.tx = best_tile.first;
-          g.ty = best_tile.second;
+      r = pull(g);
+      if (r == SFPIC_OK && (ok[bt].first != g.tx || ok[bt].second != g.ty)) {
+        for (Member *m : g.members) {
+          r = sim_retile(m->sim, ok[bt].first, ok[bt].second, 0);
+          if (r != SFPIC_OK) break;
         }
-        g.sort_every = bc;
-        g.tuned = true;
-        g.stale = true;
+        g.tx = ok[bt].first;
+        g.ty = ok[bt].second;
       }
+      g.tuned = r == SFPIC_OK;
+      g.stale = true;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -585,6 +575,17 @@ int create_member(Engine &eng, const sfpic_sim_desc &d, Member &m) {
   SF_TRY(sfpic_create(&d.grid, d.species, d.nspecies, &d.incident,
                       d.precision, &rt, &s));
   m.sim = s;
+  // the batched FP32 push is held to two workgroups per CU by its registers,
+  // so its tiles can afford the wider window of 2 cells of drift (fewer
+  // particles on the slower straggler path)
+  if (d.precision == SFPIC_FP32 && d.grid.dims == 2 && s->tg.slack < 2) {
+    const int r = sim_retile(s, s->tg.tx, s->tg.ty, 2);
+    if (r != SFPIC_OK) {
+      sfpic_destroy(s);
+      m.sim = nullptr;
+      return r;
+    }
+  }
   m.nsteps = d.nsteps;
   m.done = 0;
   m.hist = d.hist;
@@ -610,8 +611,7 @@ int batch_run_impl(sfpic_batch *b) {
   Engine &eng = b->eng;
   const auto t0 = Clock::now();
   const bool autotune = !(eng.rt.flags & SFPIC_RT_NO_AUTOTUNE) &&
-                        eng.rt.tile_x <= 0 && eng.rt.tile_y <= 0 &&
-                        eng.rt.sort_every <= 0;
+                        eng.rt.tile_x <= 0 && eng.rt.tile_y <= 0;
   hipEvent_t es, ee;
   HIP_TRY(hipEventCreate(&es));
   HIP_TRY(hipEventCreate(&ee));
@@ -624,7 +624,7 @@ int batch_run_impl(sfpic_batch *b) {
     int64_t longest = 0;
     for (Member *m : g.members)
       longest = std::max<int64_t>(longest, m->nsteps - m->done);
-    const int rounds = longest >= 480 ? 2 : (longest >= 240 ? 1 : 0);
+    const int rounds = longest >= 256 ? 2 : (longest >= 128 ? 1 : 0);
     if (autotune && rounds > 0) SF_TRY(eng.tune(g, rounds));
     for (;;) {
       SF_TRY(eng.pull(g));
@@ -637,7 +637,7 @@ int batch_run_impl(sfpic_batch *b) {
         const int64_t l = m->nsteps - m->done;
         left = l > left ? l : left;
       }
-      const int64_t reps = (left + g.sort_every - 1) / g.sort_every;
+      const int64_t reps = (left + g.graph_steps - 1) / g.graph_steps;
       for (int64_t k = 0; k < reps; ++k) {
         SF_TRY(eng.launch_superstep(g));
       }
@@ -761,7 +761,7 @@ int sfpic_batch_stats(sfpic_batch *b, sfpic_batch_info *out) {
     out->members[gi] = (int32_t)g.members.size();
     out->tile_x[gi] = g.tx;
     out->tile_y[gi] = g.ty;
-    out->sort_every[gi] = g.sort_every;
+    out->sort_every[gi] = g.rule.c_max;
     out->tuned[gi] = g.tuned ? 1 : 0;
     out->push_workgroups[gi] = g.grid;
     const int nt = (int)std::min<size_t>(g.trials.size(), SFPIC_MAX_CANDIDATES);

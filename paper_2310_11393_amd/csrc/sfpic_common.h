@@ -69,6 +69,9 @@ struct TileGeom {
   int ntx, nty, ntiles;
   uint32_t cells_per_tile;
   uint32_t nkeys;  // ntiles * cells_per_tile
+  // cells a particle may drift outside its tile (as of the last sort) and
+  // still be pushed by the tile's workgroup; sets the LDS window size
+  int slack;
 };
 
 // Scratch of the counting sort (shared by the species of one sim; each
@@ -101,6 +104,14 @@ struct PushParams {
 struct MemberState {
   int64_t step;        // n of the next step (t^n = n dt)
   int64_t steps_left;  // 0: finished; every kernel skips the member
+  int32_t since_sort;  // steps since the last sort
+  int32_t sort_due;    // the sort launches of this step sort the member
+};
+
+// A member is sorted every c_max of its own steps (members that join a
+// running group count from their own start).
+struct SortRule {
+  int32_t c_max;
 };
 
 template <typename R>
@@ -108,6 +119,7 @@ struct FieldJob {
   Fields<R> f;
   R dt, cx, cy, kx, ky;  // dt, dt/dx, dt/dy, Mur coefficients
   int member;
+  int job0, njobs;       // the member's push jobs
 };
 
 template <typename R>
@@ -133,11 +145,11 @@ struct BatchView {
   int nmembers, nf, np;
   const uint32_t *far_off, *amp_off;  // field jobs: Faraday / Ampere blocks
   const uint32_t *tile_off;           // push jobs: tiles
-  const uint32_t *slot_off;           // push jobs: blocks of 256 slots
-  const uint32_t *key_off;            // push jobs: blocks of 256 keys
-  const uint32_t *scan_off;           // push jobs: blocks of 1024 keys
-  uint32_t *counters;                 // [0] tile queue, [1 + j] stragglers
-  uint32_t n_far, n_amp, n_tiles, n_slot_blocks, n_key_blocks, n_scan_blocks;
+  // [0] tile queue, [1 + j] stragglers of push job j, [1 + np] number of
+  // push jobs to sort this step (listed in due)
+  uint32_t *counters;
+  uint32_t *due;
+  uint32_t n_far, n_amp, n_tiles;
 };
 
 // ---------------------------------------------------------------------------
@@ -569,7 +581,9 @@ hipError_t launch_batch_stragglers(const BatchView<R> &v, int dims,
                                    hipStream_t st);
 template <typename R>
 hipError_t launch_batch_sort(const BatchView<R> &v, int dims, hipStream_t st);
-hipError_t launch_batch_advance(MemberState *ms, int n, hipStream_t st);
+template <typename R>
+hipError_t launch_batch_advance(const BatchView<R> &v, SortRule rule,
+                                hipStream_t st);
 // Resident workgroups of the batched push per CU (0 on error).
 int batch_push_blocks_per_cu(bool fp64, int dims, size_t lds);
 hipError_t launch_fill_u32(uint32_t *a, uint32_t v, size_t n, hipStream_t st);

@@ -233,19 +233,32 @@ hipError_t launch_batch_ampere(const BatchView<R> &v, int dims,
   return hipGetLastError();
 }
 
-// End of a batched step: advance the step counter of every running member.
-__global__ void batch_advance_kernel(MemberState *ms, int n) {
+// End of a batched step: advance the step counter of every running member
+// and decide whether the sort launches that follow sort it.
+template <typename R>
+__global__ void batch_advance_kernel(BatchView<R> v, SortRule rule) {
   const int m = blockIdx.x * blockDim.x + threadIdx.x;
-  if (m >= n) return;
-  if (ms[m].steps_left > 0) {
-    ms[m].steps_left -= 1;
-    ms[m].step += 1;
+  if (m >= v.nmembers) return;
+  MemberState &s = v.ms[m];
+  s.sort_due = 0;
+  if (s.steps_left <= 0) return;
+  s.steps_left -= 1;
+  s.step += 1;
+  s.since_sort += 1;
+  const FieldJob<R> &F = v.fjobs[m];
+  if (s.steps_left > 0 && s.since_sort >= rule.c_max) {
+    s.sort_due = 1;
+    s.since_sort = 0;
+    for (int j = F.job0; j < F.job0 + F.njobs; ++j)
+      v.due[atomicAdd(&v.counters[1 + v.np], 1u)] = (uint32_t)j;
   }
 }
 
-hipError_t launch_batch_advance(MemberState *ms, int n, hipStream_t st) {
-  if (n <= 0) return hipSuccess;
-  batch_advance_kernel<<<(n + 255) / 256, 256, 0, st>>>(ms, n);
+template <typename R>
+hipError_t launch_batch_advance(const BatchView<R> &v, SortRule rule,
+                                hipStream_t st) {
+  if (v.nmembers <= 0) return hipSuccess;
+  batch_advance_kernel<R><<<(v.nmembers + 255) / 256, 256, 0, st>>>(v, rule);
   return hipGetLastError();
 }
 
@@ -596,7 +609,9 @@ hipError_t launch_export_particles(const Particles<R> &p, int64_t n, int dims,
   template hipError_t launch_batch_faraday<R>(const BatchView<R> &, int,      \
                                               hipStream_t);                   \
   template hipError_t launch_batch_ampere<R>(const BatchView<R> &, int,       \
-                                             hipStream_t);
+                                             hipStream_t);                    \
+  template hipError_t launch_batch_advance<R>(const BatchView<R> &, SortRule, \
+                                              hipStream_t);
 
 SFPIC_INSTANTIATE_K(double)
 SFPIC_INSTANTIATE_K(float)

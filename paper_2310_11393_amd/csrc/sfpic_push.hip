@@ -3,16 +3,16 @@
 // at the particle, Boris, Esirkepov deposition; Lytova et al., Sec. 2).
 //
 // Tiled push: one workgroup per tile of tx x ty cells.  The workgroup stages
-// the scattered E and centred B on the tile's node window (tile plus 3 nodes
-// below and 4 above in each direction) in LDS, accumulates the tile's current
-// in an FP64 LDS window of the same shape with LDS atomics, and adds that
-// window to the global current once.  Particles are staged through LDS in
-// chunks of 256 kPer and processed in transposed order (lane l takes every
-// (4 kPer)-th particle of the cell-sorted chunk), so the 64 lanes of a wave sit in
-// different cells and their LDS atomics rarely hit the same address.  A
-// particle that has drifted more than one cell out of its tile since the last
-// sort is listed and pushed afterwards by the straggler kernel from global
-// memory.
+// the scattered E and centred B on the tile's node window (the tile plus
+// slack + 2 nodes on every side, see Lay) in LDS, accumulates the tile's
+// current in an FP64 LDS window of the same shape with LDS atomics, and
+// adds that window to the global current once.  Particles are staged
+// through LDS in chunks and processed in transposed order (lane l takes
+// every (4 per)-th particle of the cell-sorted chunk), so the 64 lanes of a
+// wave sit in different cells and their LDS atomics rarely hit the same
+// address.  A particle that has drifted more than `slack` cells out of its
+// tile since the last sort is listed and pushed afterwards by the straggler
+// kernel from global memory.
 //
 // Two precisions of the same kernels: FP64 (positions as doubles in cell
 // units) and the FP32 form (packed integer cell plus float offsets, float
@@ -22,29 +22,51 @@
 
 namespace sfpic {
 
-// Particle chunk staged in LDS: kPer particles per thread.  In the
-// transposed order lane l of wave w takes chunk slots l*kStride + w*kPer + j,
-// and one pad word every kStride words spreads those lanes over the banks.
-#ifndef SFPIC_CHUNK_PER
-#define SFPIC_CHUNK_PER 4
+// Per-precision layout of the push workgroup's particle chunk in LDS: `per`
+// particles per thread.  In the transposed order lane l of wave w takes
+// chunk slots l*stride + w*per + j (stride = 4 per), and one pad word every
+// stride words spreads those lanes over the banks.  Large chunks keep the
+// 64 lanes of a wave in many different cells (fewer same-address LDS
+// atomics at high particle counts per cell).
+#ifndef SFPIC_CHUNK_PER_F64
+#define SFPIC_CHUNK_PER_F64 4
+#endif
+#ifndef SFPIC_CHUNK_PER_F32
+#define SFPIC_CHUNK_PER_F32 4
 #endif
 // Minimum resident workgroups per CU requested from the compiler for the
 // push kernels (bounds their register use).
 #ifndef SFPIC_PUSH_MIN_BLOCKS
 #define SFPIC_PUSH_MIN_BLOCKS 2
 #endif
-constexpr int kPer = SFPIC_CHUNK_PER;
-constexpr int kChunk = 256 * kPer;
-constexpr int kStride = 4 * kPer;
-constexpr int kChunkPad = kChunk + kChunk / kStride;
-constexpr int kWinExtra = 7;  // window: nodes c0-3 .. c0+T+3
+template <typename R>
+struct Lay {
+  static constexpr int per = sizeof(R) == 8 ? SFPIC_CHUNK_PER_F64
+                                            : SFPIC_CHUNK_PER_F32;
+  static constexpr int chunk = 256 * per;
+  static constexpr int stride = 4 * per;
+  static constexpr int pad = chunk + chunk / stride;  // padded chunk length
+};
+
+// The LDS field window of a tile with drift allowance `slack` (TileGeom):
+// a particle is pushed by its tile's workgroup while its cell is at most
+// slack cells outside the tile, and its order-2 gather and deposit reach 2
+// more nodes, so the window spans physical nodes c0 - slack - 2 .. c0 + T +
+// slack + 2.  Window index of physical node c0 + k is k + slack + 2; array
+// index of window index w is c0 + w - slack + 1 (3 guard cells).
+__host__ __device__ __forceinline__ int win_extra(int slack) {
+  return 2 * slack + 5;
+}
 
 __global__ void fill_u32(uint32_t *a, uint32_t v, size_t n) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) a[i] = v;
 }
 
-__device__ __forceinline__ int chunk_slot(int k) { return k + k / kStride; }
+template <typename R>
+__device__ __forceinline__ int chunk_slot(int k) {
+  return k + k / Lay<R>::stride;
+}
 
 // Workgroup -> tile: the hardware deals workgroups round-robin to the 8 XCDs;
 // giving each XCD a contiguous band of tiles keeps the halo rows that
@@ -78,18 +100,18 @@ struct PT<double> {
   __device__ static void g2l(const Particles<double> &p, uint32_t g, Word *sp,
                              int s, int dims) {
     sp[s] = p.px[g];
-    if (dims == 2) sp[kChunkPad + s] = p.py[g];
-    sp[2 * kChunkPad + s] = p.ux[g];
-    sp[3 * kChunkPad + s] = p.uy[g];
-    sp[4 * kChunkPad + s] = p.uz[g];
+    if (dims == 2) sp[Lay<double>::pad + s] = p.py[g];
+    sp[2 * Lay<double>::pad + s] = p.ux[g];
+    sp[3 * Lay<double>::pad + s] = p.uy[g];
+    sp[4 * Lay<double>::pad + s] = p.uz[g];
   }
   __device__ static void l2g(const Particles<double> &p, uint32_t g,
                              const Word *sp, int s, int dims) {
     p.px[g] = sp[s];
-    if (dims == 2) p.py[g] = sp[kChunkPad + s];
-    p.ux[g] = sp[2 * kChunkPad + s];
-    p.uy[g] = sp[3 * kChunkPad + s];
-    p.uz[g] = sp[4 * kChunkPad + s];
+    if (dims == 2) p.py[g] = sp[Lay<double>::pad + s];
+    p.ux[g] = sp[2 * Lay<double>::pad + s];
+    p.uy[g] = sp[3 * Lay<double>::pad + s];
+    p.uz[g] = sp[4 * Lay<double>::pad + s];
   }
   // Unpack LDS slot s (stride st between arrays); false if removed.
   __device__ static bool unpack(const Word *sp, int s, int st, int dims,
@@ -158,20 +180,20 @@ struct PT<float> {
   __device__ static void g2l(const Particles<float> &p, uint32_t g, Word *sp,
                              int s, int dims) {
     sp[s] = p.cell[g];
-    sp[kChunkPad + s] = __float_as_uint(p.ox[g]);
-    if (dims == 2) sp[2 * kChunkPad + s] = __float_as_uint(p.oy[g]);
-    sp[3 * kChunkPad + s] = __float_as_uint(p.ux[g]);
-    sp[4 * kChunkPad + s] = __float_as_uint(p.uy[g]);
-    sp[5 * kChunkPad + s] = __float_as_uint(p.uz[g]);
+    sp[Lay<float>::pad + s] = __float_as_uint(p.ox[g]);
+    if (dims == 2) sp[2 * Lay<float>::pad + s] = __float_as_uint(p.oy[g]);
+    sp[3 * Lay<float>::pad + s] = __float_as_uint(p.ux[g]);
+    sp[4 * Lay<float>::pad + s] = __float_as_uint(p.uy[g]);
+    sp[5 * Lay<float>::pad + s] = __float_as_uint(p.uz[g]);
   }
   __device__ static void l2g(const Particles<float> &p, uint32_t g,
                              const Word *sp, int s, int dims) {
     p.cell[g] = sp[s];
-    p.ox[g] = __uint_as_float(sp[kChunkPad + s]);
-    if (dims == 2) p.oy[g] = __uint_as_float(sp[2 * kChunkPad + s]);
-    p.ux[g] = __uint_as_float(sp[3 * kChunkPad + s]);
-    p.uy[g] = __uint_as_float(sp[4 * kChunkPad + s]);
-    p.uz[g] = __uint_as_float(sp[5 * kChunkPad + s]);
+    p.ox[g] = __uint_as_float(sp[Lay<float>::pad + s]);
+    if (dims == 2) p.oy[g] = __uint_as_float(sp[2 * Lay<float>::pad + s]);
+    p.ux[g] = __uint_as_float(sp[3 * Lay<float>::pad + s]);
+    p.uy[g] = __uint_as_float(sp[4 * Lay<float>::pad + s]);
+    p.uz[g] = __uint_as_float(sp[5 * Lay<float>::pad + s]);
   }
   __device__ static bool unpack(const Word *sp, int s, int st, int dims,
                                 int &ix, int &iy, float &fx, float &fy,
@@ -402,6 +424,10 @@ __device__ __forceinline__ void push_tile(const Fields<R> &f,
                                           uint32_t *strag, uint32_t *n_strag,
                                           int tile, double *smem) {
   using W = typename PT<R>::Word;
+  constexpr int kPer = Lay<R>::per, kStride = Lay<R>::stride;
+  constexpr int kChunk = Lay<R>::chunk, PADC = Lay<R>::pad;
+  const int kSlack = tg.slack, kWinExtra = win_extra(tg.slack);
+  const int kWinLo = tg.slack + 2;
   const uint32_t cpt = tg.cells_per_tile;
   const uint32_t pbeg = start[(size_t)tile * cpt];
   const uint32_t pend = start[(size_t)(tile + 1) * cpt];
@@ -420,8 +446,9 @@ __device__ __forceinline__ void push_tile(const Fields<R> &f,
 
   // stage E^n and Bbar^n on the node window; array index = cx0 + local
   for (int k = threadIdx.x; k < WN; k += blockDim.x) {
-    const int I = cx0 + k % WX, J = cy0 + k / WX;
-    const bool in = I < f.nx_alloc && J < f.ny_alloc;
+    const int I = cx0 + k % WX - kSlack + 1;
+    const int J = (DIMS == 2) ? cy0 + k / WX - kSlack + 1 : 0;
+    const bool in = I >= 0 && I < f.nx_alloc && J >= 0 && J < f.ny_alloc;
     const size_t g = (size_t)J * P + I;
     sf[k] = in ? f.ex[g] : R(0);
     sf[WN + k] = in ? f.ey[g] : R(0);
@@ -435,13 +462,14 @@ __device__ __forceinline__ void push_tile(const Fields<R> &f,
   }
   __syncthreads();
 
-  // gather from the LDS window: first tap at window index node - c0 + 2
+  // gather from the LDS window (window index of node p: p - c0 + kWinLo)
   auto gather = [&](int ix, int iy, int ipx, int ipy, const R wxp[3],
                     const R wxd[3], const R wyp[3], const R wyd[3], R E[3],
                     R B[3]) {
-    const int bxp = ipx - cx0 + 2, bxd = ix - cx0 + 2;
-    const int byp = (DIMS == 2) ? ipy - cy0 + 2 : 0;
-    const int byd = (DIMS == 2) ? iy - cy0 + 2 : 0;
+    // first tap (node - 1) at window index node - c0 - 1 + kWinLo
+    const int bxp = ipx - cx0 + kWinLo - 1, bxd = ix - cx0 + kWinLo - 1;
+    const int byp = (DIMS == 2) ? ipy - cy0 + kWinLo - 1 : 0;
+    const int byd = (DIMS == 2) ? iy - cy0 + kWinLo - 1 : 0;
     E[0] = gather_plane<R, DIMS>(sf, WX, bxd, byp, wxd, wyp);
     E[1] = gather_plane<R, DIMS>(sf + WN, WX, bxp, byd, wxp, wyd);
     E[2] = gather_plane<R, DIMS>(sf + 2 * WN, WX, bxp, byp, wxp, wyp);
@@ -456,43 +484,46 @@ __device__ __forceinline__ void push_tile(const Fields<R> &f,
   for (uint32_t c0 = pbeg; c0 < pend; c0 += kChunk) {
     const int cn = (int)min((uint32_t)kChunk, pend - c0);
     for (int k = threadIdx.x; k < cn; k += blockDim.x)
-      PT<R>::g2l(p, c0 + k, sp, chunk_slot(k), DIMS);
+      PT<R>::g2l(p, c0 + k, sp, chunk_slot<R>(k), DIMS);
     __syncthreads();
 #pragma unroll 1
     for (int j = 0; j < kPer; ++j) {
       const int idx = lane * kStride + wv * kPer + j;
       if (idx >= cn) continue;
-      const int s = chunk_slot(idx);
+      const int s = chunk_slot<R>(idx);
       int ix, iy;
       R fx, fy, u[3];
-      if (!PT<R>::unpack(sp, s, kChunkPad, DIMS, ix, iy, fx, fy, u)) continue;
-      // particles more than one cell outside the tile go to the straggler
+      if (!PT<R>::unpack(sp, s, PADC, DIMS, ix, iy, fx, fy, u)) continue;
+      // particles more than kSlack cells outside the tile go to the straggler
       // list and are pushed from global memory after this kernel
-      if (!(ix >= cx0 - 1 && ix <= cx0 + tg.tx &&
-            (DIMS == 1 || (iy >= cy0 - 1 && iy <= cy0 + tg.ty)))) {
+      if (!(ix >= cx0 - kSlack && ix < cx0 + tg.tx + kSlack &&
+            (DIMS == 1 ||
+             (iy >= cy0 - kSlack && iy < cy0 + tg.ty + kSlack)))) {
         strag[atomicAdd(n_strag, 1u)] = c0 + idx;
         continue;
       }
       const int ipx0 = ix + (fx >= R(0.5));
       const int ipy0 = (DIMS == 2) ? iy + (fy >= R(0.5)) : 0;
-      // window index of node ipx - 2 is ipx - c0 + 1
-      const int bx = ipx0 - cx0 + 1, by = (DIMS == 2) ? ipy0 - cy0 + 1 : 0;
+      // window index of node ipx - 2, the first deposit node
+      const int bx = ipx0 - cx0 + kWinLo - 2;
+      const int by = (DIMS == 2) ? ipy0 - cy0 + kWinLo - 2 : 0;
       const bool alive = push_particle<R, DIMS>(
           ix, iy, fx, fy, u, pp, inc, gather,
           [&](int c, int a, int b, R v) {
             atomicAdd(&sj[c * WN + (by + b) * WX + bx + a], (double)v);
           });
-      PT<R>::pack(sp, s, kChunkPad, DIMS, alive, ix, iy, fx, fy, u);
+      PT<R>::pack(sp, s, PADC, DIMS, alive, ix, iy, fx, fy, u);
     }
     __syncthreads();
     for (int k = threadIdx.x; k < cn; k += blockDim.x)
-      PT<R>::l2g(p, c0 + k, sp, chunk_slot(k), DIMS);
+      PT<R>::l2g(p, c0 + k, sp, chunk_slot<R>(k), DIMS);
     __syncthreads();
   }
   // add the tile's current window to the grid
   for (int k = threadIdx.x; k < WN; k += blockDim.x) {
-    const int I = cx0 + k % WX, J = cy0 + k / WX;
-    if (I >= f.nx_alloc || J >= f.ny_alloc) continue;
+    const int I = cx0 + k % WX - kSlack + 1;
+    const int J = (DIMS == 2) ? cy0 + k / WX - kSlack + 1 : 0;
+    if (I < 0 || I >= f.nx_alloc || J < 0 || J >= f.ny_alloc) continue;
     const size_t g = (size_t)J * P + I;
     const double vx = sj[k], vy = sj[WN + k], vz = sj[2 * WN + k];
     if (vx != 0.0) unsafeAtomicAdd(&f.jx[g], (R)vx);
@@ -512,8 +543,8 @@ push_tiled(Fields<R> f, Particles<R> p, const uint32_t *__restrict__ start,
   push_tile<R, DIMS>(f, p, start, tg, pp, inc, strag, n_strag, tile, smem);
 }
 
-// Push of one particle listed by the tiled kernel (drifted more than one
-// cell out of its tile): global gather and global atomics.
+// Push of one particle listed by the tiled kernel (drifted more than slack
+// cells out of its tile): global gather and global atomics.
 template <typename R, int DIMS>
 __device__ __forceinline__ void push_straggler(const Fields<R> &f,
                                                const Particles<R> &p,
@@ -562,10 +593,12 @@ push_stragglers(Fields<R> f, Particles<R> p, PushParams pp, IncParams inc,
 
 template <typename R>
 size_t push_lds_bytes(const TileGeom &tg, int dims) {
-  const int WX = tg.tx + kWinExtra, WY = (dims == 2) ? tg.ty + kWinExtra : 1;
+  constexpr int PADC = Lay<R>::pad;
+  const int WX = tg.tx + win_extra(tg.slack);
+  const int WY = (dims == 2) ? tg.ty + win_extra(tg.slack) : 1;
   return (size_t)3 * WX * WY * sizeof(double) +
          (size_t)6 * WX * WY * sizeof(R) +
-         (size_t)PT<R>::kWords * kChunkPad * sizeof(typename PT<R>::Word);
+         (size_t)PT<R>::kWords * PADC * sizeof(typename PT<R>::Word);
 }
 
 template <typename R>
@@ -864,19 +897,23 @@ batch_push_kernel(BatchView<R> v) {
   }
 }
 
-// Stragglers: blockIdx.y is the push job, blockIdx.x strides its list.
+// Stragglers: a persistent grid; every workgroup takes its share of every
+// push job's list, so a member with many stragglers is spread over the
+// whole chip.
 template <typename R, int DIMS>
 __global__ void __launch_bounds__(256) batch_stragglers_kernel(BatchView<R> v) {
-  const int jb = blockIdx.y;
-  const PushJob<R> &J = v.pjobs[jb];
-  if (v.ms[J.member].steps_left <= 0) return;
-  const uint32_t n = v.counters[1 + jb];
-  if (n == 0) return;
-  const PushParams pp = member_params(v, J);
-  const Particles<R> p = J.pa[J.cur];
-  for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < n;
-       k += gridDim.x * blockDim.x)
-    push_straggler<R, DIMS>(J.f, p, pp, J.inc, J.strag[k]);
+  const uint32_t stride = gridDim.x * blockDim.x;
+  const uint32_t first = blockIdx.x * blockDim.x + threadIdx.x;
+  for (int jb = 0; jb < v.np; ++jb) {
+    const PushJob<R> &J = v.pjobs[jb];
+    const uint32_t n = v.counters[1 + jb];
+    if (n <= blockIdx.x * blockDim.x) continue;
+    if (v.ms[J.member].steps_left <= 0) continue;
+    const PushParams pp = member_params(v, J);
+    const Particles<R> p = J.pa[J.cur];
+    for (uint32_t k = first; k < n; k += stride)
+      push_straggler<R, DIMS>(J.f, p, pp, J.inc, J.strag[k]);
+  }
 }
 
 template <typename R>
@@ -894,7 +931,7 @@ template <typename R>
 hipError_t launch_batch_stragglers(const BatchView<R> &v, int dims,
                                    hipStream_t st) {
   if (v.np == 0) return hipSuccess;
-  const dim3 g(16, (unsigned)v.np);
+  const unsigned g = 2048;
   if (dims == 1)
     batch_stragglers_kernel<R, 1><<<g, 256, 0, st>>>(v);
   else
@@ -919,98 +956,93 @@ int batch_push_blocks_per_cu(bool fp64, int dims, size_t lds) {
 }
 
 // Batched counting sort: the same five passes as launch_sort, each one
-// launch over all push jobs of the group.
-template <typename R>
-__device__ __forceinline__ const PushJob<R> *sort_job(const BatchView<R> &v,
-                                                      const uint32_t *off,
-                                                      uint32_t &lb) {
-  const uint32_t b = blockIdx.x;
-  const int jb = find_segment(off, v.np, b);
-  const PushJob<R> *J = &v.pjobs[jb];
-  if (v.ms[J->member].steps_left <= 0) return nullptr;
-  lb = b - off[jb];
-  return J;
-}
+// persistent launch that walks the push jobs the step's advance kernel
+// listed as due (usually none or a few), sharing each job's blocks among
+// its workgroups.  A step without sorts costs a handful of empty launches.
+#define SFPIC_FOR_DUE(v, J, nblk, lb)                                  \
+  for (uint32_t d_ = 0, nd_ = v.counters[1 + v.np]; d_ < nd_; ++d_)    \
+    for (const PushJob<R> *J = &v.pjobs[v.due[d_]]; J; J = nullptr)    \
+      for (uint32_t lb = blockIdx.x, nb_ = (nblk); lb < nb_;           \
+           lb += gridDim.x)
 
 template <typename R>
 __global__ void __launch_bounds__(256) batch_sort_clear(BatchView<R> v) {
-  uint32_t lb;
-  const PushJob<R> *J = sort_job(v, v.key_off, lb);
-  if (!J) return;
-  const uint32_t i = lb * 256 + threadIdx.x;
-  if (i <= J->tg.nkeys) J->ss.counts[i] = 0u;
+  SFPIC_FOR_DUE(v, J, (J->tg.nkeys + 1 + 255) / 256, lb) {
+    const uint32_t i = lb * 256 + threadIdx.x;
+    if (i <= J->tg.nkeys) J->ss.counts[i] = 0u;
+  }
 }
 
 template <typename R>
 __global__ void __launch_bounds__(256) batch_sort_count(BatchView<R> v,
                                                         int dims) {
-  uint32_t lb;
-  const PushJob<R> *J = sort_job(v, v.slot_off, lb);
-  if (!J) return;
-  sort_count_at<R>(J->pa[J->cur], lb * 256 + threadIdx.x, J->n_slots,
-                   *J->n_valid, J->tg, J->pp.nx, J->pp.ny, dims, J->ss.counts,
-                   J->ss.key, J->ss.rank);
+  SFPIC_FOR_DUE(v, J, (J->n_slots + 255) / 256, lb) {
+    sort_count_at<R>(J->pa[J->cur], lb * 256 + threadIdx.x, J->n_slots,
+                     *J->n_valid, J->tg, J->pp.nx, J->pp.ny, dims,
+                     J->ss.counts, J->ss.key, J->ss.rank);
+  }
 }
 
 template <typename R>
 __global__ void __launch_bounds__(256) batch_scan_blocks(BatchView<R> v) {
   __shared__ uint32_t sh[256];
-  uint32_t lb;
-  const PushJob<R> *J = sort_job(v, v.scan_off, lb);
-  if (!J) return;
-  scan_block_at(J->ss.counts, J->start, J->ss.block_sums, J->tg.nkeys + 1, lb,
-                sh);
+  SFPIC_FOR_DUE(v, J, (J->tg.nkeys + 1 + 1023) / 1024, lb) {
+    scan_block_at(J->ss.counts, J->start, J->ss.block_sums, J->tg.nkeys + 1,
+                  lb, sh);
+    __syncthreads();  // sh is reused by the next block of the loop
+  }
 }
 
 template <typename R>
 __global__ void __launch_bounds__(1024) batch_scan_sums(BatchView<R> v) {
   __shared__ uint32_t sh[1024];
-  const PushJob<R> &J = v.pjobs[blockIdx.x];
-  if (v.ms[J.member].steps_left <= 0) return;
-  scan_sums_at(J.ss.block_sums, (J.tg.nkeys + 1 + 1023) / 1024, sh);
+  const uint32_t nd = v.counters[1 + v.np];
+  for (uint32_t d = blockIdx.x; d < nd; d += gridDim.x) {
+    const PushJob<R> &J = v.pjobs[v.due[d]];
+    scan_sums_at(J.ss.block_sums, (J.tg.nkeys + 1 + 1023) / 1024, sh);
+    __syncthreads();
+  }
 }
 
 template <typename R>
 __global__ void __launch_bounds__(256) batch_scan_add(BatchView<R> v) {
-  uint32_t lb;
-  const PushJob<R> *J = sort_job(v, v.scan_off, lb);
-  if (!J) return;
-  scan_add_at(J->start, J->ss.block_sums, J->tg.nkeys + 1, lb);
+  SFPIC_FOR_DUE(v, J, (J->tg.nkeys + 1 + 1023) / 1024, lb) {
+    scan_add_at(J->start, J->ss.block_sums, J->tg.nkeys + 1, lb);
+  }
 }
 
 template <typename R>
 __global__ void __launch_bounds__(256) batch_sort_scatter(BatchView<R> v,
                                                           int dims) {
-  uint32_t lb;
-  const PushJob<R> *J = sort_job(v, v.slot_off, lb);
-  if (!J) return;
-  scatter_at<R>(J->pa[J->cur], J->pa[J->cur ^ 1], lb * 256 + threadIdx.x,
-                J->n_slots, dims, J->ss.key, J->ss.rank, J->start,
-                J->tg.nkeys);
+  SFPIC_FOR_DUE(v, J, (J->n_slots + 255) / 256, lb) {
+    scatter_at<R>(J->pa[J->cur], J->pa[J->cur ^ 1], lb * 256 + threadIdx.x,
+                  J->n_slots, dims, J->ss.key, J->ss.rank, J->start,
+                  J->tg.nkeys);
+  }
 }
 
 // Slots in use after the sort, and the sorted set becomes current.
 template <typename R>
 __global__ void batch_sort_finish(BatchView<R> v) {
-  const int jb = blockIdx.x * blockDim.x + threadIdx.x;
-  if (jb >= v.np) return;
-  PushJob<R> &J = v.pjobs[jb];
-  if (v.ms[J.member].steps_left <= 0) return;
+  const uint32_t d = blockIdx.x * blockDim.x + threadIdx.x;
+  if (d >= v.counters[1 + v.np]) return;
+  PushJob<R> &J = v.pjobs[v.due[d]];
   *J.n_valid = J.start[J.tg.nkeys];
   J.cur ^= 1;
 }
 
+#undef SFPIC_FOR_DUE
+
 template <typename R>
 hipError_t launch_batch_sort(const BatchView<R> &v, int dims, hipStream_t st) {
   if (v.np == 0) return hipSuccess;
-  if (v.n_key_blocks) batch_sort_clear<R><<<v.n_key_blocks, 256, 0, st>>>(v);
-  if (v.n_slot_blocks)
-    batch_sort_count<R><<<v.n_slot_blocks, 256, 0, st>>>(v, dims);
-  if (v.n_scan_blocks) batch_scan_blocks<R><<<v.n_scan_blocks, 256, 0, st>>>(v);
-  batch_scan_sums<R><<<v.np, 1024, 0, st>>>(v);
-  if (v.n_scan_blocks) batch_scan_add<R><<<v.n_scan_blocks, 256, 0, st>>>(v);
-  if (v.n_slot_blocks)
-    batch_sort_scatter<R><<<v.n_slot_blocks, 256, 0, st>>>(v, dims);
+  const unsigned g = 2048;
+  batch_sort_clear<R><<<g, 256, 0, st>>>(v);
+  batch_sort_count<R><<<g, 256, 0, st>>>(v, dims);
+  batch_scan_blocks<R><<<g, 256, 0, st>>>(v);
+  batch_scan_sums<R><<<(unsigned)(v.np < 256 ? v.np : 256), 1024, 0, st>>>(v);
+  batch_scan_add<R><<<g, 256, 0, st>>>(v);
+  batch_sort_scatter<R><<<g, 256, 0, st>>>(v, dims);
   batch_sort_finish<R><<<(v.np + 255) / 256, 256, 0, st>>>(v);
   return hipGetLastError();
 }

@@ -175,9 +175,10 @@ namespace sfpic {
 
 // Internal operations used by the batch and server runtime.
 int sort_all(sfpic_sim *s);
-// Set the particle tile to tx x ty cells (reallocating the sort arrays when
-// the key count grows) and re-sort every species.
-int sim_retile(sfpic_sim *s, int tx, int ty);
+// Set the particle tile to tx x ty cells with drift allowance slack (0:
+// keep the current one), reallocating the sort arrays when the key count
+// grows, and re-sort every species.
+int sim_retile(sfpic_sim *s, int tx, int ty, int slack);
 // Device bytes held by the sim.
 size_t sim_device_bytes(const sfpic_sim *s);
 // Device bytes a sim created from these arguments would hold (without
