@@ -112,7 +112,9 @@ def fp32_vs_fp64(steps=200, err_steps=50):
     num = sum(float(np.sum((a - b) ** 2)) for a, b in
               zip(fields["fp32"], fields["fp64"]))
     den = sum(float(np.sum(b ** 2)) for b in fields["fp64"])
-    res["fp32_vs_fp64_field_rel_l2"] = (num / den) ** 0.5
+    log(f"4096^2 RP: |F64|^2 = {den:.6e}, |F32 - F64|^2 = {num:.6e} after "
+        f"{err_steps} steps")
+    res["fp32_vs_fp64_field_rel_l2"] = (num / den) ** 0.5 if den > 0 else None
     res["error_after_steps"] = err_steps
     res["fp32_over_fp64"] = res["fp32_pushes_per_s"] / res["fp64_pushes_per_s"]
     return res

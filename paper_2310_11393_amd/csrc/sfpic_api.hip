@@ -437,6 +437,43 @@ int sim_footprint(const sfpic_grid *grid, const sfpic_species *species,
 
 namespace {
 
+// Field planes between device (rows of `pitch` elements) and host (rows of
+// NX elements, [NY][NX]): one contiguous copy of the whole pitched plane
+// and the row repacking on the host.  (2D copies are avoided: under the
+// rocprofv3 profiler of ROCm 7.2 hipMemcpy2D from device planes of this
+// size returned zeros while 1D copies were correct.)
+int plane_to_host(const sfpic_sim *s, int comp, void *dst) {
+  const size_t es = s->esize(), row = (size_t)s->NX * es;
+  std::vector<uint8_t> tmp;
+  try {
+    tmp.resize((size_t)s->NY * s->pitch * es);
+  } catch (...) {
+    return fail(SFPIC_E_NOMEM, "host allocation failed");
+  }
+  HIP_TRY(hipMemcpy(tmp.data(), s->planes[comp], tmp.size(),
+                    hipMemcpyDeviceToHost));
+  for (int j = 0; j < s->NY; ++j)
+    memcpy((uint8_t *)dst + j * row, tmp.data() + (size_t)j * s->pitch * es,
+           row);
+  return SFPIC_OK;
+}
+
+int plane_from_host(sfpic_sim *s, int comp, const void *src) {
+  const size_t es = s->esize(), row = (size_t)s->NX * es;
+  std::vector<uint8_t> tmp;
+  try {
+    tmp.assign((size_t)s->NY * s->pitch * es, 0);
+  } catch (...) {
+    return fail(SFPIC_E_NOMEM, "host allocation failed");
+  }
+  for (int j = 0; j < s->NY; ++j)
+    memcpy(tmp.data() + (size_t)j * s->pitch * es,
+           (const uint8_t *)src + j * row, row);
+  HIP_TRY(hipMemcpy(s->planes[comp], tmp.data(), tmp.size(),
+                    hipMemcpyHostToDevice));
+  return SFPIC_OK;
+}
+
 int guarded(sfpic_sim *s) {
   if (!s) return fail(SFPIC_E_INVAL, "sim is NULL");
   HIP_TRY(hipSetDevice(s->rt.device));
@@ -631,17 +668,10 @@ int sfpic_read_field(sfpic_sim *s, int comp, double *out, size_t n) {
     return fail(SFPIC_E_INVAL, "bad component or NULL output");
   if (n != (size_t)s->NX * s->NY) return fail(SFPIC_E_SIZE, "n must be NX*NY");
   HIP_TRY(hipStreamSynchronize(s->stream));
-  if (s->precision == SFPIC_FP64) {
-    HIP_TRY(hipMemcpy2D(out, (size_t)s->NX * 8, s->planes[comp],
-                        (size_t)s->pitch * 8, (size_t)s->NX * 8, s->NY,
-                        hipMemcpyDeviceToHost));
-    return SFPIC_OK;
-  }
   try {
+    if (s->precision == SFPIC_FP64) return plane_to_host(s, comp, out);
     std::vector<float> h(n);
-    HIP_TRY(hipMemcpy2D(h.data(), (size_t)s->NX * 4, s->planes[comp],
-                        (size_t)s->pitch * 4, (size_t)s->NX * 4, s->NY,
-                        hipMemcpyDeviceToHost));
+    SF_TRY(plane_to_host(s, comp, h.data()));
     for (size_t k = 0; k < n; ++k) out[k] = h[k];
   } catch (...) {
     return fail(SFPIC_E_NOMEM, "host allocation failed");
@@ -655,17 +685,10 @@ int sfpic_write_field(sfpic_sim *s, int comp, const double *in, size_t n) {
     return fail(SFPIC_E_INVAL, "bad component or NULL input");
   if (n != (size_t)s->NX * s->NY) return fail(SFPIC_E_SIZE, "n must be NX*NY");
   HIP_TRY(hipStreamSynchronize(s->stream));
-  if (s->precision == SFPIC_FP64) {
-    HIP_TRY(hipMemcpy2D(s->planes[comp], (size_t)s->pitch * 8, in,
-                        (size_t)s->NX * 8, (size_t)s->NX * 8, s->NY,
-                        hipMemcpyHostToDevice));
-    return SFPIC_OK;
-  }
   try {
+    if (s->precision == SFPIC_FP64) return plane_from_host(s, comp, in);
     std::vector<float> h(in, in + n);
-    HIP_TRY(hipMemcpy2D(s->planes[comp], (size_t)s->pitch * 4, h.data(),
-                        (size_t)s->NX * 4, (size_t)s->NX * 4, s->NY,
-                        hipMemcpyHostToDevice));
+    SF_TRY(plane_from_host(s, comp, h.data()));
   } catch (...) {
     return fail(SFPIC_E_NOMEM, "host allocation failed");
   }
@@ -831,9 +854,7 @@ int sfpic_get_state(sfpic_sim *s, void *buf, size_t *n) {
   memcpy(p, hdr, sizeof(hdr));
   p += sizeof(hdr);
   for (int c = 0; c < 9; ++c) {
-    HIP_TRY(hipMemcpy2D(p, (size_t)s->NX * es, s->planes[c],
-                        (size_t)s->pitch * es, (size_t)s->NX * es, s->NY,
-                        hipMemcpyDeviceToHost));
+    SF_TRY(plane_to_host(s, c, p));
     p += (size_t)s->NX * s->NY * es;
   }
   for (size_t k = 0; k < s->sp.size(); ++k) {
@@ -891,9 +912,7 @@ int sfpic_set_state(sfpic_sim *s, const void *buf, size_t n) {
     return fail(SFPIC_E_SIZE, "state size does not match this sim");
   HIP_TRY(hipStreamSynchronize(s->stream));
   for (int c = 0; c < 9; ++c) {
-    HIP_TRY(hipMemcpy2D(s->planes[c], (size_t)s->pitch * es, p,
-                        (size_t)s->NX * es, (size_t)s->NX * es, s->NY,
-                        hipMemcpyHostToDevice));
+    SF_TRY(plane_from_host(s, c, p));
     p += plane;
   }
   for (auto &st : s->sp) {
