@@ -37,6 +37,32 @@ PEAK_FP64_TFLOPS = 78.6
 PEAK_HBM_GBPS = 8000.0
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles",
+                            "push_tiled_f64_lp2048x1024.traffic.txt")
+KERNEL_SOURCES = ("sfpic_push.hip", "sfpic_common.h", "sfpic_device.h")
+
+
+def measured_traffic():
+    """HBM bytes per launch of the FP64 push from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE summary, if the kernel sources are the ones
+    that were profiled (else None)."""
+    import hashlib
+    try:
+        kv = dict(l.strip().split("=", 1) for l in open(TRAFFIC_FILE)
+                  if "=" in l)
+        h = hashlib.sha256()
+        for f in KERNEL_SOURCES:
+            with open(os.path.join(ROOT, "paper_2310_11393_amd", "csrc", f),
+                      "rb") as fh:
+                h.update(fh.read())
+        if h.hexdigest() != kv.get("sources_sha256"):
+            return None
+        return (float(kv["read_bytes_per_launch"]) +
+                float(kv["write_bytes_per_launch"]))
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -301,7 +327,7 @@ def main():
     roofline = {"bound": "alu", "achieved": round(achieved, 3),
                 "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / PEAK_FP64_TFLOPS, 4),
-                "traffic": None,
+                "traffic": measured_traffic(),
                 "kernel": "push_tiled_f64<2>",
                 "avg_launch_ms": round(avg_s * 1e3, 4),
                 "hbm_achieved_GBps": round(bytes_ / avg_s / 1e9, 1),
