@@ -207,18 +207,27 @@ def served_sweep(rate=2.0, window=30.0, steps=800, slots=16):
                 f"{st['submitted']} done {st['completed']} running "
                 f"{st['running']} queued {st['queued']}")
     queued_at_window_end = srv.stats()["queued"]
-    for k, tk in enumerate(tickets):
+    last = time.perf_counter()
+    for tk in tickets:
         while True:
             try:
-                srv.wait(tk, 10.0)
+                srv.wait(tk, 5.0)
                 break
-            except Exception as e:  # still running: report progress
+            except Exception as e:  # still running
                 if getattr(e, "code", 0) != -6:
                     raise
+            if time.perf_counter() - last > 10.0:
+                last = time.perf_counter()
                 st = srv.stats()
                 log(f"served sweep: draining, done {st['completed']}/"
                     f"{len(tickets)} running {st['running']} queued "
                     f"{st['queued']}")
+        if time.perf_counter() - last > 10.0:
+            last = time.perf_counter()
+            st = srv.stats()
+            log(f"served sweep: draining, done {st['completed']}/"
+                f"{len(tickets)} running {st['running']} queued "
+                f"{st['queued']}")
     wall = time.perf_counter() - t0
     st = srv.stats()
     srv.close()
