@@ -181,7 +181,7 @@ def batched_sweep(members=256, steps=400):
                              for t in g["trials"]]}
 
 
-def served_sweep(rate=2.0, window=30.0, steps=800, slots=16):
+def served_sweep(rate=2.0, window=30.0, steps=800, slots=64):
     """Poisson arrivals of sweep requests (10% at 2048^2 x 16 ppc) for
     `window` seconds at `rate` per second, served with continuous batching;
     all arrivals are served to completion (none dropped)."""
@@ -269,7 +269,7 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=2.0)
     ap.add_argument("--serve-window", type=float, default=30.0)
     ap.add_argument("--serve-steps", type=int, default=800)
-    ap.add_argument("--serve-slots", type=int, default=16)
+    ap.add_argument("--serve-slots", type=int, default=64)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device-to-device copy (3x) "
                          "whose profiler counters calibrate HBM traffic")
