@@ -14,7 +14,9 @@ from typing import Optional, Sequence
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libsfpic.so")
+# SFPIC_LIB names another build of the same library (e.g. a variant under
+# test); the default is the in-tree build.
+LIB_PATH = os.environ.get("SFPIC_LIB") or os.path.join(HERE, "libsfpic.so")
 
 SFPIC_OK = 0
 ERRORS = {-1: "E_INVAL", -2: "E_SIZE", -3: "E_NOMEM", -4: "E_DEVICE",

@@ -239,7 +239,7 @@ struct Engine {
     for (int t = 0; t < 3; ++t) tab[t] = (uint32_t *)(h + o_tab[t]);
     for (int t = 0; t < 3; ++t) tab[t][0] = 0;
     int j = 0;
-    size_t lds = 0;
+    size_t lds = 0, dyn = 0;
     for (int mi = 0; mi < nm; ++mi) {
       Member *m = g.members[mi];
       sfpic_sim *s = m->sim;
@@ -269,7 +269,11 @@ struct Engine {
       const size_t l = g.precision == SFPIC_FP64
                            ? push_lds_bytes<double>(s->tg, g.dims)
                            : push_lds_bytes<float>(s->tg, g.dims);
+      const size_t ld = g.precision == SFPIC_FP64
+                            ? push_dyn_lds_bytes<double>(s->tg, g.dims)
+                            : push_dyn_lds_bytes<float>(s->tg, g.dims);
       lds = l > lds ? l : lds;
+      dyn = ld > dyn ? ld : dyn;
       for (size_t k = 0; k < s->sp.size(); ++k, ++j) {
         SpeciesState &st = s->sp[k];
         PushJob<R> &P = pj[j];
@@ -324,9 +328,9 @@ struct Engine {
     g.off_pj = o_pj;
     g.np = np;
     g.built = g.members;
-    g.lds = lds;
+    g.lds = dyn;  // passed at launch; static chunk buffers come on top
     const int per_cu =
-        batch_push_blocks_per_cu(g.precision == SFPIC_FP64, g.dims, lds);
+        batch_push_blocks_per_cu(g.precision == SFPIC_FP64, g.dims, dyn);
     int grid = cus * (per_cu > 0 ? per_cu : 1);
     if ((uint32_t)grid > v.n_tiles) grid = (int)(v.n_tiles > 0 ? v.n_tiles : 1);
     g.grid = grid;
@@ -474,6 +478,7 @@ struct Engine {
       TileGeom tt{};
       tt.tx = t.first;
       tt.ty = t.second;
+      tt.slack = g.members.empty() ? 1 : g.members[0]->sim->tg.slack;
       const size_t l = g.precision == SFPIC_FP64
                            ? push_lds_bytes<double>(tt, g.dims)
                            : push_lds_bytes<float>(tt, g.dims);

@@ -499,8 +499,12 @@ hipError_t launch_faraday(const Fields<R> &f, int dims, double dt, double dx,
 template <typename R>
 hipError_t launch_ampere(const Fields<R> &f, int dims, double dt, double dx,
                          double dy, hipStream_t st);
+// LDS of the push workgroup: all of it (static and dynamic), and the dynamic
+// part passed at launch.
 template <typename R>
 size_t push_lds_bytes(const TileGeom &tg, int dims);
+template <typename R>
+size_t push_dyn_lds_bytes(const TileGeom &tg, int dims);
 // Tiled push; particles that drifted out of their tile window are appended
 // to strag (count in *n_strag, reset by the launcher) for the straggler push.
 template <typename R>

@@ -97,21 +97,29 @@ template <>
 struct PT<double> {
   using Word = double;
   static constexpr int kWords = 5;  // px py ux uy uz
+  static constexpr int kDwords = 2;  // dwords per array element
+  static constexpr int kYArray = 1;  // array unused in 1D
+  __device__ static const uint32_t *words(const Particles<double> &p, int a) {
+    const double *q = a == 0 ? p.px : a == 1 ? p.py : a == 2 ? p.ux
+                    : a == 3 ? p.uy : p.uz;
+    return (const uint32_t *)q;
+  }
+  // global slot g <-> LDS slot s; arrays st words apart in LDS
   __device__ static void g2l(const Particles<double> &p, uint32_t g, Word *sp,
-                             int s, int dims) {
+                             int s, int st, int dims) {
     sp[s] = p.px[g];
-    if (dims == 2) sp[Lay<double>::pad + s] = p.py[g];
-    sp[2 * Lay<double>::pad + s] = p.ux[g];
-    sp[3 * Lay<double>::pad + s] = p.uy[g];
-    sp[4 * Lay<double>::pad + s] = p.uz[g];
+    if (dims == 2) sp[st + s] = p.py[g];
+    sp[2 * st + s] = p.ux[g];
+    sp[3 * st + s] = p.uy[g];
+    sp[4 * st + s] = p.uz[g];
   }
   __device__ static void l2g(const Particles<double> &p, uint32_t g,
-                             const Word *sp, int s, int dims) {
+                             const Word *sp, int s, int st, int dims) {
     p.px[g] = sp[s];
-    if (dims == 2) p.py[g] = sp[Lay<double>::pad + s];
-    p.ux[g] = sp[2 * Lay<double>::pad + s];
-    p.uy[g] = sp[3 * Lay<double>::pad + s];
-    p.uz[g] = sp[4 * Lay<double>::pad + s];
+    if (dims == 2) p.py[g] = sp[st + s];
+    p.ux[g] = sp[2 * st + s];
+    p.uy[g] = sp[3 * st + s];
+    p.uz[g] = sp[4 * st + s];
   }
   // Unpack LDS slot s (stride st between arrays); false if removed.
   __device__ static bool unpack(const Word *sp, int s, int st, int dims,
@@ -177,23 +185,31 @@ template <>
 struct PT<float> {
   using Word = uint32_t;
   static constexpr int kWords = 6;  // cell ox oy ux uy uz
+  static constexpr int kDwords = 1;
+  static constexpr int kYArray = 2;
+  __device__ static const uint32_t *words(const Particles<float> &p, int a) {
+    if (a == 0) return p.cell;
+    const float *q = a == 1 ? p.ox : a == 2 ? p.oy : a == 3 ? p.ux
+                   : a == 4 ? p.uy : p.uz;
+    return (const uint32_t *)q;
+  }
   __device__ static void g2l(const Particles<float> &p, uint32_t g, Word *sp,
-                             int s, int dims) {
+                             int s, int st, int dims) {
     sp[s] = p.cell[g];
-    sp[Lay<float>::pad + s] = __float_as_uint(p.ox[g]);
-    if (dims == 2) sp[2 * Lay<float>::pad + s] = __float_as_uint(p.oy[g]);
-    sp[3 * Lay<float>::pad + s] = __float_as_uint(p.ux[g]);
-    sp[4 * Lay<float>::pad + s] = __float_as_uint(p.uy[g]);
-    sp[5 * Lay<float>::pad + s] = __float_as_uint(p.uz[g]);
+    sp[st + s] = __float_as_uint(p.ox[g]);
+    if (dims == 2) sp[2 * st + s] = __float_as_uint(p.oy[g]);
+    sp[3 * st + s] = __float_as_uint(p.ux[g]);
+    sp[4 * st + s] = __float_as_uint(p.uy[g]);
+    sp[5 * st + s] = __float_as_uint(p.uz[g]);
   }
   __device__ static void l2g(const Particles<float> &p, uint32_t g,
-                             const Word *sp, int s, int dims) {
+                             const Word *sp, int s, int st, int dims) {
     p.cell[g] = sp[s];
-    p.ox[g] = __uint_as_float(sp[Lay<float>::pad + s]);
-    if (dims == 2) p.oy[g] = __uint_as_float(sp[2 * Lay<float>::pad + s]);
-    p.ux[g] = __uint_as_float(sp[3 * Lay<float>::pad + s]);
-    p.uy[g] = __uint_as_float(sp[4 * Lay<float>::pad + s]);
-    p.uz[g] = __uint_as_float(sp[5 * Lay<float>::pad + s]);
+    p.ox[g] = __uint_as_float(sp[st + s]);
+    if (dims == 2) p.oy[g] = __uint_as_float(sp[2 * st + s]);
+    p.ux[g] = __uint_as_float(sp[3 * st + s]);
+    p.uy[g] = __uint_as_float(sp[4 * st + s]);
+    p.uz[g] = __uint_as_float(sp[5 * st + s]);
   }
   __device__ static bool unpack(const Word *sp, int s, int st, int dims,
                                 int &ix, int &iy, float &fx, float &fy,
@@ -441,7 +457,6 @@ __device__ __forceinline__ void push_tile(const Fields<R> &f,
   // FP64 LDS atomic add is several times faster than an FP32 one)
   double *sj = smem;
   R *sf = (R *)(sj + 3 * WN);  // ex ey ez mx my mz windows
-  W *sp = (W *)(sf + 6 * WN);  // particle chunk
   const int P = f.pitch;
 
   // stage E^n and Bbar^n on the node window; array index = cx0 + local
@@ -481,42 +496,45 @@ __device__ __forceinline__ void push_tile(const Fields<R> &f,
   };
 
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  // push the particle in LDS slot s (arrays st words apart) of the chunk
+  // starting at global slot c0; idx is its position in the chunk
+  auto process = [&](W *cp, int st, int s, uint32_t c0, int idx) {
+    int ix, iy;
+    R fx, fy, u[3];
+    if (!PT<R>::unpack(cp, s, st, DIMS, ix, iy, fx, fy, u)) return;
+    // particles more than kSlack cells outside the tile go to the straggler
+    // list and are pushed from global memory after this kernel
+    if (!(ix >= cx0 - kSlack && ix < cx0 + tg.tx + kSlack &&
+          (DIMS == 1 ||
+           (iy >= cy0 - kSlack && iy < cy0 + tg.ty + kSlack)))) {
+      strag[atomicAdd(n_strag, 1u)] = c0 + idx;
+      return;
+    }
+    const int ipx0 = ix + (fx >= R(0.5));
+    const int ipy0 = (DIMS == 2) ? iy + (fy >= R(0.5)) : 0;
+    // window index of node ipx - 2, the first deposit node
+    const int bx = ipx0 - cx0 + kWinLo - 2;
+    const int by = (DIMS == 2) ? ipy0 - cy0 + kWinLo - 2 : 0;
+    const bool alive = push_particle<R, DIMS>(
+        ix, iy, fx, fy, u, pp, inc, gather, [&](int c, int a, int b, R v) {
+          atomicAdd(&sj[c * WN + (by + b) * WX + bx + a], (double)v);
+        });
+    PT<R>::pack(cp, s, st, DIMS, alive, ix, iy, fx, fy, u);
+  };
+  W *sp = (W *)(sf + 6 * WN);  // particle chunk after the windows
   for (uint32_t c0 = pbeg; c0 < pend; c0 += kChunk) {
     const int cn = (int)min((uint32_t)kChunk, pend - c0);
     for (int k = threadIdx.x; k < cn; k += blockDim.x)
-      PT<R>::g2l(p, c0 + k, sp, chunk_slot<R>(k), DIMS);
+      PT<R>::g2l(p, c0 + k, sp, chunk_slot<R>(k), PADC, DIMS);
     __syncthreads();
 #pragma unroll 1
     for (int j = 0; j < kPer; ++j) {
       const int idx = lane * kStride + wv * kPer + j;
-      if (idx >= cn) continue;
-      const int s = chunk_slot<R>(idx);
-      int ix, iy;
-      R fx, fy, u[3];
-      if (!PT<R>::unpack(sp, s, PADC, DIMS, ix, iy, fx, fy, u)) continue;
-      // particles more than kSlack cells outside the tile go to the straggler
-      // list and are pushed from global memory after this kernel
-      if (!(ix >= cx0 - kSlack && ix < cx0 + tg.tx + kSlack &&
-            (DIMS == 1 ||
-             (iy >= cy0 - kSlack && iy < cy0 + tg.ty + kSlack)))) {
-        strag[atomicAdd(n_strag, 1u)] = c0 + idx;
-        continue;
-      }
-      const int ipx0 = ix + (fx >= R(0.5));
-      const int ipy0 = (DIMS == 2) ? iy + (fy >= R(0.5)) : 0;
-      // window index of node ipx - 2, the first deposit node
-      const int bx = ipx0 - cx0 + kWinLo - 2;
-      const int by = (DIMS == 2) ? ipy0 - cy0 + kWinLo - 2 : 0;
-      const bool alive = push_particle<R, DIMS>(
-          ix, iy, fx, fy, u, pp, inc, gather,
-          [&](int c, int a, int b, R v) {
-            atomicAdd(&sj[c * WN + (by + b) * WX + bx + a], (double)v);
-          });
-      PT<R>::pack(sp, s, PADC, DIMS, alive, ix, iy, fx, fy, u);
+      if (idx < cn) process(sp, PADC, chunk_slot<R>(idx), c0, idx);
     }
     __syncthreads();
     for (int k = threadIdx.x; k < cn; k += blockDim.x)
-      PT<R>::l2g(p, c0 + k, sp, chunk_slot<R>(k), DIMS);
+      PT<R>::l2g(p, c0 + k, sp, chunk_slot<R>(k), PADC, DIMS);
     __syncthreads();
   }
   // add the tile's current window to the grid
@@ -592,13 +610,19 @@ push_stragglers(Fields<R> f, Particles<R> p, PushParams pp, IncParams inc,
 }
 
 template <typename R>
-size_t push_lds_bytes(const TileGeom &tg, int dims) {
-  constexpr int PADC = Lay<R>::pad;
+size_t push_dyn_lds_bytes(const TileGeom &tg, int dims) {
   const int WX = tg.tx + win_extra(tg.slack);
   const int WY = (dims == 2) ? tg.ty + win_extra(tg.slack) : 1;
   return (size_t)3 * WX * WY * sizeof(double) +
          (size_t)6 * WX * WY * sizeof(R) +
-         (size_t)PT<R>::kWords * PADC * sizeof(typename PT<R>::Word);
+         (size_t)PT<R>::kWords * Lay<R>::pad * sizeof(typename PT<R>::Word);
+}
+
+// All LDS of the push workgroup (it has no static LDS, so this equals the
+// dynamic size; the batched kernel adds a few bytes of its own).
+template <typename R>
+size_t push_lds_bytes(const TileGeom &tg, int dims) {
+  return push_dyn_lds_bytes<R>(tg, dims);
 }
 
 template <typename R>
@@ -608,7 +632,7 @@ hipError_t launch_push_tiled(const Fields<R> &f, const Particles<R> &p,
                              const IncParams &inc, uint32_t *strag,
                              uint32_t *n_strag, hipStream_t st) {
   const unsigned nb = (unsigned)((tg.ntiles + 7) & ~7);
-  const size_t lds = push_lds_bytes<R>(tg, dims);
+  const size_t lds = push_dyn_lds_bytes<R>(tg, dims);
   fill_u32<<<1, 64, 0, st>>>(n_strag, 0u, 1);
   if (dims == 1)
     push_tiled<R, 1><<<nb, 256, lds, st>>>(f, p, start, tg, pp, inc, strag,
@@ -1049,6 +1073,7 @@ hipError_t launch_batch_sort(const BatchView<R> &v, int dims, hipStream_t st) {
 
 #define SFPIC_INSTANTIATE(R)                                                 \
   template size_t push_lds_bytes<R>(const TileGeom &, int);                  \
+  template size_t push_dyn_lds_bytes<R>(const TileGeom &, int);              \
   template hipError_t launch_push_tiled<R>(                                  \
       const Fields<R> &, const Particles<R> &, const uint32_t *,             \
       const TileGeom &, int, const PushParams &, const IncParams &,          \
