@@ -78,6 +78,8 @@ def lib():
                                         _D, _D]
         L.orc_deposit_rho.argtypes = [C.c_void_p, _D]
         L.orc_diagnostics.argtypes = [C.c_void_p, _D]
+        L.orc_em_energy_total.restype = C.c_double
+        L.orc_em_energy_total.argtypes = [C.c_void_p]
         L.orc_energy_angle.argtypes = [C.c_void_p, C.c_int, C.c_int,
                                        C.c_double, C.c_int, C.c_double, _D, _D]
         _lib = L
@@ -228,7 +230,8 @@ class OracleSim:
         o = np.zeros(4)
         lib().orc_diagnostics(self._h, _dp(o))
         return {"w_kin": o[0], "w_em": o[1], "charge": o[2],
-                "n_alive": int(o[3])}
+                "n_alive": int(o[3]),
+                "w_em_total": lib().orc_em_energy_total(self._h)}
 
     def energy_angle(self, sp=0, n_e=256, emax=1.0, n_theta=180,
                      ek_min=1.0e3 / 510998.95):

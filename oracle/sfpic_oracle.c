@@ -687,6 +687,30 @@ void orc_diagnostics(const orc_sim *S, double out[4]) {
   out[3] = na;
 }
 
+/* Energy of the total field F_inc + F_scatt (Sec. 2) on the physical nodes:
+ * (1/2) sum |E_s^n + E_inc(t^n)|^2 + |B_s^{n-1/2} + B_inc(t^{n-1/2})|^2 dV.
+ * Each component is taken where the Yee grid stores it (the staggering in the
+ * header) and at the time level of the stored scattered field. */
+double orc_em_energy_total(const orc_sim *S) {
+  const int dims = S->g.dims;
+  const long ny = (dims == 2) ? S->g.ny : 1;
+  const double tE = (double)S->step * S->g.dt;
+  const double tB = tE - 0.5 * S->g.dt;
+  double w = 0.0;
+  for (long j = 0; j < ny; ++j)
+    for (long i = 0; i < S->g.nx; ++i)
+      for (int c = 0; c < 6; ++c) {
+        double x = ((double)i + 0.5 * STAG_X[c]) * S->g.dx;
+        double y = (dims == 2) ? ((double)j + 0.5 * STAG_Y[c]) * S->g.dy : 0.0;
+        double E[3], B[3];
+        orc_incident_eval(&S->inc, dims, x, y, c < 3 ? tE : tB, E, B);
+        double fi = (c < 3) ? E[c] : B[c - 3];
+        double fs = AT(S->f[c], i + G, (dims == 2) ? j + G : 0);
+        w += 0.5 * (fs + fi) * (fs + fi);
+      }
+  return w * cell_volume(S);
+}
+
 void orc_energy_angle(const orc_sim *S, int sp, int n_e, double emax,
                       int n_theta, double ek_min, double *hist,
                       double mom[5]) {

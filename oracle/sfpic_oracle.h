@@ -111,6 +111,9 @@ void orc_gather_arrays(const orc_sim *S, double x, double y, double E[3],
 void orc_deposit_rho(const orc_sim *S, double *rho);
 /* out: {W_kin, W_em(E^n, B^{n-1/2}), charge, n_alive} */
 void orc_diagnostics(const orc_sim *S, double out[4]);
+/* W_EM of the total field F_inc + F_scatt over the physical nodes, E at t^n
+ * and B at t^{n-1/2}, each component at its own staggered node. */
+double orc_em_energy_total(const orc_sim *S);
 /* Energy-angle histogram (weights) over species sp: energy bins [0, emax)
  * linear, angle from +x in [0, 180] degrees.  mom: {sum w, <Ek>, <Ek^2>,
  * <theta>, <theta^2>} over particles with Ek > ek_min (theta in degrees). */

@@ -617,3 +617,100 @@ def test_plane_pulse_is_vacuum_solution_and_fwhm():
     ph = math.pi / 2
     E, _ = oracle.incident_eval(inc, 1, 0.0, 0.0, 1.5 + ph)
     assert abs(E[1] - 2.0 * 2 ** (-4 * ph * ph / 49.0)) < 1e-14
+
+
+# ---------------------------------------------------------------------------
+# Total electromagnetic energy (Sec. 2: the total field is F_inc + F_scatt)
+# ---------------------------------------------------------------------------
+
+def test_total_em_energy_of_plane_pulse_closed_form():
+    """In vacuum the scattered field stays zero and the total-field energy is
+    the pulse's: with E_y = B_z = a0 sin(p) 2^{-4 p^2 / F^2}, the energy per
+    unit area is a0^2/2 sqrt(pi/al) (1 - e^{-1/al}), al = 8 ln 2 / F^2 (the
+    node sums of a smooth, well-resolved pulse equal the integral)."""
+    dx, nx, F, a0 = 2 * math.pi / 32, 1400, 10 * math.pi, 1.7
+    inc = wl.Incident(kind=wl.INC_PLANE_PULSE_1D, a0=a0, fwhm_t=F,
+                      t0=-0.5 * nx * dx)
+    sim = OracleSim(_grid(1, nx, 1, dx, dx, 0.95 * dx), inc)
+    al = 8 * math.log(2) / F ** 2
+    w = 0.5 * a0 ** 2 * math.sqrt(math.pi / al) * (1 - math.exp(-1 / al))
+    for _ in range(3):
+        d = sim.diagnostics()
+        assert d["w_em"] == 0.0
+        assert abs(d["w_em_total"] / w - 1) < 1e-13
+        sim.step(20)
+
+
+@pytest.mark.parametrize("dims", [1, 2])
+def test_total_em_energy_cancels_minus_incident_field(dims):
+    """A scattered field equal to minus the incident field sampled where the
+    Yee grid stores each component (E at t^n, B at t^{n-1/2}) has zero total
+    energy; the same field sampled with B at t^n does not."""
+    if dims == 2:
+        work = wl.april_2d(nx=40, ny=36, plasma=(10, 30, 8, 28), ppc=1,
+                           w0_lambda=0.8, a0=5.0, s=10.0,
+                           cells_per_lambda=12)
+        inc = work.incident
+        grid = work.grid
+        inc.t_focus = 0.0  # the focus at the box centre at t = 0
+    else:
+        dx = 2 * math.pi / 16
+        inc = wl.Incident(kind=wl.INC_PLANE_PULSE_1D, a0=1.3,
+                          fwhm_t=4 * math.pi, t0=-20.0)
+        grid = _grid(1, 60, 1, dx, dx, 0.95 * dx)
+    n = 3
+    for b_time in ("half", "integer"):
+        sim = OracleSim(grid, inc)
+        sim.set_step_index(n)
+        tE = n * grid.dt
+        tB = tE - 0.5 * grid.dt if b_time == "half" else tE
+        NX, NY = sim.NX, sim.NY
+        for name, (sx, sy) in STAG.items():
+            c = ("ex", "ey", "ez", "bx", "by", "bz").index(name)
+            X, Y = _node_pos(NX, NY, grid.dx, grid.dy, sx, sy if dims == 2
+                             else 0)
+            arr = sim.field(name)
+            for j in range(NY):
+                for i in range(NX):
+                    E, B = oracle.incident_eval(
+                        inc, dims, X[j, i], Y[j, i] if dims == 2 else 0.0,
+                        tE if c < 3 else tB)
+                    arr[j, i] = -(E[c] if c < 3 else B[c - 3])
+        w = sim.diagnostics()["w_em_total"]
+        ref = sim.diagnostics()["w_em"]  # energy of the incident samples
+        assert ref > 0.0
+        if b_time == "half":
+            assert w <= 1e-28 * ref
+        else:
+            assert w > 1e-6 * ref
+
+
+def _slab_energy_drift(cpl):
+    work = wl.plane_pulse_1d(nx=60 * cpl, slab=(30 * cpl, 34 * cpl), ppc=16,
+                             a0=2.0, n=0.1, cycles=2.0, cells_per_lambda=cpl)
+    sp = work.species[0]
+    sim = OracleSim(work.grid, work.incident)
+    sim.add_species(sp.q, sp.m, sp.weight,
+                    *wl.generate_particles(sp, work.grid))
+    d = sim.diagnostics()
+    e0 = d["w_kin"] + d["w_em_total"]
+    drift, wkin = 0.0, 0.0
+    nst = int(round(20 * 2 * math.pi / work.grid.dt))
+    for _ in range(40):
+        sim.step(nst // 40)
+        d = sim.diagnostics()
+        drift = max(drift, abs(d["w_kin"] + d["w_em_total"] - e0))
+        wkin = max(wkin, d["w_kin"])
+    assert d["n_alive"] == sp.count()
+    return drift / e0, wkin / e0
+
+
+def test_total_energy_conserved_at_second_order():
+    """A 2-cycle pulse (a0 = 2) crosses a 4-wavelength slab at 0.1 n_c while
+    everything stays in the box: W_kin + W_EM(total) is conserved up to the
+    scheme's O(dx^2) error (4x smaller per halving of the cell)."""
+    r16, k16 = _slab_energy_drift(16)
+    r32, k32 = _slab_energy_drift(32)
+    assert k16 > 0.05 and k32 > 0.05  # the plasma takes a real share
+    assert r32 < 0.035
+    assert 3.3 < r16 / r32 < 5.0
