@@ -146,6 +146,9 @@ typedef struct {
                              sims 8, batches and servers 4)               */
   int32_t device;         /* HIP device ordinal                            */
   int32_t flags;          /* SFPIC_RT_* (batches and servers)              */
+  int32_t item_particles; /* single sims: a tile holding more particles is
+                             pushed by several workgroups, this many each;
+                             0 = default (8192); must be >= 64            */
 } sfpic_runtime;
 
 /* runtime.flags: launch a batch's steps one by one instead of replaying a
@@ -167,6 +170,10 @@ typedef struct {
                             least 4 cells inside the physical box          */
   double rho_max;        /* max |rho - rho_0| over the same nodes          */
   int32_t nonfinite;     /* 1 if a non-finite field or momentum was seen   */
+  double w_em_total;     /* 1/2 sum |E_s^n + E_inc(t^n)|^2 + |B_s^{n-1/2} +
+                            B_inc(t^{n-1/2})|^2 dV over the physical nodes,
+                            each component at its Yee node: energy of the
+                            total field F_inc + F_scatt (Sec. 2)            */
 } sfpic_diag;
 
 typedef struct {

@@ -68,7 +68,7 @@ class sfpic_runtime(C.Structure):
                 ("free", FREE_FN), ("alloc_ctx", C.c_void_p),
                 ("tile_x", C.c_int32), ("tile_y", C.c_int32),
                 ("sort_every", C.c_int32), ("device", C.c_int32),
-                ("flags", C.c_int32)]
+                ("flags", C.c_int32), ("item_particles", C.c_int32)]
 
 
 RT_NO_GRAPH, RT_NO_AUTOTUNE = 1, 2
@@ -79,7 +79,7 @@ class sfpic_diag(C.Structure):
                 ("n_alive", C.c_int64), ("w_kin", C.c_double),
                 ("w_em", C.c_double), ("charge", C.c_double),
                 ("gauss_residual", C.c_double), ("rho_max", C.c_double),
-                ("nonfinite", C.c_int32)]
+                ("nonfinite", C.c_int32), ("w_em_total", C.c_double)]
 
 
 class sfpic_hist_spec(C.Structure):
@@ -261,12 +261,13 @@ class _TorchMemory:
 
 
 def make_runtime(use_torch: bool = True, device: int = 0, tile=(0, 0),
-                 sort_every: int = 0, flags: int = 0):
+                 sort_every: int = 0, flags: int = 0, item_particles: int = 0):
     rt = sfpic_runtime()
     rt.device = device
     rt.tile_x, rt.tile_y = tile
     rt.sort_every = sort_every
     rt.flags = flags
+    rt.item_particles = item_particles
     keep = None
     if use_torch:
         try:
@@ -378,14 +379,15 @@ class Simulation:
     def __init__(self, grid, incident, species: Sequence = (),
                  explicit: Optional[Sequence] = None, precision: int = FP64,
                  use_torch: bool = True, device: int = 0, tile=(0, 0),
-                 sort_every: int = 0):
+                 sort_every: int = 0, item_particles: int = 0):
         """species: workloads.Species list (generated on the device), or
         explicit: list of dicts {q, m, weight, x, y, ux, uy, uz}."""
         L = lib()
         self.grid = grid
         self.precision = precision
         self._borrowed = False
-        self._rt, self._mem = make_runtime(use_torch, device, tile, sort_every)
+        self._rt, self._mem = make_runtime(use_torch, device, tile, sort_every,
+                                           item_particles=item_particles)
         sp_arr, n, keep = _species_structs(species, explicit)
         self.nspecies = n
         g = _grid_struct(grid)

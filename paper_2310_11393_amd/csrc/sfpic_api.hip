@@ -293,6 +293,11 @@ int setup_tiles(sfpic_sim *s) {
   if (lds_of(t) > (size_t)max_lds)
     return fail(SFPIC_E_INVAL, "tile too large for LDS");
   if (s->rt.sort_every > 0) s->sort_every = s->rt.sort_every;
+  if (s->rt.item_particles != 0) {
+    if (s->rt.item_particles < 64)
+      return fail(SFPIC_E_INVAL, "item_particles must be >= 64");
+    s->item_max = (uint32_t)s->rt.item_particles;
+  }
   const size_t nk1 = (size_t)t.nkeys + 1;
   s->ss.counts = (uint32_t *)s->dalloc(nk1 * 4);
   for (auto &st : s->sp) {
@@ -325,6 +330,12 @@ int sort_all(sfpic_sim *s) {
                              st.n_valid, st.start, s->tg, (int)s->grid.nx,
                              (int)s->grid.ny, s->grid.dims, s->ss, s->stream));
       std::swap(parts<R>(st), parts_alt<R>(st));
+      // (after a retile to more tiles the arrays may be too small: the next
+      // step's refresh_items reallocates and builds them)
+      if (st.items &&
+          st.items_words >= push_items_words(s->tg, st.n, s->item_max))
+        HIP_TRY(launch_build_items(st.start, s->tg, s->item_max, st.items,
+                                   st.n_items, s->stream));
     }
     return SFPIC_OK;
   });
@@ -426,7 +437,10 @@ int sim_footprint(const sfpic_grid *grid, const sfpic_species *species,
     nmax = cnt > nmax ? cnt : nmax;
     const size_t set = precision == SFPIC_FP64 ? 5 * al(cnt * 8) + al(cnt * 4)
                                                : 7 * al(cnt * 4);
-    b += al(4) + 2 * set + al(nk1 * 4);
+    const size_t kmax = rt && rt->item_particles >= 64
+                            ? (size_t)rt->item_particles : kItemParticles;
+    const size_t items = 2 * (ntx * nty + cnt / kmax + 1);
+    b += al(4) + 2 * set + al(nk1 * 4) + al(items * 4) + al(4);
   }
   b += 3 * al(nmax * 4) + al(staging);
   *bytes = b;
@@ -492,10 +506,34 @@ hipError_t timed(sfpic_sim *s, int cls, F &&launch) {
   return r;
 }
 
+// Work items of every species for the current sort (the start offsets may
+// also have been rewritten by a batch's sorts); the arrays are (re)allocated
+// here when the tiling needs more than they hold.
+int refresh_items(sfpic_sim *s) {
+  for (auto &st : s->sp) {
+    const size_t words = push_items_words(s->tg, st.n, s->item_max);
+    if (words > st.items_words) {
+      HIP_TRY(hipStreamSynchronize(s->stream));  // old arrays may be queued
+      s->dfree(st.items);
+      if (!st.n_items) st.n_items = (uint32_t *)s->dalloc(4);
+      st.items = (uint32_t *)s->dalloc(words * 4);
+      if (!st.items || !st.n_items) {
+        st.items_words = 0;
+        return fail(SFPIC_E_NOMEM, "work-item allocation failed");
+      }
+      st.items_words = words;
+    }
+    HIP_TRY(launch_build_items(st.start, s->tg, s->item_max, st.items,
+                               st.n_items, s->stream));
+  }
+  return SFPIC_OK;
+}
+
 template <typename R>
 int step_impl(sfpic_sim *s, int64_t nsteps) {
   const sfpic_grid &g = s->grid;
   Fields<R> &f = s->fields<R>();
+  if (nsteps > 0) SF_TRY(refresh_items(s));
   for (int64_t k = 0; k < nsteps; ++k) {
     if (s->since_sort >= s->sort_every) {
       HIP_TRY(timed(s, 3, [&] {
@@ -518,8 +556,9 @@ int step_impl(sfpic_sim *s, int64_t nsteps) {
       pp.nx = (int)g.nx;
       pp.ny = (int)g.ny;
       HIP_TRY(timed(s, 1, [&] {
-        return launch_push_tiled<R>(f, parts<R>(st), st.start, s->tg, g.dims,
-                                    pp, s->inc, s->strag, s->n_strag,
+        return launch_push_tiled<R>(f, parts<R>(st), st.start, st.items,
+                                    st.n_items, s->item_max, st.n, s->tg,
+                                    g.dims, pp, s->inc, s->strag, s->n_strag,
                                     s->stream);
       }));
       HIP_TRY(timed(s, 4, [&] {
@@ -768,6 +807,11 @@ int sfpic_diagnostics(sfpic_sim *s, sfpic_diag *out) {
                                       s->grid.dims, st.m, st.q,
                                       st.weight * dv, s->acc, s->stream));
     HIP_TRY(launch_field_sums<R>(s->fields<R>(), s->acc, s->stream));
+    const double tE = (double)s->step * s->grid.dt;
+    HIP_TRY(launch_em_total<R>(s->fields<R>(), s->grid.dims, (int)s->grid.nx,
+                               (int)s->grid.ny, s->grid.dx, s->grid.dy, tE,
+                               tE - 0.5 * s->grid.dt, s->inc, s->acc,
+                               s->stream));
     return SFPIC_OK;
   }));
   SF_TRY(deposit_rho(s, s->rho));
@@ -790,6 +834,7 @@ int sfpic_diagnostics(sfpic_sim *s, sfpic_diag *out) {
   out->w_em = h[4] * dv;
   out->gauss_residual = h[5];
   out->rho_max = h[6];
+  out->w_em_total = h[7] * dv;
   return SFPIC_OK;
 }
 

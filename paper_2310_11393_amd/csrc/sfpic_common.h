@@ -505,14 +505,24 @@ template <typename R>
 size_t push_lds_bytes(const TileGeom &tg, int dims);
 template <typename R>
 size_t push_dyn_lds_bytes(const TileGeom &tg, int dims);
-// Tiled push; particles that drifted out of their tile window are appended
-// to strag (count in *n_strag, reset by the launcher) for the straggler push.
+// Work items of the tiled push (tile, first particle), at most kmax
+// particles each, rebuilt from the sort's start offsets after every sort;
+// items holds push_items_words() words.
+hipError_t launch_build_items(const uint32_t *start, const TileGeom &tg,
+                              uint32_t kmax, uint32_t *items,
+                              uint32_t *n_items, hipStream_t st);
+size_t push_items_words(const TileGeom &tg, int64_t n_slots, uint32_t kmax);
+// Tiled push over the work items; particles that drifted out of their tile
+// window are appended to strag (count in *n_strag, reset by the launcher)
+// for the straggler push.
 template <typename R>
 hipError_t launch_push_tiled(const Fields<R> &f, const Particles<R> &p,
-                             const uint32_t *start, const TileGeom &tg,
-                             int dims, const PushParams &pp,
-                             const IncParams &inc, uint32_t *strag,
-                             uint32_t *n_strag, hipStream_t st);
+                             const uint32_t *start, const uint32_t *items,
+                             const uint32_t *n_items, uint32_t kmax,
+                             int64_t n_slots, const TileGeom &tg, int dims,
+                             const PushParams &pp, const IncParams &inc,
+                             uint32_t *strag, uint32_t *n_strag,
+                             hipStream_t st);
 template <typename R>
 hipError_t launch_push_stragglers(const Fields<R> &f, const Particles<R> &p,
                                   int dims, const PushParams &pp,
@@ -553,6 +563,12 @@ hipError_t launch_particle_sums(const Particles<R> &p, int64_t n,
                                 hipStream_t st);
 template <typename R>
 hipError_t launch_field_sums(const Fields<R> &f, double *acc, hipStream_t st);
+// acc[7] += 1/2 sum over physical nodes of |F_scatt + F_inc|^2 (E at tE, B
+// at tB), each component at its Yee node.
+template <typename R>
+hipError_t launch_em_total(const Fields<R> &f, int dims, int nx, int ny,
+                           double dx, double dy, double tE, double tB,
+                           const IncParams &inc, double *acc, hipStream_t st);
 template <typename R>
 hipError_t launch_deposit_rho(const Particles<R> &p, int64_t n,
                               const uint32_t *n_valid, int dims, double qw,

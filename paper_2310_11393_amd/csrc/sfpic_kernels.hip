@@ -442,6 +442,47 @@ hipError_t launch_field_sums(const Fields<R> &f, double *acc, hipStream_t st) {
   return hipGetLastError();
 }
 
+// Energy of the total field F_inc + F_scatt (Sec. 2) on the physical nodes:
+// 1/2 sum |E_s^n + E_inc(t^n)|^2 + |B_s^{n-1/2} + B_inc(t^{n-1/2})|^2 over the
+// six components, each taken at the node where the Yee grid stores it, with
+// the incident field in FP64.  One thread per node; sum into acc[7].
+template <typename R>
+__global__ void em_total_kernel(Fields<R> f, int dims, int nx, double dx,
+                                double dy, double tE, double tB, IncParams inc,
+                                double *acc) {
+  __shared__ double sh[8];
+  // dual (1) or primal (0) position of Ex Ey Ez Bx By Bz along x and y
+  constexpr int sx[6] = {1, 0, 0, 0, 1, 1}, sy[6] = {0, 1, 0, 1, 0, 1};
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  double e = 0.0;
+  if (i < nx) {
+    const size_t k = (size_t)(dims == 2 ? j + kGuard : 0) * f.pitch + i +
+                     kGuard;
+    const R *src[6] = {f.ex, f.ey, f.ez, f.bx, f.by, f.bz};
+#pragma unroll 1
+    for (int c = 0; c < 6; ++c) {
+      const double x = ((double)i + 0.5 * sx[c]) * dx;
+      const double y = dims == 2 ? ((double)j + 0.5 * sy[c]) * dy : 0.0;
+      double E[3], B[3];
+      incident_field(inc, dims, x, y, c < 3 ? tE : tB, E, B);
+      const double v = (double)src[c][k] + (c < 3 ? E[c] : B[c - 3]);
+      e += 0.5 * v * v;
+    }
+  }
+  e = block_sum(e, sh);
+  if (threadIdx.x == 0) unsafeAtomicAdd(&acc[7], e);
+}
+
+template <typename R>
+hipError_t launch_em_total(const Fields<R> &f, int dims, int nx, int ny,
+                           double dx, double dy, double tE, double tB,
+                           const IncParams &inc, double *acc, hipStream_t st) {
+  dim3 g((nx + 255) / 256, dims == 2 ? ny : 1);
+  em_total_kernel<R><<<g, 256, 0, st>>>(f, dims, nx, dx, dy, tE, tB, inc, acc);
+  return hipGetLastError();
+}
+
 template <typename R>
 __global__ void deposit_rho(Particles<R> p, int64_t n, const uint32_t *n_valid,
                             int dims, double qw, double *rho, int pitch) {
@@ -582,6 +623,10 @@ hipError_t launch_export_particles(const Particles<R> &p, int64_t n, int dims,
                                        double, double, hipStream_t);          \
   template hipError_t launch_field_sums<R>(const Fields<R> &, double *,       \
                                            hipStream_t);                      \
+  template hipError_t launch_em_total<R>(const Fields<R> &, int, int, int,    \
+                                         double, double, double, double,      \
+                                         const IncParams &, double *,         \
+                                         hipStream_t);                        \
   template hipError_t launch_gauss<R>(const Fields<R> &, int, int, int,       \
                                       double, double, const double *,         \
                                       const double *, int, double *,          \

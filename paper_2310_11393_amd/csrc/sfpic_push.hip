@@ -428,25 +428,23 @@ __device__ __forceinline__ bool push_particle(int &ix, int &iy, R &fx, R &fy,
 // ---------------------------------------------------------------------------
 // Tiled push
 // ---------------------------------------------------------------------------
-// One workgroup pushes every particle of one tile; smem holds the windows
-// and the particle chunk (push_lds_bytes).
+// One workgroup pushes the particles pbeg .. pend - 1 of one tile (all of
+// them, or one work item of a dense tile); smem holds the windows and the
+// particle chunk (push_lds_bytes).
 template <typename R, int DIMS>
 __device__ __forceinline__ void push_tile(const Fields<R> &f,
                                           const Particles<R> &p,
-                                          const uint32_t *__restrict__ start,
                                           const TileGeom &tg,
                                           const PushParams &pp,
                                           const IncParams &inc,
                                           uint32_t *strag, uint32_t *n_strag,
-                                          int tile, double *smem) {
+                                          int tile, uint32_t pbeg,
+                                          uint32_t pend, double *smem) {
   using W = typename PT<R>::Word;
   constexpr int kPer = Lay<R>::per, kStride = Lay<R>::stride;
   constexpr int kChunk = Lay<R>::chunk, PADC = Lay<R>::pad;
   const int kSlack = tg.slack, kWinExtra = win_extra(tg.slack);
   const int kWinLo = tg.slack + 2;
-  const uint32_t cpt = tg.cells_per_tile;
-  const uint32_t pbeg = start[(size_t)tile * cpt];
-  const uint32_t pend = start[(size_t)(tile + 1) * cpt];
   if (pbeg >= pend) return;
   const int cx0 = (tile % tg.ntx) * tg.tx;
   const int cy0 = (DIMS == 2) ? (tile / tg.ntx) * tg.ty : 0;
@@ -550,15 +548,75 @@ __device__ __forceinline__ void push_tile(const Fields<R> &f,
   }
 }
 
+// Work items of the tiled push.  After each sort every non-empty tile is cut
+// into items of at most kmax particles, stored as (tile, first particle) in
+// tile order: a dense tile (particles bunched by the beam) is shared by
+// several workgroups instead of leaving one of them running long after the
+// rest, and empty tiles cost nothing.  One workgroup of 1024 threads; each
+// thread takes 8 consecutive tiles per pass.
+__global__ void __launch_bounds__(1024)
+build_items(const uint32_t *__restrict__ start, uint32_t cpt, int ntiles,
+            uint32_t kmax, uint32_t *items, uint32_t *n_items) {
+  __shared__ uint32_t sh[1024];
+  uint32_t carry = 0;
+  for (int t0 = 0; t0 < ntiles; t0 += 8192) {
+    const int tb = t0 + (int)threadIdx.x * 8;
+    uint32_t tot = 0;
+    for (int k = 0; k < 8 && tb + k < ntiles; ++k) {
+      const size_t t = (size_t)(tb + k);
+      const uint32_t c = start[(t + 1) * cpt] - start[t * cpt];
+      tot += (c + kmax - 1) / kmax;
+    }
+    sh[threadIdx.x] = tot;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+      const uint32_t add =
+          threadIdx.x >= (unsigned)o ? sh[threadIdx.x - o] : 0u;
+      __syncthreads();
+      sh[threadIdx.x] += add;
+      __syncthreads();
+    }
+    uint32_t run = carry + sh[threadIdx.x] - tot;
+    for (int k = 0; k < 8 && tb + k < ntiles; ++k) {
+      const size_t t = (size_t)(tb + k);
+      const uint32_t e = start[(t + 1) * cpt];
+      for (uint32_t q = start[t * cpt]; q < e; q += kmax, ++run) {
+        items[2 * (size_t)run] = (uint32_t)t;
+        items[2 * (size_t)run + 1] = q;
+      }
+    }
+    carry += sh[1023];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *n_items = carry;
+}
+
+// Upper bound of the item count: every tile once plus one per kmax particles.
+__host__ __device__ __forceinline__ size_t push_item_capacity(
+    const TileGeom &tg, int64_t n_slots, uint32_t kmax) {
+  return (size_t)tg.ntiles + (size_t)(n_slots / kmax) + 1;
+}
+
 template <typename R, int DIMS>
 __global__ void __launch_bounds__(256, SFPIC_PUSH_MIN_BLOCKS)
 push_tiled(Fields<R> f, Particles<R> p, const uint32_t *__restrict__ start,
-           TileGeom tg, PushParams pp, IncParams inc, uint32_t *strag,
-           uint32_t *n_strag) {
+           const uint32_t *__restrict__ items,
+           const uint32_t *__restrict__ n_items, uint32_t kmax, TileGeom tg,
+           PushParams pp, IncParams inc, uint32_t *strag, uint32_t *n_strag) {
   extern __shared__ double smem[];
-  const int tile = xcd_tile(blockIdx.x, gridDim.x);
-  if (tile >= tg.ntiles) return;
-  push_tile<R, DIMS>(f, p, start, tg, pp, inc, strag, n_strag, tile, smem);
+  // The hardware deals workgroups round-robin to the 8 XCDs; XCD x takes
+  // items x*S .. x*S + S - 1 (S = ceil(n / 8)) in order, so neighbouring
+  // tiles share halo rows in that XCD's L2.  The grid is sized for the most
+  // items a sort can produce; the rest exit at once.
+  const uint32_t n = *n_items, S = (n + 7) >> 3, b = blockIdx.x;
+  if ((b >> 3) >= S) return;
+  const uint32_t it = (b & 7) * S + (b >> 3);
+  if (it >= n) return;
+  const int tile = (int)items[2 * (size_t)it];
+  const uint32_t pbeg = items[2 * (size_t)it + 1];
+  const uint32_t tend = start[(size_t)(tile + 1) * tg.cells_per_tile];
+  push_tile<R, DIMS>(f, p, tg, pp, inc, strag, n_strag, tile, pbeg,
+                     tend - pbeg > kmax ? pbeg + kmax : tend, smem);
 }
 
 // Push of one particle listed by the tiled kernel (drifted more than slack
@@ -625,21 +683,36 @@ size_t push_lds_bytes(const TileGeom &tg, int dims) {
   return push_dyn_lds_bytes<R>(tg, dims);
 }
 
+hipError_t launch_build_items(const uint32_t *start, const TileGeom &tg,
+                              uint32_t kmax, uint32_t *items,
+                              uint32_t *n_items, hipStream_t st) {
+  build_items<<<1, 1024, 0, st>>>(start, tg.cells_per_tile, tg.ntiles, kmax,
+                                  items, n_items);
+  return hipGetLastError();
+}
+
+size_t push_items_words(const TileGeom &tg, int64_t n_slots, uint32_t kmax) {
+  return 2 * push_item_capacity(tg, n_slots, kmax);
+}
+
 template <typename R>
 hipError_t launch_push_tiled(const Fields<R> &f, const Particles<R> &p,
-                             const uint32_t *start, const TileGeom &tg,
-                             int dims, const PushParams &pp,
-                             const IncParams &inc, uint32_t *strag,
-                             uint32_t *n_strag, hipStream_t st) {
-  const unsigned nb = (unsigned)((tg.ntiles + 7) & ~7);
+                             const uint32_t *start, const uint32_t *items,
+                             const uint32_t *n_items, uint32_t kmax,
+                             int64_t n_slots, const TileGeom &tg, int dims,
+                             const PushParams &pp, const IncParams &inc,
+                             uint32_t *strag, uint32_t *n_strag,
+                             hipStream_t st) {
+  const size_t cap = push_item_capacity(tg, n_slots, kmax);
+  const unsigned nb = (unsigned)((cap + 7) & ~(size_t)7);
   const size_t lds = push_dyn_lds_bytes<R>(tg, dims);
   fill_u32<<<1, 64, 0, st>>>(n_strag, 0u, 1);
   if (dims == 1)
-    push_tiled<R, 1><<<nb, 256, lds, st>>>(f, p, start, tg, pp, inc, strag,
-                                           n_strag);
+    push_tiled<R, 1><<<nb, 256, lds, st>>>(f, p, start, items, n_items, kmax,
+                                           tg, pp, inc, strag, n_strag);
   else
-    push_tiled<R, 2><<<nb, 256, lds, st>>>(f, p, start, tg, pp, inc, strag,
-                                           n_strag);
+    push_tiled<R, 2><<<nb, 256, lds, st>>>(f, p, start, items, n_items, kmax,
+                                           tg, pp, inc, strag, n_strag);
   return hipGetLastError();
 }
 
@@ -915,9 +988,11 @@ batch_push_kernel(BatchView<R> v) {
     const PushJob<R> &J = v.pjobs[jb];
     if (v.ms[J.member].steps_left <= 0) continue;
     const PushParams pp = member_params(v, J);
-    push_tile<R, DIMS>(J.f, J.pa[J.cur], J.start, J.tg, pp, J.inc, J.strag,
-                       &v.counters[1 + jb], (int)(item - v.tile_off[jb]),
-                       smem);
+    const int tile = (int)(item - v.tile_off[jb]);
+    const size_t t0 = (size_t)tile * J.tg.cells_per_tile;
+    push_tile<R, DIMS>(J.f, J.pa[J.cur], J.tg, pp, J.inc, J.strag,
+                       &v.counters[1 + jb], tile, J.start[t0],
+                       J.start[t0 + J.tg.cells_per_tile], smem);
   }
 }
 
@@ -1076,6 +1151,7 @@ hipError_t launch_batch_sort(const BatchView<R> &v, int dims, hipStream_t st) {
   template size_t push_dyn_lds_bytes<R>(const TileGeom &, int);              \
   template hipError_t launch_push_tiled<R>(                                  \
       const Fields<R> &, const Particles<R> &, const uint32_t *,             \
+      const uint32_t *, const uint32_t *, uint32_t, int64_t,                 \
       const TileGeom &, int, const PushParams &, const IncParams &,          \
       uint32_t *, uint32_t *, hipStream_t);                                  \
   template hipError_t launch_push_stragglers<R>(                             \

@@ -33,6 +33,9 @@ struct SpeciesState {
   int64_t n = 0;               // slots (capacity)
   uint32_t *n_valid = nullptr; // device: slots in use (live or removed)
   uint32_t *start = nullptr;   // device: cell start offsets (nkeys + 1)
+  // device: work items of the single-sim push (allocated by its first step)
+  uint32_t *items = nullptr, *n_items = nullptr;
+  size_t items_words = 0;
   Particles<double> p64{}, p64_alt{};
   Particles<float> p32{}, p32_alt{};
   // Sort scratch and straggler list of a species other than the first when
@@ -62,6 +65,13 @@ inline Particles<float> &parts_alt<float>(SpeciesState &st) {
 
 }  // namespace sfpic
 
+// Particles per work item of the single-sim push: a tile holding more is
+// split over several workgroups.
+#ifndef SFPIC_ITEM_PARTICLES
+#define SFPIC_ITEM_PARTICLES 8192
+#endif
+constexpr uint32_t kItemParticles = SFPIC_ITEM_PARTICLES;
+
 struct sfpic_sim {
   using SpeciesState = sfpic::SpeciesState;
   using IncParams = sfpic::IncParams;
@@ -84,6 +94,7 @@ struct sfpic_sim {
   SortScratch ss{};
   int sort_every = 8;
   int64_t since_sort = 0;
+  uint32_t item_max = kItemParticles;  // particles per push work item
   uint32_t *strag = nullptr, *n_strag = nullptr;  // straggler list
   double *rho0 = nullptr, *rho = nullptr, *acc = nullptr;
   std::vector<std::pair<void *, size_t>> allocs;

@@ -91,6 +91,8 @@ def test_fp64_batch_members_match_oracle(mode):
         assert r["diag"]["n_alive"] == od["n_alive"]
         assert abs(r["diag"]["w_kin"] - od["w_kin"]) <= 1e-11 * abs(od["w_kin"])
         assert abs(r["diag"]["w_em"] - od["w_em"]) <= 1e-11 * abs(od["w_em"])
+        assert abs(r["diag"]["w_em_total"] - od["w_em_total"]) <= \
+            1e-11 * abs(od["w_em_total"])
         # the member can be stepped on as an ordinary simulation afterwards
     b.close()
 
@@ -220,7 +222,7 @@ def test_server_results_equal_runs_alone():
         ad = alone.diagnostics()
         tol = 1e-11 if w.precision == wl.FP64 else 1e-4
         assert r["diag"]["n_alive"] == ad["n_alive"]
-        for key in ("w_kin", "w_em"):
+        for key in ("w_kin", "w_em", "w_em_total"):
             assert abs(r["diag"][key] - ad[key]) <= tol * abs(ad[key]), key
         if w.grid.dims == 2:
             h, mom = alone.histogram(0, 64, 0.05, 36, 0.0)

@@ -84,6 +84,8 @@ def test_fp64_parity_50_steps(case):
     assert gd["n_alive"] == od["n_alive"]
     assert abs(gd["w_kin"] - od["w_kin"]) <= 1e-11 * abs(od["w_kin"])
     assert abs(gd["w_em"] - od["w_em"]) <= 1e-11 * abs(od["w_em"])
+    assert abs(gd["w_em_total"] - od["w_em_total"]) <= \
+        1e-11 * abs(od["w_em_total"])
     assert gd["gauss_residual"] <= gauss_tol(g, gd, work.grid, 2.2e-16)
     assert gd["nonfinite"] == 0
 
@@ -128,6 +130,11 @@ def test_fp32_form_against_fp64_oracle(case):
     assert dpos <= 1e-5 and du <= 1e-4 * max(1.0, umax), (dpos, du)
     gd = g.diagnostics()
     assert gd["nonfinite"] == 0
+    # |dW| <= |F_inc + F_s| |dF_s|, so the field tolerance bounds the total
+    # energy's relative error by twice itself
+    od = o.diagnostics()
+    assert abs(gd["w_em_total"] - od["w_em_total"]) <= \
+        2 * FP32_FIELD_TOL * od["w_em_total"]
     assert gd["gauss_residual"] <= max(1e-5 * gd["rho_max"],
                                        gauss_tol(g, gd, work.grid, 1.2e-7))
 
@@ -167,12 +174,17 @@ def test_fp64_two_species_parity():
 
 
 def test_empty_and_vacuum_sims():
-    """No species: the scattered field stays exactly zero (Sec. 2 split)."""
+    """No species: the scattered field stays exactly zero (Sec. 2 split) and
+    the total-field energy is the incident field's, as in the oracle."""
     work = _small_lp()
     g = make_gpu(work, [])
     g.step(20)
     for c in ("ex", "ey", "ez", "bx", "by", "bz", "jx", "jy", "jz"):
         assert not np.any(g.read_field(c))
+    o = make_oracle(work, [])
+    o.step(20)
+    wt = o.diagnostics()["w_em_total"]
+    assert wt > 0 and abs(g.diagnostics()["w_em_total"] - wt) <= 1e-12 * wt
     # zero-weight particles move but carry no current
     sp = explicit_species(work)
     sp[0]["weight"] = 0.0
@@ -297,6 +309,7 @@ def test_end_of_run_spectra(case, prec):
     for k in range(1, 5):
         assert abs(mg[k] - mo[k]) <= 0.01 * abs(mo[k]), (k, mg[k], mo[k])
     assert abs(gd["w_kin"] - od["w_kin"]) <= 0.01 * od["w_kin"]
+    assert abs(gd["w_em_total"] - od["w_em_total"]) <= 0.01 * od["w_em_total"]
 
 
 def test_invalid_inputs_are_rejected():
@@ -314,6 +327,35 @@ def test_invalid_inputs_are_rejected():
     with pytest.raises(SfpicError) as e:
         make_gpu(work, sp)
     assert e.value.code == -1
+    with pytest.raises(SfpicError) as e:
+        make_gpu(work, explicit_species(work), item_particles=32)
+    assert e.value.code == -1
+
+
+@pytest.mark.parametrize("item,prec", [(64, wl.FP64), (200, wl.FP64),
+                                       (100, wl.FP32)])
+def test_parity_with_split_tiles(item, prec):
+    """Tiles holding more than `item` particles are pushed by several
+    workgroups (work items), each adding its own current window to the grid:
+    only the summation order changes.  With 8 ppc every 16x16 tile holds
+    2048 particles, so every tile is split (and the ragged last item of a
+    tile is short)."""
+    work = _small_lp(ppc=8, a0=30.0, s=10.0)
+    sp = explicit_species(work)
+    g = make_gpu(work, sp, precision=prec, item_particles=item)
+    o = make_oracle(work, sp)
+    g.step(work.steps)
+    o.step(work.steps)
+    tol = FP64_FIELD_TOL if prec == wl.FP64 else FP32_FIELD_TOL
+    rel, den = field_rel_l2(g, o)
+    _note(f"[items] item {item} prec {prec}: field relative L2 {rel:.3e}")
+    assert den > 0 and rel <= tol, rel
+    jrel, _ = field_rel_l2(g, o, comps=("jx", "jy", "jz"))
+    assert jrel <= tol, jrel
+    dpos, du, umax = particle_errors(g, o)
+    ptol = 1e-12 if prec == wl.FP64 else 1e-5
+    assert dpos <= ptol and du <= 10 * ptol * max(1.0, umax), (dpos, du)
+    assert g.diagnostics()["n_alive"] == o.diagnostics()["n_alive"]
 
 
 # ---------------------------------------------------------------------------
