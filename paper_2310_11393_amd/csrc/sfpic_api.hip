@@ -267,7 +267,10 @@ int setup_tiles(sfpic_sim *s) {
   };
   // drift allowance of the tile window: 1 cell keeps two 16 x 16 FP64
   // workgroups (81.6 KB each) and three FP32 ones per CU (160 KiB LDS)
-  t.slack = 1;
+  // drift allowance: FP64 reads its particles straight from HBM, so its
+  // LDS holds only the windows and a wide one is affordable; the FP32 form
+  // stages particles in LDS and keeps the narrow one (three workgroups/CU)
+  t.slack = s->precision == SFPIC_FP64 ? kSingleSlackF64 : 1;
   if (g.dims == 1) {
     t.tx = s->rt.tile_x > 0 ? s->rt.tile_x : 256;
     t.ty = 1;

@@ -2,17 +2,20 @@
 // (tile-major key) and the tiled push kernel (order-2 gather, incident field
 // at the particle, Boris, Esirkepov deposition; Lytova et al., Sec. 2).
 //
-// Tiled push: one workgroup per tile of tx x ty cells.  The workgroup stages
-// the scattered E and centred B on the tile's node window (the tile plus
-// slack + 2 nodes on every side, see Lay) in LDS, accumulates the tile's
-// current in an FP64 LDS window of the same shape with LDS atomics, and
-// adds that window to the global current once.  Particles are staged
-// through LDS in chunks and processed in transposed order (lane l takes
-// every (4 per)-th particle of the cell-sorted chunk), so the 64 lanes of a
-// wave sit in different cells and their LDS atomics rarely hit the same
-// address.  A particle that has drifted more than `slack` cells out of its
-// tile since the last sort is listed and pushed afterwards by the straggler
-// kernel from global memory.
+// Tiled push: after each sort the non-empty tiles of tx x ty cells are cut
+// into work items of at most item_particles particles, one workgroup each.
+// The workgroup stages the scattered E and centred B on its tile's node
+// window (the tile plus slack + 2 nodes on every side) in LDS, accumulates
+// the current in an FP64 LDS window of the same shape with LDS atomics, and
+// adds that window to the global current once.  The lanes of a wave push
+// particles of different cells, which keeps their LDS atomics off common
+// addresses: in FP64 the sort lays out each tile's particles with cell order
+// running down the 64 columns of each block of 1024 slots and a wave reads
+// and writes a row of 64 consecutive slots straight from HBM; in the FP32
+// form chunks of the cell-sorted range are staged through LDS and taken in
+// transposed order there.  A particle that has drifted more than `slack`
+// cells out of its tile since the last sort is listed and pushed afterwards
+// by the straggler kernel from global memory.
 //
 // Two precisions of the same kernels: FP64 (positions as doubles in cell
 // units) and the FP32 form (packed integer cell plus float offsets, float
@@ -22,32 +25,11 @@
 
 namespace sfpic {
 
-// Per-precision layout of the push workgroup's particle chunk in LDS: `per`
-// particles per thread.  In the transposed order lane l of wave w takes
-// chunk slots l*stride + w*per + j (stride = 4 per), and one pad word every
-// stride words spreads those lanes over the banks.  Large chunks keep the
-// 64 lanes of a wave in many different cells (fewer same-address LDS
-// atomics at high particle counts per cell).
-#ifndef SFPIC_CHUNK_PER_F64
-#define SFPIC_CHUNK_PER_F64 4
-#endif
-#ifndef SFPIC_CHUNK_PER_F32
-#define SFPIC_CHUNK_PER_F32 4
-#endif
 // Minimum resident workgroups per CU requested from the compiler for the
 // push kernels (bounds their register use).
 #ifndef SFPIC_PUSH_MIN_BLOCKS
 #define SFPIC_PUSH_MIN_BLOCKS 2
 #endif
-template <typename R>
-struct Lay {
-  static constexpr int per = sizeof(R) == 8 ? SFPIC_CHUNK_PER_F64
-                                            : SFPIC_CHUNK_PER_F32;
-  static constexpr int chunk = 256 * per;
-  static constexpr int stride = 4 * per;
-  static constexpr int pad = chunk + chunk / stride;  // padded chunk length
-};
-
 // The LDS field window of a tile with drift allowance `slack` (TileGeom):
 // a particle is pushed by its tile's workgroup while its cell is at most
 // slack cells outside the tile, and its order-2 gather and deposit reach 2
@@ -58,21 +40,23 @@ __host__ __device__ __forceinline__ int win_extra(int slack) {
   return 2 * slack + 5;
 }
 
+// LDS chunk of the staged particle path (the FP32 form, see PT): 1024
+// particles per chunk, 4 per thread; lane l of wave w takes chunk slots
+// l*16 + w*4 + j, so the 64 lanes of a wave sit in different cells of the
+// cell-sorted chunk, and one pad word every 16 spreads them over the banks.
+struct Chunk {
+  static constexpr int per = 4;
+  static constexpr int size = 256 * per;
+  static constexpr int stride = 4 * per;
+  static constexpr int pad = size + size / stride;  // padded length
+};
+__device__ __forceinline__ int chunk_slot(int k) {
+  return k + k / Chunk::stride;
+}
+
 __global__ void fill_u32(uint32_t *a, uint32_t v, size_t n) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) a[i] = v;
-}
-
-template <typename R>
-__device__ __forceinline__ int chunk_slot(int k) {
-  return k + k / Lay<R>::stride;
-}
-
-// Workgroup -> tile: the hardware deals workgroups round-robin to the 8 XCDs;
-// giving each XCD a contiguous band of tiles keeps the halo rows that
-// neighbouring tiles share in that XCD's L2.
-__device__ __forceinline__ int xcd_tile(int b, int nb) {
-  return (b & 7) * (nb >> 3) + (b >> 3);
 }
 
 // Largest value below 1 in precision R (offsets live in [0, 1)).
@@ -88,68 +72,21 @@ __device__ __forceinline__ float one_below<float>() {
 }
 
 // ---------------------------------------------------------------------------
-// Particle storage per precision: global SoA arrays and the LDS chunk.
+// Particle storage per precision: load and store of one slot as (cell,
+// offset) per axis and u.  kStaged selects the particle path of the push:
+//   FP64 (kStaged false): the sort transposes each block of 1024 slots (see
+//     block_slot) and the push reads and writes its rows straight from HBM;
+//   FP32 form (kStaged true): the sort keeps plain cell order and the push
+//     stages chunks through LDS and transposes there (its particles are
+//     small, so staging is cheap, and a transposing sort of 28-byte records
+//     costs more than it saves).
 // ---------------------------------------------------------------------------
 template <typename R>
 struct PT;
 
 template <>
 struct PT<double> {
-  using Word = double;
-  static constexpr int kWords = 5;  // px py ux uy uz
-  static constexpr int kDwords = 2;  // dwords per array element
-  static constexpr int kYArray = 1;  // array unused in 1D
-  __device__ static const uint32_t *words(const Particles<double> &p, int a) {
-    const double *q = a == 0 ? p.px : a == 1 ? p.py : a == 2 ? p.ux
-                    : a == 3 ? p.uy : p.uz;
-    return (const uint32_t *)q;
-  }
-  // global slot g <-> LDS slot s; arrays st words apart in LDS
-  __device__ static void g2l(const Particles<double> &p, uint32_t g, Word *sp,
-                             int s, int st, int dims) {
-    sp[s] = p.px[g];
-    if (dims == 2) sp[st + s] = p.py[g];
-    sp[2 * st + s] = p.ux[g];
-    sp[3 * st + s] = p.uy[g];
-    sp[4 * st + s] = p.uz[g];
-  }
-  __device__ static void l2g(const Particles<double> &p, uint32_t g,
-                             const Word *sp, int s, int st, int dims) {
-    p.px[g] = sp[s];
-    if (dims == 2) p.py[g] = sp[st + s];
-    p.ux[g] = sp[2 * st + s];
-    p.uy[g] = sp[3 * st + s];
-    p.uz[g] = sp[4 * st + s];
-  }
-  // Unpack LDS slot s (stride st between arrays); false if removed.
-  __device__ static bool unpack(const Word *sp, int s, int st, int dims,
-                                int &ix, int &iy, double &fx, double &fy,
-                                double u[3]) {
-    const double xi = sp[s];
-    if (xi < -1.0) return false;
-    ix = (int)floor(xi);
-    fx = xi - ix;
-    iy = 0;
-    fy = 0.0;
-    if (dims == 2) {
-      const double yi = sp[st + s];
-      iy = (int)floor(yi);
-      fy = yi - iy;
-    }
-    u[0] = sp[2 * st + s];
-    u[1] = sp[3 * st + s];
-    u[2] = sp[4 * st + s];
-    return true;
-  }
-  __device__ static void pack(Word *sp, int s, int st, int dims, bool alive,
-                              int ix, int iy, double fx, double fy,
-                              const double u[3]) {
-    sp[s] = alive ? (double)ix + fx : kDeadPos;
-    if (dims == 2) sp[st + s] = (double)iy + fy;
-    sp[2 * st + s] = u[0];
-    sp[3 * st + s] = u[1];
-    sp[4 * st + s] = u[2];
-  }
+  static constexpr bool kStaged = false;
   __device__ static bool load_global(const Particles<double> &p, uint32_t g,
                                      int dims, int &ix, int &iy, double &fx,
                                      double &fy, double u[3]) {
@@ -183,16 +120,10 @@ struct PT<double> {
 
 template <>
 struct PT<float> {
+  static constexpr bool kStaged = true;
   using Word = uint32_t;
   static constexpr int kWords = 6;  // cell ox oy ux uy uz
-  static constexpr int kDwords = 1;
-  static constexpr int kYArray = 2;
-  __device__ static const uint32_t *words(const Particles<float> &p, int a) {
-    if (a == 0) return p.cell;
-    const float *q = a == 1 ? p.ox : a == 2 ? p.oy : a == 3 ? p.ux
-                   : a == 4 ? p.uy : p.uz;
-    return (const uint32_t *)q;
-  }
+  // global slot g <-> LDS slot s; arrays st words apart in LDS
   __device__ static void g2l(const Particles<float> &p, uint32_t g, Word *sp,
                              int s, int st, int dims) {
     sp[s] = p.cell[g];
@@ -211,6 +142,7 @@ struct PT<float> {
     p.uy[g] = __uint_as_float(sp[4 * st + s]);
     p.uz[g] = __uint_as_float(sp[5 * st + s]);
   }
+  // Unpack LDS slot s (stride st between arrays); false if removed.
   __device__ static bool unpack(const Word *sp, int s, int st, int dims,
                                 int &ix, int &iy, float &fx, float &fy,
                                 float u[3]) {
@@ -429,8 +361,8 @@ __device__ __forceinline__ bool push_particle(int &ix, int &iy, R &fx, R &fy,
 // Tiled push
 // ---------------------------------------------------------------------------
 // One workgroup pushes the particles pbeg .. pend - 1 of one tile (all of
-// them, or one work item of a dense tile); smem holds the windows and the
-// particle chunk (push_lds_bytes).
+// them, or one work item of a dense tile); smem holds the field and current
+// windows and, on the staged path, the particle chunk (push_lds_bytes).
 template <typename R, int DIMS>
 __device__ __forceinline__ void push_tile(const Fields<R> &f,
                                           const Particles<R> &p,
@@ -440,9 +372,6 @@ __device__ __forceinline__ void push_tile(const Fields<R> &f,
                                           uint32_t *strag, uint32_t *n_strag,
                                           int tile, uint32_t pbeg,
                                           uint32_t pend, double *smem) {
-  using W = typename PT<R>::Word;
-  constexpr int kPer = Lay<R>::per, kStride = Lay<R>::stride;
-  constexpr int kChunk = Lay<R>::chunk, PADC = Lay<R>::pad;
   const int kSlack = tg.slack, kWinExtra = win_extra(tg.slack);
   const int kWinLo = tg.slack + 2;
   if (pbeg >= pend) return;
@@ -493,47 +422,72 @@ __device__ __forceinline__ void push_tile(const Fields<R> &f,
     B[2] = gather_plane<R, DIMS>(sf + 5 * WN, WX, bxd, byd, wxd, wyd);
   };
 
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  // push the particle in LDS slot s (arrays st words apart) of the chunk
-  // starting at global slot c0; idx is its position in the chunk
-  auto process = [&](W *cp, int st, int s, uint32_t c0, int idx) {
-    int ix, iy;
-    R fx, fy, u[3];
-    if (!PT<R>::unpack(cp, s, st, DIMS, ix, iy, fx, fy, u)) return;
-    // particles more than kSlack cells outside the tile go to the straggler
-    // list and are pushed from global memory after this kernel
+  // One particle at global slot g: a particle more than kSlack cells
+  // outside the tile goes to the straggler list (pushed from global memory
+  // after this kernel) and returns false with its state untouched;
+  // otherwise it is pushed and `alive` tells whether it stays in the box.
+  auto push_one = [&](int &ix, int &iy, R &fx, R &fy, R u[3], uint32_t g,
+                      bool &alive) -> bool {
     if (!(ix >= cx0 - kSlack && ix < cx0 + tg.tx + kSlack &&
           (DIMS == 1 ||
            (iy >= cy0 - kSlack && iy < cy0 + tg.ty + kSlack)))) {
-      strag[atomicAdd(n_strag, 1u)] = c0 + idx;
-      return;
+      strag[atomicAdd(n_strag, 1u)] = g;
+      return false;
     }
     const int ipx0 = ix + (fx >= R(0.5));
     const int ipy0 = (DIMS == 2) ? iy + (fy >= R(0.5)) : 0;
     // window index of node ipx - 2, the first deposit node
     const int bx = ipx0 - cx0 + kWinLo - 2;
     const int by = (DIMS == 2) ? ipy0 - cy0 + kWinLo - 2 : 0;
-    const bool alive = push_particle<R, DIMS>(
+    alive = push_particle<R, DIMS>(
         ix, iy, fx, fy, u, pp, inc, gather, [&](int c, int a, int b, R v) {
           atomicAdd(&sj[c * WN + (by + b) * WX + bx + a], (double)v);
         });
-    PT<R>::pack(cp, s, st, DIMS, alive, ix, iy, fx, fy, u);
+    return true;
   };
-  W *sp = (W *)(sf + 6 * WN);  // particle chunk after the windows
-  for (uint32_t c0 = pbeg; c0 < pend; c0 += kChunk) {
-    const int cn = (int)min((uint32_t)kChunk, pend - c0);
-    for (int k = threadIdx.x; k < cn; k += blockDim.x)
-      PT<R>::g2l(p, c0 + k, sp, chunk_slot<R>(k), PADC, DIMS);
-    __syncthreads();
+  if constexpr (!PT<R>::kStaged) {
+    // Straight from HBM: thread t pushes slots pbeg + t, pbeg + t + 256, ...;
+    // a wave's 64 lanes read and write 64 consecutive slots, which the sort
+    // laid out so that they belong to different cells.
 #pragma unroll 1
-    for (int j = 0; j < kPer; ++j) {
-      const int idx = lane * kStride + wv * kPer + j;
-      if (idx < cn) process(sp, PADC, chunk_slot<R>(idx), c0, idx);
+    for (uint32_t g = pbeg + threadIdx.x; g < pend; g += blockDim.x) {
+      int ix, iy;
+      R fx, fy, u[3];
+      bool alive;
+      if (!PT<R>::load_global(p, g, DIMS, ix, iy, fx, fy, u)) continue;
+      if (push_one(ix, iy, fx, fy, u, g, alive))
+        PT<R>::store_global(p, g, DIMS, alive, ix, iy, fx, fy, u);
     }
     __syncthreads();
-    for (int k = threadIdx.x; k < cn; k += blockDim.x)
-      PT<R>::l2g(p, c0 + k, sp, chunk_slot<R>(k), PADC, DIMS);
-    __syncthreads();
+  } else {
+    // Staged: chunks of the cell-sorted range through LDS, pushed in the
+    // transposed order of Chunk.
+    using W = typename PT<R>::Word;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    W *sp = (W *)(sf + 6 * WN);  // particle chunk after the windows
+    for (uint32_t c0 = pbeg; c0 < pend; c0 += Chunk::size) {
+      const int cn = (int)min((uint32_t)Chunk::size, pend - c0);
+      for (int k = threadIdx.x; k < cn; k += blockDim.x)
+        PT<R>::g2l(p, c0 + k, sp, chunk_slot(k), Chunk::pad, DIMS);
+      __syncthreads();
+#pragma unroll 1
+      for (int j = 0; j < Chunk::per; ++j) {
+        const int idx = lane * Chunk::stride + wv * Chunk::per + j;
+        if (idx >= cn) continue;
+        const int sl = chunk_slot(idx);
+        int ix, iy;
+        R fx, fy, u[3];
+        bool alive;
+        if (!PT<R>::unpack(sp, sl, Chunk::pad, DIMS, ix, iy, fx, fy, u))
+          continue;
+        if (push_one(ix, iy, fx, fy, u, c0 + idx, alive))
+          PT<R>::pack(sp, sl, Chunk::pad, DIMS, alive, ix, iy, fx, fy, u);
+      }
+      __syncthreads();
+      for (int k = threadIdx.x; k < cn; k += blockDim.x)
+        PT<R>::l2g(p, c0 + k, sp, chunk_slot(k), Chunk::pad, DIMS);
+      __syncthreads();
+    }
   }
   // add the tile's current window to the grid
   for (int k = threadIdx.x; k < WN; k += blockDim.x) {
@@ -671,9 +625,11 @@ template <typename R>
 size_t push_dyn_lds_bytes(const TileGeom &tg, int dims) {
   const int WX = tg.tx + win_extra(tg.slack);
   const int WY = (dims == 2) ? tg.ty + win_extra(tg.slack) : 1;
-  return (size_t)3 * WX * WY * sizeof(double) +
-         (size_t)6 * WX * WY * sizeof(R) +
-         (size_t)PT<R>::kWords * Lay<R>::pad * sizeof(typename PT<R>::Word);
+  size_t b = (size_t)3 * WX * WY * sizeof(double) +
+             (size_t)6 * WX * WY * sizeof(R);
+  if constexpr (PT<R>::kStaged)
+    b += (size_t)PT<R>::kWords * Chunk::pad * sizeof(typename PT<R>::Word);
+  return b;
 }
 
 // All LDS of the push workgroup (it has no static LDS, so this equals the
@@ -739,16 +695,19 @@ __device__ __forceinline__ uint32_t cell_key(int ix, int iy,
          (uint32_t)((iy - ty * tg.ty) * tg.tx + (ix - tx * tg.tx));
 }
 
-// Ranks within a cell come from atomics on the cell counters.  Particles
-// arrive cell-sorted, so the lanes of a wave share few keys: one leader lane
-// per distinct key adds the group size and hands out consecutive ranks.
+// Ranks within a cell come from atomics on the cell counters.  A wave whose
+// lanes share keys (particles in cell order, as placed at creation) elects
+// one leader lane per distinct key, which adds the group size and hands out
+// consecutive ranks; after a few such rounds the lanes still waiting hold
+// mostly distinct keys (the sorted layout puts a wave's lanes in different
+// cells) and take their ranks with one atomic each.
 __device__ __forceinline__ uint32_t wave_aggregated_rank(bool active,
                                                          uint32_t k,
                                                          uint32_t *counts) {
   const int lane = __lane_id();
   uint64_t pending = __ballot(active);
   uint32_t r = 0;
-  while (pending) {
+  for (int round = 0; round < 4 && pending; ++round) {
     const int leader = __ffsll((unsigned long long)pending) - 1;
     const uint32_t kl = __shfl(k, leader, 64);
     const bool mine = active && k == kl;
@@ -759,6 +718,7 @@ __device__ __forceinline__ uint32_t wave_aggregated_rank(bool active,
     if (mine) r = base + (uint32_t)__popcll(same & ((1ull << lane) - 1ull));
     pending &= ~same;
   }
+  if ((pending >> lane) & 1ull) r = atomicAdd(&counts[k], 1u);
   return r;
 }
 
@@ -821,6 +781,30 @@ __device__ __forceinline__ void move_particle(const Particles<float> &src,
   dst.id[d] = src.id[i];
 }
 
+// Slot of the particle of rank rb within a block of m <= 1024 slots: the
+// block is a row-major array of 64 columns (one per lane of the push's
+// waves) whose ranks run down the columns, column c holding q + 1 ranks if
+// c < r and q otherwise (m = 64 q + r).  A wave that pushes one row then
+// has its lanes q or q + 1 ranks apart in cell order, in different cells,
+// so their LDS current atomics rarely meet, while its loads and stores of
+// the row stay contiguous.
+__device__ __forceinline__ uint32_t block_slot(uint32_t rb, uint32_t m) {
+  const uint32_t q = m >> 6, r = m & 63u;
+  uint32_t c, row;
+  if (rb < r * (q + 1)) {
+    c = rb / (q + 1);
+    row = rb - c * (q + 1);
+  } else {
+    const uint32_t x = rb - r * (q + 1);
+    c = r + x / q;
+    row = x - (c - r) * q;
+  }
+  return row * 64 + c;
+}
+
+// Scatter of slot i to its sorted place: tile-major, cell order within the
+// tile; for the unstaged (FP64) path transposed within each block of 1024
+// slots from the tile start.
 template <typename R>
 __device__ __forceinline__ void scatter_at(const Particles<R> &src,
                                            const Particles<R> &dst,
@@ -829,11 +813,20 @@ __device__ __forceinline__ void scatter_at(const Particles<R> &src,
                                            const uint32_t *__restrict__ key,
                                            const uint32_t *__restrict__ rank,
                                            const uint32_t *__restrict__ start,
-                                           uint32_t nkeys) {
+                                           uint32_t nkeys, uint32_t cpt) {
   if (i >= n_slots) return;
   const uint32_t k = key[i];
   if (k >= nkeys) return;
-  move_particle(src, dst, i, start[k] + rank[i], dims);
+  if constexpr (PT<R>::kStaged) {
+    move_particle(src, dst, i, start[k] + rank[i], dims);
+  } else {
+    const size_t tk = (size_t)(k / cpt) * cpt;
+    const uint32_t t0 = start[tk], tn = start[tk + cpt] - t0;
+    const uint32_t rt = start[k] + rank[i] - t0;  // rank within the tile
+    const uint32_t b0 = rt & ~1023u;
+    const uint32_t m = tn - b0 < 1024u ? tn - b0 : 1024u;
+    move_particle(src, dst, i, t0 + b0 + block_slot(rt - b0, m), dims);
+  }
 }
 
 template <typename R>
@@ -842,9 +835,9 @@ __global__ void sort_scatter(Particles<R> src, Particles<R> dst,
                              const uint32_t *__restrict__ key,
                              const uint32_t *__restrict__ rank,
                              const uint32_t *__restrict__ start,
-                             uint32_t nkeys) {
+                             uint32_t nkeys, uint32_t cpt) {
   scatter_at<R>(src, dst, blockIdx.x * blockDim.x + threadIdx.x, n_slots,
-                dims, key, rank, start, nkeys);
+                dims, key, rank, start, nkeys, cpt);
 }
 
 // Exclusive scan of block lb of a 1024-element segment (256 threads x 4);
@@ -947,7 +940,8 @@ hipError_t launch_sort(const Particles<R> &src, const Particles<R> &dst,
   scan_add<<<nb, 256, 0, st>>>(start, s.block_sums, nk1);
   if (n_slots > 0)
     sort_scatter<R><<<(n_slots + 255) / 256, 256, 0, st>>>(
-        src, dst, n_slots, dims, s.key, s.rank, start, tg.nkeys);
+        src, dst, n_slots, dims, s.key, s.rank, start, tg.nkeys,
+        tg.cells_per_tile);
   set_valid<<<1, 1, 0, st>>>(n_valid, start, tg.nkeys);
   return hipGetLastError();
 }
@@ -1116,7 +1110,7 @@ __global__ void __launch_bounds__(256) batch_sort_scatter(BatchView<R> v,
   SFPIC_FOR_DUE(v, J, (J->n_slots + 255) / 256, lb) {
     scatter_at<R>(J->pa[J->cur], J->pa[J->cur ^ 1], lb * 256 + threadIdx.x,
                   J->n_slots, dims, J->ss.key, J->ss.rank, J->start,
-                  J->tg.nkeys);
+                  J->tg.nkeys, J->tg.cells_per_tile);
   }
 }
 
