@@ -87,6 +87,31 @@ struct PT;
 template <>
 struct PT<double> {
   static constexpr bool kStaged = false;
+  // Raw words of one slot, loaded ahead of their use, and their decoding
+  // (false if the particle was removed).
+  struct Raw {
+    double x, y, ux, uy, uz;
+  };
+  __device__ static Raw fetch(const Particles<double> &p, uint32_t g,
+                              int dims) {
+    return Raw{p.px[g], dims == 2 ? p.py[g] : 0.0, p.ux[g], p.uy[g], p.uz[g]};
+  }
+  __device__ static bool decode(const Raw &r, int dims, int &ix, int &iy,
+                                double &fx, double &fy, double u[3]) {
+    if (r.x < -1.0) return false;
+    ix = (int)floor(r.x);
+    fx = r.x - ix;
+    iy = 0;
+    fy = 0.0;
+    if (dims == 2) {
+      iy = (int)floor(r.y);
+      fy = r.y - iy;
+    }
+    u[0] = r.ux;
+    u[1] = r.uy;
+    u[2] = r.uz;
+    return true;
+  }
   __device__ static bool load_global(const Particles<double> &p, uint32_t g,
                                      int dims, int &ix, int &iy, double &fx,
                                      double &fy, double u[3]) {
@@ -448,15 +473,25 @@ __device__ __forceinline__ void push_tile(const Fields<R> &f,
   if constexpr (!PT<R>::kStaged) {
     // Straight from HBM: thread t pushes slots pbeg + t, pbeg + t + 256, ...;
     // a wave's 64 lanes read and write 64 consecutive slots, which the sort
-    // laid out so that they belong to different cells.
+    // laid out so that they belong to different cells.  The next slot's
+    // words are loaded before the current particle is pushed, so their HBM
+    // latency hides behind its arithmetic.
+    using Raw = typename PT<R>::Raw;
+    uint32_t g = pbeg + threadIdx.x;
+    Raw next{};
+    if (g < pend) next = PT<R>::fetch(p, g, DIMS);
 #pragma unroll 1
-    for (uint32_t g = pbeg + threadIdx.x; g < pend; g += blockDim.x) {
+    while (g < pend) {
+      const Raw cur = next;
+      const uint32_t gn = g + blockDim.x;
+      if (gn < pend) next = PT<R>::fetch(p, gn, DIMS);
       int ix, iy;
       R fx, fy, u[3];
       bool alive;
-      if (!PT<R>::load_global(p, g, DIMS, ix, iy, fx, fy, u)) continue;
-      if (push_one(ix, iy, fx, fy, u, g, alive))
+      if (PT<R>::decode(cur, DIMS, ix, iy, fx, fy, u) &&
+          push_one(ix, iy, fx, fy, u, g, alive))
         PT<R>::store_global(p, g, DIMS, alive, ix, iy, fx, fy, u);
+      g = gn;
     }
     __syncthreads();
   } else {
