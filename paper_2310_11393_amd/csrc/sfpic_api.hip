@@ -270,7 +270,7 @@ int setup_tiles(sfpic_sim *s) {
   // drift allowance: FP64 reads its particles straight from HBM, so its
   // LDS holds only the windows and a wide one is affordable; the FP32 form
   // stages particles in LDS and keeps the narrow one (three workgroups/CU)
-  t.slack = s->precision == SFPIC_FP64 ? kSingleSlackF64 : 1;
+  t.slack = s->precision == SFPIC_FP64 ? kSingleSlackF64 : kSingleSlackF32;
   if (g.dims == 1) {
     t.tx = s->rt.tile_x > 0 ? s->rt.tile_x : 256;
     t.ty = 1;

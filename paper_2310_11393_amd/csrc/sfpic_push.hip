@@ -871,8 +871,15 @@ __global__ void sort_scatter(Particles<R> src, Particles<R> dst,
                              const uint32_t *__restrict__ rank,
                              const uint32_t *__restrict__ start,
                              uint32_t nkeys, uint32_t cpt) {
-  scatter_at<R>(src, dst, blockIdx.x * blockDim.x + threadIdx.x, n_slots,
-                dims, key, rank, start, nkeys, cpt);
+  // The hardware deals workgroups round-robin to the 8 XCDs.  XCD x takes a
+  // contiguous band of source blocks, so the particles of one tile, which
+  // land in the same destination lines, are written through one L2 and
+  // merged there rather than leaving 8 partial copies of each line (the
+  // grid is a multiple of 8 blocks).
+  const uint32_t b = blockIdx.x, band = gridDim.x >> 3;
+  const uint32_t lb = (b & 7) * band + (b >> 3);
+  scatter_at<R>(src, dst, lb * blockDim.x + threadIdx.x, n_slots, dims, key,
+                rank, start, nkeys, cpt);
 }
 
 // Exclusive scan of block lb of a 1024-element segment (256 threads x 4);
@@ -974,7 +981,7 @@ hipError_t launch_sort(const Particles<R> &src, const Particles<R> &dst,
   scan_sums<<<1, 1024, 0, st>>>(s.block_sums, nb);
   scan_add<<<nb, 256, 0, st>>>(start, s.block_sums, nk1);
   if (n_slots > 0)
-    sort_scatter<R><<<(n_slots + 255) / 256, 256, 0, st>>>(
+    sort_scatter<R><<<((n_slots + 255) / 256 + 7) & ~7u, 256, 0, st>>>(
         src, dst, n_slots, dims, s.key, s.rank, start, tg.nkeys,
         tg.cells_per_tile);
   set_valid<<<1, 1, 0, st>>>(n_valid, start, tg.nkeys);

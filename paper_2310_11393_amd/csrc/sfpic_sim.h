@@ -76,6 +76,10 @@ constexpr uint32_t kItemParticles = SFPIC_ITEM_PARTICLES;
 #define SFPIC_SLACK_F64 3
 #endif
 constexpr int kSingleSlackF64 = SFPIC_SLACK_F64;
+#ifndef SFPIC_SLACK_F32
+#define SFPIC_SLACK_F32 1
+#endif
+constexpr int kSingleSlackF32 = SFPIC_SLACK_F32;
 
 struct sfpic_sim {
   using SpeciesState = sfpic::SpeciesState;
