@@ -9,7 +9,10 @@
  *   2. centred  Bbar^n = (B^{n-1/2} + B^{n+1/2}) / 2
  *   3. gather   E^n, Bbar^n at x^n with order-2 B-spline weights
  *   4. add the incident field F_inc(x^n, t^n) (Sec. 2: scattered field
- *      interpolated and added to the incident field at the macro-particle)
+ *      interpolated and added to the incident field at the macro-particle);
+ *      with inc.on_nodes instead F_inc sampled on the Yee nodes at t^n is
+ *      added to the arrays gathered in step 3 (the field superimposed on the
+ *      grid fields, as the paper's implementation does, Sec. 2)
  *   5. Boris rotation u^{n-1/2} -> u^{n+1/2}                   (Sec. 2 pusher)
  *   6. x^{n+1} = x^n + dt u^{n+1/2} / gamma  (in-plane components)
  *   7. Esirkepov charge-conserving current J^{n+1/2}           (Sec. 2)
@@ -591,18 +594,43 @@ static void ampere(orc_sim *S) {
 /* Step                                                                     */
 /* ------------------------------------------------------------------------ */
 
+/* Incident field sampled where the Yee grid stores each component, at time t
+ * (the prescribed-field reading of Sec. 2): tot[c] = src[c] + F_inc,c at the
+ * node of every array element, guard nodes included. */
+static void add_incident_on_nodes(const orc_sim *S, double *const src[6],
+                                  double t, double *tot[6]) {
+  const int dims = S->g.dims;
+  for (int c = 0; c < 6; ++c)
+    for (long ja = 0; ja < S->NY; ++ja)
+      for (long ia = 0; ia < S->NX; ++ia) {
+        double x = ((double)(ia - G) + 0.5 * STAG_X[c]) * S->g.dx;
+        double y = (dims == 2) ? ((double)(ja - G) + 0.5 * STAG_Y[c]) * S->g.dy
+                               : 0.0;
+        double E[3], B[3];
+        orc_incident_eval(&S->inc, dims, x, y, t, E, B);
+        AT(tot[c], ia, ja) = AT(src[c], ia, ja) + (c < 3 ? E[c] : B[c - 3]);
+      }
+}
+
 void orc_step(orc_sim *S, long nsteps) {
   const double dt = S->g.dt;
   const int dims = S->g.dims;
   const double xmax = S->g.nx * S->g.dx;
   const double ymax = (dims == 2) ? S->g.ny * S->g.dy : 0.0;
   const long ncell = S->NX * S->NY;
+  double *tot[6] = {0};
+  if (S->inc.on_nodes)
+    for (int c = 0; c < 6; ++c) tot[c] = (double *)malloc((size_t)ncell * 8);
   for (long k = 0; k < nsteps; ++k) {
     const double t = (double)S->step * dt;
     faraday(S);
     for (int c = 0; c < 3; ++c) memset(S->f[ORC_JX + c], 0, (size_t)ncell * 8);
     double *src[6] = {S->f[ORC_EX], S->f[ORC_EY], S->f[ORC_EZ],
                       S->bbar[0], S->bbar[1], S->bbar[2]};
+    if (S->inc.on_nodes) {
+      add_incident_on_nodes(S, src, t, tot);
+      for (int c = 0; c < 6; ++c) src[c] = tot[c];
+    }
     for (int s = 0; s < S->nsp; ++s) {
       orc_species *p = &S->sp[s];
       const double qm = p->q / p->m;
@@ -611,10 +639,12 @@ void orc_step(orc_sim *S, long nsteps) {
         double x0 = p->x[i], y0 = p->y[i];
         double E[3], B[3], Ei[3], Bi[3];
         gather6(S, src, x0, y0, E, B);
-        orc_incident_eval(&S->inc, dims, x0, y0, t, Ei, Bi);
-        for (int c = 0; c < 3; ++c) {
-          E[c] += Ei[c];
-          B[c] += Bi[c];
+        if (!S->inc.on_nodes) {
+          orc_incident_eval(&S->inc, dims, x0, y0, t, Ei, Bi);
+          for (int c = 0; c < 3; ++c) {
+            E[c] += Ei[c];
+            B[c] += Bi[c];
+          }
         }
         double u[3] = {p->ux[i], p->uy[i], p->uz[i]};
         orc_boris(qm, dt, u, E, B);
@@ -634,6 +664,7 @@ void orc_step(orc_sim *S, long nsteps) {
     ampere(S);
     S->step++;
   }
+  for (int c = 0; c < 6; ++c) free(tot[c]);
 }
 
 /* ------------------------------------------------------------------------ */

@@ -56,6 +56,8 @@ typedef struct {
   double phi0;    /* April: constant phase                                    */
   double x_focus, y_focus, t_focus; /* April: focus (build axes), focal time */
   double norm;    /* April: field scale, set by orc_incident_setup            */
+  int on_nodes;   /* 0: evaluated at each particle; 1: sampled on the Yee
+                     nodes at t^n and gathered with the scattered field     */
 } orc_incident;
 
 typedef struct {

@@ -116,6 +116,9 @@ class Incident:
     x_focus: float = 0.0
     y_focus: float = 0.0
     t_focus: float = 0.0
+    # 0: closed form at each particle; 1: sampled on the Yee nodes at t^n
+    # and gathered with the scattered field
+    on_nodes: int = 0
 
 
 @dataclasses.dataclass
