@@ -146,6 +146,60 @@ def fp32_vs_fp64(steps=200, err_steps=50):
     return res
 
 
+def incident_on_nodes(ref, steps, warmup):
+    """The main workload with the incident field sampled on the Yee nodes at
+    t^n and gathered with the scattered field (sfpic_incident.on_nodes)
+    instead of evaluated in closed form at each particle: throughput, and
+    how far its fields and energies end from the main run's after the same
+    steps (the price of the O(dx^2) sampling)."""
+    import numpy as np
+    import torch
+    from paper_2310_11393_amd import workloads as wl
+    from paper_2310_11393_amd.binding import Simulation
+    work = wl.lp_2048x1024()
+    work.incident.on_nodes = 1
+    log("incident on nodes: creating the same particles")
+    sim = Simulation.from_workload(work)
+    sim.step(warmup)
+    sim.sync()
+    n0 = sim.particle_count()
+    stream = torch.cuda.current_stream()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    done, chunk = 0, max(1, steps // 5)
+    while done < steps:
+        k = min(chunk, steps - done)
+        sim.step(k)
+        done += k
+        sim.sync()
+        log(f"incident on nodes: {done}/{steps} steps")
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    n1 = sim.particle_count()
+    diag = sim.diagnostics()
+    num = den = 0.0
+    for c, a in zip(("ex", "ey", "ez", "bx", "by", "bz"), ref["fields"]):
+        b = sim.read_field(c)
+        num += float(np.sum((b - a) ** 2))
+        den += float(np.sum(a ** 2))
+    sim.close()
+    rd = ref["diag"]
+    res = {"workload": "the main workload with on_nodes = 1",
+           "steps": steps,
+           "pushes_per_s": steps * 0.5 * (n0 + n1) / (ms * 1e-3),
+           "ms_per_step": ms / steps,
+           "field_rel_l2_vs_main": (num / den) ** 0.5 if den > 0 else None,
+           "w_kin_rel_vs_main": (diag["w_kin"] - rd["w_kin"]) / rd["w_kin"],
+           "w_em_total_rel_vs_main": ((diag["w_em_total"] - rd["w_em_total"])
+                                      / rd["w_em_total"])}
+    log(f"incident on nodes: {res['pushes_per_s'] / 1e9:.2f} G pushes/s, "
+        f"fields {res['field_rel_l2_vs_main']:.3e} from the main run")
+    return res
+
+
 def batched_sweep(members=256, steps=400):
     """The laser-focus / density sweep as one batch: `members` FP32 2D3V
     simulations (grid side 256..1024, 8..32 ppc, LP / RP, density and beam
@@ -260,6 +314,9 @@ def main():
     ap.add_argument("--no-fp32-compare", action="store_true",
                     help="skip the 4096^2 FP32-form vs FP64 comparison")
     ap.add_argument("--compare-steps", type=int, default=200)
+    ap.add_argument("--no-on-nodes", action="store_true",
+                    help="skip the run with the incident field sampled on "
+                         "the Yee nodes")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batched sweep")
     ap.add_argument("--batch-members", type=int, default=256)
@@ -361,7 +418,16 @@ def main():
                    max(diag["rho_max"], 1e-300),
                    "nonfinite": diag["nonfinite"], "n_alive": diag["n_alive"]},
     }
+    ref = None
+    if not args.no_on_nodes:
+        ref = {"diag": diag, "fields": [sim.read_field(c) for c in
+                                        ("ex", "ey", "ez", "bx", "by",
+                                         "bz")]}
     sim.close()
+    if ref is not None:
+        out["incident_on_nodes"] = incident_on_nodes(ref, args.steps,
+                                                     args.warmup)
+        del ref
     if not args.no_fp32_compare:
         out["fp32_vs_fp64"] = fp32_vs_fp64(args.compare_steps)
     if not args.no_batch:

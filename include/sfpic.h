@@ -122,13 +122,21 @@ typedef struct {
  * phi0 the constant phase, (x_focus, y_focus) the focus in the plane,
  * t_focus the focal time.  a0 is the modulus of the complex on-axis field
  * component at the focus at the focal time (E along y for LP, E along x for
- * RP).  Plane pulse: a0, fwhm_t (FWHM of the field envelope) and t0. */
+ * RP).  Plane pulse: a0, fwhm_t (FWHM of the field envelope) and t0.
+ * on_nodes: 0 (default) evaluates the closed form at each particle (Sec. 2:
+ * the scattered field is interpolated and added to the incident field at the
+ * macro-particle); 1 samples the incident field where the Yee grid stores
+ * each component, at t^n, and the particles gather it with the scattered
+ * field (the field superimposed on the grid fields, as the paper's
+ * implementation does; O(dx^2) interpolation error, fewer closed-form
+ * evaluations).  Single simulations only: batches and servers reject 1. */
 typedef struct {
   int32_t kind;
   double a0;
   double fwhm_t, t0;
   double w0, s, phi0;
   double x_focus, y_focus, t_focus;
+  int32_t on_nodes;
 } sfpic_incident;
 
 /* Device allocator callback (e.g. a framework's caching allocator).  Must

@@ -56,7 +56,7 @@ class sfpic_incident(C.Structure):
                 ("fwhm_t", C.c_double), ("t0", C.c_double),
                 ("w0", C.c_double), ("s", C.c_double), ("phi0", C.c_double),
                 ("x_focus", C.c_double), ("y_focus", C.c_double),
-                ("t_focus", C.c_double)]
+                ("t_focus", C.c_double), ("on_nodes", C.c_int32)]
 
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)

@@ -39,6 +39,9 @@ int prepare_incident(const sfpic_incident *in, IncParams &P) {
   memset(&P, 0, sizeof(P));
   P.kind = in ? in->kind : SFPIC_INC_NONE;
   if (P.kind == SFPIC_INC_NONE) return SFPIC_OK;
+  if (in->on_nodes != 0 && in->on_nodes != 1)
+    return fail(SFPIC_E_INVAL, "incident on_nodes must be 0 or 1");
+  P.on_nodes = in->on_nodes;
   if (P.kind == SFPIC_INC_PLANE_PULSE_1D) {
     if (!(in->fwhm_t > 0.0) || !isfinite(in->a0) || !isfinite(in->t0))
       return fail(SFPIC_E_INVAL, "plane pulse needs fwhm_t > 0, finite a0/t0");
@@ -107,11 +110,14 @@ int check_grid(const sfpic_grid *g) {
 }
 
 template <typename R>
-void set_field_ptrs(Fields<R> &f, void *const planes[12], int NX, int NY,
-                    int pitch) {
+void set_field_ptrs(Fields<R> &f, void *const planes[12],
+                    void *const inc_planes[3], int NX, int NY, int pitch) {
   R **dst[12] = {&f.ex, &f.ey, &f.ez, &f.bx, &f.by, &f.bz,
                  &f.jx, &f.jy, &f.jz, &f.mx, &f.my, &f.mz};
   for (int c = 0; c < 12; ++c) *dst[c] = (R *)planes[c];
+  f.iex = (R *)inc_planes[0];
+  f.iey = (R *)inc_planes[1];
+  f.ibz = (R *)inc_planes[2];
   f.nx_alloc = NX;
   f.ny_alloc = NY;
   f.pitch = pitch;
@@ -546,6 +552,12 @@ int step_impl(sfpic_sim *s, int64_t nsteps) {
     HIP_TRY(timed(s, 0, [&] {
       return launch_faraday<R>(f, g.dims, g.dt, g.dx, g.dy, s->stream);
     }));
+    if (s->inc.on_nodes)
+      HIP_TRY(timed(s, 1, [&] {
+        return launch_incident_nodes<R>(f, g.dims, g.dx, g.dy,
+                                        (double)s->step * g.dt, s->inc,
+                                        s->stream);
+      }));
     for (auto &st : s->sp) {
       PushParams pp;
       pp.dt = g.dt;
@@ -663,8 +675,12 @@ int sfpic_create(const sfpic_grid *grid, const sfpic_species *species,
       if (hipMemsetAsync(s->planes[c], 0, plane, s->stream) != hipSuccess)
         return bail(fail(SFPIC_E_DEVICE, "hipMemsetAsync failed"));
     }
-    set_field_ptrs(s->f64, s->planes, s->NX, s->NY, s->pitch);
-    set_field_ptrs(s->f32, s->planes, s->NX, s->NY, s->pitch);
+    if (s->inc.on_nodes)
+      for (int c = 0; c < 3; ++c)
+        if (!(s->inc_planes[c] = s->dalloc(plane)))
+          return bail(fail(SFPIC_E_NOMEM, "field allocation failed"));
+    set_field_ptrs(s->f64, s->planes, s->inc_planes, s->NX, s->NY, s->pitch);
+    set_field_ptrs(s->f32, s->planes, s->inc_planes, s->NX, s->NY, s->pitch);
     s->sp.resize(nspecies);
     for (int k = 0; k < nspecies; ++k) {
       const int r = place_species(s, s->sp[k], species[k]);

@@ -70,6 +70,9 @@ int check_desc(const sfpic_sim_desc *d) {
       (d->hist.species < 0 || d->hist.species >= d->nspecies ||
        d->hist.n_theta <= 0 || !(d->hist.e_max > 0.0)))
     return fail(SFPIC_E_INVAL, "bad histogram spec");
+  if (d->incident.on_nodes)
+    return fail(SFPIC_E_INVAL,
+                "incident on_nodes is supported for single simulations only");
   return SFPIC_OK;
 }
 

@@ -29,6 +29,9 @@ struct IncParams {
   // the amplitude normalization (real, imaginary pairs).
   double cr[3], ci[3];
   double e_phase_r, e_phase_i;  // N e^{i phi0}
+  // 1: the incident field is sampled on the Yee nodes (Fields::iex ...) and
+  // gathered with the scattered field instead of evaluated per particle
+  int on_nodes;
 };
 
 // ---------------------------------------------------------------------------
@@ -39,6 +42,10 @@ struct Fields {
   R *ex, *ey, *ez, *bx, *by, *bz;  // scattered E^n, B^{n-1/2}
   R *jx, *jy, *jz;                 // current J^{n+1/2}
   R *mx, *my, *mz;                 // centred Bbar^n
+  // incident E_x, E_y, B_z at t^n on the nodes of E_x, E_y, B_z (sampled
+  // mode; in the plane y_paper = 0 the models have no other components);
+  // null when the incident field is evaluated at the particles
+  R *iex, *iey, *ibz;
   int nx_alloc, ny_alloc;          // NX, NY including guards
   int pitch;                       // row pitch (elements)
 };
@@ -563,6 +570,11 @@ hipError_t launch_particle_sums(const Particles<R> &p, int64_t n,
                                 hipStream_t st);
 template <typename R>
 hipError_t launch_field_sums(const Fields<R> &f, double *acc, hipStream_t st);
+// Incident field sampled on the Yee nodes at time t into f.iex, f.iey, f.ibz.
+template <typename R>
+hipError_t launch_incident_nodes(const Fields<R> &f, int dims, double dx,
+                                 double dy, double t, const IncParams &inc,
+                                 hipStream_t st);
 // acc[7] += 1/2 sum over physical nodes of |F_scatt + F_inc|^2 (E at tE, B
 // at tB), each component at its Yee node.
 template <typename R>

@@ -483,6 +483,40 @@ hipError_t launch_em_total(const Fields<R> &f, int dims, int nx, int ny,
   return hipGetLastError();
 }
 
+// Incident field sampled on the Yee nodes at time t (the field superimposed
+// on the grid fields, Sec. 2): E_x on its node (dual in x), E_y on its node
+// (dual in y) and B_z on its node (dual in both) for every array element,
+// guards included (the push windows reach them); the closed form in FP64.
+// In the plane y_paper = 0 the incident models have no other components.
+template <typename R>
+__global__ void incident_nodes_kernel(Fields<R> f, int dims, double dx,
+                                      double dy, double t, IncParams inc) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  if (i >= f.nx_alloc) return;
+  const size_t k = (size_t)j * f.pitch + i;
+  const double xp = (double)(i - kGuard) * dx;
+  const double xd = ((double)(i - kGuard) + 0.5) * dx;
+  const double yp = dims == 2 ? (double)(j - kGuard) * dy : 0.0;
+  const double yd = dims == 2 ? ((double)(j - kGuard) + 0.5) * dy : 0.0;
+  double E[3], B[3];
+  incident_field(inc, dims, xd, yp, t, E, B);
+  f.iex[k] = (R)E[0];
+  incident_field(inc, dims, xp, yd, t, E, B);
+  f.iey[k] = (R)E[1];
+  incident_field(inc, dims, xd, yd, t, E, B);
+  f.ibz[k] = (R)B[2];
+}
+
+template <typename R>
+hipError_t launch_incident_nodes(const Fields<R> &f, int dims, double dx,
+                                 double dy, double t, const IncParams &inc,
+                                 hipStream_t st) {
+  dim3 g((f.nx_alloc + 255) / 256, f.ny_alloc);
+  incident_nodes_kernel<R><<<g, 256, 0, st>>>(f, dims, dx, dy, t, inc);
+  return hipGetLastError();
+}
+
 template <typename R>
 __global__ void deposit_rho(Particles<R> p, int64_t n, const uint32_t *n_valid,
                             int dims, double qw, double *rho, int pitch) {
@@ -623,6 +657,10 @@ hipError_t launch_export_particles(const Particles<R> &p, int64_t n, int dims,
                                        double, double, hipStream_t);          \
   template hipError_t launch_field_sums<R>(const Fields<R> &, double *,       \
                                            hipStream_t);                      \
+  template hipError_t launch_incident_nodes<R>(const Fields<R> &, int, double, \
+                                               double, double,                \
+                                               const IncParams &,             \
+                                               hipStream_t);                  \
   template hipError_t launch_em_total<R>(const Fields<R> &, int, int, int,    \
                                          double, double, double, double,      \
                                          const IncParams &, double *,         \

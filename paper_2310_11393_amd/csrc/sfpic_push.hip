@@ -20,6 +20,8 @@
 // Two precisions of the same kernels: FP64 (positions as doubles in cell
 // units) and the FP32 form (packed integer cell plus float offsets, float
 // fields and momenta, FP64 incident-field phase, FP64 current accumulation).
+#include <type_traits>
+
 #include "sfpic_common.h"
 #include "sfpic_device.h"
 
@@ -333,9 +335,21 @@ __device__ __forceinline__ int node_weights(int ix, R fx, R wp[3], R wd[3],
   return ix + h;
 }
 
+// Where the push takes the incident field from: the closed form at each
+// particle, the sampled Yee nodes (already in the gathered field), or either
+// as IncParams::on_nodes says.  The runtime choice costs the closed form its
+// overlap with the gather's loads but frees registers: the FP64 push uses it
+// and runs three workgroups per CU (measured faster than two without it);
+// the FP32 form and the batches instantiate the fixed choices.
+enum IncSource { kIncAtParticle = 0, kIncOnNodes = 1, kIncRuntime = 2 };
+
+__device__ __forceinline__ bool inc_at_particle(int src, const IncParams &inc) {
+  return src == kIncAtParticle || (src == kIncRuntime && !inc.on_nodes);
+}
+
 // One particle: gather (via `gather`), incident field, Boris, advance,
 // deposit (via `add`), removal test.  Position is (cell, offset) per axis.
-template <typename R, int DIMS, typename Gather, typename Add>
+template <typename R, int DIMS, int INC, typename Gather, typename Add>
 __device__ __forceinline__ bool push_particle(int &ix, int &iy, R &fx, R &fy,
                                               R u[3], const PushParams &pp,
                                               const IncParams &inc,
@@ -346,13 +360,15 @@ __device__ __forceinline__ bool push_particle(int &ix, int &iy, R &fx, R &fy,
   const int ipy = (DIMS == 2) ? node_weights(iy, fy, wyp, wyd, dy0) : 0;
   R E[3], B[3];
   gather(ix, iy, ipx, ipy, wxp, wxd, wyp, wyd, E, B);
-  R Ei[3], Bi[3];
-  incident_r(inc, DIMS, ((double)ix + (double)fx) * pp.dx,
-             ((double)iy + (double)fy) * pp.dy, pp.time, Ei, Bi);
+  if (inc_at_particle(INC, inc)) {  // else the gathered field holds it
+    R Ei[3], Bi[3];
+    incident_r(inc, DIMS, ((double)ix + (double)fx) * pp.dx,
+               ((double)iy + (double)fy) * pp.dy, pp.time, Ei, Bi);
 #pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    E[c] += Ei[c];
-    B[c] += Bi[c];
+    for (int c = 0; c < 3; ++c) {
+      E[c] += Ei[c];
+      B[c] += Bi[c];
+    }
   }
   boris<R>((R)pp.qm, (R)pp.dt, u, E, B);
   const R gi = rsqrt(R(1) + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
@@ -388,7 +404,7 @@ __device__ __forceinline__ bool push_particle(int &ix, int &iy, R &fx, R &fy,
 // One workgroup pushes the particles pbeg .. pend - 1 of one tile (all of
 // them, or one work item of a dense tile); smem holds the field and current
 // windows and, on the staged path, the particle chunk (push_lds_bytes).
-template <typename R, int DIMS>
+template <typename R, int DIMS, int INC>
 __device__ __forceinline__ void push_tile(const Fields<R> &f,
                                           const Particles<R> &p,
                                           const TileGeom &tg,
@@ -423,6 +439,11 @@ __device__ __forceinline__ void push_tile(const Fields<R> &f,
     sf[3 * WN + k] = in ? f.mx[g] : R(0);
     sf[4 * WN + k] = in ? f.my[g] : R(0);
     sf[5 * WN + k] = in ? f.mz[g] : R(0);
+    if (!inc_at_particle(INC, inc) && in) {  // sampled incident field joins
+      sf[k] = f.ex[g] + f.iex[g];
+      sf[WN + k] = f.ey[g] + f.iey[g];
+      sf[5 * WN + k] = f.mz[g] + f.ibz[g];
+    }
     sj[k] = 0.0;
     sj[WN + k] = 0.0;
     sj[2 * WN + k] = 0.0;
@@ -464,7 +485,7 @@ __device__ __forceinline__ void push_tile(const Fields<R> &f,
     // window index of node ipx - 2, the first deposit node
     const int bx = ipx0 - cx0 + kWinLo - 2;
     const int by = (DIMS == 2) ? ipy0 - cy0 + kWinLo - 2 : 0;
-    alive = push_particle<R, DIMS>(
+    alive = push_particle<R, DIMS, INC>(
         ix, iy, fx, fy, u, pp, inc, gather, [&](int c, int a, int b, R v) {
           atomicAdd(&sj[c * WN + (by + b) * WX + bx + a], (double)v);
         });
@@ -586,8 +607,18 @@ __host__ __device__ __forceinline__ size_t push_item_capacity(
   return (size_t)tg.ntiles + (size_t)(n_slots / kmax) + 1;
 }
 
-template <typename R, int DIMS>
-__global__ void __launch_bounds__(256, SFPIC_PUSH_MIN_BLOCKS)
+// Resident workgroups per CU asked of the compiler for the single-sim push:
+// three for FP64 (its window alone, 52.5 KB for a 16 x 16 tile with slack 3,
+// fits three times in the LDS; with the runtime incident choice the kernel
+// then spills 20 VGPRs and is still 6% faster than at two), two for the
+// FP32 form (its registers allow three anyway; its LDS allows three).
+template <typename R>
+constexpr int push_min_blocks() {
+  return sizeof(R) == 8 ? 3 : SFPIC_PUSH_MIN_BLOCKS;
+}
+
+template <typename R, int DIMS, int INC>
+__global__ void __launch_bounds__(256, push_min_blocks<R>())
 push_tiled(Fields<R> f, Particles<R> p, const uint32_t *__restrict__ start,
            const uint32_t *__restrict__ items,
            const uint32_t *__restrict__ n_items, uint32_t kmax, TileGeom tg,
@@ -604,8 +635,8 @@ push_tiled(Fields<R> f, Particles<R> p, const uint32_t *__restrict__ start,
   const int tile = (int)items[2 * (size_t)it];
   const uint32_t pbeg = items[2 * (size_t)it + 1];
   const uint32_t tend = start[(size_t)(tile + 1) * tg.cells_per_tile];
-  push_tile<R, DIMS>(f, p, tg, pp, inc, strag, n_strag, tile, pbeg,
-                     tend - pbeg > kmax ? pbeg + kmax : tend, smem);
+  push_tile<R, DIMS, INC>(f, p, tg, pp, inc, strag, n_strag, tile, pbeg,
+                          tend - pbeg > kmax ? pbeg + kmax : tend, smem);
 }
 
 // Push of one particle listed by the tiled kernel (drifted more than slack
@@ -630,6 +661,11 @@ __device__ __forceinline__ void push_straggler(const Fields<R> &f,
                        : R(0);
     B[1] = gather_plane<R, DIMS>(f.my, P, bxd, byp, wxd, wyp);
     B[2] = gather_plane<R, DIMS>(f.mz, P, bxd, byd, wxd, wyd);
+    if (inc.on_nodes) {  // the sampled incident field, same taps
+      E[0] += gather_plane<R, DIMS>(f.iex, P, bxd, byp, wxd, wyp);
+      E[1] += gather_plane<R, DIMS>(f.iey, P, bxp, byd, wxp, wyd);
+      B[2] += gather_plane<R, DIMS>(f.ibz, P, bxd, byd, wxd, wyd);
+    }
   };
   int ix, iy;
   R fx, fy, u[3];
@@ -638,7 +674,7 @@ __device__ __forceinline__ void push_straggler(const Fields<R> &f,
   const int ipy0 = (DIMS == 2) ? iy + (fy >= R(0.5)) : 0;
   const int bx = ipx0 - 2 + kGuard;
   const int by = (DIMS == 2) ? ipy0 - 2 + kGuard : 0;
-  const bool alive = push_particle<R, DIMS>(
+  const bool alive = push_particle<R, DIMS, kIncRuntime>(
       ix, iy, fx, fy, u, pp, inc, gather, [&](int c, int a, int b, R v) {
         R *jp = c == 0 ? f.jx : (c == 1 ? f.jy : f.jz);
         unsafeAtomicAdd(&jp[(size_t)(by + b) * P + bx + a], v);
@@ -698,12 +734,23 @@ hipError_t launch_push_tiled(const Fields<R> &f, const Particles<R> &p,
   const unsigned nb = (unsigned)((cap + 7) & ~(size_t)7);
   const size_t lds = push_dyn_lds_bytes<R>(tg, dims);
   fill_u32<<<1, 64, 0, st>>>(n_strag, 0u, 1);
-  if (dims == 1)
-    push_tiled<R, 1><<<nb, 256, lds, st>>>(f, p, start, items, n_items, kmax,
-                                           tg, pp, inc, strag, n_strag);
-  else
-    push_tiled<R, 2><<<nb, 256, lds, st>>>(f, p, start, items, n_items, kmax,
-                                           tg, pp, inc, strag, n_strag);
+  auto go = [&](auto dims_c, auto inc_c) {
+    push_tiled<R, decltype(dims_c)::value, decltype(inc_c)::value>
+        <<<nb, 256, lds, st>>>(f, p, start, items, n_items, kmax, tg, pp, inc,
+                               strag, n_strag);
+  };
+  using D1 = std::integral_constant<int, 1>;
+  using D2 = std::integral_constant<int, 2>;
+  if constexpr (sizeof(R) == 8) {
+    using I = std::integral_constant<int, kIncRuntime>;
+    dims == 1 ? go(D1{}, I{}) : go(D2{}, I{});
+  } else if (inc.on_nodes) {
+    using I = std::integral_constant<int, kIncOnNodes>;
+    dims == 1 ? go(D1{}, I{}) : go(D2{}, I{});
+  } else {
+    using I = std::integral_constant<int, kIncAtParticle>;
+    dims == 1 ? go(D1{}, I{}) : go(D2{}, I{});
+  }
   return hipGetLastError();
 }
 
@@ -1026,9 +1073,11 @@ batch_push_kernel(BatchView<R> v) {
     const PushParams pp = member_params(v, J);
     const int tile = (int)(item - v.tile_off[jb]);
     const size_t t0 = (size_t)tile * J.tg.cells_per_tile;
-    push_tile<R, DIMS>(J.f, J.pa[J.cur], J.tg, pp, J.inc, J.strag,
-                       &v.counters[1 + jb], tile, J.start[t0],
-                       J.start[t0 + J.tg.cells_per_tile], smem);
+    push_tile<R, DIMS, kIncAtParticle>(J.f, J.pa[J.cur], J.tg, pp, J.inc,
+                                       J.strag, &v.counters[1 + jb], tile,
+                                       J.start[t0],
+                                       J.start[t0 + J.tg.cells_per_tile],
+                                       smem);
   }
 }
 

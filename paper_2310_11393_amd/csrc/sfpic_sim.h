@@ -98,6 +98,7 @@ struct sfpic_sim {
   Fields<double> f64{};
   Fields<float> f32{};
   void *planes[12] = {};
+  void *inc_planes[3] = {};  // sampled incident E_x, E_y, B_z (on_nodes)
   std::vector<SpeciesState> sp;
   TileGeom tg{};
   SortScratch ss{};
