@@ -277,6 +277,29 @@ void sfpic_destroy(sfpic_sim *sim);
 int sfpic_device_bytes(sfpic_sim *sim, size_t *bytes);
 
 /* ---------------------------------------------------------------------------
+ * Beam set-up on the host (no GPU).  Normalized units as everywhere here
+ * (k = omega = c = 1, fields in m_e c omega / e); the caller converts from
+ * SI with its wavelength.
+ * ------------------------------------------------------------------------- */
+
+/* Complex April field (Sec. 4.1) of an APRIL_LP or APRIL_RP incident at the
+ * point (x, y, z) relative to the focus and time t relative to the focal
+ * time, in the paper's own axes (z = propagation, x = LP polarization):
+ * out = {Re, Im} of E_x, E_y, E_z, cB_x, cB_y, cB_z (12 doubles), scaled to
+ * the incident's a0.  The physical field is the real part.  Returns
+ * SFPIC_E_INVAL for other kinds or a NULL out. */
+int sfpic_april_field(const sfpic_incident *inc, double x, double y, double z,
+                      double t, double *out);
+
+/* Peak power of an April beam (Sec. 4.1): the cycle-averaged Poynting flux
+ * (1/2) Re{E_x cB_y* - E_y cB_x*} integrated over the focal plane at the
+ * focal time, for the incident's a0, in units of eps0 c (m_e c omega/e)^2
+ * / k^2.  The paper fixes the beam amplitude from the peak power this way;
+ * with a0 = 1, a0 for a power P follows as sqrt(P / *power).  Trapezoid
+ * rule on a square of half-side 8 w0 with spacing w0 / 24. */
+int sfpic_april_power(const sfpic_incident *inc, double *power);
+
+/* ---------------------------------------------------------------------------
  * Sweeps.  The paper studies the same set-up over ranges of beam and plasma
  * parameters (focusing, polarization, density: Secs. 3 and 4); a sweep runs
  * many independent simulations of uneven size on one GPU.  Members of one

@@ -149,7 +149,8 @@ EXPORTS = ["sfpic_create", "sfpic_step", "sfpic_sync", "sfpic_read_field",
            "sfpic_batch_stats", "sfpic_batch_destroy", "sfpic_server_create",
            "sfpic_server_submit", "sfpic_server_poll", "sfpic_server_wait",
            "sfpic_server_result", "sfpic_server_histogram",
-           "sfpic_server_stats", "sfpic_server_destroy"]
+           "sfpic_server_stats", "sfpic_server_destroy",
+           "sfpic_april_field", "sfpic_april_power"]
 
 KCLASSES = ("faraday", "push", "ampere", "sort", "stragglers")
 
@@ -197,6 +198,10 @@ def lib():
     L.sfpic_destroy.argtypes = [vp]
     L.sfpic_destroy.restype = None
     L.sfpic_device_bytes.argtypes = [vp, C.POINTER(sz)]
+    L.sfpic_april_field.argtypes = [C.POINTER(sfpic_incident), C.c_double,
+                                    C.c_double, C.c_double, C.c_double, _DP]
+    L.sfpic_april_power.argtypes = [C.POINTER(sfpic_incident),
+                                    C.POINTER(C.c_double)]
     L.sfpic_last_error.restype = C.c_char_p
     L.sfpic_version.restype = C.c_char_p
     D = C.POINTER(sfpic_sim_desc)
@@ -288,6 +293,25 @@ def _grid_struct(g) -> sfpic_grid:
     s.dims, s.nx, s.ny = int(g.dims), int(g.nx), int(g.ny)
     s.dx, s.dy, s.dt = float(g.dx), float(g.dy), float(g.dt)
     return s
+
+
+def april_field(inc, x, y, z, t):
+    """Complex (E, cB) of an April incident at (x, y, z) from the focus and
+    t from the focal time, paper axes, normalized units (two length-3
+    complex arrays)."""
+    out = np.zeros(12)
+    _check(lib().sfpic_april_field(C.byref(_incident_struct(inc)), x, y, z, t,
+                                   _dp(out)))
+    v = out[0::2] + 1j * out[1::2]
+    return v[:3], v[3:]
+
+
+def april_power(inc) -> float:
+    """Peak power of an April incident (focal plane, focal time, cycle
+    average) in units of eps0 c (m_e c omega / e)^2 / k^2."""
+    p = C.c_double()
+    _check(lib().sfpic_april_power(C.byref(_incident_struct(inc)), C.byref(p)))
+    return p.value
 
 
 def _incident_struct(inc) -> sfpic_incident:

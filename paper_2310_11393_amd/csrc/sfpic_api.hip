@@ -1027,6 +1027,49 @@ int sfpic_profile_read(sfpic_sim *s, sfpic_kernel_stats *out) {
   return SFPIC_OK;
 }
 
+int sfpic_april_field(const sfpic_incident *inc, double x, double y, double z,
+                      double t, double *out) {
+  if (!inc || !out) return fail(SFPIC_E_INVAL, "NULL argument");
+  if (inc->kind != SFPIC_INC_APRIL_LP && inc->kind != SFPIC_INC_APRIL_RP)
+    return fail(SFPIC_E_INVAL, "not an April beam");
+  IncParams P;
+  SF_TRY(prepare_incident(inc, P));
+  cx<double> e[3], b[3];
+  april_complex_fields(P, x * P.inv_a, y * P.inv_a, z * P.inv_a, t, e, b);
+  for (int c = 0; c < 3; ++c) {
+    out[2 * c] = e[c].r;
+    out[2 * c + 1] = e[c].i;
+    out[6 + 2 * c] = b[c].r;
+    out[6 + 2 * c + 1] = b[c].i;
+  }
+  return SFPIC_OK;
+}
+
+int sfpic_april_power(const sfpic_incident *inc, double *power) {
+  if (!inc || !power) return fail(SFPIC_E_INVAL, "NULL argument");
+  if (inc->kind != SFPIC_INC_APRIL_LP && inc->kind != SFPIC_INC_APRIL_RP)
+    return fail(SFPIC_E_INVAL, "not an April beam");
+  IncParams P;
+  SF_TRY(prepare_incident(inc, P));
+  const double w0 = inc->w0, h = w0 / 24.0;
+  const int n = 8 * 24;  // nodes -n .. n per axis
+  double sum = 0.0;
+  for (int j = -n; j <= n; ++j)
+    for (int i = -n; i <= n; ++i) {
+      cx<double> e[3], b[3];
+      april_complex_fields(P, i * h * P.inv_a, j * h * P.inv_a, 0.0, 0.0, e,
+                           b);
+      // Re{E_x cB_y*} - Re{E_y cB_x*}
+      const double f = (e[0].r * b[1].r + e[0].i * b[1].i) -
+                       (e[1].r * b[0].r + e[1].i * b[0].i);
+      const double wi = (i == -n || i == n) ? 0.5 : 1.0;
+      const double wj = (j == -n || j == n) ? 0.5 : 1.0;
+      sum += wi * wj * f;
+    }
+  *power = 0.5 * sum * h * h;
+  return SFPIC_OK;
+}
+
 int sfpic_device_bytes(sfpic_sim *s, size_t *bytes) {
   SF_TRY(guarded(s));
   if (!bytes) return fail(SFPIC_E_INVAL, "bytes is NULL");
