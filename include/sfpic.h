@@ -86,7 +86,13 @@ enum {
   SFPIC_INC_APRIL_LP = 2,
   /* April pulse, radial polarization (TM01, electric Hertz vector along the
    * propagation axis; cited in Sec. 4, derived here from the same phasor). */
-  SFPIC_INC_APRIL_RP = 3
+  SFPIC_INC_APRIL_RP = 3,
+  /* Sec. 3.2 paraxial 2D Gaussian beam along +x, polarized along y, with a
+   * Gaussian time envelope and the first-order longitudinal field: a0 (E0),
+   * w0 (waist), fwhm_t and t0 (envelope 2^{-4 (t - t0 - z)^2 / fwhm_t^2}),
+   * focus (x_focus, y_focus); z is the distance from the focus along x.
+   * Single simulations only: batches and servers reject it. */
+  SFPIC_INC_GAUSS_2D = 4
 };
 
 typedef struct {

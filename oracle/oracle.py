@@ -27,7 +27,8 @@ class _Incident(C.Structure):
                 ("t0", C.c_double), ("ka", C.c_double), ("s", C.c_double),
                 ("phi0", C.c_double), ("x_focus", C.c_double),
                 ("y_focus", C.c_double), ("t_focus", C.c_double),
-                ("norm", C.c_double), ("on_nodes", C.c_int)]
+                ("norm", C.c_double), ("on_nodes", C.c_int),
+                ("w0", C.c_double)]
 
 
 _D = C.POINTER(C.c_double)
@@ -109,6 +110,7 @@ def _make_incident(inc) -> _Incident:
     ci.y_focus = float(getattr(inc, "y_focus", 0.0))
     ci.t_focus = float(getattr(inc, "t_focus", 0.0))
     ci.on_nodes = int(getattr(inc, "on_nodes", 0))
+    ci.w0 = w0
     if lib().orc_incident_setup(C.byref(ci)) != 0:
         raise ValueError("incident setup failed")
     return ci

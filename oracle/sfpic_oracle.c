@@ -187,6 +187,29 @@ void orc_incident_eval(const orc_incident *inc, int dims, double x, double y,
                pow(2.0, -4.0 * ph * ph / (inc->fwhm_t * inc->fwhm_t));
     E[1] = v;
     B[2] = v;
+  } else if (inc->kind == ORC_INC_GAUSS_2D) {
+    /* Sec. 3.2, paraxial 2D Gaussian beam focused at the origin, paper axes
+     * (z propagation, x transverse):
+     *   E_x = E0 sqrt(w0/w) e^{-x^2/w^2} cos(psi) env,  B_y = E_x,
+     *   E_z = 2 E0 (x / w^2) sqrt(w0/w) e^{-x^2/w^2} sin(psi) env,
+     *   psi = z - t + x^2 / (2 R) - eta,  env = 2^{-4 (t - t0 - z)^2 / FWHM^2},
+     *   w = w0 sqrt(1 + (z/zR)^2), R = z (1 + (zR/z)^2), eta = atan(z/zR)/2,
+     *   zR = w0^2 / 2.  The longitudinal factor is x / w^2 (the leading order
+     * of div E = 0; the printed x / w is not first order in 1/(k w0)), and
+     * 1/R = z / (z^2 + zR^2) is used so that the focal plane needs no limit. */
+    double z = x - inc->x_focus;
+    double xp = (dims == 2) ? y - inc->y_focus : 0.0;
+    double zr = 0.5 * inc->w0 * inc->w0;
+    double w = inc->w0 * sqrt(1.0 + (z / zr) * (z / zr));
+    double inv_r = z / (z * z + zr * zr);
+    double eta = 0.5 * atan(z / zr);
+    double psi = z - t + 0.5 * xp * xp * inv_r - eta;
+    double ph = t - inc->t0 - z;
+    double env = pow(2.0, -4.0 * ph * ph / (inc->fwhm_t * inc->fwhm_t));
+    double amp = inc->a0 * sqrt(inc->w0 / w) * exp(-xp * xp / (w * w)) * env;
+    E[1] = amp * cos(psi);                     /* build y = paper x */
+    E[0] = 2.0 * xp / (w * w) * amp * sin(psi); /* build x = paper z */
+    B[2] = E[1];                               /* build z = paper y */
   } else if (inc->kind == ORC_INC_APRIL_LP || inc->kind == ORC_INC_APRIL_RP) {
     double a = inc->ka;
     double px = (dims == 2 ? y - inc->y_focus : 0.0) / a; /* paper x */

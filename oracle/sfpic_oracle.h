@@ -43,7 +43,9 @@ enum {
   ORC_INC_NONE = 0,
   ORC_INC_PLANE_PULSE_1D = 1, /* Sec. 3.1 exact pulse, along +x, E_y = B_z */
   ORC_INC_APRIL_LP = 2,       /* Sec. 4.1, linear polarization            */
-  ORC_INC_APRIL_RP = 3        /* radial polarization (TM01), Hertz z*Psi  */
+  ORC_INC_APRIL_RP = 3,       /* radial polarization (TM01), Hertz z*Psi  */
+  ORC_INC_GAUSS_2D = 4        /* Sec. 3.2 paraxial 2D Gaussian beam with a
+                                 first-order longitudinal E               */
 };
 
 typedef struct {
@@ -58,6 +60,7 @@ typedef struct {
   double norm;    /* April: field scale, set by orc_incident_setup            */
   int on_nodes;   /* 0: evaluated at each particle; 1: sampled on the Yee
                      nodes at t^n and gathered with the scattered field     */
+  double w0;      /* Gaussian beam: waist (k = 1 units)                     */
 } orc_incident;
 
 typedef struct {

@@ -50,6 +50,21 @@ int prepare_incident(const sfpic_incident *in, IncParams &P) {
     P.env_k = -4.0 / (in->fwhm_t * in->fwhm_t);
     return SFPIC_OK;
   }
+  if (P.kind == SFPIC_INC_GAUSS_2D) {
+    if (!(in->fwhm_t > 0.0) || !(in->w0 > 0.0) || !isfinite(in->a0) ||
+        !isfinite(in->t0) || !isfinite(in->x_focus) || !isfinite(in->y_focus))
+      return fail(SFPIC_E_INVAL,
+                  "Gaussian beam needs w0 > 0, fwhm_t > 0 and finite a0, t0, "
+                  "focus");
+    P.a0 = in->a0;
+    P.t0 = in->t0;
+    P.env_k = -4.0 / (in->fwhm_t * in->fwhm_t);
+    P.w0 = in->w0;
+    P.zr = 0.5 * in->w0 * in->w0;
+    P.x_focus = in->x_focus;
+    P.y_focus = in->y_focus;
+    return SFPIC_OK;
+  }
   if (P.kind != SFPIC_INC_APRIL_LP && P.kind != SFPIC_INC_APRIL_RP)
     return fail(SFPIC_E_INVAL, "unknown incident kind");
   const double s = in->s;

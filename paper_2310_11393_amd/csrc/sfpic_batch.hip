@@ -73,6 +73,9 @@ int check_desc(const sfpic_sim_desc *d) {
   if (d->incident.on_nodes)
     return fail(SFPIC_E_INVAL,
                 "incident on_nodes is supported for single simulations only");
+  if (d->incident.kind == SFPIC_INC_GAUSS_2D)
+    return fail(SFPIC_E_INVAL,
+                "the Gaussian beam is supported for single simulations only");
   return SFPIC_OK;
 }
 

@@ -20,8 +20,18 @@ struct IncParams {
   double a0;       // plane pulse amplitude
   double t0;       // plane pulse centre
   double env_k;    // plane pulse: -4 / fwhm^2 (exponent base 2)
-  double a;        // April: complex-source parameter (k = 1 units)
-  double inv_a;
+  // April: complex-source parameter a (k = 1 units) and 1/a.  The Gaussian
+  // beam keeps its waist w0 and Rayleigh range zR = w0^2/2 in the same two
+  // slots, so the kernels' argument block keeps its size (one 16 bytes
+  // larger cost the FP64 push 2.5%).
+  union {
+    double a;
+    double w0;
+  };
+  union {
+    double inv_a;
+    double zr;
+  };
   double inv_s;
   double a_over_s;
   double x_focus, y_focus, t_focus;
@@ -414,11 +424,39 @@ __host__ __device__ inline void april_complex_fields(const IncParams &P,
   }
 }
 
+// Sec. 3.2 paraxial Gaussian beam, focus at (x_focus, y_focus): with z along
+// the axis and r across it, w = w0 sqrt(1 + (z/zR)^2), 1/R = z / (z^2 +
+// zR^2), eta = atan(z/zR) / 2, psi = z - t + r^2/(2R) - eta,
+// E_y = B_z = E0 sqrt(w0/w) e^{-r^2/w^2} cos(psi) env and the first-order
+// longitudinal E_x = 2 (r / w^2) E0 sqrt(w0/w) e^{-r^2/w^2} sin(psi) env.
+struct Gauss2 {
+  double ex, ey;
+};
+__host__ __device__ __forceinline__ Gauss2
+gauss2d_field(const IncParams &P, int dims, double x, double y, double t) {
+  const double z = x - P.x_focus;
+  const double r = dims == 2 ? y - P.y_focus : 0.0;
+  const double zz = z / P.zr;
+  const double w = P.w0 * sqrt(1.0 + zz * zz);
+  const double inv_r = z / (z * z + P.zr * P.zr);
+  const double psi = z - t + 0.5 * r * r * inv_r - 0.5 * atan(zz);
+  const double ph = t - P.t0 - z;
+  const double amp = P.a0 * sqrt(P.w0 / w) * exp(-r * r / (w * w)) *
+                     exp2(P.env_k * ph * ph);
+  Gauss2 g;
+  g.ey = amp * cos(psi);
+  g.ex = 2.0 * r / (w * w) * amp * sin(psi);
+  return g;
+}
+
 // Real incident field in build axes (propagation +x, LP polarization y) at
-// (x, y, z = 0) and time t.
-__host__ __device__ inline void incident_field(const IncParams &P, int dims,
-                                               double x, double y, double t,
-                                               double E[3], double B[3]) {
+// (x, y, z = 0) and time t.  kGauss = false compiles the plane pulse and the
+// April beams only: the push kernels of those models are built without the
+// Gaussian beam's code, which would otherwise cost them registers.
+template <bool kGauss>
+__host__ __device__ inline void incident_field_t(const IncParams &P, int dims,
+                                                 double x, double y, double t,
+                                                 double E[3], double B[3]) {
   E[0] = E[1] = E[2] = 0.0;
   B[0] = B[1] = B[2] = 0.0;
   if (P.kind == 1) {
@@ -426,6 +464,11 @@ __host__ __device__ inline void incident_field(const IncParams &P, int dims,
     double v = P.a0 * sin(ph) * exp2(P.env_k * ph * ph);
     E[1] = v;
     B[2] = v;
+  } else if (kGauss && P.kind == 4) {
+    const Gauss2 g = gauss2d_field(P, dims, x, y, t);
+    E[0] = g.ex;
+    E[1] = g.ey;
+    B[2] = g.ey;
   } else if (P.kind == 2 || P.kind == 3) {
     double X = (dims == 2 ? (y - P.y_focus) : 0.0) * P.inv_a;  // paper x
     double Z = (x - P.x_focus) * P.inv_a;                       // paper z
@@ -440,9 +483,17 @@ __host__ __device__ inline void incident_field(const IncParams &P, int dims,
   }
 }
 
+// Every model.
+__host__ __device__ inline void incident_field(const IncParams &P, int dims,
+                                               double x, double y, double t,
+                                               double E[3], double B[3]) {
+  incident_field_t<true>(P, dims, x, y, t, E, B);
+}
+
 // Incident field for the FP32 form: the phase (positions, time, u, tau +-
 // a u_r, the plane pulse's carrier phase after range reduction) and the ring
 // neighbourhood in FP64, the powers, blocks and fields in FP32.
+template <bool kGauss>
 __device__ inline void incident_field_fp32(const IncParams &P, int dims,
                                            double x, double y, double t,
                                            float E[3], float B[3]) {
@@ -458,6 +509,13 @@ __device__ inline void incident_field_fp32(const IncParams &P, int dims,
     B[2] = v;
     return;
   }
+  if (kGauss && P.kind == 4) {  // the FP64 closed form, rounded
+    const Gauss2 g = gauss2d_field(P, dims, x, y, t);
+    E[0] = (float)g.ex;
+    E[1] = (float)g.ey;
+    B[2] = (float)g.ey;
+    return;
+  }
   if (P.kind != 2 && P.kind != 3) return;
   const double X = (dims == 2 ? (y - P.y_focus) : 0.0) * P.inv_a;
   const double Z = (x - P.x_focus) * P.inv_a;
@@ -465,7 +523,7 @@ __device__ inline void incident_field_fp32(const IncParams &P, int dims,
   const cx<double> u2 = mk(X * X + Z * Z - 1.0, 2.0 * Z);
   if (u2.r * u2.r + u2.i * u2.i < kRingU2 * kRingU2) {
     double Ed[3], Bd[3];
-    incident_field(P, dims, x, y, t, Ed, Bd);
+    incident_field_t<false>(P, dims, x, y, t, Ed, Bd);
     for (int c = 0; c < 3; ++c) {
       E[c] = (float)Ed[c];
       B[c] = (float)Bd[c];

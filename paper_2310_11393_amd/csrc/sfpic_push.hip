@@ -220,15 +220,36 @@ struct PT<float> {
   }
 };
 
+// Incident field at a particle for the push instantiated with source INC
+// (see IncSource): the Gaussian beam alone, every model, or the plane pulse
+// and the April beams.
+template <int INC>
 __device__ __forceinline__ void incident_r(const IncParams &inc, int dims,
                                            double x, double y, double t,
                                            double E[3], double B[3]) {
-  incident_field(inc, dims, x, y, t, E, B);
+  if constexpr (INC == 3) {
+    E[0] = E[1] = E[2] = B[0] = B[1] = B[2] = 0.0;
+    const Gauss2 g = gauss2d_field(inc, dims, x, y, t);
+    E[0] = g.ex;
+    E[1] = g.ey;
+    B[2] = g.ey;
+  } else {
+    incident_field_t<INC == 4>(inc, dims, x, y, t, E, B);
+  }
 }
+template <int INC>
 __device__ __forceinline__ void incident_r(const IncParams &inc, int dims,
                                            double x, double y, double t,
                                            float E[3], float B[3]) {
-  incident_field_fp32(inc, dims, x, y, t, E, B);
+  if constexpr (INC == 3) {
+    E[0] = E[1] = E[2] = B[0] = B[1] = B[2] = 0.0f;
+    const Gauss2 g = gauss2d_field(inc, dims, x, y, t);
+    E[0] = (float)g.ex;
+    E[1] = (float)g.ey;
+    B[2] = (float)g.ey;
+  } else {
+    incident_field_fp32<INC == 4>(inc, dims, x, y, t, E, B);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -341,10 +362,21 @@ __device__ __forceinline__ int node_weights(int ix, R fx, R wp[3], R wd[3],
 // overlap with the gather's loads but frees registers: the FP64 push uses it
 // and runs three workgroups per CU (measured faster than two without it);
 // the FP32 form and the batches instantiate the fixed choices.
-enum IncSource { kIncAtParticle = 0, kIncOnNodes = 1, kIncRuntime = 2 };
+// Where the push takes the incident field from and which models it is built
+// for: kIncAtParticle, kIncRuntime -- the plane pulse and the April beams;
+// kIncGauss -- the Gaussian beam at the particle; kIncAny -- every model,
+// either source (the straggler path).
+enum IncSource {
+  kIncAtParticle = 0,
+  kIncOnNodes = 1,
+  kIncRuntime = 2,
+  kIncGauss = 3,
+  kIncAny = 4
+};
 
 __device__ __forceinline__ bool inc_at_particle(int src, const IncParams &inc) {
-  return src == kIncAtParticle || (src == kIncRuntime && !inc.on_nodes);
+  return src == kIncAtParticle || src == kIncGauss ||
+         ((src == kIncRuntime || src == kIncAny) && !inc.on_nodes);
 }
 
 // One particle: gather (via `gather`), incident field, Boris, advance,
@@ -362,7 +394,7 @@ __device__ __forceinline__ bool push_particle(int &ix, int &iy, R &fx, R &fy,
   gather(ix, iy, ipx, ipy, wxp, wxd, wyp, wyd, E, B);
   if (inc_at_particle(INC, inc)) {  // else the gathered field holds it
     R Ei[3], Bi[3];
-    incident_r(inc, DIMS, ((double)ix + (double)fx) * pp.dx,
+    incident_r<INC>(inc, DIMS, ((double)ix + (double)fx) * pp.dx,
                ((double)iy + (double)fy) * pp.dy, pp.time, Ei, Bi);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -674,7 +706,7 @@ __device__ __forceinline__ void push_straggler(const Fields<R> &f,
   const int ipy0 = (DIMS == 2) ? iy + (fy >= R(0.5)) : 0;
   const int bx = ipx0 - 2 + kGuard;
   const int by = (DIMS == 2) ? ipy0 - 2 + kGuard : 0;
-  const bool alive = push_particle<R, DIMS, kIncRuntime>(
+  const bool alive = push_particle<R, DIMS, kIncAny>(
       ix, iy, fx, fy, u, pp, inc, gather, [&](int c, int a, int b, R v) {
         R *jp = c == 0 ? f.jx : (c == 1 ? f.jy : f.jz);
         unsafeAtomicAdd(&jp[(size_t)(by + b) * P + bx + a], v);
@@ -741,7 +773,10 @@ hipError_t launch_push_tiled(const Fields<R> &f, const Particles<R> &p,
   };
   using D1 = std::integral_constant<int, 1>;
   using D2 = std::integral_constant<int, 2>;
-  if constexpr (sizeof(R) == 8) {
+  if (inc.kind == 4 && !inc.on_nodes) {  // the Gaussian beam
+    using I = std::integral_constant<int, kIncGauss>;
+    dims == 1 ? go(D1{}, I{}) : go(D2{}, I{});
+  } else if constexpr (sizeof(R) == 8) {
     using I = std::integral_constant<int, kIncRuntime>;
     dims == 1 ? go(D1{}, I{}) : go(D2{}, I{});
   } else if (inc.on_nodes) {

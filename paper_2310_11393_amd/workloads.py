@@ -32,6 +32,7 @@ PHILOX_W0 = 0x9E3779B9
 PHILOX_W1 = 0xBB67AE85
 
 INC_NONE, INC_PLANE_PULSE_1D, INC_APRIL_LP, INC_APRIL_RP = 0, 1, 2, 3
+INC_GAUSS_2D = 4  # paraxial 2D Gaussian beam (Sec. 3.2)
 FP64, FP32 = 0, 1
 
 
@@ -185,6 +186,22 @@ def plane_pulse_1d(nx=2048, steps=2000, slab=(768, 1280), n=0.01, ppc=64,
     sp = Species(q=-1.0, m=1.0, density=n, region=(slab[0], slab[1], 0, 1),
                  ppc=ppc, seed=seed)
     return Workload(f"plane_pulse_1d_{nx}", grid, [sp], inc, steps)
+
+
+def gauss_beam_2d(nx=1024, ny=512, plasma=(384, 640, 128, 384), n=0.31,
+                  ppc=8, w0_lambda=16.0, cycles=1.0, a0=4.86, steps=400,
+                  seed=6, cells_per_lambda=16, cfl=0.99) -> Workload:
+    """2D3V plasma in the paraxial Gaussian beam of Sec. 3.2 (w0 = 16
+    lambda, FWHM_T = 2 pi, E0 = 4.86 there), focused at the centre of the
+    plasma block, the envelope's peak at the focus at t = 0."""
+    dx = TWO_PI / cells_per_lambda
+    grid = Grid(2, nx, ny, dx, dx, cfl * dx / math.sqrt(2.0))
+    inc = Incident(kind=INC_GAUSS_2D, a0=a0, w0=w0_lambda * TWO_PI,
+                   fwhm_t=cycles * TWO_PI, t0=0.0,
+                   x_focus=0.5 * (plasma[0] + plasma[1]) * dx,
+                   y_focus=0.5 * (plasma[2] + plasma[3]) * dx)
+    sp = Species(q=-1.0, m=1.0, density=n, region=plasma, ppc=ppc, seed=seed)
+    return Workload(f"gauss_beam_2d_{nx}x{ny}", grid, [sp], inc, steps)
 
 
 def april_2d(nx=2048, ny=1024, plasma=(512, 1536, 0, 1024), n=0.05, ppc=16,

@@ -59,6 +59,9 @@ CASES = {
                                     s=10.0, a0=30.0, temperature_ev=0.0),
     "lp2d_ragged": lambda: _small_lp(nx=101, ny=77, plasma=(30, 81, 3, 70),
                                      ppc=3, s=10.0),
+    "gauss2d_small": lambda: wl.gauss_beam_2d(
+        nx=160, ny=96, plasma=(50, 110, 20, 76), ppc=4, w0_lambda=2.0,
+        cycles=3.0, a0=3.0, steps=50, cells_per_lambda=24),
 }
 
 
@@ -111,7 +114,7 @@ FP32_FIELD_TOL = 1e-4
 
 
 @pytest.mark.parametrize("case", ["pulse1d_small", "lp2d_small", "rp2d_small",
-                                  "lp2d_ragged"])
+                                  "lp2d_ragged", "gauss2d_small"])
 def test_fp32_form_against_fp64_oracle(case):
     """FP32 form (integer cell + float offset, float fields and momenta,
     FP64 incident-field phase and current accumulation) vs the FP64 oracle:
@@ -127,7 +130,10 @@ def test_fp32_form_against_fp64_oracle(case):
     assert den > 0 and rel <= FP32_FIELD_TOL, rel
     dpos, du, umax = particle_errors(g, o)
     _note(f"[fp32] {case}: max |dx| {dpos:.2e}, max |du| {du:.2e} (|u| {umax:.2e})")
-    assert dpos <= 1e-5 and du <= 1e-4 * max(1.0, umax), (dpos, du)
+    # FP32 momentum rounding grows with |u| and moves the positions by the
+    # same factor over the run: both bounds scale with max(1, |u|max)
+    assert dpos <= 1e-5 * max(1.0, umax) and du <= 1e-4 * max(1.0, umax), \
+        (dpos, du)
     gd = g.diagnostics()
     assert gd["nonfinite"] == 0
     # |dW| <= |F_inc + F_s| |dF_s|, so the field tolerance bounds the total

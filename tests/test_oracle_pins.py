@@ -763,3 +763,49 @@ def test_incident_on_nodes_2d_second_order():
         assert np.linalg.norm(u0) > 1e-3  # the beam does push the electron
         d.append(np.linalg.norm(u1 - u0) / dt)
     assert d[0] > 1e-6 and 3.0 < d[0] / d[1] < 5.5
+
+
+# ---------------------------------------------------------------------------
+# Paraxial 2D Gaussian beam (Sec. 3.2)
+# ---------------------------------------------------------------------------
+
+def _gauss_inc():
+    lam = 2 * math.pi
+    return wl.Incident(kind=wl.INC_GAUSS_2D, a0=1.0, w0=4 * lam,
+                       fwhm_t=5 * lam, t0=0.0)
+
+
+def test_gauss2d_longitudinal_field_cancels_divergence():
+    """The first-order longitudinal field makes the beam divergence-free to
+    leading order: in the focal plane div E is < 0.5% of |dE_x/dx| (and a
+    factor x/w instead of x/w^2 would leave it at ~w), within 0.3 z_R
+    < 6%."""
+    inc = _gauss_inc()
+    h = 1e-3
+
+    def e(xb, yb, t):
+        return oracle.incident_eval(inc, 2, xb, yb, t)[0]
+    for zb, lim in ((0.0, 5e-3), (100.0, 0.06), (-80.0, 0.06)):
+        for xp in (5.0, 12.0, 25.0):
+            t = zb  # the envelope's centre is there
+            dex = (e(zb, xp + h, t)[1] - e(zb, xp - h, t)[1]) / (2 * h)
+            dez = (e(zb + h, xp, t)[0] - e(zb - h, xp, t)[0]) / (2 * h)
+            assert abs(dex) > 1e-3
+            assert abs(dex + dez) < lim * abs(dex), (zb, xp)
+
+
+def test_gauss2d_travels_along_x_at_c():
+    """On the axis the beam is a wave moving along the propagation axis:
+    dE/dt + dE/dz is a small fraction of dE/dt (Gouy phase, diffraction),
+    and B_z = E_y, E_x = 0 there."""
+    inc = _gauss_inc()
+    h = 1e-4
+    for z in (-50.0, 0.0, 60.0):
+        for t in (z - 3.0, z + 1.0):
+            e0, b0 = oracle.incident_eval(inc, 2, z, 0.0, t)
+            assert e0[0] == 0.0 and b0[2] == e0[1]
+            dt = (oracle.incident_eval(inc, 2, z, 0.0, t + h)[0][1] -
+                  oracle.incident_eval(inc, 2, z, 0.0, t - h)[0][1]) / (2 * h)
+            dz = (oracle.incident_eval(inc, 2, z + h, 0.0, t)[0][1] -
+                  oracle.incident_eval(inc, 2, z - h, 0.0, t)[0][1]) / (2 * h)
+            assert abs(dt + dz) < 0.05 * max(abs(dt), 1e-2), (z, t)
