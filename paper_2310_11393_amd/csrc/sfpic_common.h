@@ -352,17 +352,19 @@ __host__ __device__ inline AprilBlocks april_blocks_closed(const IncParams &P,
 }
 
 // Rare branch (particles near the ring): kept out of line so its registers do
-// not add to those of the common closed-form path.
+// not add to those of the common closed-form path.  It takes the few
+// parameters it reads by value: a reference to IncParams across a real call
+// would make the kernels keep the whole block in per-lane scratch memory and
+// read every incident parameter from there.
 static __host__ __device__ __attribute__((noinline)) AprilBlocks
-april_blocks_series(const IncParams &P,
-                                                            cx<double> u2,
-                                                            double tau) {
+april_blocks_series(double a_over_s, double inv_s, int s_int,
+                    cx<double> e_phase, cx<double> u2, double tau) {
   // c_m = N e^{i phi0} [prod_{k<=m} (s+k)] (i a/s)^m (1 + a/s - i tau/s)^{-(s+m+1)}
   // generated in order: c_{m} = (s + m) (i a/s) base c_{m-1}.
-  cx<double> base = cinv(mk(1.0 + P.a_over_s, -tau * P.inv_s));
-  const double s = (double)P.s_int;
-  const cx<double> step_b = mk(0.0, P.a_over_s) * base;
-  cx<double> c = mk(P.e_phase_r, P.e_phase_i) * cpowi(base, P.s_int + 1);
+  cx<double> base = cinv(mk(1.0 + a_over_s, -tau * inv_s));
+  const double s = (double)s_int;
+  const cx<double> step_b = mk(0.0, a_over_s) * base;
+  cx<double> c = e_phase * cpowi(base, s_int + 1);
   c = (s + 1.0) * (c * step_b);  // c_1
   cx<double> phitt = mk(0.0, 0.0), d1 = phitt, d1t = phitt, d2 = phitt;
   cx<double> pw = mk(1.0, 0.0), pw1 = mk(0.0, 0.0), pw2 = mk(0.0, 0.0);
@@ -402,8 +404,11 @@ __host__ __device__ inline void april_complex_fields(const IncParams &P,
                                                      cx<double> b[3]) {
   cx<double> u2 = mk(X * X + Y * Y + Z * Z - 1.0, 2.0 * Z);
   double m2 = u2.r * u2.r + u2.i * u2.i;
-  AprilBlocks k = (m2 < kRingU2 * kRingU2) ? april_blocks_series(P, u2, tau)
-                                           : april_blocks_closed(P, u2, tau);
+  AprilBlocks k = (m2 < kRingU2 * kRingU2)
+                      ? april_blocks_series(P.a_over_s, P.inv_s, P.s_int,
+                                            mk(P.e_phase_r, P.e_phase_i), u2,
+                                            tau)
+                      : april_blocks_closed(P, u2, tau);
   cx<double> zp = mk(Z, 1.0);
   if (P.kind == 2) {  // LP
     cx<double> common = k.d1 - k.phitt + zp * k.d1t;

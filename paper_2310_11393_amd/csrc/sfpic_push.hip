@@ -386,16 +386,21 @@ __device__ __forceinline__ bool push_particle(int &ix, int &iy, R &fx, R &fy,
                                               R u[3], const PushParams &pp,
                                               const IncParams &inc,
                                               Gather gather, Add add) {
+  // The incident field is evaluated before the weights and the gather, so
+  // its temporaries are dead by the time those are live (fewer registers at
+  // the peak); the sum is the same, scattered plus incident.
+  R Ei[3] = {R(0), R(0), R(0)}, Bi[3] = {R(0), R(0), R(0)};
+  const bool at_particle = inc_at_particle(INC, inc);
+  if (at_particle)  // else the gathered field holds it
+    incident_r<INC>(inc, DIMS, ((double)ix + (double)fx) * pp.dx,
+               ((double)iy + (double)fy) * pp.dy, pp.time, Ei, Bi);
   R wxp[3], wxd[3], wyp[3] = {R(1), R(0), R(0)}, wyd[3] = {R(1), R(0), R(0)};
   R dx0, dy0 = R(0);
   const int ipx = node_weights(ix, fx, wxp, wxd, dx0);
   const int ipy = (DIMS == 2) ? node_weights(iy, fy, wyp, wyd, dy0) : 0;
   R E[3], B[3];
   gather(ix, iy, ipx, ipy, wxp, wxd, wyp, wyd, E, B);
-  if (inc_at_particle(INC, inc)) {  // else the gathered field holds it
-    R Ei[3], Bi[3];
-    incident_r<INC>(inc, DIMS, ((double)ix + (double)fx) * pp.dx,
-               ((double)iy + (double)fy) * pp.dy, pp.time, Ei, Bi);
+  if (at_particle) {
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       E[c] += Ei[c];
