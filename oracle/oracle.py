@@ -28,7 +28,13 @@ class _Incident(C.Structure):
                 ("phi0", C.c_double), ("x_focus", C.c_double),
                 ("y_focus", C.c_double), ("t_focus", C.c_double),
                 ("norm", C.c_double), ("on_nodes", C.c_int),
-                ("w0", C.c_double)]
+                ("w0", C.c_double), ("z_focus", C.c_double)]
+
+
+class _Grid3(C.Structure):
+    _fields_ = [("nx", C.c_long), ("ny", C.c_long), ("nz", C.c_long),
+                ("dx", C.c_double), ("dy", C.c_double), ("dz", C.c_double),
+                ("dt", C.c_double)]
 
 
 _D = C.POINTER(C.c_double)
@@ -39,9 +45,9 @@ def lib():
     global _lib
     if _lib is None:
         path = os.path.join(_HERE, "liboracle.so")
-        src = os.path.join(_HERE, "sfpic_oracle.c")
-        if not os.path.exists(path) or \
-                os.path.getmtime(path) < os.path.getmtime(src):
+        srcs = [os.path.join(_HERE, f) for f in _build.SOURCES]
+        if not os.path.exists(path) or any(
+                os.path.getmtime(path) < os.path.getmtime(f) for f in srcs):
             _build.build(force=True)
         L = C.CDLL(path)
         L.orc_april_ka_from_w0.restype = C.c_double
@@ -83,6 +89,26 @@ def lib():
         L.orc_em_energy_total.argtypes = [C.c_void_p]
         L.orc_energy_angle.argtypes = [C.c_void_p, C.c_int, C.c_int,
                                        C.c_double, C.c_int, C.c_double, _D, _D]
+        L.orc3_incident_eval.argtypes = [C.POINTER(_Incident)] + \
+            [C.c_double] * 4 + [_D, _D]
+        L.orc3_create.restype = C.c_void_p
+        L.orc3_create.argtypes = [C.POINTER(_Grid3), C.POINTER(_Incident)]
+        L.orc3_destroy.argtypes = [C.c_void_p]
+        L.orc3_add_species.argtypes = [C.c_void_p, C.c_double, C.c_double,
+                                       C.c_double, C.c_long] + [_D] * 6
+        L.orc3_n_alloc.restype = C.c_long
+        L.orc3_n_alloc.argtypes = [C.c_void_p, C.c_int]
+        L.orc3_step_index.restype = C.c_long
+        L.orc3_step_index.argtypes = [C.c_void_p]
+        L.orc3_field.restype = _D
+        L.orc3_field.argtypes = [C.c_void_p, C.c_int]
+        L.orc3_count.restype = C.c_long
+        L.orc3_count.argtypes = [C.c_void_p, C.c_int]
+        L.orc3_get_particles.argtypes = [C.c_void_p, C.c_int] + [_D] * 6 + [_I]
+        L.orc3_gather.argtypes = [C.c_void_p] + [C.c_double] * 3 + [_D, _D]
+        L.orc3_step.argtypes = [C.c_void_p, C.c_long]
+        L.orc3_deposit_rho.argtypes = [C.c_void_p, _D]
+        L.orc3_diagnostics.argtypes = [C.c_void_p, _D]
         _lib = L
     return _lib
 
@@ -111,6 +137,7 @@ def _make_incident(inc) -> _Incident:
     ci.t_focus = float(getattr(inc, "t_focus", 0.0))
     ci.on_nodes = int(getattr(inc, "on_nodes", 0))
     ci.w0 = w0
+    ci.z_focus = float(getattr(inc, "z_focus", 0.0))
     if lib().orc_incident_setup(C.byref(ci)) != 0:
         raise ValueError("incident setup failed")
     return ci
@@ -243,3 +270,83 @@ class OracleSim:
         lib().orc_energy_angle(self._h, sp, n_e, emax, n_theta, ek_min,
                                _dp(h), _dp(mom))
         return h, mom
+
+
+def incident_eval3(inc, x, y, z, t):
+    """Incident field at a 3D point (build axes)."""
+    ci = _make_incident(inc)
+    E = np.zeros(3)
+    B = np.zeros(3)
+    lib().orc3_incident_eval(C.byref(ci), x, y, z, t, _dp(E), _dp(B))
+    return E, B
+
+
+class OracleSim3:
+    """One 3D3V simulation held by the oracle; arrays are (NZ, NY, NX)."""
+
+    def __init__(self, grid, incident):
+        g = _Grid3()
+        g.nx, g.ny, g.nz = int(grid.nx), int(grid.ny), int(grid.nz)
+        g.dx, g.dy, g.dz = float(grid.dx), float(grid.dy), float(grid.dz)
+        g.dt = float(grid.dt)
+        self.grid = grid
+        self._inc = _make_incident(incident)
+        self._h = lib().orc3_create(C.byref(g), C.byref(self._inc))
+        if not self._h:
+            raise ValueError("orc3_create failed")
+        self.shape = tuple(lib().orc3_n_alloc(self._h, a) for a in (2, 1, 0))
+        self.nsp = 0
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            lib().orc3_destroy(h)
+            self._h = None
+
+    def add_species(self, q, m, w, x, y, z, ux, uy, uz):
+        arrs = [np.ascontiguousarray(a, dtype=np.float64)
+                for a in (x, y, z, ux, uy, uz)]
+        r = lib().orc3_add_species(self._h, q, m, w, len(arrs[0]),
+                                   *[_dp(a) for a in arrs])
+        if r < 0:
+            raise ValueError("too many species")
+        self.nsp += 1
+        return r
+
+    def step(self, n=1):
+        lib().orc3_step(self._h, int(n))
+
+    @property
+    def step_index(self):
+        return lib().orc3_step_index(self._h)
+
+    def field(self, comp) -> np.ndarray:
+        """Live (writable) view of one field array, shape (NZ, NY, NX)."""
+        c = COMP[comp] if isinstance(comp, str) else int(comp)
+        return np.ctypeslib.as_array(lib().orc3_field(self._h, c),
+                                     shape=self.shape)
+
+    def particles(self, sp=0):
+        n = lib().orc3_count(self._h, sp)
+        out = [np.zeros(n) for _ in range(6)]
+        alive = np.zeros(n, dtype=np.int32)
+        lib().orc3_get_particles(self._h, sp, *[_dp(a) for a in out],
+                                 alive.ctypes.data_as(_I))
+        return (*out, alive.astype(bool))
+
+    def gather(self, x, y, z):
+        E = np.zeros(3)
+        B = np.zeros(3)
+        lib().orc3_gather(self._h, x, y, z, _dp(E), _dp(B))
+        return E, B
+
+    def rho(self):
+        r = np.zeros(self.shape)
+        lib().orc3_deposit_rho(self._h, _dp(r))
+        return r
+
+    def diagnostics(self):
+        o = np.zeros(4)
+        lib().orc3_diagnostics(self._h, _dp(o))
+        return {"w_kin": o[0], "w_em": o[1], "charge": o[2],
+                "n_alive": int(o[3])}

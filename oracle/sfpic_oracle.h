@@ -61,6 +61,7 @@ typedef struct {
   int on_nodes;   /* 0: evaluated at each particle; 1: sampled on the Yee
                      nodes at t^n and gathered with the scattered field     */
   double w0;      /* Gaussian beam: waist (k = 1 units)                     */
+  double z_focus; /* April, 3D only: focus along build z                    */
 } orc_incident;
 
 typedef struct {
@@ -125,6 +126,38 @@ double orc_em_energy_total(const orc_sim *S);
 void orc_energy_angle(const orc_sim *S, int sp, int n_e, double emax,
                       int n_theta, double ek_min, double *hist,
                       double mom[5]);
+
+/* ---- 3D3V step (sfpic_oracle3d.c) ----
+ * Grid nx x ny x nz physical cells plus ORC_GUARD guards on every side;
+ * arrays [k][j][i], i fastest.  Incident kinds: none, plane pulse (along x),
+ * April LP / RP (full six components, focus (x_focus, y_focus, z_focus)). */
+typedef struct {
+  long nx, ny, nz;
+  double dx, dy, dz, dt;
+} orc3_grid;
+
+typedef struct orc3_sim orc3_sim;
+
+void orc3_incident_eval(const orc_incident *inc, double x, double y, double z,
+                        double t, double E[3], double B[3]);
+orc3_sim *orc3_create(const orc3_grid *g, const orc_incident *inc);
+void orc3_destroy(orc3_sim *S);
+int orc3_add_species(orc3_sim *S, double q, double m, double w, long n,
+                     const double *x, const double *y, const double *z,
+                     const double *ux, const double *uy, const double *uz);
+long orc3_n_alloc(const orc3_sim *S, int axis);
+long orc3_step_index(const orc3_sim *S);
+double *orc3_field(orc3_sim *S, int comp);
+long orc3_count(const orc3_sim *S, int sp);
+void orc3_get_particles(const orc3_sim *S, int sp, double *x, double *y,
+                        double *z, double *ux, double *uy, double *uz,
+                        int *alive);
+void orc3_gather(const orc3_sim *S, double x, double y, double z, double E[3],
+                 double B[3]);
+void orc3_step(orc3_sim *S, long nsteps);
+void orc3_deposit_rho(const orc3_sim *S, double *rho);
+/* out: {W_kin, W_em(E^n, B^{n-1/2}, every array node), charge, n_alive} */
+void orc3_diagnostics(const orc3_sim *S, double out[4]);
 
 #ifdef __cplusplus
 }
