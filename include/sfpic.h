@@ -143,6 +143,7 @@ typedef struct {
   double w0, s, phi0;
   double x_focus, y_focus, t_focus;
   int32_t on_nodes;
+  double z_focus;  /* 3D runs (sfpic3_*): focus coordinate along z        */
 } sfpic_incident;
 
 /* Device allocator callback (e.g. a framework's caching allocator).  Must
@@ -451,6 +452,83 @@ int sfpic_server_stats(sfpic_server *srv, sfpic_server_info *out);
 
 /* Stop the loop (running requests are abandoned) and release everything. */
 void sfpic_server_destroy(sfpic_server *srv);
+
+/* ------------------------------------------------------------------------ */
+/* 3D3V simulations (Sec. 4 runs the method in three dimensions with the    */
+/* tightly focused April LP and RP pulses).                                 */
+/* ------------------------------------------------------------------------ */
+/* The step is the one described at the top of this header with every
+ * operator in three dimensions: all six scattered components on the Yee
+ * staggering Ex(i+1/2,j,k) Ey(i,j+1/2,k) Ez(i,j,k+1/2) Bx(i,j+1/2,k+1/2)
+ * By(i+1/2,j,k+1/2) Bz(i+1/2,j+1/2,k), J co-located with E; 3 x 3 x 3
+ * order-2 gathers; the incident field at each particle (plane pulse along x,
+ * or the full six-component April LP / RP beam focused at (x_focus, y_focus,
+ * z_focus) at t_focus; the paper's (x, y, z) are (y, z, x) here); the 3D
+ * Esirkepov (2001) current; removal of particles that leave the physical
+ * box [0, nx dx) x [0, ny dy) x [0, nz dz) after they deposit; first-order
+ * Mur on tangential E at the outer faces (z faces, then y, then x; an edge
+ * node takes the last face's value).  FP64 throughout; single simulations
+ * only (no batches or servers).  Host field arrays are [k][j][i] with i
+ * fastest, NX = nx + 2 SFPIC_GUARD, NY = ny + 2 SFPIC_GUARD, NZ = nz + 2
+ * SFPIC_GUARD. */
+typedef struct {
+  int64_t nx, ny, nz;  /* physical cells, each in [1, 32768]              */
+  double dx, dy, dz;   /* cell sizes                                      */
+  double dt;           /* dt sqrt(1/dx^2 + 1/dy^2 + 1/dz^2) < 1           */
+} sfpic3_grid;
+
+/* One mobile species, generated (n_explicit == 0, ppc > 0: ppc particles
+ * per cell of region [x0,x1) x [y0,y1) x [z0,z1), uniform in the cell,
+ * Philox4x32-10 keyed by (seed, species_index) with counter (particle id,
+ * word 2 = 0 for x and y, 3 for z, 1 and 2 for Box-Muller momenta of
+ * temperature_ev), weight density / ppc) or explicit (n_explicit > 0 arrays
+ * in physical units, every position inside the box, each particle carrying
+ * density `weight`).  As in 2D an immobile neutralizing background is
+ * implied. */
+typedef struct {
+  double q, m;
+  double density;
+  int64_t region[6];
+  int32_t ppc;
+  double temperature_ev;
+  uint64_t seed;
+  int32_t species_index;
+  int64_t n_explicit;
+  double weight;
+  const double *x, *y, *z, *ux, *uy, *uz;
+} sfpic3_species;
+
+typedef struct sfpic3_sim sfpic3_sim;
+
+/* Create a 3D simulation (scattered field zero, u^{-1/2} = u^0).  Incident
+ * kinds: none, plane pulse, April LP / RP with on_nodes = 0; the Gaussian
+ * beam is 2D only.  SFPIC_E_INVAL for bad sizes, parameters or explicit
+ * particles outside the box, SFPIC_E_NOMEM, SFPIC_E_DEVICE. */
+int sfpic3_create(const sfpic3_grid *grid, const sfpic3_species *species,
+                  int nspecies, const sfpic_incident *incident,
+                  const sfpic_runtime *runtime, sfpic3_sim **out);
+/* Enqueue nsteps >= 0 steps on the runtime stream (asynchronous). */
+int sfpic3_step(sfpic3_sim *sim, int64_t nsteps);
+int sfpic3_sync(sfpic3_sim *sim);
+/* out = {NX, NY, NZ}, the extents of host field arrays. */
+int sfpic3_dims(const sfpic3_sim *sim, int64_t out[3]);
+/* Copy one component (SFPIC_EX .. SFPIC_JZ) as [k][j][i]; n = NX NY NZ. */
+int sfpic3_read_field(sfpic3_sim *sim, int comp, double *out, size_t n);
+/* Overwrite E or B (SFPIC_EX .. SFPIC_BZ) from a host array as above. */
+int sfpic3_write_field(sfpic3_sim *sim, int comp, const double *in, size_t n);
+/* Number of particle slots of a species (live and removed). */
+int sfpic3_particle_count(sfpic3_sim *sim, int species, int64_t *n);
+/* Copy every slot of a species in creation order (physical units); alive[i]
+ * is 0 for a removed particle, whose other values are meaningless.  n must
+ * equal the slot count. */
+int sfpic3_read_particles(sfpic3_sim *sim, int species, double *x, double *y,
+                          double *z, double *ux, double *uy, double *uz,
+                          uint8_t *alive, size_t n);
+/* FP64 diagnostics as sfpic_diag (dV = dx dy dz; w_em over every array
+ * node; gauss_residual and rho_max over nodes at least 4 cells inside the
+ * box); w_em_total is not evaluated in 3D (NaN). */
+int sfpic3_diagnostics(sfpic3_sim *sim, sfpic_diag *out);
+void sfpic3_destroy(sfpic3_sim *sim);
 
 /* Message of the last failing call on this thread ("" if none). */
 const char *sfpic_last_error(void);

@@ -56,7 +56,24 @@ class sfpic_incident(C.Structure):
                 ("fwhm_t", C.c_double), ("t0", C.c_double),
                 ("w0", C.c_double), ("s", C.c_double), ("phi0", C.c_double),
                 ("x_focus", C.c_double), ("y_focus", C.c_double),
-                ("t_focus", C.c_double), ("on_nodes", C.c_int32)]
+                ("t_focus", C.c_double), ("on_nodes", C.c_int32),
+                ("z_focus", C.c_double)]
+
+
+class sfpic3_grid(C.Structure):
+    _fields_ = [("nx", C.c_int64), ("ny", C.c_int64), ("nz", C.c_int64),
+                ("dx", C.c_double), ("dy", C.c_double), ("dz", C.c_double),
+                ("dt", C.c_double)]
+
+
+class sfpic3_species(C.Structure):
+    _fields_ = [("q", C.c_double), ("m", C.c_double),
+                ("density", C.c_double), ("region", C.c_int64 * 6),
+                ("ppc", C.c_int32), ("temperature_ev", C.c_double),
+                ("seed", C.c_uint64), ("species_index", C.c_int32),
+                ("n_explicit", C.c_int64), ("weight", C.c_double),
+                ("x", _DP), ("y", _DP), ("z", _DP), ("ux", _DP),
+                ("uy", _DP), ("uz", _DP)]
 
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
@@ -150,7 +167,11 @@ EXPORTS = ["sfpic_create", "sfpic_step", "sfpic_sync", "sfpic_read_field",
            "sfpic_server_submit", "sfpic_server_poll", "sfpic_server_wait",
            "sfpic_server_result", "sfpic_server_histogram",
            "sfpic_server_stats", "sfpic_server_destroy",
-           "sfpic_april_field", "sfpic_april_power"]
+           "sfpic_april_field", "sfpic_april_power",
+           "sfpic3_create", "sfpic3_step", "sfpic3_sync", "sfpic3_dims",
+           "sfpic3_read_field", "sfpic3_write_field",
+           "sfpic3_particle_count", "sfpic3_read_particles",
+           "sfpic3_diagnostics", "sfpic3_destroy"]
 
 KCLASSES = ("faraday", "push", "ampere", "sort", "stragglers")
 
@@ -198,6 +219,21 @@ def lib():
     L.sfpic_destroy.argtypes = [vp]
     L.sfpic_destroy.restype = None
     L.sfpic_device_bytes.argtypes = [vp, C.POINTER(sz)]
+    L.sfpic3_create.argtypes = [C.POINTER(sfpic3_grid),
+                                C.POINTER(sfpic3_species), C.c_int,
+                                C.POINTER(sfpic_incident),
+                                C.POINTER(sfpic_runtime), C.POINTER(vp)]
+    L.sfpic3_step.argtypes = [vp, i64]
+    L.sfpic3_sync.argtypes = [vp]
+    L.sfpic3_dims.argtypes = [vp, C.POINTER(i64)]
+    L.sfpic3_read_field.argtypes = [vp, C.c_int, _DP, sz]
+    L.sfpic3_write_field.argtypes = [vp, C.c_int, _DP, sz]
+    L.sfpic3_particle_count.argtypes = [vp, C.c_int, C.POINTER(i64)]
+    L.sfpic3_read_particles.argtypes = [vp, C.c_int] + [_DP] * 6 + \
+        [C.POINTER(C.c_uint8), sz]
+    L.sfpic3_diagnostics.argtypes = [vp, C.POINTER(sfpic_diag)]
+    L.sfpic3_destroy.argtypes = [vp]
+    L.sfpic3_destroy.restype = None
     L.sfpic_april_field.argtypes = [C.POINTER(sfpic_incident), C.c_double,
                                     C.c_double, C.c_double, C.c_double, _DP]
     L.sfpic_april_power.argtypes = [C.POINTER(sfpic_incident),
@@ -657,3 +693,101 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+class Simulation3:
+    """One 3D3V simulation held by the library (sfpic3_*).  Field arrays are
+    (NZ, NY, NX); FP64 only."""
+
+    def __init__(self, grid, incident, species: Sequence = (),
+                 explicit: Optional[Sequence] = None, use_torch: bool = True,
+                 device: int = 0):
+        """grid: nx, ny, nz, dx, dy, dz, dt.  species: objects with q, m,
+        density, region (x0, x1, y0, y1, z0, z1), ppc, temperature_ev, seed
+        (generated on the device, species index = position in the list);
+        explicit: dicts {q, m, weight, x, y, z, ux, uy, uz}."""
+        L = lib()
+        self.grid = grid
+        self._rt, self._mem = make_runtime(use_torch, device)
+        keep = []
+        arr = []
+        for e in (explicit or ()):
+            sp = sfpic3_species()
+            sp.q, sp.m, sp.weight = e["q"], e["m"], e["weight"]
+            cols = [np.ascontiguousarray(e[k], dtype=np.float64)
+                    for k in ("x", "y", "z", "ux", "uy", "uz")]
+            keep += cols
+            sp.n_explicit = len(cols[0])
+            sp.x, sp.y, sp.z, sp.ux, sp.uy, sp.uz = [_dp(c) for c in cols]
+            arr.append(sp)
+        for k, d in enumerate(species):
+            sp = sfpic3_species()
+            sp.q, sp.m, sp.density = d.q, d.m, d.density
+            for a in range(6):
+                sp.region[a] = int(d.region[a])
+            sp.ppc = int(d.ppc)
+            sp.temperature_ev = float(getattr(d, "temperature_ev", 0.0))
+            sp.seed = int(getattr(d, "seed", 0))
+            sp.species_index = k
+            arr.append(sp)
+        n = len(arr)
+        sp_arr = (sfpic3_species * max(n, 1))(*arr)
+        g = sfpic3_grid()
+        for f, _ in sfpic3_grid._fields_:
+            setattr(g, f, getattr(grid, f))
+        inc = _incident_struct(incident)
+        h = C.c_void_p()
+        _check(L.sfpic3_create(C.byref(g), sp_arr, n, C.byref(inc),
+                               C.byref(self._rt), C.byref(h)))
+        del keep
+        self.h = h
+        self.nspecies = n
+        dims = (C.c_int64 * 3)()
+        _check(L.sfpic3_dims(h, dims))
+        self.shape = (int(dims[2]), int(dims[1]), int(dims[0]))
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().sfpic3_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, n=1):
+        _check(lib().sfpic3_step(self.h, int(n)))
+
+    def sync(self):
+        _check(lib().sfpic3_sync(self.h))
+
+    def field(self, comp) -> np.ndarray:
+        c = COMP[comp] if isinstance(comp, str) else int(comp)
+        out = np.empty(self.shape)
+        _check(lib().sfpic3_read_field(self.h, c, _dp(out), out.size))
+        return out
+
+    def write_field(self, comp, a):
+        c = COMP[comp] if isinstance(comp, str) else int(comp)
+        a = np.ascontiguousarray(a, dtype=np.float64)
+        if a.shape != self.shape:
+            raise ValueError(f"field must have shape {self.shape}")
+        _check(lib().sfpic3_write_field(self.h, c, _dp(a), a.size))
+
+    def particles(self, sp=0):
+        """(x, y, z, ux, uy, uz, alive) of every slot in creation order."""
+        n = C.c_int64()
+        _check(lib().sfpic3_particle_count(self.h, sp, C.byref(n)))
+        cols = [np.empty(n.value) for _ in range(6)]
+        alive = np.empty(n.value, dtype=np.uint8)
+        _check(lib().sfpic3_read_particles(
+            self.h, sp, *[_dp(c) for c in cols],
+            alive.ctypes.data_as(C.POINTER(C.c_uint8)), n.value))
+        return (*cols, alive.astype(bool))
+
+    def diagnostics(self) -> dict:
+        d = sfpic_diag()
+        _check(lib().sfpic3_diagnostics(self.h, C.byref(d)))
+        return {f: getattr(d, f) for f, _ in sfpic_diag._fields_}

@@ -7,7 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsfpic.so")
 SOURCES = ["sfpic_kernels.hip", "sfpic_push.hip", "sfpic_api.hip",
-           "sfpic_batch.hip"]
+           "sfpic_batch.hip", "sfpic3.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

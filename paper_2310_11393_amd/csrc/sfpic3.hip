@@ -1,0 +1,938 @@
+// 3D3V scattered-field PIC step (the method of Sec. 2 in three dimensions,
+// as the runs of Sec. 4 use it): Yee update of the scattered E and B with all
+// six components, order-2 gather of E^n and the centred B at the particle,
+// the full six-component April LP / RP field (Sec. 4.1) or the plane pulse
+// (Sec. 3.1) added at the particle, Boris, the 3D Esirkepov current, removal
+// at the box faces and first-order Mur on tangential E.
+//
+// Layout: one FP64 array per component, [k][j][i] with i fastest, row pitch
+// P (a multiple of 64 elements) >= NX = nx + 2G, NY = ny + 2G rows per
+// slab, NZ = nz + 2G slabs; index I holds the primal node (I - G) h or the
+// dual node (I - G + 1/2) h.  Staggering Ex(i+1/2,j,k) Ey(i,j+1/2,k)
+// Ez(i,j,k+1/2) Bx(i,j+1/2,k+1/2) By(i+1/2,j,k+1/2) Bz(i+1/2,j+1/2,k), J with
+// E.  Particles: positions in cell units (x / dx ...), FP64 momenta, a
+// removed particle has x < -1.
+//
+// The push runs one thread per particle slot: 27-tap gathers read the field
+// arrays through the caches (particles are created in cell order, so a
+// wave's lanes share most taps) and the current goes to global memory with
+// FP64 atomic adds, one per non-zero Esirkepov term.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/sfpic.h"
+#include "sfpic_common.h"
+#include "sfpic_device.h"
+
+namespace sfpic {
+int fail(int code, const std::string &msg);
+int prepare_incident_ext(const sfpic_incident *in, IncParams &P);
+}  // namespace sfpic
+
+namespace sfpic3 {
+using sfpic::IncParams;
+
+constexpr int G = SFPIC_GUARD;
+constexpr double kDead = -2.0;  // position marker of a removed particle
+
+struct Geo {
+  int NX, NY, NZ, P;  // array extents and row pitch
+  int nx, ny, nz;     // physical cells
+  __host__ __device__ size_t at(int i, int j, int k) const {
+    return ((size_t)k * NY + j) * P + i;
+  }
+};
+
+struct F3 {
+  double *e[3], *b[3], *j[3], *bb[3];  // E^n, B^{n-1/2}, J, centred B
+};
+
+struct Parts3 {
+  double *x[3], *u[3];
+};
+
+// ---------------------------------------------------------------------------
+// Yee solver
+// ---------------------------------------------------------------------------
+
+// B^{n+1/2} = B^{n-1/2} - dt curl_h E^n (forward differences), the centred
+// B = (B^{n-1/2} + B^{n+1/2}) / 2, and J = 0 ahead of the deposit.  A
+// component whose stencil would leave the array keeps its value.
+__global__ void __launch_bounds__(256)
+faraday3(F3 f, Geo g, double cx, double cy, double cz) {
+  const int i = blockIdx.x * 64 + threadIdx.x, j = blockIdx.y * 4 + threadIdx.y,
+            k = blockIdx.z;
+  if (i >= g.NX || j >= g.NY) return;
+  const size_t n = g.at(i, j, k), sj = g.P, sk = (size_t)g.P * g.NY;
+  const bool ix = i + 1 < g.NX, jy = j + 1 < g.NY, kz = k + 1 < g.NZ;
+  double o = f.b[0][n], v = o;
+  if (jy && kz)
+    v = o - (cy * (f.e[2][n + sj] - f.e[2][n]) - cz * (f.e[1][n + sk] - f.e[1][n]));
+  f.b[0][n] = v;
+  f.bb[0][n] = 0.5 * (o + v);
+  o = f.b[1][n];
+  v = o;
+  if (ix && kz)
+    v = o - (cz * (f.e[0][n + sk] - f.e[0][n]) - cx * (f.e[2][n + 1] - f.e[2][n]));
+  f.b[1][n] = v;
+  f.bb[1][n] = 0.5 * (o + v);
+  o = f.b[2][n];
+  v = o;
+  if (ix && jy)
+    v = o - (cx * (f.e[1][n + 1] - f.e[1][n]) - cy * (f.e[0][n + sj] - f.e[0][n]));
+  f.b[2][n] = v;
+  f.bb[2][n] = 0.5 * (o + v);
+  f.j[0][n] = 0.0;
+  f.j[1][n] = 0.0;
+  f.j[2][n] = 0.0;
+}
+
+// E^{n+1} = E^n + dt (curl_h B^{n+1/2} - J^{n+1/2}) (backward differences) on
+// the nodes that have both neighbours; the outer faces are left to Mur.
+__global__ void __launch_bounds__(256)
+ampere3(F3 f, Geo g, double dt, double cx, double cy, double cz) {
+  const int i = blockIdx.x * 64 + threadIdx.x, j = blockIdx.y * 4 + threadIdx.y,
+            k = blockIdx.z;
+  if (i >= g.NX || j >= g.NY) return;
+  const size_t n = g.at(i, j, k), sj = g.P, sk = (size_t)g.P * g.NY;
+  const bool xin = i >= 1 && i + 1 < g.NX, yin = j >= 1 && j + 1 < g.NY,
+             zin = k >= 1 && k + 1 < g.NZ;
+  const bool xlo = i + 1 < g.NX, ylo = j + 1 < g.NY, zlo = k + 1 < g.NZ;
+  if (xlo && yin && zin)
+    f.e[0][n] = f.e[0][n] + cy * (f.b[2][n] - f.b[2][n - sj]) -
+                cz * (f.b[1][n] - f.b[1][n - sk]) - dt * f.j[0][n];
+  if (xin && ylo && zin)
+    f.e[1][n] = f.e[1][n] + cz * (f.b[0][n] - f.b[0][n - sk]) -
+                cx * (f.b[2][n] - f.b[2][n - 1]) - dt * f.j[1][n];
+  if (xin && yin && zlo)
+    f.e[2][n] = f.e[2][n] + cx * (f.b[1][n] - f.b[1][n - 1]) -
+                cy * (f.b[0][n] - f.b[0][n - sj]) - dt * f.j[2][n];
+}
+
+// Faces normal to axis A hold the tangential components T0 = (A+1)%3 and
+// T1 = (A+2)%3.  The face buffer keeps E^n on the layers 0, 1, N-2, N-1
+// along A for both: [layer][comp][f][e] over the full cross-section.
+__host__ __device__ inline void face_axes(int A, int &e, int &fa) {
+  e = (A + 1) % 3;
+  fa = (A + 2) % 3;
+}
+__host__ __device__ inline int ext(const Geo &g, int a) {
+  return a == 0 ? g.NX : (a == 1 ? g.NY : g.NZ);
+}
+
+template <int A>
+__global__ void __launch_bounds__(256) save_faces3(F3 f, Geo g, double *buf) {
+  int e, fa;
+  face_axes(A, e, fa);
+  const int ne = ext(g, e), nf = ext(g, fa), na = ext(g, A);
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)ne * nf) return;
+  const int ie = (int)(t % ne), jf = (int)(t / ne);
+  const int layers[4] = {0, 1, na - 2, na - 1};
+#pragma unroll
+  for (int l = 0; l < 4; ++l) {
+    int idx[3];
+    idx[A] = layers[l];
+    idx[e] = ie;
+    idx[fa] = jf;
+    const size_t n = g.at(idx[0], idx[1], idx[2]);
+    buf[((size_t)(l * 2 + 0) * nf + jf) * ne + ie] = f.e[e][n];
+    buf[((size_t)(l * 2 + 1) * nf + jf) * ne + ie] = f.e[fa][n];
+  }
+}
+
+// First-order Mur on the two faces normal to A: E_b^{n+1} = E_in^n +
+// k (E_in^{n+1} - E_b^n), over every index a component occupies (the last
+// index along an axis where it is dual is outside the grid).
+template <int A>
+__global__ void __launch_bounds__(256)
+mur3(F3 f, Geo g, const double *buf, double kf) {
+  int e, fa;
+  face_axes(A, e, fa);
+  const int ne = ext(g, e), nf = ext(g, fa), na = ext(g, A);
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)ne * nf) return;
+  const int ie = (int)(t % ne), jf = (int)(t / ne);
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    const int comp = c == 0 ? e : fa;  // E component index
+    // component comp is dual along its own axis only
+    const int dual_e = (comp == e), dual_f = (comp == fa);
+    if (ie >= ne - dual_e || jf >= nf - dual_f) continue;
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+      int ib[3], ii[3];
+      ib[A] = side ? na - 1 : 0;
+      ii[A] = side ? na - 2 : 1;
+      ib[e] = ii[e] = ie;
+      ib[fa] = ii[fa] = jf;
+      const int lb = side ? 3 : 0, li = side ? 2 : 1;
+      const double in_old = buf[((size_t)(li * 2 + c) * nf + jf) * ne + ie];
+      const double b_old = buf[((size_t)(lb * 2 + c) * nf + jf) * ne + ie];
+      const double in_new = f.e[comp][g.at(ii[0], ii[1], ii[2])];
+      f.e[comp][g.at(ib[0], ib[1], ib[2])] = in_old + kf * (in_new - b_old);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Particles
+// ---------------------------------------------------------------------------
+
+// Incident field at (x, y, z), time t, build axes (the paper's (z, x, y)).
+__device__ __forceinline__ void incident3(const IncParams &P, double z_focus,
+                                          double x, double y, double z,
+                                          double t, double E[3], double B[3]) {
+#pragma unroll
+  for (int c = 0; c < 3; ++c) E[c] = B[c] = 0.0;
+  if (P.kind == SFPIC_INC_PLANE_PULSE_1D) {
+    const double ph = t - P.t0 - x;
+    const double v = P.a0 * sin(ph) * exp2(P.env_k * ph * ph);
+    E[1] = v;
+    B[2] = v;
+  } else if (P.kind == SFPIC_INC_APRIL_LP || P.kind == SFPIC_INC_APRIL_RP) {
+    const double X = (y - P.y_focus) * P.inv_a;  // paper x
+    const double Y = (z - z_focus) * P.inv_a;    // paper y
+    const double Z = (x - P.x_focus) * P.inv_a;  // paper z
+    sfpic::cx<double> e[3], b[3];
+    sfpic::april_complex_fields(P, X, Y, Z, t - P.t_focus, e, b);
+    E[0] = e[2].r;
+    E[1] = e[0].r;
+    E[2] = e[1].r;
+    B[0] = b[2].r;
+    B[1] = b[0].r;
+    B[2] = b[1].r;
+  }
+}
+
+// Three order-2 weights of the node nearest to xi (primal nodes at integers,
+// dual at half-integers) and the array index of the first tap.
+__device__ __forceinline__ int taps3(double xi, int dual, double w[3]) {
+  const double s = dual ? xi - 0.5 : xi;
+  const double c = floor(s + 0.5);
+  sfpic::weights3(s - c, w);
+  return (int)c - 1 + G;
+}
+
+__device__ __forceinline__ double gather27(const double *__restrict__ a,
+                                           const Geo &g, const int b[3],
+                                           const double *wx, const double *wy,
+                                           const double *wz) {
+  double v = 0.0;
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int bb = 0; bb < 3; ++bb) {
+      const double *row = a + g.at(b[0], b[1] + bb, b[2] + c);
+      v += wx[0] * wy[bb] * wz[c] * row[0] + wx[1] * wy[bb] * wz[c] * row[1] +
+           wx[2] * wy[bb] * wz[c] * row[2];
+    }
+  return v;
+}
+
+struct PushArgs {
+  double dt, qm, qw;
+  double inv_h[3], h_over_dt[3];  // 1/h, h/dt
+  double h[3];
+  double time, z_focus;
+};
+
+__global__ void __launch_bounds__(256)
+push3(F3 f, Geo g, Parts3 p, int64_t n, PushArgs a, IncParams inc) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  double xi[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) xi[d] = p.x[d][s];
+  if (xi[0] < -1.0) return;  // removed
+  // gather E^n and the centred B at x^n
+  double wp[3][3], wd[3][3];
+  int bp[3], bd[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    bp[d] = taps3(xi[d], 0, wp[d]);
+    bd[d] = taps3(xi[d], 1, wd[d]);
+  }
+  double E[3], B[3];
+  {
+    const int b0[3] = {bd[0], bp[1], bp[2]};
+    E[0] = gather27(f.e[0], g, b0, wd[0], wp[1], wp[2]);
+    const int b1[3] = {bp[0], bd[1], bp[2]};
+    E[1] = gather27(f.e[1], g, b1, wp[0], wd[1], wp[2]);
+    const int b2[3] = {bp[0], bp[1], bd[2]};
+    E[2] = gather27(f.e[2], g, b2, wp[0], wp[1], wd[2]);
+    const int b3[3] = {bp[0], bd[1], bd[2]};
+    B[0] = gather27(f.bb[0], g, b3, wp[0], wd[1], wd[2]);
+    const int b4[3] = {bd[0], bp[1], bd[2]};
+    B[1] = gather27(f.bb[1], g, b4, wd[0], wp[1], wd[2]);
+    const int b5[3] = {bd[0], bd[1], bp[2]};
+    B[2] = gather27(f.bb[2], g, b5, wd[0], wd[1], wp[2]);
+  }
+  if (inc.kind != SFPIC_INC_NONE) {
+    double Ei[3], Bi[3];
+    incident3(inc, a.z_focus, xi[0] * a.h[0], xi[1] * a.h[1], xi[2] * a.h[2],
+              a.time, Ei, Bi);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      E[c] += Ei[c];
+      B[c] += Bi[c];
+    }
+  }
+  double u[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) u[d] = p.u[d][s];
+  sfpic::boris<double>(a.qm, a.dt, u, E, B);
+  const double gi = sfpic::rsqrt(1.0 + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+  // Esirkepov: shapes on the 5 nodes c0 - 2 .. c0 + 2 around the old
+  // nearest node, before (S0) and after the move, D = S1 - S0
+  double S0[3][5], D[3][5], x1[3];
+  int c0[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    x1[d] = xi[d] + a.dt * a.inv_h[d] * (u[d] * gi);
+    const double c = floor(xi[d] + 0.5);
+    c0[d] = (int)c;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      const double node = c + (double)(k - 2);
+      S0[d][k] = sfpic::spline2(xi[d] - node);
+      D[d][k] = sfpic::spline2(x1[d] - node) - S0[d][k];
+    }
+  }
+  constexpr double third = 1.0 / 3.0;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const int e = (d + 1) % 3, fa = (d + 2) % 3;
+    const double scale = -a.qw * a.h_over_dt[d];
+    for (int kf = 0; kf < 5; ++kf)
+      for (int ke = 0; ke < 5; ++ke) {
+        const double se = S0[e][ke], de = D[e][ke], sf = S0[fa][kf],
+                     df = D[fa][kf];
+        const double tw = se * sf + 0.5 * de * sf + 0.5 * se * df + de * df * third;
+        if (tw == 0.0) continue;
+        double acc = 0.0;
+#pragma unroll
+        for (int kd = 0; kd < 4; ++kd) {
+          acc += scale * (D[d][kd] * tw);
+          if (acc != 0.0) {
+            int idx[3];
+            idx[d] = c0[d] - 2 + kd + G;
+            idx[e] = c0[e] - 2 + ke + G;
+            idx[fa] = c0[fa] - 2 + kf + G;
+            atomicAdd(f.j[d] + g.at(idx[0], idx[1], idx[2]), acc);
+          }
+        }
+      }
+  }
+  // written as "inside" so that a non-finite position is removed too (it
+  // would otherwise index the field arrays on the next step)
+  const bool out = !(x1[0] >= 0.0 && x1[0] < (double)g.nx && x1[1] >= 0.0 &&
+                     x1[1] < (double)g.ny && x1[2] >= 0.0 &&
+                     x1[2] < (double)g.nz);
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    p.x[d][s] = (d == 0 && out) ? kDead : x1[d];
+    p.u[d][s] = u[d];
+  }
+}
+
+// Explicit particles: physical positions to cell units.
+__global__ void load3(Parts3 p, int64_t n, const double *x, const double *y,
+                      const double *z, const double *ux, const double *uy,
+                      const double *uz, double ihx, double ihy, double ihz) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  p.x[0][i] = x[i] * ihx;
+  p.x[1][i] = y[i] * ihy;
+  p.x[2][i] = z[i] * ihz;
+  p.u[0][i] = ux[i];
+  p.u[1][i] = uy[i];
+  p.u[2][i] = uz[i];
+}
+
+// Generated particles: ppc per cell of the region, uniform in the cell, the
+// Philox4x32-10 stream keyed by (seed, species index) with counter (id, word
+// 2 = 0 / 1 / 2 / 3); momenta Maxwellian of width sigma (Box-Muller).
+__global__ void init3(Parts3 p, int64_t n, int64_t x0, int64_t y0, int64_t z0,
+                      int64_t ncx, int64_t ncy, int ppc, double sigma,
+                      uint32_t k0, uint32_t k1) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t cell = i / ppc;
+  const int64_t cx = x0 + cell % ncx, cy = y0 + (cell / ncx) % ncy,
+                cz = z0 + cell / (ncx * ncy);
+  const uint32_t lo = (uint32_t)i, hi = (uint32_t)((uint64_t)i >> 32);
+  uint32_t c[4] = {lo, hi, 0u, 0u}, c3[4] = {lo, hi, 3u, 0u};
+  sfpic::philox4x32_10(c, k0, k1);
+  sfpic::philox4x32_10(c3, k0, k1);
+  double a, b, cc, unused;
+  sfpic::u01_pair(c, a, b);
+  sfpic::u01_pair(c3, cc, unused);
+  double ux = 0.0, uy = 0.0, uz = 0.0;
+  if (sigma > 0.0) {
+    uint32_t c1[4] = {lo, hi, 1u, 0u}, c2[4] = {lo, hi, 2u, 0u};
+    sfpic::philox4x32_10(c1, k0, k1);
+    sfpic::philox4x32_10(c2, k0, k1);
+    double a1, b1, a2, b2;
+    sfpic::u01_pair(c1, a1, b1);
+    sfpic::u01_pair(c2, a2, b2);
+    const double r1 = sqrt(-2.0 * log1p(-a1)), r2 = sqrt(-2.0 * log1p(-a2));
+    const double tp = 6.283185307179586;
+    ux = sigma * r1 * cos(tp * b1);
+    uy = sigma * r1 * sin(tp * b1);
+    uz = sigma * r2 * cos(tp * b2);
+  }
+  p.x[0][i] = (double)cx + a;
+  p.x[1][i] = (double)cy + b;
+  p.x[2][i] = (double)cz + cc;
+  p.u[0][i] = ux;
+  p.u[1][i] = uy;
+  p.u[2][i] = uz;
+}
+
+// ---------------------------------------------------------------------------
+// Diagnostics
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ double block_sum(double v, double *sh) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0)
+    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) t += sh[k];
+  __syncthreads();
+  return t;
+}
+
+// acc[0] += sum (gamma - 1), acc[1] += live count; flag |= 1 on non-finite
+__global__ void __launch_bounds__(256)
+psums3(Parts3 p, int64_t n, double *acc, int *flag) {
+  __shared__ double sh[4];
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double g1 = 0.0, cnt = 0.0;
+  if (s < n && p.x[0][s] >= -1.0) {
+    const double u0 = p.u[0][s], u1 = p.u[1][s], u2 = p.u[2][s];
+    const double q = u0 * u0 + u1 * u1 + u2 * u2;
+    if (!isfinite(q)) atomicOr(flag, 1);
+    g1 = q / (sqrt(1.0 + q) + 1.0);  // gamma - 1 without cancellation
+    cnt = 1.0;
+  }
+  g1 = block_sum(g1, sh);
+  cnt = block_sum(cnt, sh);
+  if (threadIdx.x == 0) {
+    atomicAdd(acc, g1);
+    atomicAdd(acc + 1, cnt);
+  }
+}
+
+// acc[0] += 1/2 sum over every array element of E^2 + B^2
+__global__ void __launch_bounds__(256)
+fsums3(F3 f, size_t n, double *acc, int *flag) {
+  __shared__ double sh[4];
+  const size_t s = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double v = 0.0;
+  if (s < n) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) v += f.e[c][s] * f.e[c][s] + f.b[c][s] * f.b[c][s];
+    if (!isfinite(v)) atomicOr(flag, 1);
+  }
+  v = block_sum(0.5 * v, sh);
+  if (threadIdx.x == 0) atomicAdd(acc, v);
+}
+
+// rho += q w S(x) on the primal nodes (order-2, 27 nodes per particle)
+__global__ void __launch_bounds__(256)
+rho3(Parts3 p, int64_t n, Geo g, double qw, double *rho) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  double xi[3], w[3][3];
+  int b[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) xi[d] = p.x[d][s];
+  if (xi[0] < -1.0) return;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) b[d] = taps3(xi[d], 0, w[d]);
+  for (int c = 0; c < 3; ++c)
+    for (int bb = 0; bb < 3; ++bb)
+      for (int aa = 0; aa < 3; ++aa)
+        atomicAdd(rho + g.at(b[0] + aa, b[1] + bb, b[2] + c),
+                  qw * w[0][aa] * w[1][bb] * w[2][c]);
+}
+
+// max |div_h E - (rho - rho0)| and max |rho - rho0| over nodes at least 4
+// cells inside the physical box (non-negative doubles order as integers)
+__global__ void __launch_bounds__(256)
+gauss3(F3 f, Geo g, const double *rho, const double *rho0, double ihx,
+       double ihy, double ihz, unsigned long long *mx) {
+  const int i = blockIdx.x * 64 + threadIdx.x, j = blockIdx.y * 4 + threadIdx.y,
+            k = blockIdx.z;
+  const int lo = G + 4;
+  if (i < lo || j < lo || k < lo || i > G + g.nx - 4 || j > G + g.ny - 4 ||
+      k > G + g.nz - 4)
+    return;
+  const size_t n = g.at(i, j, k), sj = g.P, sk = (size_t)g.P * g.NY;
+  const double div = (f.e[0][n] - f.e[0][n - 1]) * ihx +
+                     (f.e[1][n] - f.e[1][n - sj]) * ihy +
+                     (f.e[2][n] - f.e[2][n - sk]) * ihz;
+  const double dr = rho[n] - rho0[n];
+  atomicMax(mx, (unsigned long long)__double_as_longlong(fabs(div - dr)));
+  atomicMax(mx + 1, (unsigned long long)__double_as_longlong(fabs(dr)));
+}
+
+}  // namespace sfpic3
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+using namespace sfpic3;
+
+struct Species3 {
+  double q = -1.0, m = 1.0, w = 0.0;
+  int64_t n = 0;
+  Parts3 p{};
+};
+
+struct sfpic3_sim {
+  sfpic3_grid grid{};
+  sfpic_runtime rt{};
+  hipStream_t st = nullptr;
+  Geo g{};
+  size_t plane = 0;  // elements per field array
+  IncParams inc{};
+  double z_focus = 0.0;
+  int64_t step = 0;
+  F3 f{};
+  double *face[3] = {};
+  std::vector<Species3> sp;
+  double *rho0 = nullptr, *rho = nullptr, *acc = nullptr;
+  std::vector<std::pair<void *, size_t>> allocs;
+
+  void *dalloc(size_t bytes) {
+    bytes = (bytes + 255) & ~(size_t)255;
+    void *p = nullptr;
+    if (rt.alloc)
+      p = rt.alloc(bytes, rt.alloc_ctx);
+    else if (hipMalloc(&p, bytes) != hipSuccess)
+      p = nullptr;
+    if (p) allocs.emplace_back(p, bytes);
+    return p;
+  }
+  void release() {
+    for (auto &a : allocs) {
+      if (rt.free)
+        rt.free(a.first, a.second, rt.alloc_ctx);
+      else
+        (void)hipFree(a.first);
+    }
+    allocs.clear();
+  }
+};
+
+namespace {
+
+#define HIP3(expr)                                                        \
+  do {                                                                    \
+    hipError_t e_ = (expr);                                               \
+    if (e_ != hipSuccess)                                                 \
+      return sfpic::fail(SFPIC_E_DEVICE,                                  \
+                         std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+dim3 node_grid(const Geo &g) {
+  return dim3((unsigned)((g.NX + 63) / 64), (unsigned)((g.NY + 3) / 4),
+              (unsigned)g.NZ);
+}
+
+unsigned blocks_for(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+template <int A>
+int face_pass(sfpic3_sim *S, bool save, double kf) {
+  int e, fa;
+  face_axes(A, e, fa);
+  const int64_t area = (int64_t)ext(S->g, e) * ext(S->g, fa);
+  if (save)
+    save_faces3<A><<<blocks_for(area), 256, 0, S->st>>>(S->f, S->g, S->face[A]);
+  else
+    mur3<A><<<blocks_for(area), 256, 0, S->st>>>(S->f, S->g, S->face[A], kf);
+  HIP3(hipGetLastError());
+  return SFPIC_OK;
+}
+
+int one_step(sfpic3_sim *S) {
+  const sfpic3_grid &gr = S->grid;
+  const double dt = gr.dt;
+  const double cx = dt / gr.dx, cy = dt / gr.dy, cz = dt / gr.dz;
+  faraday3<<<node_grid(S->g), dim3(64, 4), 0, S->st>>>(S->f, S->g, cx, cy, cz);
+  HIP3(hipGetLastError());
+  PushArgs a{};
+  a.dt = dt;
+  a.h[0] = gr.dx;
+  a.h[1] = gr.dy;
+  a.h[2] = gr.dz;
+  for (int d = 0; d < 3; ++d) {
+    a.inv_h[d] = 1.0 / a.h[d];
+    a.h_over_dt[d] = a.h[d] / dt;
+  }
+  a.time = (double)S->step * dt;
+  a.z_focus = S->z_focus;
+  for (auto &sp : S->sp) {
+    if (sp.n == 0) continue;
+    a.qm = sp.q / sp.m;
+    a.qw = sp.q * sp.w;
+    push3<<<blocks_for(sp.n), 256, 0, S->st>>>(S->f, S->g, sp.p, sp.n, a,
+                                               S->inc);
+    HIP3(hipGetLastError());
+  }
+  if (int r = face_pass<0>(S, true, 0.0)) return r;
+  if (int r = face_pass<1>(S, true, 0.0)) return r;
+  if (int r = face_pass<2>(S, true, 0.0)) return r;
+  ampere3<<<node_grid(S->g), dim3(64, 4), 0, S->st>>>(S->f, S->g, dt, cx, cy,
+                                                      cz);
+  HIP3(hipGetLastError());
+  const double kx = (dt - gr.dx) / (dt + gr.dx), ky = (dt - gr.dy) / (dt + gr.dy),
+               kz = (dt - gr.dz) / (dt + gr.dz);
+  if (int r = face_pass<2>(S, false, kz)) return r;  // z faces first
+  if (int r = face_pass<1>(S, false, ky)) return r;
+  if (int r = face_pass<0>(S, false, kx)) return r;
+  S->step++;
+  return SFPIC_OK;
+}
+
+int deposit_rho(sfpic3_sim *S, double *rho) {
+  HIP3(hipMemsetAsync(rho, 0, S->plane * 8, S->st));
+  for (auto &sp : S->sp) {
+    if (sp.n == 0) continue;
+    rho3<<<blocks_for(sp.n), 256, 0, S->st>>>(sp.p, sp.n, S->g, sp.q * sp.w,
+                                              rho);
+    HIP3(hipGetLastError());
+  }
+  return SFPIC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sfpic3_create(const sfpic3_grid *grid, const sfpic3_species *species,
+                  int nspecies, const sfpic_incident *incident,
+                  const sfpic_runtime *runtime, sfpic3_sim **out) {
+  if (!out) return sfpic::fail(SFPIC_E_INVAL, "out is NULL");
+  *out = nullptr;
+  if (!grid) return sfpic::fail(SFPIC_E_INVAL, "grid is NULL");
+  const sfpic3_grid &g = *grid;
+  if (g.nx < 1 || g.ny < 1 || g.nz < 1 || g.nx > 32768 || g.ny > 32768 ||
+      g.nz > 32768)
+    return sfpic::fail(SFPIC_E_INVAL, "3D grid needs 1 <= nx, ny, nz <= 32768");
+  if (!(g.dx > 0.0) || !(g.dy > 0.0) || !(g.dz > 0.0) || !(g.dt > 0.0))
+    return sfpic::fail(SFPIC_E_INVAL, "3D grid needs dx, dy, dz, dt > 0");
+  const double cfl =
+      g.dt * std::sqrt(1.0 / (g.dx * g.dx) + 1.0 / (g.dy * g.dy) +
+                       1.0 / (g.dz * g.dz));
+  if (!(cfl < 1.0)) return sfpic::fail(SFPIC_E_INVAL, "dt violates the 3D Yee CFL limit");
+  if (nspecies < 0 || (nspecies > 0 && !species))
+    return sfpic::fail(SFPIC_E_INVAL, "bad species list");
+  IncParams P{};
+  if (int r = sfpic::prepare_incident_ext(incident, P)) return r;
+  if (P.kind == SFPIC_INC_GAUSS_2D)
+    return sfpic::fail(SFPIC_E_INVAL, "the paraxial Gaussian beam is 2D only");
+  if (P.on_nodes)
+    return sfpic::fail(SFPIC_E_INVAL, "3D runs evaluate the incident field at the particles (on_nodes = 0)");
+  // particles: validate on the host before anything is allocated
+  for (int s = 0; s < nspecies; ++s) {
+    const sfpic3_species &d = species[s];
+    if (!(d.m > 0.0) || !std::isfinite(d.q))
+      return sfpic::fail(SFPIC_E_INVAL, "species needs m > 0 and finite q");
+    if (d.n_explicit > 0) {
+      if (!d.x || !d.y || !d.z || !d.ux || !d.uy || !d.uz)
+        return sfpic::fail(SFPIC_E_INVAL, "explicit species needs all six arrays");
+      if (!std::isfinite(d.weight))
+        return sfpic::fail(SFPIC_E_INVAL, "explicit species needs a finite weight");
+      const double hi[3] = {g.nx * g.dx, g.ny * g.dy, g.nz * g.dz};
+      const double *xs[3] = {d.x, d.y, d.z};
+      for (int64_t i = 0; i < d.n_explicit; ++i) {
+        for (int a = 0; a < 3; ++a)
+          if (!(xs[a][i] >= 0.0 && xs[a][i] < hi[a]))
+            return sfpic::fail(SFPIC_E_INVAL, "explicit particle outside the box");
+        if (!std::isfinite(d.ux[i]) || !std::isfinite(d.uy[i]) ||
+            !std::isfinite(d.uz[i]))
+          return sfpic::fail(SFPIC_E_INVAL, "non-finite explicit momentum");
+      }
+    } else if (d.n_explicit == 0 && d.ppc > 0) {
+      const int64_t *r = d.region;
+      if (!(r[0] >= 0 && r[0] < r[1] && r[1] <= g.nx && r[2] >= 0 &&
+            r[2] < r[3] && r[3] <= g.ny && r[4] >= 0 && r[4] < r[5] &&
+            r[5] <= g.nz))
+        return sfpic::fail(SFPIC_E_INVAL, "species region outside the grid");
+      if (d.temperature_ev < 0.0 || !std::isfinite(d.density))
+        return sfpic::fail(SFPIC_E_INVAL, "bad density or temperature");
+      const int64_t np = (r[1] - r[0]) * (r[3] - r[2]) * (r[5] - r[4]) * d.ppc;
+      if (np > ((int64_t)1 << 34))
+        return sfpic::fail(SFPIC_E_SIZE, "too many generated particles");
+    } else if (d.n_explicit < 0 || d.ppc < 0) {
+      return sfpic::fail(SFPIC_E_INVAL, "negative particle count");
+    }
+  }
+  HIP3(hipSetDevice(runtime ? runtime->device : 0));
+  sfpic3_sim *S = new sfpic3_sim();
+  S->grid = g;
+  if (runtime) S->rt = *runtime;
+  S->st = (hipStream_t)S->rt.stream;
+  S->inc = P;
+  S->z_focus = incident ? incident->z_focus : 0.0;
+  S->g.nx = (int)g.nx;
+  S->g.ny = (int)g.ny;
+  S->g.nz = (int)g.nz;
+  S->g.NX = (int)g.nx + 2 * G;
+  S->g.NY = (int)g.ny + 2 * G;
+  S->g.NZ = (int)g.nz + 2 * G;
+  S->g.P = (S->g.NX + 63) / 64 * 64;
+  S->plane = (size_t)S->g.P * S->g.NY * S->g.NZ;
+  auto fail_free = [&](int code, const char *msg) {
+    S->release();
+    delete S;
+    return sfpic::fail(code, msg);
+  };
+  double *planes[12];
+  for (int c = 0; c < 12; ++c) {
+    planes[c] = (double *)S->dalloc(S->plane * 8);
+    if (!planes[c]) return fail_free(SFPIC_E_NOMEM, "field allocation failed");
+    if (hipMemsetAsync(planes[c], 0, S->plane * 8, S->st) != hipSuccess)
+      return fail_free(SFPIC_E_DEVICE, "field clear failed");
+  }
+  for (int c = 0; c < 3; ++c) {
+    S->f.e[c] = planes[c];
+    S->f.b[c] = planes[3 + c];
+    S->f.j[c] = planes[6 + c];
+    S->f.bb[c] = planes[9 + c];
+  }
+  for (int A = 0; A < 3; ++A) {
+    int e, fa;
+    face_axes(A, e, fa);
+    S->face[A] = (double *)S->dalloc((size_t)8 * 8 * ext(S->g, e) * ext(S->g, fa));
+    if (!S->face[A]) return fail_free(SFPIC_E_NOMEM, "face buffer allocation failed");
+  }
+  S->rho0 = (double *)S->dalloc(S->plane * 8);
+  S->rho = (double *)S->dalloc(S->plane * 8);
+  S->acc = (double *)S->dalloc(64);
+  if (!S->rho0 || !S->rho || !S->acc)
+    return fail_free(SFPIC_E_NOMEM, "diagnostic allocation failed");
+  for (int s = 0; s < nspecies; ++s) {
+    const sfpic3_species &d = species[s];
+    Species3 sp;
+    sp.q = d.q;
+    sp.m = d.m;
+    if (d.n_explicit > 0) {
+      sp.n = d.n_explicit;
+      sp.w = d.weight;
+    } else if (d.ppc > 0) {
+      const int64_t *r = d.region;
+      sp.n = (r[1] - r[0]) * (r[3] - r[2]) * (r[5] - r[4]) * d.ppc;
+      sp.w = d.density / d.ppc;
+    }
+    if (sp.n > 0) {
+      for (int a = 0; a < 3; ++a) {
+        sp.p.x[a] = (double *)S->dalloc((size_t)sp.n * 8);
+        sp.p.u[a] = (double *)S->dalloc((size_t)sp.n * 8);
+        if (!sp.p.x[a] || !sp.p.u[a])
+          return fail_free(SFPIC_E_NOMEM, "particle allocation failed");
+      }
+      if (d.n_explicit > 0) {
+        const size_t b = (size_t)sp.n * 8;
+        double *tmp = (double *)S->dalloc(6 * b);
+        if (!tmp) return fail_free(SFPIC_E_NOMEM, "staging allocation failed");
+        const double *src[6] = {d.x, d.y, d.z, d.ux, d.uy, d.uz};
+        for (int c = 0; c < 6; ++c)
+          if (hipMemcpyAsync((char *)tmp + c * b, src[c], b,
+                             hipMemcpyHostToDevice, S->st) != hipSuccess)
+            return fail_free(SFPIC_E_DEVICE, "particle upload failed");
+        load3<<<blocks_for(sp.n), 256, 0, S->st>>>(
+            sp.p, sp.n, tmp, tmp + sp.n, tmp + 2 * sp.n, tmp + 3 * sp.n,
+            tmp + 4 * sp.n, tmp + 5 * sp.n, 1.0 / g.dx, 1.0 / g.dy, 1.0 / g.dz);
+        if (hipStreamSynchronize(S->st) != hipSuccess)
+          return fail_free(SFPIC_E_DEVICE, "particle upload failed");
+        for (size_t k = 0; k < S->allocs.size(); ++k)
+          if (S->allocs[k].first == tmp) {
+            if (S->rt.free)
+              S->rt.free(tmp, S->allocs[k].second, S->rt.alloc_ctx);
+            else
+              (void)hipFree(tmp);
+            S->allocs.erase(S->allocs.begin() + (long)k);
+            break;
+          }
+      } else {
+        const int64_t *r = d.region;
+        const double sigma =
+            d.temperature_ev > 0.0 ? std::sqrt(d.temperature_ev / (510998.95 * d.m)) : 0.0;
+        init3<<<blocks_for(sp.n), 256, 0, S->st>>>(
+            sp.p, sp.n, r[0], r[2], r[4], r[1] - r[0], r[3] - r[2], d.ppc,
+            sigma, (uint32_t)d.seed, (uint32_t)d.species_index);
+        if (hipGetLastError() != hipSuccess)
+          return fail_free(SFPIC_E_DEVICE, "particle generation failed");
+      }
+    }
+    S->sp.push_back(sp);
+  }
+  if (deposit_rho(S, S->rho0) != SFPIC_OK ||
+      hipStreamSynchronize(S->st) != hipSuccess)
+    return fail_free(SFPIC_E_DEVICE, "initial charge density failed");
+  *out = S;
+  return SFPIC_OK;
+}
+
+int sfpic3_step(sfpic3_sim *sim, int64_t nsteps) {
+  if (!sim || nsteps < 0) return sfpic::fail(SFPIC_E_INVAL, "bad step call");
+  for (int64_t k = 0; k < nsteps; ++k)
+    if (int r = one_step(sim)) return r;
+  return SFPIC_OK;
+}
+
+int sfpic3_sync(sfpic3_sim *sim) {
+  if (!sim) return sfpic::fail(SFPIC_E_INVAL, "sim is NULL");
+  HIP3(hipStreamSynchronize(sim->st));
+  return SFPIC_OK;
+}
+
+int sfpic3_dims(const sfpic3_sim *sim, int64_t out[3]) {
+  if (!sim || !out) return sfpic::fail(SFPIC_E_INVAL, "NULL argument");
+  out[0] = sim->g.NX;
+  out[1] = sim->g.NY;
+  out[2] = sim->g.NZ;
+  return SFPIC_OK;
+}
+
+static double *comp_ptr(sfpic3_sim *S, int comp) {
+  if (comp < 0 || comp >= SFPIC_NCOMP) return nullptr;
+  if (comp < 3) return S->f.e[comp];
+  if (comp < 6) return S->f.b[comp - 3];
+  return S->f.j[comp - 6];
+}
+
+int sfpic3_read_field(sfpic3_sim *sim, int comp, double *out, size_t n) {
+  if (!sim || !out) return sfpic::fail(SFPIC_E_INVAL, "NULL argument");
+  double *src = comp_ptr(sim, comp);
+  if (!src) return sfpic::fail(SFPIC_E_INVAL, "bad field component");
+  const Geo &g = sim->g;
+  if (n != (size_t)g.NX * g.NY * g.NZ)
+    return sfpic::fail(SFPIC_E_SIZE, "field buffer must hold NX*NY*NZ values");
+  HIP3(hipMemcpy2DAsync(out, (size_t)g.NX * 8, src, (size_t)g.P * 8,
+                        (size_t)g.NX * 8, (size_t)g.NY * g.NZ,
+                        hipMemcpyDeviceToHost, sim->st));
+  HIP3(hipStreamSynchronize(sim->st));
+  return SFPIC_OK;
+}
+
+int sfpic3_write_field(sfpic3_sim *sim, int comp, const double *in, size_t n) {
+  if (!sim || !in) return sfpic::fail(SFPIC_E_INVAL, "NULL argument");
+  if (comp < 0 || comp >= 6)
+    return sfpic::fail(SFPIC_E_INVAL, "only E and B can be written");
+  double *dst = comp_ptr(sim, comp);
+  const Geo &g = sim->g;
+  if (n != (size_t)g.NX * g.NY * g.NZ)
+    return sfpic::fail(SFPIC_E_SIZE, "field buffer must hold NX*NY*NZ values");
+  HIP3(hipMemcpy2DAsync(dst, (size_t)g.P * 8, in, (size_t)g.NX * 8,
+                        (size_t)g.NX * 8, (size_t)g.NY * g.NZ,
+                        hipMemcpyHostToDevice, sim->st));
+  HIP3(hipStreamSynchronize(sim->st));
+  return SFPIC_OK;
+}
+
+int sfpic3_particle_count(sfpic3_sim *sim, int species, int64_t *n) {
+  if (!sim || !n) return sfpic::fail(SFPIC_E_INVAL, "NULL argument");
+  if (species < 0 || species >= (int)sim->sp.size())
+    return sfpic::fail(SFPIC_E_INVAL, "bad species index");
+  *n = sim->sp[species].n;
+  return SFPIC_OK;
+}
+
+int sfpic3_read_particles(sfpic3_sim *sim, int species, double *x, double *y,
+                          double *z, double *ux, double *uy, double *uz,
+                          uint8_t *alive, size_t n) {
+  if (!sim || !x || !y || !z || !ux || !uy || !uz || !alive)
+    return sfpic::fail(SFPIC_E_INVAL, "NULL argument");
+  if (species < 0 || species >= (int)sim->sp.size())
+    return sfpic::fail(SFPIC_E_INVAL, "bad species index");
+  const Species3 &sp = sim->sp[species];
+  if (n != (size_t)sp.n)
+    return sfpic::fail(SFPIC_E_SIZE, "particle buffers must hold the slot count");
+  if (n == 0) return SFPIC_OK;
+  double *dst[6] = {x, y, z, ux, uy, uz};
+  for (int a = 0; a < 3; ++a) {
+    HIP3(hipMemcpyAsync(dst[a], sp.p.x[a], n * 8, hipMemcpyDeviceToHost, sim->st));
+    HIP3(hipMemcpyAsync(dst[3 + a], sp.p.u[a], n * 8, hipMemcpyDeviceToHost,
+                        sim->st));
+  }
+  HIP3(hipStreamSynchronize(sim->st));
+  const double h[3] = {sim->grid.dx, sim->grid.dy, sim->grid.dz};
+  for (size_t i = 0; i < n; ++i) {
+    alive[i] = x[i] >= -1.0;
+    for (int a = 0; a < 3; ++a) dst[a][i] *= h[a];
+  }
+  return SFPIC_OK;
+}
+
+int sfpic3_diagnostics(sfpic3_sim *sim, sfpic_diag *out) {
+  if (!sim || !out) return sfpic::fail(SFPIC_E_INVAL, "NULL argument");
+  sfpic3_sim *S = sim;
+  const sfpic3_grid &g = S->grid;
+  const double dV = g.dx * g.dy * g.dz;
+  memset(out, 0, sizeof(*out));
+  out->step = S->step;
+  out->time = (double)S->step * g.dt;
+  int *flag = (int *)(S->acc + 7);
+  std::vector<double> host(8);
+  for (auto &sp : S->sp) {
+    HIP3(hipMemsetAsync(S->acc, 0, 64, S->st));
+    if (sp.n > 0) {
+      psums3<<<blocks_for(sp.n), 256, 0, S->st>>>(sp.p, sp.n, S->acc, flag);
+      HIP3(hipGetLastError());
+    }
+    HIP3(hipMemcpyAsync(host.data(), S->acc, 64, hipMemcpyDeviceToHost, S->st));
+    HIP3(hipStreamSynchronize(S->st));
+    int fl = 0;
+    memcpy(&fl, &host[7], sizeof(int));
+    out->w_kin += sp.w * sp.m * host[0] * dV;
+    out->charge += sp.q * sp.w * host[1] * dV;
+    out->n_alive += (int64_t)host[1];
+    out->nonfinite |= fl;
+  }
+  HIP3(hipMemsetAsync(S->acc, 0, 64, S->st));
+  fsums3<<<blocks_for((int64_t)S->plane), 256, 0, S->st>>>(S->f, S->plane,
+                                                           S->acc, flag);
+  HIP3(hipGetLastError());
+  if (int r = deposit_rho(S, S->rho)) return r;
+  unsigned long long *mx = (unsigned long long *)(S->acc + 2);
+  gauss3<<<node_grid(S->g), dim3(64, 4), 0, S->st>>>(
+      S->f, S->g, S->rho, S->rho0, 1.0 / g.dx, 1.0 / g.dy, 1.0 / g.dz, mx);
+  HIP3(hipGetLastError());
+  HIP3(hipMemcpyAsync(host.data(), S->acc, 64, hipMemcpyDeviceToHost, S->st));
+  HIP3(hipStreamSynchronize(S->st));
+  out->w_em = host[0] * dV;
+  unsigned long long r0 = 0, r1 = 0;
+  memcpy(&r0, &host[2], 8);
+  memcpy(&r1, &host[3], 8);
+  double gr = 0.0, rm = 0.0;
+  memcpy(&gr, &r0, 8);
+  memcpy(&rm, &r1, 8);
+  out->gauss_residual = gr;
+  out->rho_max = rm;
+  int fl = 0;
+  memcpy(&fl, &host[7], sizeof(int));
+  out->nonfinite |= fl;
+  out->w_em_total = NAN;  // not evaluated in 3D
+  return SFPIC_OK;
+}
+
+void sfpic3_destroy(sfpic3_sim *sim) {
+  if (!sim) return;
+  (void)hipStreamSynchronize(sim->st);
+  sim->release();
+  delete sim;
+}
+
+}  // extern "C"

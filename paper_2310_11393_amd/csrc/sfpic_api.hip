@@ -344,6 +344,13 @@ int setup_tiles(sfpic_sim *s) {
 }  // namespace
 
 namespace sfpic {
+// The incident-field preparation for the 3D entry points (sfpic3.hip).
+int prepare_incident_ext(const sfpic_incident *in, IncParams &P) {
+  return prepare_incident(in, P);
+}
+}  // namespace sfpic
+
+namespace sfpic {
 
 // Counting sort of every species by cell (compacts removed particles).
 int sort_all(sfpic_sim *s) {

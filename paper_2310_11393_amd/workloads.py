@@ -120,6 +120,7 @@ class Incident:
     # 0: closed form at each particle; 1: sampled on the Yee nodes at t^n
     # and gathered with the scattered field
     on_nodes: int = 0
+    z_focus: float = 0.0  # 3D runs: focus coordinate along z
 
 
 @dataclasses.dataclass
@@ -306,3 +307,42 @@ def served_sweep(rate=20.0, window=60.0, seed=5, big_fraction=0.1,
             out.append((t, sweep_member(i, precision, steps)))
         i += 1
     return out
+
+
+# ---------------------------------------------------------------------------
+# 3D3V inputs (Sec. 4 runs the method in 3D): seeded grids and particles
+# shared by the oracle and the library.
+# ---------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class Grid3:
+    nx: int
+    ny: int
+    nz: int
+    dx: float
+    dy: float
+    dz: float
+    dt: float
+
+
+def grid3(nx, ny, nz, h=2 * math.pi / 16, cfl=0.99):
+    """Cubic cells of size h and dt = cfl h / sqrt(3) (Sec. 4 uses 0.99)."""
+    return Grid3(nx, ny, nz, h, h, h, cfl * h / math.sqrt(3.0))
+
+
+def plasma3d(seed, grid, region, ppc, u_sigma=0.0, q=-1.0, m=1.0,
+             density=0.3):
+    """Explicit particles: ppc per cell of region (x0, x1, y0, y1, z0, z1)
+    at uniform random positions in the cell, momenta normal with width
+    u_sigma (cold when 0); returns the dict the oracle and the binding take."""
+    rng = np.random.default_rng(seed)
+    x0, x1, y0, y1, z0, z1 = region
+    cz, cy, cx = np.meshgrid(np.arange(z0, z1), np.arange(y0, y1),
+                             np.arange(x0, x1), indexing="ij")
+    cells = [np.repeat(c.ravel(), ppc) for c in (cx, cy, cz)]
+    n = cells[0].size
+    h = (grid.dx, grid.dy, grid.dz)
+    pos = [(cells[d] + rng.uniform(0.0, 1.0, n)) * h[d] for d in range(3)]
+    u = rng.normal(0.0, u_sigma, (3, n)) if u_sigma > 0 else np.zeros((3, n))
+    return {"q": q, "m": m, "weight": density / ppc, "x": pos[0],
+            "y": pos[1], "z": pos[2], "ux": u[0], "uy": u[1], "uz": u[2]}

@@ -13,7 +13,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def _declared(header):
     text = open(os.path.join(ROOT, "include", header)).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(sfpic_\w+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(sfpic3?_\w+)\s*\(", text)))
 
 
 @pytest.fixture(scope="module")
@@ -48,6 +48,33 @@ def test_invalid_grid_rejected_without_gpu(L):
     assert rc == -1 and b"CFL" in L.sfpic_last_error()
 
 
+def test_invalid_3d_input_rejected_without_gpu(L):
+    from paper_2310_11393_amd import binding as b
+    h = C.c_void_p()
+    g = b.sfpic3_grid(16, 16, 16, 0.2, 0.2, 0.2, 0.2)  # CFL violated
+    assert L.sfpic3_create(C.byref(g), None, 0, None, None, C.byref(h)) == -1
+    assert b"CFL" in L.sfpic_last_error() and not h.value
+    g = b.sfpic3_grid(16, 0, 16, 0.2, 0.2, 0.2, 0.05)
+    assert L.sfpic3_create(C.byref(g), None, 0, None, None, C.byref(h)) == -1
+    g = b.sfpic3_grid(16, 16, 16, 0.2, 0.2, 0.2, 0.05)
+    inc = b.sfpic_incident()
+    inc.kind, inc.a0, inc.w0, inc.fwhm_t = 4, 1.0, 2.0, 5.0  # 2D-only beam
+    assert L.sfpic3_create(C.byref(g), None, 0, C.byref(inc), None,
+                           C.byref(h)) == -1
+    assert b"2D" in L.sfpic_last_error()
+    x = (C.c_double * 1)(3.3)  # outside [0, 16 * 0.2)
+    zero = (C.c_double * 1)(0.1)
+    sp = b.sfpic3_species()
+    sp.q, sp.m, sp.n_explicit, sp.weight = -1.0, 1.0, 1, 0.1
+    sp.x, sp.y, sp.z = x, zero, zero
+    sp.ux, sp.uy, sp.uz = zero, zero, zero
+    assert L.sfpic3_create(C.byref(g), C.byref(sp), 1, None, None,
+                           C.byref(h)) == -1
+    assert b"outside" in L.sfpic_last_error()
+    assert L.sfpic3_step(None, 1) == -1
+    L.sfpic3_destroy(None)
+
+
 def test_null_handles_rejected(L):
     assert L.sfpic_step(None, 1) == -1
     assert L.sfpic_sync(None) == -1
@@ -57,7 +84,7 @@ def test_null_handles_rejected(L):
 STRUCTS = ["sfpic_grid", "sfpic_species", "sfpic_incident", "sfpic_runtime",
            "sfpic_diag", "sfpic_hist_spec", "sfpic_kernel_stats",
            "sfpic_sim_desc", "sfpic_result", "sfpic_batch_info",
-           "sfpic_server_info"]
+           "sfpic_server_info", "sfpic3_grid", "sfpic3_species"]
 
 
 def test_ctypes_layouts_match_the_header(tmp_path):
