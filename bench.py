@@ -27,12 +27,19 @@ METRIC = ("particle-pushes/sec (push+deposit+field) FP32 vs FP64 at stated "
           "error; sweep p50/p99")
 
 # Algorithmic work of the push kernel per particle (2D3V, FP64, LP April
-# field, closed-form branch); the derivation is listed in the design doc.
+# field, closed-form branch), counting an FMA as two flops.
 PUSH_BYTES_PARTICLE = 2 * 5 * 8     # read + write x, y, ux, uy, uz (double)
 PUSH_BYTES_CELL = (6 + 3) * 8        # gather 6 field planes, deposit 3 planes
 PUSH_FLOPS = 790                     # weights 36, gather 126, incident 317,
                                      # Boris 62, advance 16, shapes 60,
                                      # deposit 165, misc 8 (common path)
+# 3D push as formulated, per particle: weights 42, gather 648 (6 x 27 taps),
+# incident (April, full 3D) ~340, Boris and advance 79, shapes 165, Esirkepov
+# 1650 (3 components x 25 transverse weights and 100 prefix terms)
+PUSH3_FLOPS = 2924
+# 3D: read + write x, y, z, ux, uy, uz (96 B) and, per cell at 2 ppc, 6 field
+# components read and 3 current components read and written (96 B / 2)
+PUSH3_BYTES = 96 + 48
 PEAK_FP64_TFLOPS = 78.6
 PEAK_HBM_GBPS = 8000.0
 
@@ -200,6 +207,50 @@ def incident_on_nodes(ref, steps, warmup):
     return res
 
 
+def three_d(steps=20, warmup=2):
+    """The 3D3V step of Sec. 4 (sfpic3_*): the paper's 2 pi [24, 24, 32]
+    box at Delta = 2 pi / 16 (512 x 384 x 384 cells), 65.5M cold electrons
+    at 0.31 n_c from the density profile's half-maximum point on, tight
+    April LP beam; FP64.  Host-timed around synchronized step batches (the
+    leg runs for seconds)."""
+    import torch
+    from paper_2310_11393_amd import workloads as wl
+    from paper_2310_11393_amd.binding import Simulation3
+    g, sp, inc = wl.paper3d_lp()
+    log(f"3D: creating {sp.count() / 1e6:.1f}M particles on "
+        f"{g.nx}x{g.ny}x{g.nz} cells")
+    sim = Simulation3(g, inc, species=[sp])
+    sim.step(warmup)
+    sim.sync()
+    n0 = sim.diagnostics()["n_alive"]
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    done, chunk = 0, max(1, steps // 4)
+    while done < steps:
+        k = min(chunk, steps - done)
+        sim.step(k)
+        sim.sync()
+        done += k
+        log(f"3D: {done}/{steps} steps")
+    sec = time.perf_counter() - t
+    d = sim.diagnostics()
+    sim.close()
+    pushes = steps * 0.5 * (n0 + d["n_alive"])
+    res = {"workload": ("3D3V FP64, 512x384x384 cells (2 pi/16), "
+                        f"{sp.count() / 1e6:.1f}M cold electrons 2 ppc at "
+                        "0.31 n_c, April LP w0=0.8 lambda s=20 a0=10"),
+           "steps": steps, "pushes_per_s": pushes / sec,
+           "ms_per_step": sec / steps * 1e3,
+           "push_flops_per_particle": PUSH3_FLOPS,
+           "push_bytes_per_particle": PUSH3_BYTES,
+           "gauss_residual_rel": d["gauss_residual"] / max(d["rho_max"],
+                                                           1e-300),
+           "nonfinite": d["nonfinite"]}
+    log(f"3D: {res['pushes_per_s'] / 1e9:.2f} G pushes/s, "
+        f"{res['ms_per_step']:.1f} ms/step")
+    return res
+
+
 def batched_sweep(members=256, steps=400):
     """The laser-focus / density sweep as one batch: `members` FP32 2D3V
     simulations (grid side 256..1024, 8..32 ppc, LP / RP, density and beam
@@ -327,6 +378,9 @@ def main():
     ap.add_argument("--serve-window", type=float, default=30.0)
     ap.add_argument("--serve-steps", type=int, default=800)
     ap.add_argument("--serve-slots", type=int, default=64)
+    ap.add_argument("--no-3d", action="store_true",
+                    help="skip the 3D3V leg (sfpic3_*)")
+    ap.add_argument("--steps-3d", type=int, default=20)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device-to-device copy (3x) "
                          "whose profiler counters calibrate HBM traffic")
@@ -430,6 +484,8 @@ def main():
         del ref
     if not args.no_fp32_compare:
         out["fp32_vs_fp64"] = fp32_vs_fp64(args.compare_steps)
+    if not args.no_3d:
+        out["three_d"] = three_d(args.steps_3d)
     if not args.no_batch:
         out["batched_sweep"] = batched_sweep(args.batch_members,
                                              args.batch_steps)

@@ -295,7 +295,10 @@ class _TorchMemory:
         def _free(ptr, nbytes, ctx):
             if ptr in self.live:
                 del self.live[ptr]
-                torch.cuda.caching_allocator_delete(ptr)
+                try:
+                    torch.cuda.caching_allocator_delete(ptr)
+                except Exception:  # interpreter shutdown: torch is gone
+                    pass
 
         self.alloc_fn = ALLOC_FN(_alloc)
         self.free_fn = FREE_FN(_free)

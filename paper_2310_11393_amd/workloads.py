@@ -325,6 +325,23 @@ class Grid3:
     dt: float
 
 
+@dataclasses.dataclass
+class Species3:
+    """A species generated on the device in 3D: ppc per cell of region
+    (x0, x1, y0, y1, z0, z1)."""
+    q: float = -1.0
+    m: float = 1.0
+    density: float = 0.01
+    region: Tuple[int, int, int, int, int, int] = (0, 1, 0, 1, 0, 1)
+    ppc: int = 1
+    temperature_ev: float = 0.0
+    seed: int = 0
+
+    def count(self) -> int:
+        x0, x1, y0, y1, z0, z1 = self.region
+        return (x1 - x0) * (y1 - y0) * (z1 - z0) * self.ppc
+
+
 def grid3(nx, ny, nz, h=2 * math.pi / 16, cfl=0.99):
     """Cubic cells of size h and dt = cfl h / sqrt(3) (Sec. 4 uses 0.99)."""
     return Grid3(nx, ny, nz, h, h, h, cfl * h / math.sqrt(3.0))
@@ -346,3 +363,23 @@ def plasma3d(seed, grid, region, ppc, u_sigma=0.0, q=-1.0, m=1.0,
     u = rng.normal(0.0, u_sigma, (3, n)) if u_sigma > 0 else np.zeros((3, n))
     return {"q": q, "m": m, "weight": density / ppc, "x": pos[0],
             "y": pos[1], "z": pos[2], "ux": u[0], "uy": u[1], "uz": u[2]}
+
+
+def paper3d_lp(nx=512, ny=384, nz=384, ppc=2, a0=10.0):
+    """Sec. 4 3D run at Delta = 2 pi / 16: the box 2 pi [24, 24, 32] is
+    512 x 384 x 384 cells with propagation along x; n_e0 = 0.31 n_c, cold,
+    ppc (unstated in the paper) per cell in a slab from the half-maximum
+    point of the Sec. 3 super-Gaussian density profile (z = z0 - FWHM_Z / 2
+    = 114.0, cell 290 of 512) to the end of the box, uniform across (a
+    sharp-edged stand-in for the order-12 profile, which rises from 1% to
+    99% within 55 units of that point); tight April LP beam, w0 = 0.8
+    lambda, s = 20, focused on the axis at the slab's front face at t =
+    60 dt.  Returns (grid, species, incident) for binding.Simulation3."""
+    g = grid3(nx, ny, nz)
+    x0 = int(round(nx * (281.5 - 335.1 / 2) / (2 * math.pi * 32)))
+    sp = Species3(q=-1.0, m=1.0, density=0.31, region=(x0, nx, 0, ny, 0, nz),
+                  ppc=ppc, temperature_ev=0.0, seed=1)
+    inc = Incident(kind=INC_APRIL_LP, a0=a0, w0=0.8 * 2 * math.pi, s=20.0,
+                   x_focus=x0 * g.dx, y_focus=ny / 2 * g.dy,
+                   z_focus=nz / 2 * g.dz, t_focus=60 * g.dt)
+    return g, sp, inc
