@@ -13,10 +13,11 @@
 // E.  Particles: positions in cell units (x / dx ...), FP64 momenta, a
 // removed particle has x < -1.
 //
-// The push runs one thread per particle slot: 27-tap gathers read the field
-// arrays through the caches (particles are created in cell order, so a
-// wave's lanes share most taps) and the current goes to global memory with
-// FP64 atomic adds, one per non-zero Esirkepov term.
+// Every step sorts the particles by 8 x 8 x 8-cell tile (a counting sort
+// with creation ids carried along) and pushes each tile with one workgroup:
+// 27-tap gathers read the field arrays through the caches (a tile's field
+// halo stays in L2), and the tile's current accumulates in an FP64 LDS window
+// that is added to the global J once, with one atomic per window node.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -37,6 +38,8 @@ namespace sfpic3 {
 using sfpic::IncParams;
 
 constexpr int G = SFPIC_GUARD;
+// slots per species: ids, ranks and tile offsets are 32-bit
+constexpr int64_t kMaxParticles = ((int64_t)1 << 31) - 1;
 constexpr double kDead = -2.0;  // position marker of a removed particle
 
 struct Geo {
@@ -241,102 +244,288 @@ struct PushArgs {
   double time, z_focus;
 };
 
+// Particle tiles: TX x TY x TZ cells.  Every step starts with the particles
+// sorted by tile (removed ones last), so a particle's old nearest node is in
+// [tile start, tile end] along each axis and, since it moves less than one
+// cell per step (the CFL limit), every node its current touches lies in the
+// tile's window of T + 5 nodes per axis (old nearest node -2 .. +2).
+constexpr int TX = 8, TY = 8, TZ = 8;
+constexpr int WX = TX + 5, WY = TY + 5, WZ = TZ + 5, WN = WX * WY * WZ;
+
+struct Tiles {
+  int ntx, nty, ntz;
+  uint32_t ntiles;  // the removed particles' key is ntiles
+};
+
+__device__ __forceinline__ uint32_t tile_key(const Tiles &t, double x,
+                                             double y, double z) {
+  if (x < -1.0) return t.ntiles;
+  const int cx = min((int)x, t.ntx * TX - 1), cy = min((int)y, t.nty * TY - 1),
+            cz = min((int)z, t.ntz * TZ - 1);
+  return ((uint32_t)(cz / TZ) * t.nty + (uint32_t)(cy / TY)) * t.ntx +
+         (uint32_t)(cx / TX);
+}
+
+// Counting pass: rank of each particle within its key.  The lanes of a wave
+// that share a key take one atomic between them (one round per distinct key
+// in the wave: the particles arrive sorted, so there are few).
 __global__ void __launch_bounds__(256)
-push3(F3 f, Geo g, Parts3 p, int64_t n, PushArgs a, IncParams inc) {
+tile_count3(Parts3 p, int64_t n, Tiles t, uint32_t *count, uint32_t *rank) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool active = s < n;
+  const uint32_t key =
+      active ? tile_key(t, p.x[0][s], p.x[1][s], p.x[2][s]) : 0u;
+  const int lane = threadIdx.x & 63;
+  uint64_t todo = __ballot(active);
+  uint32_t r = 0;
+  while (todo) {
+    const int leader = __ffsll((unsigned long long)todo) - 1;
+    const uint32_t lk = __shfl(key, leader, 64);
+    const uint64_t same = __ballot(active && key == lk);
+    uint32_t base = 0;
+    if (lane == leader) base = atomicAdd(count + lk, (uint32_t)__popcll(same));
+    base = __shfl(base, leader, 64);
+    if ((same >> lane) & 1ull)
+      r = base + (uint32_t)__popcll(same & ((1ull << lane) - 1ull));
+    todo &= ~same;
+  }
+  if (active) rank[s] = r;
+}
+
+// Exclusive scan of m counters in three passes: per 1024-block scan with the
+// block totals, a scan of the totals, and the add-back.
+__device__ __forceinline__ uint32_t block_scan_excl(uint32_t v,
+                                                    uint32_t *sh,
+                                                    uint32_t &total) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  uint32_t incl = v;
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t u = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += u;
+  }
+  if (lane == 63) sh[w] = incl;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t acc = 0;
+    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) {
+      const uint32_t c = sh[k];
+      sh[k] = acc;
+      acc += c;
+    }
+    sh[16] = acc;
+  }
+  __syncthreads();
+  const uint32_t out = sh[w] + incl - v;
+  total = sh[16];
+  __syncthreads();
+  return out;
+}
+
+__global__ void __launch_bounds__(1024)
+scan3_blocks(const uint32_t *in, uint32_t *out, uint32_t *sums, uint32_t m) {
+  __shared__ uint32_t sh[17];
+  const uint32_t i = blockIdx.x * 1024u + threadIdx.x;
+  uint32_t tot;
+  const uint32_t e = block_scan_excl(i < m ? in[i] : 0u, sh, tot);
+  if (i < m) out[i] = e;
+  if (threadIdx.x == 0) sums[blockIdx.x] = tot;
+}
+
+__global__ void __launch_bounds__(1024) scan3_sums(uint32_t *sums, uint32_t nb) {
+  __shared__ uint32_t sh[17];
+  uint32_t carry = 0;
+  for (uint32_t b0 = 0; b0 < nb; b0 += 1024u) {
+    const uint32_t i = b0 + threadIdx.x;
+    uint32_t tot;
+    const uint32_t e = block_scan_excl(i < nb ? sums[i] : 0u, sh, tot);
+    if (i < nb) sums[i] = e + carry;
+    carry += tot;
+  }
+}
+
+__global__ void __launch_bounds__(1024)
+scan3_add(uint32_t *out, const uint32_t *sums, uint32_t m) {
+  const uint32_t i = blockIdx.x * 1024u + threadIdx.x;
+  if (i < m) out[i] += sums[blockIdx.x];
+}
+
+// Scatter every slot to start[key] + rank in the other buffer, id with it.
+__global__ void __launch_bounds__(256)
+tile_scatter3(Parts3 src, Parts3 dst, const uint32_t *sid, uint32_t *did,
+              int64_t n, Tiles t, const uint32_t *start, const uint32_t *rank) {
   const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= n) return;
-  double xi[3];
+  const double x = src.x[0][s], y = src.x[1][s], z = src.x[2][s];
+  const uint32_t d = start[tile_key(t, x, y, z)] + rank[s];
+  dst.x[0][d] = x;
+  dst.x[1][d] = y;
+  dst.x[2][d] = z;
 #pragma unroll
-  for (int d = 0; d < 3; ++d) xi[d] = p.x[d][s];
-  if (xi[0] < -1.0) return;  // removed
-  // gather E^n and the centred B at x^n
-  double wp[3][3], wd[3][3];
-  int bp[3], bd[3];
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    bp[d] = taps3(xi[d], 0, wp[d]);
-    bd[d] = taps3(xi[d], 1, wd[d]);
-  }
-  double E[3], B[3];
-  {
-    const int b0[3] = {bd[0], bp[1], bp[2]};
-    E[0] = gather27(f.e[0], g, b0, wd[0], wp[1], wp[2]);
-    const int b1[3] = {bp[0], bd[1], bp[2]};
-    E[1] = gather27(f.e[1], g, b1, wp[0], wd[1], wp[2]);
-    const int b2[3] = {bp[0], bp[1], bd[2]};
-    E[2] = gather27(f.e[2], g, b2, wp[0], wp[1], wd[2]);
-    const int b3[3] = {bp[0], bd[1], bd[2]};
-    B[0] = gather27(f.bb[0], g, b3, wp[0], wd[1], wd[2]);
-    const int b4[3] = {bd[0], bp[1], bd[2]};
-    B[1] = gather27(f.bb[1], g, b4, wd[0], wp[1], wd[2]);
-    const int b5[3] = {bd[0], bd[1], bp[2]};
-    B[2] = gather27(f.bb[2], g, b5, wd[0], wd[1], wp[2]);
-  }
-  if (inc.kind != SFPIC_INC_NONE) {
-    double Ei[3], Bi[3];
-    incident3(inc, a.z_focus, xi[0] * a.h[0], xi[1] * a.h[1], xi[2] * a.h[2],
-              a.time, Ei, Bi);
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      E[c] += Ei[c];
-      B[c] += Bi[c];
-    }
-  }
-  double u[3];
-#pragma unroll
-  for (int d = 0; d < 3; ++d) u[d] = p.u[d][s];
-  sfpic::boris<double>(a.qm, a.dt, u, E, B);
-  const double gi = sfpic::rsqrt(1.0 + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
-  // Esirkepov: shapes on the 5 nodes c0 - 2 .. c0 + 2 around the old
-  // nearest node, before (S0) and after the move, D = S1 - S0
-  double S0[3][5], D[3][5], x1[3];
-  int c0[3];
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    x1[d] = xi[d] + a.dt * a.inv_h[d] * (u[d] * gi);
-    const double c = floor(xi[d] + 0.5);
-    c0[d] = (int)c;
-#pragma unroll
-    for (int k = 0; k < 5; ++k) {
-      const double node = c + (double)(k - 2);
-      S0[d][k] = sfpic::spline2(xi[d] - node);
-      D[d][k] = sfpic::spline2(x1[d] - node) - S0[d][k];
-    }
-  }
+  for (int c = 0; c < 3; ++c) dst.u[c][d] = src.u[c][s];
+  did[d] = sid[s];
+}
+
+// One workgroup per tile (XCD-aware: workgroup b takes tile (b mod 8) S +
+// b / 8, S = ceil(tiles / 8), so each XCD walks a contiguous band of tiles
+// whose field halos share its L2).  The current of the tile's particles is
+// accumulated in an FP64 LDS window and added to the global J once.
+__global__ void __launch_bounds__(256, 2)
+push3_tiled(F3 f, Geo g, Parts3 p, const uint32_t *__restrict__ start, Tiles t,
+            PushArgs a, IncParams inc) {
+  __shared__ double sj[3 * WN];
+  const uint32_t S = (t.ntiles + 7) >> 3, b = blockIdx.x;
+  const uint32_t tile = (b & 7) * S + (b >> 3);
+  if ((b >> 3) >= S || tile >= t.ntiles) return;
+  const uint32_t pbeg = start[tile], pend = start[tile + 1];
+  if (pbeg == pend) return;
+  const int tx = (int)(tile % (uint32_t)t.ntx),
+            ty = (int)((tile / (uint32_t)t.ntx) % (uint32_t)t.nty),
+            tz = (int)(tile / ((uint32_t)t.ntx * (uint32_t)t.nty));
+  // window node (0, 0, 0) is cell-node t0 - 2 along each axis
+  const int w0[3] = {tx * TX - 2, ty * TY - 2, tz * TZ - 2};
+  for (int k = threadIdx.x; k < 3 * WN; k += blockDim.x) sj[k] = 0.0;
+  __syncthreads();
   constexpr double third = 1.0 / 3.0;
+  for (uint32_t s = pbeg + threadIdx.x; s < pend; s += blockDim.x) {
+    double xi[3];
 #pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    const int e = (d + 1) % 3, fa = (d + 2) % 3;
-    const double scale = -a.qw * a.h_over_dt[d];
-    for (int kf = 0; kf < 5; ++kf)
-      for (int ke = 0; ke < 5; ++ke) {
-        const double se = S0[e][ke], de = D[e][ke], sf = S0[fa][kf],
-                     df = D[fa][kf];
-        const double tw = se * sf + 0.5 * de * sf + 0.5 * se * df + de * df * third;
-        if (tw == 0.0) continue;
-        double acc = 0.0;
+    for (int d = 0; d < 3; ++d) xi[d] = p.x[d][s];
+    double E[3], B[3];
+    if (inc.kind != SFPIC_INC_NONE) {  // incident first: its temporaries die
+      incident3(inc, a.z_focus, xi[0] * a.h[0], xi[1] * a.h[1],
+                xi[2] * a.h[2], a.time, E, B);
+    } else {
 #pragma unroll
-        for (int kd = 0; kd < 4; ++kd) {
-          acc += scale * (D[d][kd] * tw);
-          if (acc != 0.0) {
-            int idx[3];
-            idx[d] = c0[d] - 2 + kd + G;
-            idx[e] = c0[e] - 2 + ke + G;
-            idx[fa] = c0[fa] - 2 + kf + G;
-            atomicAdd(f.j[d] + g.at(idx[0], idx[1], idx[2]), acc);
+      for (int c = 0; c < 3; ++c) E[c] = B[c] = 0.0;
+    }
+    // gather E^n and the centred B at x^n, added to the incident field: one
+    // component per iteration (an unrolled gather issues all 162 loads at
+    // once and needs more registers than two workgroups per CU leave);
+    // staggering bits per component (Ex Ey Ez Bx By Bz): dual along x for
+    // Ex By Bz, along y for Ey Bx Bz, along z for Ez Bx By
+    {
+      double wp[3][3], wd[3][3];
+      int bp[3], bd[3];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        bp[d] = taps3(xi[d], 0, wp[d]);
+        bd[d] = taps3(xi[d], 1, wd[d]);
+      }
+      constexpr int kDualX = 0x31, kDualY = 0x2A, kDualZ = 0x1C;
+#pragma unroll 1
+      for (int c = 0; c < 6; ++c) {
+        const bool sx = (kDualX >> c) & 1, sy = (kDualY >> c) & 1,
+                   sz = (kDualZ >> c) & 1;
+        const double *plane =
+            c == 0 ? f.e[0]
+                   : c == 1 ? f.e[1]
+                            : c == 2 ? f.e[2]
+                                     : c == 3 ? f.bb[0]
+                                              : c == 4 ? f.bb[1] : f.bb[2];
+        double wx[3], wy[3], wz[3];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          wx[q] = sx ? wd[0][q] : wp[0][q];
+          wy[q] = sy ? wd[1][q] : wp[1][q];
+          wz[q] = sz ? wd[2][q] : wp[2][q];
+        }
+        const int b[3] = {sx ? bd[0] : bp[0], sy ? bd[1] : bp[1],
+                          sz ? bd[2] : bp[2]};
+        const double v = gather27(plane, g, b, wx, wy, wz);
+        if (c == 0) E[0] = v + E[0];
+        else if (c == 1) E[1] = v + E[1];
+        else if (c == 2) E[2] = v + E[2];
+        else if (c == 3) B[0] = v + B[0];
+        else if (c == 4) B[1] = v + B[1];
+        else B[2] = v + B[2];
+      }
+    }
+    double u[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) u[d] = p.u[d][s];
+    sfpic::boris<double>(a.qm, a.dt, u, E, B);
+    const double gi =
+        sfpic::rsqrt(1.0 + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+    // Esirkepov: shapes on the 5 nodes c0 - 2 .. c0 + 2 around the old
+    // nearest node before the move (S0) and after it (S1), D = S1 - S0.  The
+    // transverse weight of component d,
+    //   S0_e S0_f + D_e S0_f / 2 + S0_e D_f / 2 + D_e D_f / 3,
+    // equals M_e M_f + D_e D_f / 12 with M = S0 + D / 2.
+    double M[3][5], D[3][5], x1[3];
+    int c0[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      x1[d] = xi[d] + a.dt * a.inv_h[d] * (u[d] * gi);
+      const double c = floor(xi[d] + 0.5);
+      c0[d] = (int)c - 2 - w0[d];  // window index of node c0 - 2
+#pragma unroll
+      for (int k = 0; k < 5; ++k) {
+        const double node = c + (double)(k - 2);
+        const double s0 = sfpic::spline2(xi[d] - node);
+        D[d][k] = sfpic::spline2(x1[d] - node) - s0;
+        M[d][k] = s0 + 0.5 * D[d][k];
+      }
+    }
+    constexpr double twelfth = 1.0 / 12.0;
+    constexpr int kStride[3] = {1, WX, WX * WY};
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const int e = (d + 1) % 3, fa = (d + 2) % 3;
+      const double scale = -a.qw * a.h_over_dt[d];
+      double Mf[5], Df[5];  // rotated so that index 0 is the current kf
+#pragma unroll
+      for (int k = 0; k < 5; ++k) {
+        Mf[k] = M[fa][k];
+        Df[k] = D[fa][k] * twelfth;
+      }
+      int addr = d * WN + c0[0] + c0[1] * WX + c0[2] * WX * WY;
+#pragma unroll 1
+      for (int kf = 0; kf < 5; ++kf) {
+        const double mf = Mf[0], df = Df[0];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          Mf[k] = Mf[k + 1];
+          Df[k] = Df[k + 1];
+        }
+#pragma unroll
+        for (int ke = 0; ke < 5; ++ke) {
+          const double tw = M[e][ke] * mf + D[e][ke] * df;
+          if (tw == 0.0) continue;
+          double acc = 0.0;
+#pragma unroll
+          for (int kd = 0; kd < 4; ++kd) {
+            acc += scale * (D[d][kd] * tw);
+            if (acc != 0.0)
+              atomicAdd(&sj[addr + kd * kStride[d] + ke * kStride[e]], acc);
           }
         }
+        addr += kStride[fa];
       }
-  }
-  // written as "inside" so that a non-finite position is removed too (it
-  // would otherwise index the field arrays on the next step)
-  const bool out = !(x1[0] >= 0.0 && x1[0] < (double)g.nx && x1[1] >= 0.0 &&
-                     x1[1] < (double)g.ny && x1[2] >= 0.0 &&
-                     x1[2] < (double)g.nz);
+    }
+    // written as "inside" so that a non-finite position is removed too (it
+    // would otherwise index the field arrays on the next step)
+    const bool out = !(x1[0] >= 0.0 && x1[0] < (double)g.nx && x1[1] >= 0.0 &&
+                       x1[1] < (double)g.ny && x1[2] >= 0.0 &&
+                       x1[2] < (double)g.nz);
 #pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    p.x[d][s] = (d == 0 && out) ? kDead : x1[d];
-    p.u[d][s] = u[d];
+    for (int d = 0; d < 3; ++d) {
+      p.x[d][s] = (d == 0 && out) ? kDead : x1[d];
+      p.u[d][s] = u[d];
+    }
+  }
+  __syncthreads();
+  // add the window to the global current (windows of neighbouring tiles
+  // overlap by 5 nodes per axis)
+  for (int k = threadIdx.x; k < WN; k += blockDim.x) {
+    const int ix = k % WX, iy = (k / WX) % WY, iz = k / (WX * WY);
+    const int gi = w0[0] + ix + G, gj = w0[1] + iy + G, gk = w0[2] + iz + G;
+    if (gi >= g.NX || gj >= g.NY || gk >= g.NZ) continue;
+    const size_t n = g.at(gi, gj, gk);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const double v = sj[c * WN + k];
+      if (v != 0.0) atomicAdd(f.j[c] + n, v);
+    }
   }
 }
 
@@ -495,8 +684,15 @@ using namespace sfpic3;
 struct Species3 {
   double q = -1.0, m = 1.0, w = 0.0;
   int64_t n = 0;
-  Parts3 p{};
+  Parts3 p{}, alt{};                       // particles, sort target
+  uint32_t *id = nullptr, *id_alt = nullptr;  // creation index per slot
 };
+
+// iota: slot i holds particle i
+__global__ void iota3(uint32_t *id, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) id[i] = (uint32_t)i;
+}
 
 struct sfpic3_sim {
   sfpic3_grid grid{};
@@ -509,6 +705,9 @@ struct sfpic3_sim {
   int64_t step = 0;
   F3 f{};
   double *face[3] = {};
+  Tiles tiles{};
+  uint32_t *count = nullptr, *start = nullptr, *sums = nullptr;
+  uint32_t *rank = nullptr;  // per slot, sized for the largest species
   std::vector<Species3> sp;
   double *rho0 = nullptr, *rho = nullptr, *acc = nullptr;
   std::vector<std::pair<void *, size_t>> allocs;
@@ -581,12 +780,27 @@ int one_step(sfpic3_sim *S) {
   }
   a.time = (double)S->step * dt;
   a.z_focus = S->z_focus;
+  const Tiles &t = S->tiles;
+  const uint32_t m = t.ntiles + 1, nb = (m + 1023) / 1024;
+  const uint32_t grid8 = (t.ntiles + 7) / 8 * 8;
   for (auto &sp : S->sp) {
     if (sp.n == 0) continue;
+    // sort by tile (removed particles last), ids along
+    HIP3(hipMemsetAsync(S->count, 0, (size_t)m * 4, S->st));
+    tile_count3<<<blocks_for(sp.n), 256, 0, S->st>>>(sp.p, sp.n, t, S->count,
+                                                     S->rank);
+    scan3_blocks<<<nb, 1024, 0, S->st>>>(S->count, S->start, S->sums, m);
+    scan3_sums<<<1, 1024, 0, S->st>>>(S->sums, nb);
+    scan3_add<<<nb, 1024, 0, S->st>>>(S->start, S->sums, m);
+    tile_scatter3<<<blocks_for(sp.n), 256, 0, S->st>>>(
+        sp.p, sp.alt, sp.id, sp.id_alt, sp.n, t, S->start, S->rank);
+    HIP3(hipGetLastError());
+    std::swap(sp.p, sp.alt);
+    std::swap(sp.id, sp.id_alt);
     a.qm = sp.q / sp.m;
     a.qw = sp.q * sp.w;
-    push3<<<blocks_for(sp.n), 256, 0, S->st>>>(S->f, S->g, sp.p, sp.n, a,
-                                               S->inc);
+    push3_tiled<<<grid8, 256, 0, S->st>>>(S->f, S->g, sp.p, S->start, t, a,
+                                          S->inc);
     HIP3(hipGetLastError());
   }
   if (int r = face_pass<0>(S, true, 0.0)) return r;
@@ -648,6 +862,8 @@ int sfpic3_create(const sfpic3_grid *grid, const sfpic3_species *species,
     const sfpic3_species &d = species[s];
     if (!(d.m > 0.0) || !std::isfinite(d.q))
       return sfpic::fail(SFPIC_E_INVAL, "species needs m > 0 and finite q");
+    if (d.n_explicit > kMaxParticles)
+      return sfpic::fail(SFPIC_E_SIZE, "too many explicit particles");
     if (d.n_explicit > 0) {
       if (!d.x || !d.y || !d.z || !d.ux || !d.uy || !d.uz)
         return sfpic::fail(SFPIC_E_INVAL, "explicit species needs all six arrays");
@@ -672,7 +888,7 @@ int sfpic3_create(const sfpic3_grid *grid, const sfpic3_species *species,
       if (d.temperature_ev < 0.0 || !std::isfinite(d.density))
         return sfpic::fail(SFPIC_E_INVAL, "bad density or temperature");
       const int64_t np = (r[1] - r[0]) * (r[3] - r[2]) * (r[5] - r[4]) * d.ppc;
-      if (np > ((int64_t)1 << 34))
+      if (np > kMaxParticles)
         return sfpic::fail(SFPIC_E_SIZE, "too many generated particles");
     } else if (d.n_explicit < 0 || d.ppc < 0) {
       return sfpic::fail(SFPIC_E_INVAL, "negative particle count");
@@ -717,6 +933,20 @@ int sfpic3_create(const sfpic3_grid *grid, const sfpic3_species *species,
     S->face[A] = (double *)S->dalloc((size_t)8 * 8 * ext(S->g, e) * ext(S->g, fa));
     if (!S->face[A]) return fail_free(SFPIC_E_NOMEM, "face buffer allocation failed");
   }
+  S->tiles.ntx = (int)((g.nx + TX - 1) / TX);
+  S->tiles.nty = (int)((g.ny + TY - 1) / TY);
+  S->tiles.ntz = (int)((g.nz + TZ - 1) / TZ);
+  S->tiles.ntiles =
+      (uint32_t)S->tiles.ntx * (uint32_t)S->tiles.nty * (uint32_t)S->tiles.ntz;
+  {
+    // start holds ntiles + 2 offsets: the tiles, the removed bucket, the end
+    const size_t m = (size_t)S->tiles.ntiles + 2;
+    S->count = (uint32_t *)S->dalloc(m * 4);
+    S->start = (uint32_t *)S->dalloc(m * 4);
+    S->sums = (uint32_t *)S->dalloc(((m + 1023) / 1024 + 1) * 4);
+    if (!S->count || !S->start || !S->sums)
+      return fail_free(SFPIC_E_NOMEM, "sort scratch allocation failed");
+  }
   S->rho0 = (double *)S->dalloc(S->plane * 8);
   S->rho = (double *)S->dalloc(S->plane * 8);
   S->acc = (double *)S->dalloc(64);
@@ -739,9 +969,16 @@ int sfpic3_create(const sfpic3_grid *grid, const sfpic3_species *species,
       for (int a = 0; a < 3; ++a) {
         sp.p.x[a] = (double *)S->dalloc((size_t)sp.n * 8);
         sp.p.u[a] = (double *)S->dalloc((size_t)sp.n * 8);
-        if (!sp.p.x[a] || !sp.p.u[a])
+        sp.alt.x[a] = (double *)S->dalloc((size_t)sp.n * 8);
+        sp.alt.u[a] = (double *)S->dalloc((size_t)sp.n * 8);
+        if (!sp.p.x[a] || !sp.p.u[a] || !sp.alt.x[a] || !sp.alt.u[a])
           return fail_free(SFPIC_E_NOMEM, "particle allocation failed");
       }
+      sp.id = (uint32_t *)S->dalloc((size_t)sp.n * 4);
+      sp.id_alt = (uint32_t *)S->dalloc((size_t)sp.n * 4);
+      if (!sp.id || !sp.id_alt)
+        return fail_free(SFPIC_E_NOMEM, "particle id allocation failed");
+      iota3<<<blocks_for(sp.n), 256, 0, S->st>>>(sp.id, sp.n);
       if (d.n_explicit > 0) {
         const size_t b = (size_t)sp.n * 8;
         double *tmp = (double *)S->dalloc(6 * b);
@@ -778,6 +1015,10 @@ int sfpic3_create(const sfpic3_grid *grid, const sfpic3_species *species,
     }
     S->sp.push_back(sp);
   }
+  int64_t nmax = 1;
+  for (auto &sp : S->sp) nmax = std::max(nmax, sp.n);
+  S->rank = (uint32_t *)S->dalloc((size_t)nmax * 4);
+  if (!S->rank) return fail_free(SFPIC_E_NOMEM, "sort scratch allocation failed");
   if (deposit_rho(S, S->rho0) != SFPIC_OK ||
       hipStreamSynchronize(S->st) != hipSuccess)
     return fail_free(SFPIC_E_DEVICE, "initial charge density failed");
@@ -861,17 +1102,28 @@ int sfpic3_read_particles(sfpic3_sim *sim, int species, double *x, double *y,
   if (n != (size_t)sp.n)
     return sfpic::fail(SFPIC_E_SIZE, "particle buffers must hold the slot count");
   if (n == 0) return SFPIC_OK;
+  // slots are in tile order on the device: stage them, then place each by
+  // its creation index
   double *dst[6] = {x, y, z, ux, uy, uz};
+  std::vector<double> stage(6 * n);
+  std::vector<uint32_t> id(n);
   for (int a = 0; a < 3; ++a) {
-    HIP3(hipMemcpyAsync(dst[a], sp.p.x[a], n * 8, hipMemcpyDeviceToHost, sim->st));
-    HIP3(hipMemcpyAsync(dst[3 + a], sp.p.u[a], n * 8, hipMemcpyDeviceToHost,
-                        sim->st));
+    HIP3(hipMemcpyAsync(stage.data() + a * n, sp.p.x[a], n * 8,
+                        hipMemcpyDeviceToHost, sim->st));
+    HIP3(hipMemcpyAsync(stage.data() + (3 + a) * n, sp.p.u[a], n * 8,
+                        hipMemcpyDeviceToHost, sim->st));
   }
+  HIP3(hipMemcpyAsync(id.data(), sp.id, n * 4, hipMemcpyDeviceToHost, sim->st));
   HIP3(hipStreamSynchronize(sim->st));
   const double h[3] = {sim->grid.dx, sim->grid.dy, sim->grid.dz};
-  for (size_t i = 0; i < n; ++i) {
-    alive[i] = x[i] >= -1.0;
-    for (int a = 0; a < 3; ++a) dst[a][i] *= h[a];
+  for (size_t s = 0; s < n; ++s) {
+    const size_t i = id[s];
+    if (i >= n) return sfpic::fail(SFPIC_E_STATE, "particle ids corrupted");
+    alive[i] = stage[s] >= -1.0;
+    for (int a = 0; a < 3; ++a) {
+      dst[a][i] = stage[a * n + s] * h[a];
+      dst[3 + a][i] = stage[(3 + a) * n + s];
+    }
   }
   return SFPIC_OK;
 }
