@@ -13,7 +13,7 @@
 // E.  Particles: positions in cell units (x / dx ...), FP64 momenta, a
 // removed particle has x < -1.
 //
-// Every step sorts the particles by 8 x 8 x 8-cell tile (a counting sort
+// Every step sorts the particles by 8 x 8 x 8-cell tile (SFPIC3_TILE) (a counting sort
 // with creation ids carried along) and pushes each tile with one workgroup:
 // 27-tap gathers read the field arrays through the caches (a tile's field
 // halo stays in L2), and the tile's current accumulates in an FP64 LDS window
@@ -249,7 +249,14 @@ struct PushArgs {
 // [tile start, tile end] along each axis and, since it moves less than one
 // cell per step (the CFL limit), every node its current touches lies in the
 // tile's window of T + 5 nodes per axis (old nearest node -2 .. +2).
-constexpr int TX = 8, TY = 8, TZ = 8;
+#ifndef SFPIC3_TILE
+#define SFPIC3_TILE 8, 8, 8
+#endif
+#ifndef SFPIC3_PUSH_WGS
+#define SFPIC3_PUSH_WGS 3  // workgroups per CU the push is compiled for
+#endif
+constexpr int kTile[3] = {SFPIC3_TILE};
+constexpr int TX = kTile[0], TY = kTile[1], TZ = kTile[2];
 constexpr int WX = TX + 5, WY = TY + 5, WZ = TZ + 5, WN = WX * WY * WZ;
 
 struct Tiles {
@@ -369,7 +376,7 @@ tile_scatter3(Parts3 src, Parts3 dst, const uint32_t *sid, uint32_t *did,
 // b / 8, S = ceil(tiles / 8), so each XCD walks a contiguous band of tiles
 // whose field halos share its L2).  The current of the tile's particles is
 // accumulated in an FP64 LDS window and added to the global J once.
-__global__ void __launch_bounds__(256, 2)
+__global__ void __launch_bounds__(256, SFPIC3_PUSH_WGS)
 push3_tiled(F3 f, Geo g, Parts3 p, const uint32_t *__restrict__ start, Tiles t,
             PushArgs a, IncParams inc) {
   __shared__ double sj[3 * WN];
