@@ -209,15 +209,16 @@ def incident_on_nodes(ref, steps, warmup):
 
 def three_d(steps=20, warmup=2):
     """The 3D3V step of Sec. 4 (sfpic3_*): the paper's 2 pi [24, 24, 32]
-    box at Delta = 2 pi / 16 (512 x 384 x 384 cells), 65.5M cold electrons
-    at 0.31 n_c from the density profile's half-maximum point on, tight
-    April LP beam; FP64.  Host-timed around synchronized step batches (the
+    box at Delta = 2 pi / 16 (512 x 384 x 384 cells), cold electrons in the
+    Sec. 3.1 density profile (0.31 n_c peak, 2 per cell there), tight April
+    LP beam; FP64.  Host-timed around synchronized step batches (the
     leg runs for seconds)."""
     import torch
     from paper_2310_11393_amd import workloads as wl
     from paper_2310_11393_amd.binding import Simulation3
     g, sp, inc = wl.paper3d_lp()
-    log(f"3D: creating {sp.count() / 1e6:.1f}M particles on "
+    n_sp = sp.count(g.dx)
+    log(f"3D: creating {n_sp / 1e6:.1f}M particles on "
         f"{g.nx}x{g.ny}x{g.nz} cells")
     sim = Simulation3(g, inc, species=[sp])
     sim.step(warmup)
@@ -237,8 +238,9 @@ def three_d(steps=20, warmup=2):
     sim.close()
     pushes = steps * 0.5 * (n0 + d["n_alive"])
     res = {"workload": ("3D3V FP64, 512x384x384 cells (2 pi/16), "
-                        f"{sp.count() / 1e6:.1f}M cold electrons 2 ppc at "
-                        "0.31 n_c, April LP w0=0.8 lambda s=20 a0=10"),
+                        f"{n_sp / 1e6:.1f}M cold electrons, 2 ppc at the "
+                        "0.31 n_c peak of the order-12 super-Gaussian "
+                        "profile, April LP w0=0.8 lambda s=20 a0=10"),
            "steps": steps, "pushes_per_s": pushes / sec,
            "ms_per_step": sec / steps * 1e3,
            "push_flops_per_particle": PUSH3_FLOPS,

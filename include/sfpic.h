@@ -120,7 +120,23 @@ typedef struct {
   int64_t n_explicit;       /* > 0: explicit arrays below                 */
   double weight;            /* explicit: density per macro-particle      */
   const double *x, *y, *ux, *uy, *uz; /* explicit (y ignored in 1D)      */
+  /* generated, optional density profile along x (the propagation axis),
+   * see SFPIC_PROFILE_*; single simulations only (batches reject it) */
+  int32_t profile;
+  double profile_center, profile_fwhm, profile_order, profile_xmin;
 } sfpic_species;
+
+/* sfpic_species.profile: SFPIC_PROFILE_UNIFORM places ppc particles in every
+ * cell of the region.  SFPIC_PROFILE_SUPERGAUSS follows the plasma profile of
+ * Sec. 3.1 along x: n(x) = density 2^{-|2 (x - profile_center) /
+ * profile_fwhm|^profile_order} for x > profile_xmin and 0 otherwise; cell
+ * column c of the region (centre x_c) holds floor(ppc n(x_c) / density +
+ * 1/2) particles per cell, each of weight density / ppc.  Particle ids run
+ * over region rows (y; y then z in 3D) outermost, then columns, a column's
+ * particles consecutive; positions and momenta use the same Philox streams
+ * as the uniform placement, by id. */
+#define SFPIC_PROFILE_UNIFORM 0
+#define SFPIC_PROFILE_SUPERGAUSS 1
 
 /* Incident field parameters.  April models: w0 is the waist (the complex
  * source parameter a follows from k^2 w0^2 = 2 (sqrt(1 + (ka)^2) - 1),
@@ -496,6 +512,8 @@ typedef struct {
   int64_t n_explicit;
   double weight;
   const double *x, *y, *z, *ux, *uy, *uz;
+  int32_t profile;  /* SFPIC_PROFILE_*, as in sfpic_species              */
+  double profile_center, profile_fwhm, profile_order, profile_xmin;
 } sfpic3_species;
 
 typedef struct sfpic3_sim sfpic3_sim;

@@ -48,7 +48,10 @@ class sfpic_species(C.Structure):
                 ("seed", C.c_uint64), ("species_index", C.c_int32),
                 ("n_explicit", C.c_int64), ("weight", C.c_double),
                 ("x", _DP), ("y", _DP), ("ux", _DP), ("uy", _DP),
-                ("uz", _DP)]
+                ("uz", _DP),
+                ("profile", C.c_int32), ("profile_center", C.c_double),
+                ("profile_fwhm", C.c_double), ("profile_order", C.c_double),
+                ("profile_xmin", C.c_double)]
 
 
 class sfpic_incident(C.Structure):
@@ -73,7 +76,10 @@ class sfpic3_species(C.Structure):
                 ("seed", C.c_uint64), ("species_index", C.c_int32),
                 ("n_explicit", C.c_int64), ("weight", C.c_double),
                 ("x", _DP), ("y", _DP), ("z", _DP), ("ux", _DP),
-                ("uy", _DP), ("uz", _DP)]
+                ("uy", _DP), ("uz", _DP),
+                ("profile", C.c_int32), ("profile_center", C.c_double),
+                ("profile_fwhm", C.c_double), ("profile_order", C.c_double),
+                ("profile_xmin", C.c_double)]
 
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
@@ -388,8 +394,16 @@ def _species_structs(species=(), explicit=None):
             sp.temperature_ev = spec.temperature_ev
             sp.seed = spec.seed
             sp.species_index = spec.species_index
+            _set_profile(sp, spec)
             arr.append(sp)
     return (sfpic_species * max(1, len(arr)))(*arr), len(arr), keep
+
+
+def _set_profile(sp, spec):
+    """Copy a workloads species' density profile (if any) into a struct."""
+    sp.profile = int(getattr(spec, "profile", 0))
+    for f in ("center", "fwhm", "order", "xmin"):
+        setattr(sp, "profile_" + f, float(getattr(spec, "profile_" + f, 0.0)))
 
 
 def hist_spec(sp=0, n_e=256, emax=1.0, n_theta=180,
@@ -732,6 +746,7 @@ class Simulation3:
             sp.temperature_ev = float(getattr(d, "temperature_ev", 0.0))
             sp.seed = int(getattr(d, "seed", 0))
             sp.species_index = k
+            _set_profile(sp, d)
             arr.append(sp)
         n = len(arr)
         sp_arr = (sfpic3_species * max(n, 1))(*arr)

@@ -32,6 +32,9 @@
 namespace sfpic {
 int fail(int code, const std::string &msg);
 int prepare_incident_ext(const sfpic_incident *in, IncParams &P);
+int profile_offsets(int32_t profile, double center, double fwhm, double order,
+                    double xmin, int64_t x0, int64_t x1, double dx, int ppc,
+                    std::vector<uint32_t> &off);
 }  // namespace sfpic
 
 namespace sfpic3 {
@@ -553,14 +556,28 @@ __global__ void load3(Parts3 p, int64_t n, const double *x, const double *y,
 // Generated particles: ppc per cell of the region, uniform in the cell, the
 // Philox4x32-10 stream keyed by (seed, species index) with counter (id, word
 // 2 = 0 / 1 / 2 / 3); momenta Maxwellian of width sigma (Box-Muller).
+// With a density profile (off != nullptr) particle i sits in region row
+// i / per_row (y fastest, then z) and in the column whose offsets bracket
+// i % per_row.
 __global__ void init3(Parts3 p, int64_t n, int64_t x0, int64_t y0, int64_t z0,
                       int64_t ncx, int64_t ncy, int ppc, double sigma,
-                      uint32_t k0, uint32_t k1) {
+                      uint32_t k0, uint32_t k1, const uint32_t *off,
+                      uint32_t per_row) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const int64_t cell = i / ppc;
-  const int64_t cx = x0 + cell % ncx, cy = y0 + (cell / ncx) % ncy,
-                cz = z0 + cell / (ncx * ncy);
+  int64_t cx, cy, cz;
+  if (off) {
+    const int64_t row = i / per_row;
+    cx = x0 + sfpic::find_segment(off, (int)ncx,
+                                  (uint32_t)(i - row * per_row));
+    cy = y0 + row % ncy;
+    cz = z0 + row / ncy;
+  } else {
+    const int64_t cell = i / ppc;
+    cx = x0 + cell % ncx;
+    cy = y0 + (cell / ncx) % ncy;
+    cz = z0 + cell / (ncx * ncy);
+  }
   const uint32_t lo = (uint32_t)i, hi = (uint32_t)((uint64_t)i >> 32);
   uint32_t c[4] = {lo, hi, 0u, 0u}, c3[4] = {lo, hi, 3u, 0u};
   sfpic::philox4x32_10(c, k0, k1);
@@ -959,6 +976,7 @@ int sfpic3_create(const sfpic3_grid *grid, const sfpic3_species *species,
   S->acc = (double *)S->dalloc(64);
   if (!S->rho0 || !S->rho || !S->acc)
     return fail_free(SFPIC_E_NOMEM, "diagnostic allocation failed");
+  std::vector<uint32_t> off;  // column offsets of a density profile
   for (int s = 0; s < nspecies; ++s) {
     const sfpic3_species &d = species[s];
     Species3 sp;
@@ -971,6 +989,19 @@ int sfpic3_create(const sfpic3_grid *grid, const sfpic3_species *species,
       const int64_t *r = d.region;
       sp.n = (r[1] - r[0]) * (r[3] - r[2]) * (r[5] - r[4]) * d.ppc;
       sp.w = d.density / d.ppc;
+      if (d.profile != SFPIC_PROFILE_UNIFORM) {
+        if (int rc = sfpic::profile_offsets(d.profile, d.profile_center,
+                                            d.profile_fwhm, d.profile_order,
+                                            d.profile_xmin, r[0], r[1], g.dx,
+                                            d.ppc, off)) {
+          S->release();
+          delete S;
+          return rc;
+        }
+        sp.n = (int64_t)off.back() * (r[3] - r[2]) * (r[5] - r[4]);
+        if (sp.n > kMaxParticles)
+          return fail_free(SFPIC_E_SIZE, "too many generated particles");
+      }
     }
     if (sp.n > 0) {
       for (int a = 0; a < 3; ++a) {
@@ -1013,9 +1044,18 @@ int sfpic3_create(const sfpic3_grid *grid, const sfpic3_species *species,
         const int64_t *r = d.region;
         const double sigma =
             d.temperature_ev > 0.0 ? std::sqrt(d.temperature_ev / (510998.95 * d.m)) : 0.0;
+        uint32_t *doff = nullptr;
+        if (d.profile != SFPIC_PROFILE_UNIFORM) {
+          doff = (uint32_t *)S->dalloc(off.size() * 4);
+          if (!doff) return fail_free(SFPIC_E_NOMEM, "profile table allocation failed");
+          if (hipMemcpyAsync(doff, off.data(), off.size() * 4,
+                             hipMemcpyHostToDevice, S->st) != hipSuccess)
+            return fail_free(SFPIC_E_DEVICE, "profile table upload failed");
+        }
         init3<<<blocks_for(sp.n), 256, 0, S->st>>>(
             sp.p, sp.n, r[0], r[2], r[4], r[1] - r[0], r[3] - r[2], d.ppc,
-            sigma, (uint32_t)d.seed, (uint32_t)d.species_index);
+            sigma, (uint32_t)d.seed, (uint32_t)d.species_index, doff,
+            doff ? off.back() : 0u);
         if (hipGetLastError() != hipSuccess)
           return fail_free(SFPIC_E_DEVICE, "particle generation failed");
       }

@@ -247,11 +247,37 @@ int place_species(sfpic_sim *s, SpeciesState &st, const sfpic_species &in) {
     return fail(SFPIC_E_INVAL, "density < 0");
   if (!(in.temperature_ev >= 0.0))
     return fail(SFPIC_E_INVAL, "temperature < 0");
+  const double sigma = sqrt(in.temperature_ev / (510998.95 * in.m));
+  st.weight = in.ppc > 0 ? in.density / in.ppc : 0.0;
+  if (in.profile != SFPIC_PROFILE_UNIFORM && in.ppc > 0 && x1 > x0) {
+    std::vector<uint32_t> off;
+    SF_TRY(profile_offsets(in.profile, in.profile_center, in.profile_fwhm,
+                           in.profile_order, in.profile_xmin, x0, x1, g.dx,
+                           in.ppc, off));
+    const uint32_t per_row = off.back();
+    const int64_t n = (int64_t)per_row * (y1 - y0);
+    if (n > 0xFFFFFFFFll) return fail(SFPIC_E_INVAL, "too many particles");
+    SF_TRY(alloc_species(s, st, n));
+    if (n == 0) return SFPIC_OK;
+    uint32_t *doff = (uint32_t *)s->dalloc(off.size() * 4);
+    if (!doff) return fail(SFPIC_E_NOMEM, "profile table allocation failed");
+    HIP_TRY(hipMemcpyAsync(doff, off.data(), off.size() * 4,
+                           hipMemcpyHostToDevice, s->stream));
+    const int r = s->dispatch([&](auto z) -> int {
+      using R = decltype(z);
+      HIP_TRY(launch_init_particles_profile<R>(
+          parts<R>(st), n, g.dims, x0, (int)(x1 - x0), y0, doff, per_row,
+          sigma, in.seed, (uint32_t)in.species_index, s->stream));
+      return SFPIC_OK;
+    });
+    if (r) return r;
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    s->dfree(doff);
+    return SFPIC_OK;
+  }
   const int64_t n = (x1 - x0) * (y1 - y0) * (int64_t)in.ppc;
   if (n > 0xFFFFFFFFll) return fail(SFPIC_E_INVAL, "too many particles");
-  st.weight = in.ppc > 0 ? in.density / in.ppc : 0.0;
   SF_TRY(alloc_species(s, st, n));
-  const double sigma = sqrt(in.temperature_ev / (510998.95 * in.m));
   return s->dispatch([&](auto z) -> int {
     using R = decltype(z);
     HIP_TRY(launch_init_particles<R>(parts<R>(st), n, g.dims, x0, x1 - x0, y0,
@@ -344,6 +370,28 @@ int setup_tiles(sfpic_sim *s) {
 }  // namespace
 
 namespace sfpic {
+int profile_offsets(int32_t profile, double center, double fwhm, double order,
+                    double xmin, int64_t x0, int64_t x1, double dx, int ppc,
+                    std::vector<uint32_t> &off) {
+  if (profile != SFPIC_PROFILE_SUPERGAUSS)
+    return fail(SFPIC_E_INVAL, "unknown density profile");
+  if (!(fwhm > 0.0) || !(order > 0.0) || !isfinite(center) ||
+      !isfinite(fwhm) || !isfinite(order) || isnan(xmin))
+    return fail(SFPIC_E_INVAL, "profile needs fwhm > 0, order > 0, finite centre");
+  off.assign((size_t)(x1 - x0) + 1, 0u);
+  uint64_t acc = 0;
+  for (int64_t c = x0; c < x1; ++c) {
+    const double xc = ((double)c + 0.5) * dx;
+    const double f =
+        xc > xmin ? pow(2.0, -pow(fabs(2.0 * (xc - center) / fwhm), order))
+                  : 0.0;
+    acc += (uint64_t)floor((double)ppc * f + 0.5);
+    if (acc > 0xFFFFFFFFull) return fail(SFPIC_E_INVAL, "too many particles");
+    off[(size_t)(c - x0) + 1] = (uint32_t)acc;
+  }
+  return SFPIC_OK;
+}
+
 // The incident-field preparation for the 3D entry points (sfpic3.hip).
 int prepare_incident_ext(const sfpic_incident *in, IncParams &P) {
   return prepare_incident(in, P);

@@ -73,6 +73,11 @@ int check_desc(const sfpic_sim_desc *d) {
   if (d->incident.on_nodes)
     return fail(SFPIC_E_INVAL,
                 "incident on_nodes is supported for single simulations only");
+  for (int k = 0; k < d->nspecies; ++k)
+    if (d->species[k].n_explicit == 0 &&
+        d->species[k].profile != SFPIC_PROFILE_UNIFORM)
+      return fail(SFPIC_E_INVAL,
+                  "density profiles are supported for single simulations only");
   if (d->incident.kind == SFPIC_INC_GAUSS_2D)
     return fail(SFPIC_E_INVAL,
                 "the Gaussian beam is supported for single simulations only");

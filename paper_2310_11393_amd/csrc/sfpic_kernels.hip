@@ -307,6 +307,55 @@ hipError_t launch_init_particles(const Particles<R> &p, int64_t n, int dims,
   return hipGetLastError();
 }
 
+// Placement with a density profile along x: row i / per_row of the region,
+// the column whose offsets bracket i % per_row; the draws are those of
+// init_particles for the same id.
+template <typename R>
+__global__ void init_particles_profile(Particles<R> p, int64_t n, int dims,
+                                       int64_t x0, int ncx, int64_t y0,
+                                       const uint32_t *off, uint32_t per_row,
+                                       double sigma, uint32_t k0, uint32_t k1) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t row = i / per_row;
+  const uint32_t r = (uint32_t)(i - row * per_row);
+  const int64_t cx = x0 + find_segment(off, ncx, r), cy = y0 + row;
+  uint32_t c[4] = {(uint32_t)i, (uint32_t)((uint64_t)i >> 32), 0u, 0u};
+  philox4x32_10(c, k0, k1);
+  double a, b;
+  u01_pair(c, a, b);
+  double ux = 0.0, uy = 0.0, uz = 0.0;
+  if (sigma > 0.0) {
+    uint32_t c1[4] = {(uint32_t)i, (uint32_t)((uint64_t)i >> 32), 1u, 0u};
+    uint32_t c2[4] = {(uint32_t)i, (uint32_t)((uint64_t)i >> 32), 2u, 0u};
+    philox4x32_10(c1, k0, k1);
+    philox4x32_10(c2, k0, k1);
+    double a1, b1, a2, b2;
+    u01_pair(c1, a1, b1);
+    u01_pair(c2, a2, b2);
+    const double r1 = sqrt(-2.0 * log1p(-a1)), r2 = sqrt(-2.0 * log1p(-a2));
+    const double tp = 6.283185307179586;
+    ux = sigma * r1 * cos(tp * b1);
+    uy = sigma * r1 * sin(tp * b1);
+    uz = sigma * r2 * cos(tp * b2);
+  }
+  place(p, i, dims, cx, a, cy, b, ux, uy, uz);
+  p.id[i] = (uint32_t)i;
+}
+
+template <typename R>
+hipError_t launch_init_particles_profile(const Particles<R> &p, int64_t n,
+                                         int dims, int64_t x0, int ncx,
+                                         int64_t y0, const uint32_t *off,
+                                         uint32_t per_row, double sigma,
+                                         uint64_t seed, uint32_t key1,
+                                         hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  init_particles_profile<R><<<(unsigned)((n + 255) / 256), 256, 0, st>>>(
+      p, n, dims, x0, ncx, y0, off, per_row, sigma, (uint32_t)seed, key1);
+  return hipGetLastError();
+}
+
 // Explicit particles: physical positions to (cell, offset), clamped into
 // the physical box [0, nx) x [0, ny) against rounding.
 template <typename R>
@@ -672,6 +721,9 @@ hipError_t launch_export_particles(const Particles<R> &p, int64_t n, int dims,
   template hipError_t launch_init_particles<R>(                              \
       const Particles<R> &, int64_t, int, int64_t, int64_t, int64_t, int,     \
       double, uint64_t, uint32_t, double, double, hipStream_t);               \
+  template hipError_t launch_init_particles_profile<R>(                      \
+      const Particles<R> &, int64_t, int, int64_t, int, int64_t,              \
+      const uint32_t *, uint32_t, double, uint64_t, uint32_t, hipStream_t);   \
   template hipError_t launch_load_particles<R>(                              \
       const Particles<R> &, int64_t, int, const double *, const double *,     \
       const double *, const double *, const double *, double, double, int,    \

@@ -14,6 +14,23 @@ namespace sfpic {
 // Record msg as the calling thread's last error and return code.
 int fail(int code, const std::string &msg);
 
+// Column offsets of a density profile along x over region columns
+// [x0, x1): off[c + 1] - off[c] particles per cell of column c
+// (SFPIC_PROFILE_*); fails on bad profile parameters.
+int profile_offsets(int32_t profile, double center, double fwhm, double order,
+                    double xmin, int64_t x0, int64_t x1, double dx, int ppc,
+                    std::vector<uint32_t> &off);
+
+// Placement with a profile: particle i sits in row i / per_row of the region
+// (y0 + row) and in the column whose offsets bracket i % per_row.
+template <typename R>
+hipError_t launch_init_particles_profile(const Particles<R> &p, int64_t n,
+                                         int dims, int64_t x0, int ncx,
+                                         int64_t y0, const uint32_t *off,
+                                         uint32_t per_row, double sigma,
+                                         uint64_t seed, uint32_t key1,
+                                         hipStream_t st);
+
 #define HIP_TRY(expr)                                                   \
   do {                                                                  \
     hipError_t e_ = (expr);                                             \

@@ -94,14 +94,24 @@ class Species:
     temperature_ev: float = 0.0    # 0: cold
     seed: int = 0
     species_index: int = 0
+    # density profile along x (PROFILE_*): super-Gaussian parameters
+    profile: int = 0
+    profile_center: float = 0.0
+    profile_fwhm: float = 0.0
+    profile_order: float = 0.0
+    profile_xmin: float = 0.0
 
     @property
     def weight(self) -> float:
         """Density carried by one macro-particle (n / ppc)."""
         return self.density / self.ppc
 
-    def count(self) -> int:
+    def count(self, dx: float = 0.0) -> int:
+        """Particles placed (dx, the cell size along x, is needed only with a
+        density profile)."""
         x0, x1, y0, y1 = self.region
+        if self.profile:
+            return int(profile_offsets(self, x0, x1, dx)[-1]) * (y1 - y0)
         return (x1 - x0) * (y1 - y0) * self.ppc
 
 
@@ -133,6 +143,40 @@ class Workload:
     precision: int = FP64
 
 
+PROFILE_UNIFORM, PROFILE_SUPERGAUSS = 0, 1
+
+
+def profile_factor(sp, x: float) -> float:
+    """Sec. 3.1 plasma profile along x relative to the peak density:
+    2^{-|2 (x - centre) / FWHM|^order} beyond x_min, else 0."""
+    if not x > sp.profile_xmin:
+        return 0.0
+    return math.pow(2.0, -math.pow(abs(2.0 * (x - sp.profile_center) /
+                                       sp.profile_fwhm), sp.profile_order))
+
+
+def profile_offsets(sp, x0: int, x1: int, dx: float) -> np.ndarray:
+    """Column offsets: column c of [x0, x1) holds floor(ppc f(x_c) + 1/2)
+    particles per cell, x_c its centre (the library computes the same table
+    on the host)."""
+    if sp.profile != PROFILE_SUPERGAUSS:
+        raise ValueError("unknown density profile")
+    counts = [math.floor(sp.ppc * profile_factor(sp, (c + 0.5) * dx) + 0.5)
+              for c in range(x0, x1)]
+    return np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+
+
+def _profile_cells(sp, pid, x0, x1, nrows, dx):
+    """(column, row) of particle ids under a density profile: rows outer,
+    columns inner, a column's particles consecutive."""
+    off = profile_offsets(sp, x0, x1, dx)
+    per_row = int(off[-1])
+    row = pid // per_row
+    r = pid - row * per_row
+    col = np.searchsorted(off, r, side="right") - 1
+    return x0 + col, row
+
+
 def generate_particles(sp: Species, grid: Grid, first: int = 0,
                        count: Optional[int] = None):
     """Positions and momenta of particles first .. first+count-1 of a species.
@@ -143,13 +187,17 @@ def generate_particles(sp: Species, grid: Grid, first: int = 0,
     """
     x0, x1, y0, y1 = sp.region
     ncx = x1 - x0
-    total = sp.count()
+    total = sp.count(grid.dx)
     if count is None:
         count = total - first
     pid = np.arange(first, first + count, dtype=np.int64)
-    cell = pid // sp.ppc
-    cx = x0 + cell % ncx
-    cy = y0 + cell // ncx
+    if sp.profile:
+        cx, row = _profile_cells(sp, pid, x0, x1, y1 - y0, grid.dx)
+        cy = y0 + row
+    else:
+        cell = pid // sp.ppc
+        cx = x0 + cell % ncx
+        cy = y0 + cell // ncx
     key = (sp.seed, sp.species_index)
     ua, ub = u01_pair(philox4x32_10(_counters(pid, 0), key))
     x = (cx + ua) * grid.dx
@@ -336,9 +384,17 @@ class Species3:
     ppc: int = 1
     temperature_ev: float = 0.0
     seed: int = 0
+    profile: int = 0
+    profile_center: float = 0.0
+    profile_fwhm: float = 0.0
+    profile_order: float = 0.0
+    profile_xmin: float = 0.0
 
-    def count(self) -> int:
+    def count(self, dx: float = 0.0) -> int:
         x0, x1, y0, y1, z0, z1 = self.region
+        if self.profile:
+            return int(profile_offsets(self, x0, x1, dx)[-1]) * \
+                (y1 - y0) * (z1 - z0)
         return (x1 - x0) * (y1 - y0) * (z1 - z0) * self.ppc
 
 
@@ -367,19 +423,23 @@ def plasma3d(seed, grid, region, ppc, u_sigma=0.0, q=-1.0, m=1.0,
 
 def paper3d_lp(nx=512, ny=384, nz=384, ppc=2, a0=10.0):
     """Sec. 4 3D run at Delta = 2 pi / 16: the box 2 pi [24, 24, 32] is
-    512 x 384 x 384 cells with propagation along x; n_e0 = 0.31 n_c, cold,
-    ppc (unstated in the paper) per cell in a slab from the half-maximum
-    point of the Sec. 3 super-Gaussian density profile (z = z0 - FWHM_Z / 2
-    = 114.0, cell 290 of 512) to the end of the box, uniform across (a
-    sharp-edged stand-in for the order-12 profile, which rises from 1% to
-    99% within 55 units of that point); tight April LP beam, w0 = 0.8
-    lambda, s = 20, focused on the axis at the slab's front face at t =
-    60 dt.  Returns (grid, species, incident) for binding.Simulation3."""
+    512 x 384 x 384 cells with propagation along x; cold electrons with
+    peak density n_e0 = 0.31 n_c in the Sec. 3.1 super-Gaussian profile along
+    x (order 12, centre 281.5, FWHM 335.1, zero for x <= 20 pi: in this box
+    its rising side, half maximum at x = 114), uniform across; ppc (unstated
+    in the paper) at the peak, fewer where the profile is lower; tight April
+    LP beam, w0 = 0.8 lambda, s = 20, focused on the axis at the profile's
+    half-maximum point at t = 60 dt.  Returns (grid, species, incident) for
+    binding.Simulation3."""
     g = grid3(nx, ny, nz)
-    x0 = int(round(nx * (281.5 - 335.1 / 2) / (2 * math.pi * 32)))
-    sp = Species3(q=-1.0, m=1.0, density=0.31, region=(x0, nx, 0, ny, 0, nz),
-                  ppc=ppc, temperature_ev=0.0, seed=1)
+    xmin = 20 * math.pi
+    x_half = 281.5 - 335.1 / 2
+    sp = Species3(q=-1.0, m=1.0, density=0.31,
+                  region=(int(xmin / g.dx), nx, 0, ny, 0, nz), ppc=ppc,
+                  temperature_ev=0.0, seed=1, profile=PROFILE_SUPERGAUSS,
+                  profile_center=281.5, profile_fwhm=335.1, profile_order=12.0,
+                  profile_xmin=xmin)
     inc = Incident(kind=INC_APRIL_LP, a0=a0, w0=0.8 * 2 * math.pi, s=20.0,
-                   x_focus=x0 * g.dx, y_focus=ny / 2 * g.dy,
+                   x_focus=x_half, y_focus=ny / 2 * g.dy,
                    z_focus=nz / 2 * g.dz, t_focus=60 * g.dt)
     return g, sp, inc
