@@ -59,6 +59,11 @@ def _case(name):
               wl.plasma3d(15, g, (2, 15, 2, 9, 2, 7), 1, u_sigma=0.05,
                           q=1.0, m=100.0, density=0.2)]
         return g, inc, sp, 30
+    if name == "tiny":  # fewer cells than one 8^3 tile along every axis
+        g = wl.grid3(3, 2, 1, cfl=0.9)
+        inc = _inc(1, a0=1.0, fwhm_t=4.0, t0=2.0)
+        sp = [wl.plasma3d(16, g, (0, 3, 0, 2, 0, 1), 4, u_sigma=0.1)]
+        return g, inc, sp, 8
     raise KeyError(name)
 
 
@@ -106,7 +111,8 @@ def _compare_particles(gs, os_, nsp, g):
         assert du <= 1e-12 * max(1.0, umax), (s, du, umax)
 
 
-@pytest.mark.parametrize("name", ["lp3d", "rp3d", "pulse3d", "hot_ragged"])
+@pytest.mark.parametrize("name", ["lp3d", "rp3d", "pulse3d", "hot_ragged",
+                                  "tiny"])
 def test_3d_parity_with_oracle(name):
     g, inc, sp, steps = _case(name)
     print(f"[3d] case {name} grid {g.nx}x{g.ny}x{g.nz} steps {steps}",
@@ -128,7 +134,7 @@ def test_3d_parity_with_oracle(name):
     assert gd["nonfinite"] == 0
     # charge conservation holds on the device as well
     assert gd["gauss_residual"] <= 1e-11 * max(1.0, gd["rho_max"])
-    if name == "hot_ragged":
+    if name in ("hot_ragged", "tiny"):
         assert od["n_alive"] < sum(len(e["x"]) for e in sp)
 
 
