@@ -207,19 +207,23 @@ def incident_on_nodes(ref, steps, warmup):
     return res
 
 
-def three_d(steps=20, warmup=2):
+def three_d(steps=20, warmup=2, cells_per_lambda=16):
     """The 3D3V step of Sec. 4 (sfpic3_*): the paper's 2 pi [24, 24, 32]
-    box at Delta = 2 pi / 16 (512 x 384 x 384 cells), cold electrons in the
-    Sec. 3.1 density profile (0.31 n_c peak, 2 per cell there), tight April
-    LP beam; FP64.  Host-timed around synchronized step batches (the
-    leg runs for seconds)."""
+    box at Delta = 2 pi / cells_per_lambda (16: 512 x 384 x 384 cells; 32,
+    the paper's own finer resolution: 1024 x 768 x 768 = 6.0e8 cells), cold
+    electrons in the Sec. 3.1 density profile (0.31 n_c peak, 2 per cell
+    there), tight April LP beam; FP64.  Host-timed around synchronized step
+    batches (the leg runs for seconds)."""
     import torch
     from paper_2310_11393_amd import workloads as wl
     from paper_2310_11393_amd.binding import Simulation3
-    g, sp, inc = wl.paper3d_lp()
+    g, sp, inc = wl.paper3d_lp(cells_per_lambda)
     n_sp = sp.count(g.dx)
-    log(f"3D: creating {n_sp / 1e6:.1f}M particles on "
+    tag = f"3D 2pi/{cells_per_lambda}"
+    log(f"{tag}: creating {n_sp / 1e6:.1f}M particles on "
         f"{g.nx}x{g.ny}x{g.nz} cells")
+    torch.cuda.empty_cache()
+    torch.cuda.reset_peak_memory_stats()
     sim = Simulation3(g, inc, species=[sp])
     sim.step(warmup)
     sim.sync()
@@ -232,24 +236,28 @@ def three_d(steps=20, warmup=2):
         sim.step(k)
         sim.sync()
         done += k
-        log(f"3D: {done}/{steps} steps")
+        log(f"{tag}: {done}/{steps} steps")
     sec = time.perf_counter() - t
     d = sim.diagnostics()
     sim.close()
+    peak = torch.cuda.max_memory_allocated()
+    torch.cuda.empty_cache()
     pushes = steps * 0.5 * (n0 + d["n_alive"])
-    res = {"workload": ("3D3V FP64, 512x384x384 cells (2 pi/16), "
-                        f"{n_sp / 1e6:.1f}M cold electrons, 2 ppc at the "
-                        "0.31 n_c peak of the order-12 super-Gaussian "
-                        "profile, April LP w0=0.8 lambda s=20 a0=10"),
+    res = {"workload": (f"3D3V FP64, {g.nx}x{g.ny}x{g.nz} cells "
+                        f"(2 pi/{cells_per_lambda}), {n_sp / 1e6:.1f}M cold "
+                        "electrons, 2 ppc at the 0.31 n_c peak of the "
+                        "order-12 super-Gaussian profile, April LP "
+                        "w0=0.8 lambda s=20 a0=10"),
            "steps": steps, "pushes_per_s": pushes / sec,
            "ms_per_step": sec / steps * 1e3,
+           "device_bytes": peak,
            "push_flops_per_particle": PUSH3_FLOPS,
            "push_bytes_per_particle": PUSH3_BYTES,
            "gauss_residual_rel": d["gauss_residual"] / max(d["rho_max"],
                                                            1e-300),
            "nonfinite": d["nonfinite"]}
-    log(f"3D: {res['pushes_per_s'] / 1e9:.2f} G pushes/s, "
-        f"{res['ms_per_step']:.1f} ms/step")
+    log(f"{tag}: {res['pushes_per_s'] / 1e9:.2f} G pushes/s, "
+        f"{res['ms_per_step']:.1f} ms/step, {peak / 1e9:.0f} GB")
     return res
 
 
@@ -488,6 +496,8 @@ def main():
         out["fp32_vs_fp64"] = fp32_vs_fp64(args.compare_steps)
     if not args.no_3d:
         out["three_d"] = three_d(args.steps_3d)
+        out["three_d_paper_resolution"] = three_d(max(2, args.steps_3d // 2),
+                                                  cells_per_lambda=32)
     if not args.no_batch:
         out["batched_sweep"] = batched_sweep(args.batch_members,
                                              args.batch_steps)

@@ -421,9 +421,10 @@ def plasma3d(seed, grid, region, ppc, u_sigma=0.0, q=-1.0, m=1.0,
             "y": pos[1], "z": pos[2], "ux": u[0], "uy": u[1], "uz": u[2]}
 
 
-def paper3d_lp(nx=512, ny=384, nz=384, ppc=2, a0=10.0):
-    """Sec. 4 3D run at Delta = 2 pi / 16: the box 2 pi [24, 24, 32] is
-    512 x 384 x 384 cells with propagation along x; cold electrons with
+def paper3d_lp(cells_per_lambda=16, ppc=2, a0=10.0):
+    """Sec. 4 3D run: the box 2 pi [24, 24, 32] at Delta = 2 pi /
+    cells_per_lambda (16: 512 x 384 x 384 cells; 32, the paper's finer
+    resolution: 1024 x 768 x 768) with propagation along x; cold electrons with
     peak density n_e0 = 0.31 n_c in the Sec. 3.1 super-Gaussian profile along
     x (order 12, centre 281.5, FWHM 335.1, zero for x <= 20 pi: in this box
     its rising side, half maximum at x = 114), uniform across; ppc (unstated
@@ -431,7 +432,9 @@ def paper3d_lp(nx=512, ny=384, nz=384, ppc=2, a0=10.0):
     LP beam, w0 = 0.8 lambda, s = 20, focused on the axis at the profile's
     half-maximum point at t = 60 dt.  Returns (grid, species, incident) for
     binding.Simulation3."""
-    g = grid3(nx, ny, nz)
+    c = int(cells_per_lambda)
+    nx, ny, nz = 32 * c, 24 * c, 24 * c
+    g = grid3(nx, ny, nz, h=2 * math.pi / c)
     xmin = 20 * math.pi
     x_half = 281.5 - 335.1 / 2
     sp = Species3(q=-1.0, m=1.0, density=0.31,
