@@ -391,6 +391,8 @@ def main():
     ap.add_argument("--no-3d", action="store_true",
                     help="skip the 3D3V leg (sfpic3_*)")
     ap.add_argument("--steps-3d", type=int, default=20)
+    ap.add_argument("--no-3d-paper", action="store_true",
+                    help="skip the 3D leg at the paper's 2 pi/32 resolution")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device-to-device copy (3x) "
                          "whose profiler counters calibrate HBM traffic")
@@ -496,8 +498,9 @@ def main():
         out["fp32_vs_fp64"] = fp32_vs_fp64(args.compare_steps)
     if not args.no_3d:
         out["three_d"] = three_d(args.steps_3d)
-        out["three_d_paper_resolution"] = three_d(max(2, args.steps_3d // 2),
-                                                  cells_per_lambda=32)
+        if not args.no_3d_paper:
+            out["three_d_paper_resolution"] = three_d(
+                max(2, args.steps_3d // 2), cells_per_lambda=32)
     if not args.no_batch:
         out["batched_sweep"] = batched_sweep(args.batch_members,
                                              args.batch_steps)

@@ -13,11 +13,12 @@
 // E.  Particles: positions in cell units (x / dx ...), FP64 momenta, a
 // removed particle has x < -1.
 //
-// Every step sorts the particles by 8 x 8 x 8-cell tile (SFPIC3_TILE) (a counting sort
-// with creation ids carried along) and pushes each tile with one workgroup:
-// 27-tap gathers read the field arrays through the caches (a tile's field
-// halo stays in L2), and the tile's current accumulates in an FP64 LDS window
-// that is added to the global J once, with one atomic per window node.
+// Every step sorts the particles by 8 x 4 x 4-cell tile (SFPIC3_TILE; a
+// counting sort with creation ids carried along) and pushes each tile with
+// one workgroup: the tile's E and centred B halo (T + 3 nodes per axis) is
+// staged in LDS for the 27-tap gathers, and the tile's current accumulates
+// in an FP64 LDS window (T + 5 nodes per axis) that is added to the global J
+// once, with one atomic per window node.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -224,22 +225,6 @@ __device__ __forceinline__ int taps3(double xi, int dual, double w[3]) {
   return (int)c - 1 + G;
 }
 
-__device__ __forceinline__ double gather27(const double *__restrict__ a,
-                                           const Geo &g, const int b[3],
-                                           const double *wx, const double *wy,
-                                           const double *wz) {
-  double v = 0.0;
-#pragma unroll
-  for (int c = 0; c < 3; ++c)
-#pragma unroll
-    for (int bb = 0; bb < 3; ++bb) {
-      const double *row = a + g.at(b[0], b[1] + bb, b[2] + c);
-      v += wx[0] * wy[bb] * wz[c] * row[0] + wx[1] * wy[bb] * wz[c] * row[1] +
-           wx[2] * wy[bb] * wz[c] * row[2];
-    }
-  return v;
-}
-
 struct PushArgs {
   double dt, qm, qw;
   double inv_h[3], h_over_dt[3];  // 1/h, h/dt
@@ -247,13 +232,14 @@ struct PushArgs {
   double time, z_focus;
 };
 
-// Particle tiles: TX x TY x TZ cells.  Every step starts with the particles
-// sorted by tile (removed ones last), so a particle's old nearest node is in
+// Particle tiles: TX x TY x TZ cells (x, the contiguous axis, longest).
+// Every step starts with the particles sorted by tile (removed ones last),
+// so a particle's old nearest node is in
 // [tile start, tile end] along each axis and, since it moves less than one
 // cell per step (the CFL limit), every node its current touches lies in the
 // tile's window of T + 5 nodes per axis (old nearest node -2 .. +2).
 #ifndef SFPIC3_TILE
-#define SFPIC3_TILE 8, 8, 8
+#define SFPIC3_TILE 8, 4, 4
 #endif
 #ifndef SFPIC3_PUSH_WGS
 #define SFPIC3_PUSH_WGS 3  // workgroups per CU the push is compiled for
@@ -261,6 +247,9 @@ struct PushArgs {
 constexpr int kTile[3] = {SFPIC3_TILE};
 constexpr int TX = kTile[0], TY = kTile[1], TZ = kTile[2];
 constexpr int WX = TX + 5, WY = TY + 5, WZ = TZ + 5, WN = WX * WY * WZ;
+// Field window: every gather tap of a particle in the tile lies in nodes
+// t0 - 1 .. t0 + T + 1 along each axis, for primal and dual components.
+constexpr int FX = TX + 3, FY = TY + 3, FZ = TZ + 3, FN = FX * FY * FZ;
 
 struct Tiles {
   int ntx, nty, ntz;
@@ -383,6 +372,7 @@ __global__ void __launch_bounds__(256, SFPIC3_PUSH_WGS)
 push3_tiled(F3 f, Geo g, Parts3 p, const uint32_t *__restrict__ start, Tiles t,
             PushArgs a, IncParams inc) {
   __shared__ double sj[3 * WN];
+  __shared__ double sf[6 * FN];
   const uint32_t S = (t.ntiles + 7) >> 3, b = blockIdx.x;
   const uint32_t tile = (b & 7) * S + (b >> 3);
   if ((b >> 3) >= S || tile >= t.ntiles) return;
@@ -394,6 +384,21 @@ push3_tiled(F3 f, Geo g, Parts3 p, const uint32_t *__restrict__ start, Tiles t,
   // window node (0, 0, 0) is cell-node t0 - 2 along each axis
   const int w0[3] = {tx * TX - 2, ty * TY - 2, tz * TZ - 2};
   for (int k = threadIdx.x; k < 3 * WN; k += blockDim.x) sj[k] = 0.0;
+  // stage E^n and the centred B on the field window (array index of window
+  // node (0, 0, 0): w0 + 1 + G; nodes past the array read as zero and are
+  // never tapped)
+  const int fo[3] = {w0[0] + 1 + G, w0[1] + 1 + G, w0[2] + 1 + G};
+  for (int k = threadIdx.x; k < FN; k += blockDim.x) {
+    const int gi = fo[0] + k % FX, gj = fo[1] + (k / FX) % FY,
+              gk = fo[2] + k / (FX * FY);
+    const bool in = gi < g.NX && gj < g.NY && gk < g.NZ;
+    const size_t n = in ? g.at(gi, gj, gk) : 0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      sf[c * FN + k] = in ? f.e[c][n] : 0.0;
+      sf[(3 + c) * FN + k] = in ? f.bb[c][n] : 0.0;
+    }
+  }
   __syncthreads();
   constexpr double third = 1.0 / 3.0;
   for (uint32_t s = pbeg + threadIdx.x; s < pend; s += blockDim.x) {
@@ -408,9 +413,9 @@ push3_tiled(F3 f, Geo g, Parts3 p, const uint32_t *__restrict__ start, Tiles t,
 #pragma unroll
       for (int c = 0; c < 3; ++c) E[c] = B[c] = 0.0;
     }
-    // gather E^n and the centred B at x^n, added to the incident field: one
-    // component per iteration (an unrolled gather issues all 162 loads at
-    // once and needs more registers than two workgroups per CU leave);
+    // gather E^n and the centred B at x^n from the field window, added to
+    // the incident field: one component per iteration (fully unrolled, the
+    // 162 taps need more registers than three workgroups per CU leave);
     // staggering bits per component (Ex Ey Ez Bx By Bz): dual along x for
     // Ex By Bz, along y for Ey Bx Bz, along z for Ez Bx By
     {
@@ -426,12 +431,7 @@ push3_tiled(F3 f, Geo g, Parts3 p, const uint32_t *__restrict__ start, Tiles t,
       for (int c = 0; c < 6; ++c) {
         const bool sx = (kDualX >> c) & 1, sy = (kDualY >> c) & 1,
                    sz = (kDualZ >> c) & 1;
-        const double *plane =
-            c == 0 ? f.e[0]
-                   : c == 1 ? f.e[1]
-                            : c == 2 ? f.e[2]
-                                     : c == 3 ? f.bb[0]
-                                              : c == 4 ? f.bb[1] : f.bb[2];
+        const double *plane = sf + c * FN;
         double wx[3], wy[3], wz[3];
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
@@ -441,7 +441,19 @@ push3_tiled(F3 f, Geo g, Parts3 p, const uint32_t *__restrict__ start, Tiles t,
         }
         const int b[3] = {sx ? bd[0] : bp[0], sy ? bd[1] : bp[1],
                           sz ? bd[2] : bp[2]};
-        const double v = gather27(plane, g, b, wx, wy, wz);
+        double v = 0.0;
+        {
+          const int lx = b[0] - fo[0], ly = b[1] - fo[1], lz = b[2] - fo[2];
+#pragma unroll
+          for (int cz = 0; cz < 3; ++cz)
+#pragma unroll
+            for (int by = 0; by < 3; ++by) {
+              const double *row = plane + ((lz + cz) * FY + (ly + by)) * FX + lx;
+              const double wyz = wy[by] * wz[cz];
+              v += wx[0] * wyz * row[0] + wx[1] * wyz * row[1] +
+                   wx[2] * wyz * row[2];
+            }
+        }
         if (c == 0) E[0] = v + E[0];
         else if (c == 1) E[1] = v + E[1];
         else if (c == 2) E[2] = v + E[2];
