@@ -207,17 +207,17 @@ def incident_on_nodes(ref, steps, warmup):
     return res
 
 
-def three_d(steps=20, warmup=2, cells_per_lambda=16):
+def three_d(steps=20, warmup=2, cells_per_lambda=16, ppc=2):
     """The 3D3V step of Sec. 4 (sfpic3_*): the paper's 2 pi [24, 24, 32]
     box at Delta = 2 pi / cells_per_lambda (16: 512 x 384 x 384 cells; 32,
     the paper's own finer resolution: 1024 x 768 x 768 = 6.0e8 cells), cold
-    electrons in the Sec. 3.1 density profile (0.31 n_c peak, 2 per cell
+    electrons in the Sec. 3.1 density profile (0.31 n_c peak, ppc per cell
     there), tight April LP beam; FP64.  Host-timed around synchronized step
     batches (the leg runs for seconds)."""
     import torch
     from paper_2310_11393_amd import workloads as wl
     from paper_2310_11393_amd.binding import Simulation3
-    g, sp, inc = wl.paper3d_lp(cells_per_lambda)
+    g, sp, inc = wl.paper3d_lp(cells_per_lambda, ppc=ppc)
     n_sp = sp.count(g.dx)
     tag = f"3D 2pi/{cells_per_lambda}"
     log(f"{tag}: creating {n_sp / 1e6:.1f}M particles on "
@@ -245,7 +245,7 @@ def three_d(steps=20, warmup=2, cells_per_lambda=16):
     pushes = steps * 0.5 * (n0 + d["n_alive"])
     res = {"workload": (f"3D3V FP64, {g.nx}x{g.ny}x{g.nz} cells "
                         f"(2 pi/{cells_per_lambda}), {n_sp / 1e6:.1f}M cold "
-                        "electrons, 2 ppc at the 0.31 n_c peak of the "
+                        f"electrons, {ppc} ppc at the 0.31 n_c peak of the "
                         "order-12 super-Gaussian profile, April LP "
                         "w0=0.8 lambda s=20 a0=10"),
            "steps": steps, "pushes_per_s": pushes / sec,
@@ -500,7 +500,7 @@ def main():
         out["three_d"] = three_d(args.steps_3d)
         if not args.no_3d_paper:
             out["three_d_paper_resolution"] = three_d(
-                max(2, args.steps_3d // 2), cells_per_lambda=32)
+                max(2, args.steps_3d // 2), cells_per_lambda=32, ppc=4)
     if not args.no_batch:
         out["batched_sweep"] = batched_sweep(args.batch_members,
                                              args.batch_steps)
