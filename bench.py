@@ -207,24 +207,26 @@ def incident_on_nodes(ref, steps, warmup):
     return res
 
 
-def three_d(steps=20, warmup=2, cells_per_lambda=16, ppc=2):
+def three_d(steps=20, warmup=2, cells_per_lambda=16, ppc=2, precision=0):
     """The 3D3V step of Sec. 4 (sfpic3_*): the paper's 2 pi [24, 24, 32]
     box at Delta = 2 pi / cells_per_lambda (16: 512 x 384 x 384 cells; 32,
     the paper's own finer resolution: 1024 x 768 x 768 = 6.0e8 cells), cold
     electrons in the Sec. 3.1 density profile (0.31 n_c peak, ppc per cell
-    there), tight April LP beam; FP64.  Host-timed around synchronized step
+    there), tight April LP beam; FP64, or precision 1: fields and momenta
+    stored as float, arithmetic FP64.  Host-timed around synchronized step
     batches (the leg runs for seconds)."""
     import torch
     from paper_2310_11393_amd import workloads as wl
     from paper_2310_11393_amd.binding import Simulation3
     g, sp, inc = wl.paper3d_lp(cells_per_lambda, ppc=ppc)
     n_sp = sp.count(g.dx)
-    tag = f"3D 2pi/{cells_per_lambda}"
+    kind = "FP32 storage" if precision else "FP64"
+    tag = f"3D 2pi/{cells_per_lambda} {kind}"
     log(f"{tag}: creating {n_sp / 1e6:.1f}M particles on "
         f"{g.nx}x{g.ny}x{g.nz} cells")
     torch.cuda.empty_cache()
     torch.cuda.reset_peak_memory_stats()
-    sim = Simulation3(g, inc, species=[sp])
+    sim = Simulation3(g, inc, species=[sp], precision=precision)
     sim.step(warmup)
     sim.sync()
     n0 = sim.diagnostics()["n_alive"]
@@ -243,7 +245,7 @@ def three_d(steps=20, warmup=2, cells_per_lambda=16, ppc=2):
     peak = torch.cuda.max_memory_allocated()
     torch.cuda.empty_cache()
     pushes = steps * 0.5 * (n0 + d["n_alive"])
-    res = {"workload": (f"3D3V FP64, {g.nx}x{g.ny}x{g.nz} cells "
+    res = {"workload": (f"3D3V {kind}, {g.nx}x{g.ny}x{g.nz} cells "
                         f"(2 pi/{cells_per_lambda}), {n_sp / 1e6:.1f}M cold "
                         f"electrons, {ppc} ppc at the 0.31 n_c peak of the "
                         "order-12 super-Gaussian profile, April LP "
@@ -498,9 +500,11 @@ def main():
         out["fp32_vs_fp64"] = fp32_vs_fp64(args.compare_steps)
     if not args.no_3d:
         out["three_d"] = three_d(args.steps_3d)
+        out["three_d_fp32"] = three_d(args.steps_3d, precision=1)
         if not args.no_3d_paper:
             out["three_d_paper_resolution"] = three_d(
-                max(2, args.steps_3d // 2), cells_per_lambda=32, ppc=4)
+                max(2, args.steps_3d // 4), cells_per_lambda=32, ppc=8,
+                precision=1)
     if not args.no_batch:
         out["batched_sweep"] = batched_sweep(args.batch_members,
                                              args.batch_steps)

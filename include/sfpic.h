@@ -483,8 +483,9 @@ void sfpic_server_destroy(sfpic_server *srv);
  * Esirkepov (2001) current; removal of particles that leave the physical
  * box [0, nx dx) x [0, ny dy) x [0, nz dz) after they deposit; first-order
  * Mur on tangential E at the outer faces (z faces, then y, then x; an edge
- * node takes the last face's value).  FP64 throughout; single simulations
- * only (no batches or servers).  Host field arrays are [k][j][i] with i
+ * node takes the last face's value).  FP64, or FP32 storage of fields and
+ * momenta (see sfpic3_create); single simulations only (no batches or
+ * servers).  Host field arrays are [k][j][i] with i
  * fastest, NX = nx + 2 SFPIC_GUARD, NY = ny + 2 SFPIC_GUARD, NZ = nz + 2
  * SFPIC_GUARD. */
 typedef struct {
@@ -520,11 +521,16 @@ typedef struct sfpic3_sim sfpic3_sim;
 
 /* Create a 3D simulation (scattered field zero, u^{-1/2} = u^0).  Incident
  * kinds: none, plane pulse, April LP / RP with on_nodes = 0; the Gaussian
- * beam is 2D only.  SFPIC_E_INVAL for bad sizes, parameters or explicit
- * particles outside the box, SFPIC_E_NOMEM, SFPIC_E_DEVICE. */
+ * beam is 2D only.  precision: SFPIC_FP64, or SFPIC_FP32, the 3D storage
+ * form: fields and momenta stored as float (half the field memory, 12 of 24
+ * momentum bytes per particle), positions FP64 in cell units, every
+ * operation and the current accumulation in FP64 (unlike the 2D FP32 form,
+ * whose arithmetic is FP32).  SFPIC_E_INVAL for bad sizes, parameters or
+ * explicit particles outside the box, SFPIC_E_NOMEM, SFPIC_E_DEVICE. */
 int sfpic3_create(const sfpic3_grid *grid, const sfpic3_species *species,
                   int nspecies, const sfpic_incident *incident,
-                  const sfpic_runtime *runtime, sfpic3_sim **out);
+                  sfpic_precision precision, const sfpic_runtime *runtime,
+                  sfpic3_sim **out);
 /* Enqueue nsteps >= 0 steps on the runtime stream (asynchronous). */
 int sfpic3_step(sfpic3_sim *sim, int64_t nsteps);
 int sfpic3_sync(sfpic3_sim *sim);

@@ -227,7 +227,7 @@ def lib():
     L.sfpic_device_bytes.argtypes = [vp, C.POINTER(sz)]
     L.sfpic3_create.argtypes = [C.POINTER(sfpic3_grid),
                                 C.POINTER(sfpic3_species), C.c_int,
-                                C.POINTER(sfpic_incident),
+                                C.POINTER(sfpic_incident), C.c_int,
                                 C.POINTER(sfpic_runtime), C.POINTER(vp)]
     L.sfpic3_step.argtypes = [vp, i64]
     L.sfpic3_sync.argtypes = [vp]
@@ -714,11 +714,12 @@ class Server:
 
 class Simulation3:
     """One 3D3V simulation held by the library (sfpic3_*).  Field arrays are
-    (NZ, NY, NX); FP64 only."""
+    (NZ, NY, NX) as FP64 on the host; precision FP64, or FP32 (fields and
+    momenta stored as float, arithmetic in FP64)."""
 
     def __init__(self, grid, incident, species: Sequence = (),
                  explicit: Optional[Sequence] = None, use_torch: bool = True,
-                 device: int = 0):
+                 device: int = 0, precision: int = FP64):
         """grid: nx, ny, nz, dx, dy, dz, dt.  species: objects with q, m,
         density, region (x0, x1, y0, y1, z0, z1), ppc, temperature_ev, seed
         (generated on the device, species index = position in the list);
@@ -756,7 +757,8 @@ class Simulation3:
         inc = _incident_struct(incident)
         h = C.c_void_p()
         _check(L.sfpic3_create(C.byref(g), sp_arr, n, C.byref(inc),
-                               C.byref(self._rt), C.byref(h)))
+                               int(precision), C.byref(self._rt), C.byref(h)))
+        self.precision = precision
         del keep
         self.h = h
         self.nspecies = n

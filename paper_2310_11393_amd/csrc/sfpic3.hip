@@ -54,13 +54,23 @@ struct Geo {
   }
 };
 
+// Fields and momenta are stored as R (double, or float in the FP32 storage
+// form); positions are always FP64 cell units and all arithmetic is FP64.
+template <typename R>
 struct F3 {
-  double *e[3], *b[3], *j[3], *bb[3];  // E^n, B^{n-1/2}, J, centred B
+  R *e[3], *b[3], *j[3], *bb[3];  // E^n, B^{n-1/2}, J, centred B
 };
 
+template <typename R>
 struct Parts3 {
-  double *x[3], *u[3];
+  double *x[3];
+  R *u[3];
 };
+
+template <typename R>
+__device__ __forceinline__ double ld(const R *a, size_t i) {
+  return (double)a[i];
+}
 
 // ---------------------------------------------------------------------------
 // Yee solver
@@ -69,39 +79,44 @@ struct Parts3 {
 // B^{n+1/2} = B^{n-1/2} - dt curl_h E^n (forward differences), the centred
 // B = (B^{n-1/2} + B^{n+1/2}) / 2, and J = 0 ahead of the deposit.  A
 // component whose stencil would leave the array keeps its value.
+template <typename R>
 __global__ void __launch_bounds__(256)
-faraday3(F3 f, Geo g, double cx, double cy, double cz) {
+faraday3(F3<R> f, Geo g, double cx, double cy, double cz) {
   const int i = blockIdx.x * 64 + threadIdx.x, j = blockIdx.y * 4 + threadIdx.y,
             k = blockIdx.z;
   if (i >= g.NX || j >= g.NY) return;
   const size_t n = g.at(i, j, k), sj = g.P, sk = (size_t)g.P * g.NY;
   const bool ix = i + 1 < g.NX, jy = j + 1 < g.NY, kz = k + 1 < g.NZ;
-  double o = f.b[0][n], v = o;
+  double o = ld(f.b[0], n), v = o;
   if (jy && kz)
-    v = o - (cy * (f.e[2][n + sj] - f.e[2][n]) - cz * (f.e[1][n + sk] - f.e[1][n]));
-  f.b[0][n] = v;
-  f.bb[0][n] = 0.5 * (o + v);
-  o = f.b[1][n];
+    v = o - (cy * (ld(f.e[2], n + sj) - ld(f.e[2], n)) -
+             cz * (ld(f.e[1], n + sk) - ld(f.e[1], n)));
+  f.b[0][n] = (R)v;
+  f.bb[0][n] = (R)(0.5 * (o + v));
+  o = ld(f.b[1], n);
   v = o;
   if (ix && kz)
-    v = o - (cz * (f.e[0][n + sk] - f.e[0][n]) - cx * (f.e[2][n + 1] - f.e[2][n]));
-  f.b[1][n] = v;
-  f.bb[1][n] = 0.5 * (o + v);
-  o = f.b[2][n];
+    v = o - (cz * (ld(f.e[0], n + sk) - ld(f.e[0], n)) -
+             cx * (ld(f.e[2], n + 1) - ld(f.e[2], n)));
+  f.b[1][n] = (R)v;
+  f.bb[1][n] = (R)(0.5 * (o + v));
+  o = ld(f.b[2], n);
   v = o;
   if (ix && jy)
-    v = o - (cx * (f.e[1][n + 1] - f.e[1][n]) - cy * (f.e[0][n + sj] - f.e[0][n]));
-  f.b[2][n] = v;
-  f.bb[2][n] = 0.5 * (o + v);
-  f.j[0][n] = 0.0;
-  f.j[1][n] = 0.0;
-  f.j[2][n] = 0.0;
+    v = o - (cx * (ld(f.e[1], n + 1) - ld(f.e[1], n)) -
+             cy * (ld(f.e[0], n + sj) - ld(f.e[0], n)));
+  f.b[2][n] = (R)v;
+  f.bb[2][n] = (R)(0.5 * (o + v));
+  f.j[0][n] = (R)0;
+  f.j[1][n] = (R)0;
+  f.j[2][n] = (R)0;
 }
 
 // E^{n+1} = E^n + dt (curl_h B^{n+1/2} - J^{n+1/2}) (backward differences) on
 // the nodes that have both neighbours; the outer faces are left to Mur.
+template <typename R>
 __global__ void __launch_bounds__(256)
-ampere3(F3 f, Geo g, double dt, double cx, double cy, double cz) {
+ampere3(F3<R> f, Geo g, double dt, double cx, double cy, double cz) {
   const int i = blockIdx.x * 64 + threadIdx.x, j = blockIdx.y * 4 + threadIdx.y,
             k = blockIdx.z;
   if (i >= g.NX || j >= g.NY) return;
@@ -110,14 +125,17 @@ ampere3(F3 f, Geo g, double dt, double cx, double cy, double cz) {
              zin = k >= 1 && k + 1 < g.NZ;
   const bool xlo = i + 1 < g.NX, ylo = j + 1 < g.NY, zlo = k + 1 < g.NZ;
   if (xlo && yin && zin)
-    f.e[0][n] = f.e[0][n] + cy * (f.b[2][n] - f.b[2][n - sj]) -
-                cz * (f.b[1][n] - f.b[1][n - sk]) - dt * f.j[0][n];
+    f.e[0][n] = (R)(ld(f.e[0], n) + cy * (ld(f.b[2], n) - ld(f.b[2], n - sj)) -
+                    cz * (ld(f.b[1], n) - ld(f.b[1], n - sk)) -
+                    dt * ld(f.j[0], n));
   if (xin && ylo && zin)
-    f.e[1][n] = f.e[1][n] + cz * (f.b[0][n] - f.b[0][n - sk]) -
-                cx * (f.b[2][n] - f.b[2][n - 1]) - dt * f.j[1][n];
+    f.e[1][n] = (R)(ld(f.e[1], n) + cz * (ld(f.b[0], n) - ld(f.b[0], n - sk)) -
+                    cx * (ld(f.b[2], n) - ld(f.b[2], n - 1)) -
+                    dt * ld(f.j[1], n));
   if (xin && yin && zlo)
-    f.e[2][n] = f.e[2][n] + cx * (f.b[1][n] - f.b[1][n - 1]) -
-                cy * (f.b[0][n] - f.b[0][n - sj]) - dt * f.j[2][n];
+    f.e[2][n] = (R)(ld(f.e[2], n) + cx * (ld(f.b[1], n) - ld(f.b[1], n - 1)) -
+                    cy * (ld(f.b[0], n) - ld(f.b[0], n - sj)) -
+                    dt * ld(f.j[2], n));
 }
 
 // Faces normal to axis A hold the tangential components T0 = (A+1)%3 and
@@ -131,8 +149,8 @@ __host__ __device__ inline int ext(const Geo &g, int a) {
   return a == 0 ? g.NX : (a == 1 ? g.NY : g.NZ);
 }
 
-template <int A>
-__global__ void __launch_bounds__(256) save_faces3(F3 f, Geo g, double *buf) {
+template <int A, typename R>
+__global__ void __launch_bounds__(256) save_faces3(F3<R> f, Geo g, double *buf) {
   int e, fa;
   face_axes(A, e, fa);
   const int ne = ext(g, e), nf = ext(g, fa), na = ext(g, A);
@@ -147,17 +165,17 @@ __global__ void __launch_bounds__(256) save_faces3(F3 f, Geo g, double *buf) {
     idx[e] = ie;
     idx[fa] = jf;
     const size_t n = g.at(idx[0], idx[1], idx[2]);
-    buf[((size_t)(l * 2 + 0) * nf + jf) * ne + ie] = f.e[e][n];
-    buf[((size_t)(l * 2 + 1) * nf + jf) * ne + ie] = f.e[fa][n];
+    buf[((size_t)(l * 2 + 0) * nf + jf) * ne + ie] = ld(f.e[e], n);
+    buf[((size_t)(l * 2 + 1) * nf + jf) * ne + ie] = ld(f.e[fa], n);
   }
 }
 
 // First-order Mur on the two faces normal to A: E_b^{n+1} = E_in^n +
 // k (E_in^{n+1} - E_b^n), over every index a component occupies (the last
 // index along an axis where it is dual is outside the grid).
-template <int A>
+template <int A, typename R>
 __global__ void __launch_bounds__(256)
-mur3(F3 f, Geo g, const double *buf, double kf) {
+mur3(F3<R> f, Geo g, const double *buf, double kf) {
   int e, fa;
   face_axes(A, e, fa);
   const int ne = ext(g, e), nf = ext(g, fa), na = ext(g, A);
@@ -180,8 +198,8 @@ mur3(F3 f, Geo g, const double *buf, double kf) {
       const int lb = side ? 3 : 0, li = side ? 2 : 1;
       const double in_old = buf[((size_t)(li * 2 + c) * nf + jf) * ne + ie];
       const double b_old = buf[((size_t)(lb * 2 + c) * nf + jf) * ne + ie];
-      const double in_new = f.e[comp][g.at(ii[0], ii[1], ii[2])];
-      f.e[comp][g.at(ib[0], ib[1], ib[2])] = in_old + kf * (in_new - b_old);
+      const double in_new = ld(f.e[comp], g.at(ii[0], ii[1], ii[2]));
+      f.e[comp][g.at(ib[0], ib[1], ib[2])] = (R)(in_old + kf * (in_new - b_old));
     }
   }
 }
@@ -268,8 +286,9 @@ __device__ __forceinline__ uint32_t tile_key(const Tiles &t, double x,
 // Counting pass: rank of each particle within its key.  The lanes of a wave
 // that share a key take one atomic between them (one round per distinct key
 // in the wave: the particles arrive sorted, so there are few).
+template <typename R>
 __global__ void __launch_bounds__(256)
-tile_count3(Parts3 p, int64_t n, Tiles t, uint32_t *count, uint32_t *rank) {
+tile_count3(Parts3<R> p, int64_t n, Tiles t, uint32_t *count, uint32_t *rank) {
   const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool active = s < n;
   const uint32_t key =
@@ -349,8 +368,9 @@ scan3_add(uint32_t *out, const uint32_t *sums, uint32_t m) {
 }
 
 // Scatter every slot to start[key] + rank in the other buffer, id with it.
+template <typename R>
 __global__ void __launch_bounds__(256)
-tile_scatter3(Parts3 src, Parts3 dst, const uint32_t *sid, uint32_t *did,
+tile_scatter3(Parts3<R> src, Parts3<R> dst, const uint32_t *sid, uint32_t *did,
               int64_t n, Tiles t, const uint32_t *start, const uint32_t *rank) {
   const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= n) return;
@@ -368,8 +388,9 @@ tile_scatter3(Parts3 src, Parts3 dst, const uint32_t *sid, uint32_t *did,
 // b / 8, S = ceil(tiles / 8), so each XCD walks a contiguous band of tiles
 // whose field halos share its L2).  The current of the tile's particles is
 // accumulated in an FP64 LDS window and added to the global J once.
+template <typename R>
 __global__ void __launch_bounds__(256, SFPIC3_PUSH_WGS)
-push3_tiled(F3 f, Geo g, Parts3 p, const uint32_t *__restrict__ start, Tiles t,
+push3_tiled(F3<R> f, Geo g, Parts3<R> p, const uint32_t *__restrict__ start, Tiles t,
             PushArgs a, IncParams inc) {
   __shared__ double sj[3 * WN];
   __shared__ double sf[6 * FN];
@@ -395,12 +416,11 @@ push3_tiled(F3 f, Geo g, Parts3 p, const uint32_t *__restrict__ start, Tiles t,
     const size_t n = in ? g.at(gi, gj, gk) : 0;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      sf[c * FN + k] = in ? f.e[c][n] : 0.0;
-      sf[(3 + c) * FN + k] = in ? f.bb[c][n] : 0.0;
+      sf[c * FN + k] = in ? ld(f.e[c], n) : 0.0;
+      sf[(3 + c) * FN + k] = in ? ld(f.bb[c], n) : 0.0;
     }
   }
   __syncthreads();
-  constexpr double third = 1.0 / 3.0;
   for (uint32_t s = pbeg + threadIdx.x; s < pend; s += blockDim.x) {
     double xi[3];
 #pragma unroll
@@ -464,7 +484,7 @@ push3_tiled(F3 f, Geo g, Parts3 p, const uint32_t *__restrict__ start, Tiles t,
     }
     double u[3];
 #pragma unroll
-    for (int d = 0; d < 3; ++d) u[d] = p.u[d][s];
+    for (int d = 0; d < 3; ++d) u[d] = ld(p.u[d], s);
     sfpic::boris<double>(a.qm, a.dt, u, E, B);
     const double gi =
         sfpic::rsqrt(1.0 + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
@@ -532,7 +552,7 @@ push3_tiled(F3 f, Geo g, Parts3 p, const uint32_t *__restrict__ start, Tiles t,
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       p.x[d][s] = (d == 0 && out) ? kDead : x1[d];
-      p.u[d][s] = u[d];
+      p.u[d][s] = (R)u[d];
     }
   }
   __syncthreads();
@@ -546,13 +566,14 @@ push3_tiled(F3 f, Geo g, Parts3 p, const uint32_t *__restrict__ start, Tiles t,
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       const double v = sj[c * WN + k];
-      if (v != 0.0) atomicAdd(f.j[c] + n, v);
+      if (v != 0.0) atomicAdd(f.j[c] + n, (R)v);
     }
   }
 }
 
 // Explicit particles: physical positions to cell units.
-__global__ void load3(Parts3 p, int64_t n, const double *x, const double *y,
+template <typename R>
+__global__ void load3(Parts3<R> p, int64_t n, const double *x, const double *y,
                       const double *z, const double *ux, const double *uy,
                       const double *uz, double ihx, double ihy, double ihz) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -560,9 +581,9 @@ __global__ void load3(Parts3 p, int64_t n, const double *x, const double *y,
   p.x[0][i] = x[i] * ihx;
   p.x[1][i] = y[i] * ihy;
   p.x[2][i] = z[i] * ihz;
-  p.u[0][i] = ux[i];
-  p.u[1][i] = uy[i];
-  p.u[2][i] = uz[i];
+  p.u[0][i] = (R)ux[i];
+  p.u[1][i] = (R)uy[i];
+  p.u[2][i] = (R)uz[i];
 }
 
 // Generated particles: ppc per cell of the region, uniform in the cell, the
@@ -571,7 +592,8 @@ __global__ void load3(Parts3 p, int64_t n, const double *x, const double *y,
 // With a density profile (off != nullptr) particle i sits in region row
 // i / per_row (y fastest, then z) and in the column whose offsets bracket
 // i % per_row.
-__global__ void init3(Parts3 p, int64_t n, int64_t x0, int64_t y0, int64_t z0,
+template <typename R>
+__global__ void init3(Parts3<R> p, int64_t n, int64_t x0, int64_t y0, int64_t z0,
                       int64_t ncx, int64_t ncy, int ppc, double sigma,
                       uint32_t k0, uint32_t k1, const uint32_t *off,
                       uint32_t per_row) {
@@ -614,9 +636,9 @@ __global__ void init3(Parts3 p, int64_t n, int64_t x0, int64_t y0, int64_t z0,
   p.x[0][i] = (double)cx + a;
   p.x[1][i] = (double)cy + b;
   p.x[2][i] = (double)cz + cc;
-  p.u[0][i] = ux;
-  p.u[1][i] = uy;
-  p.u[2][i] = uz;
+  p.u[0][i] = (R)ux;
+  p.u[1][i] = (R)uy;
+  p.u[2][i] = (R)uz;
 }
 
 // ---------------------------------------------------------------------------
@@ -636,13 +658,14 @@ __device__ __forceinline__ double block_sum(double v, double *sh) {
 }
 
 // acc[0] += sum (gamma - 1), acc[1] += live count; flag |= 1 on non-finite
+template <typename R>
 __global__ void __launch_bounds__(256)
-psums3(Parts3 p, int64_t n, double *acc, int *flag) {
+psums3(Parts3<R> p, int64_t n, double *acc, int *flag) {
   __shared__ double sh[4];
   const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   double g1 = 0.0, cnt = 0.0;
   if (s < n && p.x[0][s] >= -1.0) {
-    const double u0 = p.u[0][s], u1 = p.u[1][s], u2 = p.u[2][s];
+    const double u0 = ld(p.u[0], s), u1 = ld(p.u[1], s), u2 = ld(p.u[2], s);
     const double q = u0 * u0 + u1 * u1 + u2 * u2;
     if (!isfinite(q)) atomicOr(flag, 1);
     g1 = q / (sqrt(1.0 + q) + 1.0);  // gamma - 1 without cancellation
@@ -657,14 +680,18 @@ psums3(Parts3 p, int64_t n, double *acc, int *flag) {
 }
 
 // acc[0] += 1/2 sum over every array element of E^2 + B^2
+template <typename R>
 __global__ void __launch_bounds__(256)
-fsums3(F3 f, size_t n, double *acc, int *flag) {
+fsums3(F3<R> f, size_t n, double *acc, int *flag) {
   __shared__ double sh[4];
   const size_t s = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   double v = 0.0;
   if (s < n) {
 #pragma unroll
-    for (int c = 0; c < 3; ++c) v += f.e[c][s] * f.e[c][s] + f.b[c][s] * f.b[c][s];
+    for (int c = 0; c < 3; ++c) {
+      const double e = ld(f.e[c], s), b = ld(f.b[c], s);
+      v += e * e + b * b;
+    }
     if (!isfinite(v)) atomicOr(flag, 1);
   }
   v = block_sum(0.5 * v, sh);
@@ -672,8 +699,9 @@ fsums3(F3 f, size_t n, double *acc, int *flag) {
 }
 
 // rho += q w S(x) on the primal nodes (order-2, 27 nodes per particle)
+template <typename R>
 __global__ void __launch_bounds__(256)
-rho3(Parts3 p, int64_t n, Geo g, double qw, double *rho) {
+rho3(Parts3<R> p, int64_t n, Geo g, double qw, double *rho) {
   const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= n) return;
   double xi[3], w[3][3];
@@ -692,8 +720,9 @@ rho3(Parts3 p, int64_t n, Geo g, double qw, double *rho) {
 
 // max |div_h E - (rho - rho0)| and max |rho - rho0| over nodes at least 4
 // cells inside the physical box (non-negative doubles order as integers)
+template <typename R>
 __global__ void __launch_bounds__(256)
-gauss3(F3 f, Geo g, const double *rho, const double *rho0, double ihx,
+gauss3(F3<R> f, Geo g, const double *rho, const double *rho0, double ihx,
        double ihy, double ihz, unsigned long long *mx) {
   const int i = blockIdx.x * 64 + threadIdx.x, j = blockIdx.y * 4 + threadIdx.y,
             k = blockIdx.z;
@@ -702,9 +731,9 @@ gauss3(F3 f, Geo g, const double *rho, const double *rho0, double ihx,
       k > G + g.nz - 4)
     return;
   const size_t n = g.at(i, j, k), sj = g.P, sk = (size_t)g.P * g.NY;
-  const double div = (f.e[0][n] - f.e[0][n - 1]) * ihx +
-                     (f.e[1][n] - f.e[1][n - sj]) * ihy +
-                     (f.e[2][n] - f.e[2][n - sk]) * ihz;
+  const double div = (ld(f.e[0], n) - ld(f.e[0], n - 1)) * ihx +
+                     (ld(f.e[1], n) - ld(f.e[1], n - sj)) * ihy +
+                     (ld(f.e[2], n) - ld(f.e[2], n - sk)) * ihz;
   const double dr = rho[n] - rho0[n];
   atomicMax(mx, (unsigned long long)__double_as_longlong(fabs(div - dr)));
   atomicMax(mx + 1, (unsigned long long)__double_as_longlong(fabs(dr)));
@@ -717,10 +746,13 @@ gauss3(F3 f, Geo g, const double *rho, const double *rho0, double ihx,
 // ---------------------------------------------------------------------------
 using namespace sfpic3;
 
+// The host keeps one pointer set per object; the momentum (and field)
+// pointers hold values of the storage type and are cast for the float
+// kernels (parts_as, fields_as).
 struct Species3 {
   double q = -1.0, m = 1.0, w = 0.0;
   int64_t n = 0;
-  Parts3 p{}, alt{};                       // particles, sort target
+  Parts3<double> p{}, alt{};               // particles, sort target
   uint32_t *id = nullptr, *id_alt = nullptr;  // creation index per slot
 };
 
@@ -739,7 +771,8 @@ struct sfpic3_sim {
   IncParams inc{};
   double z_focus = 0.0;
   int64_t step = 0;
-  F3 f{};
+  bool fp32 = false;  // fields and momenta stored as float
+  F3<double> f{};
   double *face[3] = {};
   Tiles tiles{};
   uint32_t *count = nullptr, *start = nullptr, *sums = nullptr;
@@ -786,24 +819,49 @@ dim3 node_grid(const Geo &g) {
 
 unsigned blocks_for(int64_t n) { return (unsigned)((n + 255) / 256); }
 
-template <int A>
+template <typename R>
+F3<R> fields_as(const F3<double> &f) {
+  F3<R> r;
+  for (int c = 0; c < 3; ++c) {
+    r.e[c] = (R *)f.e[c];
+    r.b[c] = (R *)f.b[c];
+    r.j[c] = (R *)f.j[c];
+    r.bb[c] = (R *)f.bb[c];
+  }
+  return r;
+}
+
+template <typename R>
+Parts3<R> parts_as(const Parts3<double> &p) {
+  Parts3<R> r;
+  for (int d = 0; d < 3; ++d) {
+    r.x[d] = p.x[d];
+    r.u[d] = (R *)p.u[d];
+  }
+  return r;
+}
+
+template <int A, typename R>
 int face_pass(sfpic3_sim *S, bool save, double kf) {
   int e, fa;
   face_axes(A, e, fa);
   const int64_t area = (int64_t)ext(S->g, e) * ext(S->g, fa);
+  const F3<R> f = fields_as<R>(S->f);
   if (save)
-    save_faces3<A><<<blocks_for(area), 256, 0, S->st>>>(S->f, S->g, S->face[A]);
+    save_faces3<A, R><<<blocks_for(area), 256, 0, S->st>>>(f, S->g, S->face[A]);
   else
-    mur3<A><<<blocks_for(area), 256, 0, S->st>>>(S->f, S->g, S->face[A], kf);
+    mur3<A, R><<<blocks_for(area), 256, 0, S->st>>>(f, S->g, S->face[A], kf);
   HIP3(hipGetLastError());
   return SFPIC_OK;
 }
 
-int one_step(sfpic3_sim *S) {
+template <typename R>
+int one_step_t(sfpic3_sim *S) {
   const sfpic3_grid &gr = S->grid;
   const double dt = gr.dt;
   const double cx = dt / gr.dx, cy = dt / gr.dy, cz = dt / gr.dz;
-  faraday3<<<node_grid(S->g), dim3(64, 4), 0, S->st>>>(S->f, S->g, cx, cy, cz);
+  const F3<R> f = fields_as<R>(S->f);
+  faraday3<R><<<node_grid(S->g), dim3(64, 4), 0, S->st>>>(f, S->g, cx, cy, cz);
   HIP3(hipGetLastError());
   PushArgs a{};
   a.dt = dt;
@@ -823,43 +881,52 @@ int one_step(sfpic3_sim *S) {
     if (sp.n == 0) continue;
     // sort by tile (removed particles last), ids along
     HIP3(hipMemsetAsync(S->count, 0, (size_t)m * 4, S->st));
-    tile_count3<<<blocks_for(sp.n), 256, 0, S->st>>>(sp.p, sp.n, t, S->count,
-                                                     S->rank);
+    tile_count3<R><<<blocks_for(sp.n), 256, 0, S->st>>>(
+        parts_as<R>(sp.p), sp.n, t, S->count, S->rank);
     scan3_blocks<<<nb, 1024, 0, S->st>>>(S->count, S->start, S->sums, m);
     scan3_sums<<<1, 1024, 0, S->st>>>(S->sums, nb);
     scan3_add<<<nb, 1024, 0, S->st>>>(S->start, S->sums, m);
-    tile_scatter3<<<blocks_for(sp.n), 256, 0, S->st>>>(
-        sp.p, sp.alt, sp.id, sp.id_alt, sp.n, t, S->start, S->rank);
+    tile_scatter3<R><<<blocks_for(sp.n), 256, 0, S->st>>>(
+        parts_as<R>(sp.p), parts_as<R>(sp.alt), sp.id, sp.id_alt, sp.n, t,
+        S->start, S->rank);
     HIP3(hipGetLastError());
     std::swap(sp.p, sp.alt);
     std::swap(sp.id, sp.id_alt);
     a.qm = sp.q / sp.m;
     a.qw = sp.q * sp.w;
-    push3_tiled<<<grid8, 256, 0, S->st>>>(S->f, S->g, sp.p, S->start, t, a,
-                                          S->inc);
+    push3_tiled<R><<<grid8, 256, 0, S->st>>>(f, S->g, parts_as<R>(sp.p),
+                                             S->start, t, a, S->inc);
     HIP3(hipGetLastError());
   }
-  if (int r = face_pass<0>(S, true, 0.0)) return r;
-  if (int r = face_pass<1>(S, true, 0.0)) return r;
-  if (int r = face_pass<2>(S, true, 0.0)) return r;
-  ampere3<<<node_grid(S->g), dim3(64, 4), 0, S->st>>>(S->f, S->g, dt, cx, cy,
-                                                      cz);
+  if (int r = face_pass<0, R>(S, true, 0.0)) return r;
+  if (int r = face_pass<1, R>(S, true, 0.0)) return r;
+  if (int r = face_pass<2, R>(S, true, 0.0)) return r;
+  ampere3<R><<<node_grid(S->g), dim3(64, 4), 0, S->st>>>(f, S->g, dt, cx, cy,
+                                                         cz);
   HIP3(hipGetLastError());
   const double kx = (dt - gr.dx) / (dt + gr.dx), ky = (dt - gr.dy) / (dt + gr.dy),
                kz = (dt - gr.dz) / (dt + gr.dz);
-  if (int r = face_pass<2>(S, false, kz)) return r;  // z faces first
-  if (int r = face_pass<1>(S, false, ky)) return r;
-  if (int r = face_pass<0>(S, false, kx)) return r;
+  if (int r = face_pass<2, R>(S, false, kz)) return r;  // z faces first
+  if (int r = face_pass<1, R>(S, false, ky)) return r;
+  if (int r = face_pass<0, R>(S, false, kx)) return r;
   S->step++;
   return SFPIC_OK;
+}
+
+int one_step(sfpic3_sim *S) {
+  return S->fp32 ? one_step_t<float>(S) : one_step_t<double>(S);
 }
 
 int deposit_rho(sfpic3_sim *S, double *rho) {
   HIP3(hipMemsetAsync(rho, 0, S->plane * 8, S->st));
   for (auto &sp : S->sp) {
     if (sp.n == 0) continue;
-    rho3<<<blocks_for(sp.n), 256, 0, S->st>>>(sp.p, sp.n, S->g, sp.q * sp.w,
-                                              rho);
+    if (S->fp32)
+      rho3<float><<<blocks_for(sp.n), 256, 0, S->st>>>(
+          parts_as<float>(sp.p), sp.n, S->g, sp.q * sp.w, rho);
+    else
+      rho3<double><<<blocks_for(sp.n), 256, 0, S->st>>>(sp.p, sp.n, S->g,
+                                                        sp.q * sp.w, rho);
     HIP3(hipGetLastError());
   }
   return SFPIC_OK;
@@ -871,8 +938,11 @@ extern "C" {
 
 int sfpic3_create(const sfpic3_grid *grid, const sfpic3_species *species,
                   int nspecies, const sfpic_incident *incident,
-                  const sfpic_runtime *runtime, sfpic3_sim **out) {
+                  sfpic_precision precision, const sfpic_runtime *runtime,
+                  sfpic3_sim **out) {
   if (!out) return sfpic::fail(SFPIC_E_INVAL, "out is NULL");
+  if (precision != SFPIC_FP64 && precision != SFPIC_FP32)
+    return sfpic::fail(SFPIC_E_INVAL, "precision must be SFPIC_FP64 or SFPIC_FP32");
   *out = nullptr;
   if (!grid) return sfpic::fail(SFPIC_E_INVAL, "grid is NULL");
   const sfpic3_grid &g = *grid;
@@ -923,8 +993,10 @@ int sfpic3_create(const sfpic3_grid *grid, const sfpic3_species *species,
         return sfpic::fail(SFPIC_E_INVAL, "species region outside the grid");
       if (d.temperature_ev < 0.0 || !std::isfinite(d.density))
         return sfpic::fail(SFPIC_E_INVAL, "bad density or temperature");
+      // a profiled species is counted (and checked) once its column
+      // offsets are known, below
       const int64_t np = (r[1] - r[0]) * (r[3] - r[2]) * (r[5] - r[4]) * d.ppc;
-      if (np > kMaxParticles)
+      if (d.profile == SFPIC_PROFILE_UNIFORM && np > kMaxParticles)
         return sfpic::fail(SFPIC_E_SIZE, "too many generated particles");
     } else if (d.n_explicit < 0 || d.ppc < 0) {
       return sfpic::fail(SFPIC_E_INVAL, "negative particle count");
@@ -933,6 +1005,8 @@ int sfpic3_create(const sfpic3_grid *grid, const sfpic3_species *species,
   HIP3(hipSetDevice(runtime ? runtime->device : 0));
   sfpic3_sim *S = new sfpic3_sim();
   S->grid = g;
+  S->fp32 = precision == SFPIC_FP32;
+  const size_t esz = S->fp32 ? 4 : 8;  // bytes per field value and momentum
   if (runtime) S->rt = *runtime;
   S->st = (hipStream_t)S->rt.stream;
   S->inc = P;
@@ -952,9 +1026,9 @@ int sfpic3_create(const sfpic3_grid *grid, const sfpic3_species *species,
   };
   double *planes[12];
   for (int c = 0; c < 12; ++c) {
-    planes[c] = (double *)S->dalloc(S->plane * 8);
+    planes[c] = (double *)S->dalloc(S->plane * esz);
     if (!planes[c]) return fail_free(SFPIC_E_NOMEM, "field allocation failed");
-    if (hipMemsetAsync(planes[c], 0, S->plane * 8, S->st) != hipSuccess)
+    if (hipMemsetAsync(planes[c], 0, S->plane * esz, S->st) != hipSuccess)
       return fail_free(SFPIC_E_DEVICE, "field clear failed");
   }
   for (int c = 0; c < 3; ++c) {
@@ -1018,9 +1092,9 @@ int sfpic3_create(const sfpic3_grid *grid, const sfpic3_species *species,
     if (sp.n > 0) {
       for (int a = 0; a < 3; ++a) {
         sp.p.x[a] = (double *)S->dalloc((size_t)sp.n * 8);
-        sp.p.u[a] = (double *)S->dalloc((size_t)sp.n * 8);
+        sp.p.u[a] = (double *)S->dalloc((size_t)sp.n * esz);
         sp.alt.x[a] = (double *)S->dalloc((size_t)sp.n * 8);
-        sp.alt.u[a] = (double *)S->dalloc((size_t)sp.n * 8);
+        sp.alt.u[a] = (double *)S->dalloc((size_t)sp.n * esz);
         if (!sp.p.x[a] || !sp.p.u[a] || !sp.alt.x[a] || !sp.alt.u[a])
           return fail_free(SFPIC_E_NOMEM, "particle allocation failed");
       }
@@ -1038,9 +1112,16 @@ int sfpic3_create(const sfpic3_grid *grid, const sfpic3_species *species,
           if (hipMemcpyAsync((char *)tmp + c * b, src[c], b,
                              hipMemcpyHostToDevice, S->st) != hipSuccess)
             return fail_free(SFPIC_E_DEVICE, "particle upload failed");
-        load3<<<blocks_for(sp.n), 256, 0, S->st>>>(
-            sp.p, sp.n, tmp, tmp + sp.n, tmp + 2 * sp.n, tmp + 3 * sp.n,
-            tmp + 4 * sp.n, tmp + 5 * sp.n, 1.0 / g.dx, 1.0 / g.dy, 1.0 / g.dz);
+        if (S->fp32)
+          load3<float><<<blocks_for(sp.n), 256, 0, S->st>>>(
+              parts_as<float>(sp.p), sp.n, tmp, tmp + sp.n, tmp + 2 * sp.n,
+              tmp + 3 * sp.n, tmp + 4 * sp.n, tmp + 5 * sp.n, 1.0 / g.dx,
+              1.0 / g.dy, 1.0 / g.dz);
+        else
+          load3<double><<<blocks_for(sp.n), 256, 0, S->st>>>(
+              sp.p, sp.n, tmp, tmp + sp.n, tmp + 2 * sp.n, tmp + 3 * sp.n,
+              tmp + 4 * sp.n, tmp + 5 * sp.n, 1.0 / g.dx, 1.0 / g.dy,
+              1.0 / g.dz);
         if (hipStreamSynchronize(S->st) != hipSuccess)
           return fail_free(SFPIC_E_DEVICE, "particle upload failed");
         for (size_t k = 0; k < S->allocs.size(); ++k)
@@ -1064,10 +1145,16 @@ int sfpic3_create(const sfpic3_grid *grid, const sfpic3_species *species,
                              hipMemcpyHostToDevice, S->st) != hipSuccess)
             return fail_free(SFPIC_E_DEVICE, "profile table upload failed");
         }
-        init3<<<blocks_for(sp.n), 256, 0, S->st>>>(
-            sp.p, sp.n, r[0], r[2], r[4], r[1] - r[0], r[3] - r[2], d.ppc,
-            sigma, (uint32_t)d.seed, (uint32_t)d.species_index, doff,
-            doff ? off.back() : 0u);
+        if (S->fp32)
+          init3<float><<<blocks_for(sp.n), 256, 0, S->st>>>(
+              parts_as<float>(sp.p), sp.n, r[0], r[2], r[4], r[1] - r[0],
+              r[3] - r[2], d.ppc, sigma, (uint32_t)d.seed,
+              (uint32_t)d.species_index, doff, doff ? off.back() : 0u);
+        else
+          init3<double><<<blocks_for(sp.n), 256, 0, S->st>>>(
+              sp.p, sp.n, r[0], r[2], r[4], r[1] - r[0], r[3] - r[2], d.ppc,
+              sigma, (uint32_t)d.seed, (uint32_t)d.species_index, doff,
+              doff ? off.back() : 0u);
         if (hipGetLastError() != hipSuccess)
           return fail_free(SFPIC_E_DEVICE, "particle generation failed");
       }
@@ -1120,10 +1207,19 @@ int sfpic3_read_field(sfpic3_sim *sim, int comp, double *out, size_t n) {
   const Geo &g = sim->g;
   if (n != (size_t)g.NX * g.NY * g.NZ)
     return sfpic::fail(SFPIC_E_SIZE, "field buffer must hold NX*NY*NZ values");
-  HIP3(hipMemcpy2DAsync(out, (size_t)g.NX * 8, src, (size_t)g.P * 8,
-                        (size_t)g.NX * 8, (size_t)g.NY * g.NZ,
+  if (!sim->fp32) {
+    HIP3(hipMemcpy2DAsync(out, (size_t)g.NX * 8, src, (size_t)g.P * 8,
+                          (size_t)g.NX * 8, (size_t)g.NY * g.NZ,
+                          hipMemcpyDeviceToHost, sim->st));
+    HIP3(hipStreamSynchronize(sim->st));
+    return SFPIC_OK;
+  }
+  std::vector<float> tmp(n);
+  HIP3(hipMemcpy2DAsync(tmp.data(), (size_t)g.NX * 4, src, (size_t)g.P * 4,
+                        (size_t)g.NX * 4, (size_t)g.NY * g.NZ,
                         hipMemcpyDeviceToHost, sim->st));
   HIP3(hipStreamSynchronize(sim->st));
+  for (size_t i = 0; i < n; ++i) out[i] = (double)tmp[i];
   return SFPIC_OK;
 }
 
@@ -1135,8 +1231,16 @@ int sfpic3_write_field(sfpic3_sim *sim, int comp, const double *in, size_t n) {
   const Geo &g = sim->g;
   if (n != (size_t)g.NX * g.NY * g.NZ)
     return sfpic::fail(SFPIC_E_SIZE, "field buffer must hold NX*NY*NZ values");
-  HIP3(hipMemcpy2DAsync(dst, (size_t)g.P * 8, in, (size_t)g.NX * 8,
-                        (size_t)g.NX * 8, (size_t)g.NY * g.NZ,
+  if (!sim->fp32) {
+    HIP3(hipMemcpy2DAsync(dst, (size_t)g.P * 8, in, (size_t)g.NX * 8,
+                          (size_t)g.NX * 8, (size_t)g.NY * g.NZ,
+                          hipMemcpyHostToDevice, sim->st));
+    HIP3(hipStreamSynchronize(sim->st));
+    return SFPIC_OK;
+  }
+  std::vector<float> tmp(in, in + n);  // rounded to the storage type
+  HIP3(hipMemcpy2DAsync(dst, (size_t)g.P * 4, tmp.data(), (size_t)g.NX * 4,
+                        (size_t)g.NX * 4, (size_t)g.NY * g.NZ,
                         hipMemcpyHostToDevice, sim->st));
   HIP3(hipStreamSynchronize(sim->st));
   return SFPIC_OK;
@@ -1165,15 +1269,22 @@ int sfpic3_read_particles(sfpic3_sim *sim, int species, double *x, double *y,
   // its creation index
   double *dst[6] = {x, y, z, ux, uy, uz};
   std::vector<double> stage(6 * n);
+  std::vector<float> ustage(sim->fp32 ? 3 * n : 0);
   std::vector<uint32_t> id(n);
   for (int a = 0; a < 3; ++a) {
     HIP3(hipMemcpyAsync(stage.data() + a * n, sp.p.x[a], n * 8,
                         hipMemcpyDeviceToHost, sim->st));
-    HIP3(hipMemcpyAsync(stage.data() + (3 + a) * n, sp.p.u[a], n * 8,
-                        hipMemcpyDeviceToHost, sim->st));
+    if (sim->fp32)
+      HIP3(hipMemcpyAsync(ustage.data() + a * n, sp.p.u[a], n * 4,
+                          hipMemcpyDeviceToHost, sim->st));
+    else
+      HIP3(hipMemcpyAsync(stage.data() + (3 + a) * n, sp.p.u[a], n * 8,
+                          hipMemcpyDeviceToHost, sim->st));
   }
   HIP3(hipMemcpyAsync(id.data(), sp.id, n * 4, hipMemcpyDeviceToHost, sim->st));
   HIP3(hipStreamSynchronize(sim->st));
+  if (sim->fp32)
+    for (size_t k = 0; k < 3 * n; ++k) stage[3 * n + k] = (double)ustage[k];
   const double h[3] = {sim->grid.dx, sim->grid.dy, sim->grid.dz};
   for (size_t s = 0; s < n; ++s) {
     const size_t i = id[s];
@@ -1200,7 +1311,12 @@ int sfpic3_diagnostics(sfpic3_sim *sim, sfpic_diag *out) {
   for (auto &sp : S->sp) {
     HIP3(hipMemsetAsync(S->acc, 0, 64, S->st));
     if (sp.n > 0) {
-      psums3<<<blocks_for(sp.n), 256, 0, S->st>>>(sp.p, sp.n, S->acc, flag);
+      if (S->fp32)
+        psums3<float><<<blocks_for(sp.n), 256, 0, S->st>>>(
+            parts_as<float>(sp.p), sp.n, S->acc, flag);
+      else
+        psums3<double><<<blocks_for(sp.n), 256, 0, S->st>>>(sp.p, sp.n,
+                                                            S->acc, flag);
       HIP3(hipGetLastError());
     }
     HIP3(hipMemcpyAsync(host.data(), S->acc, 64, hipMemcpyDeviceToHost, S->st));
@@ -1213,13 +1329,22 @@ int sfpic3_diagnostics(sfpic3_sim *sim, sfpic_diag *out) {
     out->nonfinite |= fl;
   }
   HIP3(hipMemsetAsync(S->acc, 0, 64, S->st));
-  fsums3<<<blocks_for((int64_t)S->plane), 256, 0, S->st>>>(S->f, S->plane,
-                                                           S->acc, flag);
+  if (S->fp32)
+    fsums3<float><<<blocks_for((int64_t)S->plane), 256, 0, S->st>>>(
+        fields_as<float>(S->f), S->plane, S->acc, flag);
+  else
+    fsums3<double><<<blocks_for((int64_t)S->plane), 256, 0, S->st>>>(
+        S->f, S->plane, S->acc, flag);
   HIP3(hipGetLastError());
   if (int r = deposit_rho(S, S->rho)) return r;
   unsigned long long *mx = (unsigned long long *)(S->acc + 2);
-  gauss3<<<node_grid(S->g), dim3(64, 4), 0, S->st>>>(
-      S->f, S->g, S->rho, S->rho0, 1.0 / g.dx, 1.0 / g.dy, 1.0 / g.dz, mx);
+  if (S->fp32)
+    gauss3<float><<<node_grid(S->g), dim3(64, 4), 0, S->st>>>(
+        fields_as<float>(S->f), S->g, S->rho, S->rho0, 1.0 / g.dx,
+        1.0 / g.dy, 1.0 / g.dz, mx);
+  else
+    gauss3<double><<<node_grid(S->g), dim3(64, 4), 0, S->st>>>(
+        S->f, S->g, S->rho, S->rho0, 1.0 / g.dx, 1.0 / g.dy, 1.0 / g.dz, mx);
   HIP3(hipGetLastError());
   HIP3(hipMemcpyAsync(host.data(), S->acc, 64, hipMemcpyDeviceToHost, S->st));
   HIP3(hipStreamSynchronize(S->st));

@@ -52,14 +52,20 @@ def test_invalid_3d_input_rejected_without_gpu(L):
     from paper_2310_11393_amd import binding as b
     h = C.c_void_p()
     g = b.sfpic3_grid(16, 16, 16, 0.2, 0.2, 0.2, 0.2)  # CFL violated
-    assert L.sfpic3_create(C.byref(g), None, 0, None, None, C.byref(h)) == -1
+    assert L.sfpic3_create(C.byref(g), None, 0, None, 0, None,
+                           C.byref(h)) == -1
     assert b"CFL" in L.sfpic_last_error() and not h.value
     g = b.sfpic3_grid(16, 0, 16, 0.2, 0.2, 0.2, 0.05)
-    assert L.sfpic3_create(C.byref(g), None, 0, None, None, C.byref(h)) == -1
+    assert L.sfpic3_create(C.byref(g), None, 0, None, 0, None,
+                           C.byref(h)) == -1
+    g = b.sfpic3_grid(16, 16, 16, 0.2, 0.2, 0.2, 0.05)
+    assert L.sfpic3_create(C.byref(g), None, 0, None, 7, None,
+                           C.byref(h)) == -1
+    assert b"precision" in L.sfpic_last_error()
     g = b.sfpic3_grid(16, 16, 16, 0.2, 0.2, 0.2, 0.05)
     inc = b.sfpic_incident()
     inc.kind, inc.a0, inc.w0, inc.fwhm_t = 4, 1.0, 2.0, 5.0  # 2D-only beam
-    assert L.sfpic3_create(C.byref(g), None, 0, C.byref(inc), None,
+    assert L.sfpic3_create(C.byref(g), None, 0, C.byref(inc), 0, None,
                            C.byref(h)) == -1
     assert b"2D" in L.sfpic_last_error()
     x = (C.c_double * 1)(3.3)  # outside [0, 16 * 0.2)
@@ -68,7 +74,7 @@ def test_invalid_3d_input_rejected_without_gpu(L):
     sp.q, sp.m, sp.n_explicit, sp.weight = -1.0, 1.0, 1, 0.1
     sp.x, sp.y, sp.z = x, zero, zero
     sp.ux, sp.uy, sp.uz = zero, zero, zero
-    assert L.sfpic3_create(C.byref(g), C.byref(sp), 1, None, None,
+    assert L.sfpic3_create(C.byref(g), C.byref(sp), 1, None, 0, None,
                            C.byref(h)) == -1
     assert b"outside" in L.sfpic_last_error()
     assert L.sfpic3_step(None, 1) == -1
