@@ -552,6 +552,11 @@ int sfpic3_read_particles(sfpic3_sim *sim, int species, double *x, double *y,
  * node; gauss_residual and rho_max over nodes at least 4 cells inside the
  * box); w_em_total is not evaluated in 3D (NaN). */
 int sfpic3_diagnostics(sfpic3_sim *sim, sfpic_diag *out);
+/* Energy-angle histogram of a species, as sfpic_histogram (weights w dV,
+ * dV = dx dy dz; angle from +x, the propagation axis; the spectra of
+ * Sec. 4.2). */
+int sfpic3_histogram(sfpic3_sim *sim, const sfpic_hist_spec *spec,
+                     double *out, size_t n, double *moments);
 void sfpic3_destroy(sfpic3_sim *sim);
 
 /* Message of the last failing call on this thread ("" if none). */

@@ -109,6 +109,9 @@ def lib():
         L.orc3_step.argtypes = [C.c_void_p, C.c_long]
         L.orc3_deposit_rho.argtypes = [C.c_void_p, _D]
         L.orc3_diagnostics.argtypes = [C.c_void_p, _D]
+        L.orc3_energy_angle.argtypes = [C.c_void_p, C.c_int, C.c_int,
+                                        C.c_double, C.c_int, C.c_double, _D,
+                                        _D]
         _lib = L
     return _lib
 
@@ -350,3 +353,11 @@ class OracleSim3:
         lib().orc3_diagnostics(self._h, _dp(o))
         return {"w_kin": o[0], "w_em": o[1], "charge": o[2],
                 "n_alive": int(o[3])}
+
+    def energy_angle(self, sp=0, n_e=256, emax=1.0, n_theta=180,
+                     ek_min=1.0e3 / 510998.95):
+        h = np.zeros((n_e, n_theta))
+        mom = np.zeros(5)
+        lib().orc3_energy_angle(self._h, sp, n_e, emax, n_theta, ek_min,
+                                _dp(h), _dp(mom))
+        return h, mom

@@ -426,3 +426,35 @@ void orc3_diagnostics(const orc3_sim *S, double out[4]) {
   out[2] = q;
   out[3] = na;
 }
+
+/* Energy-angle histogram of species sp (weights w dV), energy bins over
+ * [0, emax) linear, angle from +x over [0, 180] degrees; mom = {sum w, <Ek>,
+ * <Ek^2>, <theta>, <theta^2>} over particles with Ek > ek_min. */
+void orc3_energy_angle(const orc3_sim *S, int sp, int n_e, double emax,
+                       int n_theta, double ek_min, double *hist,
+                       double mom[5]) {
+  const orc3_species *p = &S->sp[sp];
+  const double dV = S->g.dx * S->g.dy * S->g.dz;
+  memset(hist, 0, (size_t)n_e * (size_t)n_theta * 8);
+  for (int k = 0; k < 5; ++k) mom[k] = 0.0;
+  for (long i = 0; i < p->n; ++i) {
+    if (!p->alive[i]) continue;
+    double ux = p->u[0][i], uy = p->u[1][i], uz = p->u[2][i];
+    double ek = p->m * (sqrt(1.0 + ux * ux + uy * uy + uz * uz) - 1.0);
+    double th = atan2(sqrt(uy * uy + uz * uz), ux) * (180.0 / 3.14159265358979323846);
+    double wt = p->w * dV;
+    long ie = (long)floor(ek / emax * n_e);
+    long it = (long)floor(th / 180.0 * n_theta);
+    if (it >= n_theta) it = n_theta - 1;
+    if (ie >= 0 && ie < n_e && it >= 0) hist[ie * n_theta + it] += wt;
+    if (ek > ek_min) {
+      mom[0] += wt;
+      mom[1] += wt * ek;
+      mom[2] += wt * ek * ek;
+      mom[3] += wt * th;
+      mom[4] += wt * th * th;
+    }
+  }
+  if (mom[0] > 0.0)
+    for (int k = 1; k < 5; ++k) mom[k] /= mom[0];
+}

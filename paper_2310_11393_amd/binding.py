@@ -177,7 +177,7 @@ EXPORTS = ["sfpic_create", "sfpic_step", "sfpic_sync", "sfpic_read_field",
            "sfpic3_create", "sfpic3_step", "sfpic3_sync", "sfpic3_dims",
            "sfpic3_read_field", "sfpic3_write_field",
            "sfpic3_particle_count", "sfpic3_read_particles",
-           "sfpic3_diagnostics", "sfpic3_destroy"]
+           "sfpic3_diagnostics", "sfpic3_histogram", "sfpic3_destroy"]
 
 KCLASSES = ("faraday", "push", "ampere", "sort", "stragglers")
 
@@ -238,6 +238,8 @@ def lib():
     L.sfpic3_read_particles.argtypes = [vp, C.c_int] + [_DP] * 6 + \
         [C.POINTER(C.c_uint8), sz]
     L.sfpic3_diagnostics.argtypes = [vp, C.POINTER(sfpic_diag)]
+    L.sfpic3_histogram.argtypes = [vp, C.POINTER(sfpic_hist_spec), _DP, sz,
+                                   _DP]
     L.sfpic3_destroy.argtypes = [vp]
     L.sfpic3_destroy.restype = None
     L.sfpic_april_field.argtypes = [C.POINTER(sfpic_incident), C.c_double,
@@ -811,3 +813,13 @@ class Simulation3:
         d = sfpic_diag()
         _check(lib().sfpic3_diagnostics(self.h, C.byref(d)))
         return {f: getattr(d, f) for f, _ in sfpic_diag._fields_}
+
+    def histogram(self, sp=0, n_e=256, emax=1.0, n_theta=180,
+                  ek_min=1.0e3 / 510998.95):
+        """(n_e, n_theta) energy-angle histogram and its moments."""
+        spec = sfpic_hist_spec(sp, n_e, emax, n_theta, ek_min)
+        out = np.empty((n_e, n_theta))
+        mom = np.empty(5)
+        _check(lib().sfpic3_histogram(self.h, C.byref(spec), _dp(out),
+                                      out.size, _dp(mom)))
+        return out, mom

@@ -739,6 +739,33 @@ gauss3(F3<R> f, Geo g, const double *rho, const double *rho0, double ihx,
   atomicMax(mx + 1, (unsigned long long)__double_as_longlong(fabs(dr)));
 }
 
+// Energy-angle histogram of live particles (weights w dV): linear kinetic
+// energy bins over [0, emax), angle from +x in [0, 180] degrees; moments
+// {sum w, w E_k, w E_k^2, w theta, w theta^2} over E_k > ek_min.
+template <typename R>
+__global__ void __launch_bounds__(256)
+hist3(Parts3<R> p, int64_t n, double m, double wdv, int n_e, double emax,
+      int n_t, double ek_min, double *hist, double *mom) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n || p.x[0][s] < -1.0) return;
+  const double ux = ld(p.u[0], s), uy = ld(p.u[1], s), uz = ld(p.u[2], s);
+  const double ek = m * (sqrt(1.0 + ux * ux + uy * uy + uz * uz) - 1.0);
+  const double th =
+      atan2(sqrt(uy * uy + uz * uz), ux) * (180.0 / 3.14159265358979323846);
+  if (!isfinite(ek) || !isfinite(th)) return;
+  const double ie = floor(ek / emax * n_e);
+  const double tt = fmin(floor(th / 180.0 * n_t), (double)(n_t - 1));
+  if (ie >= 0.0 && ie < (double)n_e && tt >= 0.0)
+    atomicAdd(&hist[(size_t)ie * n_t + (size_t)tt], wdv);
+  if (ek > ek_min) {
+    atomicAdd(&mom[0], wdv);
+    atomicAdd(&mom[1], wdv * ek);
+    atomicAdd(&mom[2], wdv * ek * ek);
+    atomicAdd(&mom[3], wdv * th);
+    atomicAdd(&mom[4], wdv * th * th);
+  }
+}
+
 }  // namespace sfpic3
 
 // ---------------------------------------------------------------------------
@@ -790,6 +817,17 @@ struct sfpic3_sim {
       p = nullptr;
     if (p) allocs.emplace_back(p, bytes);
     return p;
+  }
+  void dfree(void *p) {
+    for (size_t k = 0; k < allocs.size(); ++k)
+      if (allocs[k].first == p) {
+        if (rt.free)
+          rt.free(p, allocs[k].second, rt.alloc_ctx);
+        else
+          (void)hipFree(p);
+        allocs.erase(allocs.begin() + (long)k);
+        return;
+      }
   }
   void release() {
     for (auto &a : allocs) {
@@ -1124,15 +1162,7 @@ int sfpic3_create(const sfpic3_grid *grid, const sfpic3_species *species,
               1.0 / g.dz);
         if (hipStreamSynchronize(S->st) != hipSuccess)
           return fail_free(SFPIC_E_DEVICE, "particle upload failed");
-        for (size_t k = 0; k < S->allocs.size(); ++k)
-          if (S->allocs[k].first == tmp) {
-            if (S->rt.free)
-              S->rt.free(tmp, S->allocs[k].second, S->rt.alloc_ctx);
-            else
-              (void)hipFree(tmp);
-            S->allocs.erase(S->allocs.begin() + (long)k);
-            break;
-          }
+        S->dfree(tmp);
       } else {
         const int64_t *r = d.region;
         const double sigma =
@@ -1361,6 +1391,48 @@ int sfpic3_diagnostics(sfpic3_sim *sim, sfpic_diag *out) {
   memcpy(&fl, &host[7], sizeof(int));
   out->nonfinite |= fl;
   out->w_em_total = NAN;  // not evaluated in 3D
+  return SFPIC_OK;
+}
+
+int sfpic3_histogram(sfpic3_sim *sim, const sfpic_hist_spec *spec,
+                     double *out, size_t n, double *moments) {
+  if (!sim || !spec || !out) return sfpic::fail(SFPIC_E_INVAL, "NULL argument");
+  if (spec->species < 0 || spec->species >= (int)sim->sp.size() ||
+      spec->n_energy <= 0 || spec->n_theta <= 0 || !(spec->e_max > 0.0))
+    return sfpic::fail(SFPIC_E_INVAL, "bad histogram spec");
+  const size_t nb = (size_t)spec->n_energy * spec->n_theta;
+  if (n != nb) return sfpic::fail(SFPIC_E_SIZE, "n must be n_energy * n_theta");
+  double *d = (double *)sim->dalloc((nb + 8) * 8);
+  if (!d) return sfpic::fail(SFPIC_E_NOMEM, "histogram allocation failed");
+  const Species3 &sp = sim->sp[spec->species];
+  const double wdv = sp.w * sim->grid.dx * sim->grid.dy * sim->grid.dz;
+  double mom[8] = {0};
+  int rc = SFPIC_OK;
+  if (hipMemsetAsync(d, 0, (nb + 8) * 8, sim->st) != hipSuccess) rc = -1;
+  if (!rc && sp.n > 0) {
+    if (sim->fp32)
+      hist3<float><<<blocks_for(sp.n), 256, 0, sim->st>>>(
+          parts_as<float>(sp.p), sp.n, sp.m, wdv, spec->n_energy,
+          spec->e_max, spec->n_theta, spec->ek_min, d + 8, d);
+    else
+      hist3<double><<<blocks_for(sp.n), 256, 0, sim->st>>>(
+          sp.p, sp.n, sp.m, wdv, spec->n_energy, spec->e_max, spec->n_theta,
+          spec->ek_min, d + 8, d);
+    if (hipGetLastError() != hipSuccess) rc = -1;
+  }
+  if (!rc && (hipMemcpyAsync(out, d + 8, nb * 8, hipMemcpyDeviceToHost,
+                             sim->st) != hipSuccess ||
+              hipMemcpyAsync(mom, d, 8 * 8, hipMemcpyDeviceToHost, sim->st) !=
+                  hipSuccess ||
+              hipStreamSynchronize(sim->st) != hipSuccess))
+    rc = -1;
+  (void)hipStreamSynchronize(sim->st);
+  sim->dfree(d);
+  if (rc) return sfpic::fail(SFPIC_E_DEVICE, "histogram failed");
+  if (moments) {
+    moments[0] = mom[0];
+    for (int k = 1; k < 5; ++k) moments[k] = mom[0] > 0.0 ? mom[k] / mom[0] : 0.0;
+  }
   return SFPIC_OK;
 }
 

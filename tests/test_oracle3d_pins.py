@@ -229,3 +229,30 @@ def test_free_particle_streams_and_leaves():
     assert sim.particles()[6][0]
     sim.step(1)
     assert not sim.particles()[6][0]
+
+
+def test_energy_angle_histogram_of_known_particles():
+    """Particles of known momentum land in the bins their kinetic energy
+    m (gamma - 1) and angle from +x put them in, weighted by w dV."""
+    g = grid3(8, 8, 8)
+    u = np.array([[1.0, 0.0, 0.0],    # E_k = sqrt(2) - 1, theta = 0
+                  [0.0, 0.5, 0.0],    # theta = 90
+                  [-2.0, 0.0, 0.0],   # theta = 180 (last bin)
+                  [0.3, 0.0, 0.4]])   # theta = atan2(0.4, 0.3)
+    x = np.full(4, 4.2 * g.dx)
+    sim = O.OracleSim3(g, NOINC)
+    w = 0.25
+    sim.add_species(-1.0, 1.0, w, x, x * g.dy / g.dx, x * g.dz / g.dx,
+                    *u.T)
+    n_e, emax, n_t = 40, 2.0, 36
+    h, mom = sim.energy_angle(n_e=n_e, emax=emax, n_theta=n_t, ek_min=0.0)
+    dV = g.dx * g.dy * g.dz
+    ek = np.sqrt(1.0 + (u ** 2).sum(1)) - 1.0
+    th = np.degrees(np.arctan2(np.hypot(u[:, 1], u[:, 2]), u[:, 0]))
+    want = np.zeros((n_e, n_t))
+    for e, t in zip(ek, th):
+        want[int(e / emax * n_e), min(int(t / 180 * n_t), n_t - 1)] += w * dV
+    assert np.array_equal(h, want)
+    assert math.isclose(mom[0], 4 * w * dV, rel_tol=1e-15)
+    assert math.isclose(mom[1], ek.mean(), rel_tol=1e-14)
+    assert math.isclose(mom[3], th.mean(), rel_tol=1e-14)
