@@ -557,6 +557,13 @@ int sfpic3_diagnostics(sfpic3_sim *sim, sfpic_diag *out);
  * Sec. 4.2). */
 int sfpic3_histogram(sfpic3_sim *sim, const sfpic_hist_spec *spec,
                      double *out, size_t n, double *moments);
+/* Checkpoint / resume: with buf == NULL *n receives the state size;
+ * otherwise the state (step, E, B, every particle slot with its id) is
+ * written into the caller's buffer of *n bytes.  sfpic3_set_state restores
+ * a state taken from a simulation created with the same grid, precision and
+ * species sizes (SFPIC_E_STATE otherwise). */
+int sfpic3_get_state(sfpic3_sim *sim, void *buf, size_t *n);
+int sfpic3_set_state(sfpic3_sim *sim, const void *buf, size_t n);
 void sfpic3_destroy(sfpic3_sim *sim);
 
 /* Message of the last failing call on this thread ("" if none). */

@@ -177,7 +177,8 @@ EXPORTS = ["sfpic_create", "sfpic_step", "sfpic_sync", "sfpic_read_field",
            "sfpic3_create", "sfpic3_step", "sfpic3_sync", "sfpic3_dims",
            "sfpic3_read_field", "sfpic3_write_field",
            "sfpic3_particle_count", "sfpic3_read_particles",
-           "sfpic3_diagnostics", "sfpic3_histogram", "sfpic3_destroy"]
+           "sfpic3_diagnostics", "sfpic3_histogram", "sfpic3_get_state",
+           "sfpic3_set_state", "sfpic3_destroy"]
 
 KCLASSES = ("faraday", "push", "ampere", "sort", "stragglers")
 
@@ -240,6 +241,8 @@ def lib():
     L.sfpic3_diagnostics.argtypes = [vp, C.POINTER(sfpic_diag)]
     L.sfpic3_histogram.argtypes = [vp, C.POINTER(sfpic_hist_spec), _DP, sz,
                                    _DP]
+    L.sfpic3_get_state.argtypes = [vp, vp, C.POINTER(sz)]
+    L.sfpic3_set_state.argtypes = [vp, vp, sz]
     L.sfpic3_destroy.argtypes = [vp]
     L.sfpic3_destroy.restype = None
     L.sfpic_april_field.argtypes = [C.POINTER(sfpic_incident), C.c_double,
@@ -823,3 +826,15 @@ class Simulation3:
         _check(lib().sfpic3_histogram(self.h, C.byref(spec), _dp(out),
                                       out.size, _dp(mom)))
         return out, mom
+
+    def get_state(self) -> bytes:
+        """Checkpoint of the simulation (step, E, B, particles)."""
+        n = C.c_size_t()
+        _check(lib().sfpic3_get_state(self.h, None, C.byref(n)))
+        buf = C.create_string_buffer(n.value)
+        _check(lib().sfpic3_get_state(self.h, buf, C.byref(n)))
+        return buf.raw
+
+    def set_state(self, state: bytes):
+        buf = C.create_string_buffer(state, len(state))
+        _check(lib().sfpic3_set_state(self.h, buf, len(state)))

@@ -1436,6 +1436,110 @@ int sfpic3_histogram(sfpic3_sim *sim, const sfpic_hist_spec *spec,
   return SFPIC_OK;
 }
 
+// Checkpoint layout: header {magic, nx, ny, nz, storage bytes, nspecies,
+// step, 0} as int64, then E and B (6 arrays [NZ][NY][NX] of the storage
+// type), then per species its slot count and, in device order, x y z
+// (double), ux uy uz (storage type) and the creation ids.  J and the centred
+// B are recomputed by every step and are not saved.
+static constexpr int64_t kState3Magic = 0x3353465049433344ll;
+
+static size_t state3_bytes(const sfpic3_sim *S) {
+  const size_t es = S->fp32 ? 4 : 8;
+  size_t b = 8 * 8 + 6 * (size_t)S->g.NX * S->g.NY * S->g.NZ * es;
+  for (const auto &sp : S->sp) b += 8 + (size_t)sp.n * (3 * 8 + 3 * es + 4);
+  return b;
+}
+
+int sfpic3_get_state(sfpic3_sim *sim, void *buf, size_t *n) {
+  if (!sim || !n) return sfpic::fail(SFPIC_E_INVAL, "NULL argument");
+  const size_t need = state3_bytes(sim);
+  if (!buf) {
+    *n = need;
+    return SFPIC_OK;
+  }
+  if (*n != need) return sfpic::fail(SFPIC_E_SIZE, "state buffer size mismatch");
+  const Geo &g = sim->g;
+  const size_t es = sim->fp32 ? 4 : 8;
+  char *w = (char *)buf;
+  const int64_t hdr[8] = {kState3Magic, g.nx, g.ny, g.nz, (int64_t)es,
+                          (int64_t)sim->sp.size(), sim->step, 0};
+  memcpy(w, hdr, sizeof(hdr));
+  w += sizeof(hdr);
+  for (int c = 0; c < 6; ++c) {
+    const double *src = c < 3 ? sim->f.e[c] : sim->f.b[c - 3];
+    HIP3(hipMemcpy2DAsync(w, (size_t)g.NX * es, src, (size_t)g.P * es,
+                          (size_t)g.NX * es, (size_t)g.NY * g.NZ,
+                          hipMemcpyDeviceToHost, sim->st));
+    w += (size_t)g.NX * g.NY * g.NZ * es;
+  }
+  for (const auto &sp : sim->sp) {
+    const int64_t cnt = sp.n;
+    memcpy(w, &cnt, 8);
+    w += 8;
+    for (int a = 0; a < 3; ++a) {
+      HIP3(hipMemcpyAsync(w, sp.p.x[a], (size_t)sp.n * 8,
+                          hipMemcpyDeviceToHost, sim->st));
+      w += (size_t)sp.n * 8;
+    }
+    for (int a = 0; a < 3; ++a) {
+      HIP3(hipMemcpyAsync(w, sp.p.u[a], (size_t)sp.n * es,
+                          hipMemcpyDeviceToHost, sim->st));
+      w += (size_t)sp.n * es;
+    }
+    HIP3(hipMemcpyAsync(w, sp.id, (size_t)sp.n * 4, hipMemcpyDeviceToHost,
+                        sim->st));
+    w += (size_t)sp.n * 4;
+  }
+  HIP3(hipStreamSynchronize(sim->st));
+  return SFPIC_OK;
+}
+
+int sfpic3_set_state(sfpic3_sim *sim, const void *buf, size_t n) {
+  if (!sim || !buf) return sfpic::fail(SFPIC_E_INVAL, "NULL argument");
+  if (n != state3_bytes(sim))
+    return sfpic::fail(SFPIC_E_SIZE, "state does not fit this simulation");
+  const Geo &g = sim->g;
+  const size_t es = sim->fp32 ? 4 : 8;
+  const char *r = (const char *)buf;
+  int64_t hdr[8];
+  memcpy(hdr, r, sizeof(hdr));
+  r += sizeof(hdr);
+  if (hdr[0] != kState3Magic || hdr[1] != g.nx || hdr[2] != g.ny ||
+      hdr[3] != g.nz || hdr[4] != (int64_t)es ||
+      hdr[5] != (int64_t)sim->sp.size() || hdr[6] < 0)
+    return sfpic::fail(SFPIC_E_STATE, "state is from another configuration");
+  for (int c = 0; c < 6; ++c) {
+    double *dst = c < 3 ? sim->f.e[c] : sim->f.b[c - 3];
+    HIP3(hipMemcpy2DAsync(dst, (size_t)g.P * es, r, (size_t)g.NX * es,
+                          (size_t)g.NX * es, (size_t)g.NY * g.NZ,
+                          hipMemcpyHostToDevice, sim->st));
+    r += (size_t)g.NX * g.NY * g.NZ * es;
+  }
+  for (auto &sp : sim->sp) {
+    int64_t cnt = 0;
+    memcpy(&cnt, r, 8);
+    r += 8;
+    if (cnt != sp.n)
+      return sfpic::fail(SFPIC_E_STATE, "state species sizes differ");
+    for (int a = 0; a < 3; ++a) {
+      HIP3(hipMemcpyAsync(sp.p.x[a], r, (size_t)sp.n * 8,
+                          hipMemcpyHostToDevice, sim->st));
+      r += (size_t)sp.n * 8;
+    }
+    for (int a = 0; a < 3; ++a) {
+      HIP3(hipMemcpyAsync(sp.p.u[a], r, (size_t)sp.n * es,
+                          hipMemcpyHostToDevice, sim->st));
+      r += (size_t)sp.n * es;
+    }
+    HIP3(hipMemcpyAsync(sp.id, r, (size_t)sp.n * 4, hipMemcpyHostToDevice,
+                        sim->st));
+    r += (size_t)sp.n * 4;
+  }
+  HIP3(hipStreamSynchronize(sim->st));
+  sim->step = hdr[6];
+  return SFPIC_OK;
+}
+
 void sfpic3_destroy(sfpic3_sim *sim) {
   if (!sim) return;
   (void)hipStreamSynchronize(sim->st);

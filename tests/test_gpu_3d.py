@@ -312,3 +312,34 @@ def test_3d_histogram_parity(prec):
     assert big.sum() >= 3
     assert np.all(np.abs(hg[big] - ho[big]) <= 0.01 * ho[big])
     assert np.allclose(mg, mo, rtol=1e-9 if prec == 0 else 1e-4, atol=0)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_3d_checkpoint_resume(prec):
+    """A run resumed from a checkpoint in a fresh simulation ends where the
+    uninterrupted run ends (to rounding: the current is summed with
+    atomics in no fixed order), and states from another configuration are
+    refused."""
+    from paper_2310_11393_amd.binding import SfpicError, Simulation3
+    g, inc, sp, steps = _case("lp3d")
+    a = Simulation3(g, inc, explicit=sp, precision=prec)
+    a.step(15)
+    st = a.get_state()
+    a.step(15)
+    b = Simulation3(g, inc, explicit=sp, precision=prec)
+    b.set_state(st)
+    b.step(15)
+    assert a.diagnostics()["step"] == b.diagnostics()["step"] == 30
+    num = den = 0.0
+    for c in FIELDS:
+        x, y = a.field(c), b.field(c)
+        num += float(np.sum((x - y) ** 2))
+        den += float(np.sum(y ** 2))
+    tol = 1e-12 if prec == 0 else 1e-5
+    assert den > 0 and (num / den) ** 0.5 <= tol
+    pa, pb = a.particles(0), b.particles(0)
+    assert np.array_equal(pa[6], pb[6])
+    assert np.max(np.abs(pa[0] - pb[0])) <= tol * g.nx * g.dx
+    other = Simulation3(wl.grid3(20, 16, 12), inc, explicit=[], precision=prec)
+    with pytest.raises(SfpicError):
+        other.set_state(st)
