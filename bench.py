@@ -499,12 +499,20 @@ def main():
     if not args.no_fp32_compare:
         out["fp32_vs_fp64"] = fp32_vs_fp64(args.compare_steps)
     if not args.no_3d:
-        out["three_d"] = three_d(args.steps_3d)
-        out["three_d_fp32"] = three_d(args.steps_3d, precision=1)
+        legs = [("three_d", dict(steps=args.steps_3d)),
+                ("three_d_fp32", dict(steps=args.steps_3d, precision=1))]
         if not args.no_3d_paper:
-            out["three_d_paper_resolution"] = three_d(
-                max(2, args.steps_3d // 4), cells_per_lambda=32, ppc=8,
-                precision=1)
+            legs.append(("three_d_paper_resolution",
+                         dict(steps=max(2, args.steps_3d // 4),
+                              cells_per_lambda=32, ppc=8, precision=1)))
+        from paper_2310_11393_amd.binding import SfpicError
+        for name, kw in legs:
+            try:
+                out[name] = three_d(**kw)
+            except SfpicError as e:  # e.g. device memory taken by others
+                log(f"{name}: {e}")
+                out[name] = {"error": str(e)}
+                torch.cuda.empty_cache()
     if not args.no_batch:
         out["batched_sweep"] = batched_sweep(args.batch_members,
                                              args.batch_steps)
