@@ -242,6 +242,20 @@ int sfpic_read_field(sfpic_sim *sim, int comp, double *out, size_t n);
  * sfpic_read_field (for example to seed a run from an external state). */
 int sfpic_write_field(sfpic_sim *sim, int comp, const double *in, size_t n);
 
+/* Copy the total field F_scatt + F_inc (Sec. 2: the physical field, the
+ * scattered field stored on the grid plus the incident field in closed
+ * form) of one component (SFPIC_EX .. SFPIC_BZ) to out, laid out as for
+ * sfpic_read_field, guards included.  Each element is taken at the node
+ * where the Yee grid stores that component, E at t^n = n dt and B at
+ * t^{n-1/2}, with the incident field evaluated on the device in FP64; for
+ * on_nodes incidents this is the closed form, not its sampled copy.  A sim
+ * without an incident field returns its stored field.  This is the field
+ * the Sec. 3.1 norms compare between resolutions and between models; read
+ * at step 0 it is the incident field on the grid, the initial condition of
+ * a run that carries the whole pulse on the grid.  Returns SFPIC_E_INVAL
+ * for J or a NULL out, SFPIC_E_SIZE unless n = NX NY. */
+int sfpic_read_total_field(sfpic_sim *sim, int comp, double *out, size_t n);
+
 /* Set the step counter n (the next step starts at t^n = n dt). */
 int sfpic_set_step_index(sfpic_sim *sim, int64_t step);
 

@@ -162,7 +162,8 @@ _lib = None
 
 # every symbol declared in include/sfpic.h
 EXPORTS = ["sfpic_create", "sfpic_step", "sfpic_sync", "sfpic_read_field",
-           "sfpic_write_field", "sfpic_set_step_index",
+           "sfpic_write_field", "sfpic_read_total_field",
+           "sfpic_set_step_index",
            "sfpic_particle_count", "sfpic_read_particles",
            "sfpic_diagnostics", "sfpic_histogram", "sfpic_get_state",
            "sfpic_set_state", "sfpic_profile", "sfpic_profile_read",
@@ -211,6 +212,7 @@ def lib():
     L.sfpic_sync.argtypes = [vp]
     L.sfpic_read_field.argtypes = [vp, C.c_int, _DP, sz]
     L.sfpic_write_field.argtypes = [vp, C.c_int, _DP, sz]
+    L.sfpic_read_total_field.argtypes = [vp, C.c_int, _DP, sz]
     L.sfpic_set_step_index.argtypes = [vp, i64]
     L.sfpic_particle_count.argtypes = [vp, C.c_int, C.POINTER(i64)]
     L.sfpic_read_particles.argtypes = [vp, C.c_int, _DP, _DP, _DP, _DP, _DP,
@@ -534,6 +536,14 @@ class Simulation:
         a = np.ascontiguousarray(arr, dtype=np.float64).reshape(self.NY,
                                                                 self.NX)
         _check(lib().sfpic_write_field(self.h, c, _dp(a), a.size))
+
+    def read_total_field(self, comp) -> np.ndarray:
+        """Scattered plus incident field of one E or B component at its Yee
+        nodes (E at t^n, B at t^{n-1/2}), shape (NY, NX) with guards."""
+        c = COMP[comp] if isinstance(comp, str) else int(comp)
+        out = np.empty((self.NY, self.NX))
+        _check(lib().sfpic_read_total_field(self.h, c, _dp(out), out.size))
+        return out
 
     def set_step_index(self, n):
         _check(lib().sfpic_set_step_index(self.h, int(n)))

@@ -8,9 +8,20 @@ the finest one, taken as exact:
 over the grid points the two resolutions share, and the numerical rate
 p = log2( ||dE||_{2,h} / ||dE||_{2,h/2} ).
 
+The paper also compares two ways of carrying the pulse: (i) the whole
+field on the grid, the pulse launched by the solver, and (ii) the
+scattered-field form, through a cross-norm between the two models' finest
+solutions (same discrete norm) and through time averages of the energy
+differences, (1/N) sum_n |W_h(t_n) - W_fine(t_n)| within a model and
+(1/N) sum_n |W^(i)(t_n) - W^(ii)(t_n)| between them at the finest grid.
+Model (i) here starts from the incident pulse sampled on the Yee nodes as
+the initial condition (E at t = 0, B at -dt/2) of a run with no incident
+field, in place of a laser launched from the boundary, so both models see
+the same pulse and differ only in how it propagates to the plasma.
+
 In the scattered-field form the incident field is the same closed form on
-every grid, so differences of the total field equal differences of the
-scattered field that the library stores; this module compares those.  The
+every grid, so differences of the total field at common primal nodes equal
+differences of the scattered field; the studies record both.  The
 refinement driver runs the 1D set-up of Sec. 3.1 (plane pulse, order-12
 super-Gaussian plasma) through the library, from a quiet start (particles
 evenly spaced in each cell) so that particle noise does not mask the grid
@@ -60,6 +71,41 @@ def rate(e_h: float, e_h2: float) -> float:
     return math.log2(e_h / e_h2)
 
 
+def cross_norm(row_a: np.ndarray, row_b: np.ndarray, n: int, h: float,
+               dual: bool = False) -> float:
+    """Cross-norm of Sec. 3.1: (h sum_k |a(x_k) - b(x_k)|^2)^(1/2) between
+    two solutions on the same grid (n cells, guards included in the rows)
+    over its physical primal (n + 1) or dual (n) nodes."""
+    m = n if dual else n + 1
+    d = row_a[GUARD:GUARD + m] - row_b[GUARD:GUARD + m]
+    return math.sqrt(h * float(np.sum(d * d)))
+
+
+def energy_norm(series_a: Sequence[float], series_b: Sequence[float],
+                scale: float = 1.0) -> float:
+    """Time-averaged energy difference of Sec. 3.1,
+    (1/N) sum_{n=1..N} |W_a(t_n) - W_b(t_n)|, divided by scale (the paper
+    quotes it relative to the peak total energy)."""
+    a = np.asarray(series_a, dtype=np.float64)
+    b = np.asarray(series_b, dtype=np.float64)
+    if a.shape != b.shape or a.size == 0:
+        raise ValueError("energy series must be non-empty and of one length")
+    return float(np.mean(np.abs(a - b))) / scale
+
+
+FIELDS = ("ex", "ey", "ez", "bx", "by", "bz")
+
+
+def full_field_start(sim_ff, sim_sff) -> None:
+    """Initial condition of model (i): the total field of sim_sff (a
+    scattered-field run of the same grid at step 0, whose scattered field
+    is zero, so this is the incident pulse on the Yee nodes: E at t = 0,
+    B at t = -dt/2) written into the E and B of sim_ff, a run without an
+    incident field."""
+    for c in FIELDS:
+        sim_ff.write_field(c, sim_sff.read_total_field(c))
+
+
 def quiet_profile_1d(grid, density: float, ppc: int, center: float,
                      fwhm: float, order: float, xmin: float) -> dict:
     """Explicit cold electrons of the Sec. 3.1 profile: cell c holds
@@ -84,13 +130,22 @@ def refinement_study_1d(ms: Sequence[int], length: float, a0: float,
                         fwhm_t: float, t0: float, density: float, ppc: int,
                         center: float, fwhm: float, order: float,
                         xmin: float, t_snap: Sequence[float],
-                        cfl: float = 0.99) -> Dict[int, Dict[float, dict]]:
-    """Run the 1D scattered-field set-up of Sec. 3.1 at cell sizes
-    2 pi / (16 2^m) for m in ms through the library (FP64) and return, per
-    m and snapshot time, the scattered E_x and E_y rows (guards included)
-    and the cell count.  Snapshot times must be multiples of the coarsest
-    time step so that every resolution reaches them exactly."""
+                        cfl: float = 0.99, model: str = "sff"
+                        ) -> Dict[int, Dict[float, dict]]:
+    """Run the 1D set-up of Sec. 3.1 at cell sizes 2 pi / (16 2^m) for m in
+    ms through the library (FP64) and return, per m and snapshot time: the
+    stored E_x and E_y rows ("ex", "ey"), the total field rows ("ex_total",
+    "ey_total"; guards included), the kinetic and total electromagnetic
+    energies ("w_kin", "w_em") and the cell count and size.
+
+    model "sff" is the scattered-field form (ii); "ff" is model (i), the
+    pulse on the grid from t = 0 (full_field_start) with no incident field,
+    which needs the pulse inside the box at t = 0 (t0 < 0 places its centre
+    at x = -t0).  Snapshot times must be multiples of the coarsest time step
+    so that every resolution reaches them exactly."""
     from .binding import Simulation
+    if model not in ("sff", "ff"):
+        raise ValueError("model must be 'sff' or 'ff'")
     m0 = min(ms)
     dt0 = cfl * 2 * math.pi / (16 * 2 ** m0)
     out: Dict[int, Dict[float, dict]] = {}
@@ -102,6 +157,12 @@ def refinement_study_1d(ms: Sequence[int], length: float, a0: float,
                           t0=t0)
         e = quiet_profile_1d(grid, density, ppc, center, fwhm, order, xmin)
         sim = Simulation(grid, inc, explicit=[e])
+        if model == "ff":
+            ff = Simulation(grid, wl.Incident(kind=wl.INC_NONE),
+                            explicit=[e])
+            full_field_start(ff, sim)
+            sim.close()
+            sim = ff
         done = 0
         res = {}
         for t in t_snap:
@@ -112,8 +173,13 @@ def refinement_study_1d(ms: Sequence[int], length: float, a0: float,
             target = int(round(k0)) * 2 ** (m - m0)
             sim.step(target - done)
             done = target
+            d = sim.diagnostics()
             res[t] = {"ex": sim.read_field("ex")[0],
-                      "ey": sim.read_field("ey")[0], "nx": nx, "h": h}
+                      "ey": sim.read_field("ey")[0],
+                      "ex_total": sim.read_total_field("ex")[0],
+                      "ey_total": sim.read_total_field("ey")[0],
+                      "w_kin": d["w_kin"], "w_em": d["w_em_total"],
+                      "nx": nx, "h": h}
         sim.close()
         out[m] = res
     return out
@@ -122,7 +188,8 @@ def refinement_study_1d(ms: Sequence[int], length: float, a0: float,
 def study_norms(study: Dict[int, Dict[float, dict]], comp: str = "ey"
                 ) -> Dict[float, List[float]]:
     """Norms of every resolution but the finest against the finest, per
-    snapshot time (component ey, the transverse field, is primal; ex, the
+    snapshot time, of a recorded row: "ey" / "ex" (stored field) or
+    "ey_total" / "ex_total" (E_y, the transverse field, is primal; E_x, the
     longitudinal one, dual)."""
     ms = sorted(study)
     ref = ms[-1]
@@ -134,6 +201,34 @@ def study_norms(study: Dict[int, Dict[float, dict]], comp: str = "ey"
             c = study[m][t]
             ratio = 2 ** (ref - m)
             norms.append(l2_norm(c[comp], fine[comp], ratio, c["nx"], c["h"],
-                                 dual=(comp == "ex")))
+                                 dual=comp.startswith("ex")))
         out[t] = norms
     return out
+
+
+def study_cross_norms(study_i: Dict[int, Dict[float, dict]],
+                      study_ii: Dict[int, Dict[float, dict]],
+                      comp: str = "ey") -> Dict[int, Dict[float, float]]:
+    """Cross-norm between models (i) and (ii) of the total field comp
+    ("ex" or "ey") per resolution m and snapshot time (the paper forms it
+    at the finest grid; every grid is given here)."""
+    out: Dict[int, Dict[float, float]] = {}
+    for m in study_i:
+        out[m] = {}
+        for t, a in study_i[m].items():
+            b = study_ii[m][t]
+            out[m][t] = cross_norm(a[comp + "_total"], b[comp + "_total"],
+                                   a["nx"], a["h"], dual=(comp == "ex"))
+    return out
+
+
+def study_energy_norms(study: Dict[int, Dict[float, dict]],
+                       key: str = "w_em", scale: float = 1.0
+                       ) -> List[float]:
+    """Time-averaged difference of the energy `key` ("w_em" or "w_kin")
+    from the finest grid over the snapshot times, for every resolution but
+    the finest, divided by scale."""
+    ms = sorted(study)
+    ref = [study[ms[-1]][t][key] for t in study[ms[-1]]]
+    return [energy_norm([study[m][t][key] for t in study[ms[-1]]], ref,
+                        scale) for m in ms[:-1]]

@@ -823,6 +823,32 @@ int sfpic_write_field(sfpic_sim *s, int comp, const double *in, size_t n) {
   return SFPIC_OK;
 }
 
+int sfpic_read_total_field(sfpic_sim *s, int comp, double *out, size_t n) {
+  SF_TRY(guarded(s));
+  if (comp < SFPIC_EX || comp > SFPIC_BZ || !out)
+    return fail(SFPIC_E_INVAL, "component must be E or B, output non-NULL");
+  if (n != (size_t)s->NX * s->NY) return fail(SFPIC_E_SIZE, "n must be NX*NY");
+  // half-cell offsets of Ex Ey Ez Bx By Bz along x and y on the Yee grid
+  static const int hx[6] = {1, 0, 0, 0, 1, 1}, hy[6] = {0, 1, 0, 1, 0, 1};
+  const double tE = (double)s->step * s->grid.dt;
+  const double t = comp < 3 ? tE : tE - 0.5 * s->grid.dt;
+  // s->rho is diagnostic scratch of NY x pitch doubles; the charge
+  // diagnostics clear and refill it before every use
+  SF_TRY(s->dispatch([&](auto z) -> int {
+    using R = decltype(z);
+    HIP_TRY(launch_total_field<R>((const R *)s->planes[comp], s->pitch, s->NX,
+                                  s->NY, comp, hx[comp], hy[comp],
+                                  s->grid.dims, s->grid.dx, s->grid.dy, t,
+                                  s->inc, s->rho, s->stream));
+    return SFPIC_OK;
+  }));
+  HIP_TRY(hipMemcpy2DAsync(out, (size_t)s->NX * 8, s->rho,
+                           (size_t)s->pitch * 8, (size_t)s->NX * 8, s->NY,
+                           hipMemcpyDeviceToHost, s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  return SFPIC_OK;
+}
+
 int sfpic_set_step_index(sfpic_sim *s, int64_t step) {
   SF_TRY(guarded(s));
   if (step < 0) return fail(SFPIC_E_INVAL, "step < 0");

@@ -491,31 +491,48 @@ hipError_t launch_field_sums(const Fields<R> &f, double *acc, hipStream_t st) {
   return hipGetLastError();
 }
 
+// Component c (0..5: Ex Ey Ez Bx By Bz) of an (E, B) pair, as a select chain:
+// a run-time index into E or B would put both in private memory.
+__device__ inline double pick6(int c, const double E[3], const double B[3]) {
+  return c == 0   ? E[0]
+         : c == 1 ? E[1]
+         : c == 2 ? E[2]
+         : c == 3 ? B[0]
+         : c == 4 ? B[1]
+                  : B[2];
+}
+
 // Energy of the total field F_inc + F_scatt (Sec. 2) on the physical nodes:
 // 1/2 sum |E_s^n + E_inc(t^n)|^2 + |B_s^{n-1/2} + B_inc(t^{n-1/2})|^2 over the
 // six components, each taken at the node where the Yee grid stores it, with
 // the incident field in FP64.  One thread per node; sum into acc[7].
 template <typename R>
-__global__ void em_total_kernel(Fields<R> f, int dims, int nx, double dx,
+__global__ __launch_bounds__(256) void em_total_kernel(Fields<R> f, int dims, int nx, double dx,
                                 double dy, double tE, double tB, IncParams inc,
                                 double *acc) {
   __shared__ double sh[8];
-  // dual (1) or primal (0) position of Ex Ey Ez Bx By Bz along x and y
-  constexpr int sx[6] = {1, 0, 0, 0, 1, 1}, sy[6] = {0, 1, 0, 1, 0, 1};
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y;
   double e = 0.0;
   if (i < nx) {
     const size_t k = (size_t)(dims == 2 ? j + kGuard : 0) * f.pitch + i +
                      kGuard;
-    const R *src[6] = {f.ex, f.ey, f.ez, f.bx, f.by, f.bz};
 #pragma unroll 1
     for (int c = 0; c < 6; ++c) {
-      const double x = ((double)i + 0.5 * sx[c]) * dx;
-      const double y = dims == 2 ? ((double)j + 0.5 * sy[c]) * dy : 0.0;
+      // half-cell offsets of Ex Ey Ez Bx By Bz along x and y
+      const int hx = c == 0 || c == 4 || c == 5;
+      const int hy = c == 1 || c == 3 || c == 5;
+      const R *src = c == 0   ? f.ex
+                     : c == 1 ? f.ey
+                     : c == 2 ? f.ez
+                     : c == 3 ? f.bx
+                     : c == 4 ? f.by
+                              : f.bz;
+      const double x = ((double)i + 0.5 * hx) * dx;
+      const double y = dims == 2 ? ((double)j + 0.5 * hy) * dy : 0.0;
       double E[3], B[3];
       incident_field(inc, dims, x, y, c < 3 ? tE : tB, E, B);
-      const double v = (double)src[c][k] + (c < 3 ? E[c] : B[c - 3]);
+      const double v = (double)src[k] + pick6(c, E, B);
       e += 0.5 * v * v;
     }
   }
@@ -563,6 +580,39 @@ hipError_t launch_incident_nodes(const Fields<R> &f, int dims, double dx,
                                  hipStream_t st) {
   dim3 g((f.nx_alloc + 255) / 256, f.ny_alloc);
   incident_nodes_kernel<R><<<g, 256, 0, st>>>(f, dims, dx, dy, t, inc);
+  return hipGetLastError();
+}
+
+// Total field F_scatt + F_inc (Sec. 2) of one stored component, in FP64, at
+// every array element (guards included) of a plane of pitch `pitch`: the
+// element (i, j) sits at ((i - G) + hx / 2) dx, ((j - G) + hy / 2) dy, where
+// hx, hy are 1 for a component staggered by half a cell along that axis; the
+// incident field is the FP64 closed form at time t.
+template <typename R>
+__global__ __launch_bounds__(256) void total_field_kernel(const R *src, int pitch, int NX, int comp,
+                                   int hx, int hy, int dims, double dx,
+                                   double dy, double t, IncParams inc,
+                                   double *dst) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  if (i >= NX) return;
+  const size_t k = (size_t)j * pitch + i;
+  const double x = ((double)(i - kGuard) + 0.5 * hx) * dx;
+  const double y =
+      dims == 2 ? ((double)(j - kGuard) + 0.5 * hy) * dy : 0.0;
+  double E[3], B[3];
+  incident_field(inc, dims, x, y, t, E, B);
+  dst[k] = (double)src[k] + pick6(comp, E, B);
+}
+
+template <typename R>
+hipError_t launch_total_field(const R *src, int pitch, int NX, int NY,
+                              int comp, int hx, int hy, int dims, double dx,
+                              double dy, double t, const IncParams &inc,
+                              double *dst, hipStream_t st) {
+  dim3 g((NX + 255) / 256, NY);
+  total_field_kernel<R><<<g, 256, 0, st>>>(src, pitch, NX, comp, hx, hy, dims,
+                                           dx, dy, t, inc, dst);
   return hipGetLastError();
 }
 
@@ -714,6 +764,10 @@ hipError_t launch_export_particles(const Particles<R> &p, int64_t n, int dims,
                                          double, double, double, double,      \
                                          const IncParams &, double *,         \
                                          hipStream_t);                        \
+  template hipError_t launch_total_field<R>(const R *, int, int, int, int,  \
+                                            int, int, int, double, double,    \
+                                            double, const IncParams &,        \
+                                            double *, hipStream_t);           \
   template hipError_t launch_gauss<R>(const Fields<R> &, int, int, int,       \
                                       double, double, const double *,         \
                                       const double *, int, double *,          \

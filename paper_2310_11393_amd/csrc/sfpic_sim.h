@@ -31,6 +31,15 @@ hipError_t launch_init_particles_profile(const Particles<R> &p, int64_t n,
                                          uint64_t seed, uint32_t key1,
                                          hipStream_t st);
 
+// dst[j pitch + i] = F_scatt + F_inc of stored component comp (0..5) at its
+// Yee node (hx, hy: half-cell offsets along x and y), every element of an
+// NX x NY plane, FP64, incident field at time t.
+template <typename R>
+hipError_t launch_total_field(const R *src, int pitch, int NX, int NY,
+                              int comp, int hx, int hy, int dims, double dx,
+                              double dy, double t, const IncParams &inc,
+                              double *dst, hipStream_t st);
+
 #define HIP_TRY(expr)                                                   \
   do {                                                                  \
     hipError_t e_ = (expr);                                             \

@@ -68,3 +68,59 @@ def test_quiet_start_follows_the_profile():
     xs = np.sort(e["x"][cells == full]) / grid.dx - full
     assert np.allclose(xs, (np.arange(8) + 0.5) / 8)
     assert e["weight"] == 0.1 / 8
+
+
+def test_cross_norm_counts_physical_nodes_only():
+    nc, h = 30, 0.2
+    a = np.full(nc + 2 * G, 5.0)
+    b = a + 0.25
+    b[:G] = b[G + nc + 1:] = 1e9  # guards never enter the norm
+    assert math.isclose(cv.cross_norm(a, b, nc, h),
+                        math.sqrt(h * (nc + 1) * 0.0625), rel_tol=1e-14)
+    assert math.isclose(cv.cross_norm(a, b, nc, h, dual=True),
+                        math.sqrt(h * nc * 0.0625), rel_tol=1e-14)
+
+
+def test_energy_norm_is_the_mean_absolute_difference():
+    assert cv.energy_norm([1.0, 2.0, 3.0], [1.0, 1.0, 1.0]) == 1.0
+    assert cv.energy_norm([1.0, -2.0], [0.0, 0.0], scale=3.0) == 0.5
+    for a, b in (([1.0], [1.0, 2.0]), ([], [])):
+        try:
+            cv.energy_norm(a, b)
+        except ValueError:
+            continue
+        raise AssertionError("mismatched series accepted")
+
+
+def test_study_cross_and_energy_norms_of_second_order_models():
+    """Two models whose fields err by c_i h^2 cos(x) and whose energies err
+    by d_i h^2: the cross-norm is |c_1 - c_2| h^2 ||cos||_{2,h} (rate 2) and
+    the energy norms against the finest grid scale as h^2 - h_fine^2."""
+    L = 12.0
+    ts = (0.5, 1.0)
+
+    def study(c, d):
+        out = {}
+        for m in range(4):
+            nc = 24 * 2 ** m
+            h = L / nc
+            out[m] = {t: {"ey_total": _row(nc, h, lambda x: np.sin(x + t) +
+                                           c * h * h * np.cos(x)),
+                          "w_em": 1.0 + t + d * h * h, "nx": nc, "h": h}
+                      for t in ts}
+        return out
+
+    s1, s2 = study(0.5, 2.0), study(-0.25, -1.0)
+    cn = cv.study_cross_norms(s1, s2, "ey")
+    for m in range(4):
+        h = L / (24 * 2 ** m)
+        x = np.arange(24 * 2 ** m + 1) * h
+        want = 0.75 * h * h * math.sqrt(h * float(np.sum(np.cos(x) ** 2)))
+        for t in ts:
+            assert math.isclose(cn[m][t], want, rel_tol=1e-9)
+    assert abs(cv.rate(cn[0][ts[0]], cn[1][ts[0]]) - 2.0) < 0.05
+    hf = L / (24 * 8)
+    en = cv.study_energy_norms(s1, "w_em", scale=2.0)
+    for m, v in enumerate(en):
+        h = L / (24 * 2 ** m)
+        assert math.isclose(v, 2.0 * (h * h - hf * hf) / 2.0, rel_tol=1e-9)

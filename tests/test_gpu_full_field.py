@@ -1,0 +1,251 @@
+"""The total field and the full-field comparison model of Sec. 3.1 on the GPU.
+
+  * sfpic_read_total_field: the stored scattered field plus the incident
+    field at every Yee node equals the oracle's scattered field plus the
+    oracle's own closed form at the same nodes (2D April LP and RP, the 1D
+    pulse; FP64 to 1e-12, the FP32 form to 1e-4), and half its square
+    summed over the physical nodes is the total-field energy diagnostic;
+  * model (i), the incident pulse put on the grid at t = 0 and carried by
+    the Yee solver with no incident field: the GPU run equals the oracle run
+    started from the oracle's samples of the pulse (1e-12);
+  * the cross-norm between models (i) and (ii) falls as h^2 with the pulse
+    in vacuum (where (ii) is exact at the nodes and (i) carries the Yee
+    dispersion error) and with the pulse in the plasma, and the time-averaged
+    energy norms of each model against its finest grid fall as the cell
+    shrinks; the GPU norms equal the oracle's.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2310_11393_amd import convergence as cv
+from paper_2310_11393_amd import workloads as wl
+
+from parity_util import FIELD_COMPS, explicit_species, make_gpu, make_oracle
+
+pytestmark = pytest.mark.gpu
+
+G = 3
+# half-cell offsets of each component on the Yee grid along x and y
+HX = dict(ex=1, ey=0, ez=0, bx=0, by=1, bz=1)
+HY = dict(ex=0, ey=1, ez=0, bx=1, by=0, bz=1)
+
+
+def _note(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def oracle_incident_plane(inc, grid, comp, t, NX, NY):
+    """The oracle's closed form of one component at that component's node
+    of every array element (guards included)."""
+    import oracle
+    out = np.zeros((NY, NX))
+    c = FIELD_COMPS.index(comp)
+    for j in range(NY):
+        y = (j - G + 0.5 * HY[comp]) * grid.dy if grid.dims == 2 else 0.0
+        for i in range(NX):
+            x = (i - G + 0.5 * HX[comp]) * grid.dx
+            E, B = oracle.incident_eval(inc, grid.dims, x, y, t)
+            out[j, i] = E[c] if c < 3 else B[c - 3]
+    return out
+
+
+def oracle_total(o, grid, inc, comp):
+    """Oracle scattered field plus the oracle's closed form: E at t^n, B at
+    t^{n-1/2}."""
+    t = o.step_index * grid.dt
+    if comp.startswith("b"):
+        t -= 0.5 * grid.dt
+    return o.field(comp) + oracle_incident_plane(inc, grid, comp, t, o.NX,
+                                                 o.NY)
+
+
+def _lp(kind=wl.INC_APRIL_LP, **kw):
+    args = dict(nx=72, ny=48, plasma=(20, 52, 0, 48), ppc=4, kind=kind,
+                w0_lambda=1.0, s=20.0, a0=10.0, temperature_ev=1.0, steps=30,
+                seed=21)
+    args.update(kw)
+    return wl.april_2d(**args)
+
+
+TOTAL_CASES = {
+    "lp2d": lambda: _lp(),
+    "rp2d": lambda: _lp(kind=wl.INC_APRIL_RP, w0_lambda=0.8, s=10.0,
+                        a0=30.0, temperature_ev=0.0),
+    "pulse1d": lambda: wl.plane_pulse_1d(nx=300, slab=(100, 230), ppc=16,
+                                         a0=3.0, steps=60),
+}
+
+
+@pytest.mark.parametrize("case,prec", [("lp2d", wl.FP64), ("rp2d", wl.FP64),
+                                       ("pulse1d", wl.FP64),
+                                       ("lp2d", wl.FP32)])
+def test_total_field_matches_oracle(case, prec):
+    work = TOTAL_CASES[case]()
+    _note(f"[total] {case} prec {prec}: grid {work.grid.nx}x{work.grid.ny}, "
+          f"{work.steps} steps")
+    sp = explicit_species(work)
+    g = make_gpu(work, sp, precision=prec)
+    o = make_oracle(work, sp)
+    g.step(work.steps)
+    o.step(work.steps)
+    num = den = 0.0
+    energy = 0.0
+    nx, ny = work.grid.nx, work.grid.ny
+    for c in FIELD_COMPS:
+        a = g.read_total_field(c)
+        b = oracle_total(o, work.grid, work.incident, c)
+        assert a.shape == b.shape
+        num += float(np.sum((a - b) ** 2))
+        den += float(np.sum(b ** 2))
+        phys = a[G:G + ny, G:G + nx] if work.grid.dims == 2 else a[0, G:G + nx]
+        energy += 0.5 * float(np.sum(phys ** 2))
+    rel = math.sqrt(num / den)
+    _note(f"[total] {case}: rel L2 {rel:.3e}")
+    assert den > 0
+    assert rel <= (1e-12 if prec == wl.FP64 else 1e-4), rel
+    dv = work.grid.dx * (work.grid.dy if work.grid.dims == 2 else 1.0)
+    d = g.diagnostics()
+    assert abs(energy * dv - d["w_em_total"]) <= 1e-12 * d["w_em_total"]
+    od = o.diagnostics()
+    tol = 1e-11 if prec == wl.FP64 else 1e-4
+    assert abs(energy * dv - od["w_em_total"]) <= tol * od["w_em_total"]
+    g.close()
+
+
+def test_total_field_rejects_bad_requests():
+    from paper_2310_11393_amd.binding import SfpicError, Simulation, _dp, lib
+    work = TOTAL_CASES["pulse1d"]()
+    g = make_gpu(work)
+    out = np.zeros((g.NY, g.NX))
+    for comp in (6, 7, 8, -1):
+        with pytest.raises(SfpicError):
+            g.read_total_field(comp)
+    assert lib().sfpic_read_total_field(g.h, 0, _dp(out), out.size - 1) != 0
+    # a sim without an incident field returns its stored field
+    g.step(5)
+    none = Simulation(work.grid, wl.Incident(kind=wl.INC_NONE))
+    for c in FIELD_COMPS:
+        none.write_field(c, g.read_field(c))
+        assert np.array_equal(none.read_total_field(c), g.read_field(c))
+    none.close()
+    g.close()
+
+
+# The Sec. 3.1 set-up for the model comparison: the plane pulse centred at
+# x = 25 at t = 0 (wholly inside the box: 2^-63 of its peak at x = 0 and at
+# the plasma edge), the order-12 profile between x = 55 and the box's end.
+FF = dict(length=2 * math.pi * 24, a0=0.5, fwhm_t=2 * math.pi, t0=-25.0,
+          density=0.1, ppc=16, center=100.0, fwhm=50.0, order=12.0,
+          xmin=55.0)
+DT0 = 0.99 * 2 * math.pi / 16
+
+
+def oracle_study(ms, t_snap, model):
+    """The same study on the oracle: model (i) starts from the oracle's own
+    samples of the pulse on the Yee nodes."""
+    import oracle
+    inc = wl.Incident(kind=wl.INC_PLANE_PULSE_1D, a0=FF["a0"],
+                      fwhm_t=FF["fwhm_t"], t0=FF["t0"])
+    out = {}
+    for m in ms:
+        h = 2 * math.pi / (16 * 2 ** m)
+        nx = int(round(FF["length"] / h))
+        grid = wl.Grid(1, nx, 1, h, h, 0.99 * h)
+        e = cv.quiet_profile_1d(grid, FF["density"], FF["ppc"], FF["center"],
+                                FF["fwhm"], FF["order"], FF["xmin"])
+        o = oracle.OracleSim(grid, inc if model == "sff"
+                             else wl.Incident(kind=wl.INC_NONE))
+        o.add_species(-1.0, 1.0, e["weight"], e["x"], e["y"], e["ux"],
+                      e["uy"], e["uz"])
+        if model == "ff":
+            for c in ("ey", "bz"):
+                o.field(c)[:] = oracle_incident_plane(
+                    inc, grid, c, 0.0 if c == "ey" else -0.5 * grid.dt,
+                    o.NX, o.NY)
+        done, res = 0, {}
+        for t in t_snap:
+            target = int(round(t / DT0)) * 2 ** m
+            o.step(target - done)
+            done = target
+            row = {c + "_total": (oracle_total(o, grid, inc, c)[0]
+                                  if model == "sff" else o.field(c)[0].copy())
+                   for c in ("ex", "ey")}
+            d = o.diagnostics()
+            row.update(w_kin=d["w_kin"], w_em=d["w_em_total"], nx=nx, h=h)
+            res[t] = row
+        out[m] = res
+    return out
+
+
+def _gpu_study(ms, t_snap, model):
+    return cv.refinement_study_1d(
+        ms, length=FF["length"], a0=FF["a0"], fwhm_t=FF["fwhm_t"],
+        t0=FF["t0"], density=FF["density"], ppc=FF["ppc"],
+        center=FF["center"], fwhm=FF["fwhm"], order=FF["order"],
+        xmin=FF["xmin"], t_snap=t_snap, model=model)
+
+
+def test_full_field_model_matches_oracle():
+    t_snap = [50 * DT0, 250 * DT0]
+    for model in ("ff", "sff"):
+        _note(f"[ff] model {model}, m = 0, 1")
+        gs = _gpu_study([0, 1], t_snap, model)
+        os_ = oracle_study([0, 1], t_snap, model)
+        for m in (0, 1):
+            for t in t_snap:
+                for c in ("ex_total", "ey_total"):
+                    a, b = gs[m][t][c], os_[m][t][c]
+                    scale = max(np.abs(b).max(), 1e-300)
+                    assert np.abs(a - b).max() <= 1e-12 * max(scale, 1e-3), \
+                        (model, m, t, c)
+                for k in ("w_kin", "w_em"):
+                    assert abs(gs[m][t][k] - os_[m][t][k]) <= \
+                        1e-11 * abs(os_[m][t][k]) + 1e-300, (model, m, k)
+
+
+def test_cross_norms_fall_as_h_squared():
+    t_vac, t_in = 50 * DT0, 250 * DT0
+    ms = [0, 1, 2, 3]
+    _note("[ff] studies m = 0..3, models (i) and (ii)")
+    ff = _gpu_study(ms, [t_vac, t_in], "ff")
+    sff = _gpu_study(ms, [t_vac, t_in], "sff")
+    for m in ms:
+        # (ii) in vacuum: the scattered field is zero, the total exact
+        assert np.abs(sff[m][t_vac]["ey"]).max() < 1e-11, m
+    cy = cv.study_cross_norms(ff, sff, "ey")
+    cx = cv.study_cross_norms(ff, sff, "ex")
+    for t in (t_vac, t_in):
+        ny = [cy[m][t] for m in ms]
+        p = [cv.rate(a, b) for a, b in zip(ny, ny[1:])]
+        _note(f"[ff] t = {t:.2f}: E_y cross-norms {ny}, rates {p}")
+        assert all(1.9 <= q <= 2.1 for q in p), p
+    assert max(cx[m][t_vac] for m in ms) < 1e-12  # no E_x in vacuum
+    nxn = [cx[m][t_in] for m in ms]
+    px = [cv.rate(a, b) for a, b in zip(nxn, nxn[1:])]
+    _note(f"[ff] E_x cross-norms in the plasma {nxn}, rates {px}")
+    assert all(q >= 1.9 for q in px), px
+    # each model against its own finest grid
+    for st in (ff, sff):
+        n = cv.study_norms(st, "ey_total")[t_in]
+        assert n[0] > n[1] > n[2], n
+    peak = max(sff[m][t][k] for m in ms for t in (t_vac, t_in)
+               for k in ("w_em",))
+    for key in ("w_em", "w_kin"):
+        for st in (ff, sff):
+            en = cv.study_energy_norms(st, key, scale=peak)
+            _note(f"[ff] {key} energy norms {en}")
+            assert en[0] > en[1] > en[2], (key, en)
+        cross = cv.energy_norm([ff[3][t][key] for t in (t_vac, t_in)],
+                               [sff[3][t][key] for t in (t_vac, t_in)],
+                               scale=peak)
+        assert cross < 1e-3, (key, cross)
+    # the GPU's cross-norms at m = 0, 1 are the oracle's
+    off = oracle_study([0, 1], [t_vac, t_in], "ff")
+    osf = oracle_study([0, 1], [t_vac, t_in], "sff")
+    ocy = cv.study_cross_norms(off, osf, "ey")
+    for m in (0, 1):
+        for t in (t_vac, t_in):
+            assert abs(cy[m][t] - ocy[m][t]) <= 1e-8 * ocy[m][t], (m, t)
