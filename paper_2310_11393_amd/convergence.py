@@ -232,3 +232,178 @@ def study_energy_norms(study: Dict[int, Dict[float, dict]],
     ref = [study[ms[-1]][t][key] for t in study[ms[-1]]]
     return [energy_norm([study[m][t][key] for t in study[ms[-1]]], ref,
                         scale) for m in ms[:-1]]
+
+
+# --- 2D (Sec. 3.2) ----------------------------------------------------------
+#
+# In 2D the paper compares the two models in vacuum through the relative L1
+# error of the intensity I = E_par^2 + E_long^2 and the relative Frobenius
+# error of each component, and convergence through the 1D norm above along
+# the beam axis.  Build axes: propagation x, polarization y, so the paper's
+# transverse E is E_y (primal in x, dual in y) and its longitudinal E is E_x
+# (dual in x, primal in y).
+
+# half-cell offsets (x, y) of the stored components on the Yee grid
+STAGGER = dict(ex=(1, 0), ey=(0, 1), ez=(0, 0), bx=(0, 1), by=(1, 0),
+               bz=(1, 1))
+
+
+def physical(plane: np.ndarray, n_x: int, n_y: int, comp: str) -> np.ndarray:
+    """The physical nodes of a 2D plane with guards: (n + 1) primal or n
+    dual nodes along each axis."""
+    hx, hy = STAGGER[comp]
+    return plane[GUARD:GUARD + n_y + 1 - hy, GUARD:GUARD + n_x + 1 - hx]
+
+
+def frobenius_error(plane_a: np.ndarray, plane_b: np.ndarray, n_x: int,
+                    n_y: int, comp: str) -> float:
+    """Relative Frobenius error of Sec. 3.2, ||a - b||_F / ||b||_F over the
+    component's physical nodes (b is the reference model)."""
+    a = physical(plane_a, n_x, n_y, comp)
+    b = physical(plane_b, n_x, n_y, comp)
+    return math.sqrt(float(np.sum((a - b) ** 2)) / float(np.sum(b * b)))
+
+
+def intensity(ey: np.ndarray, ex: np.ndarray, n_x: int, n_y: int
+              ) -> np.ndarray:
+    """E_y^2 + E_x^2 at the interior primal nodes (i, j), 1 <= i < n_x,
+    1 <= j < n_y: E_y (dual in y) and E_x (dual in x) each the mean of the
+    two nodes that bracket (i, j) along their dual axis."""
+    g = GUARD
+    ey_p = 0.5 * (ey[g:g + n_y - 1, g + 1:g + n_x] +
+                  ey[g + 1:g + n_y, g + 1:g + n_x])
+    ex_p = 0.5 * (ex[g + 1:g + n_y, g:g + n_x - 1] +
+                  ex[g + 1:g + n_y, g + 1:g + n_x])
+    return ey_p * ey_p + ex_p * ex_p
+
+
+def intensity_error(ey_a, ex_a, ey_b, ex_b, n_x: int, n_y: int) -> float:
+    """Relative L1 error of the intensity, Sec. 3.2:
+    sum |I_a - I_b| / sum I_b over the interior primal nodes."""
+    ia = intensity(ey_a, ex_a, n_x, n_y)
+    ib = intensity(ey_b, ex_b, n_x, n_y)
+    return float(np.sum(np.abs(ia - ib))) / float(np.sum(ib))
+
+
+def axis_row(plane: np.ndarray, j_axis: int, comp: str) -> np.ndarray:
+    """The row of a 2D plane on the line y = j_axis h (the beam axis), guards
+    included along x: a component dual in y takes the mean of the two rows
+    that bracket the line."""
+    g = GUARD
+    if STAGGER[comp][1]:
+        return 0.5 * (plane[g + j_axis - 1] + plane[g + j_axis])
+    return plane[g + j_axis].copy()
+
+
+def refinement_study_2d(ms: Sequence[int], lx: float, ly: float, a0: float,
+                        w0: float, fwhm_t: float, x_center0: float,
+                        x_focus: float, t_snap: Sequence[float],
+                        density: float = 0.0, ppc: int = 0,
+                        center: float = 0.0, fwhm: float = 1.0,
+                        order: float = 12.0, xmin: float = 0.0,
+                        seed: int = 7, cfl: float = 0.99, model: str = "sff",
+                        keep_planes: bool = True
+                        ) -> Dict[int, Dict[float, dict]]:
+    """The 2D set-up of Sec. 3.2 through the library (FP64) at cell sizes
+    2 pi / (16 2^m): the paraxial Gaussian beam focused on the box's axis at
+    x_focus, its envelope centred at x_center0 at t = 0, optionally a cold
+    plasma with the order-`order` super-Gaussian profile along x, uniform
+    across y (density = 0: vacuum).  Per m and snapshot time: the total E_y
+    and E_x planes ("ey_total", "ex_total", if keep_planes), their rows on
+    the beam axis ("ey_axis", "ex_axis"), the energies ("w_kin", "w_em") and
+    the cell counts and size.  model "sff" / "ff" as in the 1D study; the
+    snapshot times must be multiples of the coarsest time step."""
+    from .binding import Simulation
+    if model not in ("sff", "ff"):
+        raise ValueError("model must be 'sff' or 'ff'")
+    m0 = min(ms)
+    dt0 = cfl * 2 * math.pi / (16 * 2 ** m0) / math.sqrt(2.0)
+    out: Dict[int, Dict[float, dict]] = {}
+    for m in ms:
+        h = 2 * math.pi / (16 * 2 ** m)
+        nx, ny = int(round(lx / h)), int(round(ly / h))
+        if ny % 2:
+            raise ValueError("the axis must be a node row: even ny needed")
+        grid = wl.Grid(2, nx, ny, h, h, cfl * h / math.sqrt(2.0))
+        inc = wl.Incident(kind=wl.INC_GAUSS_2D, a0=a0, w0=w0, fwhm_t=fwhm_t,
+                          t0=x_focus - x_center0, x_focus=x_focus,
+                          y_focus=0.5 * ny * h)
+        species = []
+        if density > 0.0:
+            species = [wl.Species(q=-1.0, m=1.0, density=density,
+                                  region=(0, nx, 0, ny), ppc=ppc, seed=seed,
+                                  profile=wl.PROFILE_SUPERGAUSS,
+                                  profile_center=center, profile_fwhm=fwhm,
+                                  profile_order=order, profile_xmin=xmin)]
+        sim = Simulation(grid, inc, species=species)
+        if model == "ff":
+            ff = Simulation(grid, wl.Incident(kind=wl.INC_NONE),
+                            species=species)
+            full_field_start(ff, sim)
+            sim.close()
+            sim = ff
+        done = 0
+        res = {}
+        for t in t_snap:
+            k0 = t / dt0
+            if abs(k0 - round(k0)) > 1e-9:
+                raise ValueError("snapshot times must be multiples of the "
+                                 "coarsest time step")
+            target = int(round(k0)) * 2 ** (m - m0)
+            sim.step(target - done)
+            done = target
+            d = sim.diagnostics()
+            ey = sim.read_total_field("ey")
+            ex = sim.read_total_field("ex")
+            row = {"ey_axis": axis_row(ey, ny // 2, "ey"),
+                   "ex_axis": axis_row(ex, ny // 2, "ex"),
+                   "w_kin": d["w_kin"], "w_em": d["w_em_total"],
+                   "nx": nx, "ny": ny, "h": h}
+            if keep_planes:
+                row.update(ey_total=ey, ex_total=ex)
+            res[t] = row
+        sim.close()
+        out[m] = res
+    return out
+
+
+def study_cross_errors_2d(study_i: Dict[int, Dict[float, dict]],
+                          study_ii: Dict[int, Dict[float, dict]]
+                          ) -> Dict[int, Dict[float, dict]]:
+    """Per m and snapshot time, the Sec. 3.2 comparison of model (i) with
+    model (ii) as the reference: relative intensity error "dI" and relative
+    Frobenius errors "dEy", "dEx"."""
+    out: Dict[int, Dict[float, dict]] = {}
+    for m in study_i:
+        out[m] = {}
+        for t, a in study_i[m].items():
+            b = study_ii[m][t]
+            nx, ny = a["nx"], a["ny"]
+            out[m][t] = {
+                "dI": intensity_error(a["ey_total"], a["ex_total"],
+                                      b["ey_total"], b["ex_total"], nx, ny),
+                "dEy": frobenius_error(a["ey_total"], b["ey_total"], nx, ny,
+                                       "ey"),
+                "dEx": frobenius_error(a["ex_total"], b["ex_total"], nx, ny,
+                                       "ex")}
+    return out
+
+
+def study_axis_norms(study: Dict[int, Dict[float, dict]], comp: str = "ey"
+                     ) -> Dict[float, List[float]]:
+    """Norms along the beam axis of every resolution but the finest against
+    the finest (E_y primal in x, E_x dual), per snapshot time."""
+    ms = sorted(study)
+    ref = ms[-1]
+    out = {}
+    for t in study[ref]:
+        fine = study[ref][t]
+        norms = []
+        for m in ms[:-1]:
+            c = study[m][t]
+            ratio = 2 ** (ref - m)
+            norms.append(l2_norm(c[comp + "_axis"], fine[comp + "_axis"],
+                                 ratio, c["nx"], c["h"],
+                                 dual=(comp == "ex")))
+        out[t] = norms
+    return out

@@ -124,3 +124,65 @@ def test_study_cross_and_energy_norms_of_second_order_models():
     for m, v in enumerate(en):
         h = L / (24 * 2 ** m)
         assert math.isclose(v, 2.0 * (h * h - hf * hf) / 2.0, rel_tol=1e-9)
+
+
+def _plane(nx, ny, h, comp, f):
+    """A 2D plane with guards holding f(x, y) at the component's nodes."""
+    hx, hy = cv.STAGGER[comp]
+    x = (np.arange(nx + 2 * G) - G + 0.5 * hx) * h
+    y = (np.arange(ny + 2 * G) - G + 0.5 * hy) * h
+    return f(x[None, :], y[:, None])
+
+
+def test_2d_physical_nodes_and_frobenius_error():
+    nx, ny, h = 20, 12, 0.3
+    for comp, shape in (("ey", (12, 21)), ("ex", (13, 20)), ("ez", (13, 21)),
+                        ("bz", (12, 20))):
+        p = _plane(nx, ny, h, comp, lambda x, y: 1.0 + x * y)
+        assert cv.physical(p, nx, ny, comp).shape == shape, comp
+        q = p * 1.25
+        q[:G] = 7e7  # guards never enter
+        assert math.isclose(cv.frobenius_error(q, p, nx, ny, comp), 0.25,
+                            rel_tol=1e-13)
+
+
+def test_2d_intensity_and_axis_row_are_exact_for_linear_fields():
+    nx, ny, h = 16, 10, 0.5
+    fy = lambda x, y: 0.3 + 0.2 * x - 0.7 * y  # noqa: E731
+    fx = lambda x, y: -1.1 + 0.4 * x + 0.9 * y  # noqa: E731
+    ey = _plane(nx, ny, h, "ey", fy)
+    ex = _plane(nx, ny, h, "ex", fx)
+    xi = np.arange(1, nx) * h
+    yj = np.arange(1, ny) * h
+    X, Y = np.meshgrid(xi, yj)
+    want = fy(X, Y) ** 2 + fx(X, Y) ** 2
+    assert np.allclose(cv.intensity(ey, ex, nx, ny), want, rtol=0,
+                       atol=1e-12)
+    # scaling one model's fields by s gives |s^2 - 1| exactly
+    assert math.isclose(cv.intensity_error(1.5 * ey, 1.5 * ex, ey, ex, nx,
+                                           ny), 1.25, rel_tol=1e-13)
+    x_all = (np.arange(nx + 2 * G) - G) * h
+    ja = ny // 2
+    assert np.allclose(cv.axis_row(ey, ja, "ey"), fy(x_all, ja * h),
+                       rtol=0, atol=1e-12)
+    xd = (np.arange(nx + 2 * G) - G + 0.5) * h
+    assert np.allclose(cv.axis_row(ex, ja, "ex"), fx(xd, ja * h), rtol=0,
+                       atol=1e-12)
+
+
+def test_2d_axis_norms_of_a_second_order_model():
+    L, t = 9.0, 1.0
+    study = {}
+    for m in range(3):
+        n = 18 * 2 ** m
+        h = L / n
+        row = _row(n, h, lambda x: np.sin(x) + 0.4 * h * h * np.cos(x))
+        study[m] = {t: {"ey_axis": row, "nx": n, "h": h}}
+    norms = cv.study_axis_norms(study, "ey")[t]
+    hf = L / 72
+    for m, v in enumerate(norms):
+        h = L / (18 * 2 ** m)
+        x = np.arange(18 * 2 ** m + 1) * h
+        want = 0.4 * (h * h - hf * hf) * math.sqrt(h * float(np.sum(
+            np.cos(x) ** 2)))
+        assert math.isclose(v, want, rel_tol=1e-9)

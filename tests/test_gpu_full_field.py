@@ -249,3 +249,106 @@ def test_cross_norms_fall_as_h_squared():
     for m in (0, 1):
         for t in (t_vac, t_in):
             assert abs(cy[m][t] - ocy[m][t]) <= 1e-8 * ocy[m][t], (m, t)
+
+
+# The Sec. 3.2 comparison, scaled to a 12 x 64 wavelength box (the paper's is
+# 32 x 64): the paraxial Gaussian beam with the paper's w0 = 16 lambda,
+# FWHM_T = 2 pi and E0 = 4.86, its envelope centred 3 wavelengths from the
+# entry face at t = 0 and focused mid-box on the axis y = 32 lambda.
+L2 = 2 * math.pi
+B2 = dict(lx=12 * L2, ly=64 * L2, a0=4.86, w0=16 * L2, fwhm_t=L2,
+          x_center0=3 * L2, x_focus=6 * L2)
+DT2 = 0.99 * L2 / 16 / math.sqrt(2.0)
+T2 = [69 * DT2, 137 * DT2]  # envelope at the focus / 3 wavelengths beyond
+
+
+def test_full_field_model_2d_matches_oracle():
+    """Model (i) in 2D from full_field_start (E_x, E_y, B_z of the beam on
+    their nodes) with a profiled plasma, against the oracle started from the
+    oracle's own samples of the beam."""
+    import oracle
+    from paper_2310_11393_amd.binding import Simulation
+    h = L2 / 16
+    nx, ny = 128, 256
+    grid = wl.Grid(2, nx, ny, h, h, 0.99 * h / math.sqrt(2.0))
+    inc = wl.Incident(kind=wl.INC_GAUSS_2D, a0=4.86, w0=4 * L2, fwhm_t=L2,
+                      t0=2 * L2, x_focus=4 * L2, y_focus=0.5 * ny * h)
+    sp = wl.Species(q=-1.0, m=1.0, density=0.31, region=(0, nx, 0, ny),
+                    ppc=2, seed=5, profile=wl.PROFILE_SUPERGAUSS,
+                    profile_center=30.0, profile_fwhm=12.0,
+                    profile_order=12.0, profile_xmin=20.0)
+    x, y, ux, uy, uz = wl.generate_particles(sp, grid)
+    e = dict(q=-1.0, m=1.0, weight=sp.weight, x=x, y=y, ux=ux, uy=uy, uz=uz)
+    _note(f"[ff2d] {nx}x{ny}, {len(x)} particles")
+    sff = Simulation(grid, inc, explicit=[e])
+    ff = Simulation(grid, wl.Incident(kind=wl.INC_NONE), explicit=[e])
+    cv.full_field_start(ff, sff)
+    sff.close()
+    o = oracle.OracleSim(grid, wl.Incident(kind=wl.INC_NONE))
+    o.add_species(-1.0, 1.0, sp.weight, x, y, ux, uy, uz)
+    for c in ("ex", "ey", "bz"):
+        o.field(c)[:] = oracle_incident_plane(
+            inc, grid, c, 0.0 if c[0] == "e" else -0.5 * grid.dt, o.NX, o.NY)
+    ff.step(60)
+    o.step(60)
+    num = den = 0.0
+    for c in FIELD_COMPS:
+        a, b = ff.read_field(c), o.field(c)
+        num += float(np.sum((a - b) ** 2))
+        den += float(np.sum(b ** 2))
+    rel = math.sqrt(num / den)
+    _note(f"[ff2d] rel L2 {rel:.3e}")
+    assert rel <= 1e-12, rel
+    ff.close()
+
+
+def test_2d_models_converge_in_vacuum():
+    """Sec. 3.2 in vacuum: model (ii) is the closed form at the nodes, so
+    the relative intensity error and the relative Frobenius error of E_y of
+    model (i) against it are model (i)'s Yee dispersion error, falling as
+    h^2 down to the paraxial floor (at 2 pi / 128 the rate drops to ~1.7).
+    The longitudinal E_x is not compared: the paraxial formula's first-order
+    E_x under a one-cycle envelope is not divergence-free, and the static
+    field that the grid keeps from it does not vanish with h."""
+    ms = [0, 1, 2, 3]
+    _note("[2d] vacuum studies m = 0..3, models (i) and (ii)")
+    st = {mod: cv.refinement_study_2d(ms, t_snap=T2, model=mod, **B2)
+          for mod in ("ff", "sff")}
+    ce = cv.study_cross_errors_2d(st["ff"], st["sff"])
+    for t in T2:
+        for k in ("dI", "dEy"):
+            v = [ce[m][t][k] for m in ms]
+            p = [cv.rate(a, b) for a, b in zip(v, v[1:])]
+            _note(f"[2d] t = {t:.2f} {k} {v} rates {p}")
+            assert min(p[:2]) >= 1.9, (k, p)
+            assert v[3] < v[2], (k, v)
+
+
+def test_2d_models_in_plasma():
+    """Sec. 3.2 with the order-12 profile (n_e0 = 0.31, uniform across y)
+    ahead of the focus: the energies' norms against the finest grid fall
+    in both models, the models' energies at the finest grid agree within
+    0.5% of the peak total energy, and the on-axis E_y norms fall."""
+    ms = [0, 1, 2, 3]
+    P = dict(density=0.31, ppc=2, center=55.0, fwhm=25.0, order=12.0,
+             xmin=35.0)
+    _note("[2d] plasma studies m = 0..3, models (i) and (ii)")
+    st = {mod: cv.refinement_study_2d(ms, t_snap=T2, model=mod,
+                                      keep_planes=False, **B2, **P)
+          for mod in ("ff", "sff")}
+    peak = max(st[mod][m][t]["w_em"] + st[mod][m][t]["w_kin"]
+               for mod in st for m in ms for t in T2)
+    for mod in st:
+        for key in ("w_em", "w_kin"):
+            en = cv.study_energy_norms(st[mod], key, scale=peak)
+            _note(f"[2d] {mod} {key} energy norms / peak {en}")
+            assert en[0] > en[1] > en[2], (mod, key, en)
+        n = cv.study_axis_norms(st[mod], "ey")[T2[1]]
+        _note(f"[2d] {mod} axis E_y norms {n}")
+        assert n[0] > n[1] > n[2], (mod, n)
+    for key in ("w_em", "w_kin"):
+        cross = cv.energy_norm([st["ff"][3][t][key] for t in T2],
+                               [st["sff"][3][t][key] for t in T2],
+                               scale=peak)
+        _note(f"[2d] cross {key} / peak {cross}")
+        assert cross < 5e-3, (key, cross)
