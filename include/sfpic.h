@@ -562,9 +562,18 @@ int sfpic3_particle_count(sfpic3_sim *sim, int species, int64_t *n);
 int sfpic3_read_particles(sfpic3_sim *sim, int species, double *x, double *y,
                           double *z, double *ux, double *uy, double *uz,
                           uint8_t *alive, size_t n);
+/* Total field F_scatt + F_inc of one component (SFPIC_EX .. SFPIC_BZ) at
+ * its Yee node of every array element, as sfpic_read_total_field does in
+ * 1D and 2D: E at t^n, B at t^{n-1/2}, the full six-component incident
+ * field evaluated on the device in FP64; layout as sfpic3_read_field.
+ * SFPIC_E_INVAL for J or a NULL out, SFPIC_E_SIZE unless n = NX NY NZ. */
+int sfpic3_read_total_field(sfpic3_sim *sim, int comp, double *out, size_t n);
 /* FP64 diagnostics as sfpic_diag (dV = dx dy dz; w_em over every array
  * node; gauss_residual and rho_max over nodes at least 4 cells inside the
- * box); w_em_total is not evaluated in 3D (NaN). */
+ * box; w_em_total, the energy of the total field F_scatt + F_inc, over the
+ * physical nodes i < nx, j < ny, k < nz with each component at its own Yee
+ * node, as in 2D: six incident evaluations per node, so it costs about as
+ * much as a push of six particles per node). */
 int sfpic3_diagnostics(sfpic3_sim *sim, sfpic_diag *out);
 /* Energy-angle histogram of a species, as sfpic_histogram (weights w dV,
  * dV = dx dy dz; angle from +x, the propagation axis; the spectra of

@@ -109,6 +109,8 @@ def lib():
         L.orc3_step.argtypes = [C.c_void_p, C.c_long]
         L.orc3_deposit_rho.argtypes = [C.c_void_p, _D]
         L.orc3_diagnostics.argtypes = [C.c_void_p, _D]
+        L.orc3_em_energy_total.restype = C.c_double
+        L.orc3_em_energy_total.argtypes = [C.c_void_p]
         L.orc3_energy_angle.argtypes = [C.c_void_p, C.c_int, C.c_int,
                                         C.c_double, C.c_int, C.c_double, _D,
                                         _D]
@@ -352,7 +354,8 @@ class OracleSim3:
         o = np.zeros(4)
         lib().orc3_diagnostics(self._h, _dp(o))
         return {"w_kin": o[0], "w_em": o[1], "charge": o[2],
-                "n_alive": int(o[3])}
+                "n_alive": int(o[3]),
+                "w_em_total": lib().orc3_em_energy_total(self._h)}
 
     def energy_angle(self, sp=0, n_e=256, emax=1.0, n_theta=180,
                      ek_min=1.0e3 / 510998.95):

@@ -158,6 +158,9 @@ void orc3_step(orc3_sim *S, long nsteps);
 void orc3_deposit_rho(const orc3_sim *S, double *rho);
 /* out: {W_kin, W_em(E^n, B^{n-1/2}, every array node), charge, n_alive} */
 void orc3_diagnostics(const orc3_sim *S, double out[4]);
+/* 1/2 sum |F_s + F_inc|^2 dV over the physical nodes (E at t^n, B at
+ * t^{n-1/2}), each component at its own node. */
+double orc3_em_energy_total(const orc3_sim *S);
 /* Energy-angle histogram, as orc_energy_angle, of a 3D species. */
 void orc3_energy_angle(const orc3_sim *S, int sp, int n_e, double emax,
                        int n_theta, double ek_min, double *hist,

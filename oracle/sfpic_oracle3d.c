@@ -427,6 +427,29 @@ void orc3_diagnostics(const orc3_sim *S, double out[4]) {
   out[3] = na;
 }
 
+/* Energy of the total field (Sec. 2: the physical field is the incident plus
+ * the scattered one): 1/2 sum over the physical nodes i < nx, j < ny, k < nz
+ * of (F_s + F_inc)^2 for the six components, each at its own staggered node,
+ * E at t^n and B at t^{n-1/2}, times dV. */
+double orc3_em_energy_total(const orc3_sim *S) {
+  const double tE = (double)S->step * S->g.dt, tB = tE - 0.5 * S->g.dt;
+  double w = 0.0;
+  for (long k = 0; k < S->g.nz; ++k)
+    for (long j = 0; j < S->g.ny; ++j)
+      for (long i = 0; i < S->g.nx; ++i)
+        for (int c = 0; c < 6; ++c) {
+          double E[3], B[3];
+          orc3_incident_eval(&S->inc, ((double)i + 0.5 * STAG3[c][0]) * S->g.dx,
+                             ((double)j + 0.5 * STAG3[c][1]) * S->g.dy,
+                             ((double)k + 0.5 * STAG3[c][2]) * S->g.dz,
+                             c < 3 ? tE : tB, E, B);
+          const double v = A3(S, S->f[c], i + G, j + G, k + G) +
+                           (c < 3 ? E[c] : B[c - 3]);
+          w += 0.5 * v * v;
+        }
+  return w * S->g.dx * S->g.dy * S->g.dz;
+}
+
 /* Energy-angle histogram of species sp (weights w dV), energy bins over
  * [0, emax) linear, angle from +x over [0, 180] degrees; mom = {sum w, <Ek>,
  * <Ek^2>, <theta>, <theta^2>} over particles with Ek > ek_min. */

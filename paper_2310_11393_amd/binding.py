@@ -177,6 +177,7 @@ EXPORTS = ["sfpic_create", "sfpic_step", "sfpic_sync", "sfpic_read_field",
            "sfpic_april_field", "sfpic_april_power",
            "sfpic3_create", "sfpic3_step", "sfpic3_sync", "sfpic3_dims",
            "sfpic3_read_field", "sfpic3_write_field",
+           "sfpic3_read_total_field",
            "sfpic3_particle_count", "sfpic3_read_particles",
            "sfpic3_diagnostics", "sfpic3_histogram", "sfpic3_get_state",
            "sfpic3_set_state", "sfpic3_destroy"]
@@ -237,6 +238,7 @@ def lib():
     L.sfpic3_dims.argtypes = [vp, C.POINTER(i64)]
     L.sfpic3_read_field.argtypes = [vp, C.c_int, _DP, sz]
     L.sfpic3_write_field.argtypes = [vp, C.c_int, _DP, sz]
+    L.sfpic3_read_total_field.argtypes = [vp, C.c_int, _DP, sz]
     L.sfpic3_particle_count.argtypes = [vp, C.c_int, C.POINTER(i64)]
     L.sfpic3_read_particles.argtypes = [vp, C.c_int] + [_DP] * 6 + \
         [C.POINTER(C.c_uint8), sz]
@@ -810,6 +812,14 @@ class Simulation3:
         if a.shape != self.shape:
             raise ValueError(f"field must have shape {self.shape}")
         _check(lib().sfpic3_write_field(self.h, c, _dp(a), a.size))
+
+    def total_field(self, comp) -> np.ndarray:
+        """Scattered plus incident field of one E or B component at its Yee
+        nodes (E at t^n, B at t^{n-1/2}), shape (NZ, NY, NX)."""
+        c = COMP[comp] if isinstance(comp, str) else int(comp)
+        out = np.empty(self.shape)
+        _check(lib().sfpic3_read_total_field(self.h, c, _dp(out), out.size))
+        return out
 
     def particles(self, sp=0):
         """(x, y, z, ux, uy, uz, alive) of every slot in creation order."""

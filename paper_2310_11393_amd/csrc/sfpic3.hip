@@ -739,6 +739,82 @@ gauss3(F3<R> f, Geo g, const double *rho, const double *rho0, double ihx,
   atomicMax(mx + 1, (unsigned long long)__double_as_longlong(fabs(dr)));
 }
 
+// Half-cell offsets (0 or 1/2) of Ex Ey Ez Bx By Bz along x, y, z, the field
+// pointer of component c and the matching incident component, as select
+// chains (a run-time index would put the arrays in private memory).
+__device__ __forceinline__ void stag3(int c, double &hx, double &hy,
+                                      double &hz) {
+  hx = (c == 0 || c == 4 || c == 5) ? 0.5 : 0.0;
+  hy = (c == 1 || c == 3 || c == 5) ? 0.5 : 0.0;
+  hz = (c == 2 || c == 3 || c == 4) ? 0.5 : 0.0;
+}
+
+template <typename R>
+__device__ __forceinline__ const R *comp3(const F3<R> &f, int c) {
+  return c == 0   ? f.e[0]
+         : c == 1 ? f.e[1]
+         : c == 2 ? f.e[2]
+         : c == 3 ? f.b[0]
+         : c == 4 ? f.b[1]
+                  : f.b[2];
+}
+
+__device__ __forceinline__ double pick3(int c, const double E[3],
+                                        const double B[3]) {
+  return c == 0   ? E[0]
+         : c == 1 ? E[1]
+         : c == 2 ? E[2]
+         : c == 3 ? B[0]
+         : c == 4 ? B[1]
+                  : B[2];
+}
+
+// acc[4] += 1/2 sum over the physical nodes (i, j, k < nx, ny, nz) of
+// |F_scatt + F_inc|^2 over the six components, each at its own Yee node, E at
+// tE = t^n and B at tB = t^{n-1/2}, the incident field in FP64 (the energy of
+// the total field, Sec. 2).  Grid (ceil(nx / 256), ny, nz).
+template <typename R>
+__global__ void __launch_bounds__(256)
+em_total3(F3<R> f, Geo g, IncParams inc, double z_focus, double dx, double dy,
+          double dz, double tE, double tB, double *acc) {
+  __shared__ double sh[4];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y, k = blockIdx.z;
+  double e = 0.0;
+  if (i < g.nx) {
+    const size_t n = g.at(i + G, j + G, k + G);
+#pragma unroll 1
+    for (int c = 0; c < 6; ++c) {
+      double hx, hy, hz, E[3], B[3];
+      stag3(c, hx, hy, hz);
+      incident3(inc, z_focus, (i + hx) * dx, (j + hy) * dy, (k + hz) * dz,
+                c < 3 ? tE : tB, E, B);
+      const double v = ld(comp3(f, c), n) + pick3(c, E, B);
+      e += 0.5 * v * v;
+    }
+  }
+  e = block_sum(e, sh);
+  if (threadIdx.x == 0) atomicAdd(acc + 4, e);
+}
+
+// dst = F_scatt + F_inc of component c (0..5) at every array element, its
+// node at ((i - G) + hx) dx, ((j - G) + hy) dy, ((k - G) + hz) dz, time t; FP64.
+// Grid (ceil(NX / 256), NY, NZ).
+template <typename R>
+__global__ void __launch_bounds__(256)
+total_field3(F3<R> f, Geo g, IncParams inc, double z_focus, int c, double dx,
+             double dy, double dz, double t, double *dst) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y, k = blockIdx.z;
+  if (i >= g.NX) return;
+  const size_t n = g.at(i, j, k);
+  double hx, hy, hz, E[3], B[3];
+  stag3(c, hx, hy, hz);
+  incident3(inc, z_focus, (i - G + hx) * dx, (j - G + hy) * dy,
+            (k - G + hz) * dz, t, E, B);
+  dst[n] = ld(comp3(f, c), n) + pick3(c, E, B);
+}
+
 // Energy-angle histogram of live particles (weights w dV): linear kinetic
 // energy bins over [0, emax), angle from +x in [0, 180] degrees; moments
 // {sum w, w E_k, w E_k^2, w theta, w theta^2} over E_k > ek_min.
@@ -1390,7 +1466,53 @@ int sfpic3_diagnostics(sfpic3_sim *sim, sfpic_diag *out) {
   int fl = 0;
   memcpy(&fl, &host[7], sizeof(int));
   out->nonfinite |= fl;
-  out->w_em_total = NAN;  // not evaluated in 3D
+  // energy of the total field (scattered + incident) on the physical nodes
+  HIP3(hipMemsetAsync(S->acc + 4, 0, 8, S->st));
+  {
+    const double tE = (double)S->step * g.dt, tB = tE - 0.5 * g.dt;
+    const dim3 grid3((g.nx + 255) / 256, g.ny, g.nz);
+    if (S->fp32)
+      em_total3<float><<<grid3, 256, 0, S->st>>>(
+          fields_as<float>(S->f), S->g, S->inc, S->z_focus, g.dx, g.dy, g.dz,
+          tE, tB, S->acc);
+    else
+      em_total3<double><<<grid3, 256, 0, S->st>>>(
+          S->f, S->g, S->inc, S->z_focus, g.dx, g.dy, g.dz, tE, tB, S->acc);
+    HIP3(hipGetLastError());
+  }
+  HIP3(hipMemcpyAsync(host.data(), S->acc, 64, hipMemcpyDeviceToHost, S->st));
+  HIP3(hipStreamSynchronize(S->st));
+  out->w_em_total = host[4] * dV;
+  return SFPIC_OK;
+}
+
+int sfpic3_read_total_field(sfpic3_sim *sim, int comp, double *out,
+                            size_t n) {
+  if (!sim || !out) return sfpic::fail(SFPIC_E_INVAL, "NULL argument");
+  if (comp < 0 || comp >= 6)
+    return sfpic::fail(SFPIC_E_INVAL, "component must be E or B");
+  sfpic3_sim *S = sim;
+  const Geo &g = S->g;
+  if (n != (size_t)g.NX * g.NY * g.NZ)
+    return sfpic::fail(SFPIC_E_SIZE, "field buffer must hold NX*NY*NZ values");
+  const sfpic3_grid &gr = S->grid;
+  const double tE = (double)S->step * gr.dt;
+  const double t = comp < 3 ? tE : tE - 0.5 * gr.dt;
+  const dim3 grid3((g.NX + 255) / 256, g.NY, g.NZ);
+  // S->rho is FP64 scratch of one field array; the charge diagnostics clear
+  // and refill it before every use
+  if (S->fp32)
+    total_field3<float><<<grid3, 256, 0, S->st>>>(
+        fields_as<float>(S->f), g, S->inc, S->z_focus, comp, gr.dx, gr.dy,
+        gr.dz, t, S->rho);
+  else
+    total_field3<double><<<grid3, 256, 0, S->st>>>(
+        S->f, g, S->inc, S->z_focus, comp, gr.dx, gr.dy, gr.dz, t, S->rho);
+  HIP3(hipGetLastError());
+  HIP3(hipMemcpy2DAsync(out, (size_t)g.NX * 8, S->rho, (size_t)g.P * 8,
+                        (size_t)g.NX * 8, (size_t)g.NY * g.NZ,
+                        hipMemcpyDeviceToHost, S->st));
+  HIP3(hipStreamSynchronize(S->st));
   return SFPIC_OK;
 }
 

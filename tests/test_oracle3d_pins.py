@@ -256,3 +256,22 @@ def test_energy_angle_histogram_of_known_particles():
     assert math.isclose(mom[0], 4 * w * dV, rel_tol=1e-15)
     assert math.isclose(mom[1], ek.mean(), rel_tol=1e-14)
     assert math.isclose(mom[3], th.mean(), rel_tol=1e-14)
+
+
+def test_total_field_energy_of_a_plane_pulse():
+    """The 3D total-field energy of the plane pulse inside the box is its
+    closed-form integral, a0^2 (1/2) sqrt(pi / alpha) (1 - exp(-1 / alpha))
+    with alpha = 8 ln 2 / FWHM^2, times the cross-section ny dy nz dz, at
+    step 0 and after steps (no particles: the scattered field stays zero)."""
+    g = grid3(300, 3, 4, h=(0.2, 0.3, 0.25))
+    inc = NS(kind=1, a0=0.9, fwhm_t=2 * math.pi, t0=-30.0)
+    sim = O.OracleSim3(g, inc)
+    alpha = 8.0 * math.log(2.0) / (2 * math.pi) ** 2
+    want = 0.81 * 0.5 * math.sqrt(math.pi / alpha) * (
+        1.0 - math.exp(-1.0 / alpha)) * (3 * 0.3) * (4 * 0.25)
+    for steps in (0, 30):
+        sim.step(steps)
+        d = sim.diagnostics()
+        assert d["w_em"] == 0.0
+        assert abs(d["w_em_total"] - want) <= 1e-12 * want, \
+            (steps, d["w_em_total"], want)

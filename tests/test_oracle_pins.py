@@ -809,3 +809,35 @@ def test_gauss2d_travels_along_x_at_c():
             dz = (oracle.incident_eval(inc, 2, z + h, 0.0, t)[0][1] -
                   oracle.incident_eval(inc, 2, z - h, 0.0, t)[0][1]) / (2 * h)
             assert abs(dt + dz) < 0.05 * max(abs(dt), 1e-2), (z, t)
+
+
+def _pulse_energy_per_area(a0, fwhm_t):
+    """Energy per unit transverse area of the plane pulse
+    a0 sin(phi) 2^(-4 phi^2 / FWHM^2) in E_y and B_z: 1/2 int (E^2 + B^2) =
+    a0^2 int sin^2(phi) exp(-alpha phi^2) dphi
+    = a0^2 (1/2) sqrt(pi / alpha) (1 - exp(-1 / alpha)),
+    alpha = 8 ln 2 / FWHM^2 (the Gaussian integral of cos 2 phi)."""
+    alpha = 8.0 * math.log(2.0) / fwhm_t ** 2
+    return a0 * a0 * 0.5 * math.sqrt(math.pi / alpha) * (
+        1.0 - math.exp(-1.0 / alpha))
+
+
+@pytest.mark.parametrize("dims", [1, 2])
+def test_total_field_energy_of_a_plane_pulse(dims):
+    """The total-field energy of the plane pulse wholly inside the box
+    equals its closed-form integral times the box's cross-section (the node
+    sums of a smooth, decaying field are spectrally accurate), before and
+    after steps: with no particles the scattered field stays zero."""
+    nx, ny, h = 400, 6, 0.2
+    grid = _grid(dims, nx, ny if dims == 2 else 1, h, h, 0.5 * h)
+    inc = wl.Incident(kind=wl.INC_PLANE_PULSE_1D, a0=1.7,
+                      fwhm_t=2 * math.pi, t0=-30.0)  # centre at x = 30
+    sim = OracleSim(grid, inc)
+    area = ny * h if dims == 2 else 1.0
+    want = _pulse_energy_per_area(1.7, 2 * math.pi) * area
+    for steps in (0, 40):
+        sim.step(steps)
+        d = sim.diagnostics()
+        assert d["w_em"] == 0.0
+        assert abs(d["w_em_total"] - want) <= 1e-12 * want, \
+            (steps, d["w_em_total"], want)
