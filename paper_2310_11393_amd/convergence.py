@@ -126,6 +126,26 @@ def quiet_profile_1d(grid, density: float, ppc: int, center: float,
                 uz=z)
 
 
+def _model_sim(grid, inc, model: str, **kw):
+    """A simulation of the given model: "sff", the scattered-field form
+    with incident `inc`, or "ff", model (i) started from inc's pulse on the
+    grid (the helper scattered-field run is released here)."""
+    from .binding import Simulation
+    sim = Simulation(grid, inc, **kw)
+    if model == "sff":
+        return sim
+    try:
+        ff = Simulation(grid, wl.Incident(kind=wl.INC_NONE), **kw)
+        try:
+            full_field_start(ff, sim)
+        except BaseException:
+            ff.close()
+            raise
+        return ff
+    finally:
+        sim.close()
+
+
 def refinement_study_1d(ms: Sequence[int], length: float, a0: float,
                         fwhm_t: float, t0: float, density: float, ppc: int,
                         center: float, fwhm: float, order: float,
@@ -143,7 +163,6 @@ def refinement_study_1d(ms: Sequence[int], length: float, a0: float,
     which needs the pulse inside the box at t = 0 (t0 < 0 places its centre
     at x = -t0).  Snapshot times must be multiples of the coarsest time step
     so that every resolution reaches them exactly."""
-    from .binding import Simulation
     if model not in ("sff", "ff"):
         raise ValueError("model must be 'sff' or 'ff'")
     m0 = min(ms)
@@ -156,33 +175,36 @@ def refinement_study_1d(ms: Sequence[int], length: float, a0: float,
         inc = wl.Incident(kind=wl.INC_PLANE_PULSE_1D, a0=a0, fwhm_t=fwhm_t,
                           t0=t0)
         e = quiet_profile_1d(grid, density, ppc, center, fwhm, order, xmin)
-        sim = Simulation(grid, inc, explicit=[e])
-        if model == "ff":
-            ff = Simulation(grid, wl.Incident(kind=wl.INC_NONE),
-                            explicit=[e])
-            full_field_start(ff, sim)
+        sim = _model_sim(grid, inc, model, explicit=[e])
+        try:
+            res = _snapshots_1d(sim, t_snap, dt0, m - m0, nx, h)
+        finally:
             sim.close()
-            sim = ff
-        done = 0
-        res = {}
-        for t in t_snap:
-            k0 = t / dt0
-            if abs(k0 - round(k0)) > 1e-9:
-                raise ValueError("snapshot times must be multiples of the "
-                                 "coarsest time step")
-            target = int(round(k0)) * 2 ** (m - m0)
-            sim.step(target - done)
-            done = target
-            d = sim.diagnostics()
-            res[t] = {"ex": sim.read_field("ex")[0],
-                      "ey": sim.read_field("ey")[0],
-                      "ex_total": sim.read_total_field("ex")[0],
-                      "ey_total": sim.read_total_field("ey")[0],
-                      "w_kin": d["w_kin"], "w_em": d["w_em_total"],
-                      "nx": nx, "h": h}
-        sim.close()
         out[m] = res
     return out
+
+
+def _snapshots_1d(sim, t_snap, dt0, dm, nx, h):
+    """Step sim to each snapshot time (2^dm steps per coarsest step dt0)
+    and record its rows and energies there."""
+    done = 0
+    res = {}
+    for t in t_snap:
+        k0 = t / dt0
+        if abs(k0 - round(k0)) > 1e-9:
+            raise ValueError("snapshot times must be multiples of the "
+                             "coarsest time step")
+        target = int(round(k0)) * 2 ** dm
+        sim.step(target - done)
+        done = target
+        d = sim.diagnostics()
+        res[t] = {"ex": sim.read_field("ex")[0],
+                  "ey": sim.read_field("ey")[0],
+                  "ex_total": sim.read_total_field("ex")[0],
+                  "ey_total": sim.read_total_field("ey")[0],
+                  "w_kin": d["w_kin"], "w_em": d["w_em_total"],
+                  "nx": nx, "h": h}
+    return res
 
 
 def study_norms(study: Dict[int, Dict[float, dict]], comp: str = "ey"
@@ -313,7 +335,6 @@ def refinement_study_2d(ms: Sequence[int], lx: float, ly: float, a0: float,
     the beam axis ("ey_axis", "ex_axis"), the energies ("w_kin", "w_em") and
     the cell counts and size.  model "sff" / "ff" as in the 1D study; the
     snapshot times must be multiples of the coarsest time step."""
-    from .binding import Simulation
     if model not in ("sff", "ff"):
         raise ValueError("model must be 'sff' or 'ff'")
     m0 = min(ms)
@@ -335,36 +356,40 @@ def refinement_study_2d(ms: Sequence[int], lx: float, ly: float, a0: float,
                                   profile=wl.PROFILE_SUPERGAUSS,
                                   profile_center=center, profile_fwhm=fwhm,
                                   profile_order=order, profile_xmin=xmin)]
-        sim = Simulation(grid, inc, species=species)
-        if model == "ff":
-            ff = Simulation(grid, wl.Incident(kind=wl.INC_NONE),
-                            species=species)
-            full_field_start(ff, sim)
+        sim = _model_sim(grid, inc, model, species=species)
+        try:
+            res = _snapshots_2d(sim, t_snap, dt0, m - m0, nx, ny, h,
+                                keep_planes)
+        finally:
             sim.close()
-            sim = ff
-        done = 0
-        res = {}
-        for t in t_snap:
-            k0 = t / dt0
-            if abs(k0 - round(k0)) > 1e-9:
-                raise ValueError("snapshot times must be multiples of the "
-                                 "coarsest time step")
-            target = int(round(k0)) * 2 ** (m - m0)
-            sim.step(target - done)
-            done = target
-            d = sim.diagnostics()
-            ey = sim.read_total_field("ey")
-            ex = sim.read_total_field("ex")
-            row = {"ey_axis": axis_row(ey, ny // 2, "ey"),
-                   "ex_axis": axis_row(ex, ny // 2, "ex"),
-                   "w_kin": d["w_kin"], "w_em": d["w_em_total"],
-                   "nx": nx, "ny": ny, "h": h}
-            if keep_planes:
-                row.update(ey_total=ey, ex_total=ex)
-            res[t] = row
-        sim.close()
         out[m] = res
     return out
+
+
+def _snapshots_2d(sim, t_snap, dt0, dm, nx, ny, h, keep_planes):
+    """As _snapshots_1d for the 2D study: axis rows, energies and, if
+    keep_planes, the total E_y and E_x planes."""
+    done = 0
+    res = {}
+    for t in t_snap:
+        k0 = t / dt0
+        if abs(k0 - round(k0)) > 1e-9:
+            raise ValueError("snapshot times must be multiples of the "
+                             "coarsest time step")
+        target = int(round(k0)) * 2 ** dm
+        sim.step(target - done)
+        done = target
+        d = sim.diagnostics()
+        ey = sim.read_total_field("ey")
+        ex = sim.read_total_field("ex")
+        row = {"ey_axis": axis_row(ey, ny // 2, "ey"),
+               "ex_axis": axis_row(ex, ny // 2, "ex"),
+               "w_kin": d["w_kin"], "w_em": d["w_em_total"],
+               "nx": nx, "ny": ny, "h": h}
+        if keep_planes:
+            row.update(ey_total=ey, ex_total=ex)
+        res[t] = row
+    return res
 
 
 def study_cross_errors_2d(study_i: Dict[int, Dict[float, dict]],
