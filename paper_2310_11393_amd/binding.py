@@ -821,6 +821,11 @@ class Simulation3:
         _check(lib().sfpic3_read_total_field(self.h, c, _dp(out), out.size))
         return out
 
+    # the single-simulation names, so helpers written for Simulation (for
+    # example convergence.full_field_start) take a Simulation3 as well
+    read_field = field
+    read_total_field = total_field
+
     def particles(self, sp=0):
         """(x, y, z, ux, uy, uz, alive) of every slot in creation order."""
         n = C.c_int64()

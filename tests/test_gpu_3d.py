@@ -358,3 +358,42 @@ def test_3d_checkpoint_resume(prec):
     other = Simulation3(wl.grid3(20, 16, 12), inc, explicit=[], precision=prec)
     with pytest.raises(SfpicError):
         other.set_state(st)
+
+
+def test_3d_full_field_start_matches_oracle():
+    """Model (i) of the Sec. 3.1 comparison in 3D: the April LP pulse's six
+    components written onto the grid at t = 0 (E) and -dt/2 (B) from the
+    library's total field, then carried by the solver with no incident
+    field, against the oracle started from its own samples of the pulse."""
+    from oracle import incident_eval3
+    from paper_2310_11393_amd import convergence as cv
+    from paper_2310_11393_amd.binding import Simulation3
+    g, inc, sp, _ = _case("lp3d")
+    inc = _inc(2, a0=2.0, w0=1.6, s=10.0, x_focus=10 * H, y_focus=8 * H,
+               z_focus=8 * H, t_focus=6 * g.dt)
+    sff = Simulation3(g, inc, explicit=sp)
+    ff = Simulation3(g, _inc(0), explicit=sp)
+    cv.full_field_start(ff, sff)
+    sff.close()
+    o = _oracle(g, _inc(0), sp)
+    Gd = 3
+    for ci, c in enumerate(FIELDS):
+        f = o.field(c)
+        NZ, NY, NX = f.shape
+        sx, sy, sz = STAG3[c]
+        t = -0.5 * g.dt if c[0] == "b" else 0.0
+        for k in range(NZ):
+            for j in range(NY):
+                for i in range(NX):
+                    E, B = incident_eval3(inc, (i - Gd + 0.5 * sx) * g.dx,
+                                          (j - Gd + 0.5 * sy) * g.dy,
+                                          (k - Gd + 0.5 * sz) * g.dz, t)
+                    f[k, j, i] = E[ci] if ci < 3 else B[ci - 3]
+    rel0, den0 = _rel(ff, o, FIELDS)
+    assert den0 > 0 and rel0 <= 1e-13, rel0
+    o.step(20)
+    ff.step(20)
+    rel, den = _rel(ff, o, FIELDS)
+    print(f"[3d ff] start {rel0:.2e}, after 20 steps {rel:.2e}", flush=True)
+    assert rel <= 1e-12, rel
+    _compare_particles(ff, o, len(sp), g)
