@@ -719,24 +719,46 @@ rho3(Parts3<R> p, int64_t n, Geo g, double qw, double *rho) {
 }
 
 // max |div_h E - (rho - rho0)| and max |rho - rho0| over nodes at least 4
-// cells inside the physical box (non-negative doubles order as integers)
+// cells inside the physical box (non-negative doubles order as integers).
+// The block reduces first and issues one atomic per maximum: an atomic per
+// node on two addresses serializes the whole grid.
 template <typename R>
 __global__ void __launch_bounds__(256)
 gauss3(F3<R> f, Geo g, const double *rho, const double *rho0, double ihx,
        double ihy, double ihz, unsigned long long *mx) {
+  __shared__ double sh[2][4];
   const int i = blockIdx.x * 64 + threadIdx.x, j = blockIdx.y * 4 + threadIdx.y,
             k = blockIdx.z;
   const int lo = G + 4;
-  if (i < lo || j < lo || k < lo || i > G + g.nx - 4 || j > G + g.ny - 4 ||
-      k > G + g.nz - 4)
-    return;
-  const size_t n = g.at(i, j, k), sj = g.P, sk = (size_t)g.P * g.NY;
-  const double div = (ld(f.e[0], n) - ld(f.e[0], n - 1)) * ihx +
-                     (ld(f.e[1], n) - ld(f.e[1], n - sj)) * ihy +
-                     (ld(f.e[2], n) - ld(f.e[2], n - sk)) * ihz;
-  const double dr = rho[n] - rho0[n];
-  atomicMax(mx, (unsigned long long)__double_as_longlong(fabs(div - dr)));
-  atomicMax(mx + 1, (unsigned long long)__double_as_longlong(fabs(dr)));
+  double res = 0.0, drm = 0.0;
+  if (!(i < lo || j < lo || k < lo || i > G + g.nx - 4 || j > G + g.ny - 4 ||
+        k > G + g.nz - 4)) {
+    const size_t n = g.at(i, j, k), sj = g.P, sk = (size_t)g.P * g.NY;
+    const double div = (ld(f.e[0], n) - ld(f.e[0], n - 1)) * ihx +
+                       (ld(f.e[1], n) - ld(f.e[1], n - sj)) * ihy +
+                       (ld(f.e[2], n) - ld(f.e[2], n - sk)) * ihz;
+    const double dr = rho[n] - rho0[n];
+    res = fabs(div - dr);
+    drm = fabs(dr);
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    res = fmax(res, __shfl_down(res, o, 64));
+    drm = fmax(drm, __shfl_down(drm, o, 64));
+  }
+  // blockDim (64, 4): wave w is row threadIdx.y
+  if (threadIdx.x == 0) {
+    sh[0][threadIdx.y] = res;
+    sh[1][threadIdx.y] = drm;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0 && threadIdx.y == 0) {
+    for (int w = 1; w < 4; ++w) {
+      res = fmax(res, sh[0][w]);
+      drm = fmax(drm, sh[1][w]);
+    }
+    atomicMax(mx, (unsigned long long)__double_as_longlong(res));
+    atomicMax(mx + 1, (unsigned long long)__double_as_longlong(drm));
+  }
 }
 
 // Half-cell offsets (0 or 1/2) of Ex Ey Ez Bx By Bz along x, y, z, the field
