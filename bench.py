@@ -405,9 +405,10 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
-              "(the domain decomposition is described in DESIGN.md); "
-              "run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU: the library runs a simulation "
+              "on one GPU and has no path across GPUs (sweeps would place "
+              "whole members per GPU, one large run would split into "
+              "slabs); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch
