@@ -718,6 +718,8 @@ rho3(Parts3<R> p, int64_t n, Geo g, double qw, double *rho) {
                   qw * w[0][aa] * w[1][bb] * w[2][c]);
 }
 
+constexpr int kGaussPlanes = 8;
+
 // max |div_h E - (rho - rho0)| and max |rho - rho0| over nodes at least 4
 // cells inside the physical box (non-negative doubles order as integers).
 // The block reduces first and issues one atomic per maximum: an atomic per
@@ -727,19 +729,22 @@ __global__ void __launch_bounds__(256)
 gauss3(F3<R> f, Geo g, const double *rho, const double *rho0, double ihx,
        double ihy, double ihz, unsigned long long *mx) {
   __shared__ double sh[2][4];
-  const int i = blockIdx.x * 64 + threadIdx.x, j = blockIdx.y * 4 + threadIdx.y,
-            k = blockIdx.z;
+  const int i = blockIdx.x * 64 + threadIdx.x, j = blockIdx.y * 4 + threadIdx.y;
   const int lo = G + 4;
   double res = 0.0, drm = 0.0;
-  if (!(i < lo || j < lo || k < lo || i > G + g.nx - 4 || j > G + g.ny - 4 ||
-        k > G + g.nz - 4)) {
+  // each block covers kGaussPlanes consecutive z-planes
+  for (int kk = 0; kk < kGaussPlanes; ++kk) {
+    const int k = blockIdx.z * kGaussPlanes + kk;
+    if (i < lo || j < lo || k < lo || i > G + g.nx - 4 || j > G + g.ny - 4 ||
+        k > G + g.nz - 4)
+      continue;
     const size_t n = g.at(i, j, k), sj = g.P, sk = (size_t)g.P * g.NY;
     const double div = (ld(f.e[0], n) - ld(f.e[0], n - 1)) * ihx +
                        (ld(f.e[1], n) - ld(f.e[1], n - sj)) * ihy +
                        (ld(f.e[2], n) - ld(f.e[2], n - sk)) * ihz;
     const double dr = rho[n] - rho0[n];
-    res = fabs(div - dr);
-    drm = fabs(dr);
+    res = fmax(res, fabs(div - dr));
+    drm = fmax(drm, fabs(dr));
   }
   for (int o = 32; o > 0; o >>= 1) {
     res = fmax(res, __shfl_down(res, o, 64));
@@ -951,6 +956,12 @@ namespace {
 dim3 node_grid(const Geo &g) {
   return dim3((unsigned)((g.NX + 63) / 64), (unsigned)((g.NY + 3) / 4),
               (unsigned)g.NZ);
+}
+
+// node_grid with kGaussPlanes z-planes per block
+dim3 gauss_grid(const Geo &g) {
+  const dim3 d = node_grid(g);
+  return dim3(d.x, d.y, (unsigned)((g.NZ + kGaussPlanes - 1) / kGaussPlanes));
 }
 
 unsigned blocks_for(int64_t n) { return (unsigned)((n + 255) / 256); }
@@ -1467,11 +1478,11 @@ int sfpic3_diagnostics(sfpic3_sim *sim, sfpic_diag *out) {
   if (int r = deposit_rho(S, S->rho)) return r;
   unsigned long long *mx = (unsigned long long *)(S->acc + 2);
   if (S->fp32)
-    gauss3<float><<<node_grid(S->g), dim3(64, 4), 0, S->st>>>(
+    gauss3<float><<<gauss_grid(S->g), dim3(64, 4), 0, S->st>>>(
         fields_as<float>(S->f), S->g, S->rho, S->rho0, 1.0 / g.dx,
         1.0 / g.dy, 1.0 / g.dz, mx);
   else
-    gauss3<double><<<node_grid(S->g), dim3(64, 4), 0, S->st>>>(
+    gauss3<double><<<gauss_grid(S->g), dim3(64, 4), 0, S->st>>>(
         S->f, S->g, S->rho, S->rho0, 1.0 / g.dx, 1.0 / g.dy, 1.0 / g.dz, mx);
   HIP3(hipGetLastError());
   HIP3(hipMemcpyAsync(host.data(), S->acc, 64, hipMemcpyDeviceToHost, S->st));
