@@ -659,17 +659,39 @@ template <typename R>
 __global__ void gauss_kernel(Fields<R> f, int dims, int nx, int ny,
                              double idx, double idy, const double *rho,
                              const double *rho0, int rp, double *acc) {
+  // 256 threads: the block takes the maxima first and issues one atomic for
+  // each (an atomic per node on two addresses serializes the grid)
+  __shared__ double sh[2][4];
   const int i = blockIdx.x * blockDim.x + threadIdx.x + 4;
   const int j = (dims == 2) ? blockIdx.y + 4 : 0;
-  if (i > nx - 4) return;
-  const int I = i + kGuard, J = (dims == 2) ? j + kGuard : 0;
-  const size_t k = (size_t)J * f.pitch + I;
-  double div = ((double)f.ex[k] - (double)f.ex[k - 1]) * idx;
-  if (dims == 2) div += ((double)f.ey[k] - (double)f.ey[k - f.pitch]) * idy;
-  const size_t kr = (size_t)J * rp + I;
-  const double dr = rho[kr] - rho0[kr];
-  atomic_max_pos(&acc[5], fabs(div - dr));
-  atomic_max_pos(&acc[6], fabs(dr));
+  double res = 0.0, drm = 0.0;
+  if (i <= nx - 4) {
+    const int I = i + kGuard, J = (dims == 2) ? j + kGuard : 0;
+    const size_t k = (size_t)J * f.pitch + I;
+    double div = ((double)f.ex[k] - (double)f.ex[k - 1]) * idx;
+    if (dims == 2) div += ((double)f.ey[k] - (double)f.ey[k - f.pitch]) * idy;
+    const size_t kr = (size_t)J * rp + I;
+    const double dr = rho[kr] - rho0[kr];
+    res = fabs(div - dr);
+    drm = fabs(dr);
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    res = fmax(res, __shfl_down(res, o, 64));
+    drm = fmax(drm, __shfl_down(drm, o, 64));
+  }
+  if ((threadIdx.x & 63) == 0) {
+    sh[0][threadIdx.x >> 6] = res;
+    sh[1][threadIdx.x >> 6] = drm;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < 4; ++w) {
+      res = fmax(res, sh[0][w]);
+      drm = fmax(drm, sh[1][w]);
+    }
+    atomic_max_pos(&acc[5], res);
+    atomic_max_pos(&acc[6], drm);
+  }
 }
 
 template <typename R>
