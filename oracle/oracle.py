@@ -44,11 +44,17 @@ _I = C.POINTER(C.c_int)
 def lib():
     global _lib
     if _lib is None:
-        path = os.path.join(_HERE, "liboracle.so")
-        srcs = [os.path.join(_HERE, f) for f in _build.SOURCES]
-        if not os.path.exists(path) or any(
-                os.path.getmtime(path) < os.path.getmtime(f) for f in srcs):
-            _build.build(force=True)
+        # SFPIC_ORACLE_LIB names another build of these sources (the CPU
+        # tests build copies with a mistake planted, to show that a pin
+        # catches it); the default is the in-tree library
+        path = os.environ.get("SFPIC_ORACLE_LIB")
+        if not path:
+            path = os.path.join(_HERE, "liboracle.so")
+            srcs = [os.path.join(_HERE, f) for f in _build.SOURCES]
+            if not os.path.exists(path) or any(
+                    os.path.getmtime(path) < os.path.getmtime(f)
+                    for f in srcs):
+                _build.build(force=True)
         L = C.CDLL(path)
         L.orc_april_ka_from_w0.restype = C.c_double
         L.orc_april_ka_from_w0.argtypes = [C.c_double]
