@@ -34,8 +34,8 @@
  *
  * Conventions shared by every call:
  *   - Every call returns SFPIC_OK (0) or a negative status; no C++ exception
- *     crosses the ABI.  sfpic_last_error() describes the last failure of the
- *     calling thread.
+ *     crosses the ABI.  sfpic_last_error(handle) describes the last failure
+ *     on a handle, sfpic_last_error(NULL) that of the calling thread.
  *   - Host buffers belong to the caller; inputs are read only during the call
  *     and outputs are written into caller-sized buffers (SFPIC_E_SIZE when
  *     the size does not match).
@@ -205,6 +205,19 @@ typedef struct {
                             B_inc(t^{n-1/2})|^2 dV over the physical nodes,
                             each component at its Yee node: energy of the
                             total field F_inc + F_scatt (Sec. 2)            */
+  /* Discrete continuity since the previous sfpic_diagnostics call on this
+   * sim (Sec. 2 and the charge-conserving deposition it names): with the
+   * per-node Gauss defect g^n = div_h E^n - (rho^n - rho_0), the maximum of
+   * |g^n - g^m| = |[div_h E^n - div_h E^m] - [rho^n - rho^m]| over the
+   * nodes of gauss_residual, m the step of that previous call; a field
+   * written in between (sfpic_write_field) enters it like any other change
+   * of E.  Zero, with continuity_steps = 0, on the first call and after
+   * sfpic_set_state or sfpic_set_step_index.  A non-finite value makes
+   * this and gauss_residual +inf.  3D: sfpic3_diagnostics, the same with
+   * the 3D divergence (the first call allocates one FP64 field array).    */
+  double continuity_residual;
+  double rho_abs_max;        /* max |rho^n| over the same nodes            */
+  int64_t continuity_steps;  /* n - m                                      */
 } sfpic_diag;
 
 typedef struct {
@@ -227,19 +240,27 @@ int sfpic_create(const sfpic_grid *grid, const sfpic_species *species,
                  sfpic_precision precision, const sfpic_runtime *runtime,
                  sfpic_sim **out);
 
-/* Enqueue nsteps >= 0 steps on the runtime stream (asynchronous). */
+/* Enqueue nsteps >= 0 steps on the runtime stream (asynchronous).  Each is
+ * the scattered-field step of Sec. 2 (operations and order at the top of
+ * this header: Yee update of F_scatt only, particles pushed in F_inc +
+ * F_scatt at their position, charge-conserving current into F_scatt).
+ * SFPIC_E_INVAL for nsteps < 0, SFPIC_E_DEVICE on a launch error. */
 int sfpic_step(sfpic_sim *sim, int64_t nsteps);
 
-/* Wait for all work queued on the sim's stream. */
+/* Wait for all work queued on the sim's stream (runtime plumbing; no
+ * passage of the paper defines it).  SFPIC_E_DEVICE if the work failed. */
 int sfpic_sync(sfpic_sim *sim);
 
 /* Copy one scattered-field component (SFPIC_EX .. SFPIC_JZ) to out, as
  * double, row-major [NY][NX] including guards; n must be NX * NY.  J holds
- * J^{n-1/2}, the current deposited by the last step. */
+ * J^{n-1/2}, the current deposited by the last step.  This is F_scatt, the
+ * only field the grid holds (Sec. 2); sfpic_read_total_field adds F_inc. */
 int sfpic_read_field(sfpic_sim *sim, int comp, double *out, size_t n);
 
 /* Overwrite one field component from a host array laid out as for
- * sfpic_read_field (for example to seed a run from an external state). */
+ * sfpic_read_field (for example to seed a run from an external state, such
+ * as the pulse written on the grid at t = 0 by the full-field comparison
+ * model of Sec. 3.1; Sec. 2 starts from a zero scattered field). */
 int sfpic_write_field(sfpic_sim *sim, int comp, const double *in, size_t n);
 
 /* Copy the total field F_scatt + F_inc (Sec. 2: the physical field, the
@@ -256,37 +277,48 @@ int sfpic_write_field(sfpic_sim *sim, int comp, const double *in, size_t n);
  * for J or a NULL out, SFPIC_E_SIZE unless n = NX NY. */
 int sfpic_read_total_field(sfpic_sim *sim, int comp, double *out, size_t n);
 
-/* Set the step counter n (the next step starts at t^n = n dt). */
+/* Set the step counter n (the next step starts at t^n = n dt, the time at
+ * which the Sec. 2 step evaluates F_inc at the particles). */
 int sfpic_set_step_index(sfpic_sim *sim, int64_t step);
 
-/* Number of live particles of a species. */
+/* Number of live macro-particles of a species (the particles of the
+ * Vlasov discretization, Sec. 2).  SFPIC_E_INVAL for a bad species. */
 int sfpic_particle_count(sfpic_sim *sim, int species, int64_t *n);
 
 /* Copy the live particles of a species (device order) as double, physical
- * units; id (nullable) receives each particle's creation index.  capacity
- * is the length of the caller's arrays; *n_out receives the count written
- * (SFPIC_E_SIZE if capacity is too small).  y may be NULL in 1D. */
+ * units (Table 1); id (nullable) receives each particle's creation index.
+ * capacity is the length of the caller's arrays; *n_out receives the count
+ * written (SFPIC_E_SIZE if capacity is too small).  y may be NULL in 1D. */
 int sfpic_read_particles(sfpic_sim *sim, int species, double *x, double *y,
                          double *ux, double *uy, double *uz, uint32_t *id,
                          size_t capacity, size_t *n_out);
 
-/* FP64 global diagnostics (energies, charge, Gauss-law residual). */
+/* FP64 global diagnostics: the kinetic, scattered-EM and total-EM energies
+ * whose evolution Secs. 3.1 and 3.2 compare between resolutions and models,
+ * the charge, and the Gauss-law and discrete-continuity residuals of the
+ * charge-conserving deposition that Sec. 2 names (units of Table 1).  See
+ * sfpic_diag for each quantity.  SFPIC_E_INVAL for a NULL out. */
 int sfpic_diagnostics(sfpic_sim *sim, sfpic_diag *out);
 
 /* Energy-angle histogram of a species (weights w dV), out has
  * n_energy * n_theta doubles [energy][theta]; moments (nullable) receives
  * {sum of weights, <E_k>, <E_k^2>, <theta>, <theta^2>} (theta in degrees)
- * over particles with E_k > ek_min. */
+ * over particles with E_k > ek_min.  These are the electron energy spectra
+ * against the angle from the propagation axis of Secs. 4.2 and 4.3.
+ * SFPIC_E_INVAL for a bad spec, SFPIC_E_SIZE unless n = n_energy n_theta,
+ * SFPIC_E_NOMEM if its device buffer cannot be allocated. */
 int sfpic_histogram(sfpic_sim *sim, const sfpic_hist_spec *spec,
                     double *out, size_t n, double *moments);
 
 /* Checkpoint: serialize the full state (fields, particles, step) into buf.
  * With buf == NULL, *n receives the size needed.  Otherwise *n is the
- * buffer size on input and the size written on output. */
+ * buffer size on input and the size written on output (SFPIC_E_SIZE when
+ * it is too small).  Runtime plumbing: no passage of the paper defines it. */
 int sfpic_get_state(sfpic_sim *sim, void *buf, size_t *n);
 
 /* Restore a state produced by sfpic_get_state of a sim with the same grid,
- * precision and species count. */
+ * precision and species count (SFPIC_E_INVAL otherwise, SFPIC_E_SIZE for a
+ * truncated buffer).  Runtime plumbing, as sfpic_get_state. */
 int sfpic_set_state(sfpic_sim *sim, const void *buf, size_t n);
 
 /* Per-kernel timing.  While profiling is on, every kernel launch of the
@@ -300,17 +332,19 @@ typedef struct {
   double total_ms[SFPIC_KCLASSES];
 } sfpic_kernel_stats;
 
-/* Start (enable != 0) or stop profiling; starting clears the counters. */
+/* Start (enable != 0) or stop profiling; starting clears the counters
+ * (measurement plumbing; no passage of the paper defines it). */
 int sfpic_profile(sfpic_sim *sim, int enable);
 
 /* Wait for the stream and return the accumulated per-class launch counts
  * and summed kernel durations since profiling was last started. */
 int sfpic_profile_read(sfpic_sim *sim, sfpic_kernel_stats *out);
 
-/* Release the sim and its device memory (waits for queued work). */
+/* Release the sim and its device memory (waits for queued work; NULL is
+ * ignored).  Runtime plumbing. */
 void sfpic_destroy(sfpic_sim *sim);
 
-/* Device memory held by the sim, in bytes. */
+/* Device memory held by the sim, in bytes (runtime plumbing). */
 int sfpic_device_bytes(sfpic_sim *sim, size_t *bytes);
 
 /* ---------------------------------------------------------------------------
@@ -380,7 +414,9 @@ int sfpic_desc_footprint(const sfpic_sim_desc *desc, const sfpic_runtime *rt,
 
 typedef struct sfpic_batch sfpic_batch;
 
-/* Create the n members (placing their particles).  rt->stream NULL: the
+/* The sweep of Secs. 3 and 4 (focusing, polarization and density varied
+ * over one set-up), each member the Sec. 2 step.
+ * Create the n members (placing their particles).  rt->stream NULL: the
  * batch creates its own stream.  Tile: rt->tile_x, tile_y if given,
  * otherwise chosen by the autotuner in the first steps of sfpic_batch_run
  * (runs of 128 steps or more, unless SFPIC_RT_NO_AUTOTUNE).  Sort cadence:
@@ -388,10 +424,15 @@ typedef struct sfpic_batch sfpic_batch;
 int sfpic_batch_create(int n, const sfpic_sim_desc *descs,
                        const sfpic_runtime *rt, sfpic_batch **out);
 
-/* Run every member to its nsteps and compute the results (blocking). */
+/* Run every member to its nsteps and compute the results (blocking).  A
+ * member whose fields or momenta stop being finite ends with status
+ * SFPIC_E_NUMERIC in its result and does not affect the others; the call
+ * itself then still returns SFPIC_OK (device errors return SFPIC_E_DEVICE). */
 int sfpic_batch_run(sfpic_batch *batch);
 
-/* Result of member i after sfpic_batch_run. */
+/* Result of member i after sfpic_batch_run (FP64 diagnostics and the
+ * energy-angle moments of Secs. 4.2 and 4.3).  SFPIC_E_STATE before the
+ * run, SFPIC_E_INVAL for a bad index. */
 int sfpic_batch_result(sfpic_batch *batch, int i, sfpic_result *out);
 
 /* Borrowed handle of member i (fields, particles, histograms through the
@@ -420,7 +461,10 @@ typedef struct {
   int64_t graph_launches;
 } sfpic_batch_info;
 
+/* Group, tile, cadence and autotuner record of the batch (measurement
+ * plumbing; no passage of the paper defines it). */
 int sfpic_batch_stats(sfpic_batch *batch, sfpic_batch_info *out);
+/* Release every member and the batch (NULL is ignored). */
 void sfpic_batch_destroy(sfpic_batch *batch);
 
 /* ---------------------------------------------------------------------------
@@ -458,12 +502,15 @@ typedef struct {
 int sfpic_server_create(size_t hbm_budget, int max_slots,
                         const sfpic_runtime *rt, sfpic_server **out);
 
-/* Queue a request (desc and its arrays are copied).  SFPIC_E_INVAL if it is
- * invalid or could never fit the budget. */
+/* Queue a request (desc and its arrays are copied): one member of the
+ * Secs. 3 and 4 sweep, the Sec. 2 step run for desc->nsteps.  SFPIC_E_INVAL
+ * if it is invalid or could never fit the budget.  A request that goes
+ * non-finite while it runs ends SFPIC_REQ_FAILED with status
+ * SFPIC_E_NUMERIC; the others are unaffected. */
 int sfpic_server_submit(sfpic_server *srv, const sfpic_sim_desc *desc,
                         uint64_t *ticket);
 
-/* State of a request (SFPIC_REQ_*). */
+/* State of a request (SFPIC_REQ_*; SFPIC_E_INVAL for an unknown ticket). */
 int sfpic_server_poll(sfpic_server *srv, uint64_t ticket, int *state);
 
 /* Block until the request is done or failed, or timeout_s passes
@@ -474,10 +521,13 @@ int sfpic_server_wait(sfpic_server *srv, uint64_t ticket, double timeout_s);
 int sfpic_server_result(sfpic_server *srv, uint64_t ticket,
                         sfpic_result *out);
 
-/* The request's histogram (n = hist.n_energy * hist.n_theta). */
+/* The request's energy-angle histogram (Secs. 4.2 and 4.3; n =
+ * hist.n_energy * hist.n_theta, SFPIC_E_SIZE otherwise). */
 int sfpic_server_histogram(sfpic_server *srv, uint64_t ticket, double *out,
                            size_t n);
 
+/* Counts, latency percentiles and throughput of the server (measurement
+ * plumbing; no passage of the paper defines it). */
 int sfpic_server_stats(sfpic_server *srv, sfpic_server_info *out);
 
 /* Stop the loop (running requests are abandoned) and release everything. */
@@ -545,20 +595,25 @@ int sfpic3_create(const sfpic3_grid *grid, const sfpic3_species *species,
                   int nspecies, const sfpic_incident *incident,
                   sfpic_precision precision, const sfpic_runtime *runtime,
                   sfpic3_sim **out);
-/* Enqueue nsteps >= 0 steps on the runtime stream (asynchronous). */
+/* Enqueue nsteps >= 0 steps on the runtime stream (asynchronous): the
+ * Sec. 2 step in three dimensions, as Sec. 4 runs it.  SFPIC_E_INVAL for
+ * nsteps < 0 or a NULL sim. */
 int sfpic3_step(sfpic3_sim *sim, int64_t nsteps);
+/* Wait for the queued work (runtime plumbing). */
 int sfpic3_sync(sfpic3_sim *sim);
-/* out = {NX, NY, NZ}, the extents of host field arrays. */
+/* out = {NX, NY, NZ}, the extents of host field arrays (plumbing). */
 int sfpic3_dims(const sfpic3_sim *sim, int64_t out[3]);
-/* Copy one component (SFPIC_EX .. SFPIC_JZ) as [k][j][i]; n = NX NY NZ. */
+/* Copy one component (SFPIC_EX .. SFPIC_JZ) of the scattered field (the
+ * only field on the grid, Sec. 2) as [k][j][i]; n = NX NY NZ. */
 int sfpic3_read_field(sfpic3_sim *sim, int comp, double *out, size_t n);
-/* Overwrite E or B (SFPIC_EX .. SFPIC_BZ) from a host array as above. */
+/* Overwrite E or B (SFPIC_EX .. SFPIC_BZ) from a host array as above (an
+ * initial condition other than the zero field of Sec. 2). */
 int sfpic3_write_field(sfpic3_sim *sim, int comp, const double *in, size_t n);
-/* Number of particle slots of a species (live and removed). */
+/* Number of particle slots of a species (live and removed; Sec. 2). */
 int sfpic3_particle_count(sfpic3_sim *sim, int species, int64_t *n);
-/* Copy every slot of a species in creation order (physical units); alive[i]
- * is 0 for a removed particle, whose other values are meaningless.  n must
- * equal the slot count. */
+/* Copy every slot of a species in creation order (physical units, Table 1);
+ * alive[i] is 0 for a removed particle, whose other values are
+ * meaningless.  n must equal the slot count (SFPIC_E_SIZE otherwise). */
 int sfpic3_read_particles(sfpic3_sim *sim, int species, double *x, double *y,
                           double *z, double *ux, double *uy, double *uz,
                           uint8_t *alive, size_t n);
@@ -587,12 +642,18 @@ int sfpic3_histogram(sfpic3_sim *sim, const sfpic_hist_spec *spec,
  * species sizes (SFPIC_E_STATE otherwise). */
 int sfpic3_get_state(sfpic3_sim *sim, void *buf, size_t *n);
 int sfpic3_set_state(sfpic3_sim *sim, const void *buf, size_t n);
+/* Release the 3D simulation (NULL is ignored; runtime plumbing). */
 void sfpic3_destroy(sfpic3_sim *sim);
 
-/* Message of the last failing call on this thread ("" if none). */
-const char *sfpic_last_error(void);
+/* Message of the last failure on this handle (a sim, 3D sim, batch or
+ * server handle; "" if none), valid until the next call on the handle; a
+ * failure inside a call on a handle (for example of a batch member's
+ * diagnostics during sfpic_batch_run) is recorded for that handle too.
+ * handle NULL: the last failure of the calling thread in any call, which
+ * is how the failure of a create call is read. */
+const char *sfpic_last_error(const void *handle);
 
-/* Library version string. */
+/* Library version string (plumbing). */
 const char *sfpic_version(void);
 
 #ifdef __cplusplus

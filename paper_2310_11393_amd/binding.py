@@ -102,7 +102,10 @@ class sfpic_diag(C.Structure):
                 ("n_alive", C.c_int64), ("w_kin", C.c_double),
                 ("w_em", C.c_double), ("charge", C.c_double),
                 ("gauss_residual", C.c_double), ("rho_max", C.c_double),
-                ("nonfinite", C.c_int32), ("w_em_total", C.c_double)]
+                ("nonfinite", C.c_int32), ("w_em_total", C.c_double),
+                ("continuity_residual", C.c_double),
+                ("rho_abs_max", C.c_double),
+                ("continuity_steps", C.c_int64)]
 
 
 class sfpic_hist_spec(C.Structure):
@@ -254,6 +257,7 @@ def lib():
     L.sfpic_april_power.argtypes = [C.POINTER(sfpic_incident),
                                     C.POINTER(C.c_double)]
     L.sfpic_last_error.restype = C.c_char_p
+    L.sfpic_last_error.argtypes = [C.c_void_p]
     L.sfpic_version.restype = C.c_char_p
     D = C.POINTER(sfpic_sim_desc)
     RT = C.POINTER(sfpic_runtime)
@@ -281,7 +285,7 @@ def lib():
 
 def _check(code):
     if code != SFPIC_OK:
-        raise SfpicError(code, lib().sfpic_last_error().decode())
+        raise SfpicError(code, lib().sfpic_last_error(None).decode())
 
 
 def _dp(a):

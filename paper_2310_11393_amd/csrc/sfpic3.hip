@@ -32,6 +32,14 @@
 
 namespace sfpic {
 int fail(int code, const std::string &msg);
+// the calling entry point's handle, for sfpic_last_error(handle)
+struct ErrScope {
+  explicit ErrScope(const void *handle);
+  ~ErrScope();
+  ErrScope(const ErrScope &) = delete;
+  ErrScope &operator=(const ErrScope &) = delete;
+};
+void forget_handle(const void *handle);
 int prepare_incident_ext(const sfpic_incident *in, IncParams &P);
 int profile_offsets(int32_t profile, double center, double fwhm, double order,
                     double xmin, int64_t x0, int64_t x1, double dx, int ppc,
@@ -720,18 +728,27 @@ rho3(Parts3<R> p, int64_t n, Geo g, double qw, double *rho) {
 
 constexpr int kGaussPlanes = 8;
 
-// max |div_h E - (rho - rho0)| and max |rho - rho0| over nodes at least 4
-// cells inside the physical box (non-negative doubles order as integers).
-// The block reduces first and issues one atomic per maximum: an atomic per
-// node on two addresses serializes the whole grid.
+// max |div_h E - (rho - rho0)|, max |rho - rho0|, max |g - gprev| and max
+// |rho| over nodes at least 4 cells inside the physical box, with g = div_h
+// E - (rho - rho0) the per-node Gauss defect, stored into gprev for the next
+// call (have_prev: gprev holds the previous call's defect, whose difference
+// with g is the discrete continuity residual between the calls).  Maxima of
+// non-negative doubles order as integers; a NaN counts as +inf.  The block
+// reduces first and issues one atomic per maximum: an atomic per node on
+// two addresses serializes the whole grid.
+__device__ __forceinline__ double inf_if_nan3(double v) {
+  return isnan(v) ? __builtin_huge_val() : v;
+}
+
 template <typename R>
 __global__ void __launch_bounds__(256)
 gauss3(F3<R> f, Geo g, const double *rho, const double *rho0, double ihx,
-       double ihy, double ihz, unsigned long long *mx) {
-  __shared__ double sh[2][4];
+       double ihy, double ihz, double *gprev, int have_prev,
+       unsigned long long *mx, unsigned long long *mx2) {
+  __shared__ double sh[4][4];
   const int i = blockIdx.x * 64 + threadIdx.x, j = blockIdx.y * 4 + threadIdx.y;
   const int lo = G + 4;
-  double res = 0.0, drm = 0.0;
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
   // each block covers kGaussPlanes consecutive z-planes
   for (int kk = 0; kk < kGaussPlanes; ++kk) {
     const int k = blockIdx.z * kGaussPlanes + kk;
@@ -743,26 +760,26 @@ gauss3(F3<R> f, Geo g, const double *rho, const double *rho0, double ihx,
                        (ld(f.e[1], n) - ld(f.e[1], n - sj)) * ihy +
                        (ld(f.e[2], n) - ld(f.e[2], n - sk)) * ihz;
     const double dr = rho[n] - rho0[n];
-    res = fmax(res, fabs(div - dr));
-    drm = fmax(drm, fabs(dr));
+    const double gd = div - dr;
+    v[0] = fmax(v[0], inf_if_nan3(fabs(gd)));
+    v[1] = fmax(v[1], inf_if_nan3(fabs(dr)));
+    if (have_prev) v[2] = fmax(v[2], inf_if_nan3(fabs(gd - gprev[n])));
+    v[3] = fmax(v[3], inf_if_nan3(fabs(rho[n])));
+    gprev[n] = gd;
   }
-  for (int o = 32; o > 0; o >>= 1) {
-    res = fmax(res, __shfl_down(res, o, 64));
-    drm = fmax(drm, __shfl_down(drm, o, 64));
-  }
+  for (int o = 32; o > 0; o >>= 1)
+    for (int q = 0; q < 4; ++q) v[q] = fmax(v[q], __shfl_down(v[q], o, 64));
   // blockDim (64, 4): wave w is row threadIdx.y
-  if (threadIdx.x == 0) {
-    sh[0][threadIdx.y] = res;
-    sh[1][threadIdx.y] = drm;
-  }
+  if (threadIdx.x == 0)
+    for (int q = 0; q < 4; ++q) sh[q][threadIdx.y] = v[q];
   __syncthreads();
   if (threadIdx.x == 0 && threadIdx.y == 0) {
-    for (int w = 1; w < 4; ++w) {
-      res = fmax(res, sh[0][w]);
-      drm = fmax(drm, sh[1][w]);
-    }
-    atomicMax(mx, (unsigned long long)__double_as_longlong(res));
-    atomicMax(mx + 1, (unsigned long long)__double_as_longlong(drm));
+    for (int w = 1; w < 4; ++w)
+      for (int q = 0; q < 4; ++q) v[q] = fmax(v[q], sh[q][w]);
+    atomicMax(mx, (unsigned long long)__double_as_longlong(v[0]));
+    atomicMax(mx + 1, (unsigned long long)__double_as_longlong(v[1]));
+    atomicMax(mx2, (unsigned long long)__double_as_longlong(v[2]));
+    atomicMax(mx2 + 1, (unsigned long long)__double_as_longlong(v[3]));
   }
 }
 
@@ -909,6 +926,10 @@ struct sfpic3_sim {
   uint32_t *rank = nullptr;  // per slot, sized for the largest species
   std::vector<Species3> sp;
   double *rho0 = nullptr, *rho = nullptr, *acc = nullptr;
+  // per-node Gauss defect of the last diagnostics call (allocated by the
+  // first call) and its step (-1: none, or the state has changed since)
+  double *gprev = nullptr;
+  int64_t gprev_step = -1;
   std::vector<std::pair<void *, size_t>> allocs;
 
   void *dalloc(size_t bytes) {
@@ -1206,7 +1227,7 @@ int sfpic3_create(const sfpic3_grid *grid, const sfpic3_species *species,
   }
   S->rho0 = (double *)S->dalloc(S->plane * 8);
   S->rho = (double *)S->dalloc(S->plane * 8);
-  S->acc = (double *)S->dalloc(64);
+  S->acc = (double *)S->dalloc(128);
   if (!S->rho0 || !S->rho || !S->acc)
     return fail_free(SFPIC_E_NOMEM, "diagnostic allocation failed");
   std::vector<uint32_t> off;  // column offsets of a density profile
@@ -1312,6 +1333,7 @@ int sfpic3_create(const sfpic3_grid *grid, const sfpic3_species *species,
 }
 
 int sfpic3_step(sfpic3_sim *sim, int64_t nsteps) {
+  sfpic::ErrScope es_(sim);
   if (!sim || nsteps < 0) return sfpic::fail(SFPIC_E_INVAL, "bad step call");
   for (int64_t k = 0; k < nsteps; ++k)
     if (int r = one_step(sim)) return r;
@@ -1319,12 +1341,14 @@ int sfpic3_step(sfpic3_sim *sim, int64_t nsteps) {
 }
 
 int sfpic3_sync(sfpic3_sim *sim) {
+  sfpic::ErrScope es_(sim);
   if (!sim) return sfpic::fail(SFPIC_E_INVAL, "sim is NULL");
   HIP3(hipStreamSynchronize(sim->st));
   return SFPIC_OK;
 }
 
 int sfpic3_dims(const sfpic3_sim *sim, int64_t out[3]) {
+  sfpic::ErrScope es_(sim);
   if (!sim || !out) return sfpic::fail(SFPIC_E_INVAL, "NULL argument");
   out[0] = sim->g.NX;
   out[1] = sim->g.NY;
@@ -1340,6 +1364,7 @@ static double *comp_ptr(sfpic3_sim *S, int comp) {
 }
 
 int sfpic3_read_field(sfpic3_sim *sim, int comp, double *out, size_t n) {
+  sfpic::ErrScope es_(sim);
   if (!sim || !out) return sfpic::fail(SFPIC_E_INVAL, "NULL argument");
   double *src = comp_ptr(sim, comp);
   if (!src) return sfpic::fail(SFPIC_E_INVAL, "bad field component");
@@ -1363,6 +1388,7 @@ int sfpic3_read_field(sfpic3_sim *sim, int comp, double *out, size_t n) {
 }
 
 int sfpic3_write_field(sfpic3_sim *sim, int comp, const double *in, size_t n) {
+  sfpic::ErrScope es_(sim);
   if (!sim || !in) return sfpic::fail(SFPIC_E_INVAL, "NULL argument");
   if (comp < 0 || comp >= 6)
     return sfpic::fail(SFPIC_E_INVAL, "only E and B can be written");
@@ -1386,6 +1412,7 @@ int sfpic3_write_field(sfpic3_sim *sim, int comp, const double *in, size_t n) {
 }
 
 int sfpic3_particle_count(sfpic3_sim *sim, int species, int64_t *n) {
+  sfpic::ErrScope es_(sim);
   if (!sim || !n) return sfpic::fail(SFPIC_E_INVAL, "NULL argument");
   if (species < 0 || species >= (int)sim->sp.size())
     return sfpic::fail(SFPIC_E_INVAL, "bad species index");
@@ -1396,6 +1423,7 @@ int sfpic3_particle_count(sfpic3_sim *sim, int species, int64_t *n) {
 int sfpic3_read_particles(sfpic3_sim *sim, int species, double *x, double *y,
                           double *z, double *ux, double *uy, double *uz,
                           uint8_t *alive, size_t n) {
+  sfpic::ErrScope es_(sim);
   if (!sim || !x || !y || !z || !ux || !uy || !uz || !alive)
     return sfpic::fail(SFPIC_E_INVAL, "NULL argument");
   if (species < 0 || species >= (int)sim->sp.size())
@@ -1438,6 +1466,7 @@ int sfpic3_read_particles(sfpic3_sim *sim, int species, double *x, double *y,
 }
 
 int sfpic3_diagnostics(sfpic3_sim *sim, sfpic_diag *out) {
+  sfpic::ErrScope es_(sim);
   if (!sim || !out) return sfpic::fail(SFPIC_E_INVAL, "NULL argument");
   sfpic3_sim *S = sim;
   const sfpic3_grid &g = S->grid;
@@ -1476,17 +1505,32 @@ int sfpic3_diagnostics(sfpic3_sim *sim, sfpic_diag *out) {
         S->f, S->plane, S->acc, flag);
   HIP3(hipGetLastError());
   if (int r = deposit_rho(S, S->rho)) return r;
+  if (!S->gprev) {
+    S->gprev = (double *)S->dalloc(S->plane * 8);
+    if (!S->gprev)
+      return sfpic::fail(SFPIC_E_NOMEM, "diagnostic allocation failed");
+    S->gprev_step = -1;
+  }
+  HIP3(hipMemsetAsync(S->acc + 8, 0, 16, S->st));
   unsigned long long *mx = (unsigned long long *)(S->acc + 2);
+  unsigned long long *mx2 = (unsigned long long *)(S->acc + 8);
+  const int have_prev = S->gprev_step >= 0;
   if (S->fp32)
     gauss3<float><<<gauss_grid(S->g), dim3(64, 4), 0, S->st>>>(
         fields_as<float>(S->f), S->g, S->rho, S->rho0, 1.0 / g.dx,
-        1.0 / g.dy, 1.0 / g.dz, mx);
+        1.0 / g.dy, 1.0 / g.dz, S->gprev, have_prev, mx, mx2);
   else
     gauss3<double><<<gauss_grid(S->g), dim3(64, 4), 0, S->st>>>(
-        S->f, S->g, S->rho, S->rho0, 1.0 / g.dx, 1.0 / g.dy, 1.0 / g.dz, mx);
+        S->f, S->g, S->rho, S->rho0, 1.0 / g.dx, 1.0 / g.dy, 1.0 / g.dz,
+        S->gprev, have_prev, mx, mx2);
   HIP3(hipGetLastError());
-  HIP3(hipMemcpyAsync(host.data(), S->acc, 64, hipMemcpyDeviceToHost, S->st));
+  host.resize(16);
+  HIP3(hipMemcpyAsync(host.data(), S->acc, 128, hipMemcpyDeviceToHost, S->st));
   HIP3(hipStreamSynchronize(S->st));
+  out->continuity_residual = have_prev ? host[8] : 0.0;
+  out->continuity_steps = have_prev ? S->step - S->gprev_step : 0;
+  out->rho_abs_max = host[9];
+  S->gprev_step = S->step;
   out->w_em = host[0] * dV;
   unsigned long long r0 = 0, r1 = 0;
   memcpy(&r0, &host[2], 8);
@@ -1521,6 +1565,7 @@ int sfpic3_diagnostics(sfpic3_sim *sim, sfpic_diag *out) {
 
 int sfpic3_read_total_field(sfpic3_sim *sim, int comp, double *out,
                             size_t n) {
+  sfpic::ErrScope es_(sim);
   if (!sim || !out) return sfpic::fail(SFPIC_E_INVAL, "NULL argument");
   if (comp < 0 || comp >= 6)
     return sfpic::fail(SFPIC_E_INVAL, "component must be E or B");
@@ -1551,6 +1596,7 @@ int sfpic3_read_total_field(sfpic3_sim *sim, int comp, double *out,
 
 int sfpic3_histogram(sfpic3_sim *sim, const sfpic_hist_spec *spec,
                      double *out, size_t n, double *moments) {
+  sfpic::ErrScope es_(sim);
   if (!sim || !spec || !out) return sfpic::fail(SFPIC_E_INVAL, "NULL argument");
   if (spec->species < 0 || spec->species >= (int)sim->sp.size() ||
       spec->n_energy <= 0 || spec->n_theta <= 0 || !(spec->e_max > 0.0))
@@ -1606,6 +1652,7 @@ static size_t state3_bytes(const sfpic3_sim *S) {
 }
 
 int sfpic3_get_state(sfpic3_sim *sim, void *buf, size_t *n) {
+  sfpic::ErrScope es_(sim);
   if (!sim || !n) return sfpic::fail(SFPIC_E_INVAL, "NULL argument");
   const size_t need = state3_bytes(sim);
   if (!buf) {
@@ -1650,6 +1697,7 @@ int sfpic3_get_state(sfpic3_sim *sim, void *buf, size_t *n) {
 }
 
 int sfpic3_set_state(sfpic3_sim *sim, const void *buf, size_t n) {
+  sfpic::ErrScope es_(sim);
   if (!sim || !buf) return sfpic::fail(SFPIC_E_INVAL, "NULL argument");
   if (n != state3_bytes(sim))
     return sfpic::fail(SFPIC_E_SIZE, "state does not fit this simulation");
@@ -1692,10 +1740,13 @@ int sfpic3_set_state(sfpic3_sim *sim, const void *buf, size_t n) {
   }
   HIP3(hipStreamSynchronize(sim->st));
   sim->step = hdr[6];
+  sim->gprev_step = -1;
   return SFPIC_OK;
 }
 
 void sfpic3_destroy(sfpic3_sim *sim) {
+  sfpic::ErrScope es_(sim);
+  sfpic::forget_handle(sim);
   if (!sim) return;
   (void)hipStreamSynchronize(sim->st);
   sim->release();

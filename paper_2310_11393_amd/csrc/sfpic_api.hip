@@ -7,8 +7,10 @@
 #include <math.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 #include <string>
+#include <unordered_map>
 #include <utility>
 #include <vector>
 
@@ -16,11 +18,31 @@ using namespace sfpic;
 
 namespace sfpic {
 
+// Last failure of the calling thread, and of every handle: a call records
+// its message for each handle whose entry point is active on this thread
+// (the handle of the ABI call and of the inner calls it makes).
 thread_local std::string g_last_error;
+thread_local std::vector<const void *> g_scopes;
+std::mutex g_err_mu;
+std::unordered_map<const void *, std::string> g_err_by_handle;
 
 int fail(int code, const std::string &msg) {
   g_last_error = msg;
+  if (!g_scopes.empty()) {
+    std::lock_guard<std::mutex> lk(g_err_mu);
+    for (const void *h : g_scopes)
+      if (h) g_err_by_handle[h] = msg;
+  }
   return code;
+}
+
+ErrScope::ErrScope(const void *handle) { g_scopes.push_back(handle); }
+ErrScope::~ErrScope() { g_scopes.pop_back(); }
+
+void forget_handle(const void *handle) {
+  if (!handle) return;
+  std::lock_guard<std::mutex> lk(g_err_mu);
+  g_err_by_handle.erase(handle);
 }
 
 }  // namespace sfpic
@@ -493,7 +515,7 @@ int sim_footprint(const sfpic_grid *grid, const sfpic_species *species,
   const size_t NX = (size_t)grid->nx + 2 * kGuard;
   const size_t NY = dims == 2 ? (size_t)grid->ny + 2 * kGuard : 1;
   const size_t pitch = (NX + 63) & ~(size_t)63;
-  size_t b = 12 * al(NY * pitch * es) + 2 * al(NY * pitch * 8) + al(64 * 8);
+  size_t b = 12 * al(NY * pitch * es) + 3 * al(NY * pitch * 8) + al(64 * 8);
   int tx = rt && rt->tile_x > 0 ? rt->tile_x : (dims == 2 ? 16 : 256);
   int ty = dims == 2 ? (rt && rt->tile_y > 0 ? rt->tile_y : 16) : 1;
   const size_t ntx = ((size_t)grid->nx + tx - 1) / tx;
@@ -698,7 +720,12 @@ int fetch_particles(sfpic_sim *s, SpeciesState &st, std::vector<double> &h,
 
 extern "C" {
 
-const char *sfpic_last_error(void) { return g_last_error.c_str(); }
+const char *sfpic_last_error(const void *handle) {
+  if (!handle) return g_last_error.c_str();
+  std::lock_guard<std::mutex> lk(g_err_mu);
+  auto it = g_err_by_handle.find(handle);
+  return it == g_err_by_handle.end() ? "" : it->second.c_str();
+}
 
 const char *sfpic_version(void) { return "sfpic 0.2 (gfx950)"; }
 
@@ -761,8 +788,9 @@ int sfpic_create(const sfpic_grid *grid, const sfpic_species *species,
     const size_t rbytes = (size_t)s->NY * s->pitch * 8;
     s->rho0 = (double *)s->dalloc(rbytes);
     s->rho = (double *)s->dalloc(rbytes);
+    s->gprev = (double *)s->dalloc(rbytes);
     s->acc = (double *)s->dalloc(64 * 8);
-    if (!s->rho0 || !s->rho || !s->acc)
+    if (!s->rho0 || !s->rho || !s->gprev || !s->acc)
       return bail(fail(SFPIC_E_NOMEM, "diagnostic allocation failed"));
     r = deposit_rho(s, s->rho0);
     if (r) return bail(r);
@@ -778,6 +806,7 @@ int sfpic_create(const sfpic_grid *grid, const sfpic_species *species,
 }
 
 int sfpic_step(sfpic_sim *s, int64_t nsteps) {
+  sfpic::ErrScope es_(s);
   SF_TRY(guarded(s));
   if (nsteps < 0) return fail(SFPIC_E_INVAL, "nsteps < 0");
   return s->dispatch(
@@ -785,12 +814,14 @@ int sfpic_step(sfpic_sim *s, int64_t nsteps) {
 }
 
 int sfpic_sync(sfpic_sim *s) {
+  sfpic::ErrScope es_(s);
   SF_TRY(guarded(s));
   HIP_TRY(hipStreamSynchronize(s->stream));
   return SFPIC_OK;
 }
 
 int sfpic_read_field(sfpic_sim *s, int comp, double *out, size_t n) {
+  sfpic::ErrScope es_(s);
   SF_TRY(guarded(s));
   if (comp < 0 || comp >= SFPIC_NCOMP || !out)
     return fail(SFPIC_E_INVAL, "bad component or NULL output");
@@ -808,6 +839,7 @@ int sfpic_read_field(sfpic_sim *s, int comp, double *out, size_t n) {
 }
 
 int sfpic_write_field(sfpic_sim *s, int comp, const double *in, size_t n) {
+  sfpic::ErrScope es_(s);
   SF_TRY(guarded(s));
   if (comp < 0 || comp >= SFPIC_NCOMP || !in)
     return fail(SFPIC_E_INVAL, "bad component or NULL input");
@@ -824,6 +856,7 @@ int sfpic_write_field(sfpic_sim *s, int comp, const double *in, size_t n) {
 }
 
 int sfpic_read_total_field(sfpic_sim *s, int comp, double *out, size_t n) {
+  sfpic::ErrScope es_(s);
   SF_TRY(guarded(s));
   if (comp < SFPIC_EX || comp > SFPIC_BZ || !out)
     return fail(SFPIC_E_INVAL, "component must be E or B, output non-NULL");
@@ -850,13 +883,16 @@ int sfpic_read_total_field(sfpic_sim *s, int comp, double *out, size_t n) {
 }
 
 int sfpic_set_step_index(sfpic_sim *s, int64_t step) {
+  sfpic::ErrScope es_(s);
   SF_TRY(guarded(s));
   if (step < 0) return fail(SFPIC_E_INVAL, "step < 0");
   s->step = step;
+  s->gprev_step = -1;
   return SFPIC_OK;
 }
 
 int sfpic_particle_count(sfpic_sim *s, int species, int64_t *n) {
+  sfpic::ErrScope es_(s);
   SF_TRY(guarded(s));
   if (species < 0 || species >= (int)s->sp.size() || !n)
     return fail(SFPIC_E_INVAL, "bad species");
@@ -879,6 +915,7 @@ int sfpic_particle_count(sfpic_sim *s, int species, int64_t *n) {
 int sfpic_read_particles(sfpic_sim *s, int species, double *x, double *y,
                          double *ux, double *uy, double *uz, uint32_t *id,
                          size_t capacity, size_t *n_out) {
+  sfpic::ErrScope es_(s);
   SF_TRY(guarded(s));
   if (species < 0 || species >= (int)s->sp.size())
     return fail(SFPIC_E_INVAL, "bad species");
@@ -911,10 +948,11 @@ int sfpic_read_particles(sfpic_sim *s, int species, double *x, double *y,
 }
 
 int sfpic_diagnostics(sfpic_sim *s, sfpic_diag *out) {
+  sfpic::ErrScope es_(s);
   SF_TRY(guarded(s));
   if (!out) return fail(SFPIC_E_INVAL, "out is NULL");
   const double dv = s->cell_volume();
-  HIP_TRY(hipMemsetAsync(s->acc, 0, 8 * 8, s->stream));
+  HIP_TRY(hipMemsetAsync(s->acc, 0, 16 * 8, s->stream));
   SF_TRY(s->dispatch([&](auto z) -> int {
     using R = decltype(z);
     for (auto &st : s->sp)
@@ -934,12 +972,17 @@ int sfpic_diagnostics(sfpic_sim *s, sfpic_diag *out) {
     using R = decltype(z);
     HIP_TRY(launch_gauss<R>(s->fields<R>(), s->grid.dims, (int)s->grid.nx,
                             (int)s->grid.ny, s->grid.dx, s->grid.dy, s->rho,
-                            s->rho0, s->pitch, s->acc, s->stream));
+                            s->rho0, s->pitch, s->gprev, s->gprev_step >= 0,
+                            s->acc, s->stream));
     return SFPIC_OK;
   }));
-  double h[8];
-  HIP_TRY(hipMemcpyAsync(h, s->acc, 8 * 8, hipMemcpyDeviceToHost, s->stream));
+  double h[16];
+  HIP_TRY(hipMemcpyAsync(h, s->acc, 16 * 8, hipMemcpyDeviceToHost, s->stream));
   HIP_TRY(hipStreamSynchronize(s->stream));
+  out->continuity_residual = s->gprev_step >= 0 ? h[8] : 0.0;
+  out->continuity_steps = s->gprev_step >= 0 ? s->step - s->gprev_step : 0;
+  out->rho_abs_max = h[9];
+  s->gprev_step = s->step;
   out->step = s->step;
   out->time = (double)s->step * s->grid.dt;
   out->w_kin = h[0];
@@ -955,6 +998,7 @@ int sfpic_diagnostics(sfpic_sim *s, sfpic_diag *out) {
 
 int sfpic_histogram(sfpic_sim *s, const sfpic_hist_spec *spec, double *out,
                     size_t n, double *moments) {
+  sfpic::ErrScope es_(s);
   SF_TRY(guarded(s));
   if (!spec || !out) return fail(SFPIC_E_INVAL, "NULL argument");
   if (spec->species < 0 || spec->species >= (int)s->sp.size() ||
@@ -993,6 +1037,7 @@ int sfpic_histogram(sfpic_sim *s, const sfpic_hist_spec *spec, double *out,
 // element size), 9 field planes [NY][NX] in the working precision, then per
 // species: the used slot count and the raw particle arrays of those slots.
 int sfpic_get_state(sfpic_sim *s, void *buf, size_t *n) {
+  sfpic::ErrScope es_(s);
   SF_TRY(guarded(s));
   if (!n) return fail(SFPIC_E_INVAL, "n is NULL");
   const size_t es = s->esize(), bpp = bytes_per_particle(s->precision);
@@ -1038,6 +1083,7 @@ int sfpic_get_state(sfpic_sim *s, void *buf, size_t *n) {
 }
 
 int sfpic_set_state(sfpic_sim *s, const void *buf, size_t n) {
+  sfpic::ErrScope es_(s);
   SF_TRY(guarded(s));
   if (!buf) return fail(SFPIC_E_INVAL, "buf is NULL");
   const size_t es = s->esize(), bpp = bytes_per_particle(s->precision);
@@ -1071,6 +1117,7 @@ int sfpic_set_state(sfpic_sim *s, const void *buf, size_t n) {
   if (q != end)
     return fail(SFPIC_E_SIZE, "state size does not match this sim");
   HIP_TRY(hipStreamSynchronize(s->stream));
+  s->gprev_step = -1;
   for (int c = 0; c < 9; ++c) {
     SF_TRY(plane_from_host(s, c, p));
     p += plane;
@@ -1099,6 +1146,7 @@ int sfpic_set_state(sfpic_sim *s, const void *buf, size_t n) {
 }
 
 int sfpic_profile(sfpic_sim *s, int enable) {
+  sfpic::ErrScope es_(s);
   SF_TRY(guarded(s));
   HIP_TRY(hipStreamSynchronize(s->stream));
   if (enable) s->recycle_events();
@@ -1107,6 +1155,7 @@ int sfpic_profile(sfpic_sim *s, int enable) {
 }
 
 int sfpic_profile_read(sfpic_sim *s, sfpic_kernel_stats *out) {
+  sfpic::ErrScope es_(s);
   SF_TRY(guarded(s));
   if (!out) return fail(SFPIC_E_INVAL, "out is NULL");
   HIP_TRY(hipStreamSynchronize(s->stream));
@@ -1167,6 +1216,7 @@ int sfpic_april_power(const sfpic_incident *inc, double *power) {
 }
 
 int sfpic_device_bytes(sfpic_sim *s, size_t *bytes) {
+  sfpic::ErrScope es_(s);
   SF_TRY(guarded(s));
   if (!bytes) return fail(SFPIC_E_INVAL, "bytes is NULL");
   *bytes = sim_device_bytes(s);
@@ -1174,6 +1224,8 @@ int sfpic_device_bytes(sfpic_sim *s, size_t *bytes) {
 }
 
 void sfpic_destroy(sfpic_sim *s) {
+  sfpic::ErrScope es_(s);
+  sfpic::forget_handle(s);
   if (!s) return;
   (void)hipSetDevice(s->rt.device);
   (void)hipStreamSynchronize(s->stream);

@@ -565,12 +565,21 @@ struct Engine {
   }
 
   // Result of a finished member (diagnostics and histogram on the stream).
+  // A member whose fields or momenta are no longer finite fails alone with
+  // SFPIC_E_NUMERIC (its result keeps the diagnostics that show it).
   static int finish_member(Member *m) {
     sfpic_result &res = m->res;
     res.steps = m->done;
     SF_TRY(sfpic_diagnostics(m->sim, &res.diag));
     res.pushes = (double)m->done * 0.5 * (m->n0 + (double)res.diag.n_alive);
     res.device_bytes = sim_device_bytes(m->sim);
+    if (res.diag.nonfinite) {
+      res.status = SFPIC_E_NUMERIC;
+      snprintf(res.error, sizeof(res.error),
+               "non-finite fields or momenta after %lld steps",
+               (long long)m->done);
+      return fail(SFPIC_E_NUMERIC, res.error);
+    }
     if (m->hist.n_energy > 0) {
       const size_t nb = (size_t)m->hist.n_energy * m->hist.n_theta;
       m->histogram.assign(nb, 0.0);
@@ -672,7 +681,8 @@ int batch_run_impl(sfpic_batch *b) {
   b->pushes = 0.0;
   for (auto &mp : b->members) {
     Member *m = mp.get();
-    SF_TRY(Engine::finish_member(m));
+    const int r = Engine::finish_member(m);
+    if (r != SFPIC_OK && r != SFPIC_E_NUMERIC) return r;  // a device error
     m->res.t_submit = 0.0;
     m->res.t_start = 0.0;
     m->res.t_done = t_step;
@@ -723,7 +733,7 @@ int sfpic_batch_create(int n, const sfpic_sim_desc *descs,
       const int r = create_member(b->eng, descs[i], *b->members[i]);
       if (r != SFPIC_OK) {
         const std::string msg = std::string("member ") + std::to_string(i) +
-                                ": " + sfpic_last_error();
+                                ": " + sfpic_last_error(nullptr);
         for (auto &m : b->members)
           if (m->sim) sfpic_destroy(m->sim);
         return fail(r, msg);
@@ -739,6 +749,7 @@ int sfpic_batch_create(int n, const sfpic_sim_desc *descs,
 }
 
 int sfpic_batch_run(sfpic_batch *b) {
+  sfpic::ErrScope es_(b);
   if (!b) return fail(SFPIC_E_INVAL, "batch is NULL");
   if (b->ran) return fail(SFPIC_E_STATE, "batch already ran");
   try {
@@ -750,6 +761,7 @@ int sfpic_batch_run(sfpic_batch *b) {
 }
 
 int sfpic_batch_result(sfpic_batch *b, int i, sfpic_result *out) {
+  sfpic::ErrScope es_(b);
   if (!b || !out) return fail(SFPIC_E_INVAL, "NULL argument");
   if (i < 0 || i >= (int)b->members.size())
     return fail(SFPIC_E_INVAL, "member index out of range");
@@ -759,6 +771,7 @@ int sfpic_batch_result(sfpic_batch *b, int i, sfpic_result *out) {
 }
 
 int sfpic_batch_member(sfpic_batch *b, int i, sfpic_sim **sim) {
+  sfpic::ErrScope es_(b);
   if (!b || !sim) return fail(SFPIC_E_INVAL, "NULL argument");
   if (i < 0 || i >= (int)b->members.size())
     return fail(SFPIC_E_INVAL, "member index out of range");
@@ -767,6 +780,7 @@ int sfpic_batch_member(sfpic_batch *b, int i, sfpic_sim **sim) {
 }
 
 int sfpic_batch_stats(sfpic_batch *b, sfpic_batch_info *out) {
+  sfpic::ErrScope es_(b);
   if (!b || !out) return fail(SFPIC_E_INVAL, "NULL argument");
   memset(out, 0, sizeof(*out));
   int gi = 0;
@@ -799,6 +813,8 @@ int sfpic_batch_stats(sfpic_batch *b, sfpic_batch_info *out) {
 }
 
 void sfpic_batch_destroy(sfpic_batch *b) {
+  sfpic::ErrScope es_(b);
+  sfpic::forget_handle(b);
   if (!b) return;
   (void)hipSetDevice(b->eng.rt.device);
   if (b->eng.stream) (void)hipStreamSynchronize(b->eng.stream);
@@ -882,7 +898,7 @@ void server_loop(sfpic_server *S) {
   {
     std::lock_guard<std::mutex> lk(S->mu);
     S->init_status = eng.init(&eng.rt, true);
-    if (S->init_status != SFPIC_OK) S->init_error = sfpic_last_error();
+    if (S->init_status != SFPIC_OK) S->init_error = sfpic_last_error(nullptr);
     S->ready = true;
   }
   S->cv_done.notify_all();
@@ -914,7 +930,7 @@ void server_loop(sfpic_server *S) {
       std::lock_guard<std::mutex> lk(S->mu);
       if (r != SFPIC_OK) {
         S->in_use -= q->footprint;
-        server_fail_request(S, q, r, sfpic_last_error());
+        server_fail_request(S, q, r, sfpic_last_error(nullptr));
         continue;
       }
       q->state = SFPIC_REQ_RUNNING;
@@ -960,7 +976,7 @@ void server_loop(sfpic_server *S) {
       if (rc != SFPIC_OK || q->group < 0) break;
       rc = eng.pull(eng.groups[q->group]);
     }
-    const std::string err = rc != SFPIC_OK ? sfpic_last_error() : "";
+    const std::string err = rc != SFPIC_OK ? sfpic_last_error(nullptr) : "";
     if (rc != SFPIC_OK) {
       finished.clear();
       for (Request *q : S->running) finished.push_back(q);
@@ -968,7 +984,7 @@ void server_loop(sfpic_server *S) {
     for (Request *q : finished) {
       int r = rc;
       if (r == SFPIC_OK) r = Engine::finish_member(&q->m);
-      const std::string msg = r != SFPIC_OK ? sfpic_last_error() : "";
+      const std::string msg = r != SFPIC_OK ? sfpic_last_error(nullptr) : "";
       drop_from_group(eng, q);
       sfpic_destroy(q->m.sim);
       q->m.sim = nullptr;
@@ -1056,6 +1072,7 @@ int sfpic_server_create(size_t hbm_budget, int max_slots,
 
 int sfpic_server_submit(sfpic_server *S, const sfpic_sim_desc *desc,
                         uint64_t *ticket) {
+  sfpic::ErrScope es_(S);
   try {
     if (!S || !ticket) return fail(SFPIC_E_INVAL, "NULL argument");
     SF_TRY(check_desc(desc));
@@ -1093,6 +1110,7 @@ int sfpic_server_submit(sfpic_server *S, const sfpic_sim_desc *desc,
 }
 
 int sfpic_server_poll(sfpic_server *S, uint64_t ticket, int *state) {
+  sfpic::ErrScope es_(S);
   if (!S || !state) return fail(SFPIC_E_INVAL, "NULL argument");
   std::lock_guard<std::mutex> lk(S->mu);
   auto it = S->all.find(ticket);
@@ -1102,6 +1120,7 @@ int sfpic_server_poll(sfpic_server *S, uint64_t ticket, int *state) {
 }
 
 int sfpic_server_wait(sfpic_server *S, uint64_t ticket, double timeout_s) {
+  sfpic::ErrScope es_(S);
   if (!S) return fail(SFPIC_E_INVAL, "server is NULL");
   std::unique_lock<std::mutex> lk(S->mu);
   auto it = S->all.find(ticket);
@@ -1116,6 +1135,7 @@ int sfpic_server_wait(sfpic_server *S, uint64_t ticket, double timeout_s) {
 }
 
 int sfpic_server_result(sfpic_server *S, uint64_t ticket, sfpic_result *out) {
+  sfpic::ErrScope es_(S);
   if (!S || !out) return fail(SFPIC_E_INVAL, "NULL argument");
   std::lock_guard<std::mutex> lk(S->mu);
   auto it = S->all.find(ticket);
@@ -1129,6 +1149,7 @@ int sfpic_server_result(sfpic_server *S, uint64_t ticket, sfpic_result *out) {
 
 int sfpic_server_histogram(sfpic_server *S, uint64_t ticket, double *out,
                            size_t n) {
+  sfpic::ErrScope es_(S);
   if (!S || !out) return fail(SFPIC_E_INVAL, "NULL argument");
   std::lock_guard<std::mutex> lk(S->mu);
   auto it = S->all.find(ticket);
@@ -1143,6 +1164,7 @@ int sfpic_server_histogram(sfpic_server *S, uint64_t ticket, double *out,
 }
 
 int sfpic_server_stats(sfpic_server *S, sfpic_server_info *out) {
+  sfpic::ErrScope es_(S);
   if (!S || !out) return fail(SFPIC_E_INVAL, "NULL argument");
   std::lock_guard<std::mutex> lk(S->mu);
   memset(out, 0, sizeof(*out));
@@ -1173,6 +1195,8 @@ int sfpic_server_stats(sfpic_server *S, sfpic_server_info *out) {
 }
 
 void sfpic_server_destroy(sfpic_server *S) {
+  sfpic::ErrScope es_(S);
+  sfpic::forget_handle(S);
   if (!S) return;
   {
     std::lock_guard<std::mutex> lk(S->mu);

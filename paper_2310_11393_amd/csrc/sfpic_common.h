@@ -651,8 +651,8 @@ hipError_t launch_deposit_rho(const Particles<R> &p, int64_t n,
 template <typename R>
 hipError_t launch_gauss(const Fields<R> &f, int dims, int nx, int ny,
                         double dx, double dy, const double *rho,
-                        const double *rho0, int rpitch, double *acc,
-                        hipStream_t st);
+                        const double *rho0, int rpitch, double *gprev,
+                        int have_prev, double *acc, hipStream_t st);
 template <typename R>
 hipError_t launch_histogram(const Particles<R> &p, int64_t n,
                             const uint32_t *n_valid, int dims, double m,

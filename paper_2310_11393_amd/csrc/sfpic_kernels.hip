@@ -654,17 +654,26 @@ hipError_t launch_deposit_rho(const Particles<R> &p, int64_t n,
 
 // Gauss-law residual |div_h E - (rho - rho0)| at primal nodes at least 4
 // cells inside the physical box; acc[5] = max residual, acc[6] = max |rho -
-// rho0| there.
+// rho0| there.  The per-node defect g = div_h E - (rho - rho0) is kept in
+// gprev; with have_prev the previous call's defect is read first and acc[8]
+// = max |g - gprev| is the discrete continuity residual between the two
+// calls.  acc[9] = max |rho|.  A non-finite value counts as +inf (fmax would
+// drop a NaN).
+__device__ __forceinline__ double inf_if_nan(double v) {
+  return isnan(v) ? __builtin_huge_val() : v;
+}
+
 template <typename R>
 __global__ void gauss_kernel(Fields<R> f, int dims, int nx, int ny,
                              double idx, double idy, const double *rho,
-                             const double *rho0, int rp, double *acc) {
+                             const double *rho0, int rp, double *gprev,
+                             int have_prev, double *acc) {
   // 256 threads: the block takes the maxima first and issues one atomic for
   // each (an atomic per node on two addresses serializes the grid)
-  __shared__ double sh[2][4];
+  __shared__ double sh[4][4];
   const int i = blockIdx.x * blockDim.x + threadIdx.x + 4;
   const int j = (dims == 2) ? blockIdx.y + 4 : 0;
-  double res = 0.0, drm = 0.0;
+  double v[4] = {0.0, 0.0, 0.0, 0.0};  // |g|, |rho - rho0|, |dg|, |rho|
   if (i <= nx - 4) {
     const int I = i + kGuard, J = (dims == 2) ? j + kGuard : 0;
     const size_t k = (size_t)J * f.pitch + I;
@@ -672,37 +681,37 @@ __global__ void gauss_kernel(Fields<R> f, int dims, int nx, int ny,
     if (dims == 2) div += ((double)f.ey[k] - (double)f.ey[k - f.pitch]) * idy;
     const size_t kr = (size_t)J * rp + I;
     const double dr = rho[kr] - rho0[kr];
-    res = fabs(div - dr);
-    drm = fabs(dr);
+    const double g = div - dr;
+    v[0] = inf_if_nan(fabs(g));
+    v[1] = inf_if_nan(fabs(dr));
+    if (have_prev) v[2] = inf_if_nan(fabs(g - gprev[kr]));
+    v[3] = inf_if_nan(fabs(rho[kr]));
+    gprev[kr] = g;
   }
-  for (int o = 32; o > 0; o >>= 1) {
-    res = fmax(res, __shfl_down(res, o, 64));
-    drm = fmax(drm, __shfl_down(drm, o, 64));
-  }
-  if ((threadIdx.x & 63) == 0) {
-    sh[0][threadIdx.x >> 6] = res;
-    sh[1][threadIdx.x >> 6] = drm;
-  }
+  for (int o = 32; o > 0; o >>= 1)
+    for (int q = 0; q < 4; ++q) v[q] = fmax(v[q], __shfl_down(v[q], o, 64));
+  if ((threadIdx.x & 63) == 0)
+    for (int q = 0; q < 4; ++q) sh[q][threadIdx.x >> 6] = v[q];
   __syncthreads();
   if (threadIdx.x == 0) {
-    for (int w = 1; w < 4; ++w) {
-      res = fmax(res, sh[0][w]);
-      drm = fmax(drm, sh[1][w]);
-    }
-    atomic_max_pos(&acc[5], res);
-    atomic_max_pos(&acc[6], drm);
+    for (int w = 1; w < 4; ++w)
+      for (int q = 0; q < 4; ++q) v[q] = fmax(v[q], sh[q][w]);
+    atomic_max_pos(&acc[5], v[0]);
+    atomic_max_pos(&acc[6], v[1]);
+    atomic_max_pos(&acc[8], v[2]);
+    atomic_max_pos(&acc[9], v[3]);
   }
 }
 
 template <typename R>
 hipError_t launch_gauss(const Fields<R> &f, int dims, int nx, int ny,
                         double dx, double dy, const double *rho,
-                        const double *rho0, int rpitch, double *acc,
-                        hipStream_t st) {
+                        const double *rho0, int rpitch, double *gprev,
+                        int have_prev, double *acc, hipStream_t st) {
   if (nx < 9 || (dims == 2 && ny < 9)) return hipSuccess;
   dim3 g((nx - 7 + 255) / 256, dims == 2 ? ny - 7 : 1);
   gauss_kernel<R><<<g, 256, 0, st>>>(f, dims, nx, ny, 1.0 / dx, 1.0 / dy, rho,
-                                     rho0, rpitch, acc);
+                                     rho0, rpitch, gprev, have_prev, acc);
   return hipGetLastError();
 }
 
@@ -792,8 +801,8 @@ hipError_t launch_export_particles(const Particles<R> &p, int64_t n, int dims,
                                             double *, hipStream_t);           \
   template hipError_t launch_gauss<R>(const Fields<R> &, int, int, int,       \
                                       double, double, const double *,         \
-                                      const double *, int, double *,          \
-                                      hipStream_t);                           \
+                                      const double *, int, double *, int,     \
+                                      double *, hipStream_t);                           \
   template hipError_t launch_init_particles<R>(                              \
       const Particles<R> &, int64_t, int, int64_t, int64_t, int64_t, int,     \
       double, uint64_t, uint32_t, double, double, hipStream_t);               \

@@ -421,18 +421,24 @@ __device__ __forceinline__ bool push_particle(int &ix, int &iy, R &fx, R &fy,
   esirkepov<R, DIMS>(S0x, S1x, S0y, S1y, lox, hix, loy, hiy,
                      (R)(-pp.qw * pp.dx / pp.dt), (R)(-pp.qw * pp.dy / pp.dt),
                      qvy, qvz, add);
+  // A move below one cell keeps |d1| < 2; a non-finite momentum (a
+  // simulation gone numerically bad) makes d1 NaN, and such a particle is
+  // removed here instead of being given a cell from a NaN.
+  const bool finite_move =
+      fabs(d1x) < R(4) && (DIMS == 1 || fabs(d1y) < R(4));
   // new cell and offset in [0, 1)
-  const R cx1 = floor(d1x);
+  const R cx1 = finite_move ? floor(d1x) : R(0);
   ix = ipx + (int)cx1;
-  fx = d1x - cx1;
+  fx = finite_move ? d1x - cx1 : R(0);
   if (!(fx < R(1))) fx = one_below<R>();
   if (DIMS == 2) {
-    const R cy1 = floor(d1y);
+    const R cy1 = finite_move ? floor(d1y) : R(0);
     iy = ipy + (int)cy1;
-    fy = d1y - cy1;
+    fy = finite_move ? d1y - cy1 : R(0);
     if (!(fy < R(1))) fy = one_below<R>();
   }
-  return ix >= 0 && ix < pp.nx && (DIMS == 1 || (iy >= 0 && iy < pp.ny));
+  return finite_move && ix >= 0 && ix < pp.nx &&
+         (DIMS == 1 || (iy >= 0 && iy < pp.ny));
 }
 
 // ---------------------------------------------------------------------------

@@ -11,8 +11,20 @@
 
 namespace sfpic {
 
-// Record msg as the calling thread's last error and return code.
+// Record msg as the calling thread's last error, and as the last error of
+// every handle whose entry point is active on this thread, and return code.
 int fail(int code, const std::string &msg);
+
+// Marks an ABI entry point's handle active on this thread for its lifetime.
+struct ErrScope {
+  explicit ErrScope(const void *handle);
+  ~ErrScope();
+  ErrScope(const ErrScope &) = delete;
+  ErrScope &operator=(const ErrScope &) = delete;
+};
+
+// Drop the recorded message of a handle that is being destroyed.
+void forget_handle(const void *handle);
 
 // Column offsets of a density profile along x over region columns
 // [x0, x1): off[c + 1] - off[c] particles per cell of column c
@@ -133,6 +145,10 @@ struct sfpic_sim {
   uint32_t item_max = kItemParticles;  // particles per push work item
   uint32_t *strag = nullptr, *n_strag = nullptr;  // straggler list
   double *rho0 = nullptr, *rho = nullptr, *acc = nullptr;
+  // per-node Gauss defect of the last diagnostics call and its step (-1:
+  // none, or the state has been changed since)
+  double *gprev = nullptr;
+  int64_t gprev_step = -1;
   std::vector<std::pair<void *, size_t>> allocs;
   // profiling: event pairs per kernel class, recorded in launch order
   bool profiling = false;

@@ -33,7 +33,23 @@ def test_library_exports_every_declared_symbol(L):
 
 def test_version_and_error_strings(L):
     assert b"gfx950" in L.sfpic_version()
-    assert isinstance(L.sfpic_last_error(), bytes)
+    assert isinstance(L.sfpic_last_error(None), bytes)
+
+
+def test_last_error_takes_a_handle(L):
+    """The error call follows the boundary's per-handle form: a message for
+    the last failure on a handle, NULL for the calling thread's last one."""
+    text = open(os.path.join(ROOT, "include", "sfpic.h")).read()
+    assert re.search(r"const char \*sfpic_last_error\(const void \*handle\);",
+                     text)
+    from paper_2310_11393_amd import binding as b
+    g = b.sfpic_grid(3, 64, 64, 0.2, 0.2, 0.1)
+    h = C.c_void_p()
+    assert L.sfpic_create(C.byref(g), None, 0, None, 0, None,
+                          C.byref(h)) == -1
+    assert b"dims" in L.sfpic_last_error(None)
+    # a handle that never failed (here: one that does not exist) has none
+    assert L.sfpic_last_error(C.c_void_p(0x1000)) == b""
 
 
 def test_invalid_grid_rejected_without_gpu(L):
@@ -42,10 +58,10 @@ def test_invalid_grid_rejected_without_gpu(L):
     h = C.c_void_p()
     rc = L.sfpic_create(C.byref(g), None, 0, None, 0, None, C.byref(h))
     assert rc == -1 and not h.value
-    assert b"dims" in L.sfpic_last_error()
+    assert b"dims" in L.sfpic_last_error(None)
     g = b.sfpic_grid(2, 64, 64, 0.2, 0.2, 0.2)  # CFL violated
     rc = L.sfpic_create(C.byref(g), None, 0, None, 0, None, C.byref(h))
-    assert rc == -1 and b"CFL" in L.sfpic_last_error()
+    assert rc == -1 and b"CFL" in L.sfpic_last_error(None)
 
 
 def test_invalid_3d_input_rejected_without_gpu(L):
@@ -54,20 +70,20 @@ def test_invalid_3d_input_rejected_without_gpu(L):
     g = b.sfpic3_grid(16, 16, 16, 0.2, 0.2, 0.2, 0.2)  # CFL violated
     assert L.sfpic3_create(C.byref(g), None, 0, None, 0, None,
                            C.byref(h)) == -1
-    assert b"CFL" in L.sfpic_last_error() and not h.value
+    assert b"CFL" in L.sfpic_last_error(None) and not h.value
     g = b.sfpic3_grid(16, 0, 16, 0.2, 0.2, 0.2, 0.05)
     assert L.sfpic3_create(C.byref(g), None, 0, None, 0, None,
                            C.byref(h)) == -1
     g = b.sfpic3_grid(16, 16, 16, 0.2, 0.2, 0.2, 0.05)
     assert L.sfpic3_create(C.byref(g), None, 0, None, 7, None,
                            C.byref(h)) == -1
-    assert b"precision" in L.sfpic_last_error()
+    assert b"precision" in L.sfpic_last_error(None)
     g = b.sfpic3_grid(16, 16, 16, 0.2, 0.2, 0.2, 0.05)
     inc = b.sfpic_incident()
     inc.kind, inc.a0, inc.w0, inc.fwhm_t = 4, 1.0, 2.0, 5.0  # 2D-only beam
     assert L.sfpic3_create(C.byref(g), None, 0, C.byref(inc), 0, None,
                            C.byref(h)) == -1
-    assert b"2D" in L.sfpic_last_error()
+    assert b"2D" in L.sfpic_last_error(None)
     x = (C.c_double * 1)(3.3)  # outside [0, 16 * 0.2)
     zero = (C.c_double * 1)(0.1)
     sp = b.sfpic3_species()
@@ -76,7 +92,7 @@ def test_invalid_3d_input_rejected_without_gpu(L):
     sp.ux, sp.uy, sp.uz = zero, zero, zero
     assert L.sfpic3_create(C.byref(g), C.byref(sp), 1, None, 0, None,
                            C.byref(h)) == -1
-    assert b"outside" in L.sfpic_last_error()
+    assert b"outside" in L.sfpic_last_error(None)
     assert L.sfpic3_step(None, 1) == -1
     L.sfpic3_destroy(None)
 
@@ -143,20 +159,20 @@ def test_batch_and_server_reject_bad_arguments(L):
     assert L.sfpic_batch_create(0, None, None, C.byref(h)) == -1
     d = b.SimDesc(wl.sweep_member(0), nsteps=-1)
     assert L.sfpic_batch_create(1, C.byref(d.desc), None, C.byref(h)) == -1
-    assert b"nsteps" in L.sfpic_last_error()
+    assert b"nsteps" in L.sfpic_last_error(None)
     d = b.SimDesc(wl.sweep_member(0), hist=b.hist_spec(sp=3))
     assert L.sfpic_batch_create(1, C.byref(d.desc), None, C.byref(h)) == -1
     w = wl.sweep_member(0)
     w.incident.on_nodes = 1
     d = b.SimDesc(w)
     assert L.sfpic_batch_create(1, C.byref(d.desc), None, C.byref(h)) == -1
-    assert b"on_nodes" in L.sfpic_last_error()
+    assert b"on_nodes" in L.sfpic_last_error(None)
     w = wl.sweep_member(0)
     w.species[0].profile = wl.PROFILE_SUPERGAUSS
     w.species[0].profile_fwhm, w.species[0].profile_order = 20.0, 12.0
     d = b.SimDesc(w)
     assert L.sfpic_batch_create(1, C.byref(d.desc), None, C.byref(h)) == -1
-    assert b"profile" in L.sfpic_last_error()
+    assert b"profile" in L.sfpic_last_error(None)
     assert L.sfpic_server_create(0, 0, None, C.byref(h)) == -1
     assert L.sfpic_batch_run(None) == -1
     assert L.sfpic_server_submit(None, None, None) == -1
