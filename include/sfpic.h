@@ -310,6 +310,22 @@ int sfpic_diagnostics(sfpic_sim *sim, sfpic_diag *out);
 int sfpic_histogram(sfpic_sim *sim, const sfpic_hist_spec *spec,
                     double *out, size_t n, double *moments);
 
+/* sfpic_histogram for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same histogram and moments, with the bins accumulated in
+ * a fixed device array of the library instead of a buffer allocated per
+ * call.  It calls no hipMalloc, hipFree or allocating library routine; it
+ * still copies the result to the caller's host arrays and waits for the
+ * sim's stream.  n_energy * n_theta must not exceed
+ * SFPIC_HIST_NOALLOC_MAX_BINS (SFPIC_E_SIZE otherwise); other errors as
+ * sfpic_histogram.  The array (8 + SFPIC_HIST_NOALLOC_MAX_BINS doubles,
+ * 512 KiB) exists once per GPU for the life of the process and every call
+ * on that GPU uses it: calls that overlap on one GPU (several host threads,
+ * or sims on different streams) race and must be serialized by the caller. */
+#define SFPIC_HIST_NOALLOC_MAX_BINS 65536
+int sfpic_histogram_noalloc(sfpic_sim *sim, const sfpic_hist_spec *spec,
+                            double *out, size_t n, double *moments);
+
 /* Checkpoint: serialize the full state (fields, particles, step) into buf.
  * With buf == NULL, *n receives the size needed.  Otherwise *n is the
  * buffer size on input and the size written on output (SFPIC_E_SIZE when

@@ -168,7 +168,8 @@ EXPORTS = ["sfpic_create", "sfpic_step", "sfpic_sync", "sfpic_read_field",
            "sfpic_write_field", "sfpic_read_total_field",
            "sfpic_set_step_index",
            "sfpic_particle_count", "sfpic_read_particles",
-           "sfpic_diagnostics", "sfpic_histogram", "sfpic_get_state",
+           "sfpic_diagnostics", "sfpic_histogram",
+           "sfpic_histogram_noalloc", "sfpic_get_state",
            "sfpic_set_state", "sfpic_profile", "sfpic_profile_read",
            "sfpic_destroy", "sfpic_device_bytes", "sfpic_last_error",
            "sfpic_version", "sfpic_desc_footprint", "sfpic_batch_create",
@@ -225,6 +226,8 @@ def lib():
     L.sfpic_diagnostics.argtypes = [vp, C.POINTER(sfpic_diag)]
     L.sfpic_histogram.argtypes = [vp, C.POINTER(sfpic_hist_spec), _DP, sz,
                                   _DP]
+    L.sfpic_histogram_noalloc.argtypes = [vp, C.POINTER(sfpic_hist_spec),
+                                          _DP, sz, _DP]
     L.sfpic_get_state.argtypes = [vp, vp, C.POINTER(sz)]
     L.sfpic_set_state.argtypes = [vp, vp, sz]
     L.sfpic_profile.argtypes = [vp, C.c_int]

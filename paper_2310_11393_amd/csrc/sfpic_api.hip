@@ -996,23 +996,39 @@ int sfpic_diagnostics(sfpic_sim *s, sfpic_diag *out) {
   return SFPIC_OK;
 }
 
-int sfpic_histogram(sfpic_sim *s, const sfpic_hist_spec *spec, double *out,
-                    size_t n, double *moments) {
-  sfpic::ErrScope es_(s);
-  SF_TRY(guarded(s));
+}  // extern "C"
+
+// Device scratch of sfpic_histogram_noalloc: the moment accumulators and
+// the bins of one histogram.  Each GPU holds its own copy for the life of
+// the process; host code reaches it only through the address that
+// hipGetSymbolAddress returns on that device (the array's name is not a
+// device address in host code).
+static __device__ __align__(256) double
+    scratch[8 + SFPIC_HIST_NOALLOC_MAX_BINS];
+
+namespace {
+
+int check_hist_spec(const sfpic_sim *s, const sfpic_hist_spec *spec,
+                    const double *out, size_t n) {
   if (!spec || !out) return fail(SFPIC_E_INVAL, "NULL argument");
   if (spec->species < 0 || spec->species >= (int)s->sp.size() ||
       spec->n_energy <= 0 || spec->n_theta <= 0 || !(spec->e_max > 0.0))
     return fail(SFPIC_E_INVAL, "bad histogram spec");
+  if (n != (size_t)spec->n_energy * spec->n_theta)
+    return fail(SFPIC_E_SIZE, "n must be n_energy * n_theta");
+  return SFPIC_OK;
+}
+
+// Histogram of a species into the device buffer d (8 moment accumulators,
+// then the bins), already zeroed on the sim's stream; copies the result to
+// the caller's arrays and waits for the stream.
+int histogram_into(sfpic_sim *s, const sfpic_hist_spec *spec, double *d,
+                   double *out, double *moments) {
   const size_t nb = (size_t)spec->n_energy * spec->n_theta;
-  if (n != nb) return fail(SFPIC_E_SIZE, "n must be n_energy * n_theta");
-  double *d = (double *)s->dalloc((nb + 8) * 8);
-  if (!d) return fail(SFPIC_E_NOMEM, "histogram allocation failed");
   SpeciesState &st = s->sp[spec->species];
   double mom[8] = {0};
-  int rc = s->dispatch([&](auto z) -> int {
+  SF_TRY(s->dispatch([&](auto z) -> int {
     using R = decltype(z);
-    HIP_TRY(hipMemsetAsync(d, 0, (nb + 8) * 8, s->stream));
     HIP_TRY(launch_histogram<R>(parts<R>(st), st.n, st.n_valid, s->grid.dims,
                                 st.m, st.weight * s->cell_volume(),
                                 spec->n_energy, spec->e_max, spec->n_theta,
@@ -1022,15 +1038,80 @@ int sfpic_histogram(sfpic_sim *s, const sfpic_hist_spec *spec, double *out,
     HIP_TRY(hipMemcpyAsync(mom, d, 8 * 8, hipMemcpyDeviceToHost, s->stream));
     HIP_TRY(hipStreamSynchronize(s->stream));
     return SFPIC_OK;
-  });
-  s->dfree(d);
-  if (rc) return rc;
+  }));
   if (moments) {
     moments[0] = mom[0];
     for (int k = 1; k < 5; ++k)
       moments[k] = mom[0] > 0.0 ? mom[k] / mom[0] : 0.0;
   }
   return SFPIC_OK;
+}
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxDevices] = {};
+
+// The scratch address on device `dev`, looked up once per device with that
+// device current (the caller has set it).
+int scratch_on_device(int dev, double **ptr) {
+  if (dev < 0 || dev >= kMaxDevices)
+    return fail(SFPIC_E_INVAL, "device ordinal out of range");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(SFPIC_E_DEVICE,
+                  std::string("hipGetSymbolAddress(scratch): ") +
+                      hipGetErrorString(e));
+    g_scratch_ptr[dev] = (double *)p;
+  }
+  *ptr = g_scratch_ptr[dev];
+  return SFPIC_OK;
+}
+
+__global__ void zero_f64(double *p, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0.0;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sfpic_histogram(sfpic_sim *s, const sfpic_hist_spec *spec, double *out,
+                    size_t n, double *moments) {
+  sfpic::ErrScope es_(s);
+  SF_TRY(guarded(s));
+  SF_TRY(check_hist_spec(s, spec, out, n));
+  const size_t nb = (size_t)spec->n_energy * spec->n_theta;
+  double *d = (double *)s->dalloc((nb + 8) * 8);
+  if (!d) return fail(SFPIC_E_NOMEM, "histogram allocation failed");
+  int rc = SFPIC_OK;
+  if (hipMemsetAsync(d, 0, (nb + 8) * 8, s->stream) != hipSuccess)
+    rc = fail(SFPIC_E_DEVICE, "hipMemsetAsync failed");
+  if (rc == SFPIC_OK) rc = histogram_into(s, spec, d, out, moments);
+  s->dfree(d);
+  return rc;
+}
+
+int sfpic_histogram_noalloc(sfpic_sim *s, const sfpic_hist_spec *spec,
+                            double *out, size_t n, double *moments) {
+  sfpic::ErrScope es_(s);
+  SF_TRY(guarded(s));
+  SF_TRY(check_hist_spec(s, spec, out, n));
+  const size_t nb = (size_t)spec->n_energy * spec->n_theta;
+  if (nb > SFPIC_HIST_NOALLOC_MAX_BINS)
+    return fail(SFPIC_E_SIZE,
+                "n_energy * n_theta exceeds SFPIC_HIST_NOALLOC_MAX_BINS (" +
+                    std::to_string(SFPIC_HIST_NOALLOC_MAX_BINS) + ")");
+  double *d = nullptr;
+  SF_TRY(scratch_on_device(s->rt.device, &d));
+  // the previous call's bins are still there: clear what this one uses
+  const size_t nz = nb + 8;
+  zero_f64<<<(unsigned)((nz + 255) / 256), 256, 0, s->stream>>>(d, nz);
+  HIP_TRY(hipGetLastError());
+  return histogram_into(s, spec, d, out, moments);
 }
 
 // State layout: header (magic, dims, nx, ny, precision, nspecies, step,
