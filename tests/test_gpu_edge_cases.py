@@ -166,8 +166,13 @@ def test_ring_parity_50_steps(kind, prec):
     if prec == wl.FP64:
         assert dpos <= 1e-12 and du <= 1e-12 * max(1.0, umax), (dpos, du)
     else:
-        assert dpos <= 1e-5 * max(1.0, umax) and \
-            du <= 1e-4 * max(1.0, umax), (dpos, du)
+        # FP32 momenta to 1e-4 of max(1, |u|max); a position is the time
+        # integral of the velocity, so its error is bounded by that of the
+        # momentum times the run's duration (the electrons near the ring of
+        # this tight focus reach |u| ~ 9 and move several cells)
+        t_run = work.steps * work.grid.dt
+        assert du <= 1e-4 * max(1.0, umax), du
+        assert dpos <= 1e-4 * max(1.0, umax) * t_run, (dpos, t_run)
     assert g.diagnostics()["n_alive"] == o.diagnostics()["n_alive"]
 
 
