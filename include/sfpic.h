@@ -174,7 +174,8 @@ typedef struct {
   void *alloc_ctx;
   int32_t tile_x, tile_y; /* particle tile in cells; 0 = library default   */
   int32_t sort_every;     /* steps between tile sorts; 0 = default (single
-                             sims 8, batches and servers 4)               */
+                             sims 8 in FP64 and 4 in the FP32 form;
+                             batches and servers: autotuned or 4)        */
   int32_t device;         /* HIP device ordinal                            */
   int32_t flags;          /* SFPIC_RT_* (batches and servers)              */
   int32_t item_particles; /* single sims: a tile holding more particles is
@@ -224,9 +225,22 @@ typedef struct {
   int32_t species;
   int32_t n_energy;  /* linear kinetic-energy bins over [0, e_max) (m_e c^2) */
   double e_max;
-  int32_t n_theta;   /* angle from +x, bins over [0, 180] degrees          */
+  int32_t n_theta;   /* angle bins over [0, 180] degrees                   */
   double ek_min;     /* moments use particles with E_k > ek_min            */
+  int32_t plane;     /* SFPIC_ANGLE_*: which angle the histogram bins      */
 } sfpic_hist_spec;
+
+/* sfpic_hist_spec.plane.  SFPIC_ANGLE_POLAR: the angle between the momentum
+ * and the propagation axis +x, atan2(sqrt(u_y^2 + u_z^2), u_x).
+ * SFPIC_ANGLE_XZ: the angle from +x of the momentum projected on the plane
+ * of x and z, atan2(|u_z|, u_x): the plane through the propagation axis
+ * across the linear polarization (the paper's (y, z) plane, in which
+ * Secs. 4.2 and 4.3 bin their electron spectra, 20 degrees forward and
+ * backward read as 20 and 160 degrees here).  SFPIC_ANGLE_XY: projected on
+ * the plane of x and y (the polarization plane), atan2(|u_y|, u_x). */
+#define SFPIC_ANGLE_POLAR 0
+#define SFPIC_ANGLE_XZ 1
+#define SFPIC_ANGLE_XY 2
 
 typedef struct sfpic_sim sfpic_sim;
 
@@ -302,11 +316,12 @@ int sfpic_diagnostics(sfpic_sim *sim, sfpic_diag *out);
 
 /* Energy-angle histogram of a species (weights w dV), out has
  * n_energy * n_theta doubles [energy][theta]; moments (nullable) receives
- * {sum of weights, <E_k>, <E_k^2>, <theta>, <theta^2>} (theta in degrees)
- * over particles with E_k > ek_min.  These are the electron energy spectra
- * against the angle from the propagation axis of Secs. 4.2 and 4.3.
- * SFPIC_E_INVAL for a bad spec, SFPIC_E_SIZE unless n = n_energy n_theta,
- * SFPIC_E_NOMEM if its device buffer cannot be allocated. */
+ * {sum of weights, <E_k>, <E_k^2>, <theta>, <theta^2>} (theta in degrees,
+ * the angle spec->plane selects) over particles with E_k > ek_min.  These
+ * are the electron energy spectra against the angle from the propagation
+ * axis of Secs. 4.2 and 4.3.  SFPIC_E_INVAL for a bad spec, SFPIC_E_SIZE
+ * unless n = n_energy n_theta, SFPIC_E_NOMEM if its device buffer cannot
+ * be allocated. */
 int sfpic_histogram(sfpic_sim *sim, const sfpic_hist_spec *spec,
                     double *out, size_t n, double *moments);
 
@@ -436,7 +451,10 @@ typedef struct sfpic_batch sfpic_batch;
  * batch creates its own stream.  Tile: rt->tile_x, tile_y if given,
  * otherwise chosen by the autotuner in the first steps of sfpic_batch_run
  * (runs of 128 steps or more, unless SFPIC_RT_NO_AUTOTUNE).  Sort cadence:
- * rt->sort_every if given, else 4. */
+ * rt->sort_every if given; else, when the tile is autotuned, the fastest
+ * of every 2, 4 or 8 steps on the run's own steps after the tile, timed
+ * again every 256 steps of a longer run; else 4.  The trials are real
+ * steps of the run (sfpic_batch_stats lists them). */
 int sfpic_batch_create(int n, const sfpic_sim_desc *descs,
                        const sfpic_runtime *rt, sfpic_batch **out);
 
@@ -456,7 +474,7 @@ int sfpic_batch_result(sfpic_batch *batch, int i, sfpic_result *out);
 int sfpic_batch_member(sfpic_batch *batch, int i, sfpic_sim **sim);
 
 #define SFPIC_MAX_GROUPS 4
-#define SFPIC_MAX_CANDIDATES 16
+#define SFPIC_MAX_CANDIDATES 32
 typedef struct {
   int32_t ngroups;     /* (precision, dims) classes                         */
   int32_t precision[SFPIC_MAX_GROUPS], dims[SFPIC_MAX_GROUPS];
@@ -465,7 +483,8 @@ typedef struct {
   int32_t sort_every[SFPIC_MAX_GROUPS];
   int32_t tuned[SFPIC_MAX_GROUPS];  /* 1: tile chosen by the autotuner       */
   int32_t push_workgroups[SFPIC_MAX_GROUPS];  /* persistent push grid       */
-  /* autotuner trials of each group: tile, cadence, ns per particle push    */
+  /* autotuner trials of each group in the order run (the first
+   * SFPIC_MAX_CANDIDATES): tile, cadence, ns per particle push             */
   int32_t n_candidates[SFPIC_MAX_GROUPS];
   int32_t cand_tile_x[SFPIC_MAX_GROUPS][SFPIC_MAX_CANDIDATES];
   int32_t cand_tile_y[SFPIC_MAX_GROUPS][SFPIC_MAX_CANDIDATES];

@@ -94,7 +94,8 @@ def lib():
         L.orc_em_energy_total.restype = C.c_double
         L.orc_em_energy_total.argtypes = [C.c_void_p]
         L.orc_energy_angle.argtypes = [C.c_void_p, C.c_int, C.c_int,
-                                       C.c_double, C.c_int, C.c_double, _D, _D]
+                                       C.c_double, C.c_int, C.c_double,
+                                       C.c_int, _D, _D]
         L.orc3_incident_eval.argtypes = [C.POINTER(_Incident)] + \
             [C.c_double] * 4 + [_D, _D]
         L.orc3_create.restype = C.c_void_p
@@ -118,8 +119,8 @@ def lib():
         L.orc3_em_energy_total.restype = C.c_double
         L.orc3_em_energy_total.argtypes = [C.c_void_p]
         L.orc3_energy_angle.argtypes = [C.c_void_p, C.c_int, C.c_int,
-                                        C.c_double, C.c_int, C.c_double, _D,
-                                        _D]
+                                        C.c_double, C.c_int, C.c_double,
+                                        C.c_int, _D, _D]
         _lib = L
     return _lib
 
@@ -275,11 +276,13 @@ class OracleSim:
                 "w_em_total": lib().orc_em_energy_total(self._h)}
 
     def energy_angle(self, sp=0, n_e=256, emax=1.0, n_theta=180,
-                     ek_min=1.0e3 / 510998.95):
+                     ek_min=1.0e3 / 510998.95, plane=0):
+        """plane: 0 angle from +x, 1 (2) of the momentum projected on the
+        x-z (x-y) plane."""
         h = np.zeros((n_e, n_theta))
         mom = np.zeros(5)
         lib().orc_energy_angle(self._h, sp, n_e, emax, n_theta, ek_min,
-                               _dp(h), _dp(mom))
+                               int(plane), _dp(h), _dp(mom))
         return h, mom
 
 
@@ -364,9 +367,11 @@ class OracleSim3:
                 "w_em_total": lib().orc3_em_energy_total(self._h)}
 
     def energy_angle(self, sp=0, n_e=256, emax=1.0, n_theta=180,
-                     ek_min=1.0e3 / 510998.95):
+                     ek_min=1.0e3 / 510998.95, plane=0):
+        """plane: 0 angle from +x, 1 (2) of the momentum projected on the
+        x-z (x-y) plane."""
         h = np.zeros((n_e, n_theta))
         mom = np.zeros(5)
         lib().orc3_energy_angle(self._h, sp, n_e, emax, n_theta, ek_min,
-                                _dp(h), _dp(mom))
+                                int(plane), _dp(h), _dp(mom))
         return h, mom

@@ -766,7 +766,7 @@ double orc_em_energy_total(const orc_sim *S) {
 }
 
 void orc_energy_angle(const orc_sim *S, int sp, int n_e, double emax,
-                      int n_theta, double ek_min, double *hist,
+                      int n_theta, double ek_min, int plane, double *hist,
                       double mom[5]) {
   const orc_species *p = &S->sp[sp];
   double dV = cell_volume(S);
@@ -776,7 +776,12 @@ void orc_energy_angle(const orc_sim *S, int sp, int n_e, double emax,
     if (!p->alive[i]) continue;
     double ux = p->ux[i], uy = p->uy[i], uz = p->uz[i];
     double ek = p->m * (sqrt(1.0 + ux * ux + uy * uy + uz * uz) - 1.0);
-    double th = atan2(sqrt(uy * uy + uz * uz), ux) * (180.0 / ORC_PI);
+    /* angle from +x of u (plane 0) or of its projection on the x-z (1) or
+     * x-y (2) plane */
+    double perp = plane == 1   ? fabs(uz)
+                  : plane == 2 ? fabs(uy)
+                               : sqrt(uy * uy + uz * uz);
+    double th = atan2(perp, ux) * (180.0 / ORC_PI);
     double wt = p->w * dV;
     long ie = (long)floor(ek / emax * n_e);
     long it = (long)floor(th / 180.0 * n_theta);

@@ -121,10 +121,13 @@ void orc_diagnostics(const orc_sim *S, double out[4]);
  * and B at t^{n-1/2}, each component at its own staggered node. */
 double orc_em_energy_total(const orc_sim *S);
 /* Energy-angle histogram (weights) over species sp: energy bins [0, emax)
- * linear, angle from +x in [0, 180] degrees.  mom: {sum w, <Ek>, <Ek^2>,
- * <theta>, <theta^2>} over particles with Ek > ek_min (theta in degrees). */
+ * linear, angle in [0, 180] degrees: from +x (plane 0), or of the momentum
+ * projected on the x-z plane (1; the plane across the LP polarization in
+ * which Sec. 4.2 bins its spectra) or on the x-y plane (2).  mom: {sum w,
+ * <Ek>, <Ek^2>, <theta>, <theta^2>} over particles with Ek > ek_min (theta
+ * in degrees). */
 void orc_energy_angle(const orc_sim *S, int sp, int n_e, double emax,
-                      int n_theta, double ek_min, double *hist,
+                      int n_theta, double ek_min, int plane, double *hist,
                       double mom[5]);
 
 /* ---- 3D3V step (sfpic_oracle3d.c) ----
@@ -163,7 +166,7 @@ void orc3_diagnostics(const orc3_sim *S, double out[4]);
 double orc3_em_energy_total(const orc3_sim *S);
 /* Energy-angle histogram, as orc_energy_angle, of a 3D species. */
 void orc3_energy_angle(const orc3_sim *S, int sp, int n_e, double emax,
-                       int n_theta, double ek_min, double *hist,
+                       int n_theta, double ek_min, int plane, double *hist,
                        double mom[5]);
 
 #ifdef __cplusplus

@@ -454,7 +454,7 @@ double orc3_em_energy_total(const orc3_sim *S) {
  * [0, emax) linear, angle from +x over [0, 180] degrees; mom = {sum w, <Ek>,
  * <Ek^2>, <theta>, <theta^2>} over particles with Ek > ek_min. */
 void orc3_energy_angle(const orc3_sim *S, int sp, int n_e, double emax,
-                       int n_theta, double ek_min, double *hist,
+                       int n_theta, double ek_min, int plane, double *hist,
                        double mom[5]) {
   const orc3_species *p = &S->sp[sp];
   const double dV = S->g.dx * S->g.dy * S->g.dz;
@@ -464,7 +464,14 @@ void orc3_energy_angle(const orc3_sim *S, int sp, int n_e, double emax,
     if (!p->alive[i]) continue;
     double ux = p->u[0][i], uy = p->u[1][i], uz = p->u[2][i];
     double ek = p->m * (sqrt(1.0 + ux * ux + uy * uy + uz * uz) - 1.0);
-    double th = atan2(sqrt(uy * uy + uz * uz), ux) * (180.0 / 3.14159265358979323846);
+    /* the angle from +x of the momentum, or of its projection on the x-z
+     * plane (plane 1: the plane of the propagation axis across the LP
+     * polarization, the paper's (y, z) plane of the Sec. 4.2 spectra) or on
+     * the x-y plane (plane 2) */
+    double perp = plane == 1   ? fabs(uz)
+                  : plane == 2 ? fabs(uy)
+                               : sqrt(uy * uy + uz * uz);
+    double th = atan2(perp, ux) * (180.0 / 3.14159265358979323846);
     double wt = p->w * dV;
     long ie = (long)floor(ek / emax * n_e);
     long it = (long)floor(th / 180.0 * n_theta);

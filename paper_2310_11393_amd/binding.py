@@ -111,7 +111,10 @@ class sfpic_diag(C.Structure):
 class sfpic_hist_spec(C.Structure):
     _fields_ = [("species", C.c_int32), ("n_energy", C.c_int32),
                 ("e_max", C.c_double), ("n_theta", C.c_int32),
-                ("ek_min", C.c_double)]
+                ("ek_min", C.c_double), ("plane", C.c_int32)]
+
+
+ANGLE_POLAR, ANGLE_XZ, ANGLE_XY = 0, 1, 2
 
 
 class sfpic_sim_desc(C.Structure):
@@ -129,7 +132,7 @@ class sfpic_result(C.Structure):
                 ("t_done", C.c_double), ("device_bytes", C.c_size_t)]
 
 
-MAX_GROUPS, MAX_CANDIDATES = 4, 16
+MAX_GROUPS, MAX_CANDIDATES = 4, 32
 _GI = C.c_int32 * MAX_GROUPS
 _GC = (C.c_int32 * MAX_CANDIDATES) * MAX_GROUPS
 
@@ -423,10 +426,11 @@ def _set_profile(sp, spec):
 
 
 def hist_spec(sp=0, n_e=256, emax=1.0, n_theta=180,
-              ek_min=1.0e3 / 510998.95) -> sfpic_hist_spec:
+              ek_min=1.0e3 / 510998.95, plane=ANGLE_POLAR) -> sfpic_hist_spec:
     """Energy-angle histogram: n_e energy bins over [0, emax) m_e c^2,
-    n_theta one-degree bins, moments over E_k > ek_min (default 1 keV)."""
-    return sfpic_hist_spec(sp, n_e, emax, n_theta, ek_min)
+    n_theta one-degree bins of the angle `plane` selects (ANGLE_*), moments
+    over E_k > ek_min (default 1 keV)."""
+    return sfpic_hist_spec(sp, n_e, emax, n_theta, ek_min, plane)
 
 
 class SimDesc:
@@ -579,8 +583,8 @@ class Simulation:
         return {f: getattr(d, f) for f, _ in sfpic_diag._fields_}
 
     def histogram(self, sp=0, n_e=256, emax=1.0, n_theta=180,
-                  ek_min=1.0e3 / 510998.95):
-        spec = sfpic_hist_spec(sp, n_e, emax, n_theta, ek_min)
+                  ek_min=1.0e3 / 510998.95, plane=ANGLE_POLAR):
+        spec = sfpic_hist_spec(sp, n_e, emax, n_theta, ek_min, plane)
         out = np.empty((n_e, n_theta))
         mom = np.empty(5)
         _check(lib().sfpic_histogram(self.h, C.byref(spec), _dp(out),
@@ -850,9 +854,10 @@ class Simulation3:
         return {f: getattr(d, f) for f, _ in sfpic_diag._fields_}
 
     def histogram(self, sp=0, n_e=256, emax=1.0, n_theta=180,
-                  ek_min=1.0e3 / 510998.95):
-        """(n_e, n_theta) energy-angle histogram and its moments."""
-        spec = sfpic_hist_spec(sp, n_e, emax, n_theta, ek_min)
+                  ek_min=1.0e3 / 510998.95, plane=ANGLE_POLAR):
+        """(n_e, n_theta) energy-angle histogram of the angle `plane`
+        selects (ANGLE_*) and its moments."""
+        spec = sfpic_hist_spec(sp, n_e, emax, n_theta, ek_min, plane)
         out = np.empty((n_e, n_theta))
         mom = np.empty(5)
         _check(lib().sfpic3_histogram(self.h, C.byref(spec), _dp(out),
@@ -870,3 +875,25 @@ class Simulation3:
     def set_state(self, state: bytes):
         buf = C.create_string_buffer(state, len(state))
         _check(lib().sfpic3_set_state(self.h, buf, len(state)))
+
+
+def detector_spectra(hist, angle_deg=20.0, half_width_deg=1.0):
+    """Electron energy spectra seen at `angle_deg` forward and backward
+    (Secs. 4.2 and 4.3: 20 degrees, in the plane across the polarization,
+    from a histogram with plane=ANGLE_XZ): the sums over the angle bins
+    inside [angle - w, angle + w) and [180 - angle - w, 180 - angle + w),
+    as two arrays over the energy bins.  The bin edges must fall on those
+    limits (n_theta a multiple of 180 / w)."""
+    n_t = hist.shape[1]
+    width = 180.0 / n_t
+
+    def cols(lo, hi):
+        a, b = lo / width, hi / width
+        if abs(a - round(a)) > 1e-9 or abs(b - round(b)) > 1e-9:
+            raise ValueError("angle limits do not fall on bin edges")
+        return slice(int(round(a)), int(round(b)))
+
+    fwd = cols(angle_deg - half_width_deg, angle_deg + half_width_deg)
+    back = cols(180.0 - angle_deg - half_width_deg,
+                180.0 - angle_deg + half_width_deg)
+    return hist[:, fwd].sum(axis=1), hist[:, back].sum(axis=1)

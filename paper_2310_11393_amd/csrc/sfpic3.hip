@@ -865,13 +865,17 @@ total_field3(F3<R> f, Geo g, IncParams inc, double z_focus, int c, double dx,
 template <typename R>
 __global__ void __launch_bounds__(256)
 hist3(Parts3<R> p, int64_t n, double m, double wdv, int n_e, double emax,
-      int n_t, double ek_min, double *hist, double *mom) {
+      int n_t, double ek_min, int plane, double *hist, double *mom) {
   const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= n || p.x[0][s] < -1.0) return;
   const double ux = ld(p.u[0], s), uy = ld(p.u[1], s), uz = ld(p.u[2], s);
   const double ek = m * (sqrt(1.0 + ux * ux + uy * uy + uz * uz) - 1.0);
-  const double th =
-      atan2(sqrt(uy * uy + uz * uz), ux) * (180.0 / 3.14159265358979323846);
+  // polar angle from +x, or of the momentum projected on the x-z (plane 1)
+  // or x-y (plane 2) plane
+  const double perp = plane == 1   ? fabs(uz)
+                      : plane == 2 ? fabs(uy)
+                                   : sqrt(uy * uy + uz * uz);
+  const double th = atan2(perp, ux) * (180.0 / 3.14159265358979323846);
   if (!isfinite(ek) || !isfinite(th)) return;
   const double ie = floor(ek / emax * n_e);
   const double tt = fmin(floor(th / 180.0 * n_t), (double)(n_t - 1));
@@ -1599,7 +1603,8 @@ int sfpic3_histogram(sfpic3_sim *sim, const sfpic_hist_spec *spec,
   sfpic::ErrScope es_(sim);
   if (!sim || !spec || !out) return sfpic::fail(SFPIC_E_INVAL, "NULL argument");
   if (spec->species < 0 || spec->species >= (int)sim->sp.size() ||
-      spec->n_energy <= 0 || spec->n_theta <= 0 || !(spec->e_max > 0.0))
+      spec->n_energy <= 0 || spec->n_theta <= 0 || !(spec->e_max > 0.0) ||
+      spec->plane < SFPIC_ANGLE_POLAR || spec->plane > SFPIC_ANGLE_XY)
     return sfpic::fail(SFPIC_E_INVAL, "bad histogram spec");
   const size_t nb = (size_t)spec->n_energy * spec->n_theta;
   if (n != nb) return sfpic::fail(SFPIC_E_SIZE, "n must be n_energy * n_theta");
@@ -1614,11 +1619,11 @@ int sfpic3_histogram(sfpic3_sim *sim, const sfpic_hist_spec *spec,
     if (sim->fp32)
       hist3<float><<<blocks_for(sp.n), 256, 0, sim->st>>>(
           parts_as<float>(sp.p), sp.n, sp.m, wdv, spec->n_energy,
-          spec->e_max, spec->n_theta, spec->ek_min, d + 8, d);
+          spec->e_max, spec->n_theta, spec->ek_min, spec->plane, d + 8, d);
     else
       hist3<double><<<blocks_for(sp.n), 256, 0, sim->st>>>(
           sp.p, sp.n, sp.m, wdv, spec->n_energy, spec->e_max, spec->n_theta,
-          spec->ek_min, d + 8, d);
+          spec->ek_min, spec->plane, d + 8, d);
     if (hipGetLastError() != hipSuccess) rc = -1;
   }
   if (!rc && (hipMemcpyAsync(out, d + 8, nb * 8, hipMemcpyDeviceToHost,

@@ -397,6 +397,8 @@ april_blocks_series(double a_over_s, double inv_s, int s_int,
 
 // Complex fields in the paper's axes at dimensionless (X, Y, Z) and tau, with
 // the normalization N folded in.  e[0..2] = E_x, E_y, E_z; b[0..2] = cB.
+// KIND: 2 (LP) or 3 (RP) fixed at compile time, 0 read from P.kind.
+template <int KIND = 0>
 __host__ __device__ inline void april_complex_fields(const IncParams &P,
                                                      double X, double Y,
                                                      double Z, double tau,
@@ -410,7 +412,7 @@ __host__ __device__ inline void april_complex_fields(const IncParams &P,
                                             tau)
                       : april_blocks_closed(P, u2, tau);
   cx<double> zp = mk(Z, 1.0);
-  if (P.kind == 2) {  // LP
+  if ((KIND ? KIND : P.kind) == 2) {  // LP
     cx<double> common = k.d1 - k.phitt + zp * k.d1t;
     e[0] = (X * X) * k.d2 + common;
     e[1] = (X * Y) * k.d2;
@@ -458,27 +460,32 @@ gauss2d_field(const IncParams &P, int dims, double x, double y, double t) {
 // (x, y, z = 0) and time t.  kGauss = false compiles the plane pulse and the
 // April beams only: the push kernels of those models are built without the
 // Gaussian beam's code, which would otherwise cost them registers.
-template <bool kGauss>
+//
+// KIND fixes the model at compile time (1 plane pulse, 2 April LP, 3 April
+// RP; 0: the model P.kind names): a push compiled for one model carries
+// neither the other models' code nor their parameters.
+template <bool kGauss, int KIND = 0>
 __host__ __device__ inline void incident_field_t(const IncParams &P, int dims,
                                                  double x, double y, double t,
                                                  double E[3], double B[3]) {
   E[0] = E[1] = E[2] = 0.0;
   B[0] = B[1] = B[2] = 0.0;
-  if (P.kind == 1) {
+  const int kind = KIND ? KIND : P.kind;
+  if (kind == 1) {
     double ph = t - P.t0 - x;
     double v = P.a0 * sin(ph) * exp2(P.env_k * ph * ph);
     E[1] = v;
     B[2] = v;
-  } else if (kGauss && P.kind == 4) {
+  } else if (kGauss && kind == 4) {
     const Gauss2 g = gauss2d_field(P, dims, x, y, t);
     E[0] = g.ex;
     E[1] = g.ey;
     B[2] = g.ey;
-  } else if (P.kind == 2 || P.kind == 3) {
+  } else if (kind == 2 || kind == 3) {
     double X = (dims == 2 ? (y - P.y_focus) : 0.0) * P.inv_a;  // paper x
     double Z = (x - P.x_focus) * P.inv_a;                       // paper z
     cx<double> e[3], b[3];
-    april_complex_fields(P, X, 0.0, Z, t - P.t_focus, e, b);
+    april_complex_fields<KIND>(P, X, 0.0, Z, t - P.t_focus, e, b);
     E[0] = e[2].r;  // build x = paper z
     E[1] = e[0].r;  // build y = paper x
     E[2] = e[1].r;  // build z = paper y
@@ -498,13 +505,14 @@ __host__ __device__ inline void incident_field(const IncParams &P, int dims,
 // Incident field for the FP32 form: the phase (positions, time, u, tau +-
 // a u_r, the plane pulse's carrier phase after range reduction) and the ring
 // neighbourhood in FP64, the powers, blocks and fields in FP32.
-template <bool kGauss>
+template <bool kGauss, int KIND = 0>
 __device__ inline void incident_field_fp32(const IncParams &P, int dims,
                                            double x, double y, double t,
                                            float E[3], float B[3]) {
   E[0] = E[1] = E[2] = 0.0f;
   B[0] = B[1] = B[2] = 0.0f;
-  if (P.kind == 1) {
+  const int kind = KIND ? KIND : P.kind;
+  if (kind == 1) {
     const double ph = t - P.t0 - x;
     const double two_pi = 6.283185307179586;
     const double r = ph - two_pi * rint(ph * (1.0 / two_pi));  // |r| <= pi
@@ -514,21 +522,21 @@ __device__ inline void incident_field_fp32(const IncParams &P, int dims,
     B[2] = v;
     return;
   }
-  if (kGauss && P.kind == 4) {  // the FP64 closed form, rounded
+  if (kGauss && kind == 4) {  // the FP64 closed form, rounded
     const Gauss2 g = gauss2d_field(P, dims, x, y, t);
     E[0] = (float)g.ex;
     E[1] = (float)g.ey;
     B[2] = (float)g.ey;
     return;
   }
-  if (P.kind != 2 && P.kind != 3) return;
+  if (kind != 2 && kind != 3) return;
   const double X = (dims == 2 ? (y - P.y_focus) : 0.0) * P.inv_a;
   const double Z = (x - P.x_focus) * P.inv_a;
   const double tau = t - P.t_focus;
   const cx<double> u2 = mk(X * X + Z * Z - 1.0, 2.0 * Z);
   if (u2.r * u2.r + u2.i * u2.i < kRingU2 * kRingU2) {
     double Ed[3], Bd[3];
-    incident_field_t<false>(P, dims, x, y, t, Ed, Bd);
+    incident_field_t<false, KIND>(P, dims, x, y, t, Ed, Bd);
     for (int c = 0; c < 3; ++c) {
       E[c] = (float)Ed[c];
       B[c] = (float)Bd[c];
@@ -542,7 +550,7 @@ __device__ inline void incident_field_fp32(const IncParams &P, int dims,
       mk((float)wm.r, (float)wm.i));
   const float Xf = (float)X;
   const cx<float> zp = mk((float)Z, 1.0f);
-  if (P.kind == 2) {  // LP, paper y = 0: E_x, E_z, cB_y
+  if (kind == 2) {  // LP, paper y = 0: E_x, E_z, cB_y
     const cx<float> common = k.d1 - k.phitt + zp * k.d1t;
     const cx<float> ex = (Xf * Xf) * k.d2 + common;
     const cx<float> ez = Xf * (zp * k.d2) - Xf * k.d1t;
@@ -657,8 +665,8 @@ template <typename R>
 hipError_t launch_histogram(const Particles<R> &p, int64_t n,
                             const uint32_t *n_valid, int dims, double m,
                             double wdv, int n_e, double emax, int n_t,
-                            double ek_min, double *hist, double *mom,
-                            hipStream_t st);
+                            double ek_min, int plane, double *hist,
+                            double *mom, hipStream_t st);
 
 // Batched launches (one per phase for the whole group).  `grid` of the push
 // is the number of persistent workgroups pulling tiles from the queue.

@@ -715,17 +715,27 @@ hipError_t launch_gauss(const Fields<R> &f, int dims, int nx, int ny,
   return hipGetLastError();
 }
 
+// The angle from +x that a histogram bins (degrees): polar (plane 0), or
+// of the momentum projected on the x-z (1) or x-y (2) plane.
+__device__ __forceinline__ double hist_angle(int plane, double ux, double uy,
+                                             double uz) {
+  const double perp = plane == 1   ? fabs(uz)
+                      : plane == 2 ? fabs(uy)
+                                   : sqrt(uy * uy + uz * uz);
+  return atan2(perp, ux) * (180.0 / 3.14159265358979323846);
+}
+
 template <typename R>
 __global__ void histogram(Particles<R> p, int64_t n, const uint32_t *n_valid,
                           int dims, double m, double wdv, int n_e, double emax,
-                          int n_t, double ek_min, double *hist, double *mom) {
+                          int n_t, double ek_min, int plane, double *hist,
+                          double *mom) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   double xi, yi;
   if (i >= n || i >= (int64_t)*n_valid || !pos_of(p, i, dims, xi, yi)) return;
   const double ux = p.ux[i], uy = p.uy[i], uz = p.uz[i];
   const double ek = m * (sqrt(1.0 + ux * ux + uy * uy + uz * uz) - 1.0);
-  const double th =
-      atan2(sqrt(uy * uy + uz * uz), ux) * (180.0 / 3.14159265358979323846);
+  const double th = hist_angle(plane, ux, uy, uz);
   if (!isfinite(ek) || !isfinite(th)) return;
   const double ie = floor(ek / emax * n_e);
   const double tt = fmin(floor(th / 180.0 * n_t), (double)(n_t - 1));
@@ -744,11 +754,11 @@ template <typename R>
 hipError_t launch_histogram(const Particles<R> &p, int64_t n,
                             const uint32_t *n_valid, int dims, double m,
                             double wdv, int n_e, double emax, int n_t,
-                            double ek_min, double *hist, double *mom,
-                            hipStream_t st) {
+                            double ek_min, int plane, double *hist,
+                            double *mom, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   histogram<R><<<(unsigned)((n + 255) / 256), 256, 0, st>>>(
-      p, n, n_valid, dims, m, wdv, n_e, emax, n_t, ek_min, hist, mom);
+      p, n, n_valid, dims, m, wdv, n_e, emax, n_t, ek_min, plane, hist, mom);
   return hipGetLastError();
 }
 
@@ -822,7 +832,7 @@ hipError_t launch_export_particles(const Particles<R> &p, int64_t n, int dims,
                                             double *, int, hipStream_t);      \
   template hipError_t launch_histogram<R>(                                   \
       const Particles<R> &, int64_t, const uint32_t *, int, double, double,   \
-      int, double, int, double, double *, double *, hipStream_t);             \
+      int, double, int, double, int, double *, double *, hipStream_t);      \
   template hipError_t launch_export_particles<R>(                            \
       const Particles<R> &, int64_t, int, double, double, double *,           \
       uint32_t *, hipStream_t);                                               \

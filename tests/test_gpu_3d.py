@@ -330,6 +330,45 @@ def test_3d_histogram_parity(prec):
 
 
 @pytest.mark.parametrize("prec", [0, 1])
+def test_3d_detector_spectra_parity(prec):
+    """The Sec. 4.2 / 4.3 view: the histogram of the angle that the
+    momentum projected on the plane across the LP polarization (x-z here)
+    makes with the propagation axis, and from it the spectra 20 degrees
+    forward and backward (1-degree bins, +-1 degree), against the
+    oracle's: total weight to 1e-12, well-filled bins (10-degree
+    groups) and the two spectra within 1% plus two macro-particles, moments
+    to 1e-9 (FP64) or 1e-4."""
+    from paper_2310_11393_amd.binding import (ANGLE_XZ, Simulation3,
+                                              detector_spectra)
+    g, inc, sp, steps = _case("lp3d")
+    o = _oracle(g, inc, sp)
+    G = Simulation3(g, inc, explicit=sp, precision=prec)
+    o.step(steps)
+    G.step(steps)
+    # energies up to four times the oracle's mean kinetic energy
+    _, m0 = o.energy_angle(n_e=1, emax=10.0, n_theta=1, ek_min=0.0)
+    kw = dict(n_e=24, emax=4.0 * m0[1], n_theta=180, ek_min=0.0)
+    hg, mg = G.histogram(plane=ANGLE_XZ, **kw)
+    ho, mo = o.energy_angle(plane=ANGLE_XZ, **kw)
+    w1 = sp[0]["weight"] * g.dx * g.dy * g.dz
+    assert ho.sum() > 0 and abs(hg.sum() - ho.sum()) <= 1e-12 * ho.sum()
+    # well-filled bins of the histogram in 10-degree angle bins
+    cg, co = hg.reshape(24, 18, 10).sum(2), ho.reshape(24, 18, 10).sum(2)
+    big = co > 0.01 * co.sum()
+    assert big.sum() >= 3
+    assert np.all(np.abs(cg[big] - co[big]) <= 0.01 * co[big] + 2 * w1)
+    assert np.allclose(mg, mo, rtol=1e-9 if prec == 0 else 1e-4, atol=0)
+    fg, bg = detector_spectra(hg)
+    fo, bo = detector_spectra(ho)
+    print(f"[3d spectra] prec {prec}: 20 deg forward "
+          f"{fo.sum() / w1:.0f} particles, backward {bo.sum() / w1:.0f}",
+          flush=True)
+    assert fo.sum() >= 5 * w1 and bo.sum() >= 5 * w1
+    for a, b in ((fg, fo), (bg, bo)):
+        assert np.all(np.abs(a - b) <= 0.01 * b + 2 * w1)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
 def test_3d_checkpoint_resume(prec):
     """A run resumed from a checkpoint in a fresh simulation ends where the
     uninterrupted run ends (to rounding: the current is summed with

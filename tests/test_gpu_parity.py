@@ -244,15 +244,18 @@ def test_checkpoint_roundtrip():
     assert np.array_equal(np.sort(pa[5]), np.sort(pb[5]))
 
 
-def test_histogram_parity():
+@pytest.mark.parametrize("plane", [0, 1, 2])
+def test_histogram_parity(plane):
+    """The energy-angle histogram (polar angle, or the angle in the x-z or
+    x-y plane) against the oracle's after 50 steps."""
     work = _small_lp(a0=20.0)
     sp = explicit_species(work)
     g = make_gpu(work, sp)
     o = make_oracle(work, sp)
     g.step(50)
     o.step(50)
-    hg, mg = g.histogram(n_e=64, emax=2.0, n_theta=36)
-    ho, mo = o.energy_angle(n_e=64, emax=2.0, n_theta=36)
+    hg, mg = g.histogram(n_e=64, emax=2.0, n_theta=36, plane=plane)
+    ho, mo = o.energy_angle(n_e=64, emax=2.0, n_theta=36, plane=plane)
     assert abs(hg.sum() - ho.sum()) <= 1e-12 * ho.sum()
     big = ho > 0.01 * ho.sum()
     assert np.all(np.abs(hg[big] - ho[big]) <= 0.01 * ho[big])

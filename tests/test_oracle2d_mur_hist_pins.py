@@ -3,7 +3,9 @@ faces and corners.
 
   * Histogram (the Sec. 4.2 energy-angle spectra): particles of known
     momentum land in the bins that their kinetic energy m (gamma - 1) and
-    their angle from the propagation axis +x put them in, with weight w dV
+    their angle from the propagation axis +x put them in (the polar angle,
+    or in the x-z or x-y plane the angle of the projected momentum), with
+    weight w dV
     (dV = dx dy in 2D, dx in 1D); the moments are the weighted means over
     particles above the energy cut; removed particles and energies beyond
     the last bin are handled as the definitions say.
@@ -24,7 +26,8 @@ faces and corners.
         plus a discretization margin.
   * Planted mistakes (a y-face Mur coefficient taken from the x axis, the
     corner nodes left out of the corner rule, a histogram angle measured
-    from +y) are compiled into copies of the oracle and must fail a pin.
+    from +y, the x-z view projecting on y) are compiled into copies of the
+    oracle and must fail a pin.
 """
 import math
 import os
@@ -48,10 +51,18 @@ ROOT = os.path.dirname(HERE)
 # Energy-angle histogram
 # ---------------------------------------------------------------------------
 
-def _expected_histogram(u, w, dV, n_e, emax, n_t, ek_min, alive):
+def _angle(u, plane):
+    """Angle from +x of the momentum (plane 0) or of its projection on the
+    x-z (1) or x-y (2) plane, in degrees."""
+    perp = {0: np.hypot(u[:, 1], u[:, 2]), 1: np.abs(u[:, 2]),
+            2: np.abs(u[:, 1])}[plane]
+    return np.degrees(np.arctan2(perp, u[:, 0]))
+
+
+def _expected_histogram(u, w, dV, n_e, emax, n_t, ek_min, alive, plane=0):
     want = np.zeros((n_e, n_t))
     ek = np.sqrt(1.0 + (u ** 2).sum(1)) - 1.0
-    th = np.degrees(np.arctan2(np.hypot(u[:, 1], u[:, 2]), u[:, 0]))
+    th = _angle(u, plane)
     for e, t, a in zip(ek, th, alive):
         if not a:
             continue
@@ -68,8 +79,9 @@ def _expected_histogram(u, w, dV, n_e, emax, n_t, ek_min, alive):
     return want, np.array(mom)
 
 
+@pytest.mark.parametrize("plane", [0, 1, 2])
 @pytest.mark.parametrize("dims", [1, 2])
-def test_energy_angle_histogram_of_known_particles(dims):
+def test_energy_angle_histogram_of_known_particles(dims, plane):
     dx, dy = 0.3, 0.45
     grid = wl.Grid(dims, 10, 8 if dims == 2 else 1, dx, dy, 0.1)
     u = np.array([[1.0, 0.0, 0.0],     # E_k = sqrt(2) - 1, theta = 0
@@ -93,11 +105,26 @@ def test_energy_angle_histogram_of_known_particles(dims):
     p = sim.particles()
     sim.set_particles(0, *p[:5], alive)
     n_e, emax, n_t, ek_min = 40, 2.0, 36, 1e-3
-    h, mom = sim.energy_angle(n_e=n_e, emax=emax, n_theta=n_t, ek_min=ek_min)
+    h, mom = sim.energy_angle(n_e=n_e, emax=emax, n_theta=n_t, ek_min=ek_min,
+                              plane=plane)
     dV = dx * dy if dims == 2 else dx
     want, want_mom = _expected_histogram(u, w, dV, n_e, emax, n_t, ek_min,
-                                         alive)
+                                         alive, plane)
     assert np.array_equal(h, want)
+    # angles that the planes must give: u = (0.3, -0.4, 0) is at
+    # atan2(0.4, 0.3) = 53.13 degrees from +x in the polar and x-y views and
+    # at 0 in the x-z view; u = (0.3, 0, 0.4) the other way round
+    k53 = math.floor(math.degrees(math.atan2(0.4, 0.3)) / 180 * n_t)
+    e_k = math.sqrt(1.25) - 1.0
+    ie = math.floor(e_k / emax * n_e)
+    both = h[ie, k53], h[ie, 0]
+    w1 = w * dV
+    # (0, 0.5, 0) and (0, 0, -0.5) have the same energy: 90 degrees in the
+    # polar view, 0 in the view whose plane is across them
+    if plane == 0:
+        assert both == (2 * w1, 0.0)
+    else:
+        assert both == (w1, 2 * w1)
     assert h.sum() == pytest.approx(8 * w * dV, rel=1e-15)
     np.testing.assert_allclose(mom, want_mom, rtol=1e-14, atol=0)
 
@@ -236,8 +263,13 @@ MISTAKES = {
         "test_mur_corner_nodes_follow_the_outgoing_wave"),
     # histogram angle measured from +y instead of the propagation axis
     "histogram_angle_axis": (
-        [("double th = atan2(sqrt(uy * uy + uz * uz), ux)",
-          "double th = atan2(sqrt(ux * ux + uz * uz), uy)")],
+        [("double th = atan2(perp, ux) * (180.0 / ORC_PI);",
+          "double th = atan2(perp, uy) * (180.0 / ORC_PI);")],
+        "test_energy_angle_histogram_of_known_particles"),
+    # the x-z view projecting on the wrong transverse axis
+    "histogram_plane_axis": (
+        [("double perp = plane == 1   ? fabs(uz)",
+          "double perp = plane == 1   ? fabs(uy)")],
         "test_energy_angle_histogram_of_known_particles"),
 }
 

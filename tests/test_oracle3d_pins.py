@@ -231,9 +231,12 @@ def test_free_particle_streams_and_leaves():
     assert not sim.particles()[6][0]
 
 
-def test_energy_angle_histogram_of_known_particles():
+@pytest.mark.parametrize("plane", [0, 1, 2])
+def test_energy_angle_histogram_of_known_particles(plane):
     """Particles of known momentum land in the bins their kinetic energy
-    m (gamma - 1) and angle from +x put them in, weighted by w dV."""
+    m (gamma - 1) and angle from +x put them in, weighted by w dV: the polar
+    angle (plane 0) or, in the x-z (1) or x-y (2) plane, the angle of the
+    projected momentum."""
     g = grid3(8, 8, 8)
     u = np.array([[1.0, 0.0, 0.0],    # E_k = sqrt(2) - 1, theta = 0
                   [0.0, 0.5, 0.0],    # theta = 90
@@ -245,10 +248,13 @@ def test_energy_angle_histogram_of_known_particles():
     sim.add_species(-1.0, 1.0, w, x, x * g.dy / g.dx, x * g.dz / g.dx,
                     *u.T)
     n_e, emax, n_t = 40, 2.0, 36
-    h, mom = sim.energy_angle(n_e=n_e, emax=emax, n_theta=n_t, ek_min=0.0)
+    h, mom = sim.energy_angle(n_e=n_e, emax=emax, n_theta=n_t, ek_min=0.0,
+                              plane=plane)
     dV = g.dx * g.dy * g.dz
     ek = np.sqrt(1.0 + (u ** 2).sum(1)) - 1.0
-    th = np.degrees(np.arctan2(np.hypot(u[:, 1], u[:, 2]), u[:, 0]))
+    perp = {0: np.hypot(u[:, 1], u[:, 2]), 1: np.abs(u[:, 2]),
+            2: np.abs(u[:, 1])}[plane]
+    th = np.degrees(np.arctan2(perp, u[:, 0]))
     want = np.zeros((n_e, n_t))
     for e, t in zip(ek, th):
         want[int(e / emax * n_e), min(int(t / 180 * n_t), n_t - 1)] += w * dV
