@@ -29,6 +29,9 @@ namespace {
 
 using Clock = std::chrono::steady_clock;
 
+// Steps between the autotuner's re-timings of the sort cadence in a batch.
+constexpr int64_t kRetuneSteps = 256;
+
 double seconds_since(Clock::time_point t0) {
   return std::chrono::duration<double>(Clock::now() - t0).count();
 }
@@ -68,7 +71,8 @@ int check_desc(const sfpic_sim_desc *d) {
     return fail(SFPIC_E_INVAL, "nspecies must be in [0, 8]");
   if (d->hist.n_energy > 0 &&
       (d->hist.species < 0 || d->hist.species >= d->nspecies ||
-       d->hist.n_theta <= 0 || !(d->hist.e_max > 0.0)))
+       d->hist.n_theta <= 0 || !(d->hist.e_max > 0.0) ||
+       d->hist.plane < SFPIC_ANGLE_POLAR || d->hist.plane > SFPIC_ANGLE_XY))
     return fail(SFPIC_E_INVAL, "bad histogram spec");
   if (d->incident.on_nodes)
     return fail(SFPIC_E_INVAL,
@@ -89,9 +93,12 @@ struct Group {
   int precision = SFPIC_FP64, dims = 2;
   std::vector<Member *> members;
   int tx = 0, ty = 0;
-  // sort cadence: measured on the laser-focus sweep, every 4 steps beats
-  // 8 once the beam has heated the plasma (most of a run)
+  // sort cadence: the default 4 (measured on the laser-focus sweep: every
+  // 4 steps beats 8 once the beam has heated the plasma); the autotuner
+  // times 2, 4 and 8 on the run's own steps and re-times them as the run
+  // goes on, unless the runtime fixed it
   SortRule rule{4};
+  bool cadence_fixed = false;
   int graph_steps = 8;  // steps per captured graph (a tick of the server)
   bool tuned = false;
   struct Trial {
@@ -173,7 +180,10 @@ struct Engine {
     Group &g = groups.back();
     g.precision = precision;
     g.dims = dims;
-    if (rt.sort_every > 0) g.rule = SortRule{rt.sort_every};
+    if (rt.sort_every > 0) {
+      g.rule = SortRule{rt.sort_every};
+      g.cadence_fixed = true;
+    }
     return g;
   }
 
@@ -474,10 +484,82 @@ struct Engine {
     return p;
   }
 
-  // Autotuner: the particle tile, each candidate timed on real super-steps
-  // of the run (graph_steps steps, the group's sort rule) in `rounds`
-  // passes of alternating order, so that the slow drift of the particle
-  // distribution during the run does not favour one candidate.
+  // One autotuner trial: the next super-step of the run (graph_steps real
+  // steps, eager launches) with tile tx x ty (members re-tiled if it
+  // changes) and the group's current sort cadence, timed with events;
+  // ns = nanoseconds per particle push (-1 when no member has steps left).
+  int trial(Group &g, int tx, int ty, hipEvent_t e0, hipEvent_t e1,
+            double &ns) {
+    SF_TRY(pull(g));
+    if (tx != g.tx || ty != g.ty) {
+      for (Member *m : g.members) SF_TRY(sim_retile(m->sim, tx, ty, 0));
+      g.tx = tx;
+      g.ty = ty;
+    }
+    g.stale = true;
+    SF_TRY(build(g));
+    const double pushes = superstep_pushes(g);
+    if (pushes <= 0.0) {
+      ns = -1.0;
+      return SFPIC_OK;
+    }
+    HIP_TRY(hipEventRecord(e0, stream));
+    g.ran = true;
+    SF_TRY(enqueue_superstep(g, g.graph_steps));
+    HIP_TRY(hipEventRecord(e1, stream));
+    HIP_TRY(hipEventSynchronize(e1));
+    float ms = 0.0f;
+    HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+    ns = ms * 1e6 / pushes;
+    g.trials.push_back({tx, ty, g.rule.c_max, ns});
+    return SFPIC_OK;
+  }
+
+  // Time each candidate in `rounds` passes of alternating order (the slow
+  // drift of the particle distribution during the run then favours none)
+  // and return the index with the lowest mean time per push (-1: none ran).
+  // set(k) makes candidate k current before its trial.
+  template <typename Set>
+  int best_of(Group &g, size_t n, int rounds, Set set, int &r) {
+    hipEvent_t e0, e1;
+    r = SFPIC_OK;
+    if (hipEventCreate(&e0) != hipSuccess) {
+      r = fail(SFPIC_E_DEVICE, "hipEventCreate failed");
+      return -1;
+    }
+    if (hipEventCreate(&e1) != hipSuccess) {
+      (void)hipEventDestroy(e0);
+      r = fail(SFPIC_E_DEVICE, "hipEventCreate failed");
+      return -1;
+    }
+    std::vector<double> sum(n, 0.0);
+    std::vector<int> cnt(n, 0);
+    for (int round = 0; round < rounds && r == SFPIC_OK; ++round)
+      for (size_t q = 0; q < n && r == SFPIC_OK; ++q) {
+        const size_t k = round % 2 == 0 ? q : n - 1 - q;
+        int tx = g.tx, ty = g.ty;
+        set(k, tx, ty);
+        double ns = 0.0;
+        r = trial(g, tx, ty, e0, e1, ns);
+        if (ns > 0.0) {
+          sum[k] += ns;
+          cnt[k] += 1;
+        }
+      }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    int bt = -1;
+    double best = 1e300;
+    for (size_t k = 0; k < n; ++k)
+      if (cnt[k] > 0 && sum[k] / cnt[k] < best) {
+        best = sum[k] / cnt[k];
+        bt = (int)k;
+      }
+    return bt;
+  }
+
+  // Autotuner: the particle tile, then the sort cadence, each candidate
+  // timed on real super-steps of the run (graph_steps steps).
   int tune(Group &g, int rounds) {
     std::vector<std::pair<int, int>> tiles;
     if (g.dims == 2)
@@ -496,72 +578,42 @@ struct Engine {
       if (l <= max_lds) ok.push_back(t);
     }
     if (ok.empty()) return SFPIC_OK;
-    hipEvent_t e0, e1;
-    HIP_TRY(hipEventCreate(&e0));
-    HIP_TRY(hipEventCreate(&e1));
-    const int c = g.rule.c_max;
-    auto trial = [&](int tx, int ty, double &ns) -> int {
-      SF_TRY(pull(g));
-      if (tx != g.tx || ty != g.ty) {
-        for (Member *m : g.members) SF_TRY(sim_retile(m->sim, tx, ty, 0));
-        g.tx = tx;
-        g.ty = ty;
-      }
-      g.stale = true;
-      SF_TRY(build(g));
-      const double pushes = superstep_pushes(g);
-      if (pushes <= 0.0) {
-        ns = -1.0;
-        return SFPIC_OK;
-      }
-      HIP_TRY(hipEventRecord(e0, stream));
-      g.ran = true;
-      SF_TRY(enqueue_superstep(g, g.graph_steps));
-      HIP_TRY(hipEventRecord(e1, stream));
-      HIP_TRY(hipEventSynchronize(e1));
-      float ms = 0.0f;
-      HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-      ns = ms * 1e6 / pushes;
-      g.trials.push_back({tx, ty, c, ns});
-      return SFPIC_OK;
-    };
-    const size_t n = ok.size();
-    std::vector<double> sum(n, 0.0);
-    std::vector<int> cnt(n, 0);
     int r = SFPIC_OK;
-    for (int round = 0; round < rounds && r == SFPIC_OK; ++round)
-      for (size_t q = 0; q < n && r == SFPIC_OK; ++q) {
-        const size_t k = round % 2 == 0 ? q : n - 1 - q;
-        double ns = 0.0;
-        r = trial(ok[k].first, ok[k].second, ns);
-        if (ns > 0.0) {
-          sum[k] += ns;
-          cnt[k] += 1;
-        }
-      }
-    if (r == SFPIC_OK) {
-      size_t bt = 0;
-      double best = 1e300;
-      for (size_t k = 0; k < n; ++k)
-        if (cnt[k] > 0 && sum[k] / cnt[k] < best) {
-          best = sum[k] / cnt[k];
-          bt = k;
-        }
-      r = pull(g);
-      if (r == SFPIC_OK && (ok[bt].first != g.tx || ok[bt].second != g.ty)) {
-        for (Member *m : g.members) {
-          r = sim_retile(m->sim, ok[bt].first, ok[bt].second, 0);
-          if (r != SFPIC_OK) break;
-        }
-        g.tx = ok[bt].first;
-        g.ty = ok[bt].second;
-      }
-      g.tuned = r == SFPIC_OK;
-      g.stale = true;
+    const int bt = best_of(g, ok.size(), rounds,
+                           [&](size_t k, int &tx, int &ty) {
+                             tx = ok[k].first;
+                             ty = ok[k].second;
+                           },
+                           r);
+    if (r != SFPIC_OK) return r;
+    SF_TRY(pull(g));
+    if (bt >= 0 && (ok[bt].first != g.tx || ok[bt].second != g.ty)) {
+      for (Member *m : g.members)
+        SF_TRY(sim_retile(m->sim, ok[bt].first, ok[bt].second, 0));
+      g.tx = ok[bt].first;
+      g.ty = ok[bt].second;
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    return r;
+    g.tuned = true;
+    g.stale = true;
+    if (!g.cadence_fixed) SF_TRY(tune_cadence(g, rounds));
+    return SFPIC_OK;
+  }
+
+  // The sort cadence among 2, 4 and 8 steps, timed on the run's next
+  // super-steps with the group's tile (each trial a super-step of 8 steps,
+  // so every candidate sorts at least once in it).
+  int tune_cadence(Group &g, int rounds) {
+    static const int kCadences[3] = {2, 4, 8};
+    int r = SFPIC_OK;
+    const int bc = best_of(g, 3, rounds,
+                           [&](size_t k, int &, int &) {
+                             g.rule = SortRule{kCadences[k]};
+                           },
+                           r);
+    if (r != SFPIC_OK) return r;
+    if (bc >= 0) g.rule = SortRule{kCadences[bc]};
+    g.stale = true;
+    return SFPIC_OK;
   }
 
   // Result of a finished member (diagnostics and histogram on the stream).
@@ -651,23 +703,30 @@ int batch_run_impl(sfpic_batch *b) {
       longest = std::max<int64_t>(longest, m->nsteps - m->done);
     const int rounds = longest >= 256 ? 2 : (longest >= 128 ? 1 : 0);
     if (autotune && rounds > 0) SF_TRY(eng.tune(g, rounds));
+    // the particles heat and spread as the run goes on, which moves the
+    // best cadence: re-time the cadences every kRetuneSteps steps
+    const bool retune = autotune && rounds > 0 && !g.cadence_fixed;
+    const int64_t chunk = kRetuneSteps / g.graph_steps;
     for (;;) {
       SF_TRY(eng.pull(g));
       bool any = false;
       for (Member *m : g.members) any = any || Engine::running(m);
       if (!any) break;
-      // all remaining super-steps back to back, then one pull
       int64_t left = 0;
       for (Member *m : g.members) {
         const int64_t l = m->nsteps - m->done;
         left = l > left ? l : left;
       }
-      const int64_t reps = (left + g.graph_steps - 1) / g.graph_steps;
+      int64_t reps = (left + g.graph_steps - 1) / g.graph_steps;
+      // enough steps after this chunk for a cadence pass and a chunk more
+      const bool again = retune && reps > chunk + 3 + chunk / 2;
+      if (again) reps = chunk;
+      // these super-steps back to back, then one pull
       for (int64_t k = 0; k < reps; ++k) {
         SF_TRY(eng.launch_superstep(g));
       }
-      // account: every member runs to its end inside these super-steps
       SF_TRY(eng.pull(g));
+      if (again) SF_TRY(eng.tune_cadence(g, 1));
     }
   }
   HIP_TRY(hipEventRecord(ee, eng.stream));

@@ -135,9 +135,10 @@ def test_fp32_batch_member_equals_its_run_alone():
 
 def test_autotuned_fp32_batch():
     """Runs long enough are tuned on their own first steps: every tile
-    candidate is timed on real steps (two passes for runs of 256 steps or
-    more), members are re-tiled in between, and the result still equals
-    each member's run alone."""
+    candidate, then every sort cadence (2, 4, 8) is timed on real steps (two
+    passes each for runs of 256 steps or more), members are re-tiled in
+    between, the fastest candidates are the ones used, and the result still
+    equals each member's run alone."""
     members = [_lp(precision=wl.FP32, seed=31),
                _lp(kind=wl.INC_APRIL_RP, w0_lambda=0.8, s=10.0, a0=30.0,
                    temperature_ev=0.0, nx=96, ny=96, plasma=(30, 70, 20, 80),
@@ -149,10 +150,23 @@ def test_autotuned_fp32_batch():
     g = st["groups"][0]
     _note(f"[batch] tuned: tile {g['tile']} cadence {g['sort_every']} "
           f"trials {g['trials']}")
-    assert g["tuned"] and len(g["trials"]) == 4 * 2
-    assert g["tile"] in [t[0] for t in g["trials"]]
-    assert g["sort_every"] == 4 and all(t[1] == 4 for t in g["trials"])
+    assert g["tuned"] and len(g["trials"]) == 4 * 2 + 3 * 2
+    tile_trials, cad_trials = g["trials"][:8], g["trials"][8:]
+    assert all(t[1] == 4 for t in tile_trials)
     assert all(t[2] > 0 for t in g["trials"])
+    mean = {}
+    for tile, _c, ns in tile_trials:
+        mean.setdefault(tile, []).append(ns)
+    best_tile = min(mean, key=lambda k: sum(mean[k]) / len(mean[k]))
+    assert g["tile"] == best_tile
+    # the cadence pass runs with the chosen tile and tries every cadence
+    assert all(t[0] == best_tile for t in cad_trials)
+    assert sorted({t[1] for t in cad_trials}) == [2, 4, 8]
+    cmean = {}
+    for _tile, c, ns in cad_trials:
+        cmean.setdefault(c, []).append(ns)
+    best_c = min(cmean, key=lambda k: sum(cmean[k]) / len(cmean[k]))
+    assert g["sort_every"] == best_c
     for i, (work, n) in enumerate(zip(members, steps)):
         alone = make_gpu(work, explicit_species(work), precision=wl.FP32)
         alone.step(n)
