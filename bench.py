@@ -685,6 +685,8 @@ def main():
     ap.add_argument("--steps-3d", type=int, default=20)
     ap.add_argument("--no-3d-paper", action="store_true",
                     help="skip the 3D leg at the paper's 2 pi/32 resolution")
+    ap.add_argument("--only-3d", action="store_true",
+                    help="only the FP64 3D3V leg at 2 pi/16 (profiling runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device-to-device copy (3x) "
                          "whose profiler counters calibrate HBM traffic")
@@ -723,6 +725,12 @@ def main():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
+    if args.only_3d:
+        res = {"three_d": three_d(steps=args.steps_3d, warmup=args.warmup)}
+        if args.calibrate_copy:
+            res["copy_calibration_bytes"] = calibrate_copy()
+        print(json.dumps(res), flush=True)
+        return
     work = wl.rp_4096_fp32()
     full = 0 if args.headline_only else args.full_steps
     f32 = timed_leg(work, wl.FP32, args.steps, args.warmup, BALG_RP4096_FP32,

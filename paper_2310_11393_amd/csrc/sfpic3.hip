@@ -217,22 +217,27 @@ mur3(F3<R> f, Geo g, const double *buf, double kf) {
 // ---------------------------------------------------------------------------
 
 // Incident field at (x, y, z), time t, build axes (the paper's (z, x, y)).
+// KIND = 0 takes the model IncParams::kind names at run time; the push also
+// instantiates one model fixed at compile time (KIND = the model's constant),
+// which leaves the others' code and registers out of the kernel.
+template <int KIND = 0>
 __device__ __forceinline__ void incident3(const IncParams &P, double z_focus,
                                           double x, double y, double z,
                                           double t, double E[3], double B[3]) {
+  const int kind = KIND ? KIND : P.kind;
 #pragma unroll
   for (int c = 0; c < 3; ++c) E[c] = B[c] = 0.0;
-  if (P.kind == SFPIC_INC_PLANE_PULSE_1D) {
+  if (kind == SFPIC_INC_PLANE_PULSE_1D) {
     const double ph = t - P.t0 - x;
     const double v = P.a0 * sin(ph) * exp2(P.env_k * ph * ph);
     E[1] = v;
     B[2] = v;
-  } else if (P.kind == SFPIC_INC_APRIL_LP || P.kind == SFPIC_INC_APRIL_RP) {
+  } else if (kind == SFPIC_INC_APRIL_LP || kind == SFPIC_INC_APRIL_RP) {
     const double X = (y - P.y_focus) * P.inv_a;  // paper x
     const double Y = (z - z_focus) * P.inv_a;    // paper y
     const double Z = (x - P.x_focus) * P.inv_a;  // paper z
     sfpic::cx<double> e[3], b[3];
-    sfpic::april_complex_fields(P, X, Y, Z, t - P.t_focus, e, b);
+    sfpic::april_complex_fields<KIND>(P, X, Y, Z, t - P.t_focus, e, b);
     E[0] = e[2].r;
     E[1] = e[0].r;
     E[2] = e[1].r;
@@ -266,6 +271,9 @@ struct PushArgs {
 // tile's window of T + 5 nodes per axis (old nearest node -2 .. +2).
 #ifndef SFPIC3_TILE
 #define SFPIC3_TILE 8, 4, 4
+#endif
+#ifndef SFPIC3_PUSH_THREADS
+#define SFPIC3_PUSH_THREADS 256  // threads per push workgroup
 #endif
 #ifndef SFPIC3_PUSH_WGS
 #define SFPIC3_PUSH_WGS 3  // workgroups per CU the push is compiled for
@@ -396,8 +404,8 @@ tile_scatter3(Parts3<R> src, Parts3<R> dst, const uint32_t *sid, uint32_t *did,
 // b / 8, S = ceil(tiles / 8), so each XCD walks a contiguous band of tiles
 // whose field halos share its L2).  The current of the tile's particles is
 // accumulated in an FP64 LDS window and added to the global J once.
-template <typename R>
-__global__ void __launch_bounds__(256, SFPIC3_PUSH_WGS)
+template <typename R, int KIND>
+__global__ void __launch_bounds__(SFPIC3_PUSH_THREADS, SFPIC3_PUSH_WGS)
 push3_tiled(F3<R> f, Geo g, Parts3<R> p, const uint32_t *__restrict__ start, Tiles t,
             PushArgs a, IncParams inc) {
   __shared__ double sj[3 * WN];
@@ -412,35 +420,62 @@ push3_tiled(F3<R> f, Geo g, Parts3<R> p, const uint32_t *__restrict__ start, Til
             tz = (int)(tile / ((uint32_t)t.ntx * (uint32_t)t.nty));
   // window node (0, 0, 0) is cell-node t0 - 2 along each axis
   const int w0[3] = {tx * TX - 2, ty * TY - 2, tz * TZ - 2};
-  for (int k = threadIdx.x; k < 3 * WN; k += blockDim.x) sj[k] = 0.0;
-  // stage E^n and the centred B on the field window (array index of window
+  constexpr int NT = SFPIC3_PUSH_THREADS;
+  const int tid = (int)threadIdx.x;
+#pragma unroll
+  for (int it = 0; it < (3 * WN + NT - 1) / NT; ++it) {
+    const int k = tid + it * NT;
+    if (k < 3 * WN) sj[k] = 0.0;
+  }
+  // Stage E^n and the centred B on the field window (array index of window
   // node (0, 0, 0): w0 + 1 + G; nodes past the array read as zero and are
-  // never tapped)
+  // never tapped).  All of a thread's window loads are issued first; the
+  // thread's first particle is loaded and its incident field (which needs
+  // no window) computed while they are in flight.
   const int fo[3] = {w0[0] + 1 + G, w0[1] + 1 + G, w0[2] + 1 + G};
-  for (int k = threadIdx.x; k < FN; k += blockDim.x) {
+  constexpr int kStage = (FN + NT - 1) / NT;
+  double stage[kStage][6];
+#pragma unroll
+  for (int it = 0; it < kStage; ++it) {
+    const int k = tid + it * NT;
     const int gi = fo[0] + k % FX, gj = fo[1] + (k / FX) % FY,
               gk = fo[2] + k / (FX * FY);
-    const bool in = gi < g.NX && gj < g.NY && gk < g.NZ;
+    const bool in = k < FN && gi < g.NX && gj < g.NY && gk < g.NZ;
     const size_t n = in ? g.at(gi, gj, gk) : 0;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      sf[c * FN + k] = in ? ld(f.e[c], n) : 0.0;
-      sf[(3 + c) * FN + k] = in ? ld(f.bb[c], n) : 0.0;
+      stage[it][c] = in ? ld(f.e[c], n) : 0.0;
+      stage[it][3 + c] = in ? ld(f.bb[c], n) : 0.0;
     }
   }
-  __syncthreads();
-  for (uint32_t s = pbeg + threadIdx.x; s < pend; s += blockDim.x) {
-    double xi[3];
+  uint32_t s = pbeg + (uint32_t)tid;
+  double xi[3], u[3], E[3], B[3];
+  // position, momentum and incident field of particle s
+  auto load_particle = [&]() {
 #pragma unroll
-    for (int d = 0; d < 3; ++d) xi[d] = p.x[d][s];
-    double E[3], B[3];
-    if (inc.kind != SFPIC_INC_NONE) {  // incident first: its temporaries die
-      incident3(inc, a.z_focus, xi[0] * a.h[0], xi[1] * a.h[1],
-                xi[2] * a.h[2], a.time, E, B);
+    for (int d = 0; d < 3; ++d) {
+      xi[d] = p.x[d][s];
+      u[d] = ld(p.u[d], s);
+    }
+    if (KIND || inc.kind != SFPIC_INC_NONE) {
+      incident3<KIND>(inc, a.z_focus, xi[0] * a.h[0], xi[1] * a.h[1],
+                      xi[2] * a.h[2], a.time, E, B);
     } else {
 #pragma unroll
       for (int c = 0; c < 3; ++c) E[c] = B[c] = 0.0;
     }
+  };
+  if (s < pend) load_particle();
+#pragma unroll
+  for (int it = 0; it < kStage; ++it) {
+    const int k = tid + it * NT;
+    if (k < FN) {
+#pragma unroll
+      for (int c = 0; c < 6; ++c) sf[c * FN + k] = stage[it][c];
+    }
+  }
+  __syncthreads();
+  for (; s < pend;) {
     // gather E^n and the centred B at x^n from the field window, added to
     // the incident field: one component per iteration (fully unrolled, the
     // 162 taps need more registers than three workgroups per CU leave);
@@ -490,27 +525,36 @@ push3_tiled(F3<R> f, Geo g, Parts3<R> p, const uint32_t *__restrict__ start, Til
         else B[2] = v + B[2];
       }
     }
-    double u[3];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) u[d] = ld(p.u[d], s);
     sfpic::boris<double>(a.qm, a.dt, u, E, B);
     const double gi =
         sfpic::rsqrt(1.0 + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
-    // Esirkepov: shapes on the 5 nodes c0 - 2 .. c0 + 2 around the old
-    // nearest node before the move (S0) and after it (S1), D = S1 - S0.  The
-    // transverse weight of component d,
+    // Esirkepov on the 4 nodes per axis that the old and the new shape can
+    // cover: around the old nearest node c, c - 1 .. c + 2 for a move up the
+    // axis and c - 2 .. c + 1 otherwise (a move below one cell keeps the new
+    // nearest node within one node of c).  S0 and S1 are the shapes before
+    // and after the move, D = S1 - S0; the transverse weight of component d,
     //   S0_e S0_f + D_e S0_f / 2 + S0_e D_f / 2 + D_e D_f / 3,
-    // equals M_e M_f + D_e D_f / 12 with M = S0 + D / 2.
-    double M[3][5], D[3][5], x1[3];
-    int c0[3];
+    // equals M_e M_f + D_e D_f / 12 with M = S0 + D / 2, and the current
+    // along d is the running sum of D_d over the first three nodes (the sum
+    // over all four is zero).  When the nearest node does not change, the
+    // shapes cover three nodes and only two entries of the running sum are
+    // non-zero (the other is zero, or a rounding residue of a zero sum, and
+    // is not added): entries kd_lo .. kd_hi.
+    double M[3][4], D[3][4], x1[3];
+    int lo[3], kd_lo[3], kd_hi[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       x1[d] = xi[d] + a.dt * a.inv_h[d] * (u[d] * gi);
       const double c = floor(xi[d] + 0.5);
-      c0[d] = (int)c - 2 - w0[d];  // window index of node c0 - 2
+      const int up = x1[d] >= xi[d];
+      const bool same = floor(x1[d] + 0.5) == c;
+      lo[d] = (int)c - 2 + up - w0[d];  // window index of the first node
+      kd_lo[d] = (!up && same) ? 1 : 0;
+      kd_hi[d] = (up && same) ? 1 : 2;
+      const double first = c - 2.0 + (double)up;
 #pragma unroll
-      for (int k = 0; k < 5; ++k) {
-        const double node = c + (double)(k - 2);
+      for (int k = 0; k < 4; ++k) {
+        const double node = first + (double)k;
         const double s0 = sfpic::spline2(xi[d] - node);
         D[d][k] = sfpic::spline2(x1[d] - node) - s0;
         M[d][k] = s0 + 0.5 * D[d][k];
@@ -522,30 +566,33 @@ push3_tiled(F3<R> f, Geo g, Parts3<R> p, const uint32_t *__restrict__ start, Til
     for (int d = 0; d < 3; ++d) {
       const int e = (d + 1) % 3, fa = (d + 2) % 3;
       const double scale = -a.qw * a.h_over_dt[d];
-      double Mf[5], Df[5];  // rotated so that index 0 is the current kf
+      double Mf[4], Df[4];  // rotated so that index 0 is the current kf
 #pragma unroll
-      for (int k = 0; k < 5; ++k) {
+      for (int k = 0; k < 4; ++k) {
         Mf[k] = M[fa][k];
         Df[k] = D[fa][k] * twelfth;
       }
-      int addr = d * WN + c0[0] + c0[1] * WX + c0[2] * WX * WY;
+      double sd[3];  // scale * D_d
+#pragma unroll
+      for (int k = 0; k < 3; ++k) sd[k] = scale * D[d][k];
+      int addr = d * WN + lo[0] + lo[1] * WX + lo[2] * WX * WY;
 #pragma unroll 1
-      for (int kf = 0; kf < 5; ++kf) {
+      for (int kf = 0; kf < 4; ++kf) {
         const double mf = Mf[0], df = Df[0];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
+        for (int k = 0; k < 3; ++k) {
           Mf[k] = Mf[k + 1];
           Df[k] = Df[k + 1];
         }
 #pragma unroll
-        for (int ke = 0; ke < 5; ++ke) {
+        for (int ke = 0; ke < 4; ++ke) {
           const double tw = M[e][ke] * mf + D[e][ke] * df;
-          if (tw == 0.0) continue;
+          if (tw == 0.0) continue;  // a node outside both shapes
           double acc = 0.0;
 #pragma unroll
-          for (int kd = 0; kd < 4; ++kd) {
-            acc += scale * (D[d][kd] * tw);
-            if (acc != 0.0)
+          for (int kd = 0; kd < 3; ++kd) {
+            acc += sd[kd] * tw;
+            if (kd >= kd_lo[d] && kd <= kd_hi[d])
               atomicAdd(&sj[addr + kd * kStride[d] + ke * kStride[e]], acc);
           }
         }
@@ -562,11 +609,13 @@ push3_tiled(F3<R> f, Geo g, Parts3<R> p, const uint32_t *__restrict__ start, Til
       p.x[d][s] = (d == 0 && out) ? kDead : x1[d];
       p.u[d][s] = (R)u[d];
     }
+    s += NT;
+    if (s < pend) load_particle();
   }
   __syncthreads();
   // add the window to the global current (windows of neighbouring tiles
   // overlap by 5 nodes per axis)
-  for (int k = threadIdx.x; k < WN; k += blockDim.x) {
+  for (int k = tid; k < WN; k += NT) {
     const int ix = k % WX, iy = (k / WX) % WY, iz = k / (WX * WY);
     const int gi = w0[0] + ix + G, gj = w0[1] + iy + G, gk = w0[2] + iz + G;
     if (gi >= g.NX || gj >= g.NY || gk >= g.NZ) continue;
@@ -576,6 +625,30 @@ push3_tiled(F3<R> f, Geo g, Parts3<R> p, const uint32_t *__restrict__ start, Til
       const double v = sj[c * WN + k];
       if (v != 0.0) atomicAdd(f.j[c] + n, (R)v);
     }
+  }
+}
+
+// The push for the incident model of the run: one model fixed at compile
+// time when there is one at the particles, else the run-time choice.
+template <typename R>
+void launch_push3(uint32_t grid, hipStream_t st, F3<R> f, Geo g, Parts3<R> p,
+                  const uint32_t *start, Tiles t, PushArgs a,
+                  const IncParams &inc) {
+  switch (inc.kind) {
+    case SFPIC_INC_PLANE_PULSE_1D:
+      push3_tiled<R, SFPIC_INC_PLANE_PULSE_1D><<<grid, SFPIC3_PUSH_THREADS, 0, st>>>(
+          f, g, p, start, t, a, inc);
+      break;
+    case SFPIC_INC_APRIL_LP:
+      push3_tiled<R, SFPIC_INC_APRIL_LP><<<grid, SFPIC3_PUSH_THREADS, 0, st>>>(f, g, p, start,
+                                                               t, a, inc);
+      break;
+    case SFPIC_INC_APRIL_RP:
+      push3_tiled<R, SFPIC_INC_APRIL_RP><<<grid, SFPIC3_PUSH_THREADS, 0, st>>>(f, g, p, start,
+                                                               t, a, inc);
+      break;
+    default:
+      push3_tiled<R, 0><<<grid, SFPIC3_PUSH_THREADS, 0, st>>>(f, g, p, start, t, a, inc);
   }
 }
 
@@ -1066,8 +1139,8 @@ int one_step_t(sfpic3_sim *S) {
     std::swap(sp.id, sp.id_alt);
     a.qm = sp.q / sp.m;
     a.qw = sp.q * sp.w;
-    push3_tiled<R><<<grid8, 256, 0, S->st>>>(f, S->g, parts_as<R>(sp.p),
-                                             S->start, t, a, S->inc);
+    launch_push3<R>(grid8, S->st, f, S->g, parts_as<R>(sp.p), S->start, t,
+                    a, S->inc);
     HIP3(hipGetLastError());
   }
   if (int r = face_pass<0, R>(S, true, 0.0)) return r;
