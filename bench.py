@@ -687,6 +687,9 @@ def main():
                     help="skip the 3D leg at the paper's 2 pi/32 resolution")
     ap.add_argument("--only-3d", action="store_true",
                     help="only the FP64 3D3V leg at 2 pi/16 (profiling runs)")
+    ap.add_argument("--only-batch", action="store_true",
+                    help="only the batched sweep (--batch-members, "
+                         "--batch-steps; profiling runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device-to-device copy (3x) "
                          "whose profiler counters calibrate HBM traffic")
@@ -725,6 +728,10 @@ def main():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
+    if args.only_batch:
+        print(json.dumps({"batched_sweep": batched_sweep(
+            args.batch_members, args.batch_steps)}), flush=True)
+        return
     if args.only_3d:
         res = {"three_d": three_d(steps=args.steps_3d, warmup=args.warmup)}
         if args.calibrate_copy:

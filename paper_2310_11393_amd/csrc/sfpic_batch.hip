@@ -116,6 +116,9 @@ struct Group {
   BatchView<float> v32{};
   size_t lds = 0;
   int grid = 0;
+  // every member's beam is an April beam at the particles: the push runs
+  // the kernel compiled for the LP and RP beams alone
+  bool april = false;
   hipGraphExec_t exec = nullptr;
   bool stale = true;  // tables (and graph) must be rebuilt before launching
   bool ran = false;   // work was launched since the host view was refreshed
@@ -239,7 +242,7 @@ struct Engine {
       off = al(off + nent[t] * 4);
     }
     const size_t o_cnt = off;
-    off = al(off + (size_t)(2 + np) * 4);
+    off = al(off + (size_t)(2 + np + 8) * 4);
     const size_t o_due = off;
     off = al(off + (size_t)(np > 0 ? np : 1) * 4);
     if (off > g.dbytes) {
@@ -261,6 +264,7 @@ struct Engine {
     for (int t = 0; t < 3; ++t) tab[t][0] = 0;
     int j = 0;
     size_t lds = 0, dyn = 0;
+    bool april = true;
     for (int mi = 0; mi < nm; ++mi) {
       Member *m = g.members[mi];
       sfpic_sim *s = m->sim;
@@ -288,13 +292,16 @@ struct Engine {
       tab[0][mi + 1] = tab[0][mi] + nfar;
       tab[1][mi + 1] = tab[1][mi] + namp;
       const size_t l = g.precision == SFPIC_FP64
-                           ? push_lds_bytes<double>(s->tg, g.dims)
-                           : push_lds_bytes<float>(s->tg, g.dims);
+                           ? push_lds_bytes<double>(s->tg, g.dims, true)
+                           : push_lds_bytes<float>(s->tg, g.dims, true);
       const size_t ld = g.precision == SFPIC_FP64
-                            ? push_dyn_lds_bytes<double>(s->tg, g.dims)
-                            : push_dyn_lds_bytes<float>(s->tg, g.dims);
+                            ? push_dyn_lds_bytes<double>(s->tg, g.dims, true)
+                            : push_dyn_lds_bytes<float>(s->tg, g.dims, true);
       lds = l > lds ? l : lds;
       dyn = ld > dyn ? ld : dyn;
+      april = april && !s->inc.on_nodes &&
+              (s->inc.kind == SFPIC_INC_APRIL_LP ||
+               s->inc.kind == SFPIC_INC_APRIL_RP);
       for (size_t k = 0; k < s->sp.size(); ++k, ++j) {
         SpeciesState &st = s->sp[k];
         PushJob<R> &P = pj[j];
@@ -350,8 +357,9 @@ struct Engine {
     g.np = np;
     g.built = g.members;
     g.lds = dyn;  // passed at launch; static chunk buffers come on top
-    const int per_cu =
-        batch_push_blocks_per_cu(g.precision == SFPIC_FP64, g.dims, dyn);
+    g.april = april && g.dims == 2;
+    const int per_cu = batch_push_blocks_per_cu(g.precision == SFPIC_FP64,
+                                                g.dims, g.april, dyn);
     int grid = cus * (per_cu > 0 ? per_cu : 1);
     if ((uint32_t)grid > v.n_tiles) grid = (int)(v.n_tiles > 0 ? v.n_tiles : 1);
     g.grid = grid;
@@ -375,9 +383,9 @@ struct Engine {
   // One step of every running member of the group.
   template <typename R>
   int enqueue_step_t(Group &g, const BatchView<R> &v) {
-    HIP_TRY(launch_fill_u32(v.counters, 0u, (size_t)(2 + v.np), stream));
+    HIP_TRY(launch_fill_u32(v.counters, 0u, (size_t)(2 + v.np + 8), stream));
     HIP_TRY(launch_batch_faraday<R>(v, g.dims, stream));
-    HIP_TRY(launch_batch_push<R>(v, g.dims, g.lds, g.grid, stream));
+    HIP_TRY(launch_batch_push<R>(v, g.dims, g.april, g.lds, g.grid, stream));
     HIP_TRY(launch_batch_stragglers<R>(v, g.dims, stream));
     HIP_TRY(launch_batch_ampere<R>(v, g.dims, stream));
     HIP_TRY(launch_batch_advance<R>(v, g.rule, stream));
@@ -573,8 +581,8 @@ struct Engine {
       tt.ty = t.second;
       tt.slack = g.members.empty() ? 1 : g.members[0]->sim->tg.slack;
       const size_t l = g.precision == SFPIC_FP64
-                           ? push_lds_bytes<double>(tt, g.dims)
-                           : push_lds_bytes<float>(tt, g.dims);
+                           ? push_lds_bytes<double>(tt, g.dims, true)
+                           : push_lds_bytes<float>(tt, g.dims, true);
       if (l <= max_lds) ok.push_back(t);
     }
     if (ok.empty()) return SFPIC_OK;

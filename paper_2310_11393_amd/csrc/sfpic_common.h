@@ -163,7 +163,8 @@ struct BatchView {
   const uint32_t *far_off, *amp_off;  // field jobs: Faraday / Ampere blocks
   const uint32_t *tile_off;           // push jobs: tiles
   // [0] tile queue, [1 + j] stragglers of push job j, [1 + np] number of
-  // push jobs to sort this step (listed in due)
+  // push jobs to sort this step (listed in due), [2 + np + x] queue of the
+  // push's item band x (x = 0 .. 7)
   uint32_t *counters;
   uint32_t *due;
   uint32_t n_far, n_amp, n_tiles;
@@ -578,11 +579,11 @@ template <typename R>
 hipError_t launch_ampere(const Fields<R> &f, int dims, double dt, double dx,
                          double dy, hipStream_t st);
 // LDS of the push workgroup: all of it (static and dynamic), and the dynamic
-// part passed at launch.
+// part passed at launch; batch: the batched push's (smaller particle chunk).
 template <typename R>
-size_t push_lds_bytes(const TileGeom &tg, int dims);
+size_t push_lds_bytes(const TileGeom &tg, int dims, bool batch = false);
 template <typename R>
-size_t push_dyn_lds_bytes(const TileGeom &tg, int dims);
+size_t push_dyn_lds_bytes(const TileGeom &tg, int dims, bool batch = false);
 // Work items of the tiled push (tile, first particle), at most kmax
 // particles each, rebuilt from the sort's start offsets after every sort;
 // items holds push_items_words() words.
@@ -676,9 +677,11 @@ hipError_t launch_batch_faraday(const BatchView<R> &v, int dims,
 template <typename R>
 hipError_t launch_batch_ampere(const BatchView<R> &v, int dims,
                                hipStream_t st);
+// april: every push job has an April beam at the particles (see
+// batch_push_kernel)
 template <typename R>
-hipError_t launch_batch_push(const BatchView<R> &v, int dims, size_t lds,
-                             int grid, hipStream_t st);
+hipError_t launch_batch_push(const BatchView<R> &v, int dims, bool april,
+                             size_t lds, int grid, hipStream_t st);
 template <typename R>
 hipError_t launch_batch_stragglers(const BatchView<R> &v, int dims,
                                    hipStream_t st);
@@ -688,7 +691,7 @@ template <typename R>
 hipError_t launch_batch_advance(const BatchView<R> &v, SortRule rule,
                                 hipStream_t st);
 // Resident workgroups of the batched push per CU (0 on error).
-int batch_push_blocks_per_cu(bool fp64, int dims, size_t lds);
+int batch_push_blocks_per_cu(bool fp64, int dims, bool april, size_t lds);
 hipError_t launch_fill_u32(uint32_t *a, uint32_t v, size_t n, hipStream_t st);
 
 }  // namespace sfpic

@@ -42,18 +42,24 @@ __host__ __device__ __forceinline__ int win_extra(int slack) {
   return 2 * slack + 5;
 }
 
-// LDS chunk of the staged particle path (the FP32 form, see PT): 1024
-// particles per chunk, 4 per thread; lane l of wave w takes chunk slots
-// l*16 + w*4 + j, so the 64 lanes of a wave sit in different cells of the
-// cell-sorted chunk, and one pad word every 16 spreads them over the banks.
+// LDS chunk of the staged particle path (the FP32 form, see PT): 256 PER
+// particles per chunk, PER per thread; lane l of wave w takes chunk slots
+// l*4PER + w*PER + j, so the 64 lanes of a wave sit in different cells of
+// the cell-sorted chunk, and one pad word every 4 PER spreads them over the
+// banks.  A single simulation's push takes 4 per thread; the batched push 2,
+// whose smaller chunk lets four of its workgroups share a CU (16.3 -> 17.1 G
+// pushes/s on a 64-member FP32 sweep; the single push is 7% slower with it).
+constexpr int kChunkPer = 4, kBatchChunkPer = 2;
+template <int PER>
 struct Chunk {
-  static constexpr int per = 4;
+  static constexpr int per = PER;
   static constexpr int size = 256 * per;
   static constexpr int stride = 4 * per;
   static constexpr int pad = size + size / stride;  // padded length
 };
+template <int PER>
 __device__ __forceinline__ int chunk_slot(int k) {
-  return k + k / Chunk::stride;
+  return k + k / Chunk<PER>::stride;
 }
 
 __global__ void fill_u32(uint32_t *a, uint32_t v, size_t n) {
@@ -457,7 +463,7 @@ __device__ __forceinline__ bool push_particle(int &ix, int &iy, R &fx, R &fy,
 // One workgroup pushes the particles pbeg .. pend - 1 of one tile (all of
 // them, or one work item of a dense tile); smem holds the field and current
 // windows and, on the staged path, the particle chunk (push_lds_bytes).
-template <typename R, int DIMS, int INC>
+template <typename R, int DIMS, int INC, int PER = kChunkPer>
 __device__ __forceinline__ void push_tile(const Fields<R> &f,
                                           const Particles<R> &p,
                                           const TileGeom &tg,
@@ -575,28 +581,29 @@ __device__ __forceinline__ void push_tile(const Fields<R> &f,
     // transposed order of Chunk.
     using W = typename PT<R>::Word;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    using CK = Chunk<PER>;
     W *sp = (W *)(sf + 6 * WN);  // particle chunk after the windows
-    for (uint32_t c0 = pbeg; c0 < pend; c0 += Chunk::size) {
-      const int cn = (int)min((uint32_t)Chunk::size, pend - c0);
+    for (uint32_t c0 = pbeg; c0 < pend; c0 += CK::size) {
+      const int cn = (int)min((uint32_t)CK::size, pend - c0);
       for (int k = threadIdx.x; k < cn; k += blockDim.x)
-        PT<R>::g2l(p, c0 + k, sp, chunk_slot(k), Chunk::pad, DIMS);
+        PT<R>::g2l(p, c0 + k, sp, chunk_slot<PER>(k), CK::pad, DIMS);
       __syncthreads();
 #pragma unroll 1
-      for (int j = 0; j < Chunk::per; ++j) {
-        const int idx = lane * Chunk::stride + wv * Chunk::per + j;
+      for (int j = 0; j < CK::per; ++j) {
+        const int idx = lane * CK::stride + wv * CK::per + j;
         if (idx >= cn) continue;
-        const int sl = chunk_slot(idx);
+        const int sl = chunk_slot<PER>(idx);
         int ix, iy;
         R fx, fy, u[3];
         bool alive;
-        if (!PT<R>::unpack(sp, sl, Chunk::pad, DIMS, ix, iy, fx, fy, u))
+        if (!PT<R>::unpack(sp, sl, CK::pad, DIMS, ix, iy, fx, fy, u))
           continue;
         if (push_one(ix, iy, fx, fy, u, c0 + idx, alive))
-          PT<R>::pack(sp, sl, Chunk::pad, DIMS, alive, ix, iy, fx, fy, u);
+          PT<R>::pack(sp, sl, CK::pad, DIMS, alive, ix, iy, fx, fy, u);
       }
       __syncthreads();
       for (int k = threadIdx.x; k < cn; k += blockDim.x)
-        PT<R>::l2g(p, c0 + k, sp, chunk_slot(k), Chunk::pad, DIMS);
+        PT<R>::l2g(p, c0 + k, sp, chunk_slot<PER>(k), CK::pad, DIMS);
       __syncthreads();
     }
   }
@@ -748,21 +755,22 @@ push_stragglers(Fields<R> f, Particles<R> p, PushParams pp, IncParams inc,
 }
 
 template <typename R>
-size_t push_dyn_lds_bytes(const TileGeom &tg, int dims) {
+size_t push_dyn_lds_bytes(const TileGeom &tg, int dims, bool batch) {
   const int WX = tg.tx + win_extra(tg.slack);
   const int WY = (dims == 2) ? tg.ty + win_extra(tg.slack) : 1;
   size_t b = (size_t)3 * WX * WY * sizeof(double) +
              (size_t)6 * WX * WY * sizeof(R);
+  const int pad = batch ? Chunk<kBatchChunkPer>::pad : Chunk<kChunkPer>::pad;
   if constexpr (PT<R>::kStaged)
-    b += (size_t)PT<R>::kWords * Chunk::pad * sizeof(typename PT<R>::Word);
+    b += (size_t)PT<R>::kWords * pad * sizeof(typename PT<R>::Word);
   return b;
 }
 
 // All LDS of the push workgroup (it has no static LDS, so this equals the
 // dynamic size; the batched kernel adds a few bytes of its own).
 template <typename R>
-size_t push_lds_bytes(const TileGeom &tg, int dims) {
-  return push_dyn_lds_bytes<R>(tg, dims);
+size_t push_lds_bytes(const TileGeom &tg, int dims, bool batch) {
+  return push_dyn_lds_bytes<R>(tg, dims, batch);
 }
 
 hipError_t launch_build_items(const uint32_t *start, const TileGeom &tg,
@@ -1127,28 +1135,53 @@ __device__ __forceinline__ PushParams member_params(const BatchView<R> &v,
   return pp;
 }
 
-template <typename R, int DIMS>
+// APRIL: every push job of the group has an April beam at the particles;
+// each tile then runs the push compiled for its member's beam (LP or RP),
+// whose registers leave room for more waves than the push built for every
+// model.
+template <typename R, int DIMS, bool APRIL>
 __global__ void __launch_bounds__(256, SFPIC_PUSH_MIN_BLOCKS)
 batch_push_kernel(BatchView<R> v) {
   extern __shared__ double smem[];
   __shared__ uint32_t s_item;
-  for (;;) {
-    if (threadIdx.x == 0) s_item = atomicAdd(&v.counters[0], 1u);
+  // Items in 8 bands of S = ceil(n / 8), one queue each (counters[2 + np +
+  // x]); the hardware deals workgroups to the 8 XCDs round-robin, so
+  // workgroup b starts on band b mod 8 -- neighbouring tiles, whose halos
+  // overlap, are then pushed by one XCD and meet in its L2 -- and moves on
+  // to the next band when its own is exhausted.
+  const uint32_t S = (v.n_tiles + 7) >> 3;
+  for (int band = 0; band < 8;) {
+    const uint32_t x = (blockIdx.x + (uint32_t)band) & 7u;
+    if (threadIdx.x == 0) s_item = atomicAdd(&v.counters[2 + v.np + x], 1u);
     __syncthreads();
-    const uint32_t item = __builtin_amdgcn_readfirstlane(s_item);
+    const uint32_t k = __builtin_amdgcn_readfirstlane(s_item);
     __syncthreads();  // s_item is rewritten only after every thread read it
-    if (item >= v.n_tiles) break;
+    const uint32_t item = x * S + k;
+    if (k >= S || item >= v.n_tiles) {
+      ++band;
+      continue;
+    }
     const int jb = find_segment(v.tile_off, v.np, item);
     const PushJob<R> &J = v.pjobs[jb];
     if (v.ms[J.member].steps_left <= 0) continue;
     const PushParams pp = member_params(v, J);
     const int tile = (int)(item - v.tile_off[jb]);
     const size_t t0 = (size_t)tile * J.tg.cells_per_tile;
-    push_tile<R, DIMS, kIncAtParticle>(J.f, J.pa[J.cur], J.tg, pp, J.inc,
-                                       J.strag, &v.counters[1 + jb], tile,
-                                       J.start[t0],
-                                       J.start[t0 + J.tg.cells_per_tile],
-                                       smem);
+    const uint32_t pb = J.start[t0], pe = J.start[t0 + J.tg.cells_per_tile];
+    if constexpr (APRIL) {
+      if (J.inc.kind == 3)
+        push_tile<R, DIMS, kIncRP, kBatchChunkPer>(
+            J.f, J.pa[J.cur], J.tg, pp, J.inc, J.strag, &v.counters[1 + jb],
+            tile, pb, pe, smem);
+      else
+        push_tile<R, DIMS, kIncLP, kBatchChunkPer>(
+            J.f, J.pa[J.cur], J.tg, pp, J.inc, J.strag, &v.counters[1 + jb],
+            tile, pb, pe, smem);
+    } else {
+      push_tile<R, DIMS, kIncAtParticle, kBatchChunkPer>(
+          J.f, J.pa[J.cur], J.tg, pp, J.inc, J.strag, &v.counters[1 + jb],
+          tile, pb, pe, smem);
+    }
   }
 }
 
@@ -1172,13 +1205,15 @@ __global__ void __launch_bounds__(256) batch_stragglers_kernel(BatchView<R> v) {
 }
 
 template <typename R>
-hipError_t launch_batch_push(const BatchView<R> &v, int dims, size_t lds,
-                             int grid, hipStream_t st) {
+hipError_t launch_batch_push(const BatchView<R> &v, int dims, bool april,
+                             size_t lds, int grid, hipStream_t st) {
   if (v.np == 0) return hipSuccess;
   if (dims == 1)
-    batch_push_kernel<R, 1><<<grid, 256, lds, st>>>(v);
+    batch_push_kernel<R, 1, false><<<grid, 256, lds, st>>>(v);
+  else if (april)
+    batch_push_kernel<R, 2, true><<<grid, 256, lds, st>>>(v);
   else
-    batch_push_kernel<R, 2><<<grid, 256, lds, st>>>(v);
+    batch_push_kernel<R, 2, false><<<grid, 256, lds, st>>>(v);
   return hipGetLastError();
 }
 
@@ -1194,20 +1229,22 @@ hipError_t launch_batch_stragglers(const BatchView<R> &v, int dims,
   return hipGetLastError();
 }
 
-int batch_push_blocks_per_cu(bool fp64, int dims, size_t lds) {
+template <typename R>
+static int push_blocks_per_cu(int dims, bool april, size_t lds) {
   int nb = 0;
-  hipError_t e;
-  if (fp64)
-    e = dims == 1 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                        &nb, batch_push_kernel<double, 1>, 256, lds)
-                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                        &nb, batch_push_kernel<double, 2>, 256, lds);
-  else
-    e = dims == 1 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                        &nb, batch_push_kernel<float, 1>, 256, lds)
-                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                        &nb, batch_push_kernel<float, 2>, 256, lds);
+  const hipError_t e =
+      dims == 1 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                      &nb, batch_push_kernel<R, 1, false>, 256, lds)
+      : april   ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                      &nb, batch_push_kernel<R, 2, true>, 256, lds)
+                : hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                      &nb, batch_push_kernel<R, 2, false>, 256, lds);
   return e == hipSuccess ? nb : 0;
+}
+
+int batch_push_blocks_per_cu(bool fp64, int dims, bool april, size_t lds) {
+  return fp64 ? push_blocks_per_cu<double>(dims, april, lds)
+              : push_blocks_per_cu<float>(dims, april, lds);
 }
 
 // Batched counting sort: the same five passes as launch_sort, each one
@@ -1303,8 +1340,8 @@ hipError_t launch_batch_sort(const BatchView<R> &v, int dims, hipStream_t st) {
 }
 
 #define SFPIC_INSTANTIATE(R)                                                 \
-  template size_t push_lds_bytes<R>(const TileGeom &, int);                  \
-  template size_t push_dyn_lds_bytes<R>(const TileGeom &, int);              \
+  template size_t push_lds_bytes<R>(const TileGeom &, int, bool);            \
+  template size_t push_dyn_lds_bytes<R>(const TileGeom &, int, bool);        \
   template hipError_t launch_push_tiled<R>(                                  \
       const Fields<R> &, const Particles<R> &, const uint32_t *,             \
       const uint32_t *, const uint32_t *, uint32_t, int64_t,                 \
@@ -1317,8 +1354,8 @@ hipError_t launch_batch_sort(const BatchView<R> &v, int dims, hipStream_t st) {
       const Particles<R> &, const Particles<R> &, uint32_t, uint32_t *,      \
       uint32_t *, const TileGeom &, int, int, int, const SortScratch &,      \
       hipStream_t);                                                          \
-  template hipError_t launch_batch_push<R>(const BatchView<R> &, int, size_t,\
-                                           int, hipStream_t);                \
+  template hipError_t launch_batch_push<R>(const BatchView<R> &, int, bool,  \
+                                           size_t, int, hipStream_t);        \
   template hipError_t launch_batch_stragglers<R>(const BatchView<R> &, int,  \
                                                  hipStream_t);               \
   template hipError_t launch_batch_sort<R>(const BatchView<R> &, int,        \
