@@ -265,31 +265,36 @@ __device__ __forceinline__ void incident_r(const IncParams &inc, int dims,
 }
 
 // ---------------------------------------------------------------------------
-// Esirkepov deposition of one particle.  S0 and S1 are the order-2 shapes at
-// x^n and x^{n+1} on the 5 nodes ipx-2 .. ipx+2 (ipy-2 .. ipy+2); add(c, a,
-// b, v) accumulates v into component c at node offset (a, b).  Only nodes
-// where S0 or S1 is non-zero are touched.
+// Esirkepov deposition of one particle on a 4-node frame per axis: S0 and S1
+// are the order-2 shapes at x^n and x^{n+1} on the nodes ipx - 2 + ox ..
+// ipx + 1 + ox (ipy - 2 + oy .. ipy + 1 + oy), which hold every node either
+// shape touches (ox = 1 for a move up the axis, see shapes4); add(c, a, b,
+// v) accumulates v into component c at node offset (a, b) from node ipx - 2
+// (ipy - 2).  Only nodes lo .. hi (frame indices), where S0 or S1 is
+// non-zero, are touched, and along x (y) only the entries of the running sum
+// that can be non-zero.
 // ---------------------------------------------------------------------------
 template <typename R, int DIMS, typename Add>
-__device__ __forceinline__ void esirkepov(const R S0x[5], const R S1x[5],
-                                          const R S0y[5], const R S1y[5],
-                                          int lox, int hix, int loy, int hiy,
-                                          R cxq, R cyq, R qvy, R qvz, Add add) {
-  // All loops run over the full 5-node support with compile-time indices
-  // (the shape arrays stay in registers); nodes outside [lo, hi] are skipped.
+__device__ __forceinline__ void esirkepov(const R S0x[4], const R S1x[4],
+                                          const R S0y[4], const R S1y[4],
+                                          int ox, int oy, int lox, int hix,
+                                          int loy, int hiy, R cxq, R cyq,
+                                          R qvy, R qvz, Add add) {
+  // All loops run over the full frame with compile-time indices (the shape
+  // arrays stay in registers); nodes outside [lo, hi] are skipped per lane.
   if (DIMS == 1) {
     R acc = R(0);
 #pragma unroll
-    for (int a = 0; a < 4; ++a) {
+    for (int a = 0; a < 3; ++a) {
       acc += cxq * (S1x[a] - S0x[a]);
-      if (a >= lox && a < hix) add(0, a, 0, acc);
+      if (a >= lox && a < hix) add(0, a + ox, 0, acc);
     }
 #pragma unroll
-    for (int a = 0; a < 5; ++a) {
+    for (int a = 0; a < 4; ++a) {
       if (a < lox || a > hix) continue;
       const R wv = R(0.5) * (S0x[a] + S1x[a]);
-      add(1, a, 0, qvy * wv);
-      add(2, a, 0, qvz * wv);
+      add(1, a + ox, 0, qvy * wv);
+      add(2, a + ox, 0, qvz * wv);
     }
     return;
   }
@@ -297,9 +302,9 @@ __device__ __forceinline__ void esirkepov(const R S0x[5], const R S1x[5],
   // W_z = S0x S0y + DSx S0y/2 + S0x DSy/2 + DSx DSy/3
   //     = S0x (S0y + DSy/2) + DSx (S0y/2 + DSy/3),
   // with the charge factors folded into the per-row / per-column terms.
-  R DSx[5], DSy[5], cAy[5], qAy[5], qBy[5];
+  R DSx[4], DSy[4], cAy[4], qAy[4], qBy[4];
 #pragma unroll
-  for (int k = 0; k < 5; ++k) {
+  for (int k = 0; k < 4; ++k) {
     DSx[k] = S1x[k] - S0x[k];
     DSy[k] = S1y[k] - S0y[k];
     const R ay = S0y[k] + R(0.5) * DSy[k];
@@ -308,51 +313,55 @@ __device__ __forceinline__ void esirkepov(const R S0x[5], const R S1x[5],
     qBy[k] = qvz * (R(0.5) * S0y[k] + R(1.0 / 3.0) * DSy[k]);
   }
 #pragma unroll
-  for (int b = 0; b < 5; ++b) {
+  for (int b = 0; b < 4; ++b) {
     if (b < loy || b > hiy) continue;
     R acc = R(0);
 #pragma unroll
-    for (int a = 0; a < 4; ++a) {
+    for (int a = 0; a < 3; ++a) {
       acc += DSx[a] * cAy[b];
-      if (a >= lox && a < hix) add(0, a, b, acc);
+      if (a >= lox && a < hix) add(0, a + ox, b + oy, acc);
     }
   }
 #pragma unroll
-  for (int a = 0; a < 5; ++a) {
+  for (int a = 0; a < 4; ++a) {
     if (a < lox || a > hix) continue;
     const R cAx = cyq * (S0x[a] + R(0.5) * DSx[a]);
     R acc = R(0);
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
+    for (int b = 0; b < 3; ++b) {
       acc += DSy[b] * cAx;
-      if (b >= loy && b < hiy) add(1, a, b, acc);
+      if (b >= loy && b < hiy) add(1, a + ox, b + oy, acc);
     }
   }
 #pragma unroll
-  for (int b = 0; b < 5; ++b) {
+  for (int b = 0; b < 4; ++b) {
     if (b < loy || b > hiy) continue;
 #pragma unroll
-    for (int a = 0; a < 5; ++a) {
+    for (int a = 0; a < 4; ++a) {
       if (a < lox || a > hix) continue;
-      add(2, a, b, S0x[a] * qAy[b] + DSx[a] * qBy[b]);
+      add(2, a + ox, b + oy, S0x[a] * qAy[b] + DSx[a] * qBy[b]);
     }
   }
 }
 
-// Shapes on the 5-node support: S0 from the three order-2 weights at x^n,
-// S1 from the new offset d1 = xi^{n+1} - ipx; the support of S1 is [lo, hi].
+// Shapes on the 4-node frame of one axis: the old nearest node ipx and the
+// new offset d1 = xi^{n+1} - ipx.  A move below one cell keeps the new
+// nearest node within one of ipx, so the frame ipx - 1 .. ipx + 2 (o = 1,
+// d1 >= d0) or ipx - 2 .. ipx + 1 (o = 0) holds both shapes: S0 from the
+// three order-2 weights at x^n, S1 at d1; [lo, hi]: the nodes either touches.
+// (Frame node k is node ipx - 2 + o + k.)
 template <typename R>
-__device__ __forceinline__ void shapes5(const R w0[3], R d1, R S0[5], R S1[5],
-                                        int &lo, int &hi) {
-  S0[0] = R(0);
-  S0[1] = w0[0];
-  S0[2] = w0[1];
-  S0[3] = w0[2];
-  S0[4] = R(0);
+__device__ __forceinline__ void shapes4(const R w0[3], R d0, R d1, R S0[4],
+                                        R S1[4], int &o, int &lo, int &hi) {
+  o = d1 >= d0;
+  S0[0] = o ? w0[0] : R(0);
+  S0[1] = o ? w0[1] : w0[0];
+  S0[2] = o ? w0[2] : w0[1];
+  S0[3] = o ? R(0) : w0[2];
 #pragma unroll
-  for (int k = 0; k < 5; ++k) S1[k] = spline2(d1 - R(k - 2));
-  lo = d1 < R(-0.5) ? 0 : 1;
-  hi = d1 > R(0.5) ? 4 : 3;
+  for (int k = 0; k < 4; ++k) S1[k] = spline2(d1 - R(k - 2 + o));
+  lo = (d1 < R(-0.5) ? 0 : 1) - o;
+  hi = (d1 > R(0.5) ? 4 : 3) - o;
 }
 
 // Order-2 weights of a particle at (cell ix, offset fx): primal weights
@@ -428,13 +437,13 @@ __device__ __forceinline__ bool push_particle(int &ix, int &iy, R &fx, R &fy,
   // new positions as offsets from the old nearest nodes
   const R d1x = dx0 + (R)(pp.dt * pp.inv_dx) * (u[0] * gi);
   const R d1y = (DIMS == 2) ? dy0 + (R)(pp.dt * pp.inv_dy) * (u[1] * gi) : R(0);
-  R S0x[5], S1x[5], S0y[5] = {R(0), R(1), R(0), R(0), R(0)},
-                    S1y[5] = {R(0), R(1), R(0), R(0), R(0)};
-  int lox, hix, loy = 1, hiy = 1;
-  shapes5(wxp, d1x, S0x, S1x, lox, hix);
-  if (DIMS == 2) shapes5(wyp, d1y, S0y, S1y, loy, hiy);
+  R S0x[4], S1x[4], S0y[4] = {R(0), R(1), R(0), R(0)},
+                    S1y[4] = {R(0), R(1), R(0), R(0)};
+  int ox, lox, hix, oy = 0, loy = 1, hiy = 1;
+  shapes4(wxp, dx0, d1x, S0x, S1x, ox, lox, hix);
+  if (DIMS == 2) shapes4(wyp, dy0, d1y, S0y, S1y, oy, loy, hiy);
   const R qvy = (R)pp.qw * u[1] * gi, qvz = (R)pp.qw * u[2] * gi;
-  esirkepov<R, DIMS>(S0x, S1x, S0y, S1y, lox, hix, loy, hiy,
+  esirkepov<R, DIMS>(S0x, S1x, S0y, S1y, ox, oy, lox, hix, loy, hiy,
                      (R)(-pp.qw * pp.dx / pp.dt), (R)(-pp.qw * pp.dy / pp.dt),
                      qvy, qvz, add);
   // A move below one cell keeps |d1| < 2; a non-finite momentum (a
