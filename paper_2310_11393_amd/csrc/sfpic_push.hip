@@ -175,6 +175,25 @@ struct PT<float> {
     p.uy[g] = __uint_as_float(sp[4 * st + s]);
     p.uz[g] = __uint_as_float(sp[5 * st + s]);
   }
+  // g2l in two halves: the slot's words into registers, then into LDS
+  __device__ static void fetch_words(const Particles<float> &p, uint32_t g,
+                                     int dims, Word w[kWords]) {
+    w[0] = p.cell[g];
+    w[1] = __float_as_uint(p.ox[g]);
+    w[2] = dims == 2 ? __float_as_uint(p.oy[g]) : 0u;
+    w[3] = __float_as_uint(p.ux[g]);
+    w[4] = __float_as_uint(p.uy[g]);
+    w[5] = __float_as_uint(p.uz[g]);
+  }
+  __device__ static void put_words(Word *sp, int s, int st, const Word w[kWords],
+                                   int dims) {
+    sp[s] = w[0];
+    sp[st + s] = w[1];
+    if (dims == 2) sp[2 * st + s] = w[2];
+    sp[3 * st + s] = w[3];
+    sp[4 * st + s] = w[4];
+    sp[5 * st + s] = w[5];
+  }
   // Unpack LDS slot s (stride st between arrays); false if removed.
   __device__ static bool unpack(const Word *sp, int s, int st, int dims,
                                 int &ix, int &iy, float &fx, float &fy,
@@ -497,6 +516,39 @@ __device__ __forceinline__ void push_tile(const Fields<R> &f,
   R *sf = (R *)(sj + 3 * WN);  // ex ey ez mx my mz windows
   const int P = f.pitch;
 
+  // Staged path: the words of the first chunk are loaded before the field
+  // window, so that their HBM latency overlaps the window loads; a single
+  // simulation's push also loads the next chunk while the current one is
+  // pushed (kAheadNext; the batched push keeps those registers for its
+  // fourth workgroup per CU and loads later chunks when it gets there).
+  // Thread t holds slots t + 256 j of the chunk (blockDim.x = 256).
+  constexpr bool kAhead = PT<R>::kStaged;
+  constexpr bool kAheadNext = kAhead && PER == kChunkPer;
+  constexpr int kAheadWords = 6;  // PT<float>::kWords
+  using CK = Chunk<PER>;
+  uint32_t *sp = (uint32_t *)(sf + 6 * WN);  // particle chunk after windows
+  uint32_t ahead[kAhead ? PER : 1][kAheadWords];
+  auto fetch_chunk = [&](uint32_t c0) {
+    if constexpr (kAhead) {
+#pragma unroll
+      for (int j = 0; j < PER; ++j) {
+        const uint32_t g = c0 + threadIdx.x + 256u * (uint32_t)j;
+        if (g < pend) PT<R>::fetch_words(p, g, DIMS, ahead[j]);
+      }
+    }
+  };
+  auto put_chunk = [&](int cn) {
+    if constexpr (kAhead) {
+#pragma unroll
+      for (int j = 0; j < PER; ++j) {
+        const int k = (int)threadIdx.x + 256 * j;
+        if (k < cn)
+          PT<R>::put_words(sp, chunk_slot<PER>(k), CK::pad, ahead[j], DIMS);
+      }
+    }
+  };
+  fetch_chunk(pbeg);
+
   // stage E^n and Bbar^n on the node window; array index = cx0 + local
   for (int k = threadIdx.x; k < WN; k += blockDim.x) {
     const int I = cx0 + k % WX - kSlack + 1;
@@ -518,6 +570,7 @@ __device__ __forceinline__ void push_tile(const Fields<R> &f,
     sj[WN + k] = Acc(0);
     sj[2 * WN + k] = Acc(0);
   }
+  put_chunk((int)min((uint32_t)CK::size, pend - pbeg));
   __syncthreads();
 
   // gather from the LDS window (window index of node p: p - c0 + kWinLo)
@@ -588,15 +641,17 @@ __device__ __forceinline__ void push_tile(const Fields<R> &f,
   } else {
     // Staged: chunks of the cell-sorted range through LDS, pushed in the
     // transposed order of Chunk.
-    using W = typename PT<R>::Word;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    using CK = Chunk<PER>;
-    W *sp = (W *)(sf + 6 * WN);  // particle chunk after the windows
     for (uint32_t c0 = pbeg; c0 < pend; c0 += CK::size) {
       const int cn = (int)min((uint32_t)CK::size, pend - c0);
-      for (int k = threadIdx.x; k < cn; k += blockDim.x)
-        PT<R>::g2l(p, c0 + k, sp, chunk_slot<PER>(k), CK::pad, DIMS);
-      __syncthreads();
+      const bool more = c0 + CK::size < pend;
+      if constexpr (kAheadNext) {
+        if (more) fetch_chunk(c0 + CK::size);
+      } else if (c0 != pbeg) {  // the first chunk is in LDS already
+        for (int k = threadIdx.x; k < cn; k += blockDim.x)
+          PT<R>::g2l(p, c0 + k, sp, chunk_slot<PER>(k), CK::pad, DIMS);
+        __syncthreads();
+      }
 #pragma unroll 1
       for (int j = 0; j < CK::per; ++j) {
         const int idx = lane * CK::stride + wv * CK::per + j;
@@ -611,8 +666,13 @@ __device__ __forceinline__ void push_tile(const Fields<R> &f,
           PT<R>::pack(sp, sl, CK::pad, DIMS, alive, ix, iy, fx, fy, u);
       }
       __syncthreads();
+      // each thread writes back the slots it then refills with the next
+      // chunk (its own slots: no barrier between the two)
       for (int k = threadIdx.x; k < cn; k += blockDim.x)
         PT<R>::l2g(p, c0 + k, sp, chunk_slot<PER>(k), CK::pad, DIMS);
+      if constexpr (kAheadNext) {
+        if (more) put_chunk((int)min((uint32_t)CK::size, pend - c0 - CK::size));
+      }
       __syncthreads();
     }
   }
