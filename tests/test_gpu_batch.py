@@ -97,6 +97,44 @@ def test_fp64_batch_members_match_oracle(mode):
     b.close()
 
 
+def _pulse_2d(precision):
+    """A 2D member lit by the plane pulse (no April beam)."""
+    dx = 2.0 * np.pi / 32
+    grid = wl.Grid(2, 96, 40, dx, dx, 0.95 * dx / np.sqrt(2.0))
+    fwhm = 3.0 * 2.0 * np.pi
+    inc = wl.Incident(kind=wl.INC_PLANE_PULSE_1D, a0=3.0, fwhm_t=fwhm,
+                      t0=fwhm - 30 * dx)
+    sp = wl.Species(q=-1.0, m=1.0, density=0.02, region=(30, 80, 0, 40),
+                    ppc=4, temperature_ev=1.0, seed=21)
+    return wl.Workload("pulse_2d", grid, [sp], inc, 40, precision)
+
+
+@pytest.mark.parametrize("prec", [wl.FP64, wl.FP32])
+def test_batch_of_mixed_models(prec):
+    """A 2D group in which one member has no April beam runs the push built
+    for every model (an all-April group runs the LP / RP pushes, which the
+    other tests cover); each member matches the oracle."""
+    members = [_lp(precision=prec), _pulse_2d(prec),
+               _lp(kind=wl.INC_APRIL_RP, w0_lambda=0.8, s=10.0, a0=30.0,
+                   temperature_ev=0.0, nx=96, ny=96, plasma=(30, 70, 20, 80),
+                   ppc=3, n=0.02, seed=12, precision=prec)]
+    steps = [40, 33, 37]
+    _note(f"[batch] mixed models, precision {prec}")
+    b = Batch(members, nsteps=steps, tile=(8, 4), sort_every=3, graph=False,
+              autotune=False)
+    b.run()
+    assert len(b.stats()["groups"]) == 1
+    tol = FP64_FIELD_TOL if prec == wl.FP64 else FP32_FIELD_TOL
+    for i, (work, n) in enumerate(zip(members, steps)):
+        o = make_oracle(work, explicit_species(work))
+        o.step(n)
+        rel, den = field_rel_l2(b.member(i), o)
+        _note(f"[batch] mixed member {i}: {rel:.2e}")
+        assert den > 0 and rel <= tol, (i, rel)
+        assert b.result(i)["status"] == 0
+    b.close()
+
+
 def test_fp32_batch_member_equals_its_run_alone():
     """Each FP32 member in the mix vs the same member run alone, and both vs
     the FP64 oracle."""
