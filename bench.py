@@ -523,17 +523,20 @@ def three_d(steps=20, warmup=2, cells_per_lambda=16, ppc=2, precision=0):
     return res
 
 
-def batched_sweep(members=256, steps=800):
-    """The laser-focus / density sweep as one batch: `members` FP32 2D3V
-    simulations (grid side 256..1024, 8..32 ppc, LP / RP, density and beam
-    drawn per member), `steps` steps each, tile and sort cadence from the
-    autotuner."""
+def batched_sweep(members=256, steps=800, precision=None):
+    """The laser-focus / density sweep as one batch: `members` FP32 (or, with
+    precision FP64, plain FP64) 2D3V simulations (grid side 256..1024, 8..32
+    ppc, LP / RP, density and beam drawn per member), `steps` steps each,
+    tile and sort cadence from the autotuner."""
     from paper_2310_11393_amd import workloads as wl
     from paper_2310_11393_amd.binding import Batch
-    ms = [wl.sweep_member(i) for i in range(members)]
+    if precision is None:
+        precision = wl.FP32
+    ms = [wl.sweep_member(i, precision=precision) for i in range(members)]
     npart = sum(w.species[0].count() for w in ms)
-    log(f"batched sweep: {members} members, {npart / 1e6:.1f}M particles, "
-        f"{steps} steps each")
+    kind = "FP32" if precision == wl.FP32 else "FP64"
+    log(f"batched sweep ({kind}): {members} members, {npart / 1e6:.1f}M "
+        f"particles, {steps} steps each")
     t0 = time.perf_counter()
     b = Batch(ms, nsteps=steps)
     t_create = time.perf_counter() - t0
@@ -543,9 +546,9 @@ def batched_sweep(members=256, steps=800):
     b.close()
     g = st["groups"][0]
     rate = st["pushes"] / (st["step_ms"] * 1e-3)
-    log(f"batched sweep: {rate / 1e9:.2f} G pushes/s, tile {g['tile']}, "
+    log(f"batched sweep ({kind}): {rate / 1e9:.2f} G pushes/s, tile {g['tile']}, "
         f"cadence {g['sort_every']}")
-    return {"workload": (f"{members} FP32 2D3V sweep members (side 256-1024 "
+    return {"workload": (f"{members} {kind} 2D3V sweep members (side 256-1024 "
                          f"cells at lambda/32, 8-32 ppc, n 0.001-0.1 n_c, "
                          f"w0 0.6-2 lambda, a0 5-50, LP/RP), {steps} steps "
                          f"each"),
@@ -674,6 +677,8 @@ def main():
                     help="skip the batched sweep")
     ap.add_argument("--batch-members", type=int, default=256)
     ap.add_argument("--batch-steps", type=int, default=800)
+    ap.add_argument("--batch-fp64", action="store_true",
+                    help="--only-batch: the sweep in plain FP64")
     ap.add_argument("--no-serve", action="store_true",
                     help="skip the served sweep")
     ap.add_argument("--serve-rate", type=float, default=20.0)
@@ -729,8 +734,10 @@ def main():
         sys.exit(1)
     torch.cuda.set_device(0)
     if args.only_batch:
+        from paper_2310_11393_amd import workloads as wl
+        prec = wl.FP64 if args.batch_fp64 else wl.FP32
         print(json.dumps({"batched_sweep": batched_sweep(
-            args.batch_members, args.batch_steps)}), flush=True)
+            args.batch_members, args.batch_steps, prec)}), flush=True)
         return
     if args.only_3d:
         res = {"three_d": three_d(steps=args.steps_3d, warmup=args.warmup)}
@@ -809,6 +816,12 @@ def main():
     if not args.no_batch:
         out["batched_sweep"] = batched_sweep(args.batch_members,
                                              args.batch_steps)
+        # the same sweep in plain FP64: the FP32 form's gain at batch scale
+        out["batched_sweep_fp64"] = batched_sweep(args.batch_members,
+                                                  args.batch_steps, wl.FP64)
+        out["batched_fp32_over_fp64"] = (
+            out["batched_sweep"]["pushes_per_s"] /
+            out["batched_sweep_fp64"]["pushes_per_s"])
     if not args.no_serve:
         out["served_sweep"] = served_sweep(args.serve_rate,
                                            args.serve_window,
