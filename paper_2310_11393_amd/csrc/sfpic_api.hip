@@ -554,6 +554,29 @@ int sim_footprint(const sfpic_grid *grid, const sfpic_species *species,
   return SFPIC_OK;
 }
 
+// Work items of every species for the current sort (the start offsets may
+// also have been rewritten by a batch's sorts); the arrays are (re)allocated
+// here when the tiling needs more than they hold.
+int refresh_items(sfpic_sim *s) {
+  for (auto &st : s->sp) {
+    const size_t words = push_items_words(s->tg, st.n, s->item_max);
+    if (words > st.items_words) {
+      HIP_TRY(hipStreamSynchronize(s->stream));  // old arrays may be queued
+      s->dfree(st.items);
+      if (!st.n_items) st.n_items = (uint32_t *)s->dalloc(4);
+      st.items = (uint32_t *)s->dalloc(words * 4);
+      if (!st.items || !st.n_items) {
+        st.items_words = 0;
+        return fail(SFPIC_E_NOMEM, "work-item allocation failed");
+      }
+      st.items_words = words;
+    }
+    HIP_TRY(launch_build_items(st.start, s->tg, s->item_max, st.items,
+                               st.n_items, s->stream));
+  }
+  return SFPIC_OK;
+}
+
 }  // namespace sfpic
 
 namespace {
@@ -611,29 +634,6 @@ hipError_t timed(sfpic_sim *s, int cls, F &&launch) {
   if (r == hipSuccess) r = hipEventRecord(e.second, s->stream);
   s->ev_used[cls].push_back(e);
   return r;
-}
-
-// Work items of every species for the current sort (the start offsets may
-// also have been rewritten by a batch's sorts); the arrays are (re)allocated
-// here when the tiling needs more than they hold.
-int refresh_items(sfpic_sim *s) {
-  for (auto &st : s->sp) {
-    const size_t words = push_items_words(s->tg, st.n, s->item_max);
-    if (words > st.items_words) {
-      HIP_TRY(hipStreamSynchronize(s->stream));  // old arrays may be queued
-      s->dfree(st.items);
-      if (!st.n_items) st.n_items = (uint32_t *)s->dalloc(4);
-      st.items = (uint32_t *)s->dalloc(words * 4);
-      if (!st.items || !st.n_items) {
-        st.items_words = 0;
-        return fail(SFPIC_E_NOMEM, "work-item allocation failed");
-      }
-      st.items_words = words;
-    }
-    HIP_TRY(launch_build_items(st.start, s->tg, s->item_max, st.items,
-                               st.n_items, s->stream));
-  }
-  return SFPIC_OK;
 }
 
 template <typename R>

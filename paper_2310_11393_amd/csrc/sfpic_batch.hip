@@ -245,6 +245,8 @@ struct Engine {
     off = al(off + (size_t)(2 + np + 8) * 4);
     const size_t o_due = off;
     off = al(off + (size_t)(np > 0 ? np : 1) * 4);
+    const size_t o_item = off;
+    off = al(off + (size_t)(np + 1) * 4);
     if (off > g.dbytes) {
       HIP_TRY(hipStreamSynchronize(stream));
       if (g.dbuf) (void)hipFree(g.dbuf);
@@ -269,6 +271,9 @@ struct Engine {
       Member *m = g.members[mi];
       sfpic_sim *s = m->sim;
       const sfpic_grid &gr = s->grid;
+      // the push items of the member's current sort (the batch rebuilds
+      // them after each of its sorts)
+      SF_TRY(refresh_items(s));
       ms[mi].step = s->step;
       ms[mi].steps_left = m->nsteps - m->done;
       ms[mi].since_sort = 0;
@@ -331,6 +336,9 @@ struct Engine {
         P.n_slots = (uint32_t)st.n;
         P.member = mi;
         P.cur = 0;
+        P.items = st.items;
+        P.n_items = st.n_items;
+        P.kmax = s->item_max;
         tab[2][j + 1] = tab[2][j] + (uint32_t)s->tg.ntiles;
       }
     }
@@ -349,6 +357,7 @@ struct Engine {
     v.tile_off = (const uint32_t *)(d + o_tab[2]);
     v.counters = (uint32_t *)(d + o_cnt);
     v.due = (uint32_t *)(d + o_due);
+    v.item_off = (uint32_t *)(d + o_item);
     v.n_far = tab[0][nm];
     v.n_amp = tab[1][nm];
     v.n_tiles = tab[2][np];
@@ -385,6 +394,7 @@ struct Engine {
   int enqueue_step_t(Group &g, const BatchView<R> &v) {
     HIP_TRY(launch_fill_u32(v.counters, 0u, (size_t)(2 + v.np + 8), stream));
     HIP_TRY(launch_batch_faraday<R>(v, g.dims, stream));
+    HIP_TRY(launch_batch_item_offsets<R>(v, stream));
     HIP_TRY(launch_batch_push<R>(v, g.dims, g.april, g.lds, g.grid, stream));
     HIP_TRY(launch_batch_stragglers<R>(v, g.dims, stream));
     HIP_TRY(launch_batch_ampere<R>(v, g.dims, stream));

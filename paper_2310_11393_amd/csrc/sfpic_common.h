@@ -151,6 +151,10 @@ struct PushJob {
   uint32_t n_slots;
   int member;
   int cur;             // flipped on the device by every sort
+  // work items of the push, (tile, first particle), rebuilt after each of
+  // the job's sorts; at most kmax particles each
+  uint32_t *items, *n_items;
+  uint32_t kmax;
 };
 
 // Device view of one batch group.  Offset tables have n + 1 entries.
@@ -167,6 +171,9 @@ struct BatchView {
   // push's item band x (x = 0 .. 7)
   uint32_t *counters;
   uint32_t *due;
+  // push items of every job, prefix over the jobs (np + 1 entries; the
+  // jobs of finished members have none), formed at the start of each step
+  uint32_t *item_off;
   uint32_t n_far, n_amp, n_tiles;
 };
 
@@ -687,6 +694,10 @@ hipError_t launch_batch_stragglers(const BatchView<R> &v, int dims,
                                    hipStream_t st);
 template <typename R>
 hipError_t launch_batch_sort(const BatchView<R> &v, int dims, hipStream_t st);
+// The push items of every job of the step (item_off), from the jobs' item
+// counts and their members' steps left.
+template <typename R>
+hipError_t launch_batch_item_offsets(const BatchView<R> &v, hipStream_t st);
 template <typename R>
 hipError_t launch_batch_advance(const BatchView<R> &v, SortRule rule,
                                 hipStream_t st);

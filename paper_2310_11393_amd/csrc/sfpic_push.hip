@@ -695,10 +695,11 @@ __device__ __forceinline__ void push_tile(const Fields<R> &f,
 // several workgroups instead of leaving one of them running long after the
 // rest, and empty tiles cost nothing.  One workgroup of 1024 threads; each
 // thread takes 8 consecutive tiles per pass.
-__global__ void __launch_bounds__(1024)
-build_items(const uint32_t *__restrict__ start, uint32_t cpt, int ntiles,
-            uint32_t kmax, uint32_t *items, uint32_t *n_items) {
-  __shared__ uint32_t sh[1024];
+__device__ __forceinline__ void build_items_at(const uint32_t *__restrict__ start,
+                                               uint32_t cpt, int ntiles,
+                                               uint32_t kmax, uint32_t *items,
+                                               uint32_t *n_items,
+                                               uint32_t *sh) {
   uint32_t carry = 0;
   for (int t0 = 0; t0 < ntiles; t0 += 8192) {
     const int tb = t0 + (int)threadIdx.x * 8;
@@ -730,6 +731,13 @@ build_items(const uint32_t *__restrict__ start, uint32_t cpt, int ntiles,
     __syncthreads();
   }
   if (threadIdx.x == 0) *n_items = carry;
+}
+
+__global__ void __launch_bounds__(1024)
+build_items(const uint32_t *__restrict__ start, uint32_t cpt, int ntiles,
+            uint32_t kmax, uint32_t *items, uint32_t *n_items) {
+  __shared__ uint32_t sh[1024];
+  build_items_at(start, cpt, ntiles, kmax, items, n_items, sh);
 }
 
 // Upper bound of the item count: every tile once plus one per kmax particles.
@@ -1217,8 +1225,10 @@ batch_push_kernel(BatchView<R> v) {
   // x]); the hardware deals workgroups to the 8 XCDs round-robin, so
   // workgroup b starts on band b mod 8 -- neighbouring tiles, whose halos
   // overlap, are then pushed by one XCD and meet in its L2 -- and moves on
-  // to the next band when its own is exhausted.
-  const uint32_t S = (v.n_tiles + 7) >> 3;
+  // to the next band when its own is exhausted.  The items are the jobs'
+  // work items (non-empty tiles, dense ones cut into pieces of at most kmax
+  // particles) of the running members, in job order (item_off).
+  const uint32_t n = v.item_off[v.np], S = (n + 7) >> 3;
   for (int band = 0; band < 8;) {
     const uint32_t x = (blockIdx.x + (uint32_t)band) & 7u;
     if (threadIdx.x == 0) s_item = atomicAdd(&v.counters[2 + v.np + x], 1u);
@@ -1226,17 +1236,18 @@ batch_push_kernel(BatchView<R> v) {
     const uint32_t k = __builtin_amdgcn_readfirstlane(s_item);
     __syncthreads();  // s_item is rewritten only after every thread read it
     const uint32_t item = x * S + k;
-    if (k >= S || item >= v.n_tiles) {
+    if (k >= S || item >= n) {
       ++band;
       continue;
     }
-    const int jb = find_segment(v.tile_off, v.np, item);
+    const int jb = find_segment(v.item_off, v.np, item);
     const PushJob<R> &J = v.pjobs[jb];
-    if (v.ms[J.member].steps_left <= 0) continue;
     const PushParams pp = member_params(v, J);
-    const int tile = (int)(item - v.tile_off[jb]);
-    const size_t t0 = (size_t)tile * J.tg.cells_per_tile;
-    const uint32_t pb = J.start[t0], pe = J.start[t0 + J.tg.cells_per_tile];
+    const uint32_t q = item - v.item_off[jb];
+    const int tile = (int)J.items[2 * (size_t)q];
+    const uint32_t pb = J.items[2 * (size_t)q + 1];
+    const uint32_t tend = J.start[(size_t)(tile + 1) * J.tg.cells_per_tile];
+    const uint32_t pe = tend - pb > J.kmax ? pb + J.kmax : tend;
     if constexpr (APRIL) {
       if (J.inc.kind == 3)
         push_tile<R, DIMS, kIncRP, kBatchChunkPer>(
@@ -1252,6 +1263,55 @@ batch_push_kernel(BatchView<R> v) {
           tile, pb, pe, smem);
     }
   }
+}
+
+// Prefix of the jobs' item counts (one workgroup of 1024 threads): the jobs
+// of members with no steps left contribute none.
+template <typename R>
+__global__ void __launch_bounds__(1024)
+batch_item_offsets(BatchView<R> v) {
+  __shared__ uint32_t sh[1024];
+  uint32_t carry = 0;
+  for (int base = 0; base < v.np; base += 1024) {
+    const int j = base + (int)threadIdx.x;
+    uint32_t c = 0;
+    if (j < v.np) {
+      const PushJob<R> &J = v.pjobs[j];
+      if (v.ms[J.member].steps_left > 0) c = *J.n_items;
+    }
+    sh[threadIdx.x] = c;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+      const uint32_t add =
+          threadIdx.x >= (unsigned)o ? sh[threadIdx.x - o] : 0u;
+      __syncthreads();
+      sh[threadIdx.x] += add;
+      __syncthreads();
+    }
+    if (j < v.np) v.item_off[j] = carry + sh[threadIdx.x] - c;
+    carry += sh[1023];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) v.item_off[v.np] = carry;
+}
+
+// Work items of the jobs sorted this step (one workgroup per job).
+template <typename R>
+__global__ void __launch_bounds__(1024) batch_build_items(BatchView<R> v) {
+  __shared__ uint32_t sh[1024];
+  const uint32_t nd = v.counters[1 + v.np];
+  for (uint32_t d = blockIdx.x; d < nd; d += gridDim.x) {
+    const PushJob<R> &J = v.pjobs[v.due[d]];
+    build_items_at(J.start, J.tg.cells_per_tile, J.tg.ntiles, J.kmax, J.items,
+                   J.n_items, sh);
+  }
+}
+
+template <typename R>
+hipError_t launch_batch_item_offsets(const BatchView<R> &v, hipStream_t st) {
+  if (v.np == 0) return hipSuccess;
+  batch_item_offsets<R><<<1, 1024, 0, st>>>(v);
+  return hipGetLastError();
 }
 
 // Stragglers: a persistent grid; every workgroup takes its share of every
@@ -1405,6 +1465,8 @@ hipError_t launch_batch_sort(const BatchView<R> &v, int dims, hipStream_t st) {
   batch_scan_add<R><<<g, 256, 0, st>>>(v);
   batch_sort_scatter<R><<<g, 256, 0, st>>>(v, dims);
   batch_sort_finish<R><<<(v.np + 255) / 256, 256, 0, st>>>(v);
+  batch_build_items<R><<<(unsigned)(v.np < 256 ? v.np : 256), 1024, 0, st>>>(
+      v);
   return hipGetLastError();
 }
 
@@ -1428,7 +1490,9 @@ hipError_t launch_batch_sort(const BatchView<R> &v, int dims, hipStream_t st) {
   template hipError_t launch_batch_stragglers<R>(const BatchView<R> &, int,  \
                                                  hipStream_t);               \
   template hipError_t launch_batch_sort<R>(const BatchView<R> &, int,        \
-                                           hipStream_t);
+                                           hipStream_t);                     \
+  template hipError_t launch_batch_item_offsets<R>(const BatchView<R> &,     \
+                                                   hipStream_t);
 
 SFPIC_INSTANTIATE(double)
 SFPIC_INSTANTIATE(float)

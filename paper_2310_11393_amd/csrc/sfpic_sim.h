@@ -238,6 +238,9 @@ namespace sfpic {
 
 // Internal operations used by the batch and server runtime.
 int sort_all(sfpic_sim *s);
+// (Re)allocate every species' push work items for the tiling and particle
+// count and build them from the current sort.
+int refresh_items(sfpic_sim *s);
 // Set the particle tile to tx x ty cells with drift allowance slack (0:
 // keep the current one), reallocating the sort arrays when the key count
 // grows, and re-sort every species.
