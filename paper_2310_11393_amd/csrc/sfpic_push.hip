@@ -377,8 +377,19 @@ __device__ __forceinline__ void shapes4(const R w0[3], R d0, R d1, R S0[4],
   S0[1] = o ? w0[1] : w0[0];
   S0[2] = o ? w0[2] : w0[1];
   S0[3] = o ? R(0) : w0[2];
-#pragma unroll
-  for (int k = 0; k < 4; ++k) S1[k] = spline2(d1 - R(k - 2 + o));
+  // S1: the three weights about the new nearest node c1 (relative to ipx),
+  // found as the next step will find it from the stored cell and offset,
+  // so that S1 is that step's S0; its first node c1 - 1 is frame node 0
+  // when o - c1 = 1 and frame node 1 when o = c1.
+  const R cf = floor(d1), f1 = d1 - cf;
+  const R h1 = f1 >= R(0.5) ? R(1) : R(0);
+  R w1[3];
+  weights3(f1 - h1, w1);
+  const bool lead = R(o) - (cf + h1) == R(1);
+  S1[0] = lead ? w1[0] : R(0);
+  S1[1] = lead ? w1[1] : w1[0];
+  S1[2] = lead ? w1[2] : w1[1];
+  S1[3] = lead ? R(0) : w1[2];
   lo = (d1 < R(-0.5) ? 0 : 1) - o;
   hi = (d1 > R(0.5) ? 4 : 3) - o;
 }
