@@ -539,25 +539,34 @@ push3_tiled(F3<R> f, Geo g, Parts3<R> p, const uint32_t *__restrict__ start, Til
     // over all four is zero).  When the nearest node does not change, the
     // shapes cover three nodes and only two entries of the running sum are
     // non-zero (the other is zero, or a rounding residue of a zero sum, and
-    // is not added): entries kd_lo .. kd_hi.
+    // is not added): entries kd_lo .. kd_hi.  Each shape is the three
+    // order-2 weights about its nearest node (S1 about the new one, c1,
+    // exactly as the next step's gather and S0 will find them), placed in
+    // the frame: S0 from frame node 1 - up, S1 from frame node 0 when
+    // c1 - c = up - 1 and from node 1 otherwise.
     double M[3][4], D[3][4], x1[3];
     int lo[3], kd_lo[3], kd_hi[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       x1[d] = xi[d] + a.dt * a.inv_h[d] * (u[d] * gi);
-      const double c = floor(xi[d] + 0.5);
+      const double c = floor(xi[d] + 0.5), c1 = floor(x1[d] + 0.5);
       const int up = x1[d] >= xi[d];
-      const bool same = floor(x1[d] + 0.5) == c;
+      const bool same = c1 == c;
       lo[d] = (int)c - 2 + up - w0[d];  // window index of the first node
       kd_lo[d] = (!up && same) ? 1 : 0;
       kd_hi[d] = (up && same) ? 1 : 2;
-      const double first = c - 2.0 + (double)up;
+      double w[3], w1[3];
+      sfpic::weights3(xi[d] - c, w);
+      sfpic::weights3(x1[d] - c1, w1);
+      const bool lead = c1 - c == (double)(up - 1);
+      const double S0[4] = {up ? w[0] : 0.0, up ? w[1] : w[0],
+                            up ? w[2] : w[1], up ? 0.0 : w[2]};
+      const double S1[4] = {lead ? w1[0] : 0.0, lead ? w1[1] : w1[0],
+                            lead ? w1[2] : w1[1], lead ? 0.0 : w1[2]};
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
-        const double node = first + (double)k;
-        const double s0 = sfpic::spline2(xi[d] - node);
-        D[d][k] = sfpic::spline2(x1[d] - node) - s0;
-        M[d][k] = s0 + 0.5 * D[d][k];
+        D[d][k] = S1[k] - S0[k];
+        M[d][k] = S0[k] + 0.5 * D[d][k];
       }
     }
     constexpr double twelfth = 1.0 / 12.0;
