@@ -363,12 +363,13 @@ __device__ __forceinline__ void esirkepov(const R S0x[4], const R S1x[4],
   }
 }
 
-// Shapes on the 4-node frame of one axis: the old nearest node ipx and the
-// new offset d1 = xi^{n+1} - ipx.  A move below one cell keeps the new
-// nearest node within one of ipx, so the frame ipx - 1 .. ipx + 2 (o = 1,
-// d1 >= d0) or ipx - 2 .. ipx + 1 (o = 0) holds both shapes: S0 from the
-// three order-2 weights at x^n, S1 at d1; [lo, hi]: the nodes either touches.
-// (Frame node k is node ipx - 2 + o + k.)
+// Shapes on the 4-node frame of one axis, from the old nearest node ipx,
+// the old offset d0 and the new one d1 = xi^{n+1} - ipx.  A move below one
+// cell keeps the new nearest node within one of ipx, so the frame ipx - 1
+// .. ipx + 2 (o = 1, d1 >= d0) or ipx - 2 .. ipx + 1 (o = 0) holds both
+// shapes, each the three order-2 weights about its nearest node (w0 for
+// S0); [lo, hi]: the frame nodes either touches.  (Frame node k is node
+// ipx - 2 + o + k.)
 template <typename R>
 __device__ __forceinline__ void shapes4(const R w0[3], R d0, R d1, R S0[4],
                                         R S1[4], int &o, int &lo, int &hi) {
