@@ -178,9 +178,10 @@ typedef struct {
                              batches and servers: autotuned or 4)        */
   int32_t device;         /* HIP device ordinal                            */
   int32_t flags;          /* SFPIC_RT_* (batches and servers)              */
-  int32_t item_particles; /* single sims: a tile holding more particles is
-                             pushed by several workgroups, this many each;
-                             0 = default (8192); must be >= 64            */
+  int32_t item_particles; /* a tile holding more particles is pushed by
+                             several workgroups, this many each (single
+                             sims, batch and server members); 0 = default
+                             (8192); must be >= 64                       */
 } sfpic_runtime;
 
 /* runtime.flags: launch a batch's steps one by one instead of replaying a

@@ -619,7 +619,8 @@ class Batch:
     own stream."""
 
     def __init__(self, members, nsteps=None, hist=None, device=0,
-                 tile=(0, 0), sort_every=0, graph=True, autotune=True):
+                 tile=(0, 0), sort_every=0, graph=True, autotune=True,
+                 item_particles=0):
         L = lib()
         if not isinstance(nsteps, (list, tuple)):
             nsteps = [nsteps] * len(members)
@@ -628,7 +629,8 @@ class Batch:
             *[d.desc for d in self.descs])
         flags = (0 if graph else RT_NO_GRAPH) | (0 if autotune
                                                  else RT_NO_AUTOTUNE)
-        self._rt, _ = make_runtime(False, device, tile, sort_every, flags)
+        self._rt, _ = make_runtime(False, device, tile, sort_every, flags,
+                                   item_particles)
         h = C.c_void_p()
         _check(L.sfpic_batch_create(len(self.descs), arr, C.byref(self._rt),
                                     C.byref(h)))

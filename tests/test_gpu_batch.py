@@ -57,11 +57,17 @@ def _members(precision):
 STEPS = [50, 37, 44, 41]  # not all multiples of any cadence
 
 
-@pytest.mark.parametrize("mode", ["graph", "fixed_eager"])
+@pytest.mark.parametrize("mode", ["graph", "fixed_eager", "split_items"])
 def test_fp64_batch_members_match_oracle(mode):
+    """Every member of an FP64 batch against its own oracle run: replayed
+    graphs with the library's defaults, eager launches with a fixed tile and
+    cadence, and work items of at most 64 particles (every tile shared by
+    several workgroups of the persistent push)."""
     members = _members(wl.FP64)
-    kw = {} if mode == "graph" else dict(tile=(8, 4), sort_every=3,
-                                         graph=False, autotune=False)
+    kw = ({} if mode == "graph" else
+          dict(tile=(8, 4), sort_every=3, graph=False, autotune=False))
+    if mode == "split_items":
+        kw.update(tile=(16, 8), item_particles=64)
     _note(f"[batch] fp64 {mode}: {len(members)} members")
     b = Batch(members, nsteps=STEPS, **kw)
     b.run()
