@@ -121,7 +121,7 @@ typedef struct {
   double weight;            /* explicit: density per macro-particle      */
   const double *x, *y, *ux, *uy, *uz; /* explicit (y ignored in 1D)      */
   /* generated, optional density profile along x (the propagation axis),
-   * see SFPIC_PROFILE_*; single simulations only (batches reject it) */
+   * see SFPIC_PROFILE_* (Sec. 3.1) */
   int32_t profile;
   double profile_center, profile_fwhm, profile_order, profile_xmin;
 } sfpic_species;

@@ -74,17 +74,6 @@ int check_desc(const sfpic_sim_desc *d) {
        d->hist.n_theta <= 0 || !(d->hist.e_max > 0.0) ||
        d->hist.plane < SFPIC_ANGLE_POLAR || d->hist.plane > SFPIC_ANGLE_XY))
     return fail(SFPIC_E_INVAL, "bad histogram spec");
-  if (d->incident.on_nodes)
-    return fail(SFPIC_E_INVAL,
-                "incident on_nodes is supported for single simulations only");
-  for (int k = 0; k < d->nspecies; ++k)
-    if (d->species[k].n_explicit == 0 &&
-        d->species[k].profile != SFPIC_PROFILE_UNIFORM)
-      return fail(SFPIC_E_INVAL,
-                  "density profiles are supported for single simulations only");
-  if (d->incident.kind == SFPIC_INC_GAUSS_2D)
-    return fail(SFPIC_E_INVAL,
-                "the Gaussian beam is supported for single simulations only");
   return SFPIC_OK;
 }
 
@@ -119,6 +108,8 @@ struct Group {
   // every member's beam is an April beam at the particles: the push runs
   // the kernel compiled for the LP and RP beams alone
   bool april = false;
+  // some member takes the incident field sampled on the nodes
+  bool on_nodes = false;
   hipGraphExec_t exec = nullptr;
   bool stale = true;  // tables (and graph) must be rebuilt before launching
   bool ran = false;   // work was launched since the host view was refreshed
@@ -266,7 +257,7 @@ struct Engine {
     for (int t = 0; t < 3; ++t) tab[t][0] = 0;
     int j = 0;
     size_t lds = 0, dyn = 0;
-    bool april = true;
+    bool april = true, on_nodes = false;
     for (int mi = 0; mi < nm; ++mi) {
       Member *m = g.members[mi];
       sfpic_sim *s = m->sim;
@@ -307,6 +298,7 @@ struct Engine {
       april = april && !s->inc.on_nodes &&
               (s->inc.kind == SFPIC_INC_APRIL_LP ||
                s->inc.kind == SFPIC_INC_APRIL_RP);
+      on_nodes = on_nodes || (s->inc.on_nodes && !s->sp.empty());
       for (size_t k = 0; k < s->sp.size(); ++k, ++j) {
         SpeciesState &st = s->sp[k];
         PushJob<R> &P = pj[j];
@@ -367,6 +359,7 @@ struct Engine {
     g.built = g.members;
     g.lds = dyn;  // passed at launch; static chunk buffers come on top
     g.april = april && g.dims == 2;
+    g.on_nodes = on_nodes;
     const int per_cu = batch_push_blocks_per_cu(g.precision == SFPIC_FP64,
                                                 g.dims, g.april, dyn);
     int grid = cus * (per_cu > 0 ? per_cu : 1);
@@ -394,6 +387,7 @@ struct Engine {
   int enqueue_step_t(Group &g, const BatchView<R> &v) {
     HIP_TRY(launch_fill_u32(v.counters, 0u, (size_t)(2 + v.np + 8), stream));
     HIP_TRY(launch_batch_faraday<R>(v, g.dims, stream));
+    if (g.on_nodes) HIP_TRY(launch_batch_incident_nodes<R>(v, g.dims, stream));
     HIP_TRY(launch_batch_item_offsets<R>(v, stream));
     HIP_TRY(launch_batch_push<R>(v, g.dims, g.april, g.lds, g.grid, stream));
     HIP_TRY(launch_batch_stragglers<R>(v, g.dims, stream));
@@ -684,7 +678,9 @@ int create_member(Engine &eng, const sfpic_sim_desc &d, Member &m) {
   m.nsteps = d.nsteps;
   m.done = 0;
   m.hist = d.hist;
-  m.n0 = desc_particles(d);
+  // particles placed (a density profile places fewer than region x ppc)
+  m.n0 = 0.0;
+  for (const auto &st : s->sp) m.n0 += (double)st.n;
   return SFPIC_OK;
 }
 

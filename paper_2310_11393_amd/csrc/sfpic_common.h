@@ -684,6 +684,11 @@ hipError_t launch_batch_faraday(const BatchView<R> &v, int dims,
 template <typename R>
 hipError_t launch_batch_ampere(const BatchView<R> &v, int dims,
                                hipStream_t st);
+// The incident field sampled on the nodes of the members that take it from
+// there, at each member's own time.
+template <typename R>
+hipError_t launch_batch_incident_nodes(const BatchView<R> &v, int dims,
+                                       hipStream_t st);
 // april: every push job has an April beam at the particles (see
 // batch_push_kernel)
 template <typename R>

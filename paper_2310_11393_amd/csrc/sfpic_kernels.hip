@@ -222,6 +222,57 @@ hipError_t launch_batch_faraday(const BatchView<R> &v, int dims,
   return hipGetLastError();
 }
 
+// The incident field sampled on the Yee nodes at t^n for the members that
+// take it from there (IncParams::on_nodes), over the Faraday pass's blocks;
+// as incident_nodes_kernel, with the member's time from its device step.
+template <typename R, int DIMS>
+__global__ void __launch_bounds__(256)
+batch_incident_nodes_kernel(BatchView<R> v) {
+  const uint32_t b = blockIdx.x;
+  const int jb = find_segment(v.far_off, v.nf, b);
+  const FieldJob<R> &J = v.fjobs[jb];
+  const MemberState &m = v.ms[J.member];
+  if (m.steps_left <= 0 || J.njobs == 0) return;
+  const PushJob<R> &P = v.pjobs[J.job0];
+  if (!P.inc.on_nodes) return;
+  const uint32_t lb = b - v.far_off[jb];
+  const int t = threadIdx.x;
+  int i, j;
+  if (DIMS == 2) {
+    const int nbx = (J.f.nx_alloc + 63) / 64;
+    i = (int)(lb % nbx) * 64 + (t & 63);
+    j = (int)(lb / nbx) * 4 + (t >> 6);
+  } else {
+    i = (int)lb * 256 + t;
+    j = 0;
+  }
+  if (i >= J.f.nx_alloc || j >= J.f.ny_alloc) return;
+  const double dx = P.pp.dx, dy = P.pp.dy, time = (double)m.step * P.pp.dt;
+  const size_t k = (size_t)j * J.f.pitch + i;
+  const double xp = (double)(i - kGuard) * dx;
+  const double xd = ((double)(i - kGuard) + 0.5) * dx;
+  const double yp = DIMS == 2 ? (double)(j - kGuard) * dy : 0.0;
+  const double yd = DIMS == 2 ? ((double)(j - kGuard) + 0.5) * dy : 0.0;
+  double E[3], B[3];
+  incident_field(P.inc, DIMS, xd, yp, time, E, B);
+  J.f.iex[k] = (R)E[0];
+  incident_field(P.inc, DIMS, xp, yd, time, E, B);
+  J.f.iey[k] = (R)E[1];
+  incident_field(P.inc, DIMS, xd, yd, time, E, B);
+  J.f.ibz[k] = (R)B[2];
+}
+
+template <typename R>
+hipError_t launch_batch_incident_nodes(const BatchView<R> &v, int dims,
+                                       hipStream_t st) {
+  if (v.n_far == 0) return hipSuccess;
+  if (dims == 1)
+    batch_incident_nodes_kernel<R, 1><<<v.n_far, 256, 0, st>>>(v);
+  else
+    batch_incident_nodes_kernel<R, 2><<<v.n_far, 256, 0, st>>>(v);
+  return hipGetLastError();
+}
+
 template <typename R>
 hipError_t launch_batch_ampere(const BatchView<R> &v, int dims,
                                hipStream_t st) {
@@ -840,6 +891,8 @@ hipError_t launch_export_particles(const Particles<R> &p, int64_t n, int dims,
                                               hipStream_t);                   \
   template hipError_t launch_batch_ampere<R>(const BatchView<R> &, int,       \
                                              hipStream_t);                    \
+  template hipError_t launch_batch_incident_nodes<R>(const BatchView<R> &,    \
+                                                     int, hipStream_t);       \
   template hipError_t launch_batch_advance<R>(const BatchView<R> &, SortRule, \
                                               hipStream_t);
 

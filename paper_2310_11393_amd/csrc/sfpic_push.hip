@@ -1227,9 +1227,15 @@ __device__ __forceinline__ PushParams member_params(const BatchView<R> &v,
 // APRIL: every push job of the group has an April beam at the particles;
 // each tile then runs the push compiled for its member's beam (LP or RP),
 // whose registers leave room for more waves than the push built for every
-// model.
+// model and either source (the incident field at the particles or sampled
+// on the nodes), which the other groups run.
+template <typename R, bool APRIL>
+constexpr int batch_push_min_blocks() {
+  return (APRIL && sizeof(R) == 4) ? 4 : SFPIC_PUSH_MIN_BLOCKS;
+}
+
 template <typename R, int DIMS, bool APRIL>
-__global__ void __launch_bounds__(256, SFPIC_PUSH_MIN_BLOCKS)
+__global__ void __launch_bounds__(256, (batch_push_min_blocks<R, APRIL>()))
 batch_push_kernel(BatchView<R> v) {
   extern __shared__ double smem[];
   __shared__ uint32_t s_item;
@@ -1270,7 +1276,7 @@ batch_push_kernel(BatchView<R> v) {
             J.f, J.pa[J.cur], J.tg, pp, J.inc, J.strag, &v.counters[1 + jb],
             tile, pb, pe, smem);
     } else {
-      push_tile<R, DIMS, kIncAtParticle, kBatchChunkPer>(
+      push_tile<R, DIMS, kIncAny, kBatchChunkPer>(
           J.f, J.pa[J.cur], J.tg, pp, J.inc, J.strag, &v.counters[1 + jb],
           tile, pb, pe, smem);
     }

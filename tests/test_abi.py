@@ -162,17 +162,6 @@ def test_batch_and_server_reject_bad_arguments(L):
     assert b"nsteps" in L.sfpic_last_error(None)
     d = b.SimDesc(wl.sweep_member(0), hist=b.hist_spec(sp=3))
     assert L.sfpic_batch_create(1, C.byref(d.desc), None, C.byref(h)) == -1
-    w = wl.sweep_member(0)
-    w.incident.on_nodes = 1
-    d = b.SimDesc(w)
-    assert L.sfpic_batch_create(1, C.byref(d.desc), None, C.byref(h)) == -1
-    assert b"on_nodes" in L.sfpic_last_error(None)
-    w = wl.sweep_member(0)
-    w.species[0].profile = wl.PROFILE_SUPERGAUSS
-    w.species[0].profile_fwhm, w.species[0].profile_order = 20.0, 12.0
-    d = b.SimDesc(w)
-    assert L.sfpic_batch_create(1, C.byref(d.desc), None, C.byref(h)) == -1
-    assert b"profile" in L.sfpic_last_error(None)
     assert L.sfpic_server_create(0, 0, None, C.byref(h)) == -1
     assert L.sfpic_batch_run(None) == -1
     assert L.sfpic_server_submit(None, None, None) == -1

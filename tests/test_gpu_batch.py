@@ -141,6 +141,60 @@ def test_batch_of_mixed_models(prec):
     b.close()
 
 
+def _profiled_lp(precision):
+    """An LP member whose plasma follows the Sec. 3.1 super-Gaussian profile
+    along x."""
+    w = _lp(precision=precision, ppc=6, seed=14)
+    sp = w.species[0]
+    sp.profile = wl.PROFILE_SUPERGAUSS
+    sp.profile_center, sp.profile_fwhm = 70.0 * w.grid.dx, 30.0 * w.grid.dx
+    sp.profile_order, sp.profile_xmin = 12.0, 40.0 * w.grid.dx
+    return w
+
+
+@pytest.mark.parametrize("prec", [wl.FP64, wl.FP32])
+def test_batch_of_every_incident_source(prec):
+    """A 2D batch whose members take the incident field every way a single
+    simulation can: the April beam sampled on the Yee nodes, the paraxial
+    Gaussian beam at the particles, and an April beam on a plasma with the
+    Sec. 3.1 density profile; each member matches the oracle."""
+    on_nodes = _lp(precision=prec, seed=15)
+    on_nodes.incident.on_nodes = 1
+    gauss = wl.gauss_beam_2d(nx=160, ny=96, plasma=(50, 110, 20, 76), ppc=4,
+                             w0_lambda=2.0, cycles=3.0, a0=3.0, steps=40,
+                             cells_per_lambda=24)
+    gauss.precision = prec
+    members = [on_nodes, gauss, _profiled_lp(prec)]
+    steps = [40, 35, 38]
+    _note(f"[batch] every source, precision {prec}")
+    b = Batch(members, nsteps=steps, tile=(8, 4), sort_every=3, graph=True,
+              autotune=False)
+    b.run()
+    assert len(b.stats()["groups"]) == 1
+    tol = FP64_FIELD_TOL if prec == wl.FP64 else FP32_FIELD_TOL
+    for i, (work, n) in enumerate(zip(members, steps)):
+        sp = explicit_species(work)
+        o = make_oracle(work, sp)
+        o.step(n)
+        rel, den = field_rel_l2(b.member(i), o)
+        _note(f"[batch] source member {i}: {rel:.2e}")
+        assert den > 0 and rel <= tol, (i, rel)
+        r = b.result(i)
+        assert r["status"] == 0 and r["steps"] == n
+        assert r["diag"]["n_alive"] == o.diagnostics()["n_alive"]
+    # the profiled member's pushes count the particles it placed, which the
+    # profile makes fewer than its region times ppc
+    w = members[2]
+    sp = w.species[0]
+    placed = sp.count(w.grid.dx)
+    assert placed < (sp.region[1] - sp.region[0]) * \
+        (sp.region[3] - sp.region[2]) * sp.ppc
+    r = b.result(2)
+    assert r["pushes"] == pytest.approx(
+        steps[2] * 0.5 * (placed + r["diag"]["n_alive"]), rel=1e-12)
+    b.close()
+
+
 def test_fp32_batch_member_equals_its_run_alone():
     """Each FP32 member in the mix vs the same member run alone, and both vs
     the FP64 oracle."""
