@@ -308,12 +308,20 @@ def test_batch_graph_replays_equal_eager_launches():
 def test_server_results_equal_runs_alone():
     """Requests submitted while others run join at the next tick; each
     result equals the same simulation run alone (FP64 to 1e-11 on the
-    energies, FP32 to 1e-4)."""
+    energies, FP32 to 1e-4), also for a request with the incident field on
+    the nodes and one with the Gaussian beam."""
     srv = Server(max_slots=8)
     hs = hist_spec(n_e=64, emax=0.05, n_theta=36, ek_min=0.0)
     reqs = []
-    works = _members(wl.FP64)[:3] + _members(wl.FP32)[:3]
-    steps = [40, 23, 31, 40, 23, 31]
+    on_nodes = _lp(precision=wl.FP64, seed=16)
+    on_nodes.incident.on_nodes = 1
+    gauss = wl.gauss_beam_2d(nx=160, ny=96, plasma=(50, 110, 20, 76), ppc=4,
+                             w0_lambda=2.0, cycles=3.0, a0=3.0, steps=30,
+                             cells_per_lambda=24)
+    gauss.precision = wl.FP32
+    works = (_members(wl.FP64)[:3] + _members(wl.FP32)[:3] +
+             [on_nodes, gauss])
+    steps = [40, 23, 31, 40, 23, 31, 29, 30]
     # two at once, then the rest while those run
     for k, (w, n) in enumerate(zip(works, steps)):
         reqs.append((srv.submit(w, nsteps=n, hist=hs), w, n))
