@@ -692,6 +692,9 @@ def main():
                     help="skip the 3D leg at the paper's 2 pi/32 resolution")
     ap.add_argument("--only-3d", action="store_true",
                     help="only the FP64 3D3V leg at 2 pi/16 (profiling runs)")
+    ap.add_argument("--only-serve", action="store_true",
+                    help="only the served sweep (--serve-rate, --serve-window, "
+                         "--serve-steps, --serve-slots; profiling runs)")
     ap.add_argument("--only-batch", action="store_true",
                     help="only the batched sweep (--batch-members, "
                          "--batch-steps; profiling runs)")
@@ -733,6 +736,11 @@ def main():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
+    if args.only_serve:
+        print(json.dumps({"served_sweep": served_sweep(
+            args.serve_rate, args.serve_window, args.serve_steps,
+            args.serve_slots)}), flush=True)
+        return
     if args.only_batch:
         from paper_2310_11393_amd import workloads as wl
         prec = wl.FP64 if args.batch_fp64 else wl.FP32
