@@ -81,6 +81,16 @@ struct Particles<float> {
 
 // Particle tiles: tx x ty cells (ty = 1 in 1D).  Cells are keyed tile-major:
 // key = tile * cells_per_tile + (iy mod ty) * tx + (ix mod tx).
+// Drift allowance (cells) of a single sim's tile window, per precision.
+#ifndef SFPIC_SLACK_F64
+#define SFPIC_SLACK_F64 3
+#endif
+constexpr int kSingleSlackF64 = SFPIC_SLACK_F64;
+#ifndef SFPIC_SLACK_F32
+#define SFPIC_SLACK_F32 1
+#endif
+constexpr int kSingleSlackF32 = SFPIC_SLACK_F32;
+
 struct TileGeom {
   int tx, ty;
   int ntx, nty, ntiles;
@@ -265,6 +275,27 @@ __host__ __device__ __forceinline__ cx<T> cpowi(cx<T> b, int n) {
   return r;
 }
 
+// b1^n and b2^n (n >= 1) in one binary exponentiation: n is the same in
+// every lane, and with both powers in one loop each uniform branch guards
+// eight products, which the compiler keeps as a branch instead of computing
+// both sides in every iteration and selecting.
+template <typename T>
+__host__ __device__ __forceinline__ void cpowi2(cx<T> b1, cx<T> b2, int n,
+                                                cx<T> &r1, cx<T> &r2) {
+  r1 = b1;
+  r2 = b2;
+  for (n -= 1; n > 0; n >>= 1) {
+    if (n & 1) {
+      r1 = r1 * b1;
+      r2 = r2 * b2;
+    }
+    if (n > 1) {
+      b1 = b1 * b1;
+      b2 = b2 * b2;
+    }
+  }
+}
+
 // Square root with a branch that is continuous away from the negative real
 // axis; the April fields are even in this root, so any branch is valid.
 // With h = (|z| + |Re z|)/2 > 0 the root's larger part is sqrt(h) = h /
@@ -316,7 +347,8 @@ __host__ __device__ inline Blocks<T> april_blocks_rest(const IncParams &P,
                                                        cx<T> u, cx<T> wp,
                                                        cx<T> wm) {
   cx<T> rp = cinv(wp), rm = cinv(wm);
-  cx<T> pp0 = cpowi(rp, P.s_int + 1), pm0 = cpowi(rm, P.s_int + 1);
+  cx<T> pp0, pm0;
+  cpowi2(rp, rm, P.s_int + 1, pp0, pm0);
   cx<T> pp1 = pp0 * rp, pm1 = pm0 * rm;
   cx<T> pp2 = pp1 * rp, pm2 = pm1 * rm;
   cx<T> c0 = mk((T)P.cr[0], (T)P.ci[0]), c1 = mk((T)P.cr[1], (T)P.ci[1]),

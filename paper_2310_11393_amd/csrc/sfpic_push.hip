@@ -288,16 +288,17 @@ __device__ __forceinline__ void incident_r(const IncParams &inc, int dims,
 // are the order-2 shapes at x^n and x^{n+1} on the nodes ipx - 2 + ox ..
 // ipx + 1 + ox (ipy - 2 + oy .. ipy + 1 + oy), which hold every node either
 // shape touches (ox = 1 for a move up the axis, see shapes4); add(c, a, b,
-// v) accumulates v into component c at node offset (a, b) from node ipx - 2
-// (ipy - 2).  Only nodes lo .. hi (frame indices), where S0 or S1 is
-// non-zero, are touched, and along x (y) only the entries of the running sum
-// that can be non-zero.
+// v) accumulates v into component c at frame node (a, b), i.e. node ipx - 2
+// + ox + a (ipy - 2 + oy + b): the caller binds `add` to the frame's first
+// node, so each entry's place is that base plus a constant.  Only nodes lo
+// .. hi (frame indices), where S0 or S1 is non-zero, are touched, and along
+// x (y) only the entries of the running sum that can be non-zero.
 // ---------------------------------------------------------------------------
 template <typename R, int DIMS, typename Add>
 __device__ __forceinline__ void esirkepov(const R S0x[4], const R S1x[4],
                                           const R S0y[4], const R S1y[4],
-                                          int ox, int oy, int lox, int hix,
-                                          int loy, int hiy, R cxq, R cyq,
+                                          int lox, int hix, int loy, int hiy,
+                                          R cxq, R cyq,
                                           R qvy, R qvz, Add add) {
   // All loops run over the full frame with compile-time indices (the shape
   // arrays stay in registers); nodes outside [lo, hi] are skipped per lane.
@@ -306,14 +307,14 @@ __device__ __forceinline__ void esirkepov(const R S0x[4], const R S1x[4],
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       acc += cxq * (S1x[a] - S0x[a]);
-      if (a >= lox && a < hix) add(0, a + ox, 0, acc);
+      if (a >= lox && a < hix) add(0, a, 0, acc);
     }
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
       if (a < lox || a > hix) continue;
       const R wv = R(0.5) * (S0x[a] + S1x[a]);
-      add(1, a + ox, 0, qvy * wv);
-      add(2, a + ox, 0, qvz * wv);
+      add(1, a, 0, qvy * wv);
+      add(2, a, 0, qvz * wv);
     }
     return;
   }
@@ -338,7 +339,7 @@ __device__ __forceinline__ void esirkepov(const R S0x[4], const R S1x[4],
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       acc += DSx[a] * cAy[b];
-      if (a >= lox && a < hix) add(0, a + ox, b + oy, acc);
+      if (a >= lox && a < hix) add(0, a, b, acc);
     }
   }
 #pragma unroll
@@ -349,7 +350,7 @@ __device__ __forceinline__ void esirkepov(const R S0x[4], const R S1x[4],
 #pragma unroll
     for (int b = 0; b < 3; ++b) {
       acc += DSy[b] * cAx;
-      if (b >= loy && b < hiy) add(1, a + ox, b + oy, acc);
+      if (b >= loy && b < hiy) add(1, a, b, acc);
     }
   }
 #pragma unroll
@@ -358,7 +359,7 @@ __device__ __forceinline__ void esirkepov(const R S0x[4], const R S1x[4],
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
       if (a < lox || a > hix) continue;
-      add(2, a + ox, b + oy, S0x[a] * qAy[b] + DSx[a] * qBy[b]);
+      add(2, a, b, S0x[a] * qAy[b] + DSx[a] * qBy[b]);
     }
   }
 }
@@ -436,12 +437,14 @@ __device__ __forceinline__ bool inc_at_particle(int src, const IncParams &inc) {
 }
 
 // One particle: gather (via `gather`), incident field, Boris, advance,
-// deposit (via `add`), removal test.  Position is (cell, offset) per axis.
-template <typename R, int DIMS, int INC, typename Gather, typename Add>
+// deposit (through frame(ox, oy), which returns the add of esirkepov bound
+// to the frame's first node ipx - 2 + ox, ipy - 2 + oy), removal test.
+// Position is (cell, offset) per axis.
+template <typename R, int DIMS, int INC, typename Gather, typename Frame>
 __device__ __forceinline__ bool push_particle(int &ix, int &iy, R &fx, R &fy,
                                               R u[3], const PushParams &pp,
                                               const IncParams &inc,
-                                              Gather gather, Add add) {
+                                              Gather gather, Frame frame) {
   // The incident field is evaluated before the weights and the gather, so
   // its temporaries are dead by the time those are live (fewer registers at
   // the peak); the sum is the same, scattered plus incident.
@@ -474,9 +477,9 @@ __device__ __forceinline__ bool push_particle(int &ix, int &iy, R &fx, R &fy,
   shapes4(wxp, dx0, d1x, S0x, S1x, ox, lox, hix);
   if (DIMS == 2) shapes4(wyp, dy0, d1y, S0y, S1y, oy, loy, hiy);
   const R qvy = (R)pp.qw * u[1] * gi, qvz = (R)pp.qw * u[2] * gi;
-  esirkepov<R, DIMS>(S0x, S1x, S0y, S1y, ox, oy, lox, hix, loy, hiy,
+  esirkepov<R, DIMS>(S0x, S1x, S0y, S1y, lox, hix, loy, hiy,
                      (R)(-pp.qw * pp.dx / pp.dt), (R)(-pp.qw * pp.dy / pp.dt),
-                     qvy, qvz, add);
+                     qvy, qvz, frame(ox, oy));
   // A move below one cell keeps |d1| < 2; a non-finite momentum (a
   // simulation gone numerically bad) makes d1 NaN, and such a particle is
   // removed here instead of being given a cell from a NaN.
@@ -503,7 +506,11 @@ __device__ __forceinline__ bool push_particle(int &ix, int &iy, R &fx, R &fy,
 // One workgroup pushes the particles pbeg .. pend - 1 of one tile (all of
 // them, or one work item of a dense tile); smem holds the field and current
 // windows and, on the staged path, the particle chunk (push_lds_bytes).
-template <typename R, int DIMS, int INC, int PER = kChunkPer>
+// GX > 0 fixes the tile at GX x GY cells with slack GS at compile time (it
+// must equal tg): the window strides are then constants, and the offsets of
+// a particle's gather and deposit taps fold into the LDS instructions.
+template <typename R, int DIMS, int INC, int PER = kChunkPer, int GX = 0,
+          int GY = 0, int GS = 0>
 __device__ __forceinline__ void push_tile(const Fields<R> &f,
                                           const Particles<R> &p,
                                           const TileGeom &tg,
@@ -512,13 +519,14 @@ __device__ __forceinline__ void push_tile(const Fields<R> &f,
                                           uint32_t *strag, uint32_t *n_strag,
                                           int tile, uint32_t pbeg,
                                           uint32_t pend, double *smem) {
-  const int kSlack = tg.slack, kWinExtra = win_extra(tg.slack);
-  const int kWinLo = tg.slack + 2;
+  const int TX = GX > 0 ? GX : tg.tx, TY = GX > 0 ? GY : tg.ty;
+  const int kSlack = GX > 0 ? GS : tg.slack, kWinExtra = win_extra(kSlack);
+  const int kWinLo = kSlack + 2;
   if (pbeg >= pend) return;
-  const int cx0 = (tile % tg.ntx) * tg.tx;
-  const int cy0 = (DIMS == 2) ? (tile / tg.ntx) * tg.ty : 0;
-  const int WX = tg.tx + kWinExtra;
-  const int WY = (DIMS == 2) ? tg.ty + kWinExtra : 1;
+  const int cx0 = (tile % tg.ntx) * TX;
+  const int cy0 = (DIMS == 2) ? (tile / tg.ntx) * TY : 0;
+  const int WX = TX + kWinExtra;
+  const int WY = (DIMS == 2) ? TY + kWinExtra : 1;
   const int WN = WX * WY;
   // jx jy jz windows accumulate in FP64 in both precisions: on gfx950 an
   // FP64 LDS atomic add is several times faster than an FP32 one (the FP32
@@ -609,9 +617,9 @@ __device__ __forceinline__ void push_tile(const Fields<R> &f,
   // otherwise it is pushed and `alive` tells whether it stays in the box.
   auto push_one = [&](int &ix, int &iy, R &fx, R &fy, R u[3], uint32_t g,
                       bool &alive) -> bool {
-    if (!(ix >= cx0 - kSlack && ix < cx0 + tg.tx + kSlack &&
+    if (!(ix >= cx0 - kSlack && ix < cx0 + TX + kSlack &&
           (DIMS == 1 ||
-           (iy >= cy0 - kSlack && iy < cy0 + tg.ty + kSlack)))) {
+           (iy >= cy0 - kSlack && iy < cy0 + TY + kSlack)))) {
       strag[atomicAdd(n_strag, 1u)] = g;
       return false;
     }
@@ -621,8 +629,11 @@ __device__ __forceinline__ void push_tile(const Fields<R> &f,
     const int bx = ipx0 - cx0 + kWinLo - 2;
     const int by = (DIMS == 2) ? ipy0 - cy0 + kWinLo - 2 : 0;
     alive = push_particle<R, DIMS, INC>(
-        ix, iy, fx, fy, u, pp, inc, gather, [&](int c, int a, int b, R v) {
-          atomicAdd(&sj[c * WN + (by + b) * WX + bx + a], (Acc)v);
+        ix, iy, fx, fy, u, pp, inc, gather, [&](int ox, int oy) {
+          Acc *b0 = sj + (by + oy) * WX + bx + ox;
+          return [=](int c, int a, int b, R v) {
+            atomicAdd(&b0[c * WN + b * WX + a], (Acc)v);
+          };
         });
     return true;
   };
@@ -768,7 +779,7 @@ constexpr int push_min_blocks() {
   return sizeof(R) == 8 ? 3 : SFPIC_PUSH_MIN_BLOCKS;
 }
 
-template <typename R, int DIMS, int INC>
+template <typename R, int DIMS, int INC, int GX = 0, int GY = 0, int GS = 0>
 __global__ void __launch_bounds__(256, push_min_blocks<R>())
 push_tiled(Fields<R> f, Particles<R> p, const uint32_t *__restrict__ start,
            const uint32_t *__restrict__ items,
@@ -786,8 +797,9 @@ push_tiled(Fields<R> f, Particles<R> p, const uint32_t *__restrict__ start,
   const int tile = (int)items[2 * (size_t)it];
   const uint32_t pbeg = items[2 * (size_t)it + 1];
   const uint32_t tend = start[(size_t)(tile + 1) * tg.cells_per_tile];
-  push_tile<R, DIMS, INC>(f, p, tg, pp, inc, strag, n_strag, tile, pbeg,
-                          tend - pbeg > kmax ? pbeg + kmax : tend, smem);
+  push_tile<R, DIMS, INC, kChunkPer, GX, GY, GS>(
+      f, p, tg, pp, inc, strag, n_strag, tile, pbeg,
+      tend - pbeg > kmax ? pbeg + kmax : tend, smem);
 }
 
 // Push of one particle listed by the tiled kernel (drifted more than slack
@@ -826,9 +838,12 @@ __device__ __forceinline__ void push_straggler(const Fields<R> &f,
   const int bx = ipx0 - 2 + kGuard;
   const int by = (DIMS == 2) ? ipy0 - 2 + kGuard : 0;
   const bool alive = push_particle<R, DIMS, kIncAny>(
-      ix, iy, fx, fy, u, pp, inc, gather, [&](int c, int a, int b, R v) {
-        R *jp = c == 0 ? f.jx : (c == 1 ? f.jy : f.jz);
-        unsafeAtomicAdd(&jp[(size_t)(by + b) * P + bx + a], v);
+      ix, iy, fx, fy, u, pp, inc, gather, [&](int ox, int oy) {
+        const size_t b0 = (size_t)(by + oy) * P + bx + ox;
+        return [=, &f](int c, int a, int b, R v) {
+          R *jp = c == 0 ? f.jx : (c == 1 ? f.jy : f.jz);
+          unsafeAtomicAdd(&jp[b0 + (size_t)b * P + a], v);
+        };
       });
   PT<R>::store_global(p, ip, DIMS, alive, ix, iy, fx, fy, u);
 }
@@ -886,10 +901,23 @@ hipError_t launch_push_tiled(const Fields<R> &f, const Particles<R> &p,
   const unsigned nb = (unsigned)((cap + 7) & ~(size_t)7);
   const size_t lds = push_dyn_lds_bytes<R>(tg, dims);
   fill_u32<<<1, 64, 0, st>>>(n_strag, 0u, 1);
+  // the default tile of a 2D run (16 x 16, the precision's default slack)
+  // has its geometry compiled in for the plane-wave models
+  constexpr int kFixSlack = sizeof(R) == 8 ? kSingleSlackF64 : kSingleSlackF32;
+  const bool fixed = dims == 2 && tg.tx == 16 && tg.ty == 16 &&
+                     tg.slack == kFixSlack;
   auto go = [&](auto dims_c, auto inc_c) {
-    push_tiled<R, decltype(dims_c)::value, decltype(inc_c)::value>
-        <<<nb, 256, lds, st>>>(f, p, start, items, n_items, kmax, tg, pp, inc,
-                               strag, n_strag);
+    constexpr int D = decltype(dims_c)::value, I = decltype(inc_c)::value;
+    if constexpr (D == 2 && (I == kIncLP || I == kIncRP)) {
+      if (fixed) {
+        push_tiled<R, D, I, 16, 16, kFixSlack><<<nb, 256, lds, st>>>(
+            f, p, start, items, n_items, kmax, tg, pp, inc, strag, n_strag);
+        return;
+      }
+    }
+    push_tiled<R, D, I><<<nb, 256, lds, st>>>(f, p, start, items, n_items,
+                                              kmax, tg, pp, inc, strag,
+                                              n_strag);
   };
   using D1 = std::integral_constant<int, 1>;
   using D2 = std::integral_constant<int, 2>;

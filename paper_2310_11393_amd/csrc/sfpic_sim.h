@@ -109,15 +109,6 @@ inline Particles<float> &parts_alt<float>(SpeciesState &st) {
 #define SFPIC_ITEM_PARTICLES 8192
 #endif
 constexpr uint32_t kItemParticles = SFPIC_ITEM_PARTICLES;
-// Drift allowance (cells) of an FP64 single sim's tile window.
-#ifndef SFPIC_SLACK_F64
-#define SFPIC_SLACK_F64 3
-#endif
-constexpr int kSingleSlackF64 = SFPIC_SLACK_F64;
-#ifndef SFPIC_SLACK_F32
-#define SFPIC_SLACK_F32 1
-#endif
-constexpr int kSingleSlackF32 = SFPIC_SLACK_F32;
 
 struct sfpic_sim {
   using SpeciesState = sfpic::SpeciesState;
