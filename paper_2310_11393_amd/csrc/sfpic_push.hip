@@ -62,9 +62,14 @@ __host__ __device__ inline bool fixed_geometry(const TileGeom &tg, int dims) {
 
 // LDS chunk of the staged particle path (the FP32 form, see PT): 256 PER
 // particles per chunk, PER per thread; lane l of wave w takes chunk slots
-// l*4PER + w*PER + j, so the 64 lanes of a wave sit in different cells of
-// the cell-sorted chunk, and one pad word every 4 PER spreads them over the
-// banks.  A single simulation's push takes 4 per thread; the batched push 2,
+// m(l)*4PER + w*PER + j with m(l) = 4 (l mod 16) + l / 16, so the lanes of a
+// wave sit in different cells of the cell-sorted chunk, and so do (as far as
+// the chunk allows) the 16 lanes whose LDS accesses the hardware serves
+// together: their slots are 16 PER apart, and lanes that share a cell at a
+// high particle density fall in different sixteens (against m(l) = l: single
+// 4096^2 RP push 3.82 -> 3.76 ms, 64-member sweep 18.97 -> 20.42 G pushes/s;
+// m(l) = 2 (l mod 32) + l / 32 and 8 (l mod 8) + l / 8 were slower).  One
+// pad word every 4 PER spreads the lanes over the banks.  A single simulation's push takes 4 per thread; the batched push 2,
 // whose smaller chunk lets four of its workgroups share a CU (16.3 -> 17.1 G
 // pushes/s on a 64-member FP32 sweep; the single push is 7% slower with it).
 constexpr int kChunkPer = 4, kBatchChunkPer = 2;
@@ -78,6 +83,10 @@ struct Chunk {
 template <int PER>
 __device__ __forceinline__ int chunk_slot(int k) {
   return k + k / Chunk<PER>::stride;
+}
+// Position m(l) of lane l among the 64 lane columns of a chunk.
+__device__ __forceinline__ int chunk_lane_pos(int lane) {
+  return (lane & 15) * 4 + (lane >> 4);
 }
 
 __global__ void fill_u32(uint32_t *a, uint32_t v, size_t n) {
@@ -695,7 +704,7 @@ __device__ __forceinline__ void push_tile(const Fields<R> &f,
       }
 #pragma unroll 1
       for (int j = 0; j < CK::per; ++j) {
-        const int idx = lane * CK::stride + wv * CK::per + j;
+        const int idx = chunk_lane_pos(lane) * CK::stride + wv * CK::per + j;
         if (idx >= cn) continue;
         const int sl = chunk_slot<PER>(idx);
         int ix, iy;
@@ -1080,10 +1089,15 @@ __device__ __forceinline__ void move_particle(const Particles<float> &src,
 // Slot of the particle of rank rb within a block of m <= 1024 slots: the
 // block is a row-major array of 64 columns (one per lane of the push's
 // waves) whose ranks run down the columns, column c holding q + 1 ranks if
-// c < r and q otherwise (m = 64 q + r).  A wave that pushes one row then
-// has its lanes q or q + 1 ranks apart in cell order, in different cells,
-// so their LDS current atomics rarely meet, while its loads and stores of
-// the row stay contiguous.
+// c < r and q otherwise (m = 64 q + r).  In the full rows (row < q) the
+// run of ranks c sits in column c / 4 + 16 (c mod 4), so that lane l of the
+// wave that pushes the row takes run 4 (l mod 16) + l / 16, as the staged
+// path's lanes do (chunk_lane_pos); the last, partial row keeps column c.
+// The lanes of a wave are then in different cells and the 16 lanes served
+// together 4 runs apart, so their LDS current atomics rarely meet, while
+// the wave's loads and stores of its row stay contiguous (against plain
+// column order: 4096^2 RP FP64 push 4.57 -> 4.38 ms, sort 1.01 -> 0.75 ms
+// per step).
 __device__ __forceinline__ uint32_t block_slot(uint32_t rb, uint32_t m) {
   const uint32_t q = m >> 6, r = m & 63u;
   uint32_t c, row;
@@ -1095,7 +1109,7 @@ __device__ __forceinline__ uint32_t block_slot(uint32_t rb, uint32_t m) {
     c = r + x / q;
     row = x - (c - r) * q;
   }
-  return row * 64 + c;
+  return row * 64 + (row < q ? (c >> 2) + 16 * (c & 3) : c);
 }
 
 // Scatter of slot i to its sorted place: tile-major, cell order within the
