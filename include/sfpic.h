@@ -173,9 +173,13 @@ typedef struct {
   sfpic_free_fn free;    /* NULL = hipFree                                 */
   void *alloc_ctx;
   int32_t tile_x, tile_y; /* particle tile in cells; 0 = library default   */
-  int32_t sort_every;     /* steps between tile sorts; 0 = default (single
-                             sims 8 in FP64 and 4 in the FP32 form;
-                             batches and servers: autotuned or 4)        */
+  int32_t sort_every;     /* steps between tile sorts; 0 = default: single
+                             sims adaptive, sorting 4 (FP32 form) or 8
+                             (FP64) to 16 steps after the last sort, as
+                             soon as the push two steps earlier listed
+                             more than 2^-10 of a species' particles as
+                             stragglers; batches and servers autotuned or
+                             4                                            */
   int32_t device;         /* HIP device ordinal                            */
   int32_t flags;          /* SFPIC_RT_* (batches and servers)              */
   int32_t item_particles; /* a tile holding more particles is pushed by

@@ -370,6 +370,7 @@ int setup_tiles(sfpic_sim *s) {
   // every 8 leaves a fifth of the step to the straggler push (measured on
   // the 4096^2 RP run at step 1500: 8.85 ms per step every 8, 7.59 every 4)
   s->sort_every = s->precision == SFPIC_FP32 ? 4 : 8;
+  s->sort_adaptive = s->rt.sort_every <= 0;
   if (s->rt.sort_every > 0) s->sort_every = s->rt.sort_every;
   if (s->rt.item_particles != 0) {
     if (s->rt.item_particles < 64)
@@ -636,17 +637,64 @@ hipError_t timed(sfpic_sim *s, int cls, F &&launch) {
   return r;
 }
 
+// Straggler fraction above which the adaptive cadence sorts (2^-10).  On
+// the 4096^2 RP run, against the fixed cadence (FP32 form every 4 steps,
+// FP64 every 8): first 200 steps 26.8 -> 27.9 and 22.1 -> 22.8 G pushes/s,
+// the run to step 3000 20.5 -> 20.4 and 18.6 -> 18.5; 2^-13 sorted almost
+// as often as the fixed cadence, 2^-8 and 2^-6 lost on the long run.
+constexpr double kStragSortFrac = 1.0 / 1024.0;
+
+// Whether a sort is due under the adaptive cadence (since_sort is at least
+// sort_every and below sort_max): the push of two steps ago (its counts
+// copied back to the pinned ring) listed more than kStragSortFrac of some
+// species' slots as stragglers, or its record is missing.  Waiting on that
+// step's event leaves the stream two steps of queued work.
+int adaptive_sort_due(sfpic_sim *s, bool &due) {
+  const int64_t want = s->step - 2;
+  const int slot = (int)(want & (sfpic_sim::kStragRing - 1));
+  due = true;
+  if (want < 0 || s->strag_step[slot] != want) return SFPIC_OK;
+  HIP_TRY(hipEventSynchronize(s->strag_ev[slot]));
+  const size_t ns = s->sp.size();
+  due = false;
+  for (size_t i = 0; i < ns; ++i)
+    if ((double)s->strag_host[(size_t)slot * ns + i] >
+        kStragSortFrac * (double)s->sp[i].n)
+      due = true;
+  return SFPIC_OK;
+}
+
+int adaptive_sort_init(sfpic_sim *s) {
+  if (s->strag_host) return SFPIC_OK;
+  const size_t bytes = sfpic_sim::kStragRing * s->sp.size() * 4;
+  HIP_TRY(hipHostMalloc((void **)&s->strag_host, bytes > 0 ? bytes : 4,
+                        hipHostMallocDefault));
+  for (auto &e : s->strag_ev)
+    HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  for (auto &t : s->strag_step) t = -1;
+  return SFPIC_OK;
+}
+
 template <typename R>
 int step_impl(sfpic_sim *s, int64_t nsteps) {
   const sfpic_grid &g = s->grid;
   Fields<R> &f = s->fields<R>();
   if (nsteps > 0) SF_TRY(refresh_items(s));
+  if (nsteps > 0 && s->sort_adaptive) SF_TRY(adaptive_sort_init(s));
   for (int64_t k = 0; k < nsteps; ++k) {
-    if (s->since_sort >= s->sort_every) {
+    bool sort_now = s->since_sort >= s->sort_every;
+    if (sort_now && s->sort_adaptive && s->since_sort < s->sort_max)
+      SF_TRY(adaptive_sort_due(s, sort_now));
+    if (sort_now) {
       HIP_TRY(timed(s, 3, [&] {
         return sort_all(s) == SFPIC_OK ? hipSuccess : hipErrorUnknown;
       }));
     }
+    // this step's straggler counts are read two steps later when that
+    // step's decision is adaptive
+    const bool record =
+        s->sort_adaptive && s->since_sort + 2 >= s->sort_every;
+    const int slot = (int)(s->step & (sfpic_sim::kStragRing - 1));
     HIP_TRY(timed(s, 0, [&] {
       return launch_faraday<R>(f, g.dims, g.dt, g.dx, g.dy, s->stream);
     }));
@@ -678,6 +726,14 @@ int step_impl(sfpic_sim *s, int64_t nsteps) {
         return launch_push_stragglers<R>(f, parts<R>(st), g.dims, pp, s->inc,
                                          s->strag, s->n_strag, s->stream);
       }));
+      if (record)
+        HIP_TRY(hipMemcpyAsync(
+            s->strag_host + (size_t)slot * s->sp.size() + (&st - &s->sp[0]),
+            s->n_strag, 4, hipMemcpyDeviceToHost, s->stream));
+    }
+    if (record) {
+      HIP_TRY(hipEventRecord(s->strag_ev[slot], s->stream));
+      s->strag_step[slot] = s->step;
     }
     HIP_TRY(timed(s, 2, [&] {
       return launch_ampere<R>(f, g.dims, g.dt, g.dx, g.dy, s->stream);

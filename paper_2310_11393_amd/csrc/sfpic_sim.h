@@ -133,6 +133,17 @@ struct sfpic_sim {
   SortScratch ss{};
   int sort_every = 8;
   int64_t since_sort = 0;
+  // Adaptive cadence (the default runtime): from sort_every steps after a
+  // sort up to sort_max, the next sort waits while the push two steps
+  // earlier listed no more than a fraction kStragSortFrac of any species'
+  // slots as stragglers.  The counts come back through pinned host memory,
+  // one ring slot per step, with an event each.
+  bool sort_adaptive = false;
+  int sort_max = 16;
+  static constexpr int kStragRing = 4;
+  uint32_t *strag_host = nullptr;  // kStragRing x species counts (pinned)
+  hipEvent_t strag_ev[kStragRing] = {};
+  int64_t strag_step[kStragRing] = {-1, -1, -1, -1};
   uint32_t item_max = kItemParticles;  // particles per push work item
   uint32_t *strag = nullptr, *n_strag = nullptr;  // straggler list
   double *rho0 = nullptr, *rho = nullptr, *acc = nullptr;
@@ -167,6 +178,10 @@ struct sfpic_sim {
     }
   }
   void destroy_events() {
+    for (auto &e : strag_ev)
+      if (e) (void)hipEventDestroy(e);
+    if (strag_host) (void)hipHostFree(strag_host);
+    strag_host = nullptr;
     recycle_events();
     for (auto &e : ev_free) {
       (void)hipEventDestroy(e.first);

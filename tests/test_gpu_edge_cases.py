@@ -10,6 +10,9 @@ MI355X):
     deposition that Sec. 2 names) step by step on the device;
   * the Gauss-law reduction against a known injected divergence, including
     nodes in the last partial block, and a NaN that must show as +inf;
+  * the default (adaptive) sort cadence of a single simulation: the longest
+    interval for a cold plasma that makes no stragglers, the shortest for a
+    hot one, whose run still matches the oracle;
   * a sweep member that goes non-finite fails alone with SFPIC_E_NUMERIC;
   * the per-handle error message of the C ABI.
 """
@@ -307,6 +310,72 @@ def test_gauss_residual_equals_injected_divergence_3d():
     d = sim.diagnostics()
     assert d["gauss_residual"] == math.inf
     sim.close()
+
+
+# ---------------------------------------------------------------------------
+# Adaptive sort cadence (single simulations, default runtime)
+# ---------------------------------------------------------------------------
+def _cadence_case(temperature_ev):
+    return wl.april_2d(nx=136, ny=72, plasma=(40, 100, 0, 72), ppc=4,
+                       a0=0.1, temperature_ev=temperature_ev, steps=34,
+                       seed=23)
+
+
+def _count_sorts(g, steps):
+    g.profile(True)
+    g.step(steps)
+    g.sync()
+    n = g.profile_read()["sort"][0]
+    g.profile(False)
+    return n
+
+
+@pytest.mark.parametrize("prec", [wl.FP64, wl.FP32])
+def test_adaptive_sort_cadence(prec):
+    """With the default runtime a single simulation sorts 4 (FP32 form) or 8
+    (FP64) to 16 steps after its last sort, once the push two steps earlier
+    listed more than 2^-10 of the particles as stragglers.  A 1 eV plasma
+    drifts far less than a cell in 34 steps: sorts at steps 16 and 32 only.
+    A 2 MeV plasma (momenta of 2 m c per axis, up to ~0.65 cells per step)
+    makes stragglers well within the shortest interval: a sort every
+    4 / 8 steps, as a fixed cadence of that length gives.  The hot run, whose
+    particles go through the straggler path between sorts, matches the
+    oracle (fields and particles: FP64 1e-12, FP32 form 1e-4)."""
+    steps = 34
+    shortest = 4 if prec == wl.FP32 else 8
+    cold, hot = _cadence_case(1.0), _cadence_case(2e6)
+    g = make_gpu(cold, precision=prec)
+    n_cold = _count_sorts(g, steps)
+    g.close()
+    g = make_gpu(hot, precision=prec, sort_every=shortest)
+    n_fixed = _count_sorts(g, steps)
+    g.close()
+    g = make_gpu(hot, precision=prec)
+    n_hot = _count_sorts(g, steps)
+    _note(f"[cadence] prec {prec}: cold {n_cold} sorts, hot {n_hot}, fixed "
+          f"every {shortest}: {n_fixed}")
+    assert n_cold == steps // 16
+    assert n_fixed == steps // shortest
+    assert n_hot >= n_fixed - 1
+    o = make_oracle(hot)
+    o.step(steps)
+    tol = 1e-12 if prec == wl.FP64 else 1e-4
+    rel, den = field_rel_l2(g, o)
+    dpos, du, umax = particle_errors(g, o)
+    n_gpu = g.diagnostics()["n_alive"]
+    g.close()
+    _note(f"[cadence] prec {prec}: hot run fields {rel:.2e}, particles "
+          f"{dpos:.2e} / {du:.2e} (|u| max {umax:.2f})")
+    assert den > 0 and rel <= tol, rel
+    if prec == wl.FP64:
+        assert dpos <= 1e-12 and du <= 1e-12 * max(1.0, umax), (dpos, du)
+    else:
+        # momenta to 1e-4 of max(1, |u|max), positions to that times the
+        # run's duration (the time integral of the velocity)
+        t_run = steps * hot.grid.dt
+        assert du <= 1e-4 * max(1.0, umax), du
+        assert dpos <= 1e-4 * max(1.0, umax) * t_run, (dpos, t_run)
+    assert n_gpu == o.diagnostics()["n_alive"]
 
 
 # ---------------------------------------------------------------------------
