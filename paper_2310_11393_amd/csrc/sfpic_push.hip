@@ -69,10 +69,12 @@ __host__ __device__ inline bool fixed_geometry(const TileGeom &tg, int dims) {
 // high particle density fall in different sixteens (against m(l) = l: single
 // 4096^2 RP push 3.82 -> 3.76 ms, 64-member sweep 18.97 -> 20.42 G pushes/s;
 // m(l) = 2 (l mod 32) + l / 32 and 8 (l mod 8) + l / 8 were slower).  One
-// pad word every 4 PER spreads the lanes over the banks.  A single simulation's push takes 4 per thread; the batched push 2,
-// whose smaller chunk lets four of its workgroups share a CU (16.3 -> 17.1 G
-// pushes/s on a 64-member FP32 sweep; the single push is 7% slower with it).
-constexpr int kChunkPer = 4, kBatchChunkPer = 2;
+// pad word every 4 PER spreads the lanes over the banks.  Both the single
+// and the batched push take 2 per thread: the batch's smaller chunk lets
+// four of its workgroups share a CU (16.3 -> 17.1 G pushes/s on a 64-member
+// FP32 sweep), and with the lane map above the single push is faster with it
+// too (3.76 -> 3.65 ms; with m(l) = l it was 7% slower).
+constexpr int kChunkPer = 2, kBatchChunkPer = 2;
 template <int PER>
 struct Chunk {
   static constexpr int per = PER;
@@ -537,7 +539,7 @@ __device__ __forceinline__ bool push_particle(int &ix, int &iy, R &fx, R &fy,
 // must equal tg): the window strides are then constants, and the offsets of
 // a particle's gather and deposit taps fold into the LDS instructions.
 template <typename R, int DIMS, int INC, int PER = kChunkPer, int GX = 0,
-          int GY = 0, int GS = 0>
+          int GY = 0, int GS = 0, bool NEXT = false>
 __device__ __forceinline__ void push_tile(const Fields<R> &f,
                                           const Particles<R> &p,
                                           const TileGeom &tg,
@@ -566,11 +568,11 @@ __device__ __forceinline__ void push_tile(const Fields<R> &f,
   // Staged path: the words of the first chunk are loaded before the field
   // window, so that their HBM latency overlaps the window loads; a single
   // simulation's push also loads the next chunk while the current one is
-  // pushed (kAheadNext; the batched push keeps those registers for its
-  // fourth workgroup per CU and loads later chunks when it gets there).
+  // pushed (NEXT; the batched push keeps those registers for its fourth
+  // workgroup per CU and loads later chunks when it gets there).
   // Thread t holds slots t + 256 j of the chunk (blockDim.x = 256).
   constexpr bool kAhead = PT<R>::kStaged;
-  constexpr bool kAheadNext = kAhead && PER == kChunkPer;
+  constexpr bool kAheadNext = kAhead && NEXT;
   constexpr int kAheadWords = 6;  // PT<float>::kWords
   using CK = Chunk<PER>;
   uint32_t *sp = (uint32_t *)(sf + 6 * WN);  // particle chunk after windows
@@ -824,7 +826,7 @@ push_tiled(Fields<R> f, Particles<R> p, const uint32_t *__restrict__ start,
   const int tile = (int)items[2 * (size_t)it];
   const uint32_t pbeg = items[2 * (size_t)it + 1];
   const uint32_t tend = start[(size_t)(tile + 1) * tg.cells_per_tile];
-  push_tile<R, DIMS, INC, kChunkPer, GX, GY, GS>(
+  push_tile<R, DIMS, INC, kChunkPer, GX, GY, GS, true>(
       f, p, tg, pp, inc, strag, n_strag, tile, pbeg,
       tend - pbeg > kmax ? pbeg + kmax : tend, smem);
 }
