@@ -2,6 +2,8 @@
 // Boris rotation, Philox4x32-10.
 #pragma once
 
+#include <type_traits>
+
 #include "sfpic_common.h"
 
 namespace sfpic {
@@ -58,6 +60,32 @@ __device__ __forceinline__ R gather_plane(const R *__restrict__ a, int P,
     v += wy[b] * (wx[0] * row[0] + wx[1] * row[1] + wx[2] * row[2]);
   }
   return v;
+}
+
+// gather_plane of two interleaved planes (pairs a[2n], a[2n + 1] at node n)
+// that share their taps: s0 from the first member, s1 from the second.
+template <typename R, int DIMS>
+__device__ __forceinline__ void gather_pair(const R *__restrict__ a, int P,
+                                            int bx, int by, const R wx[3],
+                                            const R wy[3], R &s0, R &s1) {
+  using V = typename std::conditional<sizeof(R) == 4, float2, double2>::type;
+  const V *p = (const V *)a;
+  if (DIMS == 1) {
+    const V t0 = p[bx], t1 = p[bx + 1], t2 = p[bx + 2];
+    s0 = wx[0] * t0.x + wx[1] * t1.x + wx[2] * t2.x;
+    s1 = wx[0] * t0.y + wx[1] * t1.y + wx[2] * t2.y;
+    return;
+  }
+  R v0 = R(0), v1 = R(0);
+#pragma unroll
+  for (int b = 0; b < 3; ++b) {
+    const V *row = p + (size_t)(by + b) * P + bx;
+    const V t0 = row[0], t1 = row[1], t2 = row[2];
+    v0 += wy[b] * (wx[0] * t0.x + wx[1] * t1.x + wx[2] * t2.x);
+    v1 += wy[b] * (wx[0] * t0.y + wx[1] * t1.y + wx[2] * t2.y);
+  }
+  s0 = v0;
+  s1 = v1;
 }
 
 // Boris rotation (Boris 1970) of u = gamma v for charge-to-mass ratio qm.

@@ -598,23 +598,38 @@ __device__ __forceinline__ void push_tile(const Fields<R> &f,
   };
   fetch_chunk(pbeg);
 
-  // stage E^n and Bbar^n on the node window; array index = cx0 + local
+  // stage E^n and Bbar^n on the node window; array index = cx0 + local.
+  // The FP32 form interleaves the components that share their taps, Ex
+  // with Bbar_y and Ey with Bbar_x, so that one 8-byte LDS read serves both
+  // (planes: (Ex, By) pairs, (Ey, Bx) pairs, Ez, Bz); FP64 keeps six planes.
+  constexpr bool kPairs = sizeof(R) == 4;
   for (int k = threadIdx.x; k < WN; k += blockDim.x) {
     const int I = cx0 + k % WX - kSlack + 1;
     const int J = (DIMS == 2) ? cy0 + k / WX - kSlack + 1 : 0;
     const bool in = I >= 0 && I < f.nx_alloc && J >= 0 && J < f.ny_alloc;
     const size_t g = (size_t)J * P + I;
-    sf[k] = in ? f.ex[g] : R(0);
-    sf[WN + k] = in ? f.ey[g] : R(0);
-    sf[2 * WN + k] = in ? f.ez[g] : R(0);
-    sf[3 * WN + k] = in ? f.mx[g] : R(0);
-    sf[4 * WN + k] = in ? f.my[g] : R(0);
-    sf[5 * WN + k] = in ? f.mz[g] : R(0);
+    R ex = in ? f.ex[g] : R(0), ey = in ? f.ey[g] : R(0);
+    R mz = in ? f.mz[g] : R(0);
     if (!inc_at_particle(INC, inc) && in) {  // sampled incident field joins
-      sf[k] = f.ex[g] + f.iex[g];
-      sf[WN + k] = f.ey[g] + f.iey[g];
-      sf[5 * WN + k] = f.mz[g] + f.ibz[g];
+      ex = f.ex[g] + f.iex[g];
+      ey = f.ey[g] + f.iey[g];
+      mz = f.mz[g] + f.ibz[g];
     }
+    const R ez = in ? f.ez[g] : R(0), mx = in ? f.mx[g] : R(0),
+            my = in ? f.my[g] : R(0);
+    if constexpr (kPairs) {
+      sf[2 * k] = ex;
+      sf[2 * k + 1] = my;
+      sf[2 * WN + 2 * k] = ey;
+      sf[2 * WN + 2 * k + 1] = mx;
+    } else {
+      sf[k] = ex;
+      sf[WN + k] = ey;
+      sf[3 * WN + k] = mx;
+      sf[4 * WN + k] = my;
+    }
+    sf[(kPairs ? 4 : 2) * WN + k] = ez;
+    sf[5 * WN + k] = mz;
     sj[k] = Acc(0);
     sj[WN + k] = Acc(0);
     sj[2 * WN + k] = Acc(0);
@@ -630,13 +645,20 @@ __device__ __forceinline__ void push_tile(const Fields<R> &f,
     const int bxp = ipx - cx0 + kWinLo - 1, bxd = ix - cx0 + kWinLo - 1;
     const int byp = (DIMS == 2) ? ipy - cy0 + kWinLo - 1 : 0;
     const int byd = (DIMS == 2) ? iy - cy0 + kWinLo - 1 : 0;
-    E[0] = gather_plane<R, DIMS>(sf, WX, bxd, byp, wxd, wyp);
-    E[1] = gather_plane<R, DIMS>(sf + WN, WX, bxp, byd, wxp, wyd);
-    E[2] = gather_plane<R, DIMS>(sf + 2 * WN, WX, bxp, byp, wxp, wyp);
-    B[0] = (DIMS == 2)
-               ? gather_plane<R, DIMS>(sf + 3 * WN, WX, bxp, byd, wxp, wyd)
-               : R(0);
-    B[1] = gather_plane<R, DIMS>(sf + 4 * WN, WX, bxd, byp, wxd, wyp);
+    if constexpr (kPairs) {
+      gather_pair<R, DIMS>(sf, WX, bxd, byp, wxd, wyp, E[0], B[1]);
+      gather_pair<R, DIMS>(sf + 2 * WN, WX, bxp, byd, wxp, wyd, E[1], B[0]);
+      if (DIMS == 1) B[0] = R(0);
+      E[2] = gather_plane<R, DIMS>(sf + 4 * WN, WX, bxp, byp, wxp, wyp);
+    } else {
+      E[0] = gather_plane<R, DIMS>(sf, WX, bxd, byp, wxd, wyp);
+      E[1] = gather_plane<R, DIMS>(sf + WN, WX, bxp, byd, wxp, wyd);
+      E[2] = gather_plane<R, DIMS>(sf + 2 * WN, WX, bxp, byp, wxp, wyp);
+      B[0] = (DIMS == 2)
+                 ? gather_plane<R, DIMS>(sf + 3 * WN, WX, bxp, byd, wxp, wyd)
+                 : R(0);
+      B[1] = gather_plane<R, DIMS>(sf + 4 * WN, WX, bxd, byp, wxd, wyp);
+    }
     B[2] = gather_plane<R, DIMS>(sf + 5 * WN, WX, bxd, byd, wxd, wyd);
   };
 
