@@ -949,6 +949,7 @@ int sfpic_set_step_index(sfpic_sim *s, int64_t step) {
   SF_TRY(guarded(s));
   if (step < 0) return fail(SFPIC_E_INVAL, "step < 0");
   s->step = step;
+  for (auto &t : s->strag_step) t = -1;  // straggler records of the old count
   s->gprev_step = -1;
   return SFPIC_OK;
 }
@@ -1285,6 +1286,7 @@ int sfpic_set_state(sfpic_sim *s, const void *buf, size_t n) {
     HIP_TRY(hipMemcpy(st.n_valid, &nv, 4, hipMemcpyHostToDevice));
   }
   s->step = hdr[6];
+  for (auto &t : s->strag_step) t = -1;  // straggler records of the old run
   SF_TRY(sort_all(s));
   HIP_TRY(hipStreamSynchronize(s->stream));
   return SFPIC_OK;
