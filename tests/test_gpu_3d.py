@@ -2,16 +2,17 @@
 
 Same seeded inputs on both sides (workloads.plasma3d); after the stated
 steps the scattered fields agree to a relative L2 of 1e-12 (E and B stacked;
-J separately), every particle's removal agrees exactly, live positions to
-1e-12 relative to the largest coordinate (in cells) and momenta to 4e-12
-relative to the largest |u| (at least 1): the rounding of a stored
+J separately), every particle's removal agrees exactly, and live positions
+and momenta to 4e-12 relative to the largest coordinate (in cells) and the
+largest |u| (at least 1): the rounding of a stored
 coordinate scales with its magnitude, and a tight focus amplifies it over
 the run (the RP case reaches 1.2-1.7e-11 cells at coordinates of 16-20
 cells after 40 steps).  The device sums each node's current in an order
 that varies from run to run (LDS and global atomics) and refines its
 reciprocals by Newton steps, so its fields differ from the oracle's by a
-few ulp every step; the momenta integrate those differences, and in the RP
-case they reach 1.1e-12 of the largest |u| in some runs.
+few ulp every step; positions and momenta integrate those differences, and
+in the RP case they reach 0.8e-12 of the largest coordinate and 1.1e-12 of
+the largest |u| in some runs.
 Cases: the April LP and RP beams of Sec. 4.1 (tight focus, full six
 components), the plane pulse of Sec. 3.1, and a hot two-species plasma
 without incident field on a ragged grid whose particles leave through every
@@ -112,7 +113,7 @@ def _compare_particles(gs, os_, nsp, g):
                  for d in range(3))
         print(f"[3d] species {s}: dpos {dpos:.2e} cells (xmax {xmax:.0f}), "
               f"du {du:.2e} (umax {umax:.2e})", flush=True)
-        assert dpos <= 1e-12 * max(1.0, xmax), (s, dpos, xmax)
+        assert dpos <= 4e-12 * max(1.0, xmax), (s, dpos, xmax)
         assert du <= 4e-12 * max(1.0, umax), (s, du, umax)
 
 
