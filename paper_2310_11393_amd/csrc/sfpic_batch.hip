@@ -664,9 +664,11 @@ int create_member(Engine &eng, const sfpic_sim_desc &d, Member &m) {
   SF_TRY(sfpic_create(&d.grid, d.species, d.nspecies, &d.incident,
                       d.precision, &rt, &s));
   m.sim = s;
-  // the batched FP32 push is held to two workgroups per CU by its registers,
-  // so its tiles can afford the wider window of 2 cells of drift (fewer
-  // particles on the slower straggler path)
+  // the batched FP32 members take 2 cells of drift (the single sims' FP32
+  // form takes 1): on the sweep, whose beams heat the plasma within a few
+  // steps, the wider window keeps enough particles off the slower straggler
+  // path to outweigh its larger LDS footprint (17.5 against 15.6 G pushes/s
+  // with 1 on the 64-member, 200-step sweep at cadence 4)
   if (d.precision == SFPIC_FP32 && d.grid.dims == 2 && s->tg.slack < 2) {
     const int r = sim_retile(s, s->tg.tx, s->tg.ty, 2);
     if (r != SFPIC_OK) {
