@@ -639,8 +639,8 @@ hipError_t timed(sfpic_sim *s, int cls, F &&launch) {
 
 // Straggler fraction above which the adaptive cadence sorts (2^-10).  On
 // the 4096^2 RP run, against the fixed cadence (FP32 form every 4 steps,
-// FP64 every 8): first 200 steps 26.8 -> 27.9 and 22.1 -> 22.8 G pushes/s,
-// the run to step 3000 20.5 -> 20.4 and 18.6 -> 18.5; 2^-13 sorted almost
+// FP64 every 8): first 200 steps 26.8 -> 28.0 and 22.1 -> 23.1 G pushes/s,
+// the run to step 3000 20.5 -> 20.5 and 18.6 -> 18.8; 2^-13 sorted almost
 // as often as the fixed cadence, 2^-8 and 2^-6 lost on the long run.
 constexpr double kStragSortFrac = 1.0 / 1024.0;
 
