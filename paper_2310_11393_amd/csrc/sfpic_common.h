@@ -79,8 +79,6 @@ struct Particles<float> {
   uint32_t *id;
 };
 
-// Particle tiles: tx x ty cells (ty = 1 in 1D).  Cells are keyed tile-major:
-// key = tile * cells_per_tile + (iy mod ty) * tx + (ix mod tx).
 // Drift allowance (cells) of a single sim's tile window, per precision.
 #ifndef SFPIC_SLACK_F64
 #define SFPIC_SLACK_F64 3
@@ -91,6 +89,8 @@ constexpr int kSingleSlackF64 = SFPIC_SLACK_F64;
 #endif
 constexpr int kSingleSlackF32 = SFPIC_SLACK_F32;
 
+// Particle tiles: tx x ty cells (ty = 1 in 1D).  Cells are keyed tile-major:
+// key = tile * cells_per_tile + (iy mod ty) * tx + (ix mod tx).
 struct TileGeom {
   int tx, ty;
   int ntx, nty, ntiles;
