@@ -538,8 +538,12 @@ __device__ __forceinline__ bool push_particle(int &ix, int &iy, R &fx, R &fy,
 // GX > 0 fixes the tile at GX x GY cells with slack GS at compile time (it
 // must equal tg): the window strides are then constants, and the offsets of
 // a particle's gather and deposit taps fold into the LDS instructions.
+// SINGLE marks the single-simulation push: it loads the next particle chunk
+// while pushing the current one, and in the FP32 form with the incident
+// field at the particles it gathers E and Bbar from global memory instead of
+// an LDS window (below).
 template <typename R, int DIMS, int INC, int PER = kChunkPer, int GX = 0,
-          int GY = 0, int GS = 0, bool NEXT = false>
+          int GY = 0, int GS = 0, bool SINGLE = false>
 __device__ __forceinline__ void push_tile(const Fields<R> &f,
                                           const Particles<R> &p,
                                           const TileGeom &tg,
@@ -568,11 +572,11 @@ __device__ __forceinline__ void push_tile(const Fields<R> &f,
   // Staged path: the words of the first chunk are loaded before the field
   // window, so that their HBM latency overlaps the window loads; a single
   // simulation's push also loads the next chunk while the current one is
-  // pushed (NEXT; the batched push keeps those registers for its fourth
+  // pushed (SINGLE; the batched push keeps those registers for its fourth
   // workgroup per CU and loads later chunks when it gets there).
   // Thread t holds slots t + 256 j of the chunk (blockDim.x = 256).
   constexpr bool kAhead = PT<R>::kStaged;
-  constexpr bool kAheadNext = kAhead && NEXT;
+  constexpr bool kAheadNext = kAhead && SINGLE;
   constexpr int kAheadWords = 6;  // PT<float>::kWords
   using CK = Chunk<PER>;
   uint32_t *sp = (uint32_t *)(sf + 6 * WN);  // particle chunk after windows
@@ -602,34 +606,44 @@ __device__ __forceinline__ void push_tile(const Fields<R> &f,
   // The FP32 form interleaves the components that share their taps, Ex
   // with Bbar_y and Ey with Bbar_x, so that one 8-byte LDS read serves both
   // (planes: (Ex, By) pairs, (Ey, Bx) pairs, Ez, Bz); FP64 keeps six planes.
+  // The single simulation's FP32 push with the incident field at the
+  // particles (kFieldGlobal) stages no field at all: it is bound by its LDS
+  // traffic (the current atomics above all) while its vector memory path
+  // has room, and the window's few KB per plane stay in the CU's L1 and the
+  // XCD's L2, so its gathers read global memory (4096^2 RP push 3.57 ->
+  // 3.37 ms; gathering Ez and Bz alone that way 3.45, four components 3.38;
+  // the batched push, held to 128 VGPRs, lost 9% with it).
   constexpr bool kPairs = sizeof(R) == 4;
+  constexpr bool kFieldGlobal = kPairs && SINGLE && INC != kIncOnNodes;
   for (int k = threadIdx.x; k < WN; k += blockDim.x) {
-    const int I = cx0 + k % WX - kSlack + 1;
-    const int J = (DIMS == 2) ? cy0 + k / WX - kSlack + 1 : 0;
-    const bool in = I >= 0 && I < f.nx_alloc && J >= 0 && J < f.ny_alloc;
-    const size_t g = (size_t)J * P + I;
-    R ex = in ? f.ex[g] : R(0), ey = in ? f.ey[g] : R(0);
-    R mz = in ? f.mz[g] : R(0);
-    if (!inc_at_particle(INC, inc) && in) {  // sampled incident field joins
-      ex = f.ex[g] + f.iex[g];
-      ey = f.ey[g] + f.iey[g];
-      mz = f.mz[g] + f.ibz[g];
+    if constexpr (!kFieldGlobal) {
+      const int I = cx0 + k % WX - kSlack + 1;
+      const int J = (DIMS == 2) ? cy0 + k / WX - kSlack + 1 : 0;
+      const bool in = I >= 0 && I < f.nx_alloc && J >= 0 && J < f.ny_alloc;
+      const size_t g = (size_t)J * P + I;
+      R ex = in ? f.ex[g] : R(0), ey = in ? f.ey[g] : R(0);
+      R mz = in ? f.mz[g] : R(0);
+      if (!inc_at_particle(INC, inc) && in) {  // sampled incident field joins
+        ex = f.ex[g] + f.iex[g];
+        ey = f.ey[g] + f.iey[g];
+        mz = f.mz[g] + f.ibz[g];
+      }
+      const R ez = in ? f.ez[g] : R(0), mx = in ? f.mx[g] : R(0),
+              my = in ? f.my[g] : R(0);
+      if constexpr (kPairs) {
+        sf[2 * k] = ex;
+        sf[2 * k + 1] = my;
+        sf[2 * WN + 2 * k] = ey;
+        sf[2 * WN + 2 * k + 1] = mx;
+      } else {
+        sf[k] = ex;
+        sf[WN + k] = ey;
+        sf[3 * WN + k] = mx;
+        sf[4 * WN + k] = my;
+      }
+      sf[(kPairs ? 4 : 2) * WN + k] = ez;
+      sf[5 * WN + k] = mz;
     }
-    const R ez = in ? f.ez[g] : R(0), mx = in ? f.mx[g] : R(0),
-            my = in ? f.my[g] : R(0);
-    if constexpr (kPairs) {
-      sf[2 * k] = ex;
-      sf[2 * k + 1] = my;
-      sf[2 * WN + 2 * k] = ey;
-      sf[2 * WN + 2 * k + 1] = mx;
-    } else {
-      sf[k] = ex;
-      sf[WN + k] = ey;
-      sf[3 * WN + k] = mx;
-      sf[4 * WN + k] = my;
-    }
-    sf[(kPairs ? 4 : 2) * WN + k] = ez;
-    sf[5 * WN + k] = mz;
     sj[k] = Acc(0);
     sj[WN + k] = Acc(0);
     sj[2 * WN + k] = Acc(0);
@@ -645,6 +659,21 @@ __device__ __forceinline__ void push_tile(const Fields<R> &f,
     const int bxp = ipx - cx0 + kWinLo - 1, bxd = ix - cx0 + kWinLo - 1;
     const int byp = (DIMS == 2) ? ipy - cy0 + kWinLo - 1 : 0;
     const int byd = (DIMS == 2) ? iy - cy0 + kWinLo - 1 : 0;
+    if constexpr (kFieldGlobal) {
+      // array index of window index w: c0 + w - kSlack + 1 (as staged)
+      const ptrdiff_t o0 =
+          (DIMS == 2 ? (ptrdiff_t)(cy0 - kSlack + 1) * P : 0) +
+          (cx0 - kSlack + 1);
+      E[0] = gather_plane<R, DIMS>(f.ex + o0, P, bxd, byp, wxd, wyp);
+      E[1] = gather_plane<R, DIMS>(f.ey + o0, P, bxp, byd, wxp, wyd);
+      E[2] = gather_plane<R, DIMS>(f.ez + o0, P, bxp, byp, wxp, wyp);
+      B[0] = (DIMS == 2) ? gather_plane<R, DIMS>(f.mx + o0, P, bxp, byd, wxp,
+                                                 wyd)
+                         : R(0);
+      B[1] = gather_plane<R, DIMS>(f.my + o0, P, bxd, byp, wxd, wyp);
+      B[2] = gather_plane<R, DIMS>(f.mz + o0, P, bxd, byd, wxd, wyd);
+      return;
+    }
     if constexpr (kPairs) {
       gather_pair<R, DIMS>(sf, WX, bxd, byp, wxd, wyp, E[0], B[1]);
       gather_pair<R, DIMS>(sf + 2 * WN, WX, bxp, byd, wxp, wyd, E[1], B[0]);
