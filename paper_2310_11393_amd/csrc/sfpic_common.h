@@ -618,11 +618,14 @@ template <typename R>
 hipError_t launch_ampere(const Fields<R> &f, int dims, double dt, double dx,
                          double dy, hipStream_t st);
 // LDS of the push workgroup: all of it (static and dynamic), and the dynamic
-// part passed at launch; batch: the batched push's (smaller particle chunk).
+// part passed at launch; batch: the batched push's; field_window: whether
+// the push stages its field window (the FP32 form's single push with the
+// incident field at the particles gathers from global memory instead).
 template <typename R>
 size_t push_lds_bytes(const TileGeom &tg, int dims, bool batch = false);
 template <typename R>
-size_t push_dyn_lds_bytes(const TileGeom &tg, int dims, bool batch = false);
+size_t push_dyn_lds_bytes(const TileGeom &tg, int dims, bool batch = false,
+                          bool field_window = true);
 // Work items of the tiled push (tile, first particle), at most kmax
 // particles each, rebuilt from the sort's start offsets after every sort;
 // items holds push_items_words() words.

@@ -579,7 +579,12 @@ __device__ __forceinline__ void push_tile(const Fields<R> &f,
   constexpr bool kAheadNext = kAhead && SINGLE;
   constexpr int kAheadWords = 6;  // PT<float>::kWords
   using CK = Chunk<PER>;
-  uint32_t *sp = (uint32_t *)(sf + 6 * WN);  // particle chunk after windows
+  // (the FP32 form interleaves field pairs; the single FP32 push with the
+  // incident field at the particles has no field window, see below)
+  constexpr bool kPairs = sizeof(R) == 4;
+  constexpr bool kFieldGlobal = kPairs && SINGLE && INC != kIncOnNodes;
+  // particle chunk after the windows
+  uint32_t *sp = (uint32_t *)(sf + (kFieldGlobal ? 0 : 6 * WN));
   uint32_t ahead[kAhead ? PER : 1][kAheadWords];
   auto fetch_chunk = [&](uint32_t c0) {
     if constexpr (kAhead) {
@@ -613,8 +618,6 @@ __device__ __forceinline__ void push_tile(const Fields<R> &f,
   // XCD's L2, so its gathers read global memory (4096^2 RP push 3.57 ->
   // 3.37 ms; gathering Ez and Bz alone that way 3.45, four components 3.38;
   // the batched push, held to 128 VGPRs, lost 9% with it).
-  constexpr bool kPairs = sizeof(R) == 4;
-  constexpr bool kFieldGlobal = kPairs && SINGLE && INC != kIncOnNodes;
   for (int k = threadIdx.x; k < WN; k += blockDim.x) {
     if constexpr (!kFieldGlobal) {
       const int I = cx0 + k % WX - kSlack + 1;
@@ -939,12 +942,13 @@ push_stragglers(Fields<R> f, Particles<R> p, PushParams pp, IncParams inc,
 }
 
 template <typename R>
-size_t push_dyn_lds_bytes(const TileGeom &tg, int dims, bool batch) {
+size_t push_dyn_lds_bytes(const TileGeom &tg, int dims, bool batch,
+                          bool field_window) {
   const int WX = tg.tx + win_extra(tg.slack) +
                  (!batch && fixed_geometry<R>(tg, dims) ? fixed_row_pad<R>() : 0);
   const int WY = (dims == 2) ? tg.ty + win_extra(tg.slack) : 1;
   size_t b = (size_t)3 * WX * WY * sizeof(double) +
-             (size_t)6 * WX * WY * sizeof(R);
+             (field_window ? (size_t)6 * WX * WY * sizeof(R) : 0);
   const int pad = batch ? Chunk<kBatchChunkPer>::pad : Chunk<kChunkPer>::pad;
   if constexpr (PT<R>::kStaged)
     b += (size_t)PT<R>::kWords * pad * sizeof(typename PT<R>::Word);
@@ -980,7 +984,10 @@ hipError_t launch_push_tiled(const Fields<R> &f, const Particles<R> &p,
                              hipStream_t st) {
   const size_t cap = push_item_capacity(tg, n_slots, kmax);
   const unsigned nb = (unsigned)((cap + 7) & ~(size_t)7);
-  const size_t lds = push_dyn_lds_bytes<R>(tg, dims);
+  // the FP32 form's push gathers from global memory unless the incident
+  // field is sampled on the nodes (push_tile)
+  const size_t lds =
+      push_dyn_lds_bytes<R>(tg, dims, false, sizeof(R) == 8 || inc.on_nodes);
   fill_u32<<<1, 64, 0, st>>>(n_strag, 0u, 1);
   // the default tile of a 2D run has its geometry compiled in for the
   // April beams (fixed_geometry; the LDS size above includes its row pad)
@@ -1603,7 +1610,7 @@ hipError_t launch_batch_sort(const BatchView<R> &v, int dims, hipStream_t st) {
 
 #define SFPIC_INSTANTIATE(R)                                                 \
   template size_t push_lds_bytes<R>(const TileGeom &, int, bool);            \
-  template size_t push_dyn_lds_bytes<R>(const TileGeom &, int, bool);        \
+  template size_t push_dyn_lds_bytes<R>(const TileGeom &, int, bool, bool);  \
   template hipError_t launch_push_tiled<R>(                                  \
       const Fields<R> &, const Particles<R> &, const uint32_t *,             \
       const uint32_t *, const uint32_t *, uint32_t, int64_t,                 \
