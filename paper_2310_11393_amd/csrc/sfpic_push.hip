@@ -4,10 +4,12 @@
 //
 // Tiled push: after each sort the non-empty tiles of tx x ty cells are cut
 // into work items of at most item_particles particles, one workgroup each.
-// The workgroup stages the scattered E and centred B on its tile's node
-// window (the tile plus slack + 2 nodes on every side) in LDS, accumulates
-// the current in an FP64 LDS window of the same shape with LDS atomics, and
-// adds that window to the global current once.  The lanes of a wave push
+// The workgroup accumulates the current in an FP64 LDS window of its tile's
+// nodes (the tile plus slack + 2 nodes on every side) with LDS atomics and
+// adds that window to the global current once; it gathers the scattered E
+// and centred B from a window of the same shape staged in LDS, or, in the
+// single simulation's FP32 push, straight from global memory (L1/L2, the
+// LDS being that push's busiest unit).  The lanes of a wave push
 // particles of different cells, which keeps their LDS atomics off common
 // addresses: in FP64 the sort lays out each tile's particles with cell order
 // running down the 64 columns of each block of 1024 slots and a wave reads
@@ -533,8 +535,9 @@ __device__ __forceinline__ bool push_particle(int &ix, int &iy, R &fx, R &fy,
 // Tiled push
 // ---------------------------------------------------------------------------
 // One workgroup pushes the particles pbeg .. pend - 1 of one tile (all of
-// them, or one work item of a dense tile); smem holds the field and current
-// windows and, on the staged path, the particle chunk (push_lds_bytes).
+// them, or one work item of a dense tile); smem holds the current window, the
+// field window unless the push gathers from global memory, and, on the
+// staged path, the particle chunk (push_dyn_lds_bytes).
 // GX > 0 fixes the tile at GX x GY cells with slack GS at compile time (it
 // must equal tg): the window strides are then constants, and the offsets of
 // a particle's gather and deposit taps fold into the LDS instructions.
