@@ -58,7 +58,8 @@ TRAFFIC_FILES = {
     "fp64": os.path.join(ROOT, "profiles",
                          "push_tiled_f64_rp4096.traffic.txt"),
 }
-KERNEL_SOURCES = ("sfpic_push.hip", "sfpic_common.h", "sfpic_device.h")
+KERNEL_SOURCES = ("sfpic_push.hip", "sfpic_common.h", "sfpic_device.h",
+                  "sfpic_sim.h")
 FIELD_COMPS = ("ex", "ey", "ez", "bx", "by", "bz")
 G = 3
 

@@ -185,7 +185,8 @@ typedef struct {
   int32_t item_particles; /* a tile holding more particles is pushed by
                              several workgroups, this many each (single
                              sims, batch and server members); 0 = default
-                             (8192); must be >= 64                       */
+                             (8192 in FP64, 4096 in the FP32 form);
+                             must be >= 64                               */
 } sfpic_runtime;
 
 /* runtime.flags: launch a batch's steps one by one instead of replaying a

@@ -372,6 +372,7 @@ int setup_tiles(sfpic_sim *s) {
   s->sort_every = s->precision == SFPIC_FP32 ? 4 : 8;
   s->sort_adaptive = s->rt.sort_every <= 0;
   if (s->rt.sort_every > 0) s->sort_every = s->rt.sort_every;
+  s->item_max = default_item_particles(s->precision);
   if (s->rt.item_particles != 0) {
     if (s->rt.item_particles < 64)
       return fail(SFPIC_E_INVAL, "item_particles must be >= 64");
@@ -546,7 +547,8 @@ int sim_footprint(const sfpic_grid *grid, const sfpic_species *species,
     const size_t set = precision == SFPIC_FP64 ? 5 * al(cnt * 8) + al(cnt * 4)
                                                : 7 * al(cnt * 4);
     const size_t kmax = rt && rt->item_particles >= 64
-                            ? (size_t)rt->item_particles : kItemParticles;
+                            ? (size_t)rt->item_particles
+                            : (size_t)default_item_particles(precision);
     const size_t items = 2 * (ntx * nty + cnt / kmax + 1);
     b += al(4) + 2 * set + al(nk1 * 4) + al(items * 4) + al(4);
   }
